@@ -1,0 +1,1810 @@
+/*
+ * eb_oracle.c -- plain FP64 CPU oracle for the embedded-boundary viscoplastic RK2 step.
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by tests/, the smoke check and the CPU-baseline leg of the
+ * bench, never by the product path.  Shares no code with the HIP library.
+ *
+ * Written for readability, not speed: every step is a plain loop over cells or faces in the
+ * order the paper states it.  Floating point is IEEE binary64 throughout; build with
+ * -ffp-contract=off so no fused multiply-add changes a rounding.
+ *
+ * Parity unpinned (no external value or closed form fixes them; they follow the written readings
+ * and are checked only against the HIP path and through convergence rates): the covered-node
+ * fallback of the wall stencil, the slope limiter and upwind tie rules, the face average of the
+ * viscosity, and the coarse-level operators and smoother of the multigrid preconditioner.
+ */
+#include "eb_oracle.h"
+
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define MAXLEV 16
+
+/* ------------------------------------------------------------------------------------------ */
+/* grid helpers                                                                                */
+/* ------------------------------------------------------------------------------------------ */
+static long cidx(const int n[3], int i, int j, int k) {
+    return (long)i + (long)n[0] * ((long)j + (long)n[1] * (long)k);
+}
+static long fidx(const int n[3], int d, int i, int j, int k) {
+    long m0 = n[0] + (d == 0), m1 = n[1] + (d == 1);
+    return (long)i + m0 * ((long)j + m1 * (long)k);
+}
+static long nfaces(const int n[3], int d) {
+    return (long)(n[0] + (d == 0)) * (n[1] + (d == 1)) * (n[2] + (d == 2));
+}
+/* cell at integer position q (wrapped in periodic directions); -1 when outside a wall */
+static long cell_at(const int n[3], const int per[3], const int q_in[3]) {
+    int q[3] = {q_in[0], q_in[1], q_in[2]};
+    for (int d = 0; d < 3; d++) {
+        if (q[d] < 0 || q[d] >= n[d]) {
+            if (!per[d]) return -1;
+            q[d] = ((q[d] % n[d]) + n[d]) % n[d];
+        }
+    }
+    return cidx(n, q[0], q[1], q[2]);
+}
+static void cell_ijk(const int n[3], long c, int q[3]) {
+    q[0] = (int)(c % n[0]);
+    q[1] = (int)((c / n[0]) % n[1]);
+    q[2] = (int)(c / ((long)n[0] * n[1]));
+}
+/* the two directions other than d, in increasing order */
+static void others(int d, int* t1, int* t2) {
+    *t1 = (d == 0) ? 1 : 0;
+    *t2 = (d == 2) ? 1 : 2;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* geometry (Sec. III.B: planar cut per cell, continuous at faces; fraction, apertures, normal) */
+/* ------------------------------------------------------------------------------------------ */
+typedef struct {
+    int n[3];
+    long N;
+    double h;
+    double* alpha;
+    double* ap[3];
+    uint8_t* mask; /* alpha > 0 */
+    /* operator built per solve */
+    double* K[3];
+    double* S;
+    double* D;
+} level_t;
+
+struct or_geom {
+    or_box box;
+    or_body body;
+    long N;
+    uint8_t* flag;
+    double* alpha;
+    double* ap[3];
+    int ncut;
+    long* cut;    /* cell of each cut cell */
+    long* cutid;  /* per cell: position in the cut list, or -1 */
+    double* nrm;  /* [ncut][3] unit normal, into the fluid */
+    double* aeb;  /* [ncut] EB area in units of h^2 */
+    double* bc;   /* [ncut][3] EB centroid, relative to the cell centre, units of h */
+    double* delta;/* [ncut] distance of the cell centre from the EB plane, units of h */
+    double* dd;   /* [ncut][2] d1, d2 */
+    int* nfb;     /* [ncut] planes whose stencil needed the covered-node fallback */
+    long* sidx;   /* [ncut][2][9] stencil cells; -1 means "use the EB wall velocity" */
+    double* sw;   /* [ncut][2][9] biquadratic weights */
+    int nfallback;
+    int nlev;
+    level_t lev[MAXLEV];
+    double R[3][3];
+};
+
+static void rotation_zyx(const double e[3], double R[3][3]) {
+    double ca = cos(e[0]), sa = sin(e[0]), cb = cos(e[1]), sb = sin(e[1]);
+    double cc = cos(e[2]), sc = sin(e[2]);
+    double Rz[3][3] = {{ca, -sa, 0}, {sa, ca, 0}, {0, 0, 1}};
+    double Ry[3][3] = {{cb, 0, sb}, {0, 1, 0}, {-sb, 0, cb}};
+    double Rx[3][3] = {{1, 0, 0}, {0, cc, -sc}, {0, sc, cc}};
+    double T[3][3];
+    for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) {
+            T[a][b] = 0;
+            for (int c = 0; c < 3; c++) T[a][b] += Rz[a][c] * Ry[c][b];
+        }
+    for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) {
+            R[a][b] = 0;
+            for (int c = 0; c < 3; c++) R[a][b] += T[a][c] * Rx[c][b];
+        }
+}
+
+/* level set: > 0 in the fluid, <= 0 in the body */
+static double levelset(const or_geom* g, const double x[3]) {
+    const or_body* b = &g->body;
+    switch (b->kind) {
+    case OR_BODY_SPHERE: {
+        double s = 0;
+        for (int d = 0; d < 3; d++) s += (x[d] - b->center[d]) * (x[d] - b->center[d]);
+        return s - b->radii[0] * b->radii[0];
+    }
+    case OR_BODY_ELLIPSOID: {
+        double s = 0;
+        for (int a = 0; a < 3; a++) {
+            double y = 0;
+            for (int d = 0; d < 3; d++) y += g->R[d][a] * (x[d] - b->center[d]);
+            s += (y / b->radii[a]) * (y / b->radii[a]);
+        }
+        return s - 1.0;
+    }
+    case OR_BODY_ZSLAB:
+        return (x[2] - b->zlo) * (b->zhi - x[2]);
+    case OR_BODY_PLANE:
+        return b->plane_n[0] * x[0] + b->plane_n[1] * x[1] + b->plane_n[2] * x[2] - b->plane_d;
+    default:
+        return 1.0;
+    }
+}
+
+/* the level set along x0 + t*h*e_d is the quadratic A t^2 + B t + psi(x0) */
+static void levelset_edge(const or_geom* g, const double x0[3], int d, double* A, double* B) {
+    const or_body* b = &g->body;
+    double h = g->box.h;
+    *A = 0;
+    *B = 0;
+    switch (b->kind) {
+    case OR_BODY_SPHERE:
+        *A = h * h;
+        *B = 2 * h * (x0[d] - b->center[d]);
+        break;
+    case OR_BODY_ELLIPSOID:
+        for (int a = 0; a < 3; a++) {
+            double y = 0;
+            for (int e = 0; e < 3; e++) y += g->R[e][a] * (x0[e] - b->center[e]);
+            double ra2 = b->radii[a] * b->radii[a];
+            *A += h * h * g->R[d][a] * g->R[d][a] / ra2;
+            *B += 2 * h * y * g->R[d][a] / ra2;
+        }
+        break;
+    case OR_BODY_ZSLAB:
+        if (d == 2) {
+            *A = -h * h;
+            *B = h * (b->zhi + b->zlo - 2 * x0[2]);
+        }
+        break;
+    case OR_BODY_PLANE:
+        *B = h * b->plane_n[d];
+        break;
+    default:
+        break;
+    }
+}
+
+/* root in [0,1] of A t^2 + B t + C, given psi(0) = C and psi(1) = C1 of different fluid state */
+static double edge_root(double A, double B, double C, double C1) {
+    if (C == 0.0) return 0.0;
+    if (C1 == 0.0) return 1.0;
+    double t;
+    if (A == 0.0) {
+        t = -C / B;
+    } else {
+        double disc = B * B - 4 * A * C;
+        if (disc < 0) disc = 0;
+        double q = -0.5 * (B + (B >= 0 ? sqrt(disc) : -sqrt(disc)));
+        double r1 = q / A;
+        double r2 = (q != 0.0) ? C / q : r1;
+        int in1 = (r1 >= 0.0 && r1 <= 1.0), in2 = (r2 >= 0.0 && r2 <= 1.0);
+        if (in1 && !in2) t = r1;
+        else if (in2 && !in1) t = r2;
+        else if (in1 && in2) t = (fabs(r1 - 0.5) <= fabs(r2 - 0.5)) ? r1 : r2;
+        else {
+            double e1 = r1 < 0 ? -r1 : r1 - 1, e2 = r2 < 0 ? -r2 : r2 - 1;
+            t = (e1 <= e2) ? r1 : r2;
+        }
+    }
+    if (t < 0) t = 0;
+    if (t > 1) t = 1;
+    return t;
+}
+
+static long node_idx(const int n[3], int i, int j, int k) {
+    return (long)i + (long)(n[0] + 1) * ((long)j + (long)(n[1] + 1) * (long)k);
+}
+
+/* is the edge from node q along d cut?  If so return 1 and the fraction t of the cut point */
+static int edge_cut(const or_geom* g, const double* psi, const int q[3], int d, double* t) {
+    const int* n = g->box.n;
+    int q1[3] = {q[0], q[1], q[2]};
+    q1[d] += 1;
+    double p0 = psi[node_idx(n, q[0], q[1], q[2])];
+    double p1 = psi[node_idx(n, q1[0], q1[1], q1[2])];
+    if ((p0 > 0) == (p1 > 0)) return 0;
+    double x0[3];
+    for (int e = 0; e < 3; e++) x0[e] = g->box.lo[e] + q[e] * g->box.h;
+    double A, B;
+    levelset_edge(g, x0, d, &A, &B);
+    *t = edge_root(A, B, p0, p1);
+    return 1;
+}
+
+/* fluid area fraction of the face normal to d whose lower corner is node q (Sec. III.B) */
+static double face_area(const or_geom* g, const double* psi, int d, const int q[3], int* amb) {
+    const int* n = g->box.n;
+    int t1, t2;
+    others(d, &t1, &t2);
+    int c[4][3];
+    for (int m = 0; m < 4; m++)
+        for (int e = 0; e < 3; e++) c[m][e] = q[e];
+    c[1][t1] += 1;
+    c[2][t1] += 1;
+    c[2][t2] += 1;
+    c[3][t2] += 1;
+    int f[4];
+    for (int m = 0; m < 4; m++) f[m] = psi[node_idx(n, c[m][0], c[m][1], c[m][2])] > 0;
+    if (f[0] && f[1] && f[2] && f[3]) return 1.0;
+    if (!f[0] && !f[1] && !f[2] && !f[3]) return 0.0;
+    double px[12], py[12];
+    int np = 0, ncut = 0;
+    double t;
+    static const double cx[4] = {0, 1, 1, 0}, cy[4] = {0, 0, 1, 1};
+    /* walk corners 0 -> 1 -> 2 -> 3 -> 0, adding fluid corners and cut points */
+    for (int m = 0; m < 4; m++) {
+        if (f[m]) {
+            px[np] = cx[m];
+            py[np] = cy[m];
+            np++;
+        }
+        int m2 = (m + 1) & 3;
+        if (f[m] != f[m2]) {
+            /* each edge is evaluated from its lower node in the positive direction */
+            if (m == 0) { edge_cut(g, psi, c[0], t1, &t); px[np] = t; py[np] = 0; }
+            else if (m == 1) { edge_cut(g, psi, c[1], t2, &t); px[np] = 1; py[np] = t; }
+            else if (m == 2) { edge_cut(g, psi, c[3], t1, &t); px[np] = t; py[np] = 1; }
+            else { edge_cut(g, psi, c[0], t2, &t); px[np] = 0; py[np] = t; }
+            np++;
+            ncut++;
+        }
+    }
+    if (ncut > 2) *amb = 1;
+    double a = 0;
+    for (int m = 0; m < np; m++) {
+        int m2 = (m + 1) % np;
+        a += px[m] * py[m2] - px[m2] * py[m];
+    }
+    return 0.5 * fabs(a);
+}
+
+/* centroid of the polygon where the plane n.x = s cuts the cube [-1/2,1/2]^3 */
+static void plane_cube_centroid(const double nv[3], double s, double b[3]) {
+    double pts[12][3];
+    int np = 0;
+    for (int d = 0; d < 3; d++) {
+        int t1, t2;
+        others(d, &t1, &t2);
+        if (nv[d] == 0.0) continue;
+        for (int o1 = 0; o1 < 2; o1++)
+            for (int o2 = 0; o2 < 2; o2++) {
+                double x[3];
+                x[t1] = o1 - 0.5;
+                x[t2] = o2 - 0.5;
+                x[d] = (s - nv[t1] * x[t1] - nv[t2] * x[t2]) / nv[d];
+                if (x[d] >= -0.5 && x[d] <= 0.5) {
+                    for (int e = 0; e < 3; e++) pts[np][e] = x[e];
+                    np++;
+                }
+            }
+    }
+    if (np == 0) {
+        for (int e = 0; e < 3; e++) b[e] = s * nv[e];
+        return;
+    }
+    double m0[3] = {0, 0, 0};
+    for (int k = 0; k < np; k++)
+        for (int e = 0; e < 3; e++) m0[e] += pts[k][e] / np;
+    /* in-plane basis */
+    double a0[3] = {0, 0, 0};
+    int dmin = 0;
+    for (int e = 1; e < 3; e++)
+        if (fabs(nv[e]) < fabs(nv[dmin])) dmin = e;
+    a0[dmin] = 1.0;
+    double dot = a0[0] * nv[0] + a0[1] * nv[1] + a0[2] * nv[2];
+    double u1[3], u2[3];
+    for (int e = 0; e < 3; e++) u1[e] = a0[e] - dot * nv[e];
+    double l = sqrt(u1[0] * u1[0] + u1[1] * u1[1] + u1[2] * u1[2]);
+    for (int e = 0; e < 3; e++) u1[e] /= l;
+    u2[0] = nv[1] * u1[2] - nv[2] * u1[1];
+    u2[1] = nv[2] * u1[0] - nv[0] * u1[2];
+    u2[2] = nv[0] * u1[1] - nv[1] * u1[0];
+    double ang[12];
+    for (int k = 0; k < np; k++) {
+        double x = 0, y = 0;
+        for (int e = 0; e < 3; e++) {
+            x += (pts[k][e] - m0[e]) * u1[e];
+            y += (pts[k][e] - m0[e]) * u2[e];
+        }
+        ang[k] = atan2(y, x);
+    }
+    for (int k = 1; k < np; k++) { /* insertion sort by angle */
+        double a = ang[k], p[3] = {pts[k][0], pts[k][1], pts[k][2]};
+        int m = k - 1;
+        while (m >= 0 && ang[m] > a) {
+            ang[m + 1] = ang[m];
+            for (int e = 0; e < 3; e++) pts[m + 1][e] = pts[m][e];
+            m--;
+        }
+        ang[m + 1] = a;
+        for (int e = 0; e < 3; e++) pts[m + 1][e] = p[e];
+    }
+    double area = 0, c[3] = {0, 0, 0};
+    for (int k = 0; k < np; k++) {
+        int k2 = (k + 1) % np;
+        double v1[3], v2[3];
+        for (int e = 0; e < 3; e++) {
+            v1[e] = pts[k][e] - m0[e];
+            v2[e] = pts[k2][e] - m0[e];
+        }
+        double cr[3] = {v1[1] * v2[2] - v1[2] * v2[1], v1[2] * v2[0] - v1[0] * v2[2],
+                        v1[0] * v2[1] - v1[1] * v2[0]};
+        double at = 0.5 * (cr[0] * nv[0] + cr[1] * nv[1] + cr[2] * nv[2]);
+        area += at;
+        for (int e = 0; e < 3; e++) c[e] += at * (m0[e] + pts[k][e] + pts[k2][e]) / 3.0;
+    }
+    if (fabs(area) < 1e-300) {
+        for (int e = 0; e < 3; e++) b[e] = m0[e];
+    } else {
+        for (int e = 0; e < 3; e++) b[e] = c[e] / area;
+    }
+}
+
+/* Lagrange weights on nodes -1, 0, +1 at position x (App. A, Eq. lagrange_polynomial) */
+static void lagrange3(double x, double w[3]) {
+    w[0] = (x - 0.0) * (x - 1.0) / ((-1.0 - 0.0) * (-1.0 - 1.0));
+    w[1] = (x + 1.0) * (x - 1.0) / ((0.0 + 1.0) * (0.0 - 1.0));
+    w[2] = (x + 1.0) * (x - 0.0) / ((1.0 + 1.0) * (1.0 - 0.0));
+}
+
+/* wall-flux stencil of one cut cell (Sec. III.B.3, Eqs. interpolation_distances, dudn) */
+static int build_wall_stencil(or_geom* g, int cid) {
+    const int* n = g->box.n;
+    const int* per = g->box.periodic;
+    long cell = g->cut[cid];
+    int q[3];
+    cell_ijk(n, cell, q);
+    const double* nv = &g->nrm[3 * cid];
+    const double* b = &g->bc[3 * cid];
+    int ds = 0;
+    for (int d = 1; d < 3; d++)
+        if (fabs(nv[d]) > fabs(nv[ds])) ds = d;
+    int s = nv[ds] > 0 ? 1 : -1;
+    int t1, t2;
+    others(ds, &t1, &t2);
+    for (int kk = 1; kk <= 2; kk++) {
+        double dk = (kk * s - b[ds]) / nv[ds];
+        g->dd[2 * cid + kk - 1] = dk;
+        double p[3];
+        for (int e = 0; e < 3; e++) p[e] = b[e] + dk * nv[e];
+        int c1 = (int)floor(p[t1] + 0.5), c2 = (int)floor(p[t2] + 0.5);
+        int ok = 0;
+        for (int attempt = 0; attempt < 2 && !ok; attempt++) {
+            if (attempt == 1) {
+                c1 += (nv[t1] > 0) - (nv[t1] < 0);
+                c2 += (nv[t2] > 0) - (nv[t2] < 0);
+            }
+            ok = 1;
+            for (int m1 = -1; m1 <= 1; m1++)
+                for (int m2 = -1; m2 <= 1; m2++) {
+                    int r[3];
+                    r[ds] = q[ds] + kk * s;
+                    r[t1] = q[t1] + c1 + m1;
+                    r[t2] = q[t2] + c2 + m2;
+                    long cc = cell_at(n, per, r);
+                    if (cc < 0) return OR_EGEOM;
+                    if (g->alpha[cc] <= 0.0) ok = 0;
+                }
+        }
+        double w1[3], w2[3];
+        lagrange3(p[t1] - c1, w1);
+        lagrange3(p[t2] - c2, w2);
+        for (int m1 = -1; m1 <= 1; m1++)
+            for (int m2 = -1; m2 <= 1; m2++) {
+                int r[3];
+                r[ds] = q[ds] + kk * s;
+                r[t1] = q[t1] + c1 + m1;
+                r[t2] = q[t2] + c2 + m2;
+                long cc = cell_at(n, per, r);
+                long slot = ((long)cid * 2 + (kk - 1)) * 9 + (m1 + 1) * 3 + (m2 + 1);
+                g->sw[slot] = w1[m1 + 1] * w2[m2 + 1];
+                g->sidx[slot] = (g->alpha[cc] > 0.0) ? cc : -1;
+            }
+        if (!ok) {
+            g->nfallback++;
+            g->nfb[cid]++;
+        }
+    }
+    return OR_OK;
+}
+
+static void build_levels(or_geom* g) {
+    level_t* L0 = &g->lev[0];
+    memcpy(L0->n, g->box.n, sizeof(L0->n));
+    L0->N = g->N;
+    L0->h = g->box.h;
+    L0->alpha = g->alpha;
+    for (int d = 0; d < 3; d++) L0->ap[d] = g->ap[d];
+    g->nlev = 1;
+    for (;;) {
+        level_t* F = &g->lev[g->nlev - 1];
+        int can = g->nlev < MAXLEV;
+        for (int d = 0; d < 3; d++)
+            if (F->n[d] % 4 != 0) can = 0;
+        if (!can) break;
+        level_t* Cl = &g->lev[g->nlev];
+        for (int d = 0; d < 3; d++) Cl->n[d] = F->n[d] / 2;
+        Cl->N = (long)Cl->n[0] * Cl->n[1] * Cl->n[2];
+        Cl->h = 2 * F->h;
+        Cl->alpha = calloc(Cl->N, sizeof(double));
+        for (int k = 0; k < Cl->n[2]; k++)
+            for (int j = 0; j < Cl->n[1]; j++)
+                for (int i = 0; i < Cl->n[0]; i++) {
+                    double s = 0;
+                    for (int c = 0; c < 8; c++)
+                        s += F->alpha[cidx(F->n, 2 * i + (c & 1), 2 * j + ((c >> 1) & 1),
+                                           2 * k + ((c >> 2) & 1))];
+                    Cl->alpha[cidx(Cl->n, i, j, k)] = s / 8.0;
+                }
+        for (int d = 0; d < 3; d++) {
+            int t1, t2;
+            others(d, &t1, &t2);
+            Cl->ap[d] = calloc(nfaces(Cl->n, d), sizeof(double));
+            int m[3] = {Cl->n[0] + (d == 0), Cl->n[1] + (d == 1), Cl->n[2] + (d == 2)};
+            for (int k = 0; k < m[2]; k++)
+                for (int j = 0; j < m[1]; j++)
+                    for (int i = 0; i < m[0]; i++) {
+                        int q[3] = {i, j, k};
+                        double s = 0;
+                        for (int o1 = 0; o1 < 2; o1++)
+                            for (int o2 = 0; o2 < 2; o2++) {
+                                int r[3];
+                                r[d] = 2 * q[d];
+                                r[t1] = 2 * q[t1] + o1;
+                                r[t2] = 2 * q[t2] + o2;
+                                s += F->ap[d][fidx(F->n, d, r[0], r[1], r[2])];
+                            }
+                        Cl->ap[d][fidx(Cl->n, d, i, j, k)] = s / 4.0;
+                    }
+        }
+        g->nlev++;
+    }
+    for (int l = 0; l < g->nlev; l++) {
+        level_t* L = &g->lev[l];
+        L->mask = calloc(L->N, 1);
+        for (long c = 0; c < L->N; c++) L->mask[c] = L->alpha[c] > 0.0;
+        for (int d = 0; d < 3; d++) L->K[d] = calloc(nfaces(L->n, d), sizeof(double));
+        L->S = calloc(L->N, sizeof(double));
+        L->D = calloc(L->N, sizeof(double));
+    }
+}
+
+or_geom* or_geom_build(const or_box* box, const or_body* body, int* err) {
+    *err = OR_OK;
+    for (int d = 0; d < 3; d++)
+        if (box->n[d] < 2 || box->n[d] % 2 != 0) {
+            *err = OR_EINVAL;
+            return NULL;
+        }
+    if (!(box->h > 0)) {
+        *err = OR_EINVAL;
+        return NULL;
+    }
+    or_geom* g = calloc(1, sizeof(or_geom));
+    g->box = *box;
+    g->body = *body;
+    if (body->kind == OR_BODY_ELLIPSOID) rotation_zyx(body->euler_zyx, g->R);
+    const int* n = box->n;
+    g->N = (long)n[0] * n[1] * n[2];
+    long nn = (long)(n[0] + 1) * (n[1] + 1) * (n[2] + 1);
+    double* psi = malloc(nn * sizeof(double));
+    for (int k = 0; k <= n[2]; k++)
+        for (int j = 0; j <= n[1]; j++)
+            for (int i = 0; i <= n[0]; i++) {
+                double x[3] = {box->lo[0] + i * box->h, box->lo[1] + j * box->h,
+                               box->lo[2] + k * box->h};
+                psi[node_idx(n, i, j, k)] = levelset(g, x);
+            }
+    /* face apertures */
+    int amb = 0;
+    for (int d = 0; d < 3; d++) {
+        g->ap[d] = calloc(nfaces(n, d), sizeof(double));
+        int m[3] = {n[0] + (d == 0), n[1] + (d == 1), n[2] + (d == 2)};
+        for (int k = 0; k < m[2]; k++)
+            for (int j = 0; j < m[1]; j++)
+                for (int i = 0; i < m[0]; i++) {
+                    int q[3] = {i, j, k};
+                    g->ap[d][fidx(n, d, i, j, k)] = face_area(g, psi, d, q, &amb);
+                }
+        if (box->periodic[d]) { /* the last face is the first one */
+            for (int k = 0; k < m[2]; k++)
+                for (int j = 0; j < m[1]; j++)
+                    for (int i = 0; i < m[0]; i++) {
+                        int q[3] = {i, j, k};
+                        if (q[d] != n[d]) continue;
+                        int q0[3] = {i, j, k};
+                        q0[d] = 0;
+                        g->ap[d][fidx(n, d, i, j, k)] = g->ap[d][fidx(n, d, q0[0], q0[1], q0[2])];
+                    }
+        }
+    }
+    /* cells */
+    g->flag = calloc(g->N, 1);
+    g->alpha = calloc(g->N, sizeof(double));
+    g->cutid = malloc(g->N * sizeof(long));
+    double* tmp_n = malloc(g->N * 3 * sizeof(double)); /* sized generously, trimmed below */
+    double* tmp_a = malloc(g->N * sizeof(double));
+    double* tmp_b = malloc(g->N * 3 * sizeof(double));
+    double* tmp_s = malloc(g->N * sizeof(double));
+    long* tmp_c = malloc(g->N * sizeof(long));
+    int ncut = 0;
+    for (int k = 0; k < n[2]; k++)
+        for (int j = 0; j < n[1]; j++)
+            for (int i = 0; i < n[0]; i++) {
+                long c = cidx(n, i, j, k);
+                int q[3] = {i, j, k};
+                double a[3][2];
+                int all1 = 1, all0 = 1;
+                double sumA = 0;
+                for (int d = 0; d < 3; d++)
+                    for (int s = 0; s < 2; s++) {
+                        int r[3] = {i, j, k};
+                        r[d] += s;
+                        a[d][s] = g->ap[d][fidx(n, d, r[0], r[1], r[2])];
+                        if (a[d][s] != 1.0) all1 = 0;
+                        if (a[d][s] != 0.0) all0 = 0;
+                        sumA += a[d][s];
+                    }
+                g->cutid[c] = -1;
+                if (all1) {
+                    g->flag[c] = 2;
+                    g->alpha[c] = 1.0;
+                    continue;
+                }
+                if (all0) {
+                    g->flag[c] = 0;
+                    g->alpha[c] = 0.0;
+                    continue;
+                }
+                double m[3], aeb = 0;
+                for (int d = 0; d < 3; d++) {
+                    m[d] = a[d][1] - a[d][0];
+                    aeb += m[d] * m[d];
+                }
+                aeb = sqrt(aeb);
+                if (aeb == 0.0) {
+                    *err = OR_EGEOM;
+                    continue;
+                }
+                double nv[3] = {m[0] / aeb, m[1] / aeb, m[2] / aeb};
+                /* plane offset: mean of n.p over the cut points on the 12 cell edges */
+                double ssum = 0;
+                int npt = 0;
+                for (int d = 0; d < 3; d++) {
+                    int t1, t2;
+                    others(d, &t1, &t2);
+                    for (int o1 = 0; o1 < 2; o1++)
+                        for (int o2 = 0; o2 < 2; o2++) {
+                            int r[3] = {q[0], q[1], q[2]};
+                            r[t1] += o1;
+                            r[t2] += o2;
+                            double t;
+                            if (edge_cut(g, psi, r, d, &t)) {
+                                double p[3];
+                                p[d] = t - 0.5;
+                                p[t1] = o1 - 0.5;
+                                p[t2] = o2 - 0.5;
+                                ssum += nv[0] * p[0] + nv[1] * p[1] + nv[2] * p[2];
+                                npt++;
+                            }
+                        }
+                }
+                double s = npt > 0 ? ssum / npt : 0.0;
+                /* divergence theorem with x.n: 3V = sum_f A_f/2 - s A_EB (cell units) */
+                double al = (0.5 * sumA - s * aeb) / 3.0;
+                if (al > 1.0) al = 1.0;
+                if (al < 1e-12) al = 1e-12;
+                g->flag[c] = 1;
+                g->alpha[c] = al;
+                g->cutid[c] = ncut;
+                tmp_c[ncut] = c;
+                for (int e = 0; e < 3; e++) tmp_n[3 * ncut + e] = nv[e];
+                tmp_a[ncut] = aeb;
+                double b[3];
+                plane_cube_centroid(nv, s, b);
+                for (int e = 0; e < 3; e++) tmp_b[3 * ncut + e] = b[e];
+                tmp_s[ncut] = -s;
+                ncut++;
+            }
+    if (amb) *err = OR_EGEOM;
+    g->ncut = ncut;
+    long nc = ncut > 0 ? ncut : 1;
+    g->cut = malloc(nc * sizeof(long));
+    g->nrm = malloc(nc * 3 * sizeof(double));
+    g->aeb = malloc(nc * sizeof(double));
+    g->bc = malloc(nc * 3 * sizeof(double));
+    g->delta = malloc(nc * sizeof(double));
+    memcpy(g->cut, tmp_c, ncut * sizeof(long));
+    memcpy(g->nrm, tmp_n, ncut * 3 * sizeof(double));
+    memcpy(g->aeb, tmp_a, ncut * sizeof(double));
+    memcpy(g->bc, tmp_b, ncut * 3 * sizeof(double));
+    memcpy(g->delta, tmp_s, ncut * sizeof(double));
+    free(tmp_c);
+    free(tmp_n);
+    free(tmp_a);
+    free(tmp_b);
+    free(tmp_s);
+    free(psi);
+    g->dd = calloc(nc * 2, sizeof(double));
+    g->sidx = calloc(nc * 18, sizeof(long));
+    g->sw = calloc(nc * 18, sizeof(double));
+    g->nfb = calloc(nc, sizeof(int));
+    for (int c = 0; c < ncut; c++) {
+        int e = build_wall_stencil(g, c);
+        if (e != OR_OK) *err = e;
+    }
+    build_levels(g);
+    return g;
+}
+
+void or_geom_free(or_geom* g) {
+    if (!g) return;
+    for (int l = 0; l < g->nlev; l++) {
+        level_t* L = &g->lev[l];
+        if (l > 0) {
+            free(L->alpha);
+            for (int d = 0; d < 3; d++) free(L->ap[d]);
+        }
+        free(L->mask);
+        for (int d = 0; d < 3; d++) free(L->K[d]);
+        free(L->S);
+        free(L->D);
+    }
+    free(g->flag);
+    free(g->alpha);
+    for (int d = 0; d < 3; d++) free(g->ap[d]);
+    free(g->cut);
+    free(g->cutid);
+    free(g->nrm);
+    free(g->aeb);
+    free(g->bc);
+    free(g->delta);
+    free(g->dd);
+    free(g->sidx);
+    free(g->sw);
+    free(g->nfb);
+    free(g);
+}
+
+int or_geom_ncut(const or_geom* g) { return g->ncut; }
+int or_geom_nlevels(const or_geom* g) { return g->nlev; }
+int or_geom_nfallback(const or_geom* g) { return g->nfallback; }
+
+void or_geom_export(const or_geom* g, uint8_t* flag, double* alpha, double* ax, double* ay,
+                    double* az) {
+    memcpy(flag, g->flag, g->N);
+    memcpy(alpha, g->alpha, g->N * sizeof(double));
+    memcpy(ax, g->ap[0], nfaces(g->box.n, 0) * sizeof(double));
+    memcpy(ay, g->ap[1], nfaces(g->box.n, 1) * sizeof(double));
+    memcpy(az, g->ap[2], nfaces(g->box.n, 2) * sizeof(double));
+}
+
+void or_cut_export(const or_geom* g, int64_t* cell, double* data) {
+    for (int c = 0; c < g->ncut; c++) {
+        cell[c] = g->cut[c];
+        for (int e = 0; e < 3; e++) data[9 * c + e] = g->nrm[3 * c + e];
+        data[9 * c + 3] = g->aeb[c];
+        for (int e = 0; e < 3; e++) data[9 * c + 4 + e] = g->bc[3 * c + e];
+        data[9 * c + 7] = g->delta[c];
+        data[9 * c + 8] = g->nfb[c];
+    }
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* wall gradient (Eq. dudn) and cell gradients (one-sided quadratic differences, Sec. III.B.4)  */
+/* ------------------------------------------------------------------------------------------ */
+/* normal derivative of component j at the EB centroid of cut cell cid */
+static double wall_dudn(const or_geom* g, int cid, const double* uj, double ueb) {
+    double ui[2];
+    for (int kk = 0; kk < 2; kk++) {
+        double s = 0;
+        for (int m = 0; m < 9; m++) {
+            long slot = ((long)cid * 2 + kk) * 9 + m;
+            long cc = g->sidx[slot];
+            s += g->sw[slot] * (cc >= 0 ? uj[cc] : ueb);
+        }
+        ui[kk] = s;
+    }
+    double d1 = g->dd[2 * cid], d2 = g->dd[2 * cid + 1];
+    return (d2 * d2 * (ui[0] - ueb) - d1 * d1 * (ui[1] - ueb)) / (d1 * d2 * (d2 - d1) * g->box.h);
+}
+
+void or_wall_gradient(const or_geom* g, const double* u, double* gw) {
+    for (int c = 0; c < g->ncut; c++)
+        for (int j = 0; j < 3; j++)
+            gw[3 * c + j] = wall_dudn(g, c, u + (long)j * g->N, g->body.u_eb[j]);
+}
+
+void or_cell_gradient(const or_geom* g, const double* u, const double* gw, double* G) {
+    const int* n = g->box.n;
+    const int* per = g->box.periodic;
+    long N = g->N;
+    double h = g->box.h;
+#pragma omp parallel for schedule(static)
+    for (long c = 0; c < N; c++) {
+        for (int a = 0; a < 9; a++) G[a * N + c] = 0.0;
+        if (g->alpha[c] <= 0.0) continue;
+        int q[3];
+        cell_ijk(n, c, q);
+        for (int d = 0; d < 3; d++) {
+            int r[3];
+            memcpy(r, q, sizeof(r));
+            r[d] = q[d] - 1;
+            long lo = cell_at(n, per, r);
+            r[d] = q[d] - 2;
+            long lo2 = cell_at(n, per, r);
+            r[d] = q[d] + 1;
+            long hi = cell_at(n, per, r);
+            r[d] = q[d] + 2;
+            long hi2 = cell_at(n, per, r);
+            int lo_wall = lo < 0, hi_wall = hi < 0;
+            int lo_open = !lo_wall && g->alpha[lo] > 0.0;
+            int hi_open = !hi_wall && g->alpha[hi] > 0.0;
+            int lo2_open = lo2 >= 0 && g->alpha[lo2] > 0.0;
+            int hi2_open = hi2 >= 0 && g->alpha[hi2] > 0.0;
+            for (int j = 0; j < 3; j++) {
+                const double* uj = u + (long)j * N;
+                double uc = uj[c];
+                /* Dirichlet domain walls enter through the ghost value 2 u_wall - u_c */
+                double vlo = lo_open ? uj[lo] : 2.0 * g->box.wall_u[2 * d][j] - uc;
+                double vhi = hi_open ? uj[hi] : 2.0 * g->box.wall_u[2 * d + 1][j] - uc;
+                int lo_ok = lo_open || lo_wall, hi_ok = hi_open || hi_wall;
+                double gr;
+                if (lo_ok && hi_ok) {
+                    gr = (vhi - vlo) / (2.0 * h);
+                } else if (hi_ok) {
+                    if (hi_open && hi2_open)
+                        gr = (-1.5 * uc + 2.0 * vhi - 0.5 * uj[hi2]) / h;
+                    else
+                        gr = (vhi - uc) / h;
+                } else if (lo_ok) {
+                    if (lo_open && lo2_open)
+                        gr = (1.5 * uc - 2.0 * vlo + 0.5 * uj[lo2]) / h;
+                    else
+                        gr = (uc - vlo) / h;
+                } else {
+                    long cid = g->cutid[c];
+                    gr = (cid >= 0) ? g->nrm[3 * cid + d] * gw[3 * cid + j] : 0.0;
+                }
+                G[(d * 3 + j) * N + c] = gr;
+            }
+        }
+    }
+}
+
+/* scaled Frobenius norm of gamma = G + G^T (Sec. II.A) */
+static double strain_norm(const double Gm[3][3]) {
+    double s = 0;
+    for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) {
+            double y = Gm[a][b] + Gm[b][a];
+            s += y * y;
+        }
+    return sqrt(0.5 * s);
+}
+
+/* apparent viscosity laws (Table rheology, Eq. papabing:viscosity) */
+static double law_eta(const or_rheo* r, double tau0, double sr) {
+    if (r->law == OR_LAW_NEWTONIAN || tau0 == 0.0) return r->mu;
+    if (r->law == OR_LAW_BINGHAM_REG) return r->mu + tau0 / (sr + r->eps);
+    if (sr == 0.0) return r->mu + tau0 / r->eps;
+    return r->mu + tau0 * (-expm1(-sr / r->eps)) / sr;
+}
+
+static void viscosity_from(const or_geom* g, const or_rheo* r, const double* theta,
+                           const double* G, const double* gw, double* eta, double* eta_eb,
+                           double* sr) {
+    long N = g->N;
+#pragma omp parallel for schedule(static)
+    for (long c = 0; c < N; c++) {
+        if (g->alpha[c] <= 0.0) {
+            eta[c] = r->mu;
+            if (sr) sr[c] = 0.0;
+            continue;
+        }
+        double Gm[3][3];
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) Gm[a][b] = G[(a * 3 + b) * N + c];
+        double s = strain_norm(Gm);
+        double t0 = r->tau0 * (theta ? theta[c] : 1.0);
+        eta[c] = law_eta(r, t0, s);
+        if (sr) sr[c] = s;
+    }
+    for (int cid = 0; cid < g->ncut; cid++) {
+        long c = g->cut[cid];
+        double Gm[3][3]; /* gradient at the wall: (grad u)_ab = n_a du_b/dn */
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) Gm[a][b] = g->nrm[3 * cid + a] * gw[3 * cid + b];
+        double s = strain_norm(Gm);
+        double t0 = r->tau0 * (theta ? theta[c] : 1.0);
+        eta_eb[cid] = law_eta(r, t0, s);
+    }
+}
+
+void or_viscosity(const or_geom* g, const or_rheo* r, const double* u, const double* theta,
+                  double* eta, double* eta_eb, double* sr) {
+    double* gw = calloc(3 * (g->ncut + 1), sizeof(double));
+    double* G = malloc(9 * g->N * sizeof(double));
+    or_wall_gradient(g, u, gw);
+    or_cell_gradient(g, u, gw, G);
+    viscosity_from(g, r, theta, G, gw, eta, eta_eb, sr);
+    free(G);
+    free(gw);
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* redistribution (Eqs. divergence_nonconservative ... divergence_final)                        */
+/* ------------------------------------------------------------------------------------------ */
+void or_redistribute(const or_geom* g, int ncomp, const double* DC, double* D) {
+    const int* n = g->box.n;
+    const int* per = g->box.periodic;
+    long N = g->N;
+    double* S = calloc(N, sizeof(double));
+    double* dD = calloc((long)ncomp * N, sizeof(double));
+    double* DH = calloc((long)ncomp * N, sizeof(double));
+#pragma omp parallel for schedule(static)
+    for (long c = 0; c < N; c++) {
+        if (g->alpha[c] <= 0.0) continue;
+        double a = g->alpha[c];
+        if (g->flag[c] != 1) {
+            for (int m = 0; m < ncomp; m++) DH[m * N + c] = DC[m * N + c];
+            continue;
+        }
+        int q[3];
+        cell_ijk(n, c, q);
+        double s = 0, acc[3] = {0, 0, 0};
+        for (int dz = -1; dz <= 1; dz++)
+            for (int dy = -1; dy <= 1; dy++)
+                for (int dx = -1; dx <= 1; dx++) {
+                    if (!dx && !dy && !dz) continue;
+                    int r[3] = {q[0] + dx, q[1] + dy, q[2] + dz};
+                    long cc = cell_at(n, per, r);
+                    if (cc < 0 || g->alpha[cc] <= 0.0) continue;
+                    s += g->alpha[cc];
+                    for (int m = 0; m < ncomp; m++) acc[m] += g->alpha[cc] * DC[m * N + cc];
+                }
+        S[c] = s;
+        for (int m = 0; m < ncomp; m++) {
+            double dnc = s > 0 ? acc[m] / s : DC[m * N + c];
+            DH[m * N + c] = a * DC[m * N + c] + (1.0 - a) * dnc;
+            dD[m * N + c] = a * (1.0 - a) * (DC[m * N + c] - dnc);
+        }
+    }
+#pragma omp parallel for schedule(static)
+    for (long c = 0; c < N; c++) {
+        for (int m = 0; m < ncomp; m++) D[m * N + c] = 0.0;
+        if (g->alpha[c] <= 0.0) continue;
+        int q[3];
+        cell_ijk(n, c, q);
+        double acc[3] = {0, 0, 0};
+        for (int dz = -1; dz <= 1; dz++)
+            for (int dy = -1; dy <= 1; dy++)
+                for (int dx = -1; dx <= 1; dx++) {
+                    if (!dx && !dy && !dz) continue;
+                    int r[3] = {q[0] + dx, q[1] + dy, q[2] + dz};
+                    long cc = cell_at(n, per, r);
+                    if (cc < 0 || g->flag[cc] != 1 || S[cc] <= 0.0) continue;
+                    for (int m = 0; m < ncomp; m++) acc[m] += dD[m * N + cc] / S[cc];
+                }
+        for (int m = 0; m < ncomp; m++) D[m * N + c] = DH[m * N + c] + acc[m];
+    }
+    free(S);
+    free(dD);
+    free(DH);
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* explicit viscous term  V = div(eta (grad u)^T)  (Eq. explicit-viscous, Sec. III.B.3)         */
+/* ------------------------------------------------------------------------------------------ */
+static void transpose_term_dc(const or_geom* g, const double* eta, const double* eta_eb,
+                              const double* u, const double* G, const double* gw, double* DC) {
+    const int* n = g->box.n;
+    const int* per = g->box.periodic;
+    long N = g->N;
+    double h = g->box.h;
+#pragma omp parallel for schedule(static)
+    for (long c = 0; c < N; c++) {
+        for (int j = 0; j < 3; j++) DC[j * N + c] = 0.0;
+        if (g->alpha[c] <= 0.0) continue;
+        int q[3];
+        cell_ijk(n, c, q);
+        for (int j = 0; j < 3; j++) {
+            double acc = 0;
+            for (int d = 0; d < 3; d++)
+                for (int side = -1; side <= 1; side += 2) {
+                    int f[3] = {q[0], q[1], q[2]};
+                    if (side > 0) f[d] += 1;
+                    double A = g->ap[d][fidx(n, d, f[0], f[1], f[2])];
+                    if (A == 0.0) continue;
+                    int r[3] = {q[0], q[1], q[2]};
+                    r[d] += side;
+                    long nb = cell_at(n, per, r);
+                    const double* ud = u + (long)d * N;
+                    double F;
+                    if (nb >= 0) {
+                        double ef = 0.5 * (eta[c] + eta[nb]);
+                        double der;
+                        if (j == d)
+                            der = side > 0 ? (ud[nb] - ud[c]) / h : (ud[c] - ud[nb]) / h;
+                        else
+                            der = 0.5 * (G[(j * 3 + d) * N + c] + G[(j * 3 + d) * N + nb]);
+                        F = ef * der;
+                    } else {
+                        double uw = g->box.wall_u[2 * d + (side > 0)][d];
+                        double der = 0.0;
+                        if (j == d)
+                            der = side > 0 ? (uw - ud[c]) / (0.5 * h) : (ud[c] - uw) / (0.5 * h);
+                        F = eta[c] * der;
+                    }
+                    acc += side * A * F;
+                }
+            long cid = g->cutid[c];
+            if (cid >= 0) {
+                const double* nv = &g->nrm[3 * cid];
+                double ng = nv[0] * gw[3 * cid] + nv[1] * gw[3 * cid + 1] + nv[2] * gw[3 * cid + 2];
+                acc -= g->aeb[cid] * eta_eb[cid] * nv[j] * ng;
+            }
+            DC[j * N + c] = acc / (g->alpha[c] * h);
+        }
+    }
+}
+
+void or_transpose_term(const or_geom* g, const double* eta, const double* eta_eb,
+                       const double* u, double* V) {
+    long N = g->N;
+    double* gw = calloc(3 * (g->ncut + 1), sizeof(double));
+    double* G = malloc(9 * N * sizeof(double));
+    double* DC = malloc(3 * N * sizeof(double));
+    or_wall_gradient(g, u, gw);
+    or_cell_gradient(g, u, gw, G);
+    transpose_term_dc(g, eta, eta_eb, u, G, gw, DC);
+    or_redistribute(g, 3, DC, V);
+    free(DC);
+    free(G);
+    free(gw);
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* slopes, face extrapolation and upwinding (Sec. III.A.3, Alg. derived lines 1-2)              */
+/* ------------------------------------------------------------------------------------------ */
+/* monotonised-central limited slope of component j along d at cell c (0 next to walls/covered) */
+static double mc_slope(const or_geom* g, const double* uj, long c, int d) {
+    const int* n = g->box.n;
+    int q[3];
+    cell_ijk(n, c, q);
+    int r[3];
+    memcpy(r, q, sizeof(r));
+    r[d] = q[d] - 1;
+    long lo = cell_at(n, g->box.periodic, r);
+    r[d] = q[d] + 1;
+    long hi = cell_at(n, g->box.periodic, r);
+    if (lo < 0 || hi < 0) return 0.0;
+    if (g->alpha[lo] <= 0.0 || g->alpha[hi] <= 0.0) return 0.0;
+    double dl = uj[c] - uj[lo], dr = uj[hi] - uj[c], dc = 0.5 * (uj[hi] - uj[lo]);
+    if (dl * dr <= 0.0) return 0.0;
+    double m = fmin(fabs(dc), fmin(2.0 * fabs(dl), 2.0 * fabs(dr)));
+    return dc > 0 ? m : -m;
+}
+
+/* left/right extrapolated states of component j on face (d, f) between cells lo and hi */
+static void face_states(const or_geom* g, const double* uj, long lo, long hi, int d, double* uL,
+                        double* uR) {
+    *uL = uj[lo] + 0.5 * mc_slope(g, uj, lo, d);
+    *uR = uj[hi] - 0.5 * mc_slope(g, uj, hi, d);
+}
+
+/* cells on either side of face (d, i,j,k); -1 where the face is a domain wall */
+static void face_cells(const or_geom* g, int d, const int f[3], long* lo, long* hi) {
+    int r[3] = {f[0], f[1], f[2]};
+    r[d] = f[d] - 1;
+    *lo = cell_at(g->box.n, g->box.periodic, r);
+    r[d] = f[d];
+    *hi = cell_at(g->box.n, g->box.periodic, r);
+}
+
+void or_face_extrap(const or_geom* g, const double* u, double* fx, double* fy, double* fz) {
+    const int* n = g->box.n;
+    double* fo[3] = {fx, fy, fz};
+    for (int d = 0; d < 3; d++) {
+        int m[3] = {n[0] + (d == 0), n[1] + (d == 1), n[2] + (d == 2)};
+        for (int k = 0; k < m[2]; k++)
+            for (int j = 0; j < m[1]; j++)
+                for (int i = 0; i < m[0]; i++) {
+                    int f[3] = {i, j, k};
+                    long fi = fidx(n, d, i, j, k);
+                    long lo, hi;
+                    face_cells(g, d, f, &lo, &hi);
+                    double A = g->ap[d][fi];
+                    double val = 0.0;
+                    if (lo < 0 || hi < 0) {
+                        val = g->box.wall_u[2 * d + (lo >= 0)][d];
+                    } else if (A > 0.0) {
+                        double uL, uR;
+                        face_states(g, u + (long)d * g->N, lo, hi, d, &uL, &uR);
+                        if (uL > 0.0 && uL + uR > 0.0) val = uL;
+                        else if (uR < 0.0 && uL + uR < 0.0) val = uR;
+                        else val = 0.0;
+                    }
+                    fo[d][fi] = val;
+                }
+    }
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* convective term C = -div(u (x) u^F) with upwinding by the projected face velocity            */
+/* ------------------------------------------------------------------------------------------ */
+static void conv_dc(const or_geom* g, const double* u, double* const uf[3], double* DC) {
+    const int* n = g->box.n;
+    long N = g->N;
+    double h = g->box.h;
+#pragma omp parallel for schedule(static)
+    for (long c = 0; c < N; c++) {
+        for (int j = 0; j < 3; j++) DC[j * N + c] = 0.0;
+        if (g->alpha[c] <= 0.0) continue;
+        int q[3];
+        cell_ijk(n, c, q);
+        for (int j = 0; j < 3; j++) {
+            double acc = 0;
+            for (int d = 0; d < 3; d++)
+                for (int side = -1; side <= 1; side += 2) {
+                    int f[3] = {q[0], q[1], q[2]};
+                    if (side > 0) f[d] += 1;
+                    long fi = fidx(n, d, f[0], f[1], f[2]);
+                    double A = g->ap[d][fi];
+                    if (A == 0.0) continue;
+                    long lo, hi;
+                    face_cells(g, d, f, &lo, &hi);
+                    double w = uf[d][fi], up;
+                    if (lo < 0 || hi < 0) {
+                        up = g->box.wall_u[2 * d + (lo >= 0)][j];
+                    } else {
+                        double uL, uR;
+                        face_states(g, u + (long)j * N, lo, hi, d, &uL, &uR);
+                        up = w > 0.0 ? uL : (w < 0.0 ? uR : 0.5 * (uL + uR));
+                    }
+                    acc += side * A * w * up;
+                }
+            long cid = g->cutid[c];
+            if (cid >= 0) { /* flux through a moving wall: u_EB (u_EB . n_out), n_out = -n */
+                const double* nv = &g->nrm[3 * cid];
+                const double* ue = g->body.u_eb;
+                double un = -(ue[0] * nv[0] + ue[1] * nv[1] + ue[2] * nv[2]);
+                acc += g->aeb[cid] * un * ue[j];
+            }
+            DC[j * N + c] = -acc / (g->alpha[c] * h);
+        }
+    }
+}
+
+void or_conv_term(const or_geom* g, const double* u, const double* uf_x, const double* uf_y,
+                  const double* uf_z, double* C) {
+    double* DC = malloc(3 * g->N * sizeof(double));
+    double* uf[3] = {(double*)uf_x, (double*)uf_y, (double*)uf_z};
+    conv_dc(g, u, uf, DC);
+    or_redistribute(g, 3, DC, C);
+    free(DC);
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* divergence of a face field, cell-centred pressure gradient                                   */
+/* ------------------------------------------------------------------------------------------ */
+void or_divergence(const or_geom* g, const double* fx, const double* fy, const double* fz,
+                   double* div) {
+    const int* n = g->box.n;
+    const double* fo[3] = {fx, fy, fz};
+    double h = g->box.h;
+#pragma omp parallel for schedule(static)
+    for (long c = 0; c < g->N; c++) {
+        div[c] = 0.0;
+        if (g->alpha[c] <= 0.0) continue;
+        int q[3];
+        cell_ijk(n, c, q);
+        double acc = 0;
+        for (int d = 0; d < 3; d++) {
+            int f[3] = {q[0], q[1], q[2]};
+            long f0 = fidx(n, d, f[0], f[1], f[2]);
+            f[d] += 1;
+            long f1 = fidx(n, d, f[0], f[1], f[2]);
+            acc += g->ap[d][f1] * fo[d][f1] - g->ap[d][f0] * fo[d][f0];
+        }
+        long cid = g->cutid[c];
+        if (cid >= 0) {
+            const double* nv = &g->nrm[3 * cid];
+            const double* ue = g->body.u_eb;
+            acc += -g->aeb[cid] * (ue[0] * nv[0] + ue[1] * nv[1] + ue[2] * nv[2]);
+        }
+        div[c] = acc / h;
+    }
+}
+
+/* aperture-weighted average of the two face gradients in each direction */
+void or_gcc(const or_geom* g, const double* p, double* gp) {
+    const int* n = g->box.n;
+    long N = g->N;
+    double h = g->box.h;
+#pragma omp parallel for schedule(static)
+    for (long c = 0; c < N; c++) {
+        for (int d = 0; d < 3; d++) gp[d * N + c] = 0.0;
+        if (g->alpha[c] <= 0.0) continue;
+        int q[3];
+        cell_ijk(n, c, q);
+        for (int d = 0; d < 3; d++) {
+            double num = 0, den = 0;
+            for (int side = -1; side <= 1; side += 2) {
+                int f[3] = {q[0], q[1], q[2]};
+                if (side > 0) f[d] += 1;
+                double A = g->ap[d][fidx(n, d, f[0], f[1], f[2])];
+                if (A == 0.0) continue;
+                long lo, hi;
+                face_cells(g, d, f, &lo, &hi);
+                double gf = (lo >= 0 && hi >= 0) ? (p[hi] - p[lo]) / h : 0.0;
+                num += A * gf;
+                den += A;
+            }
+            gp[d * N + c] = den > 0 ? num / den : 0.0;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* 7-point operators and the multigrid preconditioner                                           */
+/* ------------------------------------------------------------------------------------------ */
+enum { SYS_POISSON = 0, SYS_VISC = 1 };
+
+/* level-0 face coefficients and cell shifts, then coarse levels by averaging */
+static void build_operator(or_geom* g, int sys, double beta, double rho, double dt,
+                           const double* eta, const double* eta_eb) {
+    level_t* L0 = &g->lev[0];
+    const int* n = g->box.n;
+    double h = g->box.h;
+    for (int d = 0; d < 3; d++) {
+        int m[3] = {n[0] + (d == 0), n[1] + (d == 1), n[2] + (d == 2)};
+        for (int k = 0; k < m[2]; k++)
+            for (int j = 0; j < m[1]; j++)
+                for (int i = 0; i < m[0]; i++) {
+                    int f[3] = {i, j, k};
+                    long fi = fidx(n, d, i, j, k);
+                    long lo, hi;
+                    face_cells(g, d, f, &lo, &hi);
+                    double A = g->ap[d][fi], K = 0.0;
+                    if (A > 0.0) {
+                        if (sys == SYS_POISSON) {
+                            K = (lo >= 0 && hi >= 0) ? beta * A / (h * h) : 0.0;
+                        } else {
+                            if (lo >= 0 && hi >= 0)
+                                K = dt * A * 0.5 * (eta[lo] + eta[hi]) / (h * h);
+                            else
+                                K = 2.0 * dt * A * eta[lo >= 0 ? lo : hi] / (h * h);
+                        }
+                    }
+                    L0->K[d][fi] = K;
+                }
+    }
+    for (long c = 0; c < g->N; c++) {
+        double s = 0.0;
+        if (sys == SYS_VISC && g->alpha[c] > 0.0) {
+            s = g->alpha[c] * rho;
+            long cid = g->cutid[c];
+            if (cid >= 0) {
+                double del = g->delta[cid] > 0.5 ? g->delta[cid] : 0.5;
+                s += dt * g->aeb[cid] * eta_eb[cid] / (del * h * h);
+            }
+        }
+        L0->S[c] = s;
+    }
+    for (int l = 1; l < g->nlev; l++) {
+        level_t* F = &g->lev[l - 1];
+        level_t* C = &g->lev[l];
+        for (int d = 0; d < 3; d++) {
+            int t1, t2;
+            others(d, &t1, &t2);
+            int m[3] = {C->n[0] + (d == 0), C->n[1] + (d == 1), C->n[2] + (d == 2)};
+            for (int k = 0; k < m[2]; k++)
+                for (int j = 0; j < m[1]; j++)
+                    for (int i = 0; i < m[0]; i++) {
+                        int q[3] = {i, j, k};
+                        double s = 0;
+                        for (int o1 = 0; o1 < 2; o1++)
+                            for (int o2 = 0; o2 < 2; o2++) {
+                                int r[3];
+                                r[d] = 2 * q[d];
+                                r[t1] = 2 * q[t1] + o1;
+                                r[t2] = 2 * q[t2] + o2;
+                                s += F->K[d][fidx(F->n, d, r[0], r[1], r[2])];
+                            }
+                        C->K[d][fidx(C->n, d, i, j, k)] = s / 16.0;
+                    }
+        }
+        for (int k = 0; k < C->n[2]; k++)
+            for (int j = 0; j < C->n[1]; j++)
+                for (int i = 0; i < C->n[0]; i++) {
+                    double s = 0;
+                    for (int c = 0; c < 8; c++)
+                        s += F->S[cidx(F->n, 2 * i + (c & 1), 2 * j + ((c >> 1) & 1),
+                                       2 * k + ((c >> 2) & 1))];
+                    C->S[cidx(C->n, i, j, k)] = s / 8.0;
+                }
+    }
+    for (int l = 0; l < g->nlev; l++) {
+        level_t* L = &g->lev[l];
+        for (int k = 0; k < L->n[2]; k++)
+            for (int j = 0; j < L->n[1]; j++)
+                for (int i = 0; i < L->n[0]; i++) {
+                    long c = cidx(L->n, i, j, k);
+                    double dsum = L->S[c];
+                    for (int d = 0; d < 3; d++) {
+                        int f[3] = {i, j, k};
+                        dsum += L->K[d][fidx(L->n, d, f[0], f[1], f[2])];
+                        f[d] += 1;
+                        dsum += L->K[d][fidx(L->n, d, f[0], f[1], f[2])];
+                    }
+                    L->D[c] = L->mask[c] ? dsum : 0.0;
+                }
+    }
+}
+
+/* sum over interior faces of K_f x_nb (domain-wall faces only enter the diagonal) */
+static double offdiag_sum(const or_geom* g, const level_t* L, const double* x, int i, int j,
+                          int k) {
+    const int* per = g->box.periodic;
+    double s = 0;
+    for (int d = 0; d < 3; d++)
+        for (int side = -1; side <= 1; side += 2) {
+            int f[3] = {i, j, k};
+            if (side > 0) f[d] += 1;
+            double K = L->K[d][fidx(L->n, d, f[0], f[1], f[2])];
+            if (K == 0.0) continue;
+            int r[3] = {i, j, k};
+            r[d] += side;
+            long nb = cell_at(L->n, per, r);
+            if (nb < 0) continue;
+            s += K * x[nb];
+        }
+    return s;
+}
+
+static void level_apply(const or_geom* g, const level_t* L, int ncomp, const double* x,
+                        double* y) {
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < L->n[2]; k++)
+        for (int j = 0; j < L->n[1]; j++)
+            for (int i = 0; i < L->n[0]; i++) {
+                long c = cidx(L->n, i, j, k);
+                for (int m = 0; m < ncomp; m++) {
+                    const double* xm = x + (long)m * L->N;
+                    y[(long)m * L->N + c] =
+                        L->mask[c] ? L->D[c] * xm[c] - offdiag_sum(g, L, xm, i, j, k) : 0.0;
+                }
+            }
+}
+
+/* one Gauss-Seidel half sweep over the cells of colour (i+j+k) mod 2 == col */
+static void smooth_colour(const or_geom* g, const level_t* L, int ncomp, const double* b,
+                          double* x, int col) {
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < L->n[2]; k++)
+        for (int j = 0; j < L->n[1]; j++)
+            for (int i = 0; i < L->n[0]; i++) {
+                if (((i + j + k) & 1) != col) continue;
+                long c = cidx(L->n, i, j, k);
+                if (!L->mask[c] || L->D[c] <= 0.0) continue;
+                for (int m = 0; m < ncomp; m++) {
+                    double* xm = x + (long)m * L->N;
+                    xm[c] = (b[(long)m * L->N + c] + offdiag_sum(g, L, xm, i, j, k)) / L->D[c];
+                }
+            }
+}
+
+static void vcycle_level(const or_geom* g, int l, int ncomp, const double* b, double* x,
+                         const or_opts* o) {
+    const level_t* L = &g->lev[l];
+    long N = L->N;
+    memset(x, 0, (size_t)ncomp * N * sizeof(double));
+    if (l == g->nlev - 1) {
+        for (int s = 0; s < o->nbottom; s++) {
+            smooth_colour(g, L, ncomp, b, x, 0);
+            smooth_colour(g, L, ncomp, b, x, 1);
+        }
+        for (int s = 0; s < o->nbottom; s++) {
+            smooth_colour(g, L, ncomp, b, x, 1);
+            smooth_colour(g, L, ncomp, b, x, 0);
+        }
+        return;
+    }
+    for (int s = 0; s < o->nu1; s++) {
+        smooth_colour(g, L, ncomp, b, x, 0);
+        smooth_colour(g, L, ncomp, b, x, 1);
+    }
+    const level_t* C = &g->lev[l + 1];
+    double* r = malloc((size_t)ncomp * N * sizeof(double));
+    level_apply(g, L, ncomp, x, r);
+    for (long t = 0; t < (long)ncomp * N; t++) r[t] = b[t] - r[t];
+    double* bc = calloc((size_t)ncomp * C->N, sizeof(double));
+    double* ec = malloc((size_t)ncomp * C->N * sizeof(double));
+    /* restriction: mean of the eight children (rows are already volume-fraction weighted) */
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < C->n[2]; k++)
+        for (int j = 0; j < C->n[1]; j++)
+            for (int i = 0; i < C->n[0]; i++) {
+                long cc = cidx(C->n, i, j, k);
+                for (int m = 0; m < ncomp; m++) {
+                    double s = 0;
+                    for (int q = 0; q < 8; q++) {
+                        long fc = cidx(L->n, 2 * i + (q & 1), 2 * j + ((q >> 1) & 1),
+                                       2 * k + ((q >> 2) & 1));
+                        if (L->mask[fc]) s += r[(long)m * N + fc];
+                    }
+                    bc[(long)m * C->N + cc] = C->mask[cc] ? s / 8.0 : 0.0;
+                }
+            }
+    vcycle_level(g, l + 1, ncomp, bc, ec, o);
+    /* piecewise-constant prolongation to uncovered children */
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < L->n[2]; k++)
+        for (int j = 0; j < L->n[1]; j++)
+            for (int i = 0; i < L->n[0]; i++) {
+                long fc = cidx(L->n, i, j, k);
+                if (!L->mask[fc]) continue;
+                long cc = cidx(C->n, i / 2, j / 2, k / 2);
+                for (int m = 0; m < ncomp; m++) x[(long)m * N + fc] += ec[(long)m * C->N + cc];
+            }
+    for (int s = 0; s < o->nu2; s++) {
+        smooth_colour(g, L, ncomp, b, x, 1);
+        smooth_colour(g, L, ncomp, b, x, 0);
+    }
+    free(r);
+    free(bc);
+    free(ec);
+}
+
+void or_vcycle(const or_geom* g_in, int system, double beta, double rho, double dt,
+               const double* eta, const double* eta_eb, const double* r, double* e,
+               const or_opts* o) {
+    or_geom* g = (or_geom*)g_in;
+    build_operator(g, system, beta, rho, dt, eta, eta_eb);
+    vcycle_level(g, 0, system == SYS_VISC ? 3 : 1, r, e, o);
+}
+
+void or_poisson_apply(const or_geom* g_in, double beta, const double* p, double* out) {
+    or_geom* g = (or_geom*)g_in;
+    build_operator(g, SYS_POISSON, beta, 0, 0, NULL, NULL);
+    level_apply(g, &g->lev[0], 1, p, out);
+}
+
+/* exact viscous Helmholtz operator (Eq. implicit-viscous) with the EB wall flux of Eq. dudn,
+ * rows multiplied by the volume fraction: alpha rho u - dt * (flux sum)/(h^2) + dt A_EB eta_EB g/h */
+void or_visc_apply(const or_geom* g, double rho, double dt, const double* eta,
+                   const double* eta_eb, const double* u, double* out, int homogeneous) {
+    const int* n = g->box.n;
+    const int* per = g->box.periodic;
+    long N = g->N;
+    double h = g->box.h;
+#pragma omp parallel for schedule(static)
+    for (long c = 0; c < N; c++) {
+        for (int j = 0; j < 3; j++) out[j * N + c] = 0.0;
+        if (g->alpha[c] <= 0.0) continue;
+        int q[3];
+        cell_ijk(n, c, q);
+        long cid = g->cutid[c];
+        for (int j = 0; j < 3; j++) {
+            const double* uj = u + (long)j * N;
+            double acc = g->alpha[c] * rho * uj[c];
+            for (int d = 0; d < 3; d++)
+                for (int side = -1; side <= 1; side += 2) {
+                    int f[3] = {q[0], q[1], q[2]};
+                    if (side > 0) f[d] += 1;
+                    double A = g->ap[d][fidx(n, d, f[0], f[1], f[2])];
+                    if (A == 0.0) continue;
+                    int r[3] = {q[0], q[1], q[2]};
+                    r[d] += side;
+                    long nb = cell_at(n, per, r);
+                    if (nb >= 0) {
+                        double K = dt * A * 0.5 * (eta[c] + eta[nb]) / (h * h);
+                        acc -= K * (uj[nb] - uj[c]);
+                    } else {
+                        double uw = homogeneous ? 0.0 : g->box.wall_u[2 * d + (side > 0)][j];
+                        double K = 2.0 * dt * A * eta[c] / (h * h);
+                        acc -= K * (uw - uj[c]);
+                    }
+                }
+            if (cid >= 0) {
+                double ueb = homogeneous ? 0.0 : g->body.u_eb[j];
+                acc += dt * g->aeb[cid] * eta_eb[cid] * wall_dudn(g, (int)cid, uj, ueb) / h;
+            }
+            out[j * N + c] = acc;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Krylov drivers around the V-cycle                                                            */
+/* ------------------------------------------------------------------------------------------ */
+static double vmaxabs(const double* x, long n) {
+    double m = 0;
+    for (long t = 0; t < n; t++)
+        if (fabs(x[t]) > m) m = fabs(x[t]);
+    return m;
+}
+static double vdot(const double* x, const double* y, long n) {
+    double s = 0;
+    for (long t = 0; t < n; t++) s += x[t] * y[t];
+    return s;
+}
+
+/* preconditioned CG on the symmetric Poisson system M p = b (operator already built) */
+static int pcg(or_geom* g, const double* b, double* x, double rtol, double scale, int maxit,
+               const or_opts* o, int* iters) {
+    long N = g->N;
+    level_t* L = &g->lev[0];
+    double* r = malloc(N * sizeof(double));
+    double* z = malloc(N * sizeof(double));
+    double* p = malloc(N * sizeof(double));
+    double* q = malloc(N * sizeof(double));
+    int ret = OR_ENOCONV;
+    *iters = 0;
+    level_apply(g, L, 1, x, r);
+    for (long t = 0; t < N; t++) r[t] = b[t] - r[t];
+    double bn = vmaxabs(b, N);
+    if (scale > bn) bn = scale;
+    if (bn == 0.0 || vmaxabs(r, N) <= rtol * bn) {
+        ret = OR_OK;
+        goto done;
+    }
+    vcycle_level(g, 0, 1, r, z, o);
+    memcpy(p, z, N * sizeof(double));
+    double rz = vdot(r, z, N);
+    for (int it = 1; it <= maxit; it++) {
+        level_apply(g, L, 1, p, q);
+        double a = rz / vdot(p, q, N);
+        for (long t = 0; t < N; t++) {
+            x[t] += a * p[t];
+            r[t] -= a * q[t];
+        }
+        *iters = it;
+        if (vmaxabs(r, N) <= rtol * bn) {
+            ret = OR_OK;
+            break;
+        }
+        vcycle_level(g, 0, 1, r, z, o);
+        double rzn = vdot(r, z, N);
+        double be = rzn / rz;
+        rz = rzn;
+        for (long t = 0; t < N; t++) p[t] = z[t] + be * p[t];
+    }
+done:
+    free(r);
+    free(z);
+    free(p);
+    free(q);
+    return ret;
+}
+
+/* Poisson solve for the projections: M p = -(D w - mean), then p normalised to zero mean.
+ * Stop when max|r| <= rtol * max(max|b|, scale); scale is the largest face flux |A w|/h, the
+ * size of the terms that make up the divergence (so an already solenoidal field stops at once). */
+static int poisson_solve(or_geom* g, double beta, const double* divw, double* p, double rtol,
+                         double scale, int maxit, const or_opts* o, int* iters) {
+    long N = g->N;
+    build_operator(g, SYS_POISSON, beta, 0, 0, NULL, NULL);
+    double* b = malloc(N * sizeof(double));
+    double s = 0;
+    long cnt = 0;
+    for (long c = 0; c < N; c++)
+        if (g->alpha[c] > 0.0) {
+            s += divw[c];
+            cnt++;
+        }
+    double mean = cnt ? s / cnt : 0.0;
+    for (long c = 0; c < N; c++) b[c] = g->alpha[c] > 0.0 ? -(divw[c] - mean) : 0.0;
+    int ret = pcg(g, b, p, rtol, scale, maxit, o, iters);
+    s = 0;
+    for (long c = 0; c < N; c++)
+        if (g->alpha[c] > 0.0) s += p[c];
+    mean = cnt ? s / cnt : 0.0;
+    for (long c = 0; c < N; c++) p[c] = g->alpha[c] > 0.0 ? p[c] - mean : 0.0;
+    free(b);
+    return ret;
+}
+
+int or_visc_solve(const or_geom* g_in, double rho, double dt, const double* eta,
+                  const double* eta_eb, const double* psi, double* x, double rtol, int maxit,
+                  const or_opts* o, int* iters) {
+    or_geom* g = (or_geom*)g_in;
+    long N = g->N, N3 = 3 * N;
+    build_operator(g, SYS_VISC, 0, rho, dt, eta, eta_eb);
+    double* r = malloc(N3 * sizeof(double));
+    double* rh = malloc(N3 * sizeof(double));
+    double* p = calloc(N3, sizeof(double));
+    double* v = calloc(N3, sizeof(double));
+    double* ph = malloc(N3 * sizeof(double));
+    double* s = malloc(N3 * sizeof(double));
+    double* sh = malloc(N3 * sizeof(double));
+    double* t = malloc(N3 * sizeof(double));
+    double* zero = calloc(N3, sizeof(double));
+    int ret = OR_ENOCONV;
+    *iters = 0;
+    /* effective right-hand side b = alpha psi - A(0) (boundary values moved to the right) */
+    or_visc_apply(g, rho, dt, eta, eta_eb, zero, t, 0);
+    for (long q = 0; q < N3; q++) {
+        long c = q % N;
+        double b = g->alpha[c] > 0.0 ? g->alpha[c] * psi[q] : 0.0;
+        s[q] = b - t[q];
+    }
+    double bn = vmaxabs(s, N3);
+    double tol = rtol * bn;
+    or_visc_apply(g, rho, dt, eta, eta_eb, x, t, 0);
+    for (long q = 0; q < N3; q++) {
+        long c = q % N;
+        double b = g->alpha[c] > 0.0 ? g->alpha[c] * psi[q] : 0.0;
+        r[q] = b - t[q];
+    }
+    if (bn == 0.0 || vmaxabs(r, N3) <= tol) {
+        ret = OR_OK;
+        goto done;
+    }
+    memcpy(rh, r, N3 * sizeof(double));
+    double rho_old = 1, al = 1, om = 1;
+    for (int it = 1; it <= maxit; it++) {
+        double rr = vdot(rh, r, N3);
+        double be = (rr / rho_old) * (al / om);
+        for (long q = 0; q < N3; q++) p[q] = r[q] + be * (p[q] - om * v[q]);
+        vcycle_level(g, 0, 3, p, ph, o);
+        or_visc_apply(g, rho, dt, eta, eta_eb, ph, v, 1);
+        al = rr / vdot(rh, v, N3);
+        for (long q = 0; q < N3; q++) s[q] = r[q] - al * v[q];
+        *iters = it;
+        if (vmaxabs(s, N3) <= tol) {
+            for (long q = 0; q < N3; q++) x[q] += al * ph[q];
+            ret = OR_OK;
+            break;
+        }
+        vcycle_level(g, 0, 3, s, sh, o);
+        or_visc_apply(g, rho, dt, eta, eta_eb, sh, t, 1);
+        om = vdot(t, s, N3) / vdot(t, t, N3);
+        for (long q = 0; q < N3; q++) {
+            x[q] += al * ph[q] + om * sh[q];
+            r[q] = s[q] - om * t[q];
+        }
+        if (vmaxabs(r, N3) <= tol) {
+            ret = OR_OK;
+            break;
+        }
+        rho_old = rr;
+    }
+done:
+    free(r);
+    free(rh);
+    free(p);
+    free(v);
+    free(ph);
+    free(s);
+    free(sh);
+    free(t);
+    free(zero);
+    return ret;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* projections                                                                                  */
+/* ------------------------------------------------------------------------------------------ */
+/* face correction w -= beta (p_hi - p_lo)/h on open interior faces */
+static void face_correct(const or_geom* g, double beta, const double* p, double* const fo[3]) {
+    const int* n = g->box.n;
+    double h = g->box.h;
+    for (int d = 0; d < 3; d++) {
+        int m[3] = {n[0] + (d == 0), n[1] + (d == 1), n[2] + (d == 2)};
+        for (int k = 0; k < m[2]; k++)
+            for (int j = 0; j < m[1]; j++)
+                for (int i = 0; i < m[0]; i++) {
+                    int f[3] = {i, j, k};
+                    long fi = fidx(n, d, i, j, k);
+                    long lo, hi;
+                    face_cells(g, d, f, &lo, &hi);
+                    if (lo < 0 || hi < 0 || g->ap[d][fi] == 0.0) continue;
+                    fo[d][fi] -= beta * (p[hi] - p[lo]) / h;
+                }
+    }
+}
+
+/* cell-centred (MAC) projection of a face field (Eq. helmholtz and the Poisson problem) */
+int or_mac_project(const or_geom* g_in, double beta, double* fx, double* fy, double* fz,
+                   double* phi, double rtol, int maxit, const or_opts* o, double* div_inf,
+                   int* iters) {
+    or_geom* g = (or_geom*)g_in;
+    long N = g->N;
+    double* div = malloc(N * sizeof(double));
+    double* fo[3] = {fx, fy, fz};
+    or_divergence(g, fx, fy, fz, div);
+    double scale = 0;
+    for (int d = 0; d < 3; d++)
+        for (long f = 0; f < nfaces(g->box.n, d); f++) {
+            double a = fabs(g->ap[d][f] * fo[d][f]) / g->box.h;
+            if (a > scale) scale = a;
+        }
+    int ret = poisson_solve(g, beta, div, phi, rtol, scale, maxit, o, iters);
+    face_correct(g, beta, phi, fo);
+    or_divergence(g, fx, fy, fz, div);
+    if (div_inf) *div_inf = vmaxabs(div, N);
+    free(div);
+    return ret;
+}
+
+/* end-of-stage projection with cell-centred pressure (reading of the approximate projection):
+ * add back beta*G p_old, average to faces, project the faces exactly, correct the cells with
+ * the averaged face gradients of the new pressure. */
+int or_cc_project(const or_geom* g_in, double beta, double* u, double* p, double rtol,
+                  int maxit, const or_opts* o, double* div_inf, int* iters) {
+    or_geom* g = (or_geom*)g_in;
+    const int* n = g->box.n;
+    long N = g->N;
+    double* gp = malloc(3 * N * sizeof(double));
+    double* fo[3];
+    for (int d = 0; d < 3; d++) fo[d] = calloc(nfaces(n, d), sizeof(double));
+    or_gcc(g, p, gp);
+    for (long q = 0; q < 3 * N; q++)
+        if (g->alpha[q % N] > 0.0) u[q] += beta * gp[q];
+    for (int d = 0; d < 3; d++) {
+        int m[3] = {n[0] + (d == 0), n[1] + (d == 1), n[2] + (d == 2)};
+        for (int k = 0; k < m[2]; k++)
+            for (int j = 0; j < m[1]; j++)
+                for (int i = 0; i < m[0]; i++) {
+                    int f[3] = {i, j, k};
+                    long fi = fidx(n, d, i, j, k);
+                    long lo, hi;
+                    face_cells(g, d, f, &lo, &hi);
+                    double v = 0.0;
+                    if (lo < 0 || hi < 0)
+                        v = g->box.wall_u[2 * d + (lo >= 0)][d];
+                    else if (g->ap[d][fi] > 0.0)
+                        v = 0.5 * (u[(long)d * N + lo] + u[(long)d * N + hi]);
+                    fo[d][fi] = v;
+                }
+    }
+    int ret = or_mac_project(g, beta, fo[0], fo[1], fo[2], p, rtol, maxit, o, div_inf, iters);
+    or_gcc(g, p, gp);
+    for (long q = 0; q < 3 * N; q++)
+        if (g->alpha[q % N] > 0.0) u[q] -= beta * gp[q];
+    for (int d = 0; d < 3; d++) free(fo[d]);
+    free(gp);
+    return ret;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* DerivedQuantities (Alg. derived) and the RK2 step (Alg. advance)                             */
+/* ------------------------------------------------------------------------------------------ */
+int or_derived(const or_geom* g_in, const or_rheo* rh, const double* theta, const double* u,
+               const or_opts* o, double* C, double* eta, double* eta_eb, double* V,
+               int* iters) {
+    or_geom* g = (or_geom*)g_in;
+    const int* n = g->box.n;
+    long N = g->N;
+    double* uf[3];
+    for (int d = 0; d < 3; d++) uf[d] = calloc(nfaces(n, d), sizeof(double));
+    double* phi = calloc(N, sizeof(double));
+    or_face_extrap(g, u, uf[0], uf[1], uf[2]);
+    int ret = or_mac_project(g, 1.0, uf[0], uf[1], uf[2], phi, o->rtol_mac, o->max_iter, o,
+                             NULL, iters);
+    or_conv_term(g, u, uf[0], uf[1], uf[2], C);
+    double* gw = calloc(3 * (g->ncut + 1), sizeof(double));
+    double* G = malloc(9 * N * sizeof(double));
+    double* DC = malloc(3 * N * sizeof(double));
+    or_wall_gradient(g, u, gw);
+    or_cell_gradient(g, u, gw, G);
+    viscosity_from(g, rh, theta, G, gw, eta, eta_eb, NULL);
+    transpose_term_dc(g, eta, eta_eb, u, G, gw, DC);
+    or_redistribute(g, 3, DC, V);
+    free(DC);
+    free(G);
+    free(gw);
+    free(phi);
+    for (int d = 0; d < 3; d++) free(uf[d]);
+    return ret;
+}
+
+int or_rk2_step(const or_geom* g_in, const or_rheo* rh, const double* theta, double dt,
+                const or_opts* o, double* u, double* p, or_stats* st) {
+    or_geom* g = (or_geom*)g_in;
+    long N = g->N, N3 = 3 * N;
+    int nc = g->ncut + 1;
+    double rho = rh->rho, beta = dt / rh->rho;
+    double *Cm = malloc(N3 * 8), *Vm = malloc(N3 * 8), *em = malloc(N * 8), *ebm = malloc(nc * 8);
+    double *Cs = malloc(N3 * 8), *Vs = malloc(N3 * 8), *es = malloc(N * 8), *ebs = malloc(nc * 8);
+    double *psi = malloc(N3 * 8), *gp = malloc(N3 * 8), *ut = malloc(N3 * 8);
+    double *ps = malloc(N * 8);
+    int err = OR_OK, e, it;
+    or_stats loc;
+    memset(&loc, 0, sizeof(loc));
+    /* predictor */
+    e = or_derived(g, rh, theta, u, o, Cm, em, ebm, Vm, &it);
+    loc.it_mac[0] = it;
+    if (e) err = e;
+    or_gcc(g, p, gp);
+    for (long q = 0; q < N3; q++) {
+        int d = (int)(q / N);
+        psi[q] = rho * u[q] + dt * (rho * Cm[q] + Vm[q] - gp[q] + o->force[d]);
+    }
+    memcpy(ut, u, N3 * 8);
+    e = or_visc_solve(g, rho, dt, em, ebm, psi, ut, o->rtol_visc, o->max_iter, o, &it);
+    loc.it_visc[0] = it;
+    if (e) err = e;
+    memcpy(ps, p, N * 8);
+    e = or_cc_project(g, beta, ut, ps, o->rtol_proj, o->max_iter, o, &loc.div_proj[0], &it);
+    loc.it_proj[0] = it;
+    if (e) err = e;
+    /* corrector: derived quantities at u*, averaged with those at u^m */
+    e = or_derived(g, rh, theta, ut, o, Cs, es, ebs, Vs, &it);
+    loc.it_mac[1] = it;
+    if (e) err = e;
+    for (long q = 0; q < N3; q++) {
+        Cm[q] = 0.5 * (Cm[q] + Cs[q]);
+        Vm[q] = 0.5 * (Vm[q] + Vs[q]);
+    }
+    for (long c = 0; c < N; c++) em[c] = 0.5 * (em[c] + es[c]);
+    for (int c = 0; c < g->ncut; c++) ebm[c] = 0.5 * (ebm[c] + ebs[c]);
+    or_gcc(g, ps, gp);
+    for (long q = 0; q < N3; q++) {
+        int d = (int)(q / N);
+        psi[q] = rho * u[q] + dt * (rho * Cm[q] + Vm[q] - gp[q] + o->force[d]);
+    }
+    e = or_visc_solve(g, rho, dt, em, ebm, psi, ut, o->rtol_visc, o->max_iter, o, &it);
+    loc.it_visc[1] = it;
+    if (e) err = e;
+    e = or_cc_project(g, beta, ut, ps, o->rtol_proj, o->max_iter, o, &loc.div_proj[1], &it);
+    loc.it_proj[1] = it;
+    if (e) err = e;
+    for (long q = 0; q < N3; q++) {
+        long c = q % N;
+        u[q] = g->alpha[c] > 0.0 ? ut[q] : g->body.u_eb[q / N];
+    }
+    for (long c = 0; c < N; c++) p[c] = g->alpha[c] > 0.0 ? ps[c] : 0.0;
+    if (st) *st = loc;
+    free(Cm); free(Vm); free(em); free(ebm);
+    free(Cs); free(Vs); free(es); free(ebs);
+    free(psi); free(gp); free(ut); free(ps);
+    return err;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* drag on the embedded body (Eq. drag-force): sum over cut cells of (tau - p I) n A_EB h^2     */
+/* ------------------------------------------------------------------------------------------ */
+void or_drag(const or_geom* g, const or_rheo* r, const double* theta, const double* u,
+             const double* p, double F[3]) {
+    long N = g->N;
+    double h = g->box.h;
+    double* gw = calloc(3 * (g->ncut + 1), sizeof(double));
+    double* gp = malloc(3 * N * sizeof(double));
+    or_wall_gradient(g, u, gw);
+    or_gcc(g, p, gp);
+    F[0] = F[1] = F[2] = 0.0;
+    for (int cid = 0; cid < g->ncut; cid++) {
+        long c = g->cut[cid];
+        const double* nv = &g->nrm[3 * cid];
+        const double* gg = &gw[3 * cid];
+        double Gm[3][3];
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) Gm[a][b] = nv[a] * gg[b];
+        double eeb = law_eta(r, r->tau0 * (theta ? theta[c] : 1.0), strain_norm(Gm));
+        double pe = p[c];
+        for (int d = 0; d < 3; d++) pe += h * g->bc[3 * cid + d] * gp[d * N + c];
+        for (int a = 0; a < 3; a++) {
+            double tn = 0;
+            for (int b = 0; b < 3; b++) tn += eeb * (Gm[a][b] + Gm[b][a]) * nv[b];
+            F[a] += g->aeb[cid] * h * h * (tn - pe * nv[a]);
+        }
+    }
+    free(gw);
+    free(gp);
+}

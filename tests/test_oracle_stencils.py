@@ -1,0 +1,134 @@
+"""Oracle pins for the pointwise stencils of Sec. III.B.3-4 and the viscosity laws of Sec. II.B.
+
+* Central and one-sided three-point cell gradients are exact for quadratic fields.
+* The EB wall gradient (biquadratic interpolation in two planes and Eq. dudn) is exact for a
+  quadratic field that vanishes on a planar wall.
+* The apparent viscosity reproduces each law of Table rheology at a known strain rate, with
+  the Papanastasiou limit mu + tau0/eps at zero strain, and eta == mu bitwise when tau0 = 0.
+"""
+import numpy as np
+import pytest
+
+import eb_inputs as I
+
+
+def quad_field(shape3, h, seed):
+    nz, ny, nx = shape3
+    rng = np.random.default_rng(seed)
+    coef = rng.standard_normal((3, 10))
+    z, y, x = np.meshgrid((np.arange(nz) + 0.5) * h, (np.arange(ny) + 0.5) * h,
+                          (np.arange(nx) + 0.5) * h, indexing="ij")
+    mons = [np.ones_like(x), x, y, z, x * x, y * y, z * z, x * y, y * z, x * z]
+    dmons = {  # d/dx, d/dy, d/dz
+        0: [0 * x, 1 + 0 * x, 0 * x, 0 * x, 2 * x, 0 * x, 0 * x, y, 0 * x, z],
+        1: [0 * x, 0 * x, 1 + 0 * x, 0 * x, 0 * x, 2 * y, 0 * x, x, z, 0 * x],
+        2: [0 * x, 0 * x, 0 * x, 1 + 0 * x, 0 * x, 0 * x, 2 * z, 0 * x, y, x],
+    }
+    u = np.stack([sum(c * m for c, m in zip(coef[j], mons)) for j in range(3)])
+    G = np.zeros((3, 3) + shape3)
+    for d in range(3):
+        for j in range(3):
+            G[d, j] = sum(c * m for c, m in zip(coef[j], dmons[d]))
+    return np.ascontiguousarray(u), G
+
+
+def test_cell_gradient_exact_for_quadratics(oracle_lib):
+    O = oracle_lib
+    w = I.sphere32()
+    g = O.Geometry(w)
+    u, Gex = quad_field(g.shape, w.h, 3)
+    G = g.cell_gradient(u)
+    flag, alpha, _ = g.export()
+    n = w.n[0]
+    open_ = alpha > 0
+    checked = onesided = 0
+    for k in range(2, n - 2):
+        for j in range(2, n - 2):
+            for i in range(2, n - 2):
+                if not open_[k, j, i]:
+                    continue
+                for d in range(3):
+                    e = np.zeros(3, int)
+                    e[d] = 1
+                    lo = (k - e[2], j - e[1], i - e[0])
+                    hi = (k + e[2], j + e[1], i + e[0])
+                    lo2 = (k - 2 * e[2], j - 2 * e[1], i - 2 * e[0])
+                    hi2 = (k + 2 * e[2], j + 2 * e[1], i + 2 * e[0])
+                    a_lo, a_hi = open_[lo], open_[hi]
+                    exact_ok = (a_lo and a_hi) or (a_hi and not a_lo and open_[hi2]) or \
+                               (a_lo and not a_hi and open_[lo2])
+                    if not exact_ok:
+                        continue
+                    onesided += not (a_lo and a_hi)
+                    assert np.allclose(G[d, :, k, j, i], Gex[d, :, k, j, i], rtol=0, atol=1e-11)
+                    checked += 1
+    assert checked > 1000 and onesided > 50
+
+
+def test_wall_gradient_exact_on_planar_wall(oracle_lib):
+    O = oracle_lib
+    n = 16
+    nv = np.array([0.35, 0.8, -0.45])
+    nv /= np.linalg.norm(nv)
+    d = float(nv @ np.array([0.5, 0.5, 0.5]) + 0.021)
+    w = I.Workload(name="plane", n=(n, n, n), h=1.0 / n,
+                   body={"kind": I.BODY_PLANE, "plane_n": tuple(nv), "plane_d": d})
+    g = O.Geometry(w)
+    h = w.h
+    nz, ny, nx = g.shape
+    z, y, x = np.meshgrid((np.arange(nz) + 0.5) * h, (np.arange(ny) + 0.5) * h,
+                          (np.arange(nx) + 0.5) * h, indexing="ij")
+    rng = np.random.default_rng(5)
+    a = rng.standard_normal((3, 3))
+    c0 = rng.standard_normal(3)
+    phi = nv[0] * x + nv[1] * y + nv[2] * z - d
+    u = np.stack([phi * (a[j, 0] * x + a[j, 1] * y + a[j, 2] * z + c0[j]) for j in range(3)])
+    gw = g.wall_gradient(np.ascontiguousarray(u))
+    cell, data = g.cut()
+    checked = 0
+    for cid, (c, row) in enumerate(zip(cell, data)):
+        k, rem = divmod(int(c), n * n)
+        j, i = divmod(rem, n)
+        if min(i, j, k) < 3 or max(i, j, k) > n - 4 or row[8] != 0:
+            continue
+        xb = (np.array([i, j, k]) + 0.5) * h + h * row[4:7]
+        exact = a @ xb + c0
+        assert np.allclose(gw[cid], exact, rtol=0, atol=1e-10), (gw[cid], exact)
+        checked += 1
+    assert checked > 20
+
+
+@pytest.mark.parametrize("law", [I.LAW_NEWTONIAN, I.LAW_BINGHAM_REG, I.LAW_PAPANASTASIOU])
+def test_viscosity_laws_on_simple_shear(oracle_lib, law):
+    """u = (s z, 0, 0) in a periodic-x,y box: |gamma| = |s| exactly in every interior cell."""
+    O = oracle_lib
+    n = 8
+    s = 0.37
+    w = I.Workload(name="shear", n=(4, 4, n), h=1.0 / n, periodic=(1, 1, 0), law=law, mu=1.3,
+                   tau0=2.1, eps=0.05)
+    w.wall_u[4] = [0.0, 0.0, 0.0]
+    w.wall_u[5] = [s * 1.0, 0.0, 0.0]
+    g = O.Geometry(w)
+    zc = (np.arange(n) + 0.5) * w.h
+    u = np.zeros((3,) + g.shape)
+    u[0] = (s * zc)[:, None, None]
+    eta, _, sr = g.viscosity(u, O.make_rheo(w), with_sr=True)
+    assert np.allclose(sr, abs(s), rtol=1e-14)
+    ex = {I.LAW_NEWTONIAN: 1.3, I.LAW_BINGHAM_REG: 1.3 + 2.1 / (s + 0.05),
+          I.LAW_PAPANASTASIOU: 1.3 + 2.1 * (1 - np.exp(-s / 0.05)) / s}[law]
+    assert np.allclose(eta, ex, rtol=1e-14)
+    # zero strain: the Papanastasiou value is the limit mu + tau0/eps
+    eta0, _ = g.viscosity(np.zeros_like(u), O.make_rheo(w))
+    ex0 = {I.LAW_NEWTONIAN: 1.3, I.LAW_BINGHAM_REG: 1.3 + 2.1 / 0.05,
+           I.LAW_PAPANASTASIOU: 1.3 + 2.1 / 0.05}[law]
+    assert np.allclose(eta0[:-1], ex0, rtol=1e-14)  # the top cell sees the moving wall
+
+
+def test_newtonian_limit_bitwise(oracle_lib):
+    O = oracle_lib
+    w = I.sphere32()
+    g = O.Geometry(w)
+    u, p = O.prepare_state(w, g)
+    for law in (I.LAW_BINGHAM_REG, I.LAW_PAPANASTASIOU):
+        eta, eta_eb = g.viscosity(u, O.make_rheo(w.replace(law=law), tau0=0.0))
+        assert np.all(eta == w.mu) and np.all(eta_eb == w.mu)
