@@ -1,0 +1,221 @@
+/*
+ * eb.h -- C ABI of the MI355X (gfx950) library for one two-stage Runge-Kutta step of 3D
+ * incompressible generalised-Newtonian flow on a single box with embedded-boundary (EB) cut
+ * cells (Sverdrup, Almgren & Nikiforakis, "An embedded boundary approach for efficient
+ * simulations of viscoplastic fluids in three dimensions").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Pointers marked (device) are HIP device pointers; (host) are host pointers.
+ *  - Cell fields are [nz][ny][nx] C-contiguous (x fastest), index c = i + nx*(j + ny*k).
+ *    Vector fields are component-major [3][nz][ny][nx].  Face fields normal to x, y, z are
+ *    [nz][ny][nx+1], [nz][ny+1][nx], [nz+1][ny][nx].  Per-cut-cell arrays follow the order of
+ *    the cut list (ascending cell index).  All floating point data are IEEE binary64.
+ *  - Ownership: the caller owns every buffer, including the device workspace handed to
+ *    eb_geometry_build.  The library never allocates device memory.  The context (host
+ *    memory, allocated by the library) refers into the workspace, so the workspace must stay
+ *    alive until eb_ctx_destroy.  A context is not thread safe; calls on one context must be
+ *    serialised by the caller.
+ *  - Streams: `stream` is a hipStream_t passed as void*; NULL is the default stream.  Work is
+ *    enqueued on it.  Entry points that return host values (iteration counts, norms, forces)
+ *    synchronise that stream before returning; the solvers read one residual norm back per
+ *    iteration.
+ *  - Errors: every entry point returns 0 (EB_OK) or a negative code; eb_last_error() gives a
+ *    thread-local message.  No exception crosses the ABI.  On EB_ENOCONV outputs hold the last
+ *    iterate.
+ *  - Covered cells (volume fraction 0) take u = u_EB, p = 0, eta = mu on output.
+ */
+#ifndef EB_H
+#define EB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    EB_OK = 0,
+    EB_EINVAL = -1,   /* null pointer, bad size, odd cell count, non-positive h */
+    EB_EGEOM = -2,    /* ambiguous cut face, degenerate cut cell, wall stencil leaves the box */
+    EB_ENOCONV = -3,  /* a linear solve hit max_iter */
+    EB_ENAN = -4,     /* non-finite residual */
+    EB_EHIP = -5,     /* HIP runtime error (message carries hipGetErrorString) */
+    EB_ENOMEM = -6    /* workspace smaller than eb_workspace_bytes() */
+};
+
+enum { EB_BODY_NONE = 0, EB_BODY_SPHERE = 1, EB_BODY_ELLIPSOID = 2, EB_BODY_ZSLAB = 3,
+       EB_BODY_PLANE = 4 };
+
+/* Apparent-viscosity laws (Sec. II.B, Table rheology; Eq. papabing:viscosity):
+ *   NEWTONIAN      eta = mu
+ *   BINGHAM_REG    eta = mu + tau0/(|gamma| + eps)
+ *   PAPANASTASIOU  eta = mu + tau0 (1 - exp(-|gamma|/eps))/|gamma|   (mu + tau0/eps at 0) */
+enum { EB_LAW_NEWTONIAN = 0, EB_LAW_BINGHAM_REG = 1, EB_LAW_PAPANASTASIOU = 2 };
+
+enum { EB_FP64 = 0, EB_MIXED = 1 };            /* precision of the multigrid preconditioner */
+enum { EB_SYS_POISSON = 0, EB_SYS_VISC = 1 };  /* system for eb_mg_vcycle */
+
+typedef struct {
+    int n[3];             /* cells per direction; each a multiple of 2 */
+    double h;             /* cell size (> 0) */
+    double lo[3];         /* lower domain corner */
+    int periodic[3];      /* 1 = periodic in that direction */
+    double wall_u[6][3];  /* Dirichlet velocity of the faces -x,+x,-y,+y,-z,+z */
+} eb_box;
+
+typedef struct {
+    int kind;             /* EB_BODY_* */
+    double center[3];
+    double radii[3];      /* sphere: radii[0]; ellipsoid: semi-axes */
+    double euler_zyx[3];  /* ellipsoid orientation R = Rz(a) Ry(b) Rx(c) */
+    double zlo, zhi;      /* z-slab: fluid where zlo < z < zhi */
+    double plane_n[3];    /* plane: fluid where plane_n . x > plane_d */
+    double plane_d;
+    double u_eb[3];       /* velocity of the embedded wall (no slip) */
+} eb_body;
+
+typedef struct {
+    int law;              /* EB_LAW_* */
+    double mu, tau0, eps, rho;
+} eb_rheology;
+
+typedef struct {
+    int precision;        /* EB_FP64 or EB_MIXED */
+    double rtol_visc, rtol_mac, rtol_proj;  /* max-norm relative residual targets */
+    int max_iter;         /* per solve */
+    int nu1, nu2;         /* pre/post red-black Gauss-Seidel pairs per level */
+    int nbottom;          /* sweep pairs on the coarsest level */
+    double force[3];      /* body force per unit volume (host values) */
+} eb_step_opts;
+
+typedef struct {
+    int it_mac[2], it_visc[2], it_proj[2];  /* Krylov iterations, predictor / corrector */
+    double div_proj[2];                     /* max |div| of the projected face field */
+    int vcycles;                            /* V-cycles executed in the step */
+    int status;                             /* worst return code of the step's solves */
+} eb_step_stats;
+
+typedef struct eb_ctx eb_ctx;
+
+/* Device workspace (bytes) that eb_geometry_build needs for this box and body.  Host only. */
+size_t eb_workspace_bytes(const eb_box* box, const eb_body* body);
+
+/* Builds the cut-cell geometry on the device (Sec. III.B: planar cut per cell, continuous at
+ * faces; flags, volume fractions, face apertures, EB normal into the fluid, EB area and
+ * centroid, the wall-flux stencils of Eqs. interpolation_distances and dudn) and the
+ * multigrid level hierarchy.  ws: (device) workspace of ws_bytes >= eb_workspace_bytes().
+ * On success *ctx receives a new context.  Errors: EB_EINVAL, EB_ENOMEM, EB_EGEOM, EB_EHIP. */
+int eb_geometry_build(const eb_box* box, const eb_body* body, void* ws, size_t ws_bytes,
+                      eb_ctx** ctx, void* stream);
+
+/* Releases the host context (not the caller's workspace). */
+void eb_ctx_destroy(eb_ctx* ctx);
+
+/* Number of cut cells, multigrid levels, and wall stencils that needed the covered-node
+ * fallback.  Host only. */
+int eb_ctx_info(const eb_ctx* ctx, int* ncut, int* nlevels, int* nfallback);
+
+/* Copies the geometry into caller buffers (device): flag u8[N] (0 covered, 1 cut, 2 regular),
+ * alpha[N], apertures ax, ay, az (face layouts above); cut_cell int64[ncut]; cut_data
+ * [ncut][9] = (n_x, n_y, n_z, A_EB, b_x, b_y, b_z, delta, fallback planes).  Any pointer may
+ * be NULL to skip it. */
+int eb_geometry_export(const eb_ctx* ctx, uint8_t* flag, double* alpha, double* ax, double* ay,
+                       double* az, int64_t* cut_cell, double* cut_data, void* stream);
+
+/* Strain rate and apparent viscosity (Sec. III.B.4, Sec. II Eq. governing:stress):
+ * cell gradients by central differences, or one-sided quadratic differences where a face
+ * neighbour is covered; |gamma| = sqrt(tr(gamma gamma^T)/2) with gamma = grad u + grad u^T;
+ * eta from the law with tau0_i = tau0*theta_i.  At cut cells eta_eb comes from the wall
+ * gradient n (x) du/dn of Eq. dudn.  u (device) [3][N]; theta (device, nullable = 1) [N];
+ * eta (device) [N]; eta_eb (device) [ncut]; sr (device, nullable) [N]. */
+int eb_apparent_viscosity(const eb_ctx* ctx, const eb_rheology* rheo, const double* u,
+                          const double* theta, double* eta, double* eta_eb, double* sr,
+                          void* stream);
+
+/* Viscous operators, (device) arrays:
+ *  EB_OP_HELMHOLTZ   out = alpha rho u - dt [div(eta grad u)] with the EB wall flux of
+ *                    Eq. dudn, rows multiplied by the volume fraction (Eq. implicit-viscous);
+ *                    Dirichlet domain walls and u_EB enter as given.
+ *  EB_OP_HELMHOLTZ_H the same with homogeneous boundary values (the linear part).
+ *  EB_OP_TRANSPOSE   out = div(eta (grad u)^T) (Eq. explicit-viscous without 1/rho), hybrid
+ *                    divergence with flux redistribution (Eqs. divergence_conservative ...
+ *                    divergence_final); rho and dt are ignored. */
+enum { EB_OP_HELMHOLTZ = 0, EB_OP_HELMHOLTZ_H = 1, EB_OP_TRANSPOSE = 2 };
+int eb_viscous_apply(const eb_ctx* ctx, int mode, double rho, double dt, const double* eta,
+                     const double* eta_eb, const double* u, double* out, void* stream);
+
+/* One multigrid V-cycle e = V(r) of the preconditioner for `system`, from a zero guess:
+ * red-black Gauss-Seidel (nu1 pre, nu2 post pairs), volume-fraction-weighted restriction
+ * (mean of the children of the already alpha-weighted rows), piecewise-constant prolongation
+ * to uncovered children, nbottom sweep pairs on the coarsest level.  Poisson: beta*div(A grad)
+ * with apertures A (the projection operator).  Viscous: the 7-point part of the Helmholtz
+ * operator with the EB flux replaced by a diagonal term.  r, e (device): [N] for Poisson,
+ * [3][N] for the viscous system.  eta/eta_eb used only for the viscous system. */
+int eb_mg_vcycle(eb_ctx* ctx, int system, int precision, double beta, double rho, double dt,
+                 const double* eta, const double* eta_eb, const double* r, double* e,
+                 const eb_step_opts* opts, void* stream);
+
+/* One red-black Gauss-Seidel half sweep (cells with (i+j+k) mod 2 == colour) on the finest
+ * multigrid level, with the operator built by the most recent eb_mg_vcycle or solve for
+ * `system` at `precision` (EB_FP64: b, x are (device) double [ncomp][N]; EB_MIXED: float).
+ * ncomp = 1 (Poisson) or 3 (viscous).  The multigrid smoother in isolation, for timing and
+ * tests; EB_EINVAL if no operator of that kind has been built. */
+int eb_mg_sweep(eb_ctx* ctx, int system, int precision, int colour, const void* b, void* x,
+                void* stream);
+
+/* Implicit viscous solve (Eq. implicit-viscous): (alpha rho - dt div(eta grad)) x = alpha psi
+ * with the EB wall flux, BiCGSTAB right-preconditioned by eb_mg_vcycle, stopped when
+ * max|r| <= rtol max|b|.  psi (device) [3][N]; x (device) [3][N] in: guess, out: solution.
+ * *iters (host, nullable).  Returns EB_ENOCONV after max_iter. */
+int eb_visc_solve(eb_ctx* ctx, double rho, double dt, const double* eta, const double* eta_eb,
+                  const double* psi, double* x, double rtol, const eb_step_opts* opts,
+                  int* iters, void* stream);
+
+/* Cell-centred (MAC) projection of a face field (Eq. helmholtz and the Poisson problem that
+ * follows it): beta div(A grad phi) = div(A w), w -= beta grad phi on open faces.  fx, fy, fz
+ * (device) face fields, in/out; phi (device) [N], in: guess, out: zero-mean solution.
+ * *div_inf (host, nullable) = max |div(A w)| after the correction; *iters (host, nullable). */
+int eb_mac_project(eb_ctx* ctx, double beta, double* fx, double* fy, double* fz, double* phi,
+                   double rtol, const eb_step_opts* opts, double* div_inf, int* iters,
+                   void* stream);
+
+/* End-of-stage projection with a cell-centred pressure (Sec. III.A.4 approximated by the exact
+ * projection of face-averaged velocities): u += beta G p; w = face average of u; project w;
+ * u -= beta G p_new with G the aperture-weighted average of the two face gradients.
+ * u (device) [3][N] in/out; p (device) [N] in: old pressure, out: new pressure. */
+int eb_cc_project(eb_ctx* ctx, double beta, double* u, double* p, double rtol,
+                  const eb_step_opts* opts, double* div_inf, int* iters, void* stream);
+
+/* DerivedQuantities (Alg. derived): limited slopes, face extrapolation and upwinding, the
+ * MAC projection, convective term C = -div(u (x) u^F), eta and eta_eb, and the explicit term
+ * V = div(eta (grad u)^T), both divergences hybridised and redistributed.  (device) arrays:
+ * u [3][N] in; C [3][N], eta [N], eta_eb [ncut], V [3][N] out. */
+int eb_derived(eb_ctx* ctx, const eb_rheology* rheo, const double* theta, const double* u,
+               const eb_step_opts* opts, double* C, double* eta, double* eta_eb, double* V,
+               int* iters, void* stream);
+
+/* One RK2 step (Alg. advance): predictor and corrector, each DerivedQuantities, the
+ * semi-implicit viscous solve and the end-of-stage projection; the corrector averages C, eta,
+ * eta_eb and V.  u (device) [3][N] and p (device) [N] in/out.  stats (host, nullable). */
+int eb_rk2_step(eb_ctx* ctx, const eb_rheology* rheo, const double* theta, double dt,
+                const eb_step_opts* opts, double* u, double* p, eb_step_stats* stats,
+                void* stream);
+
+/* Force on the embedded body (Eq. drag-force): sum over cut cells of
+ * A_EB h^2 [tau_EB n - p_EB n], tau_EB = eta_EB (n (x) g + g (x) n), g = du/dn from Eq. dudn,
+ * p_EB = p + h b.G p.  n points from the body into the fluid.  F (host) [3]. */
+int eb_drag(const eb_ctx* ctx, const eb_rheology* rheo, const double* theta, const double* u,
+            const double* p, double F[3], void* stream);
+
+/* Cell-centred pressure gradient G p (aperture-weighted mean of the two face gradients in
+ * each direction; domain-wall faces carry a zero gradient).  p (device) [N], gp (device) [3][N]. */
+int eb_pressure_gradient(const eb_ctx* ctx, const double* p, double* gp, void* stream);
+
+const char* eb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EB_H */

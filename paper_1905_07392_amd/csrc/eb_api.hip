@@ -1,0 +1,824 @@
+// eb_api.hip -- host orchestration and the C ABI declared in include/eb.h.
+//
+// The caller's device workspace is carved into every array the step needs; the library never
+// allocates device memory.  Solvers keep their vectors on the device and read back one or two
+// scalars per Krylov iteration (dot products and max-norms) for the stopping test and the
+// Krylov coefficients.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "eb_internal.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+int set_err(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_check(const char* where) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_err(EB_EHIP, "%s: %s", where, hipGetErrorString(e));
+    return EB_OK;
+}
+
+struct Carver {
+    char* base;
+    size_t used;
+    bool dry;
+    template <typename T>
+    T* take(size_t count) {
+        size_t bytes = count * sizeof(T);
+        size_t off = (used + 255) & ~size_t(255);
+        used = off + bytes;
+        return dry ? nullptr : reinterpret_cast<T*>(base + off);
+    }
+};
+
+}  // namespace
+
+struct eb_ctx {
+    eb_box box;
+    eb_body body;
+    GridV grid;
+    BodyV bodyv;
+    long N;
+    int ncut, ncut_max, nlev, nfallback;
+    GeomV g;
+    Level lev[EB_MAXLEV];
+    hipStream_t s;
+    // geometry
+    uint8_t* flag;
+    double* alpha;
+    double* ap[3];
+    int *cutid, *cut, *sidx, *nfb, *blockcount, *errdev;
+    double *nrm, *aeb, *bc, *delta, *dd, *sw, *psi_nodes;
+    // reductions
+    double *part, *red;
+    // work arrays
+    double *G9, *gw, *eta0, *eta1, *eb0, *eb1, *C0, *V0, *C1, *V1, *DC, *DH, *rS, *rdD, *psi,
+        *gp, *u1, *p1, *div, *phi, *pb;
+    double* f[3];
+    double* kv[10];
+    double* pk[4];
+    int vcycles;
+    int built_sys;    // operator currently held by the levels (-1 none)
+    bool built_mixed;
+};
+
+namespace {
+
+int level_count(const int n[3]) {
+    int nl = 1;
+    int m[3] = {n[0], n[1], n[2]};
+    while (nl < EB_MAXLEV && m[0] % 4 == 0 && m[1] % 4 == 0 && m[2] % 4 == 0) {
+        for (int d = 0; d < 3; d++) m[d] /= 2;
+        nl++;
+    }
+    return nl;
+}
+
+long ncut_bound(const int n[3]) {
+    long N = (long)n[0] * n[1] * n[2];
+    long b = 24L * ((long)n[0] * n[1] + (long)n[1] * n[2] + (long)n[0] * n[2]);
+    return b < N ? b : N;
+}
+
+// assigns every device array of the context; returns the bytes used
+size_t carve(eb_ctx* c, char* base, bool dry) {
+    Carver cv{base, 0, dry};
+    GridV g = c->grid;
+    long N = c->N;
+    long M = c->ncut_max > 0 ? c->ncut_max : 1;
+    long nn = (long)(g.n[0] + 1) * (g.n[1] + 1) * (g.n[2] + 1);
+    c->psi_nodes = cv.take<double>(nn);
+    c->flag = cv.take<uint8_t>(N);
+    c->alpha = cv.take<double>(N);
+    for (int d = 0; d < 3; d++) c->ap[d] = cv.take<double>(face_count(g, d));
+    c->cutid = cv.take<int>(N);
+    c->cut = cv.take<int>(M);
+    c->nrm = cv.take<double>(3 * M);
+    c->aeb = cv.take<double>(M);
+    c->bc = cv.take<double>(3 * M);
+    c->delta = cv.take<double>(M);
+    c->dd = cv.take<double>(2 * M);
+    c->sidx = cv.take<int>(18 * M);
+    c->sw = cv.take<double>(18 * M);
+    c->nfb = cv.take<int>(M);
+    c->blockcount = cv.take<int>(grid_for(N) + 1);
+    c->errdev = cv.take<int>(1);
+    c->part = cv.take<double>(4 * 1024);
+    c->red = cv.take<double>(64);
+    // levels
+    int m[3] = {g.n[0], g.n[1], g.n[2]};
+    double h = g.h;
+    for (int l = 0; l < c->nlev; l++) {
+        Level& L = c->lev[l];
+        for (int d = 0; d < 3; d++) {
+            L.grid.n[d] = m[d];
+            L.grid.per[d] = g.per[d];
+        }
+        L.grid.h = h;
+        L.N = (long)m[0] * m[1] * m[2];
+        if (l == 0) {
+            L.alpha = c->alpha;
+            for (int d = 0; d < 3; d++) L.ap[d] = c->ap[d];
+        } else {
+            L.alpha = cv.take<double>(L.N);
+            for (int d = 0; d < 3; d++) L.ap[d] = cv.take<double>(face_count(L.grid, d));
+        }
+        L.mask = cv.take<uint8_t>(L.N);
+        for (int d = 0; d < 3; d++) L.K[d] = cv.take<double>(face_count(L.grid, d));
+        L.S = cv.take<double>(L.N);
+        L.D = cv.take<double>(L.N);
+        for (int d = 0; d < 3; d++) L.Kf[d] = cv.take<float>(face_count(L.grid, d));
+        L.Df = cv.take<float>(L.N);
+        L.x = cv.take<double>(3 * L.N);
+        L.b = cv.take<double>(3 * L.N);
+        L.r = cv.take<double>(3 * L.N);
+        L.xf = cv.take<float>(3 * L.N);
+        L.bf = cv.take<float>(3 * L.N);
+        L.rf = cv.take<float>(3 * L.N);
+        for (int d = 0; d < 3; d++) m[d] /= 2;
+        h *= 2.0;
+    }
+    c->G9 = cv.take<double>(9 * N);
+    c->gw = cv.take<double>(3 * M);
+    c->eta0 = cv.take<double>(N);
+    c->eta1 = cv.take<double>(N);
+    c->eb0 = cv.take<double>(M);
+    c->eb1 = cv.take<double>(M);
+    c->C0 = cv.take<double>(3 * N);
+    c->V0 = cv.take<double>(3 * N);
+    c->C1 = cv.take<double>(3 * N);
+    c->V1 = cv.take<double>(3 * N);
+    c->DC = cv.take<double>(3 * N);
+    c->DH = cv.take<double>(3 * M);
+    c->rS = cv.take<double>(M);
+    c->rdD = cv.take<double>(3 * M);
+    c->psi = cv.take<double>(3 * N);
+    c->gp = cv.take<double>(3 * N);
+    c->u1 = cv.take<double>(3 * N);
+    c->p1 = cv.take<double>(N);
+    c->div = cv.take<double>(N);
+    c->phi = cv.take<double>(N);
+    c->pb = cv.take<double>(N);
+    for (int d = 0; d < 3; d++) c->f[d] = cv.take<double>(face_count(g, d));
+    for (int t = 0; t < 10; t++) c->kv[t] = cv.take<double>(3 * N);
+    for (int t = 0; t < 4; t++) c->pk[t] = cv.take<double>(N);
+    return cv.used + 256;
+}
+
+void rotation_zyx(const double e[3], double R[3][3]) {
+    double ca = cos(e[0]), sa = sin(e[0]), cb = cos(e[1]), sb = sin(e[1]);
+    double cc = cos(e[2]), sc = sin(e[2]);
+    double Rz[3][3] = {{ca, -sa, 0}, {sa, ca, 0}, {0, 0, 1}};
+    double Ry[3][3] = {{cb, 0, sb}, {0, 1, 0}, {-sb, 0, cb}};
+    double Rx[3][3] = {{1, 0, 0}, {0, cc, -sc}, {0, sc, cc}};
+    double T[3][3];
+    for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) {
+            T[a][b] = 0;
+            for (int k = 0; k < 3; k++) T[a][b] += Rz[a][k] * Ry[k][b];
+        }
+    for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) {
+            R[a][b] = 0;
+            for (int k = 0; k < 3; k++) R[a][b] += T[a][k] * Rx[k][b];
+        }
+}
+
+int init_ctx(eb_ctx* c, const eb_box* box, const eb_body* body) {
+    if (!box || !body) return set_err(EB_EINVAL, "null box or body");
+    for (int d = 0; d < 3; d++)
+        if (box->n[d] < 2 || box->n[d] % 2)
+            return set_err(EB_EINVAL, "n[%d]=%d must be an even number >= 2", d, box->n[d]);
+    if (!(box->h > 0.0)) return set_err(EB_EINVAL, "h must be positive");
+    if (body->kind < EB_BODY_NONE || body->kind > EB_BODY_PLANE)
+        return set_err(EB_EINVAL, "unknown body kind %d", body->kind);
+    memset(c, 0, sizeof(*c));
+    c->built_sys = -1;
+    c->box = *box;
+    c->body = *body;
+    for (int d = 0; d < 3; d++) {
+        c->grid.n[d] = box->n[d];
+        c->grid.per[d] = box->periodic[d] ? 1 : 0;
+    }
+    c->grid.h = box->h;
+    c->N = (long)box->n[0] * box->n[1] * box->n[2];
+    c->ncut_max = (int)ncut_bound(box->n);
+    c->nlev = level_count(box->n);
+    BodyV& b = c->bodyv;
+    b.kind = body->kind;
+    for (int d = 0; d < 3; d++) {
+        b.lo[d] = box->lo[d];
+        b.c[d] = body->center[d];
+        b.r[d] = body->kind == EB_BODY_SPHERE ? body->radii[0] : body->radii[d];
+        b.pn[d] = body->plane_n[d];
+    }
+    b.zlo = body->zlo;
+    b.zhi = body->zhi;
+    b.pd = body->plane_d;
+    if (body->kind == EB_BODY_ELLIPSOID) rotation_zyx(body->euler_zyx, b.R);
+    else
+        for (int a = 0; a < 3; a++)
+            for (int e = 0; e < 3; e++) b.R[a][e] = a == e ? 1.0 : 0.0;
+    return EB_OK;
+}
+
+void fill_geomv(eb_ctx* c) {
+    GeomV& g = c->g;
+    g.grid = c->grid;
+    g.N = c->N;
+    g.ncut = c->ncut;
+    for (int f = 0; f < 6; f++)
+        for (int m = 0; m < 3; m++) g.wall[f][m] = c->box.wall_u[f][m];
+    for (int m = 0; m < 3; m++) g.ueb[m] = c->body.u_eb[m];
+    g.flag = c->flag;
+    g.alpha = c->alpha;
+    for (int d = 0; d < 3; d++) g.ap[d] = c->ap[d];
+    g.cutid = c->cutid;
+    g.cut = c->cut;
+    g.nrm = c->nrm;
+    g.aeb = c->aeb;
+    g.bc = c->bc;
+    g.delta = c->delta;
+    g.dd = c->dd;
+    g.sidx = c->sidx;
+    g.sw = c->sw;
+}
+
+// host copy of `n` reduced values
+int fetch(eb_ctx* c, double* host, int n) {
+    hipMemcpyAsync(host, c->red, n * sizeof(double), hipMemcpyDeviceToHost, c->s);
+    hipError_t e = hipStreamSynchronize(c->s);
+    if (e != hipSuccess) return set_err(EB_EHIP, "sync: %s", hipGetErrorString(e));
+    return EB_OK;
+}
+
+bool finite(double x) { return std::isfinite(x); }
+
+// ------------------------------------------------------------------------------------------
+// solvers
+// ------------------------------------------------------------------------------------------
+struct SolveCfg {
+    bool mixed;
+    int nu1, nu2, nbottom, max_iter;
+};
+
+SolveCfg cfg_of(const eb_step_opts* o) {
+    SolveCfg k;
+    k.mixed = o && o->precision == EB_MIXED;
+    k.nu1 = o && o->nu1 > 0 ? o->nu1 : 2;
+    k.nu2 = o && o->nu2 > 0 ? o->nu2 : 2;
+    k.nbottom = o && o->nbottom > 0 ? o->nbottom : 16;
+    k.max_iter = o && o->max_iter > 0 ? o->max_iter : 400;
+    return k;
+}
+
+void vcyc(eb_ctx* c, int ncomp, const SolveCfg& k, const double* b, double* x) {
+    mg_vcycle(c->lev, c->nlev, ncomp, k.mixed, b, x, k.nu1, k.nu2, k.nbottom, c->s);
+    c->vcycles++;
+}
+
+double dot1(eb_ctx* c, long n, const double* a, const double* b, int* err) {
+    const double* A[4] = {a, nullptr, nullptr, nullptr};
+    const double* B[4] = {b, nullptr, nullptr, nullptr};
+    red_dots(n, 1, A, B, c->part, c->red, c->s);
+    double v = 0;
+    *err = fetch(c, &v, 1);
+    return v;
+}
+
+double maxabs1(eb_ctx* c, long n, const double* x, int* err) {
+    red_maxabs(n, 1, x, c->part, c->red, c->s);
+    double v = 0;
+    *err = fetch(c, &v, 1);
+    return v;
+}
+
+// preconditioned CG for M p = b on level 0 (operator already built); rtol * max(|b|, scale)
+int pcg(eb_ctx* c, const double* b, double* x, double rtol, double scale, const SolveCfg& k,
+        int* iters) {
+    long N = c->N;
+    double *r = c->pk[0], *z = c->pk[1], *pd = c->pk[2], *q = c->pk[3];
+    int e = EB_OK;
+    *iters = 0;
+    mg_apply_level0(c->lev[0], 1, x, q, c->s);
+    vec_sub_scaled(N, b, 1.0, q, r, c->s);
+    double bn = maxabs1(c, N, b, &e);
+    if (e) return e;
+    if (scale > bn) bn = scale;
+    double rn = maxabs1(c, N, r, &e);
+    if (e) return e;
+    if (bn == 0.0 || rn <= rtol * bn) return EB_OK;
+    vcyc(c, 1, k, r, z);
+    vec_copy(N, z, pd, c->s);
+    double rz = dot1(c, N, r, z, &e);
+    if (e) return e;
+    for (int it = 1; it <= k.max_iter; it++) {
+        mg_apply_level0(c->lev[0], 1, pd, q, c->s);
+        double pq = dot1(c, N, pd, q, &e);
+        if (e) return e;
+        double a = rz / pq;
+        vec_axpby(N, a, pd, 1.0, x, c->s);
+        vec_axpby(N, -a, q, 1.0, r, c->s);
+        *iters = it;
+        rn = maxabs1(c, N, r, &e);
+        if (e) return e;
+        if (!finite(rn)) return set_err(EB_ENAN, "non-finite residual in the Poisson solve");
+        if (rn <= rtol * bn) return EB_OK;
+        vcyc(c, 1, k, r, z);
+        double rzn = dot1(c, N, r, z, &e);
+        if (e) return e;
+        double be = rzn / rz;
+        rz = rzn;
+        vec_axpby(N, 1.0, z, be, pd, c->s);
+    }
+    return set_err(EB_ENOCONV, "Poisson solve: no convergence in %d iterations", k.max_iter);
+}
+
+int poisson_solve(eb_ctx* c, double beta, const double* div, double* p, double rtol,
+                  double scale, const SolveCfg& k, int* iters) {
+    mg_build_poisson(c->lev, c->nlev, c->g, beta, k.mixed, c->s);
+    c->built_sys = EB_SYS_POISSON;
+    c->built_mixed = k.mixed;
+    double h2[2];
+    red_sum_open(c->g, div, c->part, c->red, c->s);
+    int e = fetch(c, h2, 2);
+    if (e) return e;
+    double mean = h2[1] > 0 ? h2[0] / h2[1] : 0.0;
+    op_poisson_rhs(c->g, div, mean, c->pb, c->s);
+    int ret = pcg(c, c->pb, p, rtol, scale, k, iters);
+    if (ret != EB_OK && ret != EB_ENOCONV) return ret;
+    red_sum_open(c->g, p, c->part, c->red, c->s);
+    e = fetch(c, h2, 2);
+    if (e) return e;
+    mean = h2[1] > 0 ? h2[0] / h2[1] : 0.0;
+    op_shift_open(c->g, p, -mean, c->s);
+    return ret;
+}
+
+int mac_project(eb_ctx* c, double beta, double* f[3], double* phi, double rtol,
+                const SolveCfg& k, double* div_inf, int* iters) {
+    op_divergence(c->g, f, c->div, c->s);
+    op_face_flux_max(c->g, f, c->part, c->red, c->s);
+    double scale = 0;
+    int e = fetch(c, &scale, 1);
+    if (e) return e;
+    int it = 0;
+    int ret = poisson_solve(c, beta, c->div, phi, rtol, scale, k, &it);
+    if (iters) *iters = it;
+    if (ret != EB_OK && ret != EB_ENOCONV) return ret;
+    op_face_correct(c->g, beta, phi, f, c->s);
+    if (div_inf) {
+        op_divergence(c->g, f, c->div, c->s);
+        *div_inf = maxabs1(c, c->N, c->div, &e);
+        if (e) return e;
+    }
+    return ret;
+}
+
+int cc_project(eb_ctx* c, double beta, double* u, double* p, double rtol, const SolveCfg& k,
+               double* div_inf, int* iters) {
+    op_gcc(c->g, p, c->gp, c->s);
+    op_axpy_open(c->g, beta, c->gp, u, 3, c->s);
+    op_cell_to_face(c->g, u, c->f, c->s);
+    int ret = mac_project(c, beta, c->f, p, rtol, k, div_inf, iters);
+    if (ret != EB_OK && ret != EB_ENOCONV) return ret;
+    op_gcc(c->g, p, c->gp, c->s);
+    op_axpy_open(c->g, -beta, c->gp, u, 3, c->s);
+    return ret;
+}
+
+// BiCGSTAB on the three-component system, right-preconditioned by the viscous V-cycle
+int visc_solve(eb_ctx* c, double rho, double dt, const double* eta, const double* eta_eb,
+               const double* psi, double* x, double rtol, const SolveCfg& k, int* iters) {
+    long N3 = 3 * c->N;
+    double *r = c->kv[0], *rh = c->kv[1], *p = c->kv[2], *v = c->kv[3], *ph = c->kv[4],
+           *sv = c->kv[5], *sh = c->kv[6], *t = c->kv[7], *b = c->kv[8], *a0 = c->kv[9];
+    mg_build_visc(c->lev, c->nlev, c->g, rho, dt, eta, eta_eb, k.mixed, c->s);
+    c->built_sys = EB_SYS_VISC;
+    c->built_mixed = k.mixed;
+    int e = EB_OK;
+    *iters = 0;
+    // effective right-hand side: alpha psi minus the boundary part A(0)
+    vec_fill(N3, 0.0, t, c->s);
+    op_visc_apply(c->g, rho, dt, eta, eta_eb, t, a0, 0, c->s);
+    vec_mask_rhs(c->g, psi, a0, b, c->s);
+    double bn = maxabs1(c, N3, b, &e);
+    if (e) return e;
+    double tol = rtol * bn;
+    // r = alpha psi - A(x) = b - A_lin(x)
+    op_visc_apply(c->g, rho, dt, eta, eta_eb, x, t, 1, c->s);
+    vec_sub_scaled(N3, b, 1.0, t, r, c->s);
+    double rn = maxabs1(c, N3, r, &e);
+    if (e) return e;
+    if (bn == 0.0 || rn <= tol) return EB_OK;
+    vec_copy(N3, r, rh, c->s);
+    vec_fill(N3, 0.0, p, c->s);
+    vec_fill(N3, 0.0, v, c->s);
+    double rho_old = 1.0, al = 1.0, om = 1.0;
+    double rr = dot1(c, N3, rh, r, &e);
+    if (e) return e;
+    for (int it = 1; it <= k.max_iter; it++) {
+        double be = (rr / rho_old) * (al / om);
+        vec_bicg_p(N3, r, be, om, v, p, c->s);
+        vcyc(c, 3, k, p, ph);
+        op_visc_apply(c->g, rho, dt, eta, eta_eb, ph, v, 1, c->s);
+        double rv = dot1(c, N3, rh, v, &e);
+        if (e) return e;
+        al = rr / rv;
+        vec_sub_scaled(N3, r, al, v, sv, c->s);
+        *iters = it;
+        double sn = maxabs1(c, N3, sv, &e);
+        if (e) return e;
+        if (!finite(sn)) return set_err(EB_ENAN, "non-finite residual in the viscous solve");
+        if (sn <= tol) {
+            vec_axpby(N3, al, ph, 1.0, x, c->s);
+            return EB_OK;
+        }
+        vcyc(c, 3, k, sv, sh);
+        op_visc_apply(c->g, rho, dt, eta, eta_eb, sh, t, 1, c->s);
+        const double* A2[4] = {t, t, nullptr, nullptr};
+        const double* B2[4] = {sv, t, nullptr, nullptr};
+        red_dots(N3, 2, A2, B2, c->part, c->red, c->s);
+        double ts[2];
+        e = fetch(c, ts, 2);
+        if (e) return e;
+        om = ts[0] / ts[1];
+        vec_bicg_update(N3, al, ph, om, sh, sv, t, x, r, c->s);
+        // next rho and the residual norm in one read-back
+        const double* A1[4] = {rh, nullptr, nullptr, nullptr};
+        const double* B1[4] = {r, nullptr, nullptr, nullptr};
+        red_dots(N3, 1, A1, B1, c->part, c->red, c->s);
+        red_maxabs(N3, 1, r, c->part + 2048, c->red + 1, c->s);
+        double two[2];
+        e = fetch(c, two, 2);
+        if (e) return e;
+        rho_old = rr;
+        rr = two[0];
+        if (!finite(two[1])) return set_err(EB_ENAN, "non-finite residual in the viscous solve");
+        if (two[1] <= tol) return EB_OK;
+    }
+    return set_err(EB_ENOCONV, "viscous solve: no convergence in %d iterations", k.max_iter);
+}
+
+int derived(eb_ctx* c, const eb_rheology& rh, const double* theta, const double* u,
+            const eb_step_opts* o, double* C, double* eta, double* eta_eb, double* V,
+            int* iters) {
+    SolveCfg k = cfg_of(o);
+    double rtol = o && o->rtol_mac > 0 ? o->rtol_mac : 1e-12;
+    op_face_extrap(c->g, u, c->f, c->s);
+    vec_fill(c->N, 0.0, c->phi, c->s);
+    int ret = mac_project(c, 1.0, c->f, c->phi, rtol, k, nullptr, iters);
+    if (ret != EB_OK && ret != EB_ENOCONV) return ret;
+    op_conv_dc(c->g, u, c->f, c->DC, c->s);
+    op_redistribute(c->g, c->DC, c->DH, c->rS, c->rdD, C, c->s);
+    op_wall_grad(c->g, u, c->gw, c->s);
+    op_grad_eta(c->g, rh, u, c->gw, theta, c->G9, eta, nullptr, c->s);
+    op_eta_eb(c->g, rh, c->gw, theta, eta_eb, c->s);
+    op_transpose_dc(c->g, u, c->G9, eta, eta_eb, c->gw, c->DC, c->s);
+    op_redistribute(c->g, c->DC, c->DH, c->rS, c->rdD, V, c->s);
+    int h = hip_check("derived");
+    return h ? h : ret;
+}
+
+int worst(int a, int b) { return a != EB_OK ? a : b; }
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------
+// C ABI
+// ------------------------------------------------------------------------------------------
+extern "C" {
+
+const char* eb_last_error(void) { return g_err.c_str(); }
+
+size_t eb_workspace_bytes(const eb_box* box, const eb_body* body) {
+    eb_ctx c;
+    if (init_ctx(&c, box, body) != EB_OK) return 0;
+    return carve(&c, nullptr, true);
+}
+
+int eb_geometry_build(const eb_box* box, const eb_body* body, void* ws, size_t ws_bytes,
+                      eb_ctx** out, void* stream) {
+    if (!out || !ws) return set_err(EB_EINVAL, "null workspace or context pointer");
+    eb_ctx* c = new eb_ctx;
+    int e = init_ctx(c, box, body);
+    if (e) {
+        delete c;
+        return e;
+    }
+    size_t need = carve(c, nullptr, true);
+    if (ws_bytes < need) {
+        delete c;
+        return set_err(EB_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, need);
+    }
+    carve(c, (char*)ws, false);
+    c->s = (hipStream_t)stream;
+    int ncut = 0;
+    geom_build_device(c->grid, c->bodyv, c->psi_nodes, c->flag, c->alpha, c->ap, c->cutid,
+                      c->cut, c->blockcount, c->ncut_max, &ncut, c->errdev, c->s);
+    if ((e = hip_check("geometry"))) {
+        delete c;
+        return e;
+    }
+    if (ncut > c->ncut_max) {
+        delete c;
+        return set_err(EB_EGEOM, "%d cut cells exceed the bound %d", ncut, c->ncut_max);
+    }
+    c->ncut = ncut;
+    const double* apc[3] = {c->ap[0], c->ap[1], c->ap[2]};
+    geom_cut_fill(c->grid, c->bodyv, c->psi_nodes, apc, c->cut, ncut, c->cutid, c->nrm, c->aeb,
+                  c->bc, c->delta, c->s);
+    // per-cut arrays are [component][ncut]: rebase the strided views on the real count
+    fill_geomv(c);
+    geom_wall_stencil(c->g, c->dd, c->sidx, c->sw, c->nfb, c->errdev, c->s);
+    for (int l = 1; l < c->nlev; l++) level_coarsen_geometry(c->lev[l - 1], c->lev[l], c->s);
+    for (int l = 0; l < c->nlev; l++) level_mask(c->lev[l], c->s);
+    int err = 0;
+    hipMemcpyAsync(&err, c->errdev, sizeof(int), hipMemcpyDeviceToHost, c->s);
+    hipError_t he = hipStreamSynchronize(c->s);
+    if (he != hipSuccess) {
+        delete c;
+        return set_err(EB_EHIP, "geometry sync: %s", hipGetErrorString(he));
+    }
+    if ((e = hip_check("geometry"))) {
+        delete c;
+        return e;
+    }
+    if (err) {
+        delete c;
+        return set_err(EB_EGEOM, "geometry error flags 0x%x (1 ambiguous face, 2 degenerate cut "
+                                 "cell, 4 wall stencil outside the box)", err);
+    }
+    // fallback count
+    c->nfallback = 0;
+    if (ncut > 0) {
+        int* tmp = new int[ncut];
+        hipMemcpyAsync(tmp, c->nfb, ncut * sizeof(int), hipMemcpyDeviceToHost, c->s);
+        hipStreamSynchronize(c->s);
+        for (int q = 0; q < ncut; q++) c->nfallback += tmp[q];
+        delete[] tmp;
+    }
+    *out = c;
+    return EB_OK;
+}
+
+void eb_ctx_destroy(eb_ctx* ctx) { delete ctx; }
+
+int eb_ctx_info(const eb_ctx* c, int* ncut, int* nlevels, int* nfallback) {
+    if (!c) return set_err(EB_EINVAL, "null context");
+    if (ncut) *ncut = c->ncut;
+    if (nlevels) *nlevels = c->nlev;
+    if (nfallback) *nfallback = c->nfallback;
+    return EB_OK;
+}
+
+}  // extern "C"
+
+namespace {
+__global__ void k_export_cut(GeomV g, const int* __restrict__ nfb, int64_t* __restrict__ cell,
+                             double* __restrict__ data) {
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    int nc = g.ncut;
+    if (q >= nc) return;
+    if (cell) cell[q] = g.cut[q];
+    if (data) {
+        double* row = data + 9L * q;
+        for (int e = 0; e < 3; e++) row[e] = g.nrm[(long)e * nc + q];
+        row[3] = g.aeb[q];
+        for (int e = 0; e < 3; e++) row[4 + e] = g.bc[(long)e * nc + q];
+        row[7] = g.delta[q];
+        row[8] = nfb[q];
+    }
+}
+}  // namespace
+
+extern "C" {
+
+int eb_geometry_export(const eb_ctx* c, uint8_t* flag, double* alpha, double* ax, double* ay,
+                       double* az, int64_t* cut_cell, double* cut_data, void* stream) {
+    if (!c) return set_err(EB_EINVAL, "null context");
+    hipStream_t s = (hipStream_t)stream;
+    if (flag) hipMemcpyAsync(flag, c->flag, c->N, hipMemcpyDeviceToDevice, s);
+    if (alpha) hipMemcpyAsync(alpha, c->alpha, c->N * 8, hipMemcpyDeviceToDevice, s);
+    double* dst[3] = {ax, ay, az};
+    for (int d = 0; d < 3; d++)
+        if (dst[d])
+            hipMemcpyAsync(dst[d], c->ap[d], face_count(c->grid, d) * 8, hipMemcpyDeviceToDevice,
+                           s);
+    if (c->ncut > 0 && (cut_cell || cut_data))
+        k_export_cut<<<grid_for(c->ncut), EB_BLOCK, 0, s>>>(c->g, c->nfb, cut_cell, cut_data);
+    return hip_check("eb_geometry_export");
+}
+
+int eb_apparent_viscosity(const eb_ctx* cc, const eb_rheology* rheo, const double* u,
+                          const double* theta, double* eta, double* eta_eb, double* sr,
+                          void* stream) {
+    eb_ctx* c = const_cast<eb_ctx*>(cc);
+    if (!c || !rheo || !u || !eta || (!eta_eb && c->ncut > 0))
+        return set_err(EB_EINVAL, "null argument");
+    hipStream_t s = (hipStream_t)stream;
+    op_wall_grad(c->g, u, c->gw, s);
+    op_grad_eta(c->g, *rheo, u, c->gw, theta, c->G9, eta, sr, s);
+    op_eta_eb(c->g, *rheo, c->gw, theta, eta_eb, s);
+    return hip_check("eb_apparent_viscosity");
+}
+
+int eb_viscous_apply(const eb_ctx* cc, int mode, double rho, double dt, const double* eta,
+                     const double* eta_eb, const double* u, double* out, void* stream) {
+    eb_ctx* c = const_cast<eb_ctx*>(cc);
+    if (!c || !eta || !u || !out || (!eta_eb && c->ncut > 0))
+        return set_err(EB_EINVAL, "null argument");
+    hipStream_t s = (hipStream_t)stream;
+    if (mode == EB_OP_HELMHOLTZ || mode == EB_OP_HELMHOLTZ_H) {
+        op_visc_apply(c->g, rho, dt, eta, eta_eb, u, out, mode == EB_OP_HELMHOLTZ_H, s);
+    } else if (mode == EB_OP_TRANSPOSE) {
+        eb_rheology nw{EB_LAW_NEWTONIAN, 1.0, 0.0, 1.0, 1.0};
+        op_wall_grad(c->g, u, c->gw, s);
+        op_grad_eta(c->g, nw, u, c->gw, nullptr, c->G9, c->eta1, nullptr, s);
+        op_transpose_dc(c->g, u, c->G9, eta, eta_eb, c->gw, c->DC, s);
+        op_redistribute(c->g, c->DC, c->DH, c->rS, c->rdD, out, s);
+    } else {
+        return set_err(EB_EINVAL, "unknown mode %d", mode);
+    }
+    return hip_check("eb_viscous_apply");
+}
+
+int eb_mg_vcycle(eb_ctx* c, int system, int precision, double beta, double rho, double dt,
+                 const double* eta, const double* eta_eb, const double* r, double* e,
+                 const eb_step_opts* opts, void* stream) {
+    if (!c || !r || !e) return set_err(EB_EINVAL, "null argument");
+    c->s = (hipStream_t)stream;
+    SolveCfg k = cfg_of(opts);
+    k.mixed = precision == EB_MIXED;
+    if (system == EB_SYS_POISSON) {
+        mg_build_poisson(c->lev, c->nlev, c->g, beta, k.mixed, c->s);
+        c->built_sys = EB_SYS_POISSON;
+        c->built_mixed = k.mixed;
+        vcyc(c, 1, k, r, e);
+    } else if (system == EB_SYS_VISC) {
+        if (!eta || (!eta_eb && c->ncut > 0)) return set_err(EB_EINVAL, "null viscosity");
+        mg_build_visc(c->lev, c->nlev, c->g, rho, dt, eta, eta_eb, k.mixed, c->s);
+        c->built_sys = EB_SYS_VISC;
+        c->built_mixed = k.mixed;
+        vcyc(c, 3, k, r, e);
+    } else {
+        return set_err(EB_EINVAL, "unknown system %d", system);
+    }
+    return hip_check("eb_mg_vcycle");
+}
+
+int eb_mg_sweep(eb_ctx* c, int system, int precision, int colour, const void* b, void* x,
+                void* stream) {
+    if (!c || !b || !x) return set_err(EB_EINVAL, "null argument");
+    bool f32 = precision == EB_MIXED;
+    if (c->built_sys != system || c->built_mixed != f32)
+        return set_err(EB_EINVAL, "no operator for system %d precision %d is built", system,
+                       precision);
+    if (f32 && c->nlev < 2) return set_err(EB_EINVAL, "single-level hierarchy is FP64 only");
+    mg_sweep_level0(c->lev[0], system == EB_SYS_VISC ? 3 : 1, f32, b, x, colour & 1,
+                    (hipStream_t)stream);
+    return hip_check("eb_mg_sweep");
+}
+
+int eb_visc_solve(eb_ctx* c, double rho, double dt, const double* eta, const double* eta_eb,
+                  const double* psi, double* x, double rtol, const eb_step_opts* opts,
+                  int* iters, void* stream) {
+    if (!c || !eta || !psi || !x || (!eta_eb && c->ncut > 0))
+        return set_err(EB_EINVAL, "null argument");
+    c->s = (hipStream_t)stream;
+    int it = 0;
+    int ret = visc_solve(c, rho, dt, eta, eta_eb, psi, x, rtol, cfg_of(opts), &it);
+    if (iters) *iters = it;
+    int h = hip_check("eb_visc_solve");
+    return h ? h : ret;
+}
+
+int eb_mac_project(eb_ctx* c, double beta, double* fx, double* fy, double* fz, double* phi,
+                   double rtol, const eb_step_opts* opts, double* div_inf, int* iters,
+                   void* stream) {
+    if (!c || !fx || !fy || !fz || !phi) return set_err(EB_EINVAL, "null argument");
+    c->s = (hipStream_t)stream;
+    double* f[3] = {fx, fy, fz};
+    int ret = mac_project(c, beta, f, phi, rtol, cfg_of(opts), div_inf, iters);
+    int h = hip_check("eb_mac_project");
+    return h ? h : ret;
+}
+
+int eb_cc_project(eb_ctx* c, double beta, double* u, double* p, double rtol,
+                  const eb_step_opts* opts, double* div_inf, int* iters, void* stream) {
+    if (!c || !u || !p) return set_err(EB_EINVAL, "null argument");
+    c->s = (hipStream_t)stream;
+    int ret = cc_project(c, beta, u, p, rtol, cfg_of(opts), div_inf, iters);
+    int h = hip_check("eb_cc_project");
+    return h ? h : ret;
+}
+
+int eb_derived(eb_ctx* c, const eb_rheology* rheo, const double* theta, const double* u,
+               const eb_step_opts* opts, double* C, double* eta, double* eta_eb, double* V,
+               int* iters, void* stream) {
+    if (!c || !rheo || !u || !C || !eta || !V || (!eta_eb && c->ncut > 0))
+        return set_err(EB_EINVAL, "null argument");
+    c->s = (hipStream_t)stream;
+    int it = 0;
+    int ret = derived(c, *rheo, theta, u, opts, C, eta, eta_eb, V, &it);
+    if (iters) *iters = it;
+    return ret;
+}
+
+int eb_rk2_step(eb_ctx* c, const eb_rheology* rheo, const double* theta, double dt,
+                const eb_step_opts* o, double* u, double* p, eb_step_stats* stats,
+                void* stream) {
+    if (!c || !rheo || !o || !u || !p) return set_err(EB_EINVAL, "null argument");
+    if (!(rheo->rho > 0.0) || !(dt > 0.0)) return set_err(EB_EINVAL, "rho and dt must be > 0");
+    c->s = (hipStream_t)stream;
+    c->vcycles = 0;
+    SolveCfg k = cfg_of(o);
+    eb_step_stats st;
+    memset(&st, 0, sizeof(st));
+    long N = c->N, N3 = 3 * N;
+    double rho = rheo->rho, beta = dt / rho;
+    int status = EB_OK, ret, it;
+    // predictor: derived quantities at u^m
+    ret = derived(c, *rheo, theta, u, o, c->C0, c->eta0, c->eb0, c->V0, &it);
+    st.it_mac[0] = it;
+    if (ret != EB_OK && ret != EB_ENOCONV) return ret;
+    status = worst(status, ret);
+    op_gcc(c->g, p, c->gp, c->s);
+    op_psi(c->g, rho, dt, u, c->C0, c->V0, c->gp, o->force, c->psi, c->s);
+    vec_copy(N3, u, c->u1, c->s);
+    ret = visc_solve(c, rho, dt, c->eta0, c->eb0, c->psi, c->u1, o->rtol_visc, k, &it);
+    st.it_visc[0] = it;
+    if (ret != EB_OK && ret != EB_ENOCONV) return ret;
+    status = worst(status, ret);
+    vec_copy(N, p, c->p1, c->s);
+    ret = cc_project(c, beta, c->u1, c->p1, o->rtol_proj, k, &st.div_proj[0], &it);
+    st.it_proj[0] = it;
+    if (ret != EB_OK && ret != EB_ENOCONV) return ret;
+    status = worst(status, ret);
+    // corrector: derived quantities at u*, averaged with the predictor's
+    ret = derived(c, *rheo, theta, c->u1, o, c->C1, c->eta1, c->eb1, c->V1, &it);
+    st.it_mac[1] = it;
+    if (ret != EB_OK && ret != EB_ENOCONV) return ret;
+    status = worst(status, ret);
+    op_average(N3, c->C1, c->C0, c->s);
+    op_average(N3, c->V1, c->V0, c->s);
+    op_average(N, c->eta1, c->eta0, c->s);
+    op_average(c->ncut, c->eb1, c->eb0, c->s);
+    op_gcc(c->g, c->p1, c->gp, c->s);
+    op_psi(c->g, rho, dt, u, c->C0, c->V0, c->gp, o->force, c->psi, c->s);
+    ret = visc_solve(c, rho, dt, c->eta0, c->eb0, c->psi, c->u1, o->rtol_visc, k, &it);
+    st.it_visc[1] = it;
+    if (ret != EB_OK && ret != EB_ENOCONV) return ret;
+    status = worst(status, ret);
+    ret = cc_project(c, beta, c->u1, c->p1, o->rtol_proj, k, &st.div_proj[1], &it);
+    st.it_proj[1] = it;
+    if (ret != EB_OK && ret != EB_ENOCONV) return ret;
+    status = worst(status, ret);
+    vec_copy(N3, c->u1, u, c->s);
+    vec_copy(N, c->p1, p, c->s);
+    op_finalize_state(c->g, u, p, c->s);
+    st.vcycles = c->vcycles;
+    st.status = status;
+    if (stats) *stats = st;
+    int h = hip_check("eb_rk2_step");
+    return h ? h : status;
+}
+
+int eb_drag(const eb_ctx* cc, const eb_rheology* rheo, const double* theta, const double* u,
+            const double* p, double F[3], void* stream) {
+    eb_ctx* c = const_cast<eb_ctx*>(cc);
+    if (!c || !rheo || !u || !p || !F) return set_err(EB_EINVAL, "null argument");
+    c->s = (hipStream_t)stream;
+    F[0] = F[1] = F[2] = 0.0;
+    if (c->ncut == 0) return EB_OK;
+    op_wall_grad(c->g, u, c->gw, c->s);
+    op_gcc(c->g, p, c->gp, c->s);
+    op_drag_terms(c->g, *rheo, theta, c->gw, p, c->gp, c->DC, c->s);
+    red_sum(c->ncut, 3, c->DC, c->part, c->red, c->s);
+    int e = fetch(c, F, 3);
+    if (e) return e;
+    return hip_check("eb_drag");
+}
+
+int eb_pressure_gradient(const eb_ctx* cc, const double* p, double* gp, void* stream) {
+    eb_ctx* c = const_cast<eb_ctx*>(cc);
+    if (!c || !p || !gp) return set_err(EB_EINVAL, "null argument");
+    op_gcc(c->g, p, gp, (hipStream_t)stream);
+    return hip_check("eb_pressure_gradient");
+}
+
+}  // extern "C"

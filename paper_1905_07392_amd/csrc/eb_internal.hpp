@@ -1,0 +1,222 @@
+// eb_internal.hpp -- shared device structures and launcher declarations of the EB RK2 library.
+//
+// Layout: cell c = i + nx*(j + ny*k); faces normal to d have n_d + 1 entries along d.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/eb.h"
+
+#define EB_MAXLEV 16
+#define EB_BLOCK 256
+
+// ------------------------------------------------------------------------------------------
+// views passed by value to kernels
+// ------------------------------------------------------------------------------------------
+struct GridV {
+    int n[3];
+    int per[3];
+    double h;
+};
+
+struct BodyV {
+    int kind;
+    double lo[3];    // domain origin (node (0,0,0))
+    double c[3];
+    double r[3];
+    double R[3][3];  // world <- body rotation (ellipsoid)
+    double zlo, zhi;
+    double pn[3];
+    double pd;
+};
+
+// Fine-level geometry (read-only after the build)
+struct GeomV {
+    GridV grid;
+    long N;
+    int ncut;
+    double wall[6][3];
+    double ueb[3];
+    const uint8_t* flag;
+    const double* alpha;
+    const double* ap[3];
+    const int* cutid;   // per cell, -1 if not cut
+    const int* cut;     // per cut: cell
+    const double* nrm;  // [3][ncut] (component-major)
+    const double* aeb;
+    const double* bc;   // [3][ncut]
+    const double* delta;
+    const double* dd;   // [2][ncut]
+    const int* sidx;    // [18][ncut]
+    const double* sw;   // [18][ncut]
+};
+
+template <typename T>
+struct LevelV {
+    GridV grid;
+    long N;
+    const T* K[3];
+    const T* D;
+    const uint8_t* mask;
+};
+
+// ------------------------------------------------------------------------------------------
+// small device helpers
+// ------------------------------------------------------------------------------------------
+__host__ __device__ inline long cell_index(const GridV& g, int i, int j, int k) {
+    return (long)i + (long)g.n[0] * ((long)j + (long)g.n[1] * (long)k);
+}
+__host__ __device__ inline long face_index(const GridV& g, int d, int i, int j, int k) {
+    long m0 = g.n[0] + (d == 0), m1 = g.n[1] + (d == 1);
+    return (long)i + m0 * ((long)j + m1 * (long)k);
+}
+__host__ __device__ inline long face_count(const GridV& g, int d) {
+    return (long)(g.n[0] + (d == 0)) * (g.n[1] + (d == 1)) * (g.n[2] + (d == 2));
+}
+// cell at integer coordinates (wrapping periodic directions); -1 outside a wall
+__host__ __device__ inline long cell_at(const GridV& g, int i, int j, int k) {
+    int q[3] = {i, j, k};
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        if (q[d] < 0 || q[d] >= g.n[d]) {
+            if (!g.per[d]) return -1;
+            q[d] = q[d] < 0 ? q[d] + g.n[d] : q[d] - g.n[d];
+        }
+    }
+    return cell_index(g, q[0], q[1], q[2]);
+}
+__host__ __device__ inline void cell_coords(const GridV& g, long c, int& i, int& j, int& k) {
+    i = (int)(c % g.n[0]);
+    long t = c / g.n[0];
+    j = (int)(t % g.n[1]);
+    k = (int)(t / g.n[1]);
+}
+
+inline unsigned grid_for(long n, int block = EB_BLOCK) {
+    long b = (n + block - 1) / block;
+    return (unsigned)(b > 0 ? b : 1);
+}
+
+// ------------------------------------------------------------------------------------------
+// host-side level storage
+// ------------------------------------------------------------------------------------------
+struct Level {
+    GridV grid;
+    long N;
+    double* alpha;
+    uint8_t* mask;
+    double* ap[3];
+    double* K[3];
+    double* S;
+    double* D;
+    float* Kf[3];
+    float* Df;
+    double *x, *b, *r;  // 3 components each
+    float *xf, *bf, *rf;
+    LevelV<double> v64() const {
+        LevelV<double> v;
+        v.grid = grid;
+        v.N = N;
+        for (int d = 0; d < 3; d++) v.K[d] = K[d];
+        v.D = D;
+        v.mask = mask;
+        return v;
+    }
+    LevelV<float> v32() const {
+        LevelV<float> v;
+        v.grid = grid;
+        v.N = N;
+        for (int d = 0; d < 3; d++) v.K[d] = Kf[d];
+        v.D = Df;
+        v.mask = mask;
+        return v;
+    }
+};
+
+// ------------------------------------------------------------------------------------------
+// launchers (each .hip file owns its kernels)
+// ------------------------------------------------------------------------------------------
+// geometry
+int geom_build_device(const GridV& grid, const BodyV& body, double* psi_nodes, uint8_t* flag,
+                      double* alpha, double* ap[3], int* cutid, int* cut, int* blockcount,
+                      int ncut_max, int* ncut_out, int* err_dev, hipStream_t s);
+void geom_cut_fill(const GridV& grid, const BodyV& body, const double* psi, const double* ap[3],
+                   const int* cut, int ncut, int* cutid, double* nrm, double* aeb, double* bc,
+                   double* delta, hipStream_t s);
+void geom_wall_stencil(const GeomV& g, double* dd, int* sidx, double* sw, int* nfb,
+                       int* err_dev, hipStream_t s);
+void level_coarsen_geometry(const Level& F, Level& C, hipStream_t s);
+void level_mask(Level& L, hipStream_t s);
+void level_coarsen_faces(const GridV& gc, const GridV& gf, int d, const double* ff, double* fc,
+                         double scale, hipStream_t s);
+void level_coarsen_cells(const GridV& gc, const GridV& gf, const double* f, double* c,
+                         hipStream_t s);
+
+// pointwise and stencil operators
+void op_wall_grad(const GeomV& g, const double* u, double* gw, hipStream_t s);
+void op_grad_eta(const GeomV& g, const eb_rheology& r, const double* u, const double* gw,
+                 const double* theta, double* G9, double* eta, double* sr, hipStream_t s);
+void op_eta_eb(const GeomV& g, const eb_rheology& r, const double* gw, const double* theta,
+               double* eta_eb, hipStream_t s);
+void op_transpose_dc(const GeomV& g, const double* u, const double* G9, const double* eta,
+                     const double* eta_eb, const double* gw, double* DC, hipStream_t s);
+void op_face_extrap(const GeomV& g, const double* u, double* f[3], hipStream_t s);
+void op_divergence(const GeomV& g, double* const f[3], double* div, hipStream_t s);
+void op_conv_dc(const GeomV& g, const double* u, double* const f[3], double* DC, hipStream_t s);
+void op_redistribute(const GeomV& g, const double* DC, double* DH, double* S, double* dD,
+                     double* D, hipStream_t s);
+void op_gcc(const GeomV& g, const double* p, double* gp, hipStream_t s);
+void op_axpy_open(const GeomV& g, double a, const double* x, double* y, int ncomp,
+                  hipStream_t s);
+void op_cell_to_face(const GeomV& g, const double* u, double* f[3], hipStream_t s);
+void op_face_correct(const GeomV& g, double beta, const double* p, double* f[3], hipStream_t s);
+void op_psi(const GeomV& g, double rho, double dt, const double* u, const double* C,
+            const double* V, const double* gp, const double f[3], double* psi, hipStream_t s);
+void op_average(long n, const double* a, double* b, hipStream_t s);  // b = (a+b)/2
+void op_finalize_state(const GeomV& g, double* u, double* p, hipStream_t s);
+void op_drag_terms(const GeomV& g, const eb_rheology& r, const double* theta, const double* gw,
+                   const double* p, const double* gp, double* terms, hipStream_t s);
+void op_poisson_rhs(const GeomV& g, const double* div, double mean, double* b, hipStream_t s);
+void op_shift_open(const GeomV& g, double* x, double shift, hipStream_t s);
+
+// multigrid and Krylov
+void mg_build_poisson(Level* lev, int nlev, const GeomV& g, double beta, bool mixed,
+                      hipStream_t s);
+void mg_build_visc(Level* lev, int nlev, const GeomV& g, double rho, double dt,
+                   const double* eta, const double* eta_eb, bool mixed, hipStream_t s);
+void mg_vcycle(Level* lev, int nlev, int ncomp, bool mixed, const double* b, double* x,
+               int nu1, int nu2, int nbottom, hipStream_t s);
+void mg_apply_level0(const Level& L, int ncomp, const double* x, double* y, hipStream_t s);
+void mg_sweep_level0(const Level& L, int ncomp, bool f32, const void* b, void* x, int colour,
+                     hipStream_t s);
+void op_visc_apply(const GeomV& g, double rho, double dt, const double* eta,
+                   const double* eta_eb, const double* u, double* out, int homogeneous,
+                   hipStream_t s);
+
+// reductions: per-block partials (part, >= 4*1024 doubles) then one fixed-order final pass
+// into out (device)
+int red_blocks(long n);
+void red_dots(long n, int npairs, const double* const a[4], const double* const b[4],
+              double* part, double* out, hipStream_t s);
+void red_maxabs(long n, int ncomp, const double* x, double* part, double* out, hipStream_t s);
+void red_sum_open(const GeomV& g, const double* x, double* part, double* out, hipStream_t s);
+void red_sum(long n, int nrow, const double* x, double* part, double* out, hipStream_t s);
+void op_face_flux_max(const GeomV& g, double* const f[3], double* part, double* out,
+                      hipStream_t s);
+
+// vector kernels
+void vec_copy(long n, const double* x, double* y, hipStream_t s);
+void vec_fill(long n, double v, double* y, hipStream_t s);
+void vec_axpby(long n, double a, const double* x, double b, double* y, hipStream_t s);
+// y = x + a*(y - b*z)
+void vec_bicg_p(long n, const double* r, double beta, double omega, const double* v, double* p,
+                hipStream_t s);
+// z = x - a*y
+void vec_sub_scaled(long n, const double* x, double a, const double* y, double* z,
+                    hipStream_t s);
+void vec_bicg_update(long n, double al, const double* ph, double om, const double* sh,
+                     const double* sv, const double* t, double* x, double* r, hipStream_t s);
+void vec_mask_rhs(const GeomV& g, const double* psi, const double* a0, double* b,
+                  hipStream_t s);

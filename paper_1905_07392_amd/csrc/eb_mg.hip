@@ -1,0 +1,732 @@
+// eb_mg.hip -- geometric multigrid preconditioner, the exact EB viscous operator, reductions
+// and Krylov vector kernels.
+//
+// Level operators are 7-point and symmetric: (M x)_c = D_c x_c - sum_f K_f x_nb(f), where a
+// face on a Dirichlet domain wall only adds its K to D.  Level 0 takes its face coefficients
+// from the apertures (Poisson) or apertures and face viscosities (viscous); coarse levels
+// average four child faces (and rescale by 1/4 for the doubled spacing) and eight child
+// cell shifts.  Smoothing is red-black Gauss-Seidel; within a colour every update depends only
+// on the other colour, so the result does not depend on thread order.
+#include "eb_internal.hpp"
+
+namespace {
+
+// ------------------------------------------------------------------------------------------
+// operator construction
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ void face_ijk(const GridV& g, int d, long f, int& i, int& j, int& k) {
+    int m0 = g.n[0] + (d == 0), m1 = g.n[1] + (d == 1);
+    i = (int)(f % m0);
+    long r = f / m0;
+    j = (int)(r % m1);
+    k = (int)(r / m1);
+}
+
+__global__ void k_K_poisson(GeomV g, int d, double beta, double* __restrict__ K) {
+    long nf = face_count(g.grid, d);
+    long f = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (f >= nf) return;
+    int i, j, k;
+    face_ijk(g.grid, d, f, i, j, k);
+    int q[3] = {i, j, k};
+    q[d] -= 1;
+    long lo = cell_at(g.grid, q[0], q[1], q[2]);
+    q[d] += 1;
+    long hi = cell_at(g.grid, q[0], q[1], q[2]);
+    double A = g.ap[d][f];
+    double h = g.grid.h;
+    K[f] = (A > 0.0 && lo >= 0 && hi >= 0) ? beta * A / (h * h) : 0.0;
+}
+
+__global__ void k_K_visc(GeomV g, int d, double dt, const double* __restrict__ eta,
+                         double* __restrict__ K) {
+    long nf = face_count(g.grid, d);
+    long f = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (f >= nf) return;
+    int i, j, k;
+    face_ijk(g.grid, d, f, i, j, k);
+    int q[3] = {i, j, k};
+    q[d] -= 1;
+    long lo = cell_at(g.grid, q[0], q[1], q[2]);
+    q[d] += 1;
+    long hi = cell_at(g.grid, q[0], q[1], q[2]);
+    double A = g.ap[d][f];
+    double h2 = g.grid.h * g.grid.h;
+    double v = 0.0;
+    if (A > 0.0) {
+        if (lo >= 0 && hi >= 0)
+            v = dt * A * 0.5 * (eta[lo] + eta[hi]) / h2;
+        else
+            v = 2.0 * dt * A * eta[lo >= 0 ? lo : hi] / h2;
+    }
+    K[f] = v;
+}
+
+__global__ void k_S_visc(GeomV g, double rho, double dt, const double* __restrict__ eta_eb,
+                         double* __restrict__ S) {
+    long c = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (c >= g.N) return;
+    double al = g.alpha[c];
+    double v = 0.0;
+    if (al > 0.0) {
+        v = al * rho;
+        int q = g.cutid[c];
+        if (q >= 0) {
+            double del = g.delta[q] > 0.5 ? g.delta[q] : 0.5;
+            v += dt * g.aeb[q] * eta_eb[q] / (del * g.grid.h * g.grid.h);
+        }
+    }
+    S[c] = v;
+}
+
+__global__ void k_diag(GridV g, const double* __restrict__ Kx, const double* __restrict__ Ky,
+                       const double* __restrict__ Kz, const double* __restrict__ S,
+                       const uint8_t* __restrict__ mask, double* __restrict__ D) {
+    long N = (long)g.n[0] * g.n[1] * g.n[2];
+    long c = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (c >= N) return;
+    if (!mask[c]) {
+        D[c] = 0.0;
+        return;
+    }
+    int i, j, k;
+    cell_coords(g, c, i, j, k);
+    const double* K[3] = {Kx, Ky, Kz};
+    double s = S ? S[c] : 0.0;
+    for (int d = 0; d < 3; d++) {
+        int q[3] = {i, j, k};
+        s += K[d][face_index(g, d, q[0], q[1], q[2])];
+        q[d] += 1;
+        s += K[d][face_index(g, d, q[0], q[1], q[2])];
+    }
+    D[c] = s;
+}
+
+__global__ void k_to_float(long n, const double* __restrict__ a, float* __restrict__ b) {
+    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t < n) b[t] = (float)a[t];
+}
+
+template <typename A, typename B>
+__global__ void k_cast(long n, const A* __restrict__ a, B* __restrict__ b) {
+    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t < n) b[t] = (B)a[t];
+}
+
+// ------------------------------------------------------------------------------------------
+// smoother, residual, transfers
+// ------------------------------------------------------------------------------------------
+// sum over the six faces of K_f x_nb (faces without a neighbour cell only feed the diagonal)
+template <typename T, int NC>
+__device__ __forceinline__ void offdiag(const LevelV<T>& L, const T* __restrict__ x, int i, int j,
+                                        int k, T acc[NC]) {
+    const GridV& g = L.grid;
+    long N = L.N;
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+#pragma unroll
+        for (int side = 0; side < 2; side++) {
+            int f[3] = {i, j, k};
+            f[d] += side;
+            T K = L.K[d][face_index(g, d, f[0], f[1], f[2])];
+            if (K == (T)0) continue;
+            int q[3] = {i, j, k};
+            q[d] += side ? 1 : -1;
+            long nb = cell_at(g, q[0], q[1], q[2]);
+            if (nb < 0) continue;
+#pragma unroll
+            for (int m = 0; m < NC; m++) acc[m] += K * x[m * N + nb];
+        }
+    }
+}
+
+template <typename T, int NC>
+__global__ void k_smooth(LevelV<T> L, const T* __restrict__ b, T* __restrict__ x, int col) {
+    const GridV& g = L.grid;
+    long half = L.N / 2;
+    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t >= half) return;
+    int nxh = g.n[0] / 2;
+    long row = t / nxh;
+    int ih = (int)(t - row * nxh);
+    int j = (int)(row % g.n[1]);
+    int k = (int)(row / g.n[1]);
+    int i = 2 * ih + ((j + k + col) & 1);
+    long c = cell_index(g, i, j, k);
+    if (!L.mask[c]) return;
+    T dg = L.D[c];
+    if (!(dg > (T)0)) return;
+    T acc[NC];
+#pragma unroll
+    for (int m = 0; m < NC; m++) acc[m] = b[m * L.N + c];
+    offdiag<T, NC>(L, x, i, j, k, acc);
+#pragma unroll
+    for (int m = 0; m < NC; m++) x[m * L.N + c] = acc[m] / dg;
+}
+
+// r = b - M x (b may be null: r = -M x is not needed; apply handled separately)
+template <typename T, int NC>
+__global__ void k_resid(LevelV<T> L, const T* __restrict__ b, const T* __restrict__ x,
+                        T* __restrict__ r) {
+    long c = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (c >= L.N) return;
+    if (!L.mask[c]) {
+#pragma unroll
+        for (int m = 0; m < NC; m++) r[m * L.N + c] = (T)0;
+        return;
+    }
+    int i, j, k;
+    cell_coords(L.grid, c, i, j, k);
+    T acc[NC];
+#pragma unroll
+    for (int m = 0; m < NC; m++) acc[m] = (T)0;
+    offdiag<T, NC>(L, x, i, j, k, acc);
+    T dg = L.D[c];
+#pragma unroll
+    for (int m = 0; m < NC; m++) {
+        T mx = dg * x[m * L.N + c] - acc[m];
+        r[m * L.N + c] = b ? b[m * L.N + c] - mx : mx;
+    }
+}
+
+template <typename TF, typename TC, int NC>
+__global__ void k_restrict(GridV gf, GridV gc, const uint8_t* __restrict__ mf,
+                           const uint8_t* __restrict__ mc, const TF* __restrict__ rf,
+                           TC* __restrict__ bc) {
+    long Nc = (long)gc.n[0] * gc.n[1] * gc.n[2];
+    long Nf = (long)gf.n[0] * gf.n[1] * gf.n[2];
+    long c = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (c >= Nc) return;
+    int i, j, k;
+    cell_coords(gc, c, i, j, k);
+    TF s[NC];
+#pragma unroll
+    for (int m = 0; m < NC; m++) s[m] = (TF)0;
+    for (int q = 0; q < 8; q++) {
+        long f = cell_index(gf, 2 * i + (q & 1), 2 * j + ((q >> 1) & 1), 2 * k + (q >> 2));
+        if (!mf[f]) continue;
+#pragma unroll
+        for (int m = 0; m < NC; m++) s[m] += rf[m * Nf + f];
+    }
+#pragma unroll
+    for (int m = 0; m < NC; m++) bc[m * Nc + c] = mc[c] ? (TC)(s[m] / (TF)8) : (TC)0;
+}
+
+template <typename TC, typename TF, int NC>
+__global__ void k_prolong(GridV gf, GridV gc, const uint8_t* __restrict__ mf,
+                          const TC* __restrict__ ec, TF* __restrict__ xf) {
+    long Nc = (long)gc.n[0] * gc.n[1] * gc.n[2];
+    long Nf = (long)gf.n[0] * gf.n[1] * gf.n[2];
+    long f = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (f >= Nf) return;
+    if (!mf[f]) return;
+    int i, j, k;
+    cell_coords(gf, f, i, j, k);
+    long c = cell_index(gc, i >> 1, j >> 1, k >> 1);
+#pragma unroll
+    for (int m = 0; m < NC; m++) xf[m * Nf + f] += (TF)ec[m * Nc + c];
+}
+
+// ------------------------------------------------------------------------------------------
+// exact EB viscous Helmholtz operator (Eq. implicit-viscous with the wall flux of Eq. dudn)
+// ------------------------------------------------------------------------------------------
+__global__ void k_visc_apply(GeomV g, double rho, double dt, const double* __restrict__ eta,
+                             const double* __restrict__ eta_eb, const double* __restrict__ u,
+                             double* __restrict__ out, int homog) {
+    long N = g.N;
+    long c = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (c >= N) return;
+    double al = g.alpha[c];
+    if (!(al > 0.0)) {
+        for (int m = 0; m < 3; m++) out[m * N + c] = 0.0;
+        return;
+    }
+    int i, j, k;
+    cell_coords(g.grid, c, i, j, k);
+    double h2 = g.grid.h * g.grid.h;
+    double acc[3];
+    for (int m = 0; m < 3; m++) acc[m] = al * rho * u[m * N + c];
+    double ec = eta[c];
+    for (int d = 0; d < 3; d++)
+        for (int side = 0; side < 2; side++) {
+            int f[3] = {i, j, k};
+            f[d] += side;
+            double A = g.ap[d][face_index(g.grid, d, f[0], f[1], f[2])];
+            if (A == 0.0) continue;
+            int q[3] = {i, j, k};
+            q[d] += side ? 1 : -1;
+            long nb = cell_at(g.grid, q[0], q[1], q[2]);
+            if (nb >= 0) {
+                double K = dt * A * 0.5 * (ec + eta[nb]) / h2;
+                for (int m = 0; m < 3; m++) acc[m] -= K * (u[m * N + nb] - u[m * N + c]);
+            } else {
+                double K = 2.0 * dt * A * ec / h2;
+                for (int m = 0; m < 3; m++) {
+                    double uw = homog ? 0.0 : g.wall[2 * d + side][m];
+                    acc[m] -= K * (uw - u[m * N + c]);
+                }
+            }
+        }
+    int q = g.cutid[c];
+    if (q >= 0) {
+        int nc = g.ncut;
+        double d1 = g.dd[q], d2 = g.dd[nc + q];
+        double den = d1 * d2 * (d2 - d1) * g.grid.h;
+        double coef = dt * g.aeb[q] * eta_eb[q] / g.grid.h;
+        for (int m = 0; m < 3; m++) {
+            double ue = homog ? 0.0 : g.ueb[m];
+            double s1 = 0.0, s2 = 0.0;
+            for (int t = 0; t < 9; t++) {
+                int c1 = g.sidx[(long)t * nc + q];
+                s1 += g.sw[(long)t * nc + q] * (c1 >= 0 ? u[m * N + c1] : ue);
+                int c2 = g.sidx[(long)(t + 9) * nc + q];
+                s2 += g.sw[(long)(t + 9) * nc + q] * (c2 >= 0 ? u[m * N + c2] : ue);
+            }
+            double gn = (d2 * d2 * (s1 - ue) - d1 * d1 * (s2 - ue)) / den;
+            acc[m] += coef * gn;
+        }
+    }
+    for (int m = 0; m < 3; m++) out[m * N + c] = acc[m];
+}
+
+// ------------------------------------------------------------------------------------------
+// reductions (fixed grid, fixed order: deterministic for a given size)
+// ------------------------------------------------------------------------------------------
+constexpr int RED_MAXB = 1024;
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < (unsigned)o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+__device__ __forceinline__ double block_max(double v, double* sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < (unsigned)o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+        __syncthreads();
+    }
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+struct DotArgs {
+    const double* a[4];
+    const double* b[4];
+};
+
+__global__ void k_dots(long n, int np, DotArgs args, double* __restrict__ part) {
+    __shared__ double sh[EB_BLOCK];
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n;
+         t += (long)gridDim.x * blockDim.x)
+        for (int p = 0; p < np; p++) s[p] += args.a[p][t] * args.b[p][t];
+    for (int p = 0; p < np; p++) {
+        double v = block_sum(s[p], sh);
+        if (threadIdx.x == 0) part[p * gridDim.x + blockIdx.x] = v;
+    }
+}
+
+// per-component max |x| of a [ncomp][n] array
+__global__ void k_maxabs(long n, int ncomp, const double* __restrict__ x,
+                         double* __restrict__ part) {
+    __shared__ double sh[EB_BLOCK];
+    for (int m = 0; m < ncomp; m++) {
+        double v = 0.0;
+        for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n;
+             t += (long)gridDim.x * blockDim.x)
+            v = fmax(v, fabs(x[m * n + t]));
+        v = block_max(v, sh);
+        if (threadIdx.x == 0) part[m * gridDim.x + blockIdx.x] = v;
+    }
+}
+
+__global__ void k_sum_open(GeomV g, const double* __restrict__ x, double* __restrict__ part) {
+    __shared__ double sh[EB_BLOCK];
+    double s = 0.0, cnt = 0.0;
+    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < g.N;
+         t += (long)gridDim.x * blockDim.x)
+        if (g.alpha[t] > 0.0) {
+            s += x[t];
+            cnt += 1.0;
+        }
+    double v = block_sum(s, sh);
+    double w = block_sum(cnt, sh);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = v;
+        part[gridDim.x + blockIdx.x] = w;
+    }
+}
+
+// per-row sums of a [nrow][n] array
+__global__ void k_rowsum(long n, int nrow, const double* __restrict__ x,
+                         double* __restrict__ part) {
+    __shared__ double sh[EB_BLOCK];
+    for (int p = 0; p < nrow; p++) {
+        double v = 0.0;
+        for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n;
+             t += (long)gridDim.x * blockDim.x)
+            v += x[p * n + t];
+        v = block_sum(v, sh);
+        if (threadIdx.x == 0) part[p * gridDim.x + blockIdx.x] = v;
+    }
+}
+
+__global__ void k_face_flux_max(GeomV g, const double* __restrict__ fx,
+                                const double* __restrict__ fy, const double* __restrict__ fz,
+                                double* __restrict__ part) {
+    __shared__ double sh[EB_BLOCK];
+    const double* fo[3] = {fx, fy, fz};
+    double v = 0.0;
+    for (int d = 0; d < 3; d++) {
+        long nf = face_count(g.grid, d);
+        for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < nf;
+             t += (long)gridDim.x * blockDim.x)
+            v = fmax(v, fabs(g.ap[d][t] * fo[d][t]));
+    }
+    v = block_max(v, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = v / g.grid.h;
+}
+
+// out[p] = reduction over nb partials of row p (mode 0 sum, 1 max), fixed order
+__global__ void k_final(const double* __restrict__ part, int nb, int nrow, int mode,
+                        double* __restrict__ out) {
+    __shared__ double sh[EB_BLOCK];
+    for (int p = 0; p < nrow; p++) {
+        double v = 0.0;
+        for (int t = threadIdx.x; t < nb; t += blockDim.x)
+            v = mode ? fmax(v, part[p * nb + t]) : v + part[p * nb + t];
+        v = mode ? block_max(v, sh) : block_sum(v, sh);
+        if (threadIdx.x == 0) out[p] = v;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// vector kernels
+// ------------------------------------------------------------------------------------------
+__global__ void k_copy(long n, const double* __restrict__ x, double* __restrict__ y) {
+    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t < n) y[t] = x[t];
+}
+__global__ void k_fill(long n, double v, double* __restrict__ y) {
+    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t < n) y[t] = v;
+}
+template <typename T>
+__global__ void k_zero(long n, T* __restrict__ y) {
+    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t < n) y[t] = (T)0;
+}
+__global__ void k_axpby(long n, double a, const double* __restrict__ x, double b,
+                        double* __restrict__ y) {
+    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t < n) y[t] = a * x[t] + b * y[t];
+}
+__global__ void k_bicg_p(long n, const double* __restrict__ r, double beta, double omega,
+                         const double* __restrict__ v, double* __restrict__ p) {
+    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t < n) p[t] = r[t] + beta * (p[t] - omega * v[t]);
+}
+__global__ void k_sub_scaled(long n, const double* __restrict__ x, double a,
+                             const double* __restrict__ y, double* __restrict__ z) {
+    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t < n) z[t] = x[t] - a * y[t];
+}
+__global__ void k_bicg_update(long n, double al, const double* __restrict__ ph, double om,
+                              const double* __restrict__ sh, const double* __restrict__ sv,
+                              const double* __restrict__ tv, double* __restrict__ x,
+                              double* __restrict__ r) {
+    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t < n) {
+        x[t] += al * ph[t] + om * sh[t];
+        r[t] = sv[t] - om * tv[t];
+    }
+}
+// b = alpha psi - a0 on open cells (a0 = A(0), the boundary part of the affine operator)
+__global__ void k_mask_rhs(GeomV g, const double* __restrict__ psi, const double* __restrict__ a0,
+                           double* __restrict__ b) {
+    long N = g.N;
+    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t >= 3 * N) return;
+    long c = t % N;
+    double al = g.alpha[c];
+    b[t] = al > 0.0 ? al * psi[t] - a0[t] : 0.0;
+}
+
+// ------------------------------------------------------------------------------------------
+// V-cycle driver helpers
+// ------------------------------------------------------------------------------------------
+template <typename T>
+void smooth_pass(const Level& L, int nc, const T* b, T* x, int col, hipStream_t s);
+template <>
+void smooth_pass<double>(const Level& L, int nc, const double* b, double* x, int col,
+                         hipStream_t s) {
+    unsigned gb = grid_for(L.N / 2);
+    if (nc == 3) k_smooth<double, 3><<<gb, EB_BLOCK, 0, s>>>(L.v64(), b, x, col);
+    else k_smooth<double, 1><<<gb, EB_BLOCK, 0, s>>>(L.v64(), b, x, col);
+}
+template <>
+void smooth_pass<float>(const Level& L, int nc, const float* b, float* x, int col,
+                        hipStream_t s) {
+    unsigned gb = grid_for(L.N / 2);
+    if (nc == 3) k_smooth<float, 3><<<gb, EB_BLOCK, 0, s>>>(L.v32(), b, x, col);
+    else k_smooth<float, 1><<<gb, EB_BLOCK, 0, s>>>(L.v32(), b, x, col);
+}
+template <typename T>
+void resid_pass(const Level& L, int nc, const T* b, const T* x, T* r, hipStream_t s);
+template <>
+void resid_pass<double>(const Level& L, int nc, const double* b, const double* x, double* r,
+                        hipStream_t s) {
+    if (nc == 3) k_resid<double, 3><<<grid_for(L.N), EB_BLOCK, 0, s>>>(L.v64(), b, x, r);
+    else k_resid<double, 1><<<grid_for(L.N), EB_BLOCK, 0, s>>>(L.v64(), b, x, r);
+}
+template <>
+void resid_pass<float>(const Level& L, int nc, const float* b, const float* x, float* r,
+                       hipStream_t s) {
+    if (nc == 3) k_resid<float, 3><<<grid_for(L.N), EB_BLOCK, 0, s>>>(L.v32(), b, x, r);
+    else k_resid<float, 1><<<grid_for(L.N), EB_BLOCK, 0, s>>>(L.v32(), b, x, r);
+}
+template <typename TF, typename TC>
+void restrict_pass(const Level& F, const Level& C, int nc, const TF* rf, TC* bc, hipStream_t s) {
+    if (nc == 3)
+        k_restrict<TF, TC, 3><<<grid_for(C.N), EB_BLOCK, 0, s>>>(F.grid, C.grid, F.mask, C.mask,
+                                                                rf, bc);
+    else
+        k_restrict<TF, TC, 1><<<grid_for(C.N), EB_BLOCK, 0, s>>>(F.grid, C.grid, F.mask, C.mask,
+                                                                rf, bc);
+}
+template <typename TC, typename TF>
+void prolong_pass(const Level& F, const Level& C, int nc, const TC* ec, TF* xf, hipStream_t s) {
+    if (nc == 3)
+        k_prolong<TC, TF, 3><<<grid_for(F.N), EB_BLOCK, 0, s>>>(F.grid, C.grid, F.mask, ec, xf);
+    else
+        k_prolong<TC, TF, 1><<<grid_for(F.N), EB_BLOCK, 0, s>>>(F.grid, C.grid, F.mask, ec, xf);
+}
+
+struct VArgs {
+    Level* lev;
+    int nlev, nc, nu1, nu2, nbottom;
+    bool mixed;
+    hipStream_t s;
+};
+
+bool level_f32(const VArgs& a, int l) { return a.mixed && l < a.nlev - 1; }
+
+template <typename T>
+T* xl(Level& L);
+template <>
+double* xl<double>(Level& L) { return L.x; }
+template <>
+float* xl<float>(Level& L) { return L.xf; }
+template <typename T>
+T* bl(Level& L);
+template <>
+double* bl<double>(Level& L) { return L.b; }
+template <>
+float* bl<float>(Level& L) { return L.bf; }
+template <typename T>
+T* rl(Level& L);
+template <>
+double* rl<double>(Level& L) { return L.r; }
+template <>
+float* rl<float>(Level& L) { return L.rf; }
+
+void vcycle_rec(const VArgs& a, int l);
+
+template <typename T>
+void vcycle_level(const VArgs& a, int l) {
+    Level& L = a.lev[l];
+    T* x = xl<T>(L);
+    T* b = bl<T>(L);
+    k_zero<T><<<grid_for(a.nc * L.N), EB_BLOCK, 0, a.s>>>(a.nc * L.N, x);
+    if (l == a.nlev - 1) {
+        for (int t = 0; t < a.nbottom; t++) {
+            smooth_pass<T>(L, a.nc, b, x, 0, a.s);
+            smooth_pass<T>(L, a.nc, b, x, 1, a.s);
+        }
+        for (int t = 0; t < a.nbottom; t++) {
+            smooth_pass<T>(L, a.nc, b, x, 1, a.s);
+            smooth_pass<T>(L, a.nc, b, x, 0, a.s);
+        }
+        return;
+    }
+    for (int t = 0; t < a.nu1; t++) {
+        smooth_pass<T>(L, a.nc, b, x, 0, a.s);
+        smooth_pass<T>(L, a.nc, b, x, 1, a.s);
+    }
+    T* r = rl<T>(L);
+    resid_pass<T>(L, a.nc, b, x, r, a.s);
+    Level& C = a.lev[l + 1];
+    if (level_f32(a, l + 1)) restrict_pass<T, float>(L, C, a.nc, r, C.bf, a.s);
+    else restrict_pass<T, double>(L, C, a.nc, r, C.b, a.s);
+    vcycle_rec(a, l + 1);
+    if (level_f32(a, l + 1)) prolong_pass<float, T>(L, C, a.nc, C.xf, x, a.s);
+    else prolong_pass<double, T>(L, C, a.nc, C.x, x, a.s);
+    for (int t = 0; t < a.nu2; t++) {
+        smooth_pass<T>(L, a.nc, b, x, 1, a.s);
+        smooth_pass<T>(L, a.nc, b, x, 0, a.s);
+    }
+}
+
+void vcycle_rec(const VArgs& a, int l) {
+    if (level_f32(a, l)) vcycle_level<float>(a, l);
+    else vcycle_level<double>(a, l);
+}
+
+void finish_operator(Level* lev, int nlev, bool mixed, hipStream_t s) {
+    for (int l = 1; l < nlev; l++) {
+        for (int d = 0; d < 3; d++)
+            level_coarsen_faces(lev[l].grid, lev[l - 1].grid, d, lev[l - 1].K[d], lev[l].K[d],
+                                1.0 / 16.0, s);
+        level_coarsen_cells(lev[l].grid, lev[l - 1].grid, lev[l - 1].S, lev[l].S, s);
+    }
+    for (int l = 0; l < nlev; l++) {
+        Level& L = lev[l];
+        k_diag<<<grid_for(L.N), EB_BLOCK, 0, s>>>(L.grid, L.K[0], L.K[1], L.K[2], L.S, L.mask,
+                                                  L.D);
+        if (mixed && l < nlev - 1) {
+            for (int d = 0; d < 3; d++) {
+                long nf = face_count(L.grid, d);
+                k_to_float<<<grid_for(nf), EB_BLOCK, 0, s>>>(nf, L.K[d], L.Kf[d]);
+            }
+            k_to_float<<<grid_for(L.N), EB_BLOCK, 0, s>>>(L.N, L.D, L.Df);
+        }
+    }
+}
+
+}  // namespace
+
+void mg_build_poisson(Level* lev, int nlev, const GeomV& g, double beta, bool mixed,
+                      hipStream_t s) {
+    for (int d = 0; d < 3; d++)
+        k_K_poisson<<<grid_for(face_count(g.grid, d)), EB_BLOCK, 0, s>>>(g, d, beta, lev[0].K[d]);
+    k_zero<double><<<grid_for(g.N), EB_BLOCK, 0, s>>>(g.N, lev[0].S);
+    finish_operator(lev, nlev, mixed, s);
+}
+
+void mg_build_visc(Level* lev, int nlev, const GeomV& g, double rho, double dt,
+                   const double* eta, const double* eta_eb, bool mixed, hipStream_t s) {
+    for (int d = 0; d < 3; d++)
+        k_K_visc<<<grid_for(face_count(g.grid, d)), EB_BLOCK, 0, s>>>(g, d, dt, eta, lev[0].K[d]);
+    k_S_visc<<<grid_for(g.N), EB_BLOCK, 0, s>>>(g, rho, dt, eta_eb, lev[0].S);
+    finish_operator(lev, nlev, mixed, s);
+}
+
+void mg_vcycle(Level* lev, int nlev, int ncomp, bool mixed, const double* b, double* x, int nu1,
+               int nu2, int nbottom, hipStream_t s) {
+    VArgs a{lev, nlev, ncomp, nu1, nu2, nbottom, mixed, s};
+    Level& L0 = lev[0];
+    long n = (long)ncomp * L0.N;
+    // level 0 works on the caller's arrays in FP64 mode; in mixed mode on FP32 copies
+    double* keep_b = L0.b;
+    double* keep_x = L0.x;
+    if (level_f32(a, 0)) {
+        k_cast<double, float><<<grid_for(n), EB_BLOCK, 0, s>>>(n, b, L0.bf);
+        vcycle_rec(a, 0);
+        k_cast<float, double><<<grid_for(n), EB_BLOCK, 0, s>>>(n, L0.xf, x);
+    } else {
+        L0.b = const_cast<double*>(b);
+        L0.x = x;
+        vcycle_rec(a, 0);
+        L0.b = keep_b;
+        L0.x = keep_x;
+    }
+}
+
+void mg_sweep_level0(const Level& L, int ncomp, bool f32, const void* b, void* x, int colour,
+                     hipStream_t s) {
+    if (f32)
+        smooth_pass<float>(L, ncomp, (const float*)b, (float*)x, colour, s);
+    else
+        smooth_pass<double>(L, ncomp, (const double*)b, (double*)x, colour, s);
+}
+
+void mg_apply_level0(const Level& L, int ncomp, const double* x, double* y, hipStream_t s) {
+    resid_pass<double>(L, ncomp, nullptr, x, y, s);
+}
+
+void op_visc_apply(const GeomV& g, double rho, double dt, const double* eta,
+                   const double* eta_eb, const double* u, double* out, int homogeneous,
+                   hipStream_t s) {
+    k_visc_apply<<<grid_for(g.N), EB_BLOCK, 0, s>>>(g, rho, dt, eta, eta_eb, u, out, homogeneous);
+}
+
+// ------------------------------------------------------------------------------------------
+// reductions: results land in out (device); the caller copies what it needs to the host
+// ------------------------------------------------------------------------------------------
+int red_blocks(long n) {
+    long b = (n + EB_BLOCK - 1) / EB_BLOCK;
+    if (b > RED_MAXB) b = RED_MAXB;
+    return (int)(b < 1 ? 1 : b);
+}
+
+void red_dots(long n, int np, const double* const a[4], const double* const b[4], double* part,
+              double* out, hipStream_t s) {
+    DotArgs args;
+    for (int p = 0; p < 4; p++) {
+        args.a[p] = p < np ? a[p] : nullptr;
+        args.b[p] = p < np ? b[p] : nullptr;
+    }
+    int nb = red_blocks(n);
+    k_dots<<<nb, EB_BLOCK, 0, s>>>(n, np, args, part);
+    k_final<<<1, EB_BLOCK, 0, s>>>(part, nb, np, 0, out);
+}
+
+void red_maxabs(long n, int ncomp, const double* x, double* part, double* out, hipStream_t s) {
+    int nb = red_blocks(n);
+    k_maxabs<<<nb, EB_BLOCK, 0, s>>>(n, ncomp, x, part);
+    k_final<<<1, EB_BLOCK, 0, s>>>(part, nb, ncomp, 1, out);
+}
+
+void red_sum_open(const GeomV& g, const double* x, double* part, double* out, hipStream_t s) {
+    int nb = red_blocks(g.N);
+    k_sum_open<<<nb, EB_BLOCK, 0, s>>>(g, x, part);
+    k_final<<<1, EB_BLOCK, 0, s>>>(part, nb, 2, 0, out);
+}
+
+void red_sum(long n, int nrow, const double* x, double* part, double* out, hipStream_t s) {
+    int nb = red_blocks(n);
+    k_rowsum<<<nb, EB_BLOCK, 0, s>>>(n, nrow, x, part);
+    k_final<<<1, EB_BLOCK, 0, s>>>(part, nb, nrow, 0, out);
+}
+
+void op_face_flux_max(const GeomV& g, double* const f[3], double* part, double* out,
+                      hipStream_t s) {
+    long n = face_count(g.grid, 0);
+    int nb = red_blocks(n);
+    k_face_flux_max<<<nb, EB_BLOCK, 0, s>>>(g, f[0], f[1], f[2], part);
+    k_final<<<1, EB_BLOCK, 0, s>>>(part, nb, 1, 1, out);
+}
+
+void vec_copy(long n, const double* x, double* y, hipStream_t s) {
+    if (n > 0) k_copy<<<grid_for(n), EB_BLOCK, 0, s>>>(n, x, y);
+}
+void vec_fill(long n, double v, double* y, hipStream_t s) {
+    if (n > 0) k_fill<<<grid_for(n), EB_BLOCK, 0, s>>>(n, v, y);
+}
+void vec_axpby(long n, double a, const double* x, double b, double* y, hipStream_t s) {
+    k_axpby<<<grid_for(n), EB_BLOCK, 0, s>>>(n, a, x, b, y);
+}
+void vec_bicg_p(long n, const double* r, double beta, double omega, const double* v, double* p,
+                hipStream_t s) {
+    k_bicg_p<<<grid_for(n), EB_BLOCK, 0, s>>>(n, r, beta, omega, v, p);
+}
+void vec_sub_scaled(long n, const double* x, double a, const double* y, double* z,
+                    hipStream_t s) {
+    k_sub_scaled<<<grid_for(n), EB_BLOCK, 0, s>>>(n, x, a, y, z);
+}
+void vec_bicg_update(long n, double al, const double* ph, double om, const double* sh,
+                     const double* sv, const double* t, double* x, double* r, hipStream_t s) {
+    k_bicg_update<<<grid_for(n), EB_BLOCK, 0, s>>>(n, al, ph, om, sh, sv, t, x, r);
+}
+void vec_mask_rhs(const GeomV& g, const double* psi, const double* a0, double* b,
+                  hipStream_t s) {
+    k_mask_rhs<<<grid_for(3 * g.N), EB_BLOCK, 0, s>>>(g, psi, a0, b);
+}
