@@ -35,6 +35,8 @@ def parse():
     ap.add_argument("--kernel-only", action="store_true",
                     help="only the smoother timing loop (for the profiler)")
     ap.add_argument("--sweeps", type=int, default=40)
+    ap.add_argument("--nu", type=int, default=2, help="smoothing pairs before and after")
+    ap.add_argument("--nbottom", type=int, default=16)
     return ap.parse_args()
 
 
@@ -107,6 +109,8 @@ def main():
         w = w.replace(n=(args.n,) * 3, h=1.0 / args.n, name=f"sphere{args.n}")
     prec = api.EB_MIXED if args.precision == "mixed" else api.EB_FP64
     box, body, rheo, opts = pkg.from_workload(w, precision=prec)
+    opts.nu1 = opts.nu2 = args.nu
+    opts.nbottom = args.nbottom
     dev = torch.device("cuda:0")
     ctx = api.eb_geometry_build(box, body, dev)
     u = torch.from_numpy(I.initial_velocity(w)).to(dev)
@@ -142,8 +146,11 @@ def main():
     print(f"[bench] timed {args.steps} steps: {ms_step:.2f} ms/step, {mlups:.1f} MLUPS; "
           f"last stats {stats[-1]}", file=sys.stderr, flush=True)
 
-    # roofline of the dominant kernel: the finest-level viscous smoother with the operator of
-    # the last corrector solve
+    # roofline of the dominant kernel: the finest-level viscous smoother, with the viscous
+    # operator of the final state (one V-cycle builds it)
+    eta, eta_eb = api.eb_apparent_viscosity(ctx, rheo, u)
+    api.eb_mg_vcycle(ctx, api.EB_SYS_VISC, torch.zeros_like(u), opts, precision=prec, rho=w.rho,
+                     dt=w.dt, eta=eta, eta_eb=eta_eb)
     ms_k = time_smoother(api, ctx, prec, args.sweeps, torch)
     wbytes = 4 if prec == api.EB_MIXED else 8
     algo = smoother_bytes_per_launch(ctx.N, 3, wbytes)

@@ -71,10 +71,20 @@ struct eb_ctx {
     double* f[3];
     double* kv[10];
     double* pk[4];
-    int vcycles;
     int built_sys;    // operator currently held by the levels (-1 none)
     bool built_mixed;
+    // device Krylov scalars, per-solve (state, count) slots, per-solve divergence norms
+    double* ks;
+    int* kst;
+    double* divs;
+    // pinned host words for the lagged convergence poll, and their events
+    int* pin;
+    hipEvent_t ev[2];
 };
+
+namespace {
+constexpr int NSLOT = 8;
+}
 
 namespace {
 
@@ -119,6 +129,9 @@ size_t carve(eb_ctx* c, char* base, bool dry) {
     c->errdev = cv.take<int>(1);
     c->part = cv.take<double>(4 * 1024);
     c->red = cv.take<double>(64);
+    c->ks = cv.take<double>(KS_COUNT);
+    c->kst = cv.take<int>(2 * NSLOT);
+    c->divs = cv.take<double>(NSLOT);
     // levels
     int m[3] = {g.n[0], g.n[1], g.n[2]};
     double h = g.h;
@@ -266,10 +279,11 @@ int fetch(eb_ctx* c, double* host, int n) {
     return EB_OK;
 }
 
-bool finite(double x) { return std::isfinite(x); }
-
 // ------------------------------------------------------------------------------------------
-// solvers
+// solvers.  Krylov scalars and the convergence state live on the device (eb_krylov.hip): the
+// host enqueues whole iterations and polls the state of the previous iteration while the
+// current one runs, so the GPU never waits for the host.  Each solve reports into a state
+// slot (state, count) that callers read once at the end.
 // ------------------------------------------------------------------------------------------
 struct SolveCfg {
     bool mixed;
@@ -286,203 +300,180 @@ SolveCfg cfg_of(const eb_step_opts* o) {
     return k;
 }
 
-void vcyc(eb_ctx* c, int ncomp, const SolveCfg& k, const double* b, double* x) {
-    mg_vcycle(c->lev, c->nlev, ncomp, k.mixed, b, x, k.nu1, k.nu2, k.nbottom, c->s);
-    c->vcycles++;
+void vcyc(eb_ctx* c, int ncomp, const SolveCfg& k, const double* b, double* x, const int* gate) {
+    mg_vcycle(c->lev, c->nlev, ncomp, k.mixed, b, x, k.nu1, k.nu2, k.nbottom, c->s, gate);
 }
 
-double dot1(eb_ctx* c, long n, const double* a, const double* b, int* err) {
-    const double* A[4] = {a, nullptr, nullptr, nullptr};
-    const double* B[4] = {b, nullptr, nullptr, nullptr};
-    red_dots(n, 1, A, B, c->part, c->red, c->s);
-    double v = 0;
-    *err = fetch(c, &v, 1);
-    return v;
+// lagged convergence test: enqueue the read-back of the slot's state after iteration it and
+// wait for the one of iteration it-1 (already executed or about to be)
+bool poll_done(eb_ctx* c, int slot, int it) {
+    int b = it & 1;
+    hipMemcpyAsync(&c->pin[2 * b], c->kst + 2 * slot, 2 * sizeof(int), hipMemcpyDeviceToHost,
+                   c->s);
+    hipEventRecord(c->ev[b], c->s);
+    if (it < 2) return false;
+    int pb = (it - 1) & 1;
+    hipEventSynchronize(c->ev[pb]);
+    return c->pin[2 * pb] != 0;
 }
 
-double maxabs1(eb_ctx* c, long n, const double* x, int* err) {
-    red_maxabs(n, 1, x, c->part, c->red, c->s);
-    double v = 0;
-    *err = fetch(c, &v, 1);
-    return v;
-}
-
-// preconditioned CG for M p = b on level 0 (operator already built); rtol * max(|b|, scale)
-int pcg(eb_ctx* c, const double* b, double* x, double rtol, double scale, const SolveCfg& k,
-        int* iters) {
+// preconditioned CG for M x = b on level 0 (operator already built), state in `slot`;
+// ks[KS_RTOL] and ks[KS_SCALE] must be set
+void pcg(eb_ctx* c, const double* b, double* x, const SolveCfg& k, int slot) {
     long N = c->N;
     double *r = c->pk[0], *z = c->pk[1], *pd = c->pk[2], *q = c->pk[3];
-    int e = EB_OK;
-    *iters = 0;
+    double* ks = c->ks;
+    int* st = c->kst + 2 * slot;
+    const double* A1[4] = {nullptr, nullptr, nullptr, nullptr};
+    const double* B1[4] = {nullptr, nullptr, nullptr, nullptr};
     mg_apply_level0(c->lev[0], 1, x, q, c->s);
     vec_sub_scaled(N, b, 1.0, q, r, c->s);
-    double bn = maxabs1(c, N, b, &e);
-    if (e) return e;
-    if (scale > bn) bn = scale;
-    double rn = maxabs1(c, N, r, &e);
-    if (e) return e;
-    if (bn == 0.0 || rn <= rtol * bn) return EB_OK;
-    vcyc(c, 1, k, r, z);
+    red_maxabs(N, 1, b, c->part, ks + KS_BN, c->s);
+    red_maxabs(N, 1, r, c->part, ks + KS_RN, c->s);
+    ks_op(KS_INIT, ks, st, 0, c->s);
+    vcyc(c, 1, k, r, z, st);
     vec_copy(N, z, pd, c->s);
-    double rz = dot1(c, N, r, z, &e);
-    if (e) return e;
+    A1[0] = r;
+    B1[0] = z;
+    red_dots(N, 1, A1, B1, c->part, ks + KS_RZ, c->s, st);
     for (int it = 1; it <= k.max_iter; it++) {
-        mg_apply_level0(c->lev[0], 1, pd, q, c->s);
-        double pq = dot1(c, N, pd, q, &e);
-        if (e) return e;
-        double a = rz / pq;
-        vec_axpby(N, a, pd, 1.0, x, c->s);
-        vec_axpby(N, -a, q, 1.0, r, c->s);
-        *iters = it;
-        rn = maxabs1(c, N, r, &e);
-        if (e) return e;
-        if (!finite(rn)) return set_err(EB_ENAN, "non-finite residual in the Poisson solve");
-        if (rn <= rtol * bn) return EB_OK;
-        vcyc(c, 1, k, r, z);
-        double rzn = dot1(c, N, r, z, &e);
-        if (e) return e;
-        double be = rzn / rz;
-        rz = rzn;
-        vec_axpby(N, 1.0, z, be, pd, c->s);
+        mg_apply_level0(c->lev[0], 1, pd, q, c->s, st);
+        A1[0] = pd;
+        B1[0] = q;
+        red_dots(N, 1, A1, B1, c->part, ks + KS_PQ, c->s, st);
+        ks_op(KS_CG_ALPHA, ks, st, it, c->s);
+        ks_cg_xr(N, x, r, pd, q, ks, st, c->s);
+        red_maxabs(N, 1, r, c->part, ks + KS_RN, c->s, st);
+        ks_op(KS_CHECK_R, ks, st, it, c->s);
+        vcyc(c, 1, k, r, z, st);
+        A1[0] = r;
+        B1[0] = z;
+        red_dots(N, 1, A1, B1, c->part, ks + KS_RZN, c->s, st);
+        ks_op(KS_CG_BETA, ks, st, it, c->s);
+        ks_cg_p(N, pd, z, ks, st, c->s);
+        if (poll_done(c, slot, it)) break;
     }
-    return set_err(EB_ENOCONV, "Poisson solve: no convergence in %d iterations", k.max_iter);
 }
 
-int poisson_solve(eb_ctx* c, double beta, const double* div, double* p, double rtol,
-                  double scale, const SolveCfg& k, int* iters) {
+// Poisson solve for the projections: M p = -(D w - mean), then p normalised to zero mean
+void poisson_solve(eb_ctx* c, double beta, const double* div, double* p, const SolveCfg& k,
+                   int slot) {
     mg_build_poisson(c->lev, c->nlev, c->g, beta, k.mixed, c->s);
     c->built_sys = EB_SYS_POISSON;
     c->built_mixed = k.mixed;
-    double h2[2];
-    red_sum_open(c->g, div, c->part, c->red, c->s);
-    int e = fetch(c, h2, 2);
-    if (e) return e;
-    double mean = h2[1] > 0 ? h2[0] / h2[1] : 0.0;
-    op_poisson_rhs(c->g, div, mean, c->pb, c->s);
-    int ret = pcg(c, c->pb, p, rtol, scale, k, iters);
-    if (ret != EB_OK && ret != EB_ENOCONV) return ret;
-    red_sum_open(c->g, p, c->part, c->red, c->s);
-    e = fetch(c, h2, 2);
-    if (e) return e;
-    mean = h2[1] > 0 ? h2[0] / h2[1] : 0.0;
-    op_shift_open(c->g, p, -mean, c->s);
-    return ret;
+    red_sum_open(c->g, div, c->part, c->ks + KS_SUM, c->s);
+    op_poisson_rhs(c->g, div, c->ks + KS_SUM, c->pb, c->s);
+    pcg(c, c->pb, p, k, slot);
+    red_sum_open(c->g, p, c->part, c->ks + KS_SUM, c->s);
+    op_shift_open(c->g, p, c->ks + KS_SUM, c->s);
 }
 
-int mac_project(eb_ctx* c, double beta, double* f[3], double* phi, double rtol,
-                const SolveCfg& k, double* div_inf, int* iters) {
+// stop rule: max|r| <= rtol * max(max|b|, max_f |A_f w_f|/h)
+void mac_project(eb_ctx* c, double beta, double* f[3], double* phi, double rtol,
+                 const SolveCfg& k, int slot, bool want_div) {
     op_divergence(c->g, f, c->div, c->s);
-    op_face_flux_max(c->g, f, c->part, c->red, c->s);
-    double scale = 0;
-    int e = fetch(c, &scale, 1);
-    if (e) return e;
-    int it = 0;
-    int ret = poisson_solve(c, beta, c->div, phi, rtol, scale, k, &it);
-    if (iters) *iters = it;
-    if (ret != EB_OK && ret != EB_ENOCONV) return ret;
+    op_face_flux_max(c->g, f, c->part, c->ks + KS_SCALE, c->s);
+    ks_set(c->ks, KS_RTOL, rtol, c->s);
+    poisson_solve(c, beta, c->div, phi, k, slot);
     op_face_correct(c->g, beta, phi, f, c->s);
-    if (div_inf) {
+    if (want_div) {
         op_divergence(c->g, f, c->div, c->s);
-        *div_inf = maxabs1(c, c->N, c->div, &e);
-        if (e) return e;
+        red_maxabs(c->N, 1, c->div, c->part, c->divs + slot, c->s);
     }
-    return ret;
 }
 
-int cc_project(eb_ctx* c, double beta, double* u, double* p, double rtol, const SolveCfg& k,
-               double* div_inf, int* iters) {
+void cc_project(eb_ctx* c, double beta, double* u, double* p, double rtol, const SolveCfg& k,
+                int slot, bool want_div) {
     op_gcc(c->g, p, c->gp, c->s);
     op_axpy_open(c->g, beta, c->gp, u, 3, c->s);
     op_cell_to_face(c->g, u, c->f, c->s);
-    int ret = mac_project(c, beta, c->f, p, rtol, k, div_inf, iters);
-    if (ret != EB_OK && ret != EB_ENOCONV) return ret;
+    mac_project(c, beta, c->f, p, rtol, k, slot, want_div);
     op_gcc(c->g, p, c->gp, c->s);
     op_axpy_open(c->g, -beta, c->gp, u, 3, c->s);
-    return ret;
 }
 
-// BiCGSTAB on the three-component system, right-preconditioned by the viscous V-cycle
-int visc_solve(eb_ctx* c, double rho, double dt, const double* eta, const double* eta_eb,
-               const double* psi, double* x, double rtol, const SolveCfg& k, int* iters) {
+// BiCGSTAB on the three-component system, right-preconditioned by the viscous V-cycle; the
+// slot's count holds half-iterations (= V-cycles)
+void visc_solve(eb_ctx* c, double rho, double dt, const double* eta, const double* eta_eb,
+                const double* psi, double* x, double rtol, const SolveCfg& k, int slot) {
     long N3 = 3 * c->N;
     double *r = c->kv[0], *rh = c->kv[1], *p = c->kv[2], *v = c->kv[3], *ph = c->kv[4],
            *sv = c->kv[5], *sh = c->kv[6], *t = c->kv[7], *b = c->kv[8], *a0 = c->kv[9];
+    double* ks = c->ks;
+    int* st = c->kst + 2 * slot;
     mg_build_visc(c->lev, c->nlev, c->g, rho, dt, eta, eta_eb, k.mixed, c->s);
     c->built_sys = EB_SYS_VISC;
     c->built_mixed = k.mixed;
-    int e = EB_OK;
-    *iters = 0;
     // effective right-hand side: alpha psi minus the boundary part A(0)
     vec_fill(N3, 0.0, t, c->s);
     op_visc_apply(c->g, rho, dt, eta, eta_eb, t, a0, 0, c->s);
     vec_mask_rhs(c->g, psi, a0, b, c->s);
-    double bn = maxabs1(c, N3, b, &e);
-    if (e) return e;
-    double tol = rtol * bn;
-    // r = alpha psi - A(x) = b - A_lin(x)
+    red_maxabs(N3, 1, b, c->part, ks + KS_BN, c->s);
+    ks_set(ks, KS_SCALE, 0.0, c->s);
+    ks_set(ks, KS_RTOL, rtol, c->s);
+    // r = b - A_lin(x)
     op_visc_apply(c->g, rho, dt, eta, eta_eb, x, t, 1, c->s);
     vec_sub_scaled(N3, b, 1.0, t, r, c->s);
-    double rn = maxabs1(c, N3, r, &e);
-    if (e) return e;
-    if (bn == 0.0 || rn <= tol) return EB_OK;
+    red_maxabs(N3, 1, r, c->part, ks + KS_RN, c->s);
+    ks_op(KS_INIT, ks, st, 0, c->s);
     vec_copy(N3, r, rh, c->s);
     vec_fill(N3, 0.0, p, c->s);
     vec_fill(N3, 0.0, v, c->s);
-    double rho_old = 1.0, al = 1.0, om = 1.0;
-    double rr = dot1(c, N3, rh, r, &e);
-    if (e) return e;
+    const double* A1[4] = {rh, nullptr, nullptr, nullptr};
+    const double* B1[4] = {r, nullptr, nullptr, nullptr};
+    red_dots(N3, 1, A1, B1, c->part, ks + KS_RR, c->s, st);
     for (int it = 1; it <= k.max_iter; it++) {
-        double be = (rr / rho_old) * (al / om);
-        vec_bicg_p(N3, r, be, om, v, p, c->s);
-        vcyc(c, 3, k, p, ph);
-        op_visc_apply(c->g, rho, dt, eta, eta_eb, ph, v, 1, c->s);
-        double rv = dot1(c, N3, rh, v, &e);
-        if (e) return e;
-        al = rr / rv;
-        vec_sub_scaled(N3, r, al, v, sv, c->s);
-        *iters = it;
-        double sn = maxabs1(c, N3, sv, &e);
-        if (e) return e;
-        if (!finite(sn)) return set_err(EB_ENAN, "non-finite residual in the viscous solve");
-        if (sn <= tol) {
-            vec_axpby(N3, al, ph, 1.0, x, c->s);
-            return EB_OK;
-        }
-        vcyc(c, 3, k, sv, sh);
-        op_visc_apply(c->g, rho, dt, eta, eta_eb, sh, t, 1, c->s);
+        ks_op(KS_BI_BETA, ks, st, it, c->s);
+        ks_bi_p(N3, p, r, v, ks, st, c->s);
+        vcyc(c, 3, k, p, ph, st);
+        op_visc_apply(c->g, rho, dt, eta, eta_eb, ph, v, 1, c->s, st);
+        const double* Av[4] = {rh, nullptr, nullptr, nullptr};
+        const double* Bv[4] = {v, nullptr, nullptr, nullptr};
+        red_dots(N3, 1, Av, Bv, c->part, ks + KS_RV, c->s, st);
+        ks_op(KS_BI_ALPHA, ks, st, it, c->s);
+        ks_bi_s(N3, sv, r, v, ks, st, c->s);
+        red_maxabs(N3, 1, sv, c->part, ks + KS_SN, c->s, st);
+        ks_op(KS_BI_CHECK_S, ks, st, it, c->s);
+        ks_bi_xs(N3, x, ph, ks, st, c->s);
+        ks_op(KS_BI_FINISH_S, ks, st, it, c->s);
+        vcyc(c, 3, k, sv, sh, st);
+        op_visc_apply(c->g, rho, dt, eta, eta_eb, sh, t, 1, c->s, st);
         const double* A2[4] = {t, t, nullptr, nullptr};
         const double* B2[4] = {sv, t, nullptr, nullptr};
-        red_dots(N3, 2, A2, B2, c->part, c->red, c->s);
-        double ts[2];
-        e = fetch(c, ts, 2);
-        if (e) return e;
-        om = ts[0] / ts[1];
-        vec_bicg_update(N3, al, ph, om, sh, sv, t, x, r, c->s);
-        // next rho and the residual norm in one read-back
-        const double* A1[4] = {rh, nullptr, nullptr, nullptr};
-        const double* B1[4] = {r, nullptr, nullptr, nullptr};
-        red_dots(N3, 1, A1, B1, c->part, c->red, c->s);
-        red_maxabs(N3, 1, r, c->part + 2048, c->red + 1, c->s);
-        double two[2];
-        e = fetch(c, two, 2);
-        if (e) return e;
-        rho_old = rr;
-        rr = two[0];
-        if (!finite(two[1])) return set_err(EB_ENAN, "non-finite residual in the viscous solve");
-        if (two[1] <= tol) return EB_OK;
+        red_dots(N3, 2, A2, B2, c->part, ks + KS_TS, c->s, st);
+        ks_op(KS_BI_OMEGA, ks, st, it, c->s);
+        ks_bi_xr(N3, x, r, ph, sh, sv, t, ks, st, c->s);
+        red_dots(N3, 1, A1, B1, c->part, ks + KS_RRN, c->s, st);
+        red_maxabs(N3, 1, r, c->part, ks + KS_RN, c->s, st);
+        ks_op(KS_BI_CHECK_R, ks, st, it, c->s);
+        if (poll_done(c, slot, it)) break;
     }
-    return set_err(EB_ENOCONV, "viscous solve: no convergence in %d iterations", k.max_iter);
 }
 
+// reads `n` solve slots (state, count) after the stream drains
+int read_slots(eb_ctx* c, int n, int* host) {
+    hipMemcpyAsync(host, c->kst, 2 * n * sizeof(int), hipMemcpyDeviceToHost, c->s);
+    hipError_t e = hipStreamSynchronize(c->s);
+    if (e != hipSuccess) return set_err(EB_EHIP, "sync: %s", hipGetErrorString(e));
+    return EB_OK;
+}
+
+// return code of one solve from its slot
+int slot_code(const int* sl, const char* what, int max_iter) {
+    if (sl[0] == 2) return EB_OK;
+    if (sl[0] == 3) return set_err(EB_ENAN, "%s: non-finite residual", what);
+    return set_err(EB_ENOCONV, "%s: no convergence in %d iterations", what, max_iter);
+}
+
+// DerivedQuantities; the MAC projection reports into `slot`
 int derived(eb_ctx* c, const eb_rheology& rh, const double* theta, const double* u,
             const eb_step_opts* o, double* C, double* eta, double* eta_eb, double* V,
-            int* iters) {
+            int slot) {
     SolveCfg k = cfg_of(o);
     double rtol = o && o->rtol_mac > 0 ? o->rtol_mac : 1e-12;
     op_face_extrap(c->g, u, c->f, c->s);
     vec_fill(c->N, 0.0, c->phi, c->s);
-    int ret = mac_project(c, 1.0, c->f, c->phi, rtol, k, nullptr, iters);
-    if (ret != EB_OK && ret != EB_ENOCONV) return ret;
+    mac_project(c, 1.0, c->f, c->phi, rtol, k, slot, false);
     op_conv_dc(c->g, u, c->f, c->DC, c->s);
     op_redistribute(c->g, c->DC, c->DH, c->rS, c->rdD, C, c->s);
     op_wall_grad(c->g, u, c->gw, c->s);
@@ -490,11 +481,8 @@ int derived(eb_ctx* c, const eb_rheology& rh, const double* theta, const double*
     op_eta_eb(c->g, rh, c->gw, theta, eta_eb, c->s);
     op_transpose_dc(c->g, u, c->G9, eta, eta_eb, c->gw, c->DC, c->s);
     op_redistribute(c->g, c->DC, c->DH, c->rS, c->rdD, V, c->s);
-    int h = hip_check("derived");
-    return h ? h : ret;
+    return hip_check("derived");
 }
-
-int worst(int a, int b) { return a != EB_OK ? a : b; }
 
 }  // namespace
 
@@ -572,11 +560,25 @@ int eb_geometry_build(const eb_box* box, const eb_body* body, void* ws, size_t w
         for (int q = 0; q < ncut; q++) c->nfallback += tmp[q];
         delete[] tmp;
     }
+    if (hipHostMalloc((void**)&c->pin, 4 * sizeof(int), hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev[1], hipEventDisableTiming) != hipSuccess) {
+        eb_ctx_destroy(c);
+        return set_err(EB_EHIP, "pinned polling buffer or events: %s",
+                       hipGetErrorString(hipGetLastError()));
+    }
+    hipMemsetAsync(c->kst, 0, 2 * NSLOT * sizeof(int), c->s);
     *out = c;
     return EB_OK;
 }
 
-void eb_ctx_destroy(eb_ctx* ctx) { delete ctx; }
+void eb_ctx_destroy(eb_ctx* ctx) {
+    if (!ctx) return;
+    if (ctx->pin) hipHostFree(ctx->pin);
+    for (int b = 0; b < 2; b++)
+        if (ctx->ev[b]) hipEventDestroy(ctx->ev[b]);
+    delete ctx;
+}
 
 int eb_ctx_info(const eb_ctx* c, int* ncut, int* nlevels, int* nfallback) {
     if (!c) return set_err(EB_EINVAL, "null context");
@@ -668,13 +670,13 @@ int eb_mg_vcycle(eb_ctx* c, int system, int precision, double beta, double rho, 
         mg_build_poisson(c->lev, c->nlev, c->g, beta, k.mixed, c->s);
         c->built_sys = EB_SYS_POISSON;
         c->built_mixed = k.mixed;
-        vcyc(c, 1, k, r, e);
+        vcyc(c, 1, k, r, e, nullptr);
     } else if (system == EB_SYS_VISC) {
         if (!eta || (!eta_eb && c->ncut > 0)) return set_err(EB_EINVAL, "null viscosity");
         mg_build_visc(c->lev, c->nlev, c->g, rho, dt, eta, eta_eb, k.mixed, c->s);
         c->built_sys = EB_SYS_VISC;
         c->built_mixed = k.mixed;
-        vcyc(c, 3, k, r, e);
+        vcyc(c, 3, k, r, e, nullptr);
     } else {
         return set_err(EB_EINVAL, "unknown system %d", system);
     }
@@ -688,7 +690,8 @@ int eb_mg_sweep(eb_ctx* c, int system, int precision, int colour, const void* b,
     if (c->built_sys != system || c->built_mixed != f32)
         return set_err(EB_EINVAL, "no operator for system %d precision %d is built", system,
                        precision);
-    if (f32 && c->nlev < 2) return set_err(EB_EINVAL, "single-level hierarchy is FP64 only");
+    if (f32 && mg_tail_level(c->lev, c->nlev) == 0)
+        return set_err(EB_EINVAL, "this hierarchy runs entirely in FP64");
     mg_sweep_level0(c->lev[0], system == EB_SYS_VISC ? 3 : 1, f32, b, x, colour & 1,
                     (hipStream_t)stream);
     return hip_check("eb_mg_sweep");
@@ -700,11 +703,14 @@ int eb_visc_solve(eb_ctx* c, double rho, double dt, const double* eta, const dou
     if (!c || !eta || !psi || !x || (!eta_eb && c->ncut > 0))
         return set_err(EB_EINVAL, "null argument");
     c->s = (hipStream_t)stream;
-    int it = 0;
-    int ret = visc_solve(c, rho, dt, eta, eta_eb, psi, x, rtol, cfg_of(opts), &it);
-    if (iters) *iters = it;
+    SolveCfg k = cfg_of(opts);
+    visc_solve(c, rho, dt, eta, eta_eb, psi, x, rtol, k, 0);
     int h = hip_check("eb_visc_solve");
-    return h ? h : ret;
+    if (h) return h;
+    int sl[2];
+    if ((h = read_slots(c, 1, sl))) return h;
+    if (iters) *iters = (sl[1] + 1) / 2;
+    return slot_code(sl, "viscous solve", k.max_iter);
 }
 
 int eb_mac_project(eb_ctx* c, double beta, double* fx, double* fy, double* fz, double* phi,
@@ -713,18 +719,30 @@ int eb_mac_project(eb_ctx* c, double beta, double* fx, double* fy, double* fz, d
     if (!c || !fx || !fy || !fz || !phi) return set_err(EB_EINVAL, "null argument");
     c->s = (hipStream_t)stream;
     double* f[3] = {fx, fy, fz};
-    int ret = mac_project(c, beta, f, phi, rtol, cfg_of(opts), div_inf, iters);
+    SolveCfg k = cfg_of(opts);
+    mac_project(c, beta, f, phi, rtol, k, 0, true);
     int h = hip_check("eb_mac_project");
-    return h ? h : ret;
+    if (h) return h;
+    int sl[2];
+    if ((h = read_slots(c, 1, sl))) return h;
+    if (iters) *iters = sl[1];
+    if (div_inf) hipMemcpy(div_inf, c->divs, sizeof(double), hipMemcpyDeviceToHost);
+    return slot_code(sl, "MAC projection", k.max_iter);
 }
 
 int eb_cc_project(eb_ctx* c, double beta, double* u, double* p, double rtol,
                   const eb_step_opts* opts, double* div_inf, int* iters, void* stream) {
     if (!c || !u || !p) return set_err(EB_EINVAL, "null argument");
     c->s = (hipStream_t)stream;
-    int ret = cc_project(c, beta, u, p, rtol, cfg_of(opts), div_inf, iters);
+    SolveCfg k = cfg_of(opts);
+    cc_project(c, beta, u, p, rtol, k, 0, true);
     int h = hip_check("eb_cc_project");
-    return h ? h : ret;
+    if (h) return h;
+    int sl[2];
+    if ((h = read_slots(c, 1, sl))) return h;
+    if (iters) *iters = sl[1];
+    if (div_inf) hipMemcpy(div_inf, c->divs, sizeof(double), hipMemcpyDeviceToHost);
+    return slot_code(sl, "projection", k.max_iter);
 }
 
 int eb_derived(eb_ctx* c, const eb_rheology* rheo, const double* theta, const double* u,
@@ -733,10 +751,12 @@ int eb_derived(eb_ctx* c, const eb_rheology* rheo, const double* theta, const do
     if (!c || !rheo || !u || !C || !eta || !V || (!eta_eb && c->ncut > 0))
         return set_err(EB_EINVAL, "null argument");
     c->s = (hipStream_t)stream;
-    int it = 0;
-    int ret = derived(c, *rheo, theta, u, opts, C, eta, eta_eb, V, &it);
-    if (iters) *iters = it;
-    return ret;
+    int h = derived(c, *rheo, theta, u, opts, C, eta, eta_eb, V, 0);
+    if (h) return h;
+    int sl[2];
+    if ((h = read_slots(c, 1, sl))) return h;
+    if (iters) *iters = sl[1];
+    return slot_code(sl, "MAC projection", cfg_of(opts).max_iter);
 }
 
 int eb_rk2_step(eb_ctx* c, const eb_rheology* rheo, const double* theta, double dt,
@@ -745,57 +765,57 @@ int eb_rk2_step(eb_ctx* c, const eb_rheology* rheo, const double* theta, double 
     if (!c || !rheo || !o || !u || !p) return set_err(EB_EINVAL, "null argument");
     if (!(rheo->rho > 0.0) || !(dt > 0.0)) return set_err(EB_EINVAL, "rho and dt must be > 0");
     c->s = (hipStream_t)stream;
-    c->vcycles = 0;
     SolveCfg k = cfg_of(o);
-    eb_step_stats st;
-    memset(&st, 0, sizeof(st));
     long N = c->N, N3 = 3 * N;
     double rho = rheo->rho, beta = dt / rho;
-    int status = EB_OK, ret, it;
+    int h;
+    // slots: 0/3 MAC projection, 1/4 viscous solve, 2/5 end-of-stage projection
     // predictor: derived quantities at u^m
-    ret = derived(c, *rheo, theta, u, o, c->C0, c->eta0, c->eb0, c->V0, &it);
-    st.it_mac[0] = it;
-    if (ret != EB_OK && ret != EB_ENOCONV) return ret;
-    status = worst(status, ret);
+    if ((h = derived(c, *rheo, theta, u, o, c->C0, c->eta0, c->eb0, c->V0, 0))) return h;
     op_gcc(c->g, p, c->gp, c->s);
     op_psi(c->g, rho, dt, u, c->C0, c->V0, c->gp, o->force, c->psi, c->s);
     vec_copy(N3, u, c->u1, c->s);
-    ret = visc_solve(c, rho, dt, c->eta0, c->eb0, c->psi, c->u1, o->rtol_visc, k, &it);
-    st.it_visc[0] = it;
-    if (ret != EB_OK && ret != EB_ENOCONV) return ret;
-    status = worst(status, ret);
+    visc_solve(c, rho, dt, c->eta0, c->eb0, c->psi, c->u1, o->rtol_visc, k, 1);
     vec_copy(N, p, c->p1, c->s);
-    ret = cc_project(c, beta, c->u1, c->p1, o->rtol_proj, k, &st.div_proj[0], &it);
-    st.it_proj[0] = it;
-    if (ret != EB_OK && ret != EB_ENOCONV) return ret;
-    status = worst(status, ret);
+    cc_project(c, beta, c->u1, c->p1, o->rtol_proj, k, 2, true);
     // corrector: derived quantities at u*, averaged with the predictor's
-    ret = derived(c, *rheo, theta, c->u1, o, c->C1, c->eta1, c->eb1, c->V1, &it);
-    st.it_mac[1] = it;
-    if (ret != EB_OK && ret != EB_ENOCONV) return ret;
-    status = worst(status, ret);
+    if ((h = derived(c, *rheo, theta, c->u1, o, c->C1, c->eta1, c->eb1, c->V1, 3))) return h;
     op_average(N3, c->C1, c->C0, c->s);
     op_average(N3, c->V1, c->V0, c->s);
     op_average(N, c->eta1, c->eta0, c->s);
     op_average(c->ncut, c->eb1, c->eb0, c->s);
     op_gcc(c->g, c->p1, c->gp, c->s);
     op_psi(c->g, rho, dt, u, c->C0, c->V0, c->gp, o->force, c->psi, c->s);
-    ret = visc_solve(c, rho, dt, c->eta0, c->eb0, c->psi, c->u1, o->rtol_visc, k, &it);
-    st.it_visc[1] = it;
-    if (ret != EB_OK && ret != EB_ENOCONV) return ret;
-    status = worst(status, ret);
-    ret = cc_project(c, beta, c->u1, c->p1, o->rtol_proj, k, &st.div_proj[1], &it);
-    st.it_proj[1] = it;
-    if (ret != EB_OK && ret != EB_ENOCONV) return ret;
-    status = worst(status, ret);
+    visc_solve(c, rho, dt, c->eta0, c->eb0, c->psi, c->u1, o->rtol_visc, k, 4);
+    cc_project(c, beta, c->u1, c->p1, o->rtol_proj, k, 5, true);
     vec_copy(N3, c->u1, u, c->s);
     vec_copy(N, c->p1, p, c->s);
     op_finalize_state(c->g, u, p, c->s);
-    st.vcycles = c->vcycles;
+    if ((h = hip_check("eb_rk2_step"))) return h;
+    // one read-back for the whole step
+    int sl[12];
+    double dv[6];
+    if ((h = read_slots(c, 6, sl))) return h;
+    hipMemcpy(dv, c->divs, 6 * sizeof(double), hipMemcpyDeviceToHost);
+    eb_step_stats st;
+    memset(&st, 0, sizeof(st));
+    int status = EB_OK;
+    const char* names[3] = {"MAC projection", "viscous solve", "projection"};
+    for (int q = 0; q < 6; q++) {
+        int cnt = sl[2 * q + 1];
+        int stage = q / 3, kind = q % 3;
+        if (kind == 0) st.it_mac[stage] = cnt;
+        if (kind == 1) st.it_visc[stage] = (cnt + 1) / 2;
+        if (kind == 2) {
+            st.it_proj[stage] = cnt;
+            st.div_proj[stage] = dv[q];
+        }
+        st.vcycles += cnt;
+        if (status == EB_OK && sl[2 * q] != 2) status = slot_code(&sl[2 * q], names[kind], k.max_iter);
+    }
     st.status = status;
     if (stats) *stats = st;
-    int h = hip_check("eb_rk2_step");
-    return h ? h : status;
+    return status;
 }
 
 int eb_drag(const eb_ctx* cc, const eb_rheology* rheo, const double* theta, const double* u,

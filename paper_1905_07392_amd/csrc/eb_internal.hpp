@@ -60,6 +60,7 @@ struct LevelV {
     const T* K[3];
     const T* D;
     const uint8_t* mask;
+    const int* gate;  // nullable: kernels return at once while *gate != 0
 };
 
 // ------------------------------------------------------------------------------------------
@@ -115,6 +116,7 @@ struct Level {
     float* Df;
     double *x, *b, *r;  // 3 components each
     float *xf, *bf, *rf;
+    const int* gate = nullptr;
     LevelV<double> v64() const {
         LevelV<double> v;
         v.grid = grid;
@@ -122,6 +124,7 @@ struct Level {
         for (int d = 0; d < 3; d++) v.K[d] = K[d];
         v.D = D;
         v.mask = mask;
+        v.gate = gate;
         return v;
     }
     LevelV<float> v32() const {
@@ -131,6 +134,7 @@ struct Level {
         for (int d = 0; d < 3; d++) v.K[d] = Kf[d];
         v.D = Df;
         v.mask = mask;
+        v.gate = gate;
         return v;
     }
 };
@@ -178,8 +182,32 @@ void op_average(long n, const double* a, double* b, hipStream_t s);  // b = (a+b
 void op_finalize_state(const GeomV& g, double* u, double* p, hipStream_t s);
 void op_drag_terms(const GeomV& g, const eb_rheology& r, const double* theta, const double* gw,
                    const double* p, const double* gp, double* terms, hipStream_t s);
-void op_poisson_rhs(const GeomV& g, const double* div, double mean, double* b, hipStream_t s);
-void op_shift_open(const GeomV& g, double* x, double shift, hipStream_t s);
+void op_poisson_rhs(const GeomV& g, const double* div, const double* sumcnt, double* b,
+                    hipStream_t s);
+void op_shift_open(const GeomV& g, double* x, const double* sumcnt, hipStream_t s);
+
+// device-resident Krylov scalars (slots of a double array) and scalar updates
+enum {
+    KS_RTOL, KS_BN, KS_SCALE, KS_TOL, KS_RN, KS_SN, KS_RHO_OLD, KS_AL, KS_OM, KS_BE, KS_RZ,
+    KS_RZN, KS_PQ, KS_RR, KS_RV, KS_TS, KS_TT, KS_SUM, KS_CNT, KS_RRN, KS_COUNT = 24
+};
+enum {
+    KS_INIT, KS_CG_ALPHA, KS_CHECK_R, KS_CG_BETA, KS_BI_BETA, KS_BI_ALPHA, KS_BI_CHECK_S,
+    KS_BI_FINISH_S, KS_BI_OMEGA, KS_BI_CHECK_R
+};
+void ks_op(int op, double* ks, int* st, int it, hipStream_t s);
+void ks_set(double* ks, int idx, double v, hipStream_t s);
+void ks_cg_xr(long n, double* x, double* r, const double* p, const double* q, const double* ks,
+              const int* st, hipStream_t s);
+void ks_cg_p(long n, double* p, const double* z, const double* ks, const int* st, hipStream_t s);
+void ks_bi_p(long n, double* p, const double* r, const double* v, const double* ks,
+             const int* st, hipStream_t s);
+void ks_bi_s(long n, double* sv, const double* r, const double* v, const double* ks,
+             const int* st, hipStream_t s);
+void ks_bi_xs(long n, double* x, const double* ph, const double* ks, const int* st,
+              hipStream_t s);
+void ks_bi_xr(long n, double* x, double* r, const double* ph, const double* sh, const double* sv,
+              const double* t, const double* ks, const int* st, hipStream_t s);
 
 // multigrid and Krylov
 void mg_build_poisson(Level* lev, int nlev, const GeomV& g, double beta, bool mixed,
@@ -187,20 +215,24 @@ void mg_build_poisson(Level* lev, int nlev, const GeomV& g, double beta, bool mi
 void mg_build_visc(Level* lev, int nlev, const GeomV& g, double rho, double dt,
                    const double* eta, const double* eta_eb, bool mixed, hipStream_t s);
 void mg_vcycle(Level* lev, int nlev, int ncomp, bool mixed, const double* b, double* x,
-               int nu1, int nu2, int nbottom, hipStream_t s);
-void mg_apply_level0(const Level& L, int ncomp, const double* x, double* y, hipStream_t s);
+               int nu1, int nu2, int nbottom, hipStream_t s, const int* gate = nullptr);
+void mg_apply_level0(const Level& L, int ncomp, const double* x, double* y, hipStream_t s,
+                     const int* gate = nullptr);
+// first multigrid level run by the one-work-group tail (FP32 copies exist only above it)
+int mg_tail_level(const Level* lev, int nlev);
 void mg_sweep_level0(const Level& L, int ncomp, bool f32, const void* b, void* x, int colour,
                      hipStream_t s);
 void op_visc_apply(const GeomV& g, double rho, double dt, const double* eta,
                    const double* eta_eb, const double* u, double* out, int homogeneous,
-                   hipStream_t s);
+                   hipStream_t s, const int* gate = nullptr);
 
 // reductions: per-block partials (part, >= 4*1024 doubles) then one fixed-order final pass
 // into out (device)
 int red_blocks(long n);
 void red_dots(long n, int npairs, const double* const a[4], const double* const b[4],
-              double* part, double* out, hipStream_t s);
-void red_maxabs(long n, int ncomp, const double* x, double* part, double* out, hipStream_t s);
+              double* part, double* out, hipStream_t s, const int* gate = nullptr);
+void red_maxabs(long n, int ncomp, const double* x, double* part, double* out, hipStream_t s,
+                const int* gate = nullptr);
 void red_sum_open(const GeomV& g, const double* x, double* part, double* out, hipStream_t s);
 void red_sum(long n, int nrow, const double* x, double* part, double* out, hipStream_t s);
 void op_face_flux_max(const GeomV& g, double* const f[3], double* part, double* out,

@@ -108,7 +108,8 @@ __global__ void k_to_float(long n, const double* __restrict__ a, float* __restri
 }
 
 template <typename A, typename B>
-__global__ void k_cast(long n, const A* __restrict__ a, B* __restrict__ b) {
+__global__ void k_cast(long n, const A* __restrict__ a, B* __restrict__ b, const int* gate) {
+    if (gate && *gate) return;
     long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (t < n) b[t] = (B)a[t];
 }
@@ -140,12 +141,12 @@ __device__ __forceinline__ void offdiag(const LevelV<T>& L, const T* __restrict_
     }
 }
 
+// one Gauss-Seidel update of the t-th cell of colour col (cells of a colour are numbered row by
+// row, nx/2 per row)
 template <typename T, int NC>
-__global__ void k_smooth(LevelV<T> L, const T* __restrict__ b, T* __restrict__ x, int col) {
+__device__ __forceinline__ void smooth_cell(const LevelV<T>& L, const T* __restrict__ b,
+                                            T* __restrict__ x, long t, int col) {
     const GridV& g = L.grid;
-    long half = L.N / 2;
-    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    if (t >= half) return;
     int nxh = g.n[0] / 2;
     long row = t / nxh;
     int ih = (int)(t - row * nxh);
@@ -164,12 +165,10 @@ __global__ void k_smooth(LevelV<T> L, const T* __restrict__ b, T* __restrict__ x
     for (int m = 0; m < NC; m++) x[m * L.N + c] = acc[m] / dg;
 }
 
-// r = b - M x (b may be null: r = -M x is not needed; apply handled separately)
+// r = b - M x at cell c (b null: r = M x)
 template <typename T, int NC>
-__global__ void k_resid(LevelV<T> L, const T* __restrict__ b, const T* __restrict__ x,
-                        T* __restrict__ r) {
-    long c = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    if (c >= L.N) return;
+__device__ __forceinline__ void resid_cell(const LevelV<T>& L, const T* __restrict__ b,
+                                           const T* __restrict__ x, T* __restrict__ r, long c) {
     if (!L.mask[c]) {
 #pragma unroll
         for (int m = 0; m < NC; m++) r[m * L.N + c] = (T)0;
@@ -189,14 +188,15 @@ __global__ void k_resid(LevelV<T> L, const T* __restrict__ b, const T* __restric
     }
 }
 
+// coarse right-hand side: mean of the eight children (rows are already alpha-weighted)
 template <typename TF, typename TC, int NC>
-__global__ void k_restrict(GridV gf, GridV gc, const uint8_t* __restrict__ mf,
-                           const uint8_t* __restrict__ mc, const TF* __restrict__ rf,
-                           TC* __restrict__ bc) {
+__device__ __forceinline__ void restrict_cell(const GridV& gf, const GridV& gc,
+                                              const uint8_t* __restrict__ mf,
+                                              const uint8_t* __restrict__ mc,
+                                              const TF* __restrict__ rf, TC* __restrict__ bc,
+                                              long c) {
     long Nc = (long)gc.n[0] * gc.n[1] * gc.n[2];
     long Nf = (long)gf.n[0] * gf.n[1] * gf.n[2];
-    long c = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    if (c >= Nc) return;
     int i, j, k;
     cell_coords(gc, c, i, j, k);
     TF s[NC];
@@ -212,13 +212,14 @@ __global__ void k_restrict(GridV gf, GridV gc, const uint8_t* __restrict__ mf,
     for (int m = 0; m < NC; m++) bc[m * Nc + c] = mc[c] ? (TC)(s[m] / (TF)8) : (TC)0;
 }
 
+// piecewise-constant prolongation of the coarse correction to open children
 template <typename TC, typename TF, int NC>
-__global__ void k_prolong(GridV gf, GridV gc, const uint8_t* __restrict__ mf,
-                          const TC* __restrict__ ec, TF* __restrict__ xf) {
+__device__ __forceinline__ void prolong_cell(const GridV& gf, const GridV& gc,
+                                             const uint8_t* __restrict__ mf,
+                                             const TC* __restrict__ ec, TF* __restrict__ xf,
+                                             long f) {
     long Nc = (long)gc.n[0] * gc.n[1] * gc.n[2];
     long Nf = (long)gf.n[0] * gf.n[1] * gf.n[2];
-    long f = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    if (f >= Nf) return;
     if (!mf[f]) return;
     int i, j, k;
     cell_coords(gf, f, i, j, k);
@@ -227,12 +228,212 @@ __global__ void k_prolong(GridV gf, GridV gc, const uint8_t* __restrict__ mf,
     for (int m = 0; m < NC; m++) xf[m * Nf + f] += (TF)ec[m * Nc + c];
 }
 
+template <typename T, int NC>
+__global__ void k_smooth(LevelV<T> L, const T* __restrict__ b, T* __restrict__ x, int col) {
+    if (L.gate && *L.gate) return;
+    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t < L.N / 2) smooth_cell<T, NC>(L, b, x, t, col);
+}
+
+template <typename T, int NC>
+__global__ void k_resid(LevelV<T> L, const T* __restrict__ b, const T* __restrict__ x,
+                        T* __restrict__ r) {
+    if (L.gate && *L.gate) return;
+    long c = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (c < L.N) resid_cell<T, NC>(L, b, x, r, c);
+}
+
+template <typename TF, typename TC, int NC>
+__global__ void k_restrict(GridV gf, GridV gc, const uint8_t* __restrict__ mf,
+                           const uint8_t* __restrict__ mc, const TF* __restrict__ rf,
+                           TC* __restrict__ bc, const int* gate) {
+    if (gate && *gate) return;
+    long Nc = (long)gc.n[0] * gc.n[1] * gc.n[2];
+    long c = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (c < Nc) restrict_cell<TF, TC, NC>(gf, gc, mf, mc, rf, bc, c);
+}
+
+template <typename TC, typename TF, int NC>
+__global__ void k_prolong(GridV gf, GridV gc, const uint8_t* __restrict__ mf,
+                          const TC* __restrict__ ec, TF* __restrict__ xf, const int* gate) {
+    if (gate && *gate) return;
+    long Nf = (long)gf.n[0] * gf.n[1] * gf.n[2];
+    long f = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (f < Nf) prolong_cell<TC, TF, NC>(gf, gc, mf, ec, xf, f);
+}
+
+// ------------------------------------------------------------------------------------------
+// the small coarse levels of a V-cycle, all in one work-group (one launch instead of ~100):
+// the same operations in the same order as the per-level kernels, separated by barriers.  The
+// operators, right-hand sides and iterates of these levels are staged in LDS, so each of the
+// ~100 barrier-separated phases costs LDS latency instead of a global-memory round trip.
+// ------------------------------------------------------------------------------------------
+constexpr int TAIL_MAXL = 8;
+constexpr int TAIL_THREADS = 1024;
+constexpr size_t TAIL_LDS_BYTES = 65536;
+
+struct TailArgs {
+    int nl, nu1, nu2, nbottom;
+    LevelV<double> L[TAIL_MAXL];
+    double* x0;        // iterate of the first tail level (global, written back)
+    const int* gate;
+    const double* b0;  // right-hand side of the first tail level (global)
+    // LDS byte offsets per level: x, b, K[3], D, mask
+    unsigned ox[TAIL_MAXL], ob[TAIL_MAXL], oK[TAIL_MAXL][3], oD[TAIL_MAXL], om[TAIL_MAXL];
+};
+
+// residual b - M x at fine cell f (0 outside the open cells)
+template <int NC>
+__device__ __forceinline__ void resid_value(const LevelV<double>& L, const double* b,
+                                            const double* x, long f, double r[NC]) {
+    if (!L.mask[f]) {
+#pragma unroll
+        for (int m = 0; m < NC; m++) r[m] = 0.0;
+        return;
+    }
+    int i, j, k;
+    cell_coords(L.grid, f, i, j, k);
+    double acc[NC];
+#pragma unroll
+    for (int m = 0; m < NC; m++) acc[m] = 0.0;
+    offdiag<double, NC>(L, x, i, j, k, acc);
+#pragma unroll
+    for (int m = 0; m < NC; m++) r[m] = b[m * L.N + f] - (L.D[f] * x[m * L.N + f] - acc[m]);
+}
+
+template <int NC>
+__device__ void tail_sweep(const LevelV<double>& L, const double* b, double* x, int col) {
+    for (long t = threadIdx.x; t < L.N / 2; t += blockDim.x) smooth_cell<double, NC>(L, b, x, t, col);
+    __syncthreads();
+}
+
+template <int NC>
+__global__ void __launch_bounds__(TAIL_THREADS) k_vcycle_tail(TailArgs A) {
+    if (A.gate && *A.gate) return;
+    extern __shared__ double lds_d[];
+    char* lds = reinterpret_cast<char*>(lds_d);
+    int nl = A.nl;
+    // stage the operators and the first right-hand side in LDS
+    for (int l = 0; l < nl; l++) {
+        const LevelV<double>& G = A.L[l];
+        for (int d = 0; d < 3; d++) {
+            long nf = face_count(G.grid, d);
+            double* dst = reinterpret_cast<double*>(lds + A.oK[l][d]);
+            for (long t = threadIdx.x; t < nf; t += blockDim.x) dst[t] = G.K[d][t];
+        }
+        double* Dd = reinterpret_cast<double*>(lds + A.oD[l]);
+        uint8_t* md = reinterpret_cast<uint8_t*>(lds + A.om[l]);
+        for (long t = threadIdx.x; t < G.N; t += blockDim.x) {
+            Dd[t] = G.D[t];
+            md[t] = G.mask[t];
+        }
+    }
+    {
+        double* bd = reinterpret_cast<double*>(lds + A.ob[0]);
+        for (long t = threadIdx.x; t < NC * A.L[0].N; t += blockDim.x) bd[t] = A.b0[t];
+    }
+    __syncthreads();
+    auto lv = [&](int l) {
+        LevelV<double> v = A.L[l];
+        for (int d = 0; d < 3; d++) v.K[d] = reinterpret_cast<const double*>(lds + A.oK[l][d]);
+        v.D = reinterpret_cast<const double*>(lds + A.oD[l]);
+        v.mask = reinterpret_cast<const uint8_t*>(lds + A.om[l]);
+        return v;
+    };
+    auto X = [&](int l) { return reinterpret_cast<double*>(lds + A.ox[l]); };
+    auto B = [&](int l) { return reinterpret_cast<double*>(lds + A.ob[l]); };
+    for (int l = 0; l < nl; l++) {
+        LevelV<double> L = lv(l);
+        double* x = X(l);
+        double* b = B(l);
+        for (long t = threadIdx.x; t < NC * L.N; t += blockDim.x) x[t] = 0.0;
+        __syncthreads();
+        if (l == nl - 1) {
+            for (int s = 0; s < A.nbottom; s++) {
+                tail_sweep<NC>(L, b, x, 0);
+                tail_sweep<NC>(L, b, x, 1);
+            }
+            for (int s = 0; s < A.nbottom; s++) {
+                tail_sweep<NC>(L, b, x, 1);
+                tail_sweep<NC>(L, b, x, 0);
+            }
+            break;
+        }
+        for (int s = 0; s < A.nu1; s++) {
+            tail_sweep<NC>(L, b, x, 0);
+            tail_sweep<NC>(L, b, x, 1);
+        }
+        // residual and restriction fused: the coarse right-hand side is the mean of the eight
+        // children's residuals
+        LevelV<double> C = lv(l + 1);
+        double* bc = B(l + 1);
+        for (long c = threadIdx.x; c < C.N; c += blockDim.x) {
+            int i, j, k;
+            cell_coords(C.grid, c, i, j, k);
+            double s[NC];
+#pragma unroll
+            for (int m = 0; m < NC; m++) s[m] = 0.0;
+            for (int q = 0; q < 8; q++) {
+                long f = cell_index(L.grid, 2 * i + (q & 1), 2 * j + ((q >> 1) & 1), 2 * k + (q >> 2));
+                double r[NC];
+                resid_value<NC>(L, b, x, f, r);
+#pragma unroll
+                for (int m = 0; m < NC; m++) s[m] += r[m];
+            }
+#pragma unroll
+            for (int m = 0; m < NC; m++) bc[m * C.N + c] = C.mask[c] ? s[m] / 8.0 : 0.0;
+        }
+        __syncthreads();
+    }
+    for (int l = nl - 2; l >= 0; l--) {
+        LevelV<double> L = lv(l);
+        LevelV<double> C = lv(l + 1);
+        double* x = X(l);
+        for (long f = threadIdx.x; f < L.N; f += blockDim.x)
+            prolong_cell<double, double, NC>(L.grid, C.grid, L.mask, X(l + 1), x, f);
+        __syncthreads();
+        for (int s = 0; s < A.nu2; s++) {
+            tail_sweep<NC>(L, B(l), x, 1);
+            tail_sweep<NC>(L, B(l), x, 0);
+        }
+    }
+    double* x0 = X(0);
+    for (long t = threadIdx.x; t < NC * A.L[0].N; t += blockDim.x) A.x0[t] = x0[t];
+}
+
+// LDS bytes for levels [t, nlev) with nc components; fills the offsets when A is given
+size_t tail_layout(const Level* lev, int nlev, int t, int nc, TailArgs* A) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = (off + bytes + 15) & ~size_t(15);
+        return (unsigned)o;
+    };
+    for (int l = t; l < nlev; l++) {
+        const Level& L = lev[l];
+        int q = l - t;
+        unsigned ox = take(nc * L.N * 8), ob = take(nc * L.N * 8);
+        unsigned oK[3];
+        for (int d = 0; d < 3; d++) oK[d] = take(face_count(L.grid, d) * 8);
+        unsigned oD = take(L.N * 8), om = take(L.N);
+        if (A) {
+            A->ox[q] = ox;
+            A->ob[q] = ob;
+            for (int d = 0; d < 3; d++) A->oK[q][d] = oK[d];
+            A->oD[q] = oD;
+            A->om[q] = om;
+        }
+    }
+    return off;
+}
+
 // ------------------------------------------------------------------------------------------
 // exact EB viscous Helmholtz operator (Eq. implicit-viscous with the wall flux of Eq. dudn)
 // ------------------------------------------------------------------------------------------
 __global__ void k_visc_apply(GeomV g, double rho, double dt, const double* __restrict__ eta,
                              const double* __restrict__ eta_eb, const double* __restrict__ u,
-                             double* __restrict__ out, int homog) {
+                             double* __restrict__ out, int homog, const int* gate) {
+    if (gate && *gate) return;
     long N = g.N;
     long c = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (c >= N) return;
@@ -322,7 +523,8 @@ struct DotArgs {
     const double* b[4];
 };
 
-__global__ void k_dots(long n, int np, DotArgs args, double* __restrict__ part) {
+__global__ void k_dots(long n, int np, DotArgs args, double* __restrict__ part, const int* gate) {
+    if (gate && *gate) return;
     __shared__ double sh[EB_BLOCK];
     double s[4] = {0.0, 0.0, 0.0, 0.0};
     for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n;
@@ -336,7 +538,8 @@ __global__ void k_dots(long n, int np, DotArgs args, double* __restrict__ part) 
 
 // per-component max |x| of a [ncomp][n] array
 __global__ void k_maxabs(long n, int ncomp, const double* __restrict__ x,
-                         double* __restrict__ part) {
+                         double* __restrict__ part, const int* gate) {
+    if (gate && *gate) return;
     __shared__ double sh[EB_BLOCK];
     for (int m = 0; m < ncomp; m++) {
         double v = 0.0;
@@ -397,7 +600,8 @@ __global__ void k_face_flux_max(GeomV g, const double* __restrict__ fx,
 
 // out[p] = reduction over nb partials of row p (mode 0 sum, 1 max), fixed order
 __global__ void k_final(const double* __restrict__ part, int nb, int nrow, int mode,
-                        double* __restrict__ out) {
+                        double* __restrict__ out, const int* gate) {
+    if (gate && *gate) return;
     __shared__ double sh[EB_BLOCK];
     for (int p = 0; p < nrow; p++) {
         double v = 0.0;
@@ -420,7 +624,8 @@ __global__ void k_fill(long n, double v, double* __restrict__ y) {
     if (t < n) y[t] = v;
 }
 template <typename T>
-__global__ void k_zero(long n, T* __restrict__ y) {
+__global__ void k_zero(long n, T* __restrict__ y, const int* gate = nullptr) {
+    if (gate && *gate) return;
     long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (t < n) y[t] = (T)0;
 }
@@ -497,17 +702,27 @@ template <typename TF, typename TC>
 void restrict_pass(const Level& F, const Level& C, int nc, const TF* rf, TC* bc, hipStream_t s) {
     if (nc == 3)
         k_restrict<TF, TC, 3><<<grid_for(C.N), EB_BLOCK, 0, s>>>(F.grid, C.grid, F.mask, C.mask,
-                                                                rf, bc);
+                                                                rf, bc, F.gate);
     else
         k_restrict<TF, TC, 1><<<grid_for(C.N), EB_BLOCK, 0, s>>>(F.grid, C.grid, F.mask, C.mask,
-                                                                rf, bc);
+                                                                rf, bc, F.gate);
 }
 template <typename TC, typename TF>
 void prolong_pass(const Level& F, const Level& C, int nc, const TC* ec, TF* xf, hipStream_t s) {
     if (nc == 3)
-        k_prolong<TC, TF, 3><<<grid_for(F.N), EB_BLOCK, 0, s>>>(F.grid, C.grid, F.mask, ec, xf);
+        k_prolong<TC, TF, 3><<<grid_for(F.N), EB_BLOCK, 0, s>>>(F.grid, C.grid, F.mask, ec, xf, F.gate);
     else
-        k_prolong<TC, TF, 1><<<grid_for(F.N), EB_BLOCK, 0, s>>>(F.grid, C.grid, F.mask, ec, xf);
+        k_prolong<TC, TF, 1><<<grid_for(F.N), EB_BLOCK, 0, s>>>(F.grid, C.grid, F.mask, ec, xf, F.gate);
+}
+
+// first level handled by the one-work-group tail: the largest set of coarsest levels whose
+// viscous (three-component) data fit in the LDS budget
+int tail_level(const Level* lev, int nlev) {
+    int t = nlev - 1;
+    while (t > 0 && nlev - (t - 1) <= TAIL_MAXL &&
+           tail_layout(lev, nlev, t - 1, 3, nullptr) <= TAIL_LDS_BYTES)
+        t--;
+    return t;
 }
 
 struct VArgs {
@@ -515,9 +730,27 @@ struct VArgs {
     int nlev, nc, nu1, nu2, nbottom;
     bool mixed;
     hipStream_t s;
+    int tail;
+    bool tail_fits;  // the tail levels fit the LDS budget (else per-level kernels)
 };
 
-bool level_f32(const VArgs& a, int l) { return a.mixed && l < a.nlev - 1; }
+// levels above the tail run in FP32 in mixed mode; the tail (and so the coarsest solve) is FP64
+bool level_f32(const VArgs& a, int l) { return a.mixed && l < a.tail; }
+
+void launch_tail(const VArgs& a) {
+    TailArgs T;
+    T.nl = a.nlev - a.tail;
+    T.nu1 = a.nu1;
+    T.nu2 = a.nu2;
+    T.nbottom = a.nbottom;
+    for (int q = 0; q < T.nl; q++) T.L[q] = a.lev[a.tail + q].v64();
+    T.x0 = a.lev[a.tail].x;
+    T.gate = a.lev[a.tail].gate;
+    T.b0 = a.lev[a.tail].b;
+    size_t bytes = tail_layout(a.lev, a.nlev, a.tail, a.nc, &T);
+    if (a.nc == 3) k_vcycle_tail<3><<<1, TAIL_THREADS, bytes, a.s>>>(T);
+    else k_vcycle_tail<1><<<1, TAIL_THREADS, bytes, a.s>>>(T);
+}
 
 template <typename T>
 T* xl(Level& L);
@@ -545,7 +778,7 @@ void vcycle_level(const VArgs& a, int l) {
     Level& L = a.lev[l];
     T* x = xl<T>(L);
     T* b = bl<T>(L);
-    k_zero<T><<<grid_for(a.nc * L.N), EB_BLOCK, 0, a.s>>>(a.nc * L.N, x);
+    k_zero<T><<<grid_for(a.nc * L.N), EB_BLOCK, 0, a.s>>>(a.nc * L.N, x, L.gate);
     if (l == a.nlev - 1) {
         for (int t = 0; t < a.nbottom; t++) {
             smooth_pass<T>(L, a.nc, b, x, 0, a.s);
@@ -576,11 +809,13 @@ void vcycle_level(const VArgs& a, int l) {
 }
 
 void vcycle_rec(const VArgs& a, int l) {
-    if (level_f32(a, l)) vcycle_level<float>(a, l);
+    if (l == a.tail && a.tail_fits) launch_tail(a);
+    else if (level_f32(a, l)) vcycle_level<float>(a, l);
     else vcycle_level<double>(a, l);
 }
 
 void finish_operator(Level* lev, int nlev, bool mixed, hipStream_t s) {
+    int tail = tail_level(lev, nlev);
     for (int l = 1; l < nlev; l++) {
         for (int d = 0; d < 3; d++)
             level_coarsen_faces(lev[l].grid, lev[l - 1].grid, d, lev[l - 1].K[d], lev[l].K[d],
@@ -591,7 +826,7 @@ void finish_operator(Level* lev, int nlev, bool mixed, hipStream_t s) {
         Level& L = lev[l];
         k_diag<<<grid_for(L.N), EB_BLOCK, 0, s>>>(L.grid, L.K[0], L.K[1], L.K[2], L.S, L.mask,
                                                   L.D);
-        if (mixed && l < nlev - 1) {
+        if (mixed && l < tail) {
             for (int d = 0; d < 3; d++) {
                 long nf = face_count(L.grid, d);
                 k_to_float<<<grid_for(nf), EB_BLOCK, 0, s>>>(nf, L.K[d], L.Kf[d]);
@@ -620,17 +855,20 @@ void mg_build_visc(Level* lev, int nlev, const GeomV& g, double rho, double dt,
 }
 
 void mg_vcycle(Level* lev, int nlev, int ncomp, bool mixed, const double* b, double* x, int nu1,
-               int nu2, int nbottom, hipStream_t s) {
-    VArgs a{lev, nlev, ncomp, nu1, nu2, nbottom, mixed, s};
+               int nu2, int nbottom, hipStream_t s, const int* gate) {
+    for (int l = 0; l < nlev; l++) lev[l].gate = gate;
+    int tl = tail_level(lev, nlev);
+    VArgs a{lev, nlev, ncomp, nu1, nu2, nbottom, mixed, s, tl,
+            tail_layout(lev, nlev, tl, ncomp, nullptr) <= TAIL_LDS_BYTES};
     Level& L0 = lev[0];
     long n = (long)ncomp * L0.N;
     // level 0 works on the caller's arrays in FP64 mode; in mixed mode on FP32 copies
     double* keep_b = L0.b;
     double* keep_x = L0.x;
     if (level_f32(a, 0)) {
-        k_cast<double, float><<<grid_for(n), EB_BLOCK, 0, s>>>(n, b, L0.bf);
+        k_cast<double, float><<<grid_for(n), EB_BLOCK, 0, s>>>(n, b, L0.bf, gate);
         vcycle_rec(a, 0);
-        k_cast<float, double><<<grid_for(n), EB_BLOCK, 0, s>>>(n, L0.xf, x);
+        k_cast<float, double><<<grid_for(n), EB_BLOCK, 0, s>>>(n, L0.xf, x, gate);
     } else {
         L0.b = const_cast<double*>(b);
         L0.x = x;
@@ -638,6 +876,7 @@ void mg_vcycle(Level* lev, int nlev, int ncomp, bool mixed, const double* b, dou
         L0.b = keep_b;
         L0.x = keep_x;
     }
+    for (int l = 0; l < nlev; l++) lev[l].gate = nullptr;
 }
 
 void mg_sweep_level0(const Level& L, int ncomp, bool f32, const void* b, void* x, int colour,
@@ -648,14 +887,18 @@ void mg_sweep_level0(const Level& L, int ncomp, bool f32, const void* b, void* x
         smooth_pass<double>(L, ncomp, (const double*)b, (double*)x, colour, s);
 }
 
-void mg_apply_level0(const Level& L, int ncomp, const double* x, double* y, hipStream_t s) {
-    resid_pass<double>(L, ncomp, nullptr, x, y, s);
+void mg_apply_level0(const Level& L, int ncomp, const double* x, double* y, hipStream_t s,
+                     const int* gate) {
+    Level G = L;
+    G.gate = gate;
+    resid_pass<double>(G, ncomp, nullptr, x, y, s);
 }
 
 void op_visc_apply(const GeomV& g, double rho, double dt, const double* eta,
                    const double* eta_eb, const double* u, double* out, int homogeneous,
-                   hipStream_t s) {
-    k_visc_apply<<<grid_for(g.N), EB_BLOCK, 0, s>>>(g, rho, dt, eta, eta_eb, u, out, homogeneous);
+                   hipStream_t s, const int* gate) {
+    k_visc_apply<<<grid_for(g.N), EB_BLOCK, 0, s>>>(g, rho, dt, eta, eta_eb, u, out, homogeneous,
+                                                    gate);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -668,33 +911,34 @@ int red_blocks(long n) {
 }
 
 void red_dots(long n, int np, const double* const a[4], const double* const b[4], double* part,
-              double* out, hipStream_t s) {
+              double* out, hipStream_t s, const int* gate) {
     DotArgs args;
     for (int p = 0; p < 4; p++) {
         args.a[p] = p < np ? a[p] : nullptr;
         args.b[p] = p < np ? b[p] : nullptr;
     }
     int nb = red_blocks(n);
-    k_dots<<<nb, EB_BLOCK, 0, s>>>(n, np, args, part);
-    k_final<<<1, EB_BLOCK, 0, s>>>(part, nb, np, 0, out);
+    k_dots<<<nb, EB_BLOCK, 0, s>>>(n, np, args, part, gate);
+    k_final<<<1, EB_BLOCK, 0, s>>>(part, nb, np, 0, out, gate);
 }
 
-void red_maxabs(long n, int ncomp, const double* x, double* part, double* out, hipStream_t s) {
+void red_maxabs(long n, int ncomp, const double* x, double* part, double* out, hipStream_t s,
+                const int* gate) {
     int nb = red_blocks(n);
-    k_maxabs<<<nb, EB_BLOCK, 0, s>>>(n, ncomp, x, part);
-    k_final<<<1, EB_BLOCK, 0, s>>>(part, nb, ncomp, 1, out);
+    k_maxabs<<<nb, EB_BLOCK, 0, s>>>(n, ncomp, x, part, gate);
+    k_final<<<1, EB_BLOCK, 0, s>>>(part, nb, ncomp, 1, out, gate);
 }
 
 void red_sum_open(const GeomV& g, const double* x, double* part, double* out, hipStream_t s) {
     int nb = red_blocks(g.N);
     k_sum_open<<<nb, EB_BLOCK, 0, s>>>(g, x, part);
-    k_final<<<1, EB_BLOCK, 0, s>>>(part, nb, 2, 0, out);
+    k_final<<<1, EB_BLOCK, 0, s>>>(part, nb, 2, 0, out, nullptr);
 }
 
 void red_sum(long n, int nrow, const double* x, double* part, double* out, hipStream_t s) {
     int nb = red_blocks(n);
     k_rowsum<<<nb, EB_BLOCK, 0, s>>>(n, nrow, x, part);
-    k_final<<<1, EB_BLOCK, 0, s>>>(part, nb, nrow, 0, out);
+    k_final<<<1, EB_BLOCK, 0, s>>>(part, nb, nrow, 0, out, nullptr);
 }
 
 void op_face_flux_max(const GeomV& g, double* const f[3], double* part, double* out,
@@ -702,7 +946,7 @@ void op_face_flux_max(const GeomV& g, double* const f[3], double* part, double* 
     long n = face_count(g.grid, 0);
     int nb = red_blocks(n);
     k_face_flux_max<<<nb, EB_BLOCK, 0, s>>>(g, f[0], f[1], f[2], part);
-    k_final<<<1, EB_BLOCK, 0, s>>>(part, nb, 1, 1, out);
+    k_final<<<1, EB_BLOCK, 0, s>>>(part, nb, 1, 1, out, nullptr);
 }
 
 void vec_copy(long n, const double* x, double* y, hipStream_t s) {
@@ -730,3 +974,5 @@ void vec_mask_rhs(const GeomV& g, const double* psi, const double* a0, double* b
                   hipStream_t s) {
     k_mask_rhs<<<grid_for(3 * g.N), EB_BLOCK, 0, s>>>(g, psi, a0, b);
 }
+
+int mg_tail_level(const Level* lev, int nlev) { return tail_level(lev, nlev); }

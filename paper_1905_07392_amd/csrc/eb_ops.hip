@@ -511,17 +511,21 @@ __global__ void k_drag_terms(GeomV g, eb_rheology rh, const double* __restrict__
     }
 }
 
-__global__ void k_poisson_rhs(GeomV g, const double* __restrict__ div, double mean,
-                              double* __restrict__ b) {
+// b = -(div - mean) on open cells; mean = sumcnt[0]/sumcnt[1] computed on the device
+__global__ void k_poisson_rhs(GeomV g, const double* __restrict__ div,
+                              const double* __restrict__ sumcnt, double* __restrict__ b) {
     long c = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (c >= g.N) return;
+    double mean = sumcnt[1] > 0.0 ? sumcnt[0] / sumcnt[1] : 0.0;
     b[c] = g.alpha[c] > 0.0 ? -(div[c] - mean) : 0.0;
 }
 
-__global__ void k_shift_open(GeomV g, double* __restrict__ x, double shift) {
+// x -= mean on open cells (0 elsewhere)
+__global__ void k_shift_open(GeomV g, double* __restrict__ x, const double* __restrict__ sumcnt) {
     long c = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (c >= g.N) return;
-    x[c] = g.alpha[c] > 0.0 ? x[c] + shift : 0.0;
+    double mean = sumcnt[1] > 0.0 ? sumcnt[0] / sumcnt[1] : 0.0;
+    x[c] = g.alpha[c] > 0.0 ? x[c] - mean : 0.0;
 }
 
 }  // namespace
@@ -587,9 +591,10 @@ void op_drag_terms(const GeomV& g, const eb_rheology& r, const double* theta, co
     if (g.ncut > 0)
         k_drag_terms<<<grid_for(g.ncut), EB_BLOCK, 0, s>>>(g, r, theta, gw, p, gp, terms);
 }
-void op_poisson_rhs(const GeomV& g, const double* div, double mean, double* b, hipStream_t s) {
-    k_poisson_rhs<<<grid_for(g.N), EB_BLOCK, 0, s>>>(g, div, mean, b);
+void op_poisson_rhs(const GeomV& g, const double* div, const double* sumcnt, double* b,
+                    hipStream_t s) {
+    k_poisson_rhs<<<grid_for(g.N), EB_BLOCK, 0, s>>>(g, div, sumcnt, b);
 }
-void op_shift_open(const GeomV& g, double* x, double shift, hipStream_t s) {
-    k_shift_open<<<grid_for(g.N), EB_BLOCK, 0, s>>>(g, x, shift);
+void op_shift_open(const GeomV& g, double* x, const double* sumcnt, hipStream_t s) {
+    k_shift_open<<<grid_for(g.N), EB_BLOCK, 0, s>>>(g, x, sumcnt);
 }
