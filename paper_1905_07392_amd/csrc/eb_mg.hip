@@ -228,6 +228,50 @@ __device__ __forceinline__ void prolong_cell(const GridV& gf, const GridV& gc,
     for (int m = 0; m < NC; m++) xf[m * Nf + f] += (TF)ec[m * Nc + c];
 }
 
+// first red half sweep from a zero iterate, over the whole grid: red cells get b/D (all their
+// neighbours are zero), every other cell 0 -- the zero fill and the first sweep in one pass
+template <typename T, int NC>
+__global__ void k_smooth_first(LevelV<T> L, const T* __restrict__ b, T* __restrict__ x) {
+    if (L.gate && *L.gate) return;
+    long c = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (c >= L.N) return;
+    int i, j, k;
+    cell_coords(L.grid, c, i, j, k);
+    bool upd = ((i + j + k) & 1) == 0 && L.mask[c] && L.D[c] > (T)0;
+    T dg = upd ? L.D[c] : (T)1;
+#pragma unroll
+    for (int m = 0; m < NC; m++) x[m * L.N + c] = upd ? (b[m * L.N + c] + (T)0) / dg : (T)0;
+}
+
+// residual of the fine level restricted to the coarse right-hand side in one pass
+template <typename TF, typename TC, int NC>
+__global__ void k_resid_restrict(LevelV<TF> L, const TF* __restrict__ b, const TF* __restrict__ x,
+                                 GridV gc, const uint8_t* __restrict__ mc, TC* __restrict__ bc) {
+    if (L.gate && *L.gate) return;
+    long Nc = (long)gc.n[0] * gc.n[1] * gc.n[2];
+    long c = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (c >= Nc) return;
+    int i, j, k;
+    cell_coords(gc, c, i, j, k);
+    TF s[NC];
+#pragma unroll
+    for (int m = 0; m < NC; m++) s[m] = (TF)0;
+    for (int q = 0; q < 8; q++) {
+        int fi = 2 * i + (q & 1), fj = 2 * j + ((q >> 1) & 1), fk = 2 * k + (q >> 2);
+        long f = cell_index(L.grid, fi, fj, fk);
+        if (!L.mask[f]) continue;
+        TF acc[NC];
+#pragma unroll
+        for (int m = 0; m < NC; m++) acc[m] = (TF)0;
+        offdiag<TF, NC>(L, x, fi, fj, fk, acc);
+        TF dg = L.D[f];
+#pragma unroll
+        for (int m = 0; m < NC; m++) s[m] += b[m * L.N + f] - (dg * x[m * L.N + f] - acc[m]);
+    }
+#pragma unroll
+    for (int m = 0; m < NC; m++) bc[m * Nc + c] = mc[c] ? (TC)(s[m] / (TF)8) : (TC)0;
+}
+
 template <typename T, int NC>
 __global__ void k_smooth(LevelV<T> L, const T* __restrict__ b, T* __restrict__ x, int col) {
     if (L.gate && *L.gate) return;
@@ -707,6 +751,28 @@ void restrict_pass(const Level& F, const Level& C, int nc, const TF* rf, TC* bc,
         k_restrict<TF, TC, 1><<<grid_for(C.N), EB_BLOCK, 0, s>>>(F.grid, C.grid, F.mask, C.mask,
                                                                 rf, bc, F.gate);
 }
+template <typename T>
+LevelV<T> level_view(const Level& L);
+template <>
+LevelV<double> level_view<double>(const Level& L) { return L.v64(); }
+template <>
+LevelV<float> level_view<float>(const Level& L) { return L.v32(); }
+
+template <typename T>
+void first_pass(const Level& L, int nc, const T* b, T* x, hipStream_t s) {
+    if (nc == 3) k_smooth_first<T, 3><<<grid_for(L.N), EB_BLOCK, 0, s>>>(level_view<T>(L), b, x);
+    else k_smooth_first<T, 1><<<grid_for(L.N), EB_BLOCK, 0, s>>>(level_view<T>(L), b, x);
+}
+template <typename TF, typename TC>
+void resid_restrict_pass(const Level& F, const Level& C, int nc, const TF* b, const TF* x,
+                         TC* bc, hipStream_t s) {
+    if (nc == 3)
+        k_resid_restrict<TF, TC, 3><<<grid_for(C.N), EB_BLOCK, 0, s>>>(level_view<TF>(F), b, x,
+                                                                      C.grid, C.mask, bc);
+    else
+        k_resid_restrict<TF, TC, 1><<<grid_for(C.N), EB_BLOCK, 0, s>>>(level_view<TF>(F), b, x,
+                                                                      C.grid, C.mask, bc);
+}
 template <typename TC, typename TF>
 void prolong_pass(const Level& F, const Level& C, int nc, const TC* ec, TF* xf, hipStream_t s) {
     if (nc == 3)
@@ -778,7 +844,8 @@ void vcycle_level(const VArgs& a, int l) {
     Level& L = a.lev[l];
     T* x = xl<T>(L);
     T* b = bl<T>(L);
-    k_zero<T><<<grid_for(a.nc * L.N), EB_BLOCK, 0, a.s>>>(a.nc * L.N, x, L.gate);
+    if (l == a.nlev - 1 || a.nu1 < 1)
+        k_zero<T><<<grid_for(a.nc * L.N), EB_BLOCK, 0, a.s>>>(a.nc * L.N, x, L.gate);
     if (l == a.nlev - 1) {
         for (int t = 0; t < a.nbottom; t++) {
             smooth_pass<T>(L, a.nc, b, x, 0, a.s);
@@ -791,14 +858,13 @@ void vcycle_level(const VArgs& a, int l) {
         return;
     }
     for (int t = 0; t < a.nu1; t++) {
-        smooth_pass<T>(L, a.nc, b, x, 0, a.s);
+        if (t == 0) first_pass<T>(L, a.nc, b, x, a.s);
+        else smooth_pass<T>(L, a.nc, b, x, 0, a.s);
         smooth_pass<T>(L, a.nc, b, x, 1, a.s);
     }
-    T* r = rl<T>(L);
-    resid_pass<T>(L, a.nc, b, x, r, a.s);
     Level& C = a.lev[l + 1];
-    if (level_f32(a, l + 1)) restrict_pass<T, float>(L, C, a.nc, r, C.bf, a.s);
-    else restrict_pass<T, double>(L, C, a.nc, r, C.b, a.s);
+    if (level_f32(a, l + 1)) resid_restrict_pass<T, float>(L, C, a.nc, b, x, C.bf, a.s);
+    else resid_restrict_pass<T, double>(L, C, a.nc, b, x, C.b, a.s);
     vcycle_rec(a, l + 1);
     if (level_f32(a, l + 1)) prolong_pass<float, T>(L, C, a.nc, C.xf, x, a.s);
     else prolong_pass<double, T>(L, C, a.nc, C.x, x, a.s);
