@@ -1685,9 +1685,10 @@ int or_cc_project(const or_geom* g_in, double beta, double* u, double* p, double
 /* ------------------------------------------------------------------------------------------ */
 /* DerivedQuantities (Alg. derived) and the RK2 step (Alg. advance)                             */
 /* ------------------------------------------------------------------------------------------ */
-int or_derived(const or_geom* g_in, const or_rheo* rh, const double* theta, const double* u,
-               const or_opts* o, double* C, double* eta, double* eta_eb, double* V,
-               int* iters) {
+/* uf_keep (nullable): receives the projected face velocities used for the upwinding */
+static int derived_impl(const or_geom* g_in, const or_rheo* rh, const double* theta,
+                        const double* u, const or_opts* o, double* C, double* eta,
+                        double* eta_eb, double* V, int* iters, double* const uf_keep[3]) {
     or_geom* g = (or_geom*)g_in;
     const int* n = g->box.n;
     long N = g->N;
@@ -1706,6 +1707,8 @@ int or_derived(const or_geom* g_in, const or_rheo* rh, const double* theta, cons
     viscosity_from(g, rh, theta, G, gw, eta, eta_eb, NULL);
     transpose_term_dc(g, eta, eta_eb, u, G, gw, DC);
     or_redistribute(g, 3, DC, V);
+    if (uf_keep)
+        for (int d = 0; d < 3; d++) memcpy(uf_keep[d], uf[d], nfaces(n, d) * sizeof(double));
     free(DC);
     free(G);
     free(gw);
@@ -1714,8 +1717,27 @@ int or_derived(const or_geom* g_in, const or_rheo* rh, const double* theta, cons
     return ret;
 }
 
-int or_rk2_step(const or_geom* g_in, const or_rheo* rh, const double* theta, double dt,
-                const or_opts* o, double* u, double* p, or_stats* st) {
+int or_derived(const or_geom* g, const or_rheo* rh, const double* theta, const double* u,
+               const or_opts* o, double* C, double* eta, double* eta_eb, double* V,
+               int* iters) {
+    return derived_impl(g, rh, theta, u, o, C, eta, eta_eb, V, iters, NULL);
+}
+
+/* intermediate fields of one step, kept for the reverse sweep */
+typedef struct {
+    double* ufm[3]; /* projected face velocities of the predictor */
+    double* em;     /* viscosity at u^m (predictor operator) */
+    double* ebm;
+    double* us1;    /* predictor solve, before its projection */
+    double* u1;     /* projected predictor velocity u* */
+    double* uf1[3]; /* projected face velocities of the corrector */
+    double* ea;     /* averaged viscosity (corrector operator) */
+    double* eba;
+    double* us2;    /* corrector solve, before its projection */
+} rk2_tape;
+
+static int rk2_impl(const or_geom* g_in, const or_rheo* rh, const double* theta, double dt,
+                    const or_opts* o, double* u, double* p, or_stats* st, rk2_tape* tp) {
     or_geom* g = (or_geom*)g_in;
     long N = g->N, N3 = 3 * N;
     int nc = g->ncut + 1;
@@ -1728,7 +1750,7 @@ int or_rk2_step(const or_geom* g_in, const or_rheo* rh, const double* theta, dou
     or_stats loc;
     memset(&loc, 0, sizeof(loc));
     /* predictor */
-    e = or_derived(g, rh, theta, u, o, Cm, em, ebm, Vm, &it);
+    e = derived_impl(g, rh, theta, u, o, Cm, em, ebm, Vm, &it, tp ? tp->ufm : NULL);
     loc.it_mac[0] = it;
     if (e) err = e;
     or_gcc(g, p, gp);
@@ -1740,12 +1762,18 @@ int or_rk2_step(const or_geom* g_in, const or_rheo* rh, const double* theta, dou
     e = or_visc_solve(g, rho, dt, em, ebm, psi, ut, o->rtol_visc, o->max_iter, o, &it);
     loc.it_visc[0] = it;
     if (e) err = e;
+    if (tp) {
+        memcpy(tp->em, em, N * 8);
+        memcpy(tp->ebm, ebm, nc * 8);
+        memcpy(tp->us1, ut, N3 * 8);
+    }
     memcpy(ps, p, N * 8);
     e = or_cc_project(g, beta, ut, ps, o->rtol_proj, o->max_iter, o, &loc.div_proj[0], &it);
     loc.it_proj[0] = it;
     if (e) err = e;
     /* corrector: derived quantities at u*, averaged with those at u^m */
-    e = or_derived(g, rh, theta, ut, o, Cs, es, ebs, Vs, &it);
+    if (tp) memcpy(tp->u1, ut, N3 * 8);
+    e = derived_impl(g, rh, theta, ut, o, Cs, es, ebs, Vs, &it, tp ? tp->uf1 : NULL);
     loc.it_mac[1] = it;
     if (e) err = e;
     for (long q = 0; q < N3; q++) {
@@ -1762,6 +1790,11 @@ int or_rk2_step(const or_geom* g_in, const or_rheo* rh, const double* theta, dou
     e = or_visc_solve(g, rho, dt, em, ebm, psi, ut, o->rtol_visc, o->max_iter, o, &it);
     loc.it_visc[1] = it;
     if (e) err = e;
+    if (tp) {
+        memcpy(tp->ea, em, N * 8);
+        memcpy(tp->eba, ebm, nc * 8);
+        memcpy(tp->us2, ut, N3 * 8);
+    }
     e = or_cc_project(g, beta, ut, ps, o->rtol_proj, o->max_iter, o, &loc.div_proj[1], &it);
     loc.it_proj[1] = it;
     if (e) err = e;
@@ -1775,6 +1808,11 @@ int or_rk2_step(const or_geom* g_in, const or_rheo* rh, const double* theta, dou
     free(Cs); free(Vs); free(es); free(ebs);
     free(psi); free(gp); free(ut); free(ps);
     return err;
+}
+
+int or_rk2_step(const or_geom* g, const or_rheo* rh, const double* theta, double dt,
+                const or_opts* o, double* u, double* p, or_stats* st) {
+    return rk2_impl(g, rh, theta, dt, o, u, p, st, NULL);
 }
 
 /* ------------------------------------------------------------------------------------------ */
@@ -1807,4 +1845,934 @@ void or_drag(const or_geom* g, const or_rheo* r, const double* theta, const doub
     }
     free(gw);
     free(gp);
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* adjoint (reverse mode) of the step.  Each routine is the exact transpose of the linearised  */
+/* forward routine above it in the file, with                                                   */
+/*   - every iterative solve taken as exact (implicit-function rule: the transposed system is  */
+/*     solved, not the iteration differentiated),                                               */
+/*   - every switch frozen at its forward value: upwind side, limiter branch, one-sided        */
+/*     stencil choice, largest normal component, covered-node fallback.                        */
+/* Adjoint arguments named *b hold d(loss)/d(that quantity) and are accumulated (+=) unless a   */
+/* comment says otherwise.                                                                      */
+/* ------------------------------------------------------------------------------------------ */
+static void wall_dudn_adj(const or_geom* g, int cid, double gb, double* ubj) {
+    double d1 = g->dd[2 * cid], d2 = g->dd[2 * cid + 1];
+    double den = d1 * d2 * (d2 - d1) * g->box.h;
+    for (int kk = 0; kk < 2; kk++) {
+        double cf = kk == 0 ? d2 * d2 / den : -d1 * d1 / den;
+        for (int m = 0; m < 9; m++) {
+            long slot = ((long)cid * 2 + kk) * 9 + m;
+            long cc = g->sidx[slot];
+            if (cc >= 0) ubj[cc] += g->sw[slot] * cf * gb;
+        }
+    }
+}
+
+void or_wall_gradient_adj(const or_geom* g, const double* gwb, double* ub) {
+    for (int c = 0; c < g->ncut; c++)
+        for (int j = 0; j < 3; j++) wall_dudn_adj(g, c, gwb[3 * c + j], ub + (long)j * g->N);
+}
+
+void or_cell_gradient_adj(const or_geom* g, const double* Gb, double* ub, double* gwb) {
+    const int* n = g->box.n;
+    const int* per = g->box.periodic;
+    long N = g->N;
+    double h = g->box.h;
+    for (long c = 0; c < N; c++) {
+        if (g->alpha[c] <= 0.0) continue;
+        int q[3];
+        cell_ijk(n, c, q);
+        for (int d = 0; d < 3; d++) {
+            int r[3];
+            memcpy(r, q, sizeof(r));
+            r[d] = q[d] - 1;
+            long lo = cell_at(n, per, r);
+            r[d] = q[d] - 2;
+            long lo2 = cell_at(n, per, r);
+            r[d] = q[d] + 1;
+            long hi = cell_at(n, per, r);
+            r[d] = q[d] + 2;
+            long hi2 = cell_at(n, per, r);
+            int lo_wall = lo < 0, hi_wall = hi < 0;
+            int lo_open = !lo_wall && g->alpha[lo] > 0.0;
+            int hi_open = !hi_wall && g->alpha[hi] > 0.0;
+            int lo2_open = lo2 >= 0 && g->alpha[lo2] > 0.0;
+            int hi2_open = hi2 >= 0 && g->alpha[hi2] > 0.0;
+            int lo_ok = lo_open || lo_wall, hi_ok = hi_open || hi_wall;
+            for (int j = 0; j < 3; j++) {
+                double gb = Gb[(d * 3 + j) * N + c];
+                double* u = ub + (long)j * N;
+                if (lo_ok && hi_ok) {
+                    double w = gb / (2.0 * h); /* ghost values 2 u_wall - u_c at walls */
+                    if (hi_open) u[hi] += w;
+                    else u[c] -= w;
+                    if (lo_open) u[lo] -= w;
+                    else u[c] += w;
+                } else if (hi_ok) {
+                    if (hi_open && hi2_open) {
+                        u[c] += -1.5 * gb / h;
+                        u[hi] += 2.0 * gb / h;
+                        u[hi2] += -0.5 * gb / h;
+                    } else {
+                        if (hi_open) u[hi] += gb / h;
+                        else u[c] -= gb / h;
+                        u[c] -= gb / h;
+                    }
+                } else if (lo_ok) {
+                    if (lo_open && lo2_open) {
+                        u[c] += 1.5 * gb / h;
+                        u[lo] += -2.0 * gb / h;
+                        u[lo2] += 0.5 * gb / h;
+                    } else {
+                        u[c] += gb / h;
+                        if (lo_open) u[lo] -= gb / h;
+                        else u[c] += gb / h;
+                    }
+                } else {
+                    long cid = g->cutid[c];
+                    if (cid >= 0) gwb[3 * cid + j] += g->nrm[3 * cid + d] * gb;
+                }
+            }
+        }
+    }
+}
+
+/* d eta / d(strain-rate norm) and d eta / d tau0 of the law in law_eta */
+static void law_deriv(const or_rheo* r, double tau0, double sr, double* d_sr, double* d_tau0) {
+    if (r->law == OR_LAW_NEWTONIAN) {
+        *d_sr = 0.0;
+        *d_tau0 = 0.0;
+        return;
+    }
+    if (r->law == OR_LAW_BINGHAM_REG) {
+        double q = 1.0 / (sr + r->eps);
+        *d_tau0 = q;
+        *d_sr = -tau0 * q * q;
+        return;
+    }
+    /* Papanastasiou: eta = mu + tau0 f(sr), f(s) = (1 - exp(-s/eps))/s; with x = s/eps,
+     * f'(s) = g'(x)/eps^2, g(x) = (1 - e^-x)/x, g'(x) = (x e^-x + expm1(-x))/x^2, whose Taylor
+     * series -1/2 + x/3 - x^2/8 + x^3/30 - x^4/144 avoids the cancellation for small x. */
+    double e = r->eps, x = sr / e, gp;
+    if (x < 1e-2)
+        gp = -0.5 + x * (1.0 / 3.0 + x * (-1.0 / 8.0 + x * (1.0 / 30.0 - x / 144.0)));
+    else
+        gp = (x * exp(-x) + expm1(-x)) / (x * x);
+    *d_tau0 = sr == 0.0 ? 1.0 / e : -expm1(-x) / sr;
+    *d_sr = tau0 * gp / (e * e);
+}
+
+/* strain_norm backward: d sr / d G_ab = (G_ab + G_ba)/sr (zero at sr = 0) */
+static void strain_norm_adj(const double Gm[3][3], double sr, double srb, double Gmb[3][3]) {
+    for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) Gmb[a][b] = sr > 0.0 ? srb * (Gm[a][b] + Gm[b][a]) / sr : 0.0;
+}
+
+static void viscosity_adj(const or_geom* g, const or_rheo* r, const double* theta,
+                          const double* G, const double* gw, const double* etab,
+                          const double* etaebb, double* Gb, double* gwb, double* tau0b) {
+    long N = g->N;
+    for (long c = 0; c < N; c++) {
+        if (g->alpha[c] <= 0.0) continue;
+        double Gm[3][3], Gmb[3][3], dsr, dt0;
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) Gm[a][b] = G[(a * 3 + b) * N + c];
+        double s = strain_norm(Gm);
+        law_deriv(r, r->tau0 * (theta ? theta[c] : 1.0), s, &dsr, &dt0);
+        tau0b[c] += dt0 * etab[c];
+        strain_norm_adj(Gm, s, dsr * etab[c], Gmb);
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) Gb[(a * 3 + b) * N + c] += Gmb[a][b];
+    }
+    for (int cid = 0; cid < g->ncut; cid++) {
+        long c = g->cut[cid];
+        const double* nv = &g->nrm[3 * cid];
+        double Gm[3][3], Gmb[3][3], dsr, dt0;
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) Gm[a][b] = nv[a] * gw[3 * cid + b];
+        double s = strain_norm(Gm);
+        law_deriv(r, r->tau0 * (theta ? theta[c] : 1.0), s, &dsr, &dt0);
+        tau0b[c] += dt0 * etaebb[cid];
+        strain_norm_adj(Gm, s, dsr * etaebb[cid], Gmb);
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) gwb[3 * cid + b] += nv[a] * Gmb[a][b];
+    }
+}
+
+void or_redistribute_adj(const or_geom* g, int ncomp, const double* Db, double* DCb) {
+    const int* n = g->box.n;
+    const int* per = g->box.periodic;
+    long N = g->N;
+    double* S = calloc(N, sizeof(double));
+    double* dDb = calloc((long)ncomp * N, sizeof(double));
+    for (long c = 0; c < N; c++) {
+        if (g->alpha[c] <= 0.0 || g->flag[c] != 1) continue;
+        int q[3];
+        cell_ijk(n, c, q);
+        double s = 0;
+        for (int dz = -1; dz <= 1; dz++)
+            for (int dy = -1; dy <= 1; dy++)
+                for (int dx = -1; dx <= 1; dx++) {
+                    if (!dx && !dy && !dz) continue;
+                    int r[3] = {q[0] + dx, q[1] + dy, q[2] + dz};
+                    long cc = cell_at(n, per, r);
+                    if (cc < 0 || g->alpha[cc] <= 0.0) continue;
+                    s += g->alpha[cc];
+                }
+        S[c] = s;
+    }
+    /* the second pass adds dD_k / S_k of every cut neighbour k to each open cell */
+    for (long c = 0; c < N; c++) {
+        if (g->alpha[c] <= 0.0) continue;
+        int q[3];
+        cell_ijk(n, c, q);
+        for (int dz = -1; dz <= 1; dz++)
+            for (int dy = -1; dy <= 1; dy++)
+                for (int dx = -1; dx <= 1; dx++) {
+                    if (!dx && !dy && !dz) continue;
+                    int r[3] = {q[0] + dx, q[1] + dy, q[2] + dz};
+                    long cc = cell_at(n, per, r);
+                    if (cc < 0 || g->flag[cc] != 1 || S[cc] <= 0.0) continue;
+                    for (int m = 0; m < ncomp; m++) dDb[m * N + cc] += Db[m * N + c] / S[cc];
+                }
+    }
+    /* the first pass: DH = a DC + (1-a) DNC and dD = a (1-a) (DC - DNC) on cut cells */
+    for (long c = 0; c < N; c++) {
+        if (g->alpha[c] <= 0.0) continue;
+        if (g->flag[c] != 1) {
+            for (int m = 0; m < ncomp; m++) DCb[m * N + c] += Db[m * N + c];
+            continue;
+        }
+        double a = g->alpha[c];
+        int q[3];
+        cell_ijk(n, c, q);
+        for (int m = 0; m < ncomp; m++) {
+            double dhb = Db[m * N + c], ddb = dDb[m * N + c];
+            DCb[m * N + c] += a * dhb + a * (1.0 - a) * ddb;
+            double dncb = (1.0 - a) * dhb - a * (1.0 - a) * ddb;
+            if (S[c] <= 0.0) {
+                DCb[m * N + c] += dncb;
+                continue;
+            }
+            for (int dz = -1; dz <= 1; dz++)
+                for (int dy = -1; dy <= 1; dy++)
+                    for (int dx = -1; dx <= 1; dx++) {
+                        if (!dx && !dy && !dz) continue;
+                        int r[3] = {q[0] + dx, q[1] + dy, q[2] + dz};
+                        long cc = cell_at(n, per, r);
+                        if (cc < 0 || g->alpha[cc] <= 0.0) continue;
+                        DCb[m * N + cc] += g->alpha[cc] / S[c] * dncb;
+                    }
+        }
+    }
+    free(S);
+    free(dDb);
+}
+
+static void transpose_term_adj(const or_geom* g, const double* eta, const double* eta_eb,
+                               const double* u, const double* G, const double* gw,
+                               const double* DCb, double* etab, double* etaebb, double* ub,
+                               double* Gb, double* gwb) {
+    const int* n = g->box.n;
+    const int* per = g->box.periodic;
+    long N = g->N;
+    double h = g->box.h;
+    for (long c = 0; c < N; c++) {
+        if (g->alpha[c] <= 0.0) continue;
+        int q[3];
+        cell_ijk(n, c, q);
+        for (int j = 0; j < 3; j++) {
+            double wj = DCb[j * N + c] / (g->alpha[c] * h);
+            for (int d = 0; d < 3; d++)
+                for (int side = -1; side <= 1; side += 2) {
+                    int f[3] = {q[0], q[1], q[2]};
+                    if (side > 0) f[d] += 1;
+                    double A = g->ap[d][fidx(n, d, f[0], f[1], f[2])];
+                    if (A == 0.0) continue;
+                    int r[3] = {q[0], q[1], q[2]};
+                    r[d] += side;
+                    long nb = cell_at(n, per, r);
+                    const double* ud = u + (long)d * N;
+                    double cf = side * A * wj; /* adjoint of the face flux F */
+                    if (nb >= 0) {
+                        double ef = 0.5 * (eta[c] + eta[nb]);
+                        double der;
+                        if (j == d)
+                            der = side > 0 ? (ud[nb] - ud[c]) / h : (ud[c] - ud[nb]) / h;
+                        else
+                            der = 0.5 * (G[(j * 3 + d) * N + c] + G[(j * 3 + d) * N + nb]);
+                        etab[c] += 0.5 * cf * der;
+                        etab[nb] += 0.5 * cf * der;
+                        if (j == d) {
+                            double t = cf * ef / h;
+                            ub[d * N + nb] += side > 0 ? t : -t;
+                            ub[d * N + c] += side > 0 ? -t : t;
+                        } else {
+                            Gb[(j * 3 + d) * N + c] += 0.5 * cf * ef;
+                            Gb[(j * 3 + d) * N + nb] += 0.5 * cf * ef;
+                        }
+                    } else if (j == d) {
+                        double uw = g->box.wall_u[2 * d + (side > 0)][d];
+                        double der = side > 0 ? (uw - ud[c]) / (0.5 * h) : (ud[c] - uw) / (0.5 * h);
+                        etab[c] += cf * der;
+                        double t = cf * eta[c] / (0.5 * h);
+                        ub[d * N + c] += side > 0 ? -t : t;
+                    }
+                }
+            long cid = g->cutid[c];
+            if (cid >= 0) {
+                const double* nv = &g->nrm[3 * cid];
+                double ng = nv[0] * gw[3 * cid] + nv[1] * gw[3 * cid + 1] + nv[2] * gw[3 * cid + 2];
+                etaebb[cid] += -g->aeb[cid] * nv[j] * ng * wj;
+                for (int b = 0; b < 3; b++)
+                    gwb[3 * cid + b] += -g->aeb[cid] * eta_eb[cid] * nv[j] * nv[b] * wj;
+            }
+        }
+    }
+}
+
+/* limited slope backward with the branch of the forward frozen: the slope equals the central
+ * difference, twice the left or twice the right difference, or zero */
+static void mc_slope_adj(const or_geom* g, const double* uj, long c, int d, double sb,
+                         double* ubj) {
+    const int* n = g->box.n;
+    int q[3];
+    cell_ijk(n, c, q);
+    int r[3];
+    memcpy(r, q, sizeof(r));
+    r[d] = q[d] - 1;
+    long lo = cell_at(n, g->box.periodic, r);
+    r[d] = q[d] + 1;
+    long hi = cell_at(n, g->box.periodic, r);
+    if (lo < 0 || hi < 0) return;
+    if (g->alpha[lo] <= 0.0 || g->alpha[hi] <= 0.0) return;
+    double dl = uj[c] - uj[lo], dr = uj[hi] - uj[c], dc = 0.5 * (uj[hi] - uj[lo]);
+    if (dl * dr <= 0.0) return;
+    double adc = fabs(dc), al = 2.0 * fabs(dl), ar = 2.0 * fabs(dr);
+    if (adc <= fmin(al, ar)) {
+        ubj[hi] += 0.5 * sb;
+        ubj[lo] -= 0.5 * sb;
+    } else if (al <= ar) {
+        ubj[c] += 2.0 * sb;
+        ubj[lo] -= 2.0 * sb;
+    } else {
+        ubj[hi] += 2.0 * sb;
+        ubj[c] -= 2.0 * sb;
+    }
+}
+
+static void face_states_adj(const or_geom* g, const double* uj, long lo, long hi, int d,
+                            double uLb, double uRb, double* ubj) {
+    ubj[lo] += uLb;
+    mc_slope_adj(g, uj, lo, d, 0.5 * uLb, ubj);
+    ubj[hi] += uRb;
+    mc_slope_adj(g, uj, hi, d, -0.5 * uRb, ubj);
+}
+
+void or_face_extrap_adj(const or_geom* g, const double* u, const double* fbx,
+                        const double* fby, const double* fbz, double* ub) {
+    const int* n = g->box.n;
+    const double* fb[3] = {fbx, fby, fbz};
+    for (int d = 0; d < 3; d++) {
+        int m[3] = {n[0] + (d == 0), n[1] + (d == 1), n[2] + (d == 2)};
+        for (int k = 0; k < m[2]; k++)
+            for (int j = 0; j < m[1]; j++)
+                for (int i = 0; i < m[0]; i++) {
+                    int f[3] = {i, j, k};
+                    long fi = fidx(n, d, i, j, k);
+                    long lo, hi;
+                    face_cells(g, d, f, &lo, &hi);
+                    if (lo < 0 || hi < 0 || g->ap[d][fi] <= 0.0) continue;
+                    const double* ud = u + (long)d * g->N;
+                    double uL, uR;
+                    face_states(g, ud, lo, hi, d, &uL, &uR);
+                    if (uL > 0.0 && uL + uR > 0.0)
+                        face_states_adj(g, ud, lo, hi, d, fb[d][fi], 0.0, ub + (long)d * g->N);
+                    else if (uR < 0.0 && uL + uR < 0.0)
+                        face_states_adj(g, ud, lo, hi, d, 0.0, fb[d][fi], ub + (long)d * g->N);
+                }
+    }
+}
+
+static void conv_adj(const or_geom* g, const double* u, double* const uf[3], const double* DCb,
+                     double* ub, double* const ufb[3]) {
+    const int* n = g->box.n;
+    long N = g->N;
+    double h = g->box.h;
+    for (long c = 0; c < N; c++) {
+        if (g->alpha[c] <= 0.0) continue;
+        int q[3];
+        cell_ijk(n, c, q);
+        for (int j = 0; j < 3; j++) {
+            double wj = -DCb[j * N + c] / (g->alpha[c] * h);
+            for (int d = 0; d < 3; d++)
+                for (int side = -1; side <= 1; side += 2) {
+                    int f[3] = {q[0], q[1], q[2]};
+                    if (side > 0) f[d] += 1;
+                    long fi = fidx(n, d, f[0], f[1], f[2]);
+                    double A = g->ap[d][fi];
+                    if (A == 0.0) continue;
+                    long lo, hi;
+                    face_cells(g, d, f, &lo, &hi);
+                    double w = uf[d][fi], cf = side * A * wj;
+                    if (lo < 0 || hi < 0) {
+                        ufb[d][fi] += cf * g->box.wall_u[2 * d + (lo >= 0)][j];
+                        continue;
+                    }
+                    double uL, uR;
+                    face_states(g, u + (long)j * N, lo, hi, d, &uL, &uR);
+                    double up = w > 0.0 ? uL : (w < 0.0 ? uR : 0.5 * (uL + uR));
+                    ufb[d][fi] += cf * up;
+                    double upb = cf * w;
+                    double uLb = w > 0.0 ? upb : (w < 0.0 ? 0.0 : 0.5 * upb);
+                    double uRb = w > 0.0 ? 0.0 : (w < 0.0 ? upb : 0.5 * upb);
+                    face_states_adj(g, u + (long)j * N, lo, hi, d, uLb, uRb, ub + (long)j * N);
+                }
+        }
+    }
+}
+
+/* transpose of the face gradient G_f (open interior faces) applied to a face field */
+static void face_grad_T(const or_geom* g, double* const fb[3], double* y) {
+    const int* n = g->box.n;
+    double h = g->box.h;
+    memset(y, 0, g->N * sizeof(double));
+    for (int d = 0; d < 3; d++) {
+        int m[3] = {n[0] + (d == 0), n[1] + (d == 1), n[2] + (d == 2)};
+        for (int k = 0; k < m[2]; k++)
+            for (int j = 0; j < m[1]; j++)
+                for (int i = 0; i < m[0]; i++) {
+                    int f[3] = {i, j, k};
+                    long fi = fidx(n, d, i, j, k);
+                    long lo, hi;
+                    face_cells(g, d, f, &lo, &hi);
+                    if (lo < 0 || hi < 0 || g->ap[d][fi] == 0.0) continue;
+                    y[hi] += fb[d][fi] / h;
+                    y[lo] -= fb[d][fi] / h;
+                }
+    }
+}
+
+/* face field t = D^T z, the transpose of the linear part of or_divergence.  Along a periodic
+ * direction faces 0 and n are stored twice; face 0 enters only the divergence of the cell above
+ * it and face n only that of the cell below it. */
+static void div_T(const or_geom* g, const double* z, double* const t[3]) {
+    const int* n = g->box.n;
+    double h = g->box.h;
+    for (int d = 0; d < 3; d++) {
+        int m[3] = {n[0] + (d == 0), n[1] + (d == 1), n[2] + (d == 2)};
+        for (int k = 0; k < m[2]; k++)
+            for (int j = 0; j < m[1]; j++)
+                for (int i = 0; i < m[0]; i++) {
+                    int f[3] = {i, j, k};
+                    long fi = fidx(n, d, i, j, k);
+                    long lo, hi;
+                    face_cells(g, d, f, &lo, &hi);
+                    double s = 0.0;
+                    if (f[d] > 0 && lo >= 0 && g->alpha[lo] > 0.0) s += z[lo];
+                    if (f[d] < n[d] && hi >= 0 && g->alpha[hi] > 0.0) s -= z[hi];
+                    t[d][fi] = g->ap[d][fi] * s / h;
+                }
+    }
+}
+
+/* MAC projection backward.  Forward (exact solve): w' = w + beta G_f L^+ D w + const, with
+ * L the Poisson matrix (symmetric) and L^+ its pseudo-inverse on the open cells (the mean
+ * removal makes the right-hand side consistent).  Backward: wb += beta D^T L^+ G_f^T wb. */
+int or_mac_project_adj(const or_geom* g_in, double beta, double* fbx, double* fby, double* fbz,
+                       double rtol, int maxit, const or_opts* o, int* iters) {
+    or_geom* g = (or_geom*)g_in;
+    const int* n = g->box.n;
+    long N = g->N;
+    double* fb[3] = {fbx, fby, fbz};
+    double* y = malloc(N * sizeof(double));
+    double* z = calloc(N, sizeof(double));
+    double* t[3];
+    for (int d = 0; d < 3; d++) t[d] = malloc(nfaces(n, d) * sizeof(double));
+    face_grad_T(g, fb, y);
+    double scale = 0;
+    for (int d = 0; d < 3; d++)
+        for (long f = 0; f < nfaces(n, d); f++)
+            if (fabs(fb[d][f]) / g->box.h > scale) scale = fabs(fb[d][f]) / g->box.h;
+    for (long c = 0; c < N; c++) y[c] = -y[c];
+    /* poisson_solve solves L z = -(div - mean(div)) with zero-mean z: here div = -y */
+    int ret = poisson_solve(g, beta, y, z, rtol, scale, maxit, o, iters);
+    div_T(g, z, t);
+    for (int d = 0; d < 3; d++)
+        for (long f = 0; f < nfaces(n, d); f++) fb[d][f] += beta * t[d][f];
+    for (int d = 0; d < 3; d++) free(t[d]);
+    free(y);
+    free(z);
+    return ret;
+}
+
+/* transpose of or_gcc, accumulated into pb */
+void or_gcc_adj(const or_geom* g, const double* gpb, double* pb) {
+    const int* n = g->box.n;
+    long N = g->N;
+    double h = g->box.h;
+    for (long c = 0; c < N; c++) {
+        if (g->alpha[c] <= 0.0) continue;
+        int q[3];
+        cell_ijk(n, c, q);
+        for (int d = 0; d < 3; d++) {
+            double den = 0;
+            for (int side = -1; side <= 1; side += 2) {
+                int f[3] = {q[0], q[1], q[2]};
+                if (side > 0) f[d] += 1;
+                den += g->ap[d][fidx(n, d, f[0], f[1], f[2])];
+            }
+            if (den <= 0.0) continue;
+            for (int side = -1; side <= 1; side += 2) {
+                int f[3] = {q[0], q[1], q[2]};
+                if (side > 0) f[d] += 1;
+                double A = g->ap[d][fidx(n, d, f[0], f[1], f[2])];
+                if (A == 0.0) continue;
+                long lo, hi;
+                face_cells(g, d, f, &lo, &hi);
+                if (lo < 0 || hi < 0) continue;
+                double tt = gpb[d * N + c] * A / (den * h);
+                pb[hi] += tt;
+                pb[lo] -= tt;
+            }
+        }
+    }
+}
+
+/* end-of-stage projection backward.  Forward: u1 = u + beta Gcc p_old, w = F u1 + const,
+ * phi = -L^+ D w, u_new = u1 - beta Gcc phi, p_new = phi.  On entry ub, pb hold the adjoints
+ * of u_new, p_new; on exit those of u and p_old (overwritten, open cells only). */
+int or_cc_project_adj(const or_geom* g_in, double beta, double* ub, double* pb, double rtol,
+                      int maxit, const or_opts* o, int* iters) {
+    or_geom* g = (or_geom*)g_in;
+    const int* n = g->box.n;
+    long N = g->N;
+    double* phib = calloc(N, sizeof(double));
+    double* gpb = malloc(3 * N * sizeof(double));
+    double* z = calloc(N, sizeof(double));
+    double* t[3];
+    for (int d = 0; d < 3; d++) t[d] = malloc(nfaces(n, d) * sizeof(double));
+    for (long q = 0; q < 3 * N; q++) gpb[q] = g->alpha[q % N] > 0.0 ? -beta * ub[q] : 0.0;
+    for (long c = 0; c < N; c++) phib[c] = g->alpha[c] > 0.0 ? pb[c] : 0.0;
+    or_gcc_adj(g, gpb, phib);
+    double scale = vmaxabs(phib, N);
+    for (long c = 0; c < N; c++) phib[c] = -phib[c];
+    /* z = L^+ phib (poisson_solve with div = -phib) */
+    int ret = poisson_solve(g, beta, phib, z, rtol, scale, maxit, o, iters);
+    div_T(g, z, t);
+    /* ub1 = ub - F^T D^T z */
+    for (int d = 0; d < 3; d++) {
+        int m[3] = {n[0] + (d == 0), n[1] + (d == 1), n[2] + (d == 2)};
+        for (int k = 0; k < m[2]; k++)
+            for (int j = 0; j < m[1]; j++)
+                for (int i = 0; i < m[0]; i++) {
+                    int f[3] = {i, j, k};
+                    long fi = fidx(n, d, i, j, k);
+                    long lo, hi;
+                    face_cells(g, d, f, &lo, &hi);
+                    if (lo < 0 || hi < 0 || g->ap[d][fi] <= 0.0) continue;
+                    ub[(long)d * N + lo] -= 0.5 * t[d][fi];
+                    ub[(long)d * N + hi] -= 0.5 * t[d][fi];
+                }
+    }
+    for (long q = 0; q < 3 * N; q++) {
+        if (g->alpha[q % N] <= 0.0) ub[q] = 0.0;
+        gpb[q] = beta * ub[q];
+    }
+    memset(pb, 0, N * sizeof(double));
+    or_gcc_adj(g, gpb, pb);
+    for (int d = 0; d < 3; d++) free(t[d]);
+    free(phib);
+    free(gpb);
+    free(z);
+    return ret;
+}
+
+/* transpose of the homogeneous viscous operator of or_visc_apply: the 7-point part is
+ * symmetric, the wall-flux rows of the cut cells are scattered back onto their stencils */
+static void visc_apply_T(const or_geom* g, double rho, double dt, const double* eta,
+                         const double* eta_eb, const double* lam, double* out) {
+    long N = g->N;
+    const int* n = g->box.n;
+    const int* per = g->box.periodic;
+    double h = g->box.h;
+    for (long c = 0; c < N; c++) {
+        for (int j = 0; j < 3; j++) out[j * N + c] = 0.0;
+        if (g->alpha[c] <= 0.0) continue;
+        int q[3];
+        cell_ijk(n, c, q);
+        for (int j = 0; j < 3; j++) {
+            const double* lj = lam + (long)j * N;
+            double acc = g->alpha[c] * rho * lj[c];
+            for (int d = 0; d < 3; d++)
+                for (int side = -1; side <= 1; side += 2) {
+                    int f[3] = {q[0], q[1], q[2]};
+                    if (side > 0) f[d] += 1;
+                    double A = g->ap[d][fidx(n, d, f[0], f[1], f[2])];
+                    if (A == 0.0) continue;
+                    int r[3] = {q[0], q[1], q[2]};
+                    r[d] += side;
+                    long nb = cell_at(n, per, r);
+                    if (nb >= 0) acc -= dt * A * 0.5 * (eta[c] + eta[nb]) / (h * h) * (lj[nb] - lj[c]);
+                    else acc += 2.0 * dt * A * eta[c] / (h * h) * lj[c];
+                }
+            out[j * N + c] = acc;
+        }
+    }
+    for (int cid = 0; cid < g->ncut; cid++) {
+        long c = g->cut[cid];
+        for (int j = 0; j < 3; j++)
+            wall_dudn_adj(g, cid, dt * g->aeb[cid] * eta_eb[cid] * lam[j * N + c] / h,
+                          out + (long)j * N);
+    }
+}
+
+/* BiCGSTAB on A^T lam = rhs, right-preconditioned by the same (symmetric) V-cycle; the
+ * viscous operator of the multigrid levels must already be built */
+static int visc_solve_T(or_geom* g, double rho, double dt, const double* eta,
+                        const double* eta_eb, const double* rhs, double* x, double rtol,
+                        int maxit, const or_opts* o, int* iters) {
+    long N3 = 3 * g->N;
+    double* r = malloc(N3 * sizeof(double));
+    double* rh = malloc(N3 * sizeof(double));
+    double* p = calloc(N3, sizeof(double));
+    double* v = calloc(N3, sizeof(double));
+    double* ph = malloc(N3 * sizeof(double));
+    double* s = malloc(N3 * sizeof(double));
+    double* sh = malloc(N3 * sizeof(double));
+    double* t = malloc(N3 * sizeof(double));
+    int ret = OR_ENOCONV;
+    *iters = 0;
+    memset(x, 0, N3 * sizeof(double));
+    memcpy(r, rhs, N3 * sizeof(double));
+    double bn = vmaxabs(rhs, N3), tol = rtol * bn;
+    if (bn == 0.0) {
+        ret = OR_OK;
+        goto done;
+    }
+    memcpy(rh, r, N3 * sizeof(double));
+    double rho_old = 1, al = 1, om = 1;
+    for (int it = 1; it <= maxit; it++) {
+        double rr = vdot(rh, r, N3);
+        double be = (rr / rho_old) * (al / om);
+        for (long q = 0; q < N3; q++) p[q] = r[q] + be * (p[q] - om * v[q]);
+        vcycle_level(g, 0, 3, p, ph, o);
+        visc_apply_T(g, rho, dt, eta, eta_eb, ph, v);
+        al = rr / vdot(rh, v, N3);
+        for (long q = 0; q < N3; q++) s[q] = r[q] - al * v[q];
+        *iters = it;
+        if (vmaxabs(s, N3) <= tol) {
+            for (long q = 0; q < N3; q++) x[q] += al * ph[q];
+            ret = OR_OK;
+            break;
+        }
+        vcycle_level(g, 0, 3, s, sh, o);
+        visc_apply_T(g, rho, dt, eta, eta_eb, sh, t);
+        om = vdot(t, s, N3) / vdot(t, t, N3);
+        for (long q = 0; q < N3; q++) {
+            x[q] += al * ph[q] + om * sh[q];
+            r[q] = s[q] - om * t[q];
+        }
+        if (vmaxabs(r, N3) <= tol) {
+            ret = OR_OK;
+            break;
+        }
+        rho_old = rr;
+    }
+done:
+    free(r); free(rh); free(p); free(v); free(ph); free(s); free(sh); free(t);
+    return ret;
+}
+
+/* viscosity backward of the viscous residual R(u; eta) = or_visc_apply(u) (with boundary
+ * values): etab -= (dR/deta)^T lam, etaebb -= (dR/deta_EB)^T lam at the solution u */
+static void visc_coef_adj(const or_geom* g, double dt, const double* u, const double* lam,
+                          double* etab, double* etaebb) {
+    const int* n = g->box.n;
+    const int* per = g->box.periodic;
+    long N = g->N;
+    double h = g->box.h;
+    for (long c = 0; c < N; c++) {
+        if (g->alpha[c] <= 0.0) continue;
+        int q[3];
+        cell_ijk(n, c, q);
+        for (int d = 0; d < 3; d++)
+            for (int side = -1; side <= 1; side += 2) {
+                int f[3] = {q[0], q[1], q[2]};
+                if (side > 0) f[d] += 1;
+                double A = g->ap[d][fidx(n, d, f[0], f[1], f[2])];
+                if (A == 0.0) continue;
+                int r[3] = {q[0], q[1], q[2]};
+                r[d] += side;
+                long nb = cell_at(n, per, r);
+                for (int j = 0; j < 3; j++) {
+                    const double* uj = u + (long)j * N;
+                    double lc = lam[j * N + c];
+                    if (nb >= 0) {
+                        double t = dt * A / (2.0 * h * h) * (uj[nb] - uj[c]) * lc;
+                        etab[c] += t;
+                        etab[nb] += t;
+                    } else {
+                        double uw = g->box.wall_u[2 * d + (side > 0)][j];
+                        etab[c] += 2.0 * dt * A / (h * h) * (uw - uj[c]) * lc;
+                    }
+                }
+            }
+    }
+    for (int cid = 0; cid < g->ncut; cid++) {
+        long c = g->cut[cid];
+        for (int j = 0; j < 3; j++)
+            etaebb[cid] -= dt * g->aeb[cid] / h *
+                           wall_dudn(g, cid, u + (long)j * N, g->body.u_eb[j]) * lam[j * N + c];
+    }
+}
+
+/* backward of the implicit viscous solve R(x; eta) = alpha psi: lam = A^-T xb,
+ * psib += alpha lam, and the viscosity adjoints accumulate */
+static int visc_solve_adj(or_geom* g, double rho, double dt, const double* eta,
+                          const double* eta_eb, const double* x, const double* xb, double rtol,
+                          int maxit, const or_opts* o, double* psib, double* etab,
+                          double* etaebb, int* iters) {
+    long N = g->N, N3 = 3 * N;
+    double* rhs = malloc(N3 * sizeof(double));
+    double* lam = malloc(N3 * sizeof(double));
+    for (long q = 0; q < N3; q++) rhs[q] = g->alpha[q % N] > 0.0 ? xb[q] : 0.0;
+    build_operator(g, SYS_VISC, 0, rho, dt, eta, eta_eb);
+    int ret = visc_solve_T(g, rho, dt, eta, eta_eb, rhs, lam, rtol, maxit, o, iters);
+    for (long q = 0; q < N3; q++) psib[q] += g->alpha[q % N] * lam[q];
+    visc_coef_adj(g, dt, x, lam, etab, etaebb);
+    free(rhs);
+    free(lam);
+    return ret;
+}
+
+int or_visc_solve_adj(const or_geom* g, double rho, double dt, const double* eta,
+                      const double* eta_eb, const double* x, const double* xb, double rtol,
+                      int maxit, const or_opts* o, double* psib, double* etab, double* etaebb,
+                      int* iters) {
+    return visc_solve_adj((or_geom*)g, rho, dt, eta, eta_eb, x, xb, rtol, maxit, o, psib, etab,
+                          etaebb, iters);
+}
+
+/* backward of the derived quantities (C, eta, eta_EB, V) at u; uf: the projected face
+ * velocities of the forward (nullable: recomputed) */
+int or_derived_adj(const or_geom* g_in, const or_rheo* rh, const double* theta, const double* u,
+                   const double* const uf_in[3], const or_opts* o, const double* Cb,
+                   const double* etab_in, const double* etaebb_in, const double* Vb, double* ub,
+                   double* tau0b, int* iters) {
+    or_geom* g = (or_geom*)g_in;
+    const int* n = g->box.n;
+    long N = g->N;
+    int nc = g->ncut + 1;
+    double* uf[3];
+    double* ufb[3];
+    for (int d = 0; d < 3; d++) {
+        uf[d] = malloc(nfaces(n, d) * sizeof(double));
+        ufb[d] = calloc(nfaces(n, d), sizeof(double));
+    }
+    int ret = OR_OK, it = 0;
+    if (uf_in) {
+        for (int d = 0; d < 3; d++) memcpy(uf[d], uf_in[d], nfaces(n, d) * sizeof(double));
+    } else {
+        double* phi = calloc(N, sizeof(double));
+        or_face_extrap(g, u, uf[0], uf[1], uf[2]);
+        ret = or_mac_project(g, 1.0, uf[0], uf[1], uf[2], phi, o->rtol_mac, o->max_iter, o,
+                             NULL, &it);
+        free(phi);
+    }
+    double* gw = calloc(3 * nc, sizeof(double));
+    double* G = malloc(9 * N * sizeof(double));
+    double* eta = malloc(N * sizeof(double));
+    double* eta_eb = calloc(nc, sizeof(double));
+    double* etab = malloc(N * sizeof(double));
+    double* etaebb = calloc(nc, sizeof(double));
+    double* DCb = calloc(3 * N, sizeof(double));
+    double* Gb = calloc(9 * N, sizeof(double));
+    double* gwb = calloc(3 * nc, sizeof(double));
+    or_wall_gradient(g, u, gw);
+    or_cell_gradient(g, u, gw, G);
+    viscosity_from(g, rh, theta, G, gw, eta, eta_eb, NULL);
+    memcpy(etab, etab_in, N * sizeof(double));
+    memcpy(etaebb, etaebb_in, g->ncut * sizeof(double));
+    /* V = R(DC_V) */
+    or_redistribute_adj(g, 3, Vb, DCb);
+    transpose_term_adj(g, eta, eta_eb, u, G, gw, DCb, etab, etaebb, ub, Gb, gwb);
+    viscosity_adj(g, rh, theta, G, gw, etab, etaebb, Gb, gwb, tau0b);
+    or_cell_gradient_adj(g, Gb, ub, gwb);
+    or_wall_gradient_adj(g, gwb, ub);
+    /* C = R(DC_C(u, P uf(u))) */
+    memset(DCb, 0, 3 * N * sizeof(double));
+    or_redistribute_adj(g, 3, Cb, DCb);
+    conv_adj(g, u, uf, DCb, ub, ufb);
+    int e = or_mac_project_adj(g, 1.0, ufb[0], ufb[1], ufb[2], o->rtol_mac, o->max_iter, o,
+                               iters);
+    if (e) ret = e;
+    or_face_extrap_adj(g, u, ufb[0], ufb[1], ufb[2], ub);
+    for (int d = 0; d < 3; d++) {
+        free(uf[d]);
+        free(ufb[d]);
+    }
+    free(gw); free(G); free(eta); free(eta_eb); free(etab); free(etaebb);
+    free(DCb); free(Gb); free(gwb);
+    return ret;
+}
+
+/* backward of psi = rho u + dt (rho C + V - Gcc p + f) */
+static void psi_adj(const or_geom* g, double rho, double dt, const double* psib, double* ub,
+                    double* Cb, double* Vb, double* pb) {
+    long N3 = 3 * g->N;
+    double* gpb = malloc(N3 * sizeof(double));
+    for (long q = 0; q < N3; q++) {
+        ub[q] += rho * psib[q];
+        Cb[q] += dt * rho * psib[q];
+        Vb[q] += dt * psib[q];
+        gpb[q] = -dt * psib[q];
+    }
+    or_gcc_adj(g, gpb, pb);
+    free(gpb);
+}
+
+int or_rk2_step_adjoint(const or_geom* g_in, const or_rheo* rh, const double* theta, double dt,
+                        const or_opts* o, const double* u0, const double* p0, double* ub,
+                        double* pb, double* tau0b, or_stats* st) {
+    or_geom* g = (or_geom*)g_in;
+    const int* n = g->box.n;
+    long N = g->N, N3 = 3 * N;
+    int nc = g->ncut + 1;
+    double rho = rh->rho, beta = dt / rh->rho;
+    int err = OR_OK, e, it;
+    or_stats loc;
+    memset(&loc, 0, sizeof(loc));
+    /* replay the forward step, keeping its intermediate fields */
+    rk2_tape tp;
+    for (int d = 0; d < 3; d++) {
+        tp.ufm[d] = malloc(nfaces(n, d) * 8);
+        tp.uf1[d] = malloc(nfaces(n, d) * 8);
+    }
+    tp.em = malloc(N * 8);
+    tp.ea = malloc(N * 8);
+    tp.ebm = calloc(nc, 8);
+    tp.eba = calloc(nc, 8);
+    tp.us1 = malloc(N3 * 8);
+    tp.u1 = malloc(N3 * 8);
+    tp.us2 = malloc(N3 * 8);
+    double* u = malloc(N3 * 8);
+    double* p = malloc(N * 8);
+    memcpy(u, u0, N3 * 8);
+    memcpy(p, p0, N * 8);
+    e = rk2_impl(g, rh, theta, dt, o, u, p, NULL, &tp);
+    if (e) err = e;
+    /* reverse sweep */
+    double* ubm = calloc(N3, 8); /* adjoint of u^m, accumulated */
+    double* x = malloc(N3 * 8);
+    double* pbs = malloc(N * 8);
+    double* psib = calloc(N3, 8);
+    double* Cb = calloc(N3, 8);
+    double* Vb = calloc(N3, 8);
+    double* etab = calloc(N, 8);
+    double* etaebb = calloc(nc, 8);
+    double* Ch = malloc(N3 * 8);
+    double* Vh = malloc(N3 * 8);
+    double* eh = malloc(N * 8);
+    double* ebh = calloc(nc, 8);
+    for (long q = 0; q < N3; q++) x[q] = g->alpha[q % N] > 0.0 ? ub[q] : 0.0;
+    for (long c = 0; c < N; c++) pbs[c] = g->alpha[c] > 0.0 ? pb[c] : 0.0;
+    /* corrector projection and solve */
+    e = or_cc_project_adj(g, beta, x, pbs, o->rtol_proj, o->max_iter, o, &it);
+    loc.it_proj[1] = it;
+    if (e) err = e;
+    e = visc_solve_adj(g, rho, dt, tp.ea, tp.eba, tp.us2, x, o->rtol_visc, o->max_iter, o, psib,
+                       etab, etaebb, &it);
+    loc.it_visc[1] = it;
+    if (e) err = e;
+    psi_adj(g, rho, dt, psib, ubm, Cb, Vb, pbs);
+    /* averages: both stages receive half */
+    for (long q = 0; q < N3; q++) {
+        Ch[q] = 0.5 * Cb[q];
+        Vh[q] = 0.5 * Vb[q];
+    }
+    for (long c = 0; c < N; c++) eh[c] = 0.5 * etab[c];
+    for (int c = 0; c < g->ncut; c++) ebh[c] = 0.5 * etaebb[c];
+    /* corrector derived quantities at u* */
+    memset(x, 0, N3 * 8);
+    e = or_derived_adj(g, rh, theta, tp.u1, (const double* const*)tp.uf1, o, Ch, eh, ebh, Vh, x,
+                       tau0b, &it);
+    loc.it_mac[1] = it;
+    if (e) err = e;
+    /* predictor projection and solve */
+    e = or_cc_project_adj(g, beta, x, pbs, o->rtol_proj, o->max_iter, o, &it);
+    loc.it_proj[0] = it;
+    if (e) err = e;
+    memset(psib, 0, N3 * 8);
+    e = visc_solve_adj(g, rho, dt, tp.em, tp.ebm, tp.us1, x, o->rtol_visc, o->max_iter, o, psib,
+                       eh, ebh, &it);
+    loc.it_visc[0] = it;
+    if (e) err = e;
+    memcpy(Cb, Ch, N3 * 8);
+    memcpy(Vb, Vh, N3 * 8);
+    psi_adj(g, rho, dt, psib, ubm, Cb, Vb, pbs);
+    e = or_derived_adj(g, rh, theta, u0, (const double* const*)tp.ufm, o, Cb, eh, ebh, Vb, ubm,
+                       tau0b, &it);
+    loc.it_mac[0] = it;
+    if (e) err = e;
+    for (long q = 0; q < N3; q++) ub[q] = g->alpha[q % N] > 0.0 ? ubm[q] : 0.0;
+    for (long c = 0; c < N; c++) pb[c] = g->alpha[c] > 0.0 ? pbs[c] : 0.0;
+    if (st) *st = loc;
+    for (int d = 0; d < 3; d++) {
+        free(tp.ufm[d]);
+        free(tp.uf1[d]);
+    }
+    free(tp.em); free(tp.ea); free(tp.ebm); free(tp.eba); free(tp.us1); free(tp.u1);
+    free(tp.us2); free(u); free(p); free(ubm); free(x); free(pbs); free(psib); free(Cb);
+    free(Vb); free(etab); free(etaebb); free(Ch); free(Vh); free(eh); free(ebh);
+    return err;
+}
+
+/* drag backward: Fb is d(loss)/dF; ub, pb, tau0b accumulate */
+void or_drag_adj(const or_geom* g, const or_rheo* r, const double* theta, const double* u,
+                 const double Fb[3], double* ub, double* pb, double* tau0b) {
+    long N = g->N;
+    double h = g->box.h;
+    double* gw = calloc(3 * (g->ncut + 1), sizeof(double));
+    double* gwb = calloc(3 * (g->ncut + 1), sizeof(double));
+    double* gpb = calloc(3 * N, sizeof(double));
+    or_wall_gradient(g, u, gw);
+    for (int cid = 0; cid < g->ncut; cid++) {
+        long c = g->cut[cid];
+        const double* nv = &g->nrm[3 * cid];
+        const double* gg = &gw[3 * cid];
+        double Gm[3][3], Gmb[3][3], Sb[3][3];
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) Gm[a][b] = nv[a] * gg[b];
+        double t0 = r->tau0 * (theta ? theta[c] : 1.0);
+        double sr = strain_norm(Gm);
+        double eeb = law_eta(r, t0, sr), dsr, dt0;
+        law_deriv(r, t0, sr, &dsr, &dt0);
+        double w[3], etab = 0.0, peb = 0.0;
+        for (int a = 0; a < 3; a++) w[a] = Fb[a] * g->aeb[cid] * h * h;
+        for (int a = 0; a < 3; a++) {
+            for (int b = 0; b < 3; b++) etab += w[a] * (Gm[a][b] + Gm[b][a]) * nv[b];
+            peb -= w[a] * nv[a];
+        }
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) Gmb[a][b] = 0.0;
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) {
+                Gmb[a][b] += eeb * w[a] * nv[b];
+                Gmb[b][a] += eeb * w[a] * nv[b];
+            }
+        tau0b[c] += dt0 * etab;
+        strain_norm_adj(Gm, sr, dsr * etab, Sb);
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) gwb[3 * cid + b] += nv[a] * (Gmb[a][b] + Sb[a][b]);
+        pb[c] += peb;
+        for (int d = 0; d < 3; d++) gpb[d * N + c] += h * g->bc[3 * cid + d] * peb;
+    }
+    or_wall_gradient_adj(g, gwb, ub);
+    or_gcc_adj(g, gpb, pb);
+    free(gw);
+    free(gwb);
+    free(gpb);
 }

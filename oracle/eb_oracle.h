@@ -118,6 +118,39 @@ int or_rk2_step(const or_geom* g, const or_rheo* r, const double* theta, double 
 void or_drag(const or_geom* g, const or_rheo* r, const double* theta, const double* u,
              const double* p, double F[3]);
 
+/* ---- adjoint (reverse mode): exact transposes of the linearised forward routines, solves taken
+ * as exact, switches frozen at their forward values.  Arguments ending in b are adjoints
+ * (d loss / d quantity) and accumulate unless stated otherwise. ---- */
+void or_wall_gradient_adj(const or_geom* g, const double* gwb, double* ub);
+void or_cell_gradient_adj(const or_geom* g, const double* Gb, double* ub, double* gwb);
+void or_redistribute_adj(const or_geom* g, int ncomp, const double* Db, double* DCb);
+void or_face_extrap_adj(const or_geom* g, const double* u, const double* fbx, const double* fby,
+                        const double* fbz, double* ub);
+void or_gcc_adj(const or_geom* g, const double* gpb, double* pb);
+/* in place: face adjoints of the projected field in, of the input field out */
+int or_mac_project_adj(const or_geom* g, double beta, double* fbx, double* fby, double* fbz,
+                       double rtol, int maxit, const or_opts* o, int* iters);
+/* in place: (ub, pb) of (u_new, p_new) in, of (u, p_old) out */
+int or_cc_project_adj(const or_geom* g, double beta, double* ub, double* pb, double rtol,
+                      int maxit, const or_opts* o, int* iters);
+/* x: the forward solution; xb its adjoint; psib, etab, etaebb accumulate */
+int or_visc_solve_adj(const or_geom* g, double rho, double dt, const double* eta,
+                      const double* eta_eb, const double* x, const double* xb, double rtol,
+                      int maxit, const or_opts* o, double* psib, double* etab, double* etaebb,
+                      int* iters);
+/* uf: projected face velocities of the forward (nullable: recomputed) */
+int or_derived_adj(const or_geom* g, const or_rheo* r, const double* theta, const double* u,
+                   const double* const uf[3], const or_opts* o, const double* Cb,
+                   const double* etab, const double* etaebb, const double* Vb, double* ub,
+                   double* tau0b, int* iters);
+/* (u0, p0): the step's input.  ub, pb: adjoints of the step's output on entry, of its input on
+ * exit.  tau0b[c] accumulates d loss / d tau0_c, with tau0_c = tau0 * theta[c]. */
+int or_rk2_step_adjoint(const or_geom* g, const or_rheo* r, const double* theta, double dt,
+                        const or_opts* o, const double* u0, const double* p0, double* ub,
+                        double* pb, double* tau0b, or_stats* st);
+void or_drag_adj(const or_geom* g, const or_rheo* r, const double* theta, const double* u,
+                 const double Fb[3], double* ub, double* pb, double* tau0b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -84,6 +84,19 @@ def lib():
             "or_derived": (_I, [_P, _P, _P, _P, _P, _P, _P, _P, _P, C.POINTER(C.c_int)]),
             "or_rk2_step": (_I, [_P, _P, _P, _D, _P, _P, _P, _P]),
             "or_drag": (None, [_P, _P, _P, _P, _P, _P]),
+            "or_wall_gradient_adj": (None, [_P, _P, _P]),
+            "or_cell_gradient_adj": (None, [_P, _P, _P, _P]),
+            "or_redistribute_adj": (None, [_P, _I, _P, _P]),
+            "or_face_extrap_adj": (None, [_P, _P, _P, _P, _P, _P]),
+            "or_gcc_adj": (None, [_P, _P, _P]),
+            "or_mac_project_adj": (_I, [_P, _D, _P, _P, _P, _D, _I, _P, C.POINTER(C.c_int)]),
+            "or_cc_project_adj": (_I, [_P, _D, _P, _P, _D, _I, _P, C.POINTER(C.c_int)]),
+            "or_visc_solve_adj": (_I, [_P, _D, _D, _P, _P, _P, _P, _D, _I, _P, _P, _P, _P,
+                                       C.POINTER(C.c_int)]),
+            "or_derived_adj": (_I, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                    C.POINTER(C.c_int)]),
+            "or_rk2_step_adjoint": (_I, [_P, _P, _P, _D, _P, _P, _P, _P, _P, _P, _P]),
+            "or_drag_adj": (None, [_P, _P, _P, _P, _P, _P, _P, _P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -356,6 +369,121 @@ class Geometry:
         lib().or_drag(self.g, C.byref(rheo), _ptr(theta), _ptr(np.ascontiguousarray(u)),
                       _ptr(np.ascontiguousarray(p)), _ptr(F))
         return F
+
+
+    # ---------------------------------------------------------------- adjoint (reverse mode)
+    def _c(self, a):
+        return np.array(a, dtype=np.float64, copy=True, order="C")
+
+    def wall_gradient_adj(self, gwb):
+        ub = np.zeros((3,) + self.shape)
+        g = np.zeros((max(self.ncut, 1), 3))
+        g[: self.ncut] = gwb
+        lib().or_wall_gradient_adj(self.g, _ptr(g), _ptr(ub))
+        return ub
+
+    def cell_gradient_adj(self, Gb):
+        """Adjoint of G = cell_gradient(u, gw) for fixed gw input: returns (ub, gwb)."""
+        ub = np.zeros((3,) + self.shape)
+        gwb = np.zeros((max(self.ncut, 1), 3))
+        lib().or_cell_gradient_adj(self.g, _ptr(self._c(Gb)), _ptr(ub), _ptr(gwb))
+        return ub, gwb[: self.ncut]
+
+    def cell_gradient_from(self, u, gw):
+        G = np.zeros((3, 3) + self.shape)
+        g = np.zeros((max(self.ncut, 1), 3))
+        g[: self.ncut] = gw
+        lib().or_cell_gradient(self.g, _ptr(self._c(u)), _ptr(g), _ptr(G))
+        return G
+
+    def redistribute_adj(self, Db):
+        Db = self._c(Db)
+        DCb = np.zeros_like(Db)
+        lib().or_redistribute_adj(self.g, Db.size // self.N, _ptr(Db), _ptr(DCb))
+        return DCb
+
+    def face_extrap_adj(self, u, fb):
+        ub = np.zeros((3,) + self.shape)
+        f = [self._c(a) for a in fb]
+        lib().or_face_extrap_adj(self.g, _ptr(self._c(u)), *[_ptr(a) for a in f], _ptr(ub))
+        return ub
+
+    def gcc_adj(self, gpb):
+        pb = np.zeros(self.shape)
+        lib().or_gcc_adj(self.g, _ptr(self._c(gpb)), _ptr(pb))
+        return pb
+
+    def mac_project_adj(self, fb, beta, opts, rtol=None):
+        f = [self._c(a) for a in fb]
+        it = C.c_int(0)
+        rt = opts.rtol_mac if rtol is None else rtol
+        e = lib().or_mac_project_adj(self.g, beta, *[_ptr(a) for a in f], rt, opts.max_iter,
+                                     C.byref(opts), C.byref(it))
+        if e:
+            raise OracleError(f"or_mac_project_adj: {e}")
+        return f, it.value
+
+    def cc_project_adj(self, ub, pb, beta, opts, rtol=None):
+        ub = self._c(ub)
+        pb = self._c(pb)
+        it = C.c_int(0)
+        rt = opts.rtol_proj if rtol is None else rtol
+        e = lib().or_cc_project_adj(self.g, beta, _ptr(ub), _ptr(pb), rt, opts.max_iter,
+                                    C.byref(opts), C.byref(it))
+        if e:
+            raise OracleError(f"or_cc_project_adj: {e}")
+        return ub, pb, it.value
+
+    def visc_solve_adj(self, rho, dt, eta, eta_eb, x, xb, opts, rtol=None):
+        psib = np.zeros((3,) + self.shape)
+        etab = np.zeros(self.shape)
+        etaebb = np.zeros(max(self.ncut, 1))
+        it = C.c_int(0)
+        rt = opts.rtol_visc if rtol is None else rtol
+        e = lib().or_visc_solve_adj(self.g, rho, dt, _ptr(self._c(eta)), _ptr(self._eb(eta_eb)),
+                                    _ptr(self._c(x)), _ptr(self._c(xb)), rt, opts.max_iter,
+                                    C.byref(opts), _ptr(psib), _ptr(etab), _ptr(etaebb),
+                                    C.byref(it))
+        if e:
+            raise OracleError(f"or_visc_solve_adj: {e}")
+        return psib, etab, etaebb[: self.ncut], it.value
+
+    def derived_adj(self, u, rheo, opts, Cb, etab, etaebb, Vb, theta=None):
+        ub = np.zeros((3,) + self.shape)
+        tau0b = np.zeros(self.shape)
+        it = C.c_int(0)
+        e = lib().or_derived_adj(self.g, C.byref(rheo), _ptr(theta), _ptr(self._c(u)), None,
+                                 C.byref(opts), _ptr(self._c(Cb)), _ptr(self._c(etab)),
+                                 _ptr(self._eb(etaebb)), _ptr(self._c(Vb)), _ptr(ub),
+                                 _ptr(tau0b), C.byref(it))
+        if e:
+            raise OracleError(f"or_derived_adj: {e}")
+        return ub, tau0b
+
+    def rk2_step_adjoint(self, u0, p0, rheo, dt, opts, ub, pb, theta=None):
+        """Adjoint of one step at input (u0, p0): (ub, pb) of the output in, those of the input
+        out, plus d loss / d tau0_c per cell (tau0_c = rheo.tau0 * theta_c)."""
+        ub = self._c(ub)
+        pb = self._c(pb)
+        tau0b = np.zeros(self.shape)
+        st = OrStats()
+        e = lib().or_rk2_step_adjoint(self.g, C.byref(rheo), _ptr(theta), dt, C.byref(opts),
+                                      _ptr(self._c(u0)), _ptr(self._c(p0)), _ptr(ub), _ptr(pb),
+                                      _ptr(tau0b), C.byref(st))
+        if e:
+            raise OracleError(f"or_rk2_step_adjoint: {e}")
+        stats = {"it_mac": list(st.it_mac), "it_visc": list(st.it_visc),
+                 "it_proj": list(st.it_proj)}
+        return ub, pb, tau0b, stats
+
+    def drag_adj(self, u, rheo, Fb, theta=None):
+        ub = np.zeros((3,) + self.shape)
+        pb = np.zeros(self.shape)
+        tau0b = np.zeros(self.shape)
+        fb = np.ascontiguousarray(np.asarray(Fb, dtype=np.float64))
+        lib().or_drag_adj(self.g, C.byref(rheo), _ptr(theta), _ptr(self._c(u)), _ptr(fb),
+                          _ptr(ub), _ptr(pb), _ptr(tau0b))
+        return ub, pb, tau0b
 
 
 def prepare_state(w, geom: Geometry, opts=None):
