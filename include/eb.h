@@ -213,6 +213,72 @@ int eb_drag(const eb_ctx* ctx, const eb_rheology* rheo, const double* theta, con
  * each direction; domain-wall faces carry a zero gradient).  p (device) [N], gp (device) [3][N]. */
 int eb_pressure_gradient(const eb_ctx* ctx, const double* p, double* gp, void* stream);
 
+/* ---------------------------------------------------------------------------------------
+ * Reverse mode.  The adjoint of the step is the exact transpose of the step linearised about
+ * its forward state: every solve is transposed rather than differentiated through its
+ * iterations (the Poisson systems are symmetric, the viscous system is solved with A^T and the
+ * same V-cycle), and every switch is frozen at its forward value (upwind side, slope-limiter
+ * branch, one-sided gradient stencil, wall-stencil plane).  Adjoint arrays (suffix b) hold
+ * d(loss)/d(quantity); unless stated otherwise they are (device) arrays in the layouts above
+ * and the entry point adds into them.  Adjoints of covered cells are zero on output.  The
+ * yield-stress adjoint tau0b[c] is d(loss)/d(tau0_c) with tau0_c = rheo->tau0 * theta[c]; the
+ * Bingham-number derivative follows as sum_c theta[c] tau0b[c].
+ * --------------------------------------------------------------------------------------- */
+
+/* Bytes of the (device) tape one step records for its reverse sweep: the projected face
+ * velocities and the viscosities of both stages and the velocities after each solve and
+ * projection.  Host only. */
+size_t eb_tape_bytes(const eb_ctx* ctx);
+
+/* eb_rk2_step that also fills `tape` (device, eb_tape_bytes, caller-owned) for
+ * eb_rk2_step_adjoint.  Same arguments, results and errors as eb_rk2_step. */
+int eb_rk2_step_taped(eb_ctx* ctx, const eb_rheology* rheo, const double* theta, double dt,
+                      const eb_step_opts* opts, double* u, double* p, void* tape,
+                      eb_step_stats* stats, void* stream);
+
+/* Adjoint of one RK2 step (Alg. advance).  u0 (device) [3][N]: the step's input velocity;
+ * tape: recorded by eb_rk2_step_taped from u0 with the same rheo, theta, dt and opts.
+ * ub [3][N], pb [N]: in, the adjoints of the step's output (u, p); out, those of its input
+ * (overwritten).  tau0b [N]: accumulated.  stats (host, nullable): iterations of the six
+ * transposed solves (it_mac: adjoint MAC projections, it_visc: transposed viscous solves,
+ * it_proj: adjoint end-of-stage projections).  Errors as eb_rk2_step. */
+int eb_rk2_step_adjoint(eb_ctx* ctx, const eb_rheology* rheo, const double* theta, double dt,
+                        const eb_step_opts* opts, const double* u0, const void* tape,
+                        double* ub, double* pb, double* tau0b, eb_step_stats* stats,
+                        void* stream);
+
+/* Adjoint of eb_drag (Eq. drag-force) at (u, p): fbar (host) [3] = d(loss)/dF; ub [3][N],
+ * pb [N] and tau0b [N] accumulate (pb is set to zero on covered cells). */
+int eb_drag_adjoint(const eb_ctx* ctx, const eb_rheology* rheo, const double* theta,
+                    const double* u, const double fbar[3], double* ub, double* pb,
+                    double* tau0b, void* stream);
+
+/* Adjoint of eb_mac_project on its face field: fbx, fby, fbz (device) in, the adjoint of the
+ * projected field; out, that of the input field.  One Poisson solve to rtol. */
+int eb_mac_project_adjoint(eb_ctx* ctx, double beta, double* fbx, double* fby, double* fbz,
+                           double rtol, const eb_step_opts* opts, int* iters, void* stream);
+
+/* Adjoint of eb_cc_project: ub [3][N], pb [N] in, the adjoints of (u, p) after the
+ * projection; out, those of (u, p) before it (overwritten). */
+int eb_cc_project_adjoint(eb_ctx* ctx, double beta, double* ub, double* pb, double rtol,
+                          const eb_step_opts* opts, int* iters, void* stream);
+
+/* Adjoint of eb_visc_solve at its solution x (device) [3][N] with adjoint xb [3][N]:
+ * solves A^T lam = xb (BiCGSTAB, same V-cycle preconditioner); psib [3][N] is written
+ * (= alpha lam); etab [N] and etaebb [ncut] accumulate the viscosity adjoints. */
+int eb_visc_solve_adjoint(eb_ctx* ctx, double rho, double dt, const double* eta,
+                          const double* eta_eb, const double* x, const double* xb, double rtol,
+                          const eb_step_opts* opts, double* psib, double* etab, double* etaebb,
+                          int* iters, void* stream);
+
+/* Adjoint of eb_derived at u: Cb, Vb [3][N], etab [N], etaebb [ncut] are the adjoints of its
+ * outputs; ub [3][N] and tau0b [N] accumulate.  The face velocities are recomputed (one
+ * forward MAC projection) before the adjoint one. */
+int eb_derived_adjoint(eb_ctx* ctx, const eb_rheology* rheo, const double* theta, const double* u,
+                       const double* Cb, const double* etab, const double* etaebb,
+                       const double* Vb, double* ub, double* tau0b, const eb_step_opts* opts,
+                       int* iters, void* stream);
+
 const char* eb_last_error(void);
 
 #ifdef __cplusplus

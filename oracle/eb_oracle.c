@@ -2292,10 +2292,7 @@ int or_mac_project_adj(const or_geom* g_in, double beta, double* fbx, double* fb
     double* t[3];
     for (int d = 0; d < 3; d++) t[d] = malloc(nfaces(n, d) * sizeof(double));
     face_grad_T(g, fb, y);
-    double scale = 0;
-    for (int d = 0; d < 3; d++)
-        for (long f = 0; f < nfaces(n, d); f++)
-            if (fabs(fb[d][f]) / g->box.h > scale) scale = fabs(fb[d][f]) / g->box.h;
+    double scale = vmaxabs(y, N); /* stop rule: max|r| <= rtol * max|G_f^T wb| */
     for (long c = 0; c < N; c++) y[c] = -y[c];
     /* poisson_solve solves L z = -(div - mean(div)) with zero-mean z: here div = -y */
     int ret = poisson_solve(g, beta, y, z, rtol, scale, maxit, o, iters);

@@ -19,7 +19,9 @@ __all__ = ["EbContext", "make_box", "make_body", "make_rheology", "make_opts",
            "eb_workspace_bytes", "eb_geometry_build", "eb_geometry_export",
            "eb_apparent_viscosity", "eb_viscous_apply", "eb_mg_vcycle", "eb_visc_solve",
            "eb_mac_project", "eb_cc_project", "eb_derived", "eb_rk2_step", "eb_drag",
-           "eb_pressure_gradient", "EB_FP64", "EB_MIXED", "EB_OP_HELMHOLTZ",
+           "eb_pressure_gradient", "eb_tape_bytes", "eb_rk2_step_taped", "eb_rk2_step_adjoint",
+           "eb_drag_adjoint", "eb_mac_project_adjoint", "eb_cc_project_adjoint",
+           "eb_visc_solve_adjoint", "eb_derived_adjoint", "EB_FP64", "EB_MIXED", "EB_OP_HELMHOLTZ",
            "EB_OP_HELMHOLTZ_H", "EB_OP_TRANSPOSE", "EB_SYS_POISSON", "EB_SYS_VISC"]
 
 
@@ -273,10 +275,13 @@ def eb_rk2_step(ctx: EbContext, rheo: EbRheology, dt, opts: EbStepOpts, u, p, th
                                C.byref(st), _stream(ctx.device))
     if not (allow_noconv and code == L.EB_ENOCONV):
         check(code, "eb_rk2_step")
-    stats = {"it_mac": list(st.it_mac), "it_visc": list(st.it_visc),
-             "it_proj": list(st.it_proj), "div_proj": list(st.div_proj),
-             "vcycles": st.vcycles, "status": st.status}
-    return u, p, stats
+    return u, p, _stats(st)
+
+
+def _stats(st):
+    return {"it_mac": list(st.it_mac), "it_visc": list(st.it_visc),
+            "it_proj": list(st.it_proj), "div_proj": list(st.div_proj),
+            "vcycles": st.vcycles, "status": st.status}
 
 
 def eb_drag(ctx: EbContext, rheo: EbRheology, u, p, theta=None):
@@ -292,3 +297,119 @@ def eb_pressure_gradient(ctx: EbContext, p):
     check(L.lib().eb_pressure_gradient(ctx.ptr, _f64(p, ctx.shape, "p"), _p(gp),
                                        _stream(ctx.device)), "eb_pressure_gradient")
     return gp
+
+
+# ----------------------------------------------------------------------------------------------
+# reverse mode
+# ----------------------------------------------------------------------------------------------
+def eb_tape_bytes(ctx: EbContext) -> int:
+    return int(L.lib().eb_tape_bytes(ctx.ptr))
+
+
+def new_tape(ctx: EbContext):
+    return torch.empty(eb_tape_bytes(ctx), dtype=torch.uint8, device=ctx.device)
+
+
+def eb_rk2_step_taped(ctx: EbContext, rheo: EbRheology, dt, opts: EbStepOpts, u, p, tape,
+                      theta=None, inplace=False):
+    """eb_rk2_step that records the step's tape (a uint8 tensor of eb_tape_bytes)."""
+    if not inplace:
+        u = u.clone().contiguous()
+        p = p.clone().contiguous()
+    if tape.numel() < eb_tape_bytes(ctx):
+        raise ValueError("tape smaller than eb_tape_bytes")
+    st = EbStepStats()
+    th = _f64(theta, ctx.shape, "theta") if theta is not None else None
+    check(L.lib().eb_rk2_step_taped(ctx.ptr, C.byref(rheo), th, float(dt), C.byref(opts),
+                                    _f64(u, (3,) + ctx.shape, "u"), _f64(p, ctx.shape, "p"),
+                                    _p(tape), C.byref(st), _stream(ctx.device)),
+          "eb_rk2_step_taped")
+    return u, p, _stats(st)
+
+
+def eb_rk2_step_adjoint(ctx: EbContext, rheo: EbRheology, dt, opts: EbStepOpts, u0, tape, ub,
+                        pb, theta=None, tau0b=None):
+    """Adjoint of the step taped from u0.  Returns (ub_in, pb_in, tau0b, stats); tau0b is
+    accumulated into the given tensor when one is passed."""
+    ub = ub.clone().contiguous()
+    pb = pb.clone().contiguous()
+    tb = ctx.scalar() if tau0b is None else tau0b
+    st = EbStepStats()
+    th = _f64(theta, ctx.shape, "theta") if theta is not None else None
+    check(L.lib().eb_rk2_step_adjoint(ctx.ptr, C.byref(rheo), th, float(dt), C.byref(opts),
+                                      _f64(u0, (3,) + ctx.shape, "u0"), _p(tape),
+                                      _f64(ub, (3,) + ctx.shape, "ub"),
+                                      _f64(pb, ctx.shape, "pb"), _f64(tb, ctx.shape, "tau0b"),
+                                      C.byref(st), _stream(ctx.device)), "eb_rk2_step_adjoint")
+    return ub, pb, tb, _stats(st)
+
+
+def eb_drag_adjoint(ctx: EbContext, rheo: EbRheology, u, fbar, theta=None, ub=None, pb=None,
+                    tau0b=None):
+    """Adjoint of eb_drag at u; (ub, pb, tau0b) accumulate into the tensors given (or zeros)."""
+    ub = ctx.vec() if ub is None else ub
+    pb = ctx.scalar() if pb is None else pb
+    tb = ctx.scalar() if tau0b is None else tau0b
+    fb = (C.c_double * 3)(*[float(x) for x in fbar])
+    th = _f64(theta, ctx.shape, "theta") if theta is not None else None
+    check(L.lib().eb_drag_adjoint(ctx.ptr, C.byref(rheo), th, _f64(u, (3,) + ctx.shape, "u"), fb,
+                                  _f64(ub, (3,) + ctx.shape, "ub"), _f64(pb, ctx.shape, "pb"),
+                                  _f64(tb, ctx.shape, "tau0b"), _stream(ctx.device)),
+          "eb_drag_adjoint")
+    return ub, pb, tb
+
+
+def eb_mac_project_adjoint(ctx: EbContext, fb, beta, opts: EbStepOpts, rtol=None):
+    f = [a.clone().contiguous() for a in fb]
+    for a, s in zip(f, ctx.face_shapes):
+        _f64(a, s, "face")
+    it = C.c_int(0)
+    rt = opts.rtol_mac if rtol is None else rtol
+    check(L.lib().eb_mac_project_adjoint(ctx.ptr, float(beta), _p(f[0]), _p(f[1]), _p(f[2]),
+                                         float(rt), C.byref(opts), C.byref(it),
+                                         _stream(ctx.device)), "eb_mac_project_adjoint")
+    return f, it.value
+
+
+def eb_cc_project_adjoint(ctx: EbContext, ub, pb, beta, opts: EbStepOpts, rtol=None):
+    ub = ub.clone().contiguous()
+    pb = pb.clone().contiguous()
+    it = C.c_int(0)
+    rt = opts.rtol_proj if rtol is None else rtol
+    check(L.lib().eb_cc_project_adjoint(ctx.ptr, float(beta), _f64(ub, (3,) + ctx.shape, "ub"),
+                                        _f64(pb, ctx.shape, "pb"), float(rt), C.byref(opts),
+                                        C.byref(it), _stream(ctx.device)),
+          "eb_cc_project_adjoint")
+    return ub, pb, it.value
+
+
+def eb_visc_solve_adjoint(ctx: EbContext, rho, dt, eta, eta_eb, x, xb, opts: EbStepOpts,
+                          rtol=None):
+    psib = ctx.vec()
+    etab = ctx.scalar()
+    etaebb = ctx.zeros(max(ctx.ncut, 1))
+    it = C.c_int(0)
+    rt = opts.rtol_visc if rtol is None else rtol
+    check(L.lib().eb_visc_solve_adjoint(ctx.ptr, float(rho), float(dt),
+                                        _f64(eta, ctx.shape, "eta"), _p(_eb_arr(ctx, eta_eb)),
+                                        _f64(x, (3,) + ctx.shape, "x"),
+                                        _f64(xb, (3,) + ctx.shape, "xb"), float(rt),
+                                        C.byref(opts), _p(psib), _p(etab), _p(etaebb),
+                                        C.byref(it), _stream(ctx.device)),
+          "eb_visc_solve_adjoint")
+    return psib, etab, etaebb[: ctx.ncut], it.value
+
+
+def eb_derived_adjoint(ctx: EbContext, rheo: EbRheology, u, opts: EbStepOpts, Cb, etab, etaebb,
+                       Vb, theta=None):
+    ub = ctx.vec()
+    tb = ctx.scalar()
+    it = C.c_int(0)
+    th = _f64(theta, ctx.shape, "theta") if theta is not None else None
+    check(L.lib().eb_derived_adjoint(ctx.ptr, C.byref(rheo), th, _f64(u, (3,) + ctx.shape, "u"),
+                                     _f64(Cb, (3,) + ctx.shape, "Cb"),
+                                     _f64(etab, ctx.shape, "etab"), _p(_eb_arr(ctx, etaebb)),
+                                     _f64(Vb, (3,) + ctx.shape, "Vb"), _p(ub), _p(tb),
+                                     C.byref(opts), C.byref(it), _stream(ctx.device)),
+          "eb_derived_adjoint")
+    return ub, tb, it.value

@@ -7,8 +7,11 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "eb_internal.hpp"
 
@@ -80,6 +83,12 @@ struct eb_ctx {
     // pinned host words for the lagged convergence poll, and their events
     int* pin;
     hipEvent_t ev[2];
+    // adjoint: transposed wall stencil and reverse-sweep arrays
+    int *wt_map, *wt_ptr, *wt_ent;
+    WallT wt;
+    double *Gb, *ubm, *lam, *ehb, *ebhb, *rX, *rY, *gwb;
+    double* ufb[3];
+    LRV lr;
 };
 
 namespace {
@@ -189,7 +198,84 @@ size_t carve(eb_ctx* c, char* base, bool dry) {
     for (int d = 0; d < 3; d++) c->f[d] = cv.take<double>(face_count(g, d));
     for (int t = 0; t < 10; t++) c->kv[t] = cv.take<double>(3 * N);
     for (int t = 0; t < 4; t++) c->pk[t] = cv.take<double>(N);
+    c->wt_map = cv.take<int>(N);
+    c->wt_ptr = cv.take<int>(18 * M + 1);
+    c->wt_ent = cv.take<int>(18 * M);
+    c->Gb = cv.take<double>(9 * N);
+    c->ubm = cv.take<double>(3 * N);
+    c->lam = cv.take<double>(3 * N);
+    c->ehb = cv.take<double>(N);
+    c->ebhb = cv.take<double>(M);
+    c->rX = cv.take<double>(3 * M);
+    c->rY = cv.take<double>(3 * M);
+    c->gwb = cv.take<double>(3 * M);
+    for (int d = 0; d < 3; d++) {
+        c->ufb[d] = cv.take<double>(face_count(g, d));
+        c->lr.L[d] = cv.take<double>(3 * face_count(g, d));
+        c->lr.R[d] = cv.take<double>(3 * face_count(g, d));
+    }
     return cv.used + 256;
+}
+
+// Intermediate fields of one step kept for the reverse sweep (a caller-owned device buffer).
+struct TapeV {
+    double* ufm[3];  // projected face velocities of the predictor
+    double* uf1[3];  // and of the corrector
+    double *em, *ea;   // viscosity of the predictor and averaged (corrector) operators
+    double *ebm, *eba; // their wall viscosities
+    double *us1, *u1, *us2;  // predictor solve, projected u*, corrector solve
+};
+
+size_t tape_carve(const eb_ctx* c, char* base, TapeV* t) {
+    Carver cv{base, 0, base == nullptr};
+    long N = c->N;
+    long M = c->ncut > 0 ? c->ncut : 1;
+    for (int d = 0; d < 3; d++) t->ufm[d] = cv.take<double>(face_count(c->grid, d));
+    for (int d = 0; d < 3; d++) t->uf1[d] = cv.take<double>(face_count(c->grid, d));
+    t->em = cv.take<double>(N);
+    t->ea = cv.take<double>(N);
+    t->ebm = cv.take<double>(M);
+    t->eba = cv.take<double>(M);
+    t->us1 = cv.take<double>(3 * N);
+    t->u1 = cv.take<double>(3 * N);
+    t->us2 = cv.take<double>(3 * N);
+    return cv.used;
+}
+
+// transposed wall stencil, built on the host from the device stencil (once per geometry):
+// entries sorted by (cell, flat position) so every gather sums in a fixed order
+int build_wall_transpose(eb_ctx* c) {
+    int nc = c->ncut;
+    long N = c->N;
+    std::vector<int> sidx((size_t)18 * nc);
+    std::vector<int> map(N, -1);
+    std::vector<int> ptr(1, 0), ent;
+    if (nc > 0) {
+        hipMemcpy(sidx.data(), c->sidx, sidx.size() * sizeof(int), hipMemcpyDeviceToHost);
+        std::vector<std::pair<int, int>> pairs;
+        pairs.reserve(sidx.size());
+        for (size_t e = 0; e < sidx.size(); e++)
+            if (sidx[e] >= 0) pairs.emplace_back(sidx[e], (int)e);
+        std::sort(pairs.begin(), pairs.end());
+        ent.reserve(pairs.size());
+        for (size_t t = 0; t < pairs.size(); t++) {
+            if (t == 0 || pairs[t].first != pairs[t - 1].first) {
+                if (t > 0) ptr.push_back((int)t);
+                map[pairs[t].first] = (int)ptr.size() - 1;
+            }
+            ent.push_back(pairs[t].second);
+        }
+        ptr.push_back((int)pairs.size());
+        if (pairs.empty()) ptr.assign(1, 0);
+    }
+    hipMemcpy(c->wt_map, map.data(), N * sizeof(int), hipMemcpyHostToDevice);
+    hipMemcpy(c->wt_ptr, ptr.data(), ptr.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (!ent.empty())
+        hipMemcpy(c->wt_ent, ent.data(), ent.size() * sizeof(int), hipMemcpyHostToDevice);
+    c->wt.map = c->wt_map;
+    c->wt.ptr = c->wt_ptr;
+    c->wt.ent = c->wt_ent;
+    return hip_check("wall stencil transpose");
 }
 
 void rotation_zyx(const double e[3], double R[3][3]) {
@@ -394,25 +480,39 @@ void cc_project(eb_ctx* c, double beta, double* u, double* p, double rtol, const
 
 // BiCGSTAB on the three-component system, right-preconditioned by the viscous V-cycle; the
 // slot's count holds half-iterations (= V-cycles)
+//
+// transposed: solve A^T x = psi instead (psi is then the right-hand side itself, already zero
+// on covered cells; x starts from zero).  The V-cycle preconditioner is symmetric, so the same
+// hierarchy serves both systems.
 void visc_solve(eb_ctx* c, double rho, double dt, const double* eta, const double* eta_eb,
-                const double* psi, double* x, double rtol, const SolveCfg& k, int slot) {
+                const double* psi, double* x, double rtol, const SolveCfg& k, int slot,
+                bool transposed = false) {
     long N3 = 3 * c->N;
     double *r = c->kv[0], *rh = c->kv[1], *p = c->kv[2], *v = c->kv[3], *ph = c->kv[4],
            *sv = c->kv[5], *sh = c->kv[6], *t = c->kv[7], *b = c->kv[8], *a0 = c->kv[9];
     double* ks = c->ks;
     int* st = c->kst + 2 * slot;
+    auto apply = [&](const double* in, double* out, const int* gate) {
+        if (transposed) adj_visc_apply_T(c->g, rho, dt, eta, eta_eb, c->wt, in, out, c->s, gate);
+        else op_visc_apply(c->g, rho, dt, eta, eta_eb, in, out, 1, c->s, gate);
+    };
     mg_build_visc(c->lev, c->nlev, c->g, rho, dt, eta, eta_eb, k.mixed, c->s);
     c->built_sys = EB_SYS_VISC;
     c->built_mixed = k.mixed;
-    // effective right-hand side: alpha psi minus the boundary part A(0)
-    vec_fill(N3, 0.0, t, c->s);
-    op_visc_apply(c->g, rho, dt, eta, eta_eb, t, a0, 0, c->s);
-    vec_mask_rhs(c->g, psi, a0, b, c->s);
+    if (transposed) {
+        vec_copy(N3, psi, b, c->s);
+        vec_fill(N3, 0.0, x, c->s);
+    } else {
+        // effective right-hand side: alpha psi minus the boundary part A(0)
+        vec_fill(N3, 0.0, t, c->s);
+        op_visc_apply(c->g, rho, dt, eta, eta_eb, t, a0, 0, c->s);
+        vec_mask_rhs(c->g, psi, a0, b, c->s);
+    }
     red_maxabs(N3, 1, b, c->part, ks + KS_BN, c->s);
     ks_set(ks, KS_SCALE, 0.0, c->s);
     ks_set(ks, KS_RTOL, rtol, c->s);
     // r = b - A_lin(x)
-    op_visc_apply(c->g, rho, dt, eta, eta_eb, x, t, 1, c->s);
+    apply(x, t, nullptr);
     vec_sub_scaled(N3, b, 1.0, t, r, c->s);
     red_maxabs(N3, 1, r, c->part, ks + KS_RN, c->s);
     ks_op(KS_INIT, ks, st, 0, c->s);
@@ -426,7 +526,7 @@ void visc_solve(eb_ctx* c, double rho, double dt, const double* eta, const doubl
         ks_op(KS_BI_BETA, ks, st, it, c->s);
         ks_bi_p(N3, p, r, v, ks, st, c->s);
         vcyc(c, 3, k, p, ph, st);
-        op_visc_apply(c->g, rho, dt, eta, eta_eb, ph, v, 1, c->s, st);
+        apply(ph, v, st);
         const double* Av[4] = {rh, nullptr, nullptr, nullptr};
         const double* Bv[4] = {v, nullptr, nullptr, nullptr};
         red_dots(N3, 1, Av, Bv, c->part, ks + KS_RV, c->s, st);
@@ -437,7 +537,7 @@ void visc_solve(eb_ctx* c, double rho, double dt, const double* eta, const doubl
         ks_bi_xs(N3, x, ph, ks, st, c->s);
         ks_op(KS_BI_FINISH_S, ks, st, it, c->s);
         vcyc(c, 3, k, sv, sh, st);
-        op_visc_apply(c->g, rho, dt, eta, eta_eb, sh, t, 1, c->s, st);
+        apply(sh, t, st);
         const double* A2[4] = {t, t, nullptr, nullptr};
         const double* B2[4] = {sv, t, nullptr, nullptr};
         red_dots(N3, 2, A2, B2, c->part, ks + KS_TS, c->s, st);
@@ -482,6 +582,70 @@ int derived(eb_ctx* c, const eb_rheology& rh, const double* theta, const double*
     op_transpose_dc(c->g, u, c->G9, eta, eta_eb, c->gw, c->DC, c->s);
     op_redistribute(c->g, c->DC, c->DH, c->rS, c->rdD, V, c->s);
     return hip_check("derived");
+}
+
+// ------------------------------------------------------------------------------------------
+// reverse sweep.  Each helper is the adjoint of the forward helper of the same name; solves
+// are transposed (the Poisson matrix is symmetric, the viscous one is not), never
+// differentiated through their iterations.
+// ------------------------------------------------------------------------------------------
+// MAC projection: fb += beta D^T L^+ G_f^T fb   (fb in place)
+void mac_project_adj(eb_ctx* c, double beta, double* fb[3], double rtol, const SolveCfg& k,
+                     int slot) {
+    adj_face_grad_T_neg(c->g, fb, c->div, c->s);
+    red_maxabs(c->N, 1, c->div, c->part, c->ks + KS_SCALE, c->s);
+    ks_set(c->ks, KS_RTOL, rtol, c->s);
+    vec_fill(c->N, 0.0, c->phi, c->s);
+    poisson_solve(c, beta, c->div, c->phi, k, slot);
+    adj_div_T_add(c->g, beta, c->phi, fb, c->s);
+}
+
+// end-of-stage projection: (ub, pb) of (u_new, p_new) in, of (u, p_old) out
+void cc_project_adj(eb_ctx* c, double beta, double* ub, double* pb, double rtol,
+                    const SolveCfg& k, int slot) {
+    // phib = pb - beta Gcc^T ub, stored negated for the Poisson solve (which returns L^+ phib)
+    adj_gcc_T(c->g, -beta, ub, pb, c->div, c->s);
+    adj_scale(c->N, -1.0, c->div, c->s);
+    red_maxabs(c->N, 1, c->div, c->part, c->ks + KS_SCALE, c->s);
+    ks_set(c->ks, KS_RTOL, rtol, c->s);
+    vec_fill(c->N, 0.0, c->phi, c->s);
+    poisson_solve(c, beta, c->div, c->phi, k, slot);
+    adj_cc_cell(c->g, c->phi, ub, c->s);
+    adj_gcc_T(c->g, beta, ub, nullptr, pb, c->s);
+}
+
+// implicit viscous solve: lam = A^-T xb (in c->lam); etab, etaebb (acc)
+void visc_solve_adj(eb_ctx* c, double rho, double dt, const double* eta, const double* eta_eb,
+                    const double* x, const double* xb, double rtol, const SolveCfg& k, int slot,
+                    double* etab, double* etaebb) {
+    adj_mask_open(c->g, 3, xb, c->gp, c->s);
+    visc_solve(c, rho, dt, eta, eta_eb, c->gp, c->lam, rtol, k, slot, true);
+    adj_visc_coef(c->g, dt, x, c->lam, etab, etaebb, c->s);
+}
+
+// derived quantities at u; uf: the projected face velocities of the forward pass
+void derived_adj(eb_ctx* c, const eb_rheology& rh, const double* theta, const double* u,
+                 double* const uf[3], const double* Cb, const double* etab,
+                 const double* etaebb, const double* Vb, double* ub, double* tau0b, double rtol,
+                 const SolveCfg& k, int slot) {
+    const GeomV& g = c->g;
+    op_wall_grad(g, u, c->gw, c->s);
+    op_grad_eta(g, rh, u, c->gw, theta, c->G9, c->eta0, nullptr, c->s);
+    op_eta_eb(g, rh, c->gw, theta, c->eb0, c->s);
+    adj_redistribute(g, Vb, c->rX, c->rY, c->DC, c->s);
+    adj_visc_terms(g, rh, theta, u, c->G9, c->eta0, c->eb0, c->gw, c->DC, etab, etaebb, ub, c->Gb,
+                   c->gwb, tau0b, c->s);
+    adj_grad_gather(g, c->wt, c->Gb, c->gwb, ub, c->s);
+    adj_redistribute(g, Cb, c->rX, c->rY, c->DC, c->s);
+    adj_conv_face_w(g, u, uf, c->DC, c->ufb, c->s);
+    mac_project_adj(c, 1.0, c->ufb, rtol, k, slot);
+    adj_conv_lr(g, u, uf, c->DC, c->ufb, c->lr, ub, c->s);
+}
+
+// psi = rho u + dt (rho C + V - Gcc p + f): from lam = A^-T xb
+void psi_adj(eb_ctx* c, double rho, double dt, double* ub, double* Cb, double* Vb, double* pb) {
+    adj_psi(c->g, rho, dt, c->lam, c->psi, ub, Cb, Vb, c->s);
+    adj_gcc_T(c->g, -dt, c->psi, pb, pb, c->s);
 }
 
 }  // namespace
@@ -568,6 +732,11 @@ int eb_geometry_build(const eb_box* box, const eb_body* body, void* ws, size_t w
                        hipGetErrorString(hipGetLastError()));
     }
     hipMemsetAsync(c->kst, 0, 2 * NSLOT * sizeof(int), c->s);
+    hipStreamSynchronize(c->s);
+    if ((e = build_wall_transpose(c))) {
+        eb_ctx_destroy(c);
+        return e;
+    }
     *out = c;
     return EB_OK;
 }
@@ -759,48 +928,23 @@ int eb_derived(eb_ctx* c, const eb_rheology* rheo, const double* theta, const do
     return slot_code(sl, "MAC projection", cfg_of(opts).max_iter);
 }
 
-int eb_rk2_step(eb_ctx* c, const eb_rheology* rheo, const double* theta, double dt,
-                const eb_step_opts* o, double* u, double* p, eb_step_stats* stats,
-                void* stream) {
-    if (!c || !rheo || !o || !u || !p) return set_err(EB_EINVAL, "null argument");
-    if (!(rheo->rho > 0.0) || !(dt > 0.0)) return set_err(EB_EINVAL, "rho and dt must be > 0");
-    c->s = (hipStream_t)stream;
-    SolveCfg k = cfg_of(o);
-    long N = c->N, N3 = 3 * N;
-    double rho = rheo->rho, beta = dt / rho;
-    int h;
-    // slots: 0/3 MAC projection, 1/4 viscous solve, 2/5 end-of-stage projection
-    // predictor: derived quantities at u^m
-    if ((h = derived(c, *rheo, theta, u, o, c->C0, c->eta0, c->eb0, c->V0, 0))) return h;
-    op_gcc(c->g, p, c->gp, c->s);
-    op_psi(c->g, rho, dt, u, c->C0, c->V0, c->gp, o->force, c->psi, c->s);
-    vec_copy(N3, u, c->u1, c->s);
-    visc_solve(c, rho, dt, c->eta0, c->eb0, c->psi, c->u1, o->rtol_visc, k, 1);
-    vec_copy(N, p, c->p1, c->s);
-    cc_project(c, beta, c->u1, c->p1, o->rtol_proj, k, 2, true);
-    // corrector: derived quantities at u*, averaged with the predictor's
-    if ((h = derived(c, *rheo, theta, c->u1, o, c->C1, c->eta1, c->eb1, c->V1, 3))) return h;
-    op_average(N3, c->C1, c->C0, c->s);
-    op_average(N3, c->V1, c->V0, c->s);
-    op_average(N, c->eta1, c->eta0, c->s);
-    op_average(c->ncut, c->eb1, c->eb0, c->s);
-    op_gcc(c->g, c->p1, c->gp, c->s);
-    op_psi(c->g, rho, dt, u, c->C0, c->V0, c->gp, o->force, c->psi, c->s);
-    visc_solve(c, rho, dt, c->eta0, c->eb0, c->psi, c->u1, o->rtol_visc, k, 4);
-    cc_project(c, beta, c->u1, c->p1, o->rtol_proj, k, 5, true);
-    vec_copy(N3, c->u1, u, c->s);
-    vec_copy(N, c->p1, p, c->s);
-    op_finalize_state(c->g, u, p, c->s);
-    if ((h = hip_check("eb_rk2_step"))) return h;
-    // one read-back for the whole step
+}  // extern "C"
+
+namespace {
+
+// stats and return code of a step (forward or reverse) from its six solve slots
+int step_status(eb_ctx* c, const SolveCfg& k, eb_step_stats* stats, bool adjoint) {
     int sl[12];
     double dv[6];
+    int h;
     if ((h = read_slots(c, 6, sl))) return h;
     hipMemcpy(dv, c->divs, 6 * sizeof(double), hipMemcpyDeviceToHost);
     eb_step_stats st;
     memset(&st, 0, sizeof(st));
     int status = EB_OK;
-    const char* names[3] = {"MAC projection", "viscous solve", "projection"};
+    const char* names[2][3] = {{"MAC projection", "viscous solve", "projection"},
+                               {"adjoint MAC projection", "transposed viscous solve",
+                                "adjoint projection"}};
     for (int q = 0; q < 6; q++) {
         int cnt = sl[2 * q + 1];
         int stage = q / 3, kind = q % 3;
@@ -808,14 +952,140 @@ int eb_rk2_step(eb_ctx* c, const eb_rheology* rheo, const double* theta, double 
         if (kind == 1) st.it_visc[stage] = (cnt + 1) / 2;
         if (kind == 2) {
             st.it_proj[stage] = cnt;
-            st.div_proj[stage] = dv[q];
+            st.div_proj[stage] = adjoint ? 0.0 : dv[q];
         }
         st.vcycles += cnt;
-        if (status == EB_OK && sl[2 * q] != 2) status = slot_code(&sl[2 * q], names[kind], k.max_iter);
+        if (status == EB_OK && sl[2 * q] != 2)
+            status = slot_code(&sl[2 * q], names[adjoint][kind], k.max_iter);
     }
     st.status = status;
     if (stats) *stats = st;
     return status;
+}
+
+int rk2_impl(eb_ctx* c, const eb_rheology* rheo, const double* theta, double dt,
+             const eb_step_opts* o, double* u, double* p, eb_step_stats* stats, TapeV* tp) {
+    if (!c || !rheo || !o || !u || !p) return set_err(EB_EINVAL, "null argument");
+    if (!(rheo->rho > 0.0) || !(dt > 0.0)) return set_err(EB_EINVAL, "rho and dt must be > 0");
+    SolveCfg k = cfg_of(o);
+    long N = c->N, N3 = 3 * N;
+    int nc = c->ncut;
+    double rho = rheo->rho, beta = dt / rho;
+    int h;
+    // slots: 0/3 MAC projection, 1/4 viscous solve, 2/5 end-of-stage projection
+    // predictor: derived quantities at u^m
+    if ((h = derived(c, *rheo, theta, u, o, c->C0, c->eta0, c->eb0, c->V0, 0))) return h;
+    if (tp) {
+        for (int d = 0; d < 3; d++) vec_copy(face_count(c->grid, d), c->f[d], tp->ufm[d], c->s);
+        vec_copy(N, c->eta0, tp->em, c->s);
+        if (nc > 0) vec_copy(nc, c->eb0, tp->ebm, c->s);
+    }
+    op_gcc(c->g, p, c->gp, c->s);
+    op_psi(c->g, rho, dt, u, c->C0, c->V0, c->gp, o->force, c->psi, c->s);
+    vec_copy(N3, u, c->u1, c->s);
+    visc_solve(c, rho, dt, c->eta0, c->eb0, c->psi, c->u1, o->rtol_visc, k, 1);
+    if (tp) vec_copy(N3, c->u1, tp->us1, c->s);
+    vec_copy(N, p, c->p1, c->s);
+    cc_project(c, beta, c->u1, c->p1, o->rtol_proj, k, 2, true);
+    if (tp) vec_copy(N3, c->u1, tp->u1, c->s);
+    // corrector: derived quantities at u*, averaged with the predictor's
+    if ((h = derived(c, *rheo, theta, c->u1, o, c->C1, c->eta1, c->eb1, c->V1, 3))) return h;
+    if (tp)
+        for (int d = 0; d < 3; d++) vec_copy(face_count(c->grid, d), c->f[d], tp->uf1[d], c->s);
+    op_average(N3, c->C1, c->C0, c->s);
+    op_average(N3, c->V1, c->V0, c->s);
+    op_average(N, c->eta1, c->eta0, c->s);
+    op_average(nc, c->eb1, c->eb0, c->s);
+    if (tp) {
+        vec_copy(N, c->eta0, tp->ea, c->s);
+        if (nc > 0) vec_copy(nc, c->eb0, tp->eba, c->s);
+    }
+    op_gcc(c->g, c->p1, c->gp, c->s);
+    op_psi(c->g, rho, dt, u, c->C0, c->V0, c->gp, o->force, c->psi, c->s);
+    visc_solve(c, rho, dt, c->eta0, c->eb0, c->psi, c->u1, o->rtol_visc, k, 4);
+    if (tp) vec_copy(N3, c->u1, tp->us2, c->s);
+    cc_project(c, beta, c->u1, c->p1, o->rtol_proj, k, 5, true);
+    vec_copy(N3, c->u1, u, c->s);
+    vec_copy(N, c->p1, p, c->s);
+    op_finalize_state(c->g, u, p, c->s);
+    if ((h = hip_check("eb_rk2_step"))) return h;
+    // one read-back for the whole step
+    return step_status(c, k, stats, false);
+}
+
+}  // namespace
+
+extern "C" {
+
+int eb_rk2_step(eb_ctx* c, const eb_rheology* rheo, const double* theta, double dt,
+                const eb_step_opts* o, double* u, double* p, eb_step_stats* stats,
+                void* stream) {
+    if (!c) return set_err(EB_EINVAL, "null context");
+    c->s = (hipStream_t)stream;
+    return rk2_impl(c, rheo, theta, dt, o, u, p, stats, nullptr);
+}
+
+size_t eb_tape_bytes(const eb_ctx* c) {
+    if (!c) return 0;
+    TapeV t;
+    return tape_carve(c, nullptr, &t);
+}
+
+int eb_rk2_step_taped(eb_ctx* c, const eb_rheology* rheo, const double* theta, double dt,
+                      const eb_step_opts* o, double* u, double* p, void* tape,
+                      eb_step_stats* stats, void* stream) {
+    if (!c || !tape) return set_err(EB_EINVAL, "null context or tape");
+    c->s = (hipStream_t)stream;
+    TapeV t;
+    tape_carve(c, (char*)tape, &t);
+    return rk2_impl(c, rheo, theta, dt, o, u, p, stats, &t);
+}
+
+int eb_rk2_step_adjoint(eb_ctx* c, const eb_rheology* rheo, const double* theta, double dt,
+                        const eb_step_opts* o, const double* u0, const void* tape, double* ub,
+                        double* pb, double* tau0b, eb_step_stats* stats, void* stream) {
+    if (!c || !rheo || !o || !u0 || !tape || !ub || !pb || !tau0b)
+        return set_err(EB_EINVAL, "null argument");
+    if (!(rheo->rho > 0.0) || !(dt > 0.0)) return set_err(EB_EINVAL, "rho and dt must be > 0");
+    c->s = (hipStream_t)stream;
+    TapeV t;
+    tape_carve(c, (char*)const_cast<void*>(tape), &t);
+    SolveCfg k = cfg_of(o);
+    const GeomV& g = c->g;
+    long N = c->N, N3 = 3 * N;
+    int nc = c->ncut;
+    double rho = rheo->rho, beta = dt / rho;
+    double rt_mac = o->rtol_mac > 0 ? o->rtol_mac : 1e-12;
+    double *x = c->u1, *pbs = c->p1, *Cb = c->C0, *Vb = c->V0;
+    vec_fill(N3, 0.0, c->ubm, c->s);
+    vec_fill(N3, 0.0, Cb, c->s);
+    vec_fill(N3, 0.0, Vb, c->s);
+    vec_fill(N, 0.0, c->ehb, c->s);
+    if (nc > 0) vec_fill(nc, 0.0, c->ebhb, c->s);
+    adj_mask_open(g, 3, ub, x, c->s);
+    adj_mask_open(g, 1, pb, pbs, c->s);
+    // corrector: projection, viscous solve, psi
+    cc_project_adj(c, beta, x, pbs, o->rtol_proj, k, 5);
+    visc_solve_adj(c, rho, dt, t.ea, t.eba, t.us2, x, o->rtol_visc, k, 4, c->ehb, c->ebhb);
+    psi_adj(c, rho, dt, c->ubm, Cb, Vb, pbs);
+    // the averaged operator and explicit terms: half to each stage
+    adj_scale(N3, 0.5, Cb, c->s);
+    adj_scale(N3, 0.5, Vb, c->s);
+    adj_scale(N, 0.5, c->ehb, c->s);
+    adj_scale(nc, 0.5, c->ebhb, c->s);
+    vec_fill(N3, 0.0, x, c->s);
+    derived_adj(c, *rheo, theta, t.u1, t.uf1, Cb, c->ehb, c->ebhb, Vb, x, tau0b, rt_mac, k, 3);
+    // predictor
+    cc_project_adj(c, beta, x, pbs, o->rtol_proj, k, 2);
+    visc_solve_adj(c, rho, dt, t.em, t.ebm, t.us1, x, o->rtol_visc, k, 1, c->ehb, c->ebhb);
+    psi_adj(c, rho, dt, c->ubm, Cb, Vb, pbs);
+    derived_adj(c, *rheo, theta, u0, t.ufm, Cb, c->ehb, c->ebhb, Vb, c->ubm, tau0b, rt_mac, k,
+                0);
+    adj_mask_open(g, 3, c->ubm, ub, c->s);
+    adj_mask_open(g, 1, pbs, pb, c->s);
+    int h;
+    if ((h = hip_check("eb_rk2_step_adjoint"))) return h;
+    return step_status(c, k, stats, true);
 }
 
 int eb_drag(const eb_ctx* cc, const eb_rheology* rheo, const double* theta, const double* u,
@@ -832,6 +1102,102 @@ int eb_drag(const eb_ctx* cc, const eb_rheology* rheo, const double* theta, cons
     int e = fetch(c, F, 3);
     if (e) return e;
     return hip_check("eb_drag");
+}
+
+int eb_drag_adjoint(const eb_ctx* cc, const eb_rheology* rheo, const double* theta,
+                    const double* u, const double fbar[3], double* ub, double* pb,
+                    double* tau0b, void* stream) {
+    eb_ctx* c = const_cast<eb_ctx*>(cc);
+    if (!c || !rheo || !u || !fbar || !ub || !pb || !tau0b)
+        return set_err(EB_EINVAL, "null argument");
+    c->s = (hipStream_t)stream;
+    if (c->ncut == 0) return EB_OK;
+    op_wall_grad(c->g, u, c->gw, c->s);
+    vec_fill(3 * c->N, 0.0, c->gp, c->s);
+    adj_drag(c->g, *rheo, theta, c->gw, fbar, c->gwb, tau0b, pb, c->gp, c->s);
+    adj_grad_gather(c->g, c->wt, nullptr, c->gwb, ub, c->s);
+    adj_gcc_T(c->g, 1.0, c->gp, pb, pb, c->s);
+    return hip_check("eb_drag_adjoint");
+}
+
+int eb_mac_project_adjoint(eb_ctx* c, double beta, double* fbx, double* fby, double* fbz,
+                           double rtol, const eb_step_opts* opts, int* iters, void* stream) {
+    if (!c || !fbx || !fby || !fbz) return set_err(EB_EINVAL, "null argument");
+    c->s = (hipStream_t)stream;
+    SolveCfg k = cfg_of(opts);
+    double* fb[3] = {fbx, fby, fbz};
+    mac_project_adj(c, beta, fb, rtol, k, 0);
+    int h = hip_check("eb_mac_project_adjoint");
+    if (h) return h;
+    int sl[2];
+    if ((h = read_slots(c, 1, sl))) return h;
+    if (iters) *iters = sl[1];
+    return slot_code(sl, "adjoint MAC projection", k.max_iter);
+}
+
+int eb_cc_project_adjoint(eb_ctx* c, double beta, double* ub, double* pb, double rtol,
+                          const eb_step_opts* opts, int* iters, void* stream) {
+    if (!c || !ub || !pb) return set_err(EB_EINVAL, "null argument");
+    c->s = (hipStream_t)stream;
+    SolveCfg k = cfg_of(opts);
+    adj_mask_open(c->g, 3, ub, c->u1, c->s);
+    adj_mask_open(c->g, 1, pb, c->p1, c->s);
+    cc_project_adj(c, beta, c->u1, c->p1, rtol, k, 0);
+    vec_copy(3 * c->N, c->u1, ub, c->s);
+    vec_copy(c->N, c->p1, pb, c->s);
+    int h = hip_check("eb_cc_project_adjoint");
+    if (h) return h;
+    int sl[2];
+    if ((h = read_slots(c, 1, sl))) return h;
+    if (iters) *iters = sl[1];
+    return slot_code(sl, "adjoint projection", k.max_iter);
+}
+
+int eb_visc_solve_adjoint(eb_ctx* c, double rho, double dt, const double* eta,
+                          const double* eta_eb, const double* x, const double* xb, double rtol,
+                          const eb_step_opts* opts, double* psib, double* etab, double* etaebb,
+                          int* iters, void* stream) {
+    if (!c || !eta || !x || !xb || !psib || !etab || ((!eta_eb || !etaebb) && c->ncut > 0))
+        return set_err(EB_EINVAL, "null argument");
+    c->s = (hipStream_t)stream;
+    SolveCfg k = cfg_of(opts);
+    visc_solve_adj(c, rho, dt, eta, eta_eb, x, xb, rtol, k, 0, etab, etaebb);
+    adj_psi(c->g, 0.0, 0.0, c->lam, psib, c->ubm, c->C0, c->V0, c->s);
+    int h = hip_check("eb_visc_solve_adjoint");
+    if (h) return h;
+    int sl[2];
+    if ((h = read_slots(c, 1, sl))) return h;
+    if (iters) *iters = (sl[1] + 1) / 2;
+    return slot_code(sl, "transposed viscous solve", k.max_iter);
+}
+
+int eb_derived_adjoint(eb_ctx* c, const eb_rheology* rheo, const double* theta, const double* u,
+                       const double* Cb, const double* etab, const double* etaebb,
+                       const double* Vb, double* ub, double* tau0b, const eb_step_opts* opts,
+                       int* iters, void* stream) {
+    if (!c || !rheo || !u || !Cb || !etab || !Vb || !ub || !tau0b ||
+        (!etaebb && c->ncut > 0))
+        return set_err(EB_EINVAL, "null argument");
+    c->s = (hipStream_t)stream;
+    SolveCfg k = cfg_of(opts);
+    double rtol = opts && opts->rtol_mac > 0 ? opts->rtol_mac : 1e-12;
+    // the forward face velocities: extrapolate and project (slot 1), keep a copy
+    op_face_extrap(c->g, u, c->f, c->s);
+    vec_fill(c->N, 0.0, c->phi, c->s);
+    mac_project(c, 1.0, c->f, c->phi, rtol, k, 1, false);
+    double* uf[3];
+    for (int d = 0; d < 3; d++) {
+        uf[d] = c->kv[d];  // Krylov scratch, idle here
+        vec_copy(face_count(c->grid, d), c->f[d], uf[d], c->s);
+    }
+    derived_adj(c, *rheo, theta, u, uf, Cb, etab, etaebb, Vb, ub, tau0b, rtol, k, 0);
+    int h = hip_check("eb_derived_adjoint");
+    if (h) return h;
+    int sl[4];
+    if ((h = read_slots(c, 2, sl))) return h;
+    if (iters) *iters = sl[1];
+    if (sl[2] != 2) return slot_code(sl + 2, "MAC projection", k.max_iter);
+    return slot_code(sl, "adjoint MAC projection", k.max_iter);
 }
 
 int eb_pressure_gradient(const eb_ctx* cc, const double* p, double* gp, void* stream) {

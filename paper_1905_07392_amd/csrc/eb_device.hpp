@@ -1,0 +1,62 @@
+// eb_device.hpp -- device helpers shared by the forward and the adjoint kernels.
+#pragma once
+#include "eb_internal.hpp"
+
+// apparent viscosity (Table rheology, Eq. papabing:viscosity)
+__device__ __forceinline__ double eta_law(int law, double mu, double eps, double tau0,
+                                          double sr) {
+    if (law == EB_LAW_NEWTONIAN || tau0 == 0.0) return mu;
+    if (law == EB_LAW_BINGHAM_REG) return mu + tau0 / (sr + eps);
+    if (sr == 0.0) return mu + tau0 / eps;
+    return mu + tau0 * (-expm1(-sr / eps)) / sr;
+}
+
+// sqrt(tr(gamma gamma^T)/2), gamma = G + G^T
+__device__ __forceinline__ double strain_rate(const double G[3][3]) {
+    double s = 0.0;
+    for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) {
+            double y = G[a][b] + G[b][a];
+            s += y * y;
+        }
+    return sqrt(0.5 * s);
+}
+
+__device__ __forceinline__ long nbr(const GridV& g, int i, int j, int k, int d, int side) {
+    int q[3] = {i, j, k};
+    q[d] += side;
+    return cell_at(g, q[0], q[1], q[2]);
+}
+
+// monotonised-central limited slope of component uj along d at cell c
+__device__ inline double mc_slope(const GeomV& g, const double* __restrict__ uj, long c, int d) {
+    int i, j, k;
+    cell_coords(g.grid, c, i, j, k);
+    long lo = nbr(g.grid, i, j, k, d, -1), hi = nbr(g.grid, i, j, k, d, 1);
+    if (lo < 0 || hi < 0) return 0.0;
+    if (!(g.alpha[lo] > 0.0) || !(g.alpha[hi] > 0.0)) return 0.0;
+    double uc = uj[c];
+    double dl = uc - uj[lo], dr = uj[hi] - uc, dc = 0.5 * (uj[hi] - uj[lo]);
+    if (dl * dr <= 0.0) return 0.0;
+    double m = fmin(fabs(dc), fmin(2.0 * fabs(dl), 2.0 * fabs(dr)));
+    return dc > 0.0 ? m : -m;
+}
+
+// cells on either side of face (d; fi, fj, fk); -1 at a wall
+__device__ __forceinline__ void face_cells(const GridV& g, int d, int fi, int fj, int fk,
+                                           long& lo, long& hi) {
+    int q[3] = {fi, fj, fk};
+    q[d] -= 1;
+    lo = cell_at(g, q[0], q[1], q[2]);
+    q[d] += 1;
+    hi = cell_at(g, q[0], q[1], q[2]);
+}
+
+__device__ __forceinline__ void face_coords(const GridV& g, int d, long f, int& i, int& j,
+                                            int& k) {
+    int m0 = g.n[0] + (d == 0), m1 = g.n[1] + (d == 1);
+    i = (int)(f % m0);
+    long r = f / m0;
+    j = (int)(r % m1);
+    k = (int)(r / m1);
+}

@@ -252,3 +252,48 @@ void vec_bicg_update(long n, double al, const double* ph, double om, const doubl
                      const double* sv, const double* t, double* x, double* r, hipStream_t s);
 void vec_mask_rhs(const GeomV& g, const double* psi, const double* a0, double* b,
                   hipStream_t s);
+
+// ------------------------------------------------------------------------------------------
+// adjoint (eb_adjoint.hip)
+// ------------------------------------------------------------------------------------------
+// transposed wall stencil: for cell c with map[c] = r >= 0, entries ent[ptr[r] .. ptr[r+1])
+// are the flat stencil positions (slot * ncut + cut) that read u at c, in increasing order
+struct WallT {
+    const int* map;
+    const int* ptr;
+    const int* ent;
+};
+// adjoints of the left/right face states, [component][face] per direction
+struct LRV {
+    double* L[3];
+    double* R[3];
+};
+void adj_redistribute(const GeomV& g, const double* Db, double* X, double* Y, double* DCb,
+                      hipStream_t s);
+void adj_visc_terms(const GeomV& g, const eb_rheology& r, const double* theta, const double* u,
+                    const double* G9, const double* eta, const double* eta_eb, const double* gw,
+                    const double* DCb, const double* etab_in, const double* etaebb_in,
+                    double* ub, double* Gb, double* gwb, double* tau0b, hipStream_t s);
+void adj_grad_gather(const GeomV& g, const WallT& wt, const double* Gb, const double* gwb,
+                     double* ub, hipStream_t s);
+void adj_conv_face_w(const GeomV& g, const double* u, double* const w[3], const double* DCb,
+                     double* wb[3], hipStream_t s);
+void adj_conv_lr(const GeomV& g, const double* u, double* const w[3], const double* DCb,
+                 double* const wbin[3], const LRV& lr, double* ub, hipStream_t s);
+void adj_face_grad_T_neg(const GeomV& g, double* const fb[3], double* out, hipStream_t s);
+void adj_div_T_add(const GeomV& g, double beta, const double* z, double* wb[3], hipStream_t s);
+void adj_cc_cell(const GeomV& g, const double* z, double* ub, hipStream_t s);
+void adj_gcc_T(const GeomV& g, double a, const double* v, const double* base, double* out,
+               hipStream_t s);
+void adj_visc_apply_T(const GeomV& g, double rho, double dt, const double* eta,
+                      const double* eta_eb, const WallT& wt, const double* lam, double* out,
+                      hipStream_t s, const int* gate = nullptr);
+void adj_visc_coef(const GeomV& g, double dt, const double* x, const double* lam, double* etab,
+                   double* etaebb, hipStream_t s);
+void adj_psi(const GeomV& g, double rho, double dt, const double* lam, double* psib, double* ub,
+             double* Cb, double* Vb, hipStream_t s);
+void adj_drag(const GeomV& g, const eb_rheology& r, const double* theta, const double* gw,
+              const double fb[3], double* gwb, double* tau0b, double* pb, double* gpb,
+              hipStream_t s);
+void adj_mask_open(const GeomV& g, int ncomp, const double* in, double* out, hipStream_t s);
+void adj_scale(long n, double a, double* x, hipStream_t s);
