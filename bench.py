@@ -37,16 +37,20 @@ def parse():
     ap.add_argument("--sweeps", type=int, default=40)
     ap.add_argument("--nu", type=int, default=2, help="smoothing pairs before and after")
     ap.add_argument("--nbottom", type=int, default=16)
+    ap.add_argument("--adjoint-steps", type=int, default=20,
+                    help="steps of the adjoint/forward ratio run (0 skips it)")
+    ap.add_argument("--ckpt-every", type=int, default=5)
     return ap.parse_args()
 
 
 def smoother_bytes_per_launch(N, ncomp, w):
-    """Algorithmic bytes of one red-black half sweep over N cells with ncomp components.
+    """Algorithmic bytes of one red-black half sweep (one launch, one colour: N/2 updated cells).
 
-    Per launch (one colour): read the other colour's x (N/2 ncomp w), write this colour's x
-    (N/2 ncomp w), read b (N/2 ncomp w), read D (N/2 w), read the three face-coefficient arrays
-    (each face touches exactly one updated cell: 3 N w), read the open-cell mask (N/2 bytes)."""
-    return N * (1.5 * ncomp * w + 0.5 * w + 3.0 * w + 0.5)
+    Per updated cell a Gauss-Seidel sweep must move the iterate once in and once out
+    (2 ncomp w), the right-hand side (ncomp w), the cell viscosity the face coefficients are
+    formed from (w) and the cell-type flag (1 byte): 10 w + 1 bytes for three components
+    (81 in FP64, 41 in FP32)."""
+    return (N // 2) * (3 * ncomp * w + w + 1)
 
 
 def time_smoother(api, ctx, precision, sweeps, torch):
@@ -68,6 +72,36 @@ def time_smoother(api, ctx, precision, sweeps, torch):
     e1.record(stream)
     e1.synchronize()
     return e0.elapsed_time(e1) / sweeps
+
+
+def adjoint_ratio(api, AG, ctx, w, opts, nsteps, every, torch, I):
+    """Adjoint run: the 128^3 sphere with tau0_c = Bi theta_c (theta = 1 + 0.05 U(-1,1), seed 1,
+    Bi = 10), u starting at the wall velocity, nsteps steps with checkpoints every `every`;
+    loss = z-force on the sphere.  Returns wall times of the forward (nsteps steps + drag) and of
+    the backward (segment recomputation with tapes + step adjoints + drag adjoint)."""
+    import copy
+
+    o = copy.copy(opts)
+    o.precision = api.EB_FP64
+    rheo = api.make_rheology(w.law, w.mu, w.tau0, w.eps, w.rho)
+    dev = ctx.device
+    u0 = torch.from_numpy(I.initial_velocity(w)).to(dev)
+    p0 = torch.zeros(ctx.shape, dtype=torch.float64, device=dev)
+    theta = torch.from_numpy(I.yield_field(w, seed=1)).to(dev).requires_grad_(True)
+    bi = torch.tensor(float(w.tau0), dtype=torch.float64, device=dev, requires_grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u, p = AG.rollout(ctx, rheo, w.dt, o, u0, p0, theta, bi, nsteps, ckpt_every=every)
+    fz = AG.drag(ctx, rheo, u, p, theta, bi)[2]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    fz.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    return {"steps": nsteps, "ckpt_every": every, "fwd_s": round(t1 - t0, 4),
+            "bwd_s": round(t2 - t1, 4), "ratio": round((t2 - t1) / (t1 - t0), 3),
+            "Fz": fz.item(), "dFz_dBi": bi.grad.item(),
+            "dFz_dtheta_maxabs": theta.grad.abs().max().item()}
 
 
 def cpu_baseline(w, u0, p0, n_steps=1):
@@ -123,7 +157,7 @@ def main():
         api.eb_mg_vcycle(ctx, api.EB_SYS_VISC, r, opts, precision=prec, rho=w.rho, dt=w.dt,
                          eta=eta, eta_eb=eta_eb)
         ms = time_smoother(api, ctx, prec, args.sweeps, torch)
-        print(json.dumps({"kernel": "k_smooth<3> finest level", "avg_ms": ms}))
+        print(json.dumps({"kernel": "k_smooth_rb<3> finest level", "avg_ms": ms}))
         return
 
     print(f"[bench] {w.name} n={w.n} precision={args.precision} warmup={args.warmup} "
@@ -157,7 +191,7 @@ def main():
     achieved = algo / (ms_k * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_smooth (finest level, 3 components, one colour)",
+                "kernel": "k_smooth_rb (finest level, 3 components, one colour)",
                 "kernel_ms": round(ms_k, 5), "bytes_per_launch": int(algo)}
 
     out = {"metric": METRIC, "value": round(mlups, 3), "unit": "MLUPS", "n_gpus": 1,
@@ -171,6 +205,12 @@ def main():
                       "iterations_last_step": {k: stats[-1][k] for k in
                                                ("it_mac", "it_visc", "it_proj", "vcycles")}},
            "roofline": roofline}
+    if args.adjoint_steps > 0:
+        from paper_1905_07392_amd import autograd as AG
+
+        adj = adjoint_ratio(api, AG, ctx, w, opts, args.adjoint_steps, args.ckpt_every, torch, I)
+        out["adjoint"] = adj
+        print(f"[bench] adjoint: {adj}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         val, cores, tcpu = cpu_baseline(w, u0_host, p0_host)
         out["cpu_baseline"] = {"value": round(val, 4), "unit": "MLUPS", "cores": cores,

@@ -17,9 +17,11 @@
  *    alive until eb_ctx_destroy.  A context is not thread safe; calls on one context must be
  *    serialised by the caller.
  *  - Streams: `stream` is a hipStream_t passed as void*; NULL is the default stream.  Work is
- *    enqueued on it.  Entry points that return host values (iteration counts, norms, forces)
- *    synchronise that stream before returning; the solvers read one residual norm back per
- *    iteration.
+ *    ordered on it: the library runs it on a stream of its own that waits for the caller's
+ *    earlier work, and the caller's stream waits for the library's work before anything
+ *    enqueued later.  Entry points that return host values (iteration counts, norms, forces)
+ *    wait for the library's work before returning; the solvers poll one convergence word per
+ *    iteration, one iteration behind the device.
  *  - Errors: every entry point returns 0 (EB_OK) or a negative code; eb_last_error() gives a
  *    thread-local message.  No exception crosses the ABI.  On EB_ENOCONV outputs hold the last
  *    iterate.
@@ -113,6 +115,11 @@ int eb_geometry_build(const eb_box* box, const eb_body* body, void* ws, size_t w
 /* Releases the host context (not the caller's workspace). */
 void eb_ctx_destroy(eb_ctx* ctx);
 
+/* Solver iterations are captured once per configuration as HIP graphs and replayed (on by
+ * default; the environment variable EB_GRAPHS=0 turns it off for new contexts).  enable = 0
+ * launches every kernel individually instead; results are identical either way.  Host only. */
+int eb_ctx_set_graphs(eb_ctx* ctx, int enable);
+
 /* Number of cut cells, multigrid levels, and wall stencils that needed the covered-node
  * fallback.  Host only. */
 int eb_ctx_info(const eb_ctx* ctx, int* ncut, int* nlevels, int* nfallback);
@@ -160,8 +167,12 @@ int eb_mg_vcycle(eb_ctx* ctx, int system, int precision, double beta, double rho
 /* One red-black Gauss-Seidel half sweep (cells with (i+j+k) mod 2 == colour) on the finest
  * multigrid level, with the operator built by the most recent eb_mg_vcycle or solve for
  * `system` at `precision` (EB_FP64: b, x are (device) double [ncomp][N]; EB_MIXED: float).
- * ncomp = 1 (Poisson) or 3 (viscous).  The multigrid smoother in isolation, for timing and
- * tests; EB_EINVAL if no operator of that kind has been built. */
+ * ncomp = 1 (Poisson) or 3 (viscous).  b and x are in the finest level's colour-split order:
+ * per component, the cells of colour 0 in natural order, then those of colour 1, so cell
+ * c = (i,j,k) sits at ((i+j+k) mod 2) * N/2 + c/2.  Regular cells recompute their coefficients
+ * from the viscosity array the operator was built from, which must still be valid.  The
+ * multigrid smoother in isolation, for timing and tests; EB_EINVAL if no operator of that kind
+ * has been built. */
 int eb_mg_sweep(eb_ctx* ctx, int system, int precision, int colour, const void* b, void* x,
                 void* stream);
 

@@ -56,6 +56,7 @@ SIGNATURES = {
     "eb_geometry_build": (_I, [_P, _P, _P, C.c_size_t, C.POINTER(_P), _P]),
     "eb_ctx_destroy": (None, [_P]),
     "eb_ctx_info": (_I, [_P, _IP, _IP, _IP]),
+    "eb_ctx_set_graphs": (_I, [_P, _I]),
     "eb_geometry_export": (_I, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "eb_apparent_viscosity": (_I, [_P, _P, _P, _P, _P, _P, _P, _P]),
     "eb_viscous_apply": (_I, [_P, _I, _D, _D, _P, _P, _P, _P, _P]),

@@ -138,6 +138,10 @@ class EbContext:
         except Exception:
             pass
 
+    def set_graphs(self, enable: bool):
+        """Replay captured solver iterations (default) or launch every kernel individually."""
+        check(L.lib().eb_ctx_set_graphs(self.ptr, int(bool(enable))), "eb_ctx_set_graphs")
+
     def zeros(self, *shape):
         return torch.zeros(shape, dtype=torch.float64, device=self.device)
 

@@ -454,19 +454,21 @@ __global__ void k_conv_face_lr(GeomV g, int d, const double* __restrict__ u,
     long nf = face_count(g.grid, d);
     long f = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (f >= nf) return;
-    int fi[3];
-    face_coords(g.grid, d, f, fi[0], fi[1], fi[2]);
+    int f0, f1, f2;
+    face_coords(g.grid, d, f, f0, f1, f2);
+    int fd = d == 0 ? f0 : (d == 1 ? f1 : f2);
     double L[3], R[3];
     face_state_bar(g, d, f, u, w, DCb, wbin, L, R);
-    int tw = seam_twin(g.grid, d, fi[d]);
+    int tw = seam_twin(g.grid, d, fd);
     if (tw >= 0) {
-        int ft[3] = {fi[0], fi[1], fi[2]};
-        ft[d] = tw;
+        long ft = face_index(g.grid, d, d == 0 ? tw : f0, d == 1 ? tw : f1, d == 2 ? tw : f2);
         double L2[3], R2[3];
-        face_state_bar(g, d, face_index(g.grid, d, ft[0], ft[1], ft[2]), u, w, DCb, wbin, L2, R2);
+        face_state_bar(g, d, ft, u, w, DCb, wbin, L2, R2);
+        bool top = fd == g.grid.n[d];  // cell n-1 reads face n, cell 0 reads face 0
+#pragma unroll
         for (int j = 0; j < 3; j++) {
-            if (fi[d] == g.grid.n[d]) L[j] += L2[j];  // cell n-1 reads face n
-            else R[j] += R2[j];                       // cell 0 reads face 0
+            if (top) L[j] += L2[j];
+            else R[j] += R2[j];
         }
     }
     for (int j = 0; j < 3; j++) {
@@ -766,7 +768,7 @@ __global__ void k_psi_adj(GeomV g, double rho, double dt, const double* __restri
     long N = g.N;
     long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (t >= 3 * N) return;
-    long c = t % N;
+    long c = (long)((unsigned)t % (unsigned)N);  // 3N < 2^32
     double a = g.alpha[c];
     double ps = a > 0.0 ? a * lam[t] : 0.0;
     psib[t] = ps;
@@ -830,7 +832,7 @@ __global__ void k_mask_open(GeomV g, int ncomp, const double* __restrict__ in,
     long N = g.N;
     long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (t >= N * ncomp) return;
-    out[t] = g.alpha[t % N] > 0.0 ? in[t] : 0.0;
+    out[t] = g.alpha[(unsigned)t % (unsigned)N] > 0.0 ? in[t] : 0.0;
 }
 
 __global__ void k_scale(long n, double a, double* __restrict__ x) {

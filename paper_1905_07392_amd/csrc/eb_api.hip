@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <utility>
@@ -83,6 +84,12 @@ struct eb_ctx {
     // pinned host words for the lagged convergence poll, and their events
     int* pin;
     hipEvent_t ev[2];
+    // the library's own stream (fenced to the caller's with two events) and the captured
+    // Krylov iterations replayed on it
+    hipStream_t own;
+    hipEvent_t fence_in, fence_out;
+    int graphs_on;
+    struct GraphCache* graphs;
     // adjoint: transposed wall stencil and reverse-sweep arrays
     int *wt_map, *wt_ptr, *wt_ent;
     WallT wt;
@@ -139,7 +146,7 @@ size_t carve(eb_ctx* c, char* base, bool dry) {
     c->part = cv.take<double>(4 * 1024);
     c->red = cv.take<double>(64);
     c->ks = cv.take<double>(KS_COUNT);
-    c->kst = cv.take<int>(2 * NSLOT);
+    c->kst = cv.take<int>(3 * NSLOT);  // (state, count) per slot, then the iteration counters
     c->divs = cv.take<double>(NSLOT);
     // levels
     int m[3] = {g.n[0], g.n[1], g.n[2]};
@@ -171,6 +178,7 @@ size_t carve(eb_ctx* c, char* base, bool dry) {
         L.xf = cv.take<float>(3 * L.N);
         L.bf = cv.take<float>(3 * L.N);
         L.rf = cv.take<float>(3 * L.N);
+        if (l == 0) L.etaf = cv.take<float>(L.N);
         for (int d = 0; d < 3; d++) m[d] /= 2;
         h *= 2.0;
     }
@@ -251,7 +259,7 @@ int build_wall_transpose(eb_ctx* c) {
     std::vector<int> map(N, -1);
     std::vector<int> ptr(1, 0), ent;
     if (nc > 0) {
-        hipMemcpy(sidx.data(), c->sidx, sidx.size() * sizeof(int), hipMemcpyDeviceToHost);
+        (void)hipMemcpy(sidx.data(), c->sidx, sidx.size() * sizeof(int), hipMemcpyDeviceToHost);
         std::vector<std::pair<int, int>> pairs;
         pairs.reserve(sidx.size());
         for (size_t e = 0; e < sidx.size(); e++)
@@ -268,10 +276,10 @@ int build_wall_transpose(eb_ctx* c) {
         ptr.push_back((int)pairs.size());
         if (pairs.empty()) ptr.assign(1, 0);
     }
-    hipMemcpy(c->wt_map, map.data(), N * sizeof(int), hipMemcpyHostToDevice);
-    hipMemcpy(c->wt_ptr, ptr.data(), ptr.size() * sizeof(int), hipMemcpyHostToDevice);
+    (void)hipMemcpy(c->wt_map, map.data(), N * sizeof(int), hipMemcpyHostToDevice);
+    (void)hipMemcpy(c->wt_ptr, ptr.data(), ptr.size() * sizeof(int), hipMemcpyHostToDevice);
     if (!ent.empty())
-        hipMemcpy(c->wt_ent, ent.data(), ent.size() * sizeof(int), hipMemcpyHostToDevice);
+        (void)hipMemcpy(c->wt_ent, ent.data(), ent.size() * sizeof(int), hipMemcpyHostToDevice);
     c->wt.map = c->wt_map;
     c->wt.ptr = c->wt_ptr;
     c->wt.ent = c->wt_ent;
@@ -371,6 +379,83 @@ int fetch(eb_ctx* c, double* host, int n) {
 // current one runs, so the GPU never waits for the host.  Each solve reports into a state
 // slot (state, count) that callers read once at the end.
 // ------------------------------------------------------------------------------------------
+// ------------------------------------------------------------------------------------------
+// Krylov iterations as captured graphs.  An iteration launches a fixed sequence of kernels
+// whose arguments depend only on the solve's configuration (buffers, coefficients, slot), so it
+// is captured once per configuration and replayed with one launch.  The key holds every value
+// baked into the captured kernels' arguments.
+// ------------------------------------------------------------------------------------------
+}  // namespace
+
+struct GraphKey {
+    int kind, slot, nc, mixed, nu1, nu2, nbottom, transposed;
+    const void* p[6];
+    double v[4];
+};
+
+struct GraphCache {
+    std::vector<std::pair<GraphKey, hipGraphExec_t>> entries;
+    ~GraphCache() {
+        for (auto& e : entries)
+            if (e.second) (void)hipGraphExecDestroy(e.second);
+    }
+};
+
+namespace {
+
+GraphKey make_key() {
+    GraphKey k;
+    memset(&k, 0, sizeof(k));  // padding too, so keys compare bytewise
+    return k;
+}
+
+// runs one iteration body: replayed from the cache when graphs are on, captured on first use;
+// if capture or instantiation fails the body runs eagerly from then on for that key
+template <typename F>
+void run_iteration(eb_ctx* c, const GraphKey& key, F&& body) {
+    if (!c->graphs_on || !c->graphs) {
+        body();
+        return;
+    }
+    for (auto& e : c->graphs->entries)
+        if (memcmp(&e.first, &key, sizeof(GraphKey)) == 0) {
+            if (e.second) (void)hipGraphLaunch(e.second, c->s);
+            else body();
+            return;
+        }
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    if (hipStreamBeginCapture(c->s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+        body();
+        if (hipStreamEndCapture(c->s, &graph) == hipSuccess && graph) {
+            if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
+                exec = nullptr;
+            (void)hipGraphDestroy(graph);
+        }
+    }
+    (void)hipGetLastError();  // a failed capture leaves no sticky error; run eagerly instead
+    c->graphs->entries.emplace_back(key, exec);
+    if (exec) (void)hipGraphLaunch(exec, c->s);
+    else body();
+}
+
+// work of a public call runs on the library's stream, ordered after the caller's prior work
+// and before the caller's later work
+struct StreamScope {
+    eb_ctx* c;
+    hipStream_t user;
+    StreamScope(eb_ctx* ctx, void* stream) : c(ctx), user((hipStream_t)stream) {
+        hipEventRecord(c->fence_in, user);
+        hipStreamWaitEvent(c->own, c->fence_in, 0);
+        c->s = c->own;
+    }
+    ~StreamScope() {
+        hipEventRecord(c->fence_out, c->own);
+        hipStreamWaitEvent(user, c->fence_out, 0);
+        c->s = user;
+    }
+};
+
 struct SolveCfg {
     bool mixed;
     int nu1, nu2, nbottom, max_iter;
@@ -410,33 +495,47 @@ void pcg(eb_ctx* c, const double* b, double* x, const SolveCfg& k, int slot) {
     double *r = c->pk[0], *z = c->pk[1], *pd = c->pk[2], *q = c->pk[3];
     double* ks = c->ks;
     int* st = c->kst + 2 * slot;
+    int* itc = c->kst + 2 * NSLOT + slot;
     const double* A1[4] = {nullptr, nullptr, nullptr, nullptr};
     const double* B1[4] = {nullptr, nullptr, nullptr, nullptr};
     mg_apply_level0(c->lev[0], 1, x, q, c->s);
     vec_sub_scaled(N, b, 1.0, q, r, c->s);
     red_maxabs(N, 1, b, c->part, ks + KS_BN, c->s);
     red_maxabs(N, 1, r, c->part, ks + KS_RN, c->s);
-    ks_op(KS_INIT, ks, st, 0, c->s);
+    ks_op(KS_INIT, ks, st, itc, c->s);
     vcyc(c, 1, k, r, z, st);
     vec_copy(N, z, pd, c->s);
     A1[0] = r;
     B1[0] = z;
     red_dots(N, 1, A1, B1, c->part, ks + KS_RZ, c->s, st);
-    for (int it = 1; it <= k.max_iter; it++) {
+    GraphKey key = make_key();
+    key.kind = 1;
+    key.slot = slot;
+    key.nc = 1;
+    key.mixed = k.mixed;
+    key.nu1 = k.nu1;
+    key.nu2 = k.nu2;
+    key.nbottom = k.nbottom;
+    key.p[0] = x;
+    key.v[0] = c->lev[0].beta;
+    auto body = [&]() {
+        const double* A[4] = {pd, nullptr, nullptr, nullptr};
+        const double* B[4] = {q, nullptr, nullptr, nullptr};
         mg_apply_level0(c->lev[0], 1, pd, q, c->s, st);
-        A1[0] = pd;
-        B1[0] = q;
-        red_dots(N, 1, A1, B1, c->part, ks + KS_PQ, c->s, st);
-        ks_op(KS_CG_ALPHA, ks, st, it, c->s);
+        red_dots(N, 1, A, B, c->part, ks + KS_PQ, c->s, st);
+        ks_op(KS_CG_ALPHA, ks, st, itc, c->s);
         ks_cg_xr(N, x, r, pd, q, ks, st, c->s);
         red_maxabs(N, 1, r, c->part, ks + KS_RN, c->s, st);
-        ks_op(KS_CHECK_R, ks, st, it, c->s);
+        ks_op(KS_CHECK_R, ks, st, itc, c->s);
         vcyc(c, 1, k, r, z, st);
-        A1[0] = r;
-        B1[0] = z;
-        red_dots(N, 1, A1, B1, c->part, ks + KS_RZN, c->s, st);
-        ks_op(KS_CG_BETA, ks, st, it, c->s);
+        A[0] = r;
+        B[0] = z;
+        red_dots(N, 1, A, B, c->part, ks + KS_RZN, c->s, st);
+        ks_op(KS_CG_BETA, ks, st, itc, c->s);
         ks_cg_p(N, pd, z, ks, st, c->s);
+    };
+    for (int it = 1; it <= k.max_iter; it++) {
+        run_iteration(c, key, body);
         if (poll_done(c, slot, it)) break;
     }
 }
@@ -492,6 +591,7 @@ void visc_solve(eb_ctx* c, double rho, double dt, const double* eta, const doubl
            *sv = c->kv[5], *sh = c->kv[6], *t = c->kv[7], *b = c->kv[8], *a0 = c->kv[9];
     double* ks = c->ks;
     int* st = c->kst + 2 * slot;
+    int* itc = c->kst + 2 * NSLOT + slot;
     auto apply = [&](const double* in, double* out, const int* gate) {
         if (transposed) adj_visc_apply_T(c->g, rho, dt, eta, eta_eb, c->wt, in, out, c->s, gate);
         else op_visc_apply(c->g, rho, dt, eta, eta_eb, in, out, 1, c->s, gate);
@@ -515,37 +615,54 @@ void visc_solve(eb_ctx* c, double rho, double dt, const double* eta, const doubl
     apply(x, t, nullptr);
     vec_sub_scaled(N3, b, 1.0, t, r, c->s);
     red_maxabs(N3, 1, r, c->part, ks + KS_RN, c->s);
-    ks_op(KS_INIT, ks, st, 0, c->s);
+    ks_op(KS_INIT, ks, st, itc, c->s);
     vec_copy(N3, r, rh, c->s);
     vec_fill(N3, 0.0, p, c->s);
     vec_fill(N3, 0.0, v, c->s);
     const double* A1[4] = {rh, nullptr, nullptr, nullptr};
     const double* B1[4] = {r, nullptr, nullptr, nullptr};
     red_dots(N3, 1, A1, B1, c->part, ks + KS_RR, c->s, st);
-    for (int it = 1; it <= k.max_iter; it++) {
-        ks_op(KS_BI_BETA, ks, st, it, c->s);
+    GraphKey key = make_key();
+    key.kind = 2;
+    key.slot = slot;
+    key.nc = 3;
+    key.mixed = k.mixed;
+    key.nu1 = k.nu1;
+    key.nu2 = k.nu2;
+    key.nbottom = k.nbottom;
+    key.transposed = transposed;
+    key.p[0] = x;
+    key.p[1] = eta;
+    key.p[2] = eta_eb;
+    key.v[0] = rho;
+    key.v[1] = dt;
+    auto body = [&]() {
+        ks_op(KS_BI_BETA, ks, st, itc, c->s);
         ks_bi_p(N3, p, r, v, ks, st, c->s);
         vcyc(c, 3, k, p, ph, st);
         apply(ph, v, st);
         const double* Av[4] = {rh, nullptr, nullptr, nullptr};
         const double* Bv[4] = {v, nullptr, nullptr, nullptr};
         red_dots(N3, 1, Av, Bv, c->part, ks + KS_RV, c->s, st);
-        ks_op(KS_BI_ALPHA, ks, st, it, c->s);
+        ks_op(KS_BI_ALPHA, ks, st, itc, c->s);
         ks_bi_s(N3, sv, r, v, ks, st, c->s);
         red_maxabs(N3, 1, sv, c->part, ks + KS_SN, c->s, st);
-        ks_op(KS_BI_CHECK_S, ks, st, it, c->s);
+        ks_op(KS_BI_CHECK_S, ks, st, itc, c->s);
         ks_bi_xs(N3, x, ph, ks, st, c->s);
-        ks_op(KS_BI_FINISH_S, ks, st, it, c->s);
+        ks_op(KS_BI_FINISH_S, ks, st, itc, c->s);
         vcyc(c, 3, k, sv, sh, st);
         apply(sh, t, st);
         const double* A2[4] = {t, t, nullptr, nullptr};
         const double* B2[4] = {sv, t, nullptr, nullptr};
         red_dots(N3, 2, A2, B2, c->part, ks + KS_TS, c->s, st);
-        ks_op(KS_BI_OMEGA, ks, st, it, c->s);
+        ks_op(KS_BI_OMEGA, ks, st, itc, c->s);
         ks_bi_xr(N3, x, r, ph, sh, sv, t, ks, st, c->s);
         red_dots(N3, 1, A1, B1, c->part, ks + KS_RRN, c->s, st);
         red_maxabs(N3, 1, r, c->part, ks + KS_RN, c->s, st);
-        ks_op(KS_BI_CHECK_R, ks, st, it, c->s);
+        ks_op(KS_BI_CHECK_R, ks, st, itc, c->s);
+    };
+    for (int it = 1; it <= k.max_iter; it++) {
+        run_iteration(c, key, body);
         if (poll_done(c, slot, it)) break;
     }
 }
@@ -731,8 +848,18 @@ int eb_geometry_build(const eb_box* box, const eb_body* body, void* ws, size_t w
         return set_err(EB_EHIP, "pinned polling buffer or events: %s",
                        hipGetErrorString(hipGetLastError()));
     }
-    hipMemsetAsync(c->kst, 0, 2 * NSLOT * sizeof(int), c->s);
+    hipMemsetAsync(c->kst, 0, 3 * NSLOT * sizeof(int), c->s);
     hipStreamSynchronize(c->s);
+    if (hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->fence_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->fence_out, hipEventDisableTiming) != hipSuccess) {
+        eb_ctx_destroy(c);
+        return set_err(EB_EHIP, "library stream or events: %s",
+                       hipGetErrorString(hipGetLastError()));
+    }
+    c->graphs = new GraphCache;
+    const char* env = getenv("EB_GRAPHS");
+    c->graphs_on = env ? atoi(env) != 0 : 1;
     if ((e = build_wall_transpose(c))) {
         eb_ctx_destroy(c);
         return e;
@@ -743,10 +870,21 @@ int eb_geometry_build(const eb_box* box, const eb_body* body, void* ws, size_t w
 
 void eb_ctx_destroy(eb_ctx* ctx) {
     if (!ctx) return;
+    if (ctx->own) hipStreamSynchronize(ctx->own);
+    delete ctx->graphs;
+    if (ctx->own) hipStreamDestroy(ctx->own);
+    if (ctx->fence_in) hipEventDestroy(ctx->fence_in);
+    if (ctx->fence_out) hipEventDestroy(ctx->fence_out);
     if (ctx->pin) hipHostFree(ctx->pin);
     for (int b = 0; b < 2; b++)
         if (ctx->ev[b]) hipEventDestroy(ctx->ev[b]);
     delete ctx;
+}
+
+int eb_ctx_set_graphs(eb_ctx* c, int enable) {
+    if (!c) return set_err(EB_EINVAL, "null context");
+    c->graphs_on = enable ? 1 : 0;
+    return EB_OK;
 }
 
 int eb_ctx_info(const eb_ctx* c, int* ncut, int* nlevels, int* nfallback) {
@@ -832,7 +970,7 @@ int eb_mg_vcycle(eb_ctx* c, int system, int precision, double beta, double rho, 
                  const double* eta, const double* eta_eb, const double* r, double* e,
                  const eb_step_opts* opts, void* stream) {
     if (!c || !r || !e) return set_err(EB_EINVAL, "null argument");
-    c->s = (hipStream_t)stream;
+    StreamScope scope_(c, stream);
     SolveCfg k = cfg_of(opts);
     k.mixed = precision == EB_MIXED;
     if (system == EB_SYS_POISSON) {
@@ -871,7 +1009,7 @@ int eb_visc_solve(eb_ctx* c, double rho, double dt, const double* eta, const dou
                   int* iters, void* stream) {
     if (!c || !eta || !psi || !x || (!eta_eb && c->ncut > 0))
         return set_err(EB_EINVAL, "null argument");
-    c->s = (hipStream_t)stream;
+    StreamScope scope_(c, stream);
     SolveCfg k = cfg_of(opts);
     visc_solve(c, rho, dt, eta, eta_eb, psi, x, rtol, k, 0);
     int h = hip_check("eb_visc_solve");
@@ -886,7 +1024,7 @@ int eb_mac_project(eb_ctx* c, double beta, double* fx, double* fy, double* fz, d
                    double rtol, const eb_step_opts* opts, double* div_inf, int* iters,
                    void* stream) {
     if (!c || !fx || !fy || !fz || !phi) return set_err(EB_EINVAL, "null argument");
-    c->s = (hipStream_t)stream;
+    StreamScope scope_(c, stream);
     double* f[3] = {fx, fy, fz};
     SolveCfg k = cfg_of(opts);
     mac_project(c, beta, f, phi, rtol, k, 0, true);
@@ -902,7 +1040,7 @@ int eb_mac_project(eb_ctx* c, double beta, double* fx, double* fy, double* fz, d
 int eb_cc_project(eb_ctx* c, double beta, double* u, double* p, double rtol,
                   const eb_step_opts* opts, double* div_inf, int* iters, void* stream) {
     if (!c || !u || !p) return set_err(EB_EINVAL, "null argument");
-    c->s = (hipStream_t)stream;
+    StreamScope scope_(c, stream);
     SolveCfg k = cfg_of(opts);
     cc_project(c, beta, u, p, rtol, k, 0, true);
     int h = hip_check("eb_cc_project");
@@ -919,7 +1057,7 @@ int eb_derived(eb_ctx* c, const eb_rheology* rheo, const double* theta, const do
                int* iters, void* stream) {
     if (!c || !rheo || !u || !C || !eta || !V || (!eta_eb && c->ncut > 0))
         return set_err(EB_EINVAL, "null argument");
-    c->s = (hipStream_t)stream;
+    StreamScope scope_(c, stream);
     int h = derived(c, *rheo, theta, u, opts, C, eta, eta_eb, V, 0);
     if (h) return h;
     int sl[2];
@@ -1021,7 +1159,7 @@ int eb_rk2_step(eb_ctx* c, const eb_rheology* rheo, const double* theta, double 
                 const eb_step_opts* o, double* u, double* p, eb_step_stats* stats,
                 void* stream) {
     if (!c) return set_err(EB_EINVAL, "null context");
-    c->s = (hipStream_t)stream;
+    StreamScope scope_(c, stream);
     return rk2_impl(c, rheo, theta, dt, o, u, p, stats, nullptr);
 }
 
@@ -1035,7 +1173,7 @@ int eb_rk2_step_taped(eb_ctx* c, const eb_rheology* rheo, const double* theta, d
                       const eb_step_opts* o, double* u, double* p, void* tape,
                       eb_step_stats* stats, void* stream) {
     if (!c || !tape) return set_err(EB_EINVAL, "null context or tape");
-    c->s = (hipStream_t)stream;
+    StreamScope scope_(c, stream);
     TapeV t;
     tape_carve(c, (char*)tape, &t);
     return rk2_impl(c, rheo, theta, dt, o, u, p, stats, &t);
@@ -1047,7 +1185,7 @@ int eb_rk2_step_adjoint(eb_ctx* c, const eb_rheology* rheo, const double* theta,
     if (!c || !rheo || !o || !u0 || !tape || !ub || !pb || !tau0b)
         return set_err(EB_EINVAL, "null argument");
     if (!(rheo->rho > 0.0) || !(dt > 0.0)) return set_err(EB_EINVAL, "rho and dt must be > 0");
-    c->s = (hipStream_t)stream;
+    StreamScope scope_(c, stream);
     TapeV t;
     tape_carve(c, (char*)const_cast<void*>(tape), &t);
     SolveCfg k = cfg_of(o);
@@ -1092,7 +1230,7 @@ int eb_drag(const eb_ctx* cc, const eb_rheology* rheo, const double* theta, cons
             const double* p, double F[3], void* stream) {
     eb_ctx* c = const_cast<eb_ctx*>(cc);
     if (!c || !rheo || !u || !p || !F) return set_err(EB_EINVAL, "null argument");
-    c->s = (hipStream_t)stream;
+    StreamScope scope_(c, stream);
     F[0] = F[1] = F[2] = 0.0;
     if (c->ncut == 0) return EB_OK;
     op_wall_grad(c->g, u, c->gw, c->s);
@@ -1110,7 +1248,7 @@ int eb_drag_adjoint(const eb_ctx* cc, const eb_rheology* rheo, const double* the
     eb_ctx* c = const_cast<eb_ctx*>(cc);
     if (!c || !rheo || !u || !fbar || !ub || !pb || !tau0b)
         return set_err(EB_EINVAL, "null argument");
-    c->s = (hipStream_t)stream;
+    StreamScope scope_(c, stream);
     if (c->ncut == 0) return EB_OK;
     op_wall_grad(c->g, u, c->gw, c->s);
     vec_fill(3 * c->N, 0.0, c->gp, c->s);
@@ -1123,7 +1261,7 @@ int eb_drag_adjoint(const eb_ctx* cc, const eb_rheology* rheo, const double* the
 int eb_mac_project_adjoint(eb_ctx* c, double beta, double* fbx, double* fby, double* fbz,
                            double rtol, const eb_step_opts* opts, int* iters, void* stream) {
     if (!c || !fbx || !fby || !fbz) return set_err(EB_EINVAL, "null argument");
-    c->s = (hipStream_t)stream;
+    StreamScope scope_(c, stream);
     SolveCfg k = cfg_of(opts);
     double* fb[3] = {fbx, fby, fbz};
     mac_project_adj(c, beta, fb, rtol, k, 0);
@@ -1138,7 +1276,7 @@ int eb_mac_project_adjoint(eb_ctx* c, double beta, double* fbx, double* fby, dou
 int eb_cc_project_adjoint(eb_ctx* c, double beta, double* ub, double* pb, double rtol,
                           const eb_step_opts* opts, int* iters, void* stream) {
     if (!c || !ub || !pb) return set_err(EB_EINVAL, "null argument");
-    c->s = (hipStream_t)stream;
+    StreamScope scope_(c, stream);
     SolveCfg k = cfg_of(opts);
     adj_mask_open(c->g, 3, ub, c->u1, c->s);
     adj_mask_open(c->g, 1, pb, c->p1, c->s);
@@ -1159,7 +1297,7 @@ int eb_visc_solve_adjoint(eb_ctx* c, double rho, double dt, const double* eta,
                           int* iters, void* stream) {
     if (!c || !eta || !x || !xb || !psib || !etab || ((!eta_eb || !etaebb) && c->ncut > 0))
         return set_err(EB_EINVAL, "null argument");
-    c->s = (hipStream_t)stream;
+    StreamScope scope_(c, stream);
     SolveCfg k = cfg_of(opts);
     visc_solve_adj(c, rho, dt, eta, eta_eb, x, xb, rtol, k, 0, etab, etaebb);
     adj_psi(c->g, 0.0, 0.0, c->lam, psib, c->ubm, c->C0, c->V0, c->s);
@@ -1178,7 +1316,7 @@ int eb_derived_adjoint(eb_ctx* c, const eb_rheology* rheo, const double* theta, 
     if (!c || !rheo || !u || !Cb || !etab || !Vb || !ub || !tau0b ||
         (!etaebb && c->ncut > 0))
         return set_err(EB_EINVAL, "null argument");
-    c->s = (hipStream_t)stream;
+    StreamScope scope_(c, stream);
     SolveCfg k = cfg_of(opts);
     double rtol = opts && opts->rtol_mac > 0 ? opts->rtol_mac : 1e-12;
     // the forward face velocities: extrapolate and project (slot 1), keep a copy

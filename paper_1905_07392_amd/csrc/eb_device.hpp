@@ -54,9 +54,10 @@ __device__ __forceinline__ void face_cells(const GridV& g, int d, int fi, int fj
 
 __device__ __forceinline__ void face_coords(const GridV& g, int d, long f, int& i, int& j,
                                             int& k) {
-    int m0 = g.n[0] + (d == 0), m1 = g.n[1] + (d == 1);
-    i = (int)(f % m0);
-    long r = f / m0;
-    j = (int)(r % m1);
-    k = (int)(r / m1);
+    unsigned m0 = g.n[0] + (d == 0), m1 = g.n[1] + (d == 1), fu = (unsigned)f;
+    unsigned r = fu / m0;
+    i = (int)(fu - r * m0);
+    unsigned kk = r / m1;
+    j = (int)(r - kk * m1);
+    k = (int)kk;
 }

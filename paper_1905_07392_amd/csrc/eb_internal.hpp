@@ -88,11 +88,15 @@ __host__ __device__ inline long cell_at(const GridV& g, int i, int j, int k) {
     }
     return cell_index(g, q[0], q[1], q[2]);
 }
+// 32-bit unsigned division: boxes hold fewer than 2^32 cells, and 64-bit division is many
+// times slower on the GPU
 __host__ __device__ inline void cell_coords(const GridV& g, long c, int& i, int& j, int& k) {
-    i = (int)(c % g.n[0]);
-    long t = c / g.n[0];
-    j = (int)(t % g.n[1]);
-    k = (int)(t / g.n[1]);
+    unsigned cu = (unsigned)c, nx = (unsigned)g.n[0], ny = (unsigned)g.n[1];
+    unsigned t = cu / nx;
+    i = (int)(cu - t * nx);
+    unsigned k2 = t / ny;
+    j = (int)(t - k2 * ny);
+    k = (int)k2;
 }
 
 inline unsigned grid_for(long n, int block = EB_BLOCK) {
@@ -117,6 +121,13 @@ struct Level {
     double *x, *b, *r;  // 3 components each
     float *xf, *bf, *rf;
     const int* gate = nullptr;
+    // finest level only: what its operator was built from, so the smoother can recompute the
+    // coefficients of regular cells instead of reading them (flag: 0 covered, 1 cut, 2 regular)
+    const uint8_t* flag = nullptr;
+    const double* eta = nullptr;
+    float* etaf = nullptr;  // FP32 copy of eta for the mixed-precision smoother
+    int sys = 0;  // EB_SYS_POISSON or EB_SYS_VISC
+    double rho = 0.0, dt = 0.0, beta = 0.0;
     LevelV<double> v64() const {
         LevelV<double> v;
         v.grid = grid;
@@ -195,7 +206,8 @@ enum {
     KS_INIT, KS_CG_ALPHA, KS_CHECK_R, KS_CG_BETA, KS_BI_BETA, KS_BI_ALPHA, KS_BI_CHECK_S,
     KS_BI_FINISH_S, KS_BI_OMEGA, KS_BI_CHECK_R
 };
-void ks_op(int op, double* ks, int* st, int it, hipStream_t s);
+// st: the solve's (state, count) pair; itc: its device iteration counter
+void ks_op(int op, double* ks, int* st, int* itc, hipStream_t s);
 void ks_set(double* ks, int idx, double v, hipStream_t s);
 void ks_cg_xr(long n, double* x, double* r, const double* p, const double* q, const double* ks,
               const int* st, hipStream_t s);

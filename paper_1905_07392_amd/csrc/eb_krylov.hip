@@ -4,21 +4,28 @@
 // norms) lives in a small device array and every kernel of an iteration reads a device state
 // word: 0 running, 1 converged at the half step (BiCGSTAB, x update pending), 2 converged,
 // 3 non-finite residual.  Once the state leaves 0 the remaining kernels of the solve return at
-// once, so iterations the host enqueued ahead of the convergence test do no work.
+// once, so iterations the host enqueued ahead of the convergence test do no work.  The
+// iteration number is counted on the device as well, so every iteration launches identical
+// kernels with identical arguments (and can be replayed as one captured graph).
 #include "eb_internal.hpp"
 
 namespace {
 
 __device__ __forceinline__ bool finite_d(double x) { return isfinite(x); }
 
-__global__ void k_scal(int op, double* __restrict__ ks, int* __restrict__ st, int it) {
+__global__ void k_scal(int op, double* __restrict__ ks, int* __restrict__ st,
+                       int* __restrict__ itc) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     int s = *st;
+    // the first scalar op of each iteration advances the count while the solve runs
+    if (s == 0 && (op == KS_CG_ALPHA || op == KS_BI_BETA)) *itc += 1;
+    int it = *itc;
     switch (op) {
     case KS_INIT: {  // tol = rtol * max(bn, scale); converged already if rn <= tol
         double bn = ks[KS_BN] > ks[KS_SCALE] ? ks[KS_BN] : ks[KS_SCALE];
         ks[KS_TOL] = ks[KS_RTOL] * bn;
         st[1] = 0;
+        *itc = 0;
         if (!finite_d(ks[KS_RN])) *st = 3;
         else if (bn == 0.0 || ks[KS_RN] <= ks[KS_TOL]) *st = 2;
         else *st = 0;
@@ -142,8 +149,8 @@ __global__ void k_set(double* __restrict__ ks, int idx, double v) {
 
 }  // namespace
 
-void ks_op(int op, double* ks, int* st, int it, hipStream_t s) {
-    k_scal<<<1, 64, 0, s>>>(op, ks, st, it);
+void ks_op(int op, double* ks, int* st, int* itc, hipStream_t s) {
+    k_scal<<<1, 64, 0, s>>>(op, ks, st, itc);
 }
 void ks_set(double* ks, int idx, double v, hipStream_t s) { k_set<<<1, 64, 0, s>>>(ks, idx, v); }
 void ks_cg_xr(long n, double* x, double* r, const double* p, const double* q, const double* ks,

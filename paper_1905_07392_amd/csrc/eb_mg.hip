@@ -15,11 +15,12 @@ namespace {
 // operator construction
 // ------------------------------------------------------------------------------------------
 __device__ __forceinline__ void face_ijk(const GridV& g, int d, long f, int& i, int& j, int& k) {
-    int m0 = g.n[0] + (d == 0), m1 = g.n[1] + (d == 1);
-    i = (int)(f % m0);
-    long r = f / m0;
-    j = (int)(r % m1);
-    k = (int)(r / m1);
+    unsigned m0 = g.n[0] + (d == 0), m1 = g.n[1] + (d == 1), fu = (unsigned)f;
+    unsigned r = fu / m0;
+    i = (int)(fu - r * m0);
+    unsigned kk = r / m1;
+    j = (int)(r - kk * m1);
+    k = (int)kk;
 }
 
 __global__ void k_K_poisson(GeomV g, int d, double beta, double* __restrict__ K) {
@@ -147,11 +148,12 @@ template <typename T, int NC>
 __device__ __forceinline__ void smooth_cell(const LevelV<T>& L, const T* __restrict__ b,
                                             T* __restrict__ x, long t, int col) {
     const GridV& g = L.grid;
-    int nxh = g.n[0] / 2;
-    long row = t / nxh;
-    int ih = (int)(t - row * nxh);
-    int j = (int)(row % g.n[1]);
-    int k = (int)(row / g.n[1]);
+    unsigned nxh = (unsigned)g.n[0] >> 1, ny = (unsigned)g.n[1];
+    unsigned row = (unsigned)t / nxh;
+    int ih = (int)((unsigned)t - row * nxh);
+    unsigned kk = row / ny;
+    int j = (int)(row - kk * ny);
+    int k = (int)kk;
     int i = 2 * ih + ((j + k + col) & 1);
     long c = cell_index(g, i, j, k);
     if (!L.mask[c]) return;
@@ -243,33 +245,70 @@ __global__ void k_smooth_first(LevelV<T> L, const T* __restrict__ b, T* __restri
     for (int m = 0; m < NC; m++) x[m * L.N + c] = upd ? (b[m * L.N + c] + (T)0) / dg : (T)0;
 }
 
-// residual of the fine level restricted to the coarse right-hand side in one pass
+// Residual of the fine level restricted to the coarse right-hand side in one pass.  A block
+// handles RR_COARSE consecutive coarse cells: each thread forms the residual of one of their
+// eight children, then one thread per coarse cell sums the children in the fixed order
+// q = 0..7 (child (2i + (q&1), 2j + (q>>1&1), 2k + (q>>2))).
+constexpr int RR_COARSE = 32;
+constexpr int RR_THREADS = 8 * RR_COARSE;
+
+// thread t of a block: child bits and coarse slot, x fastest so rows of fine cells are read
+// contiguously
+__device__ __forceinline__ void rr_child(int t, int& a, int& cl, int& bq, int& cq) {
+    a = t & 1;
+    cl = (t >> 1) & (RR_COARSE - 1);
+    bq = (t >> 6) & 1;
+    cq = t >> 7;
+}
+__device__ __forceinline__ int rr_thread(int cl, int q) {
+    return ((q >> 2) * 2 + ((q >> 1) & 1)) * (2 * RR_COARSE) + cl * 2 + (q & 1);
+}
+
 template <typename TF, typename TC, int NC>
-__global__ void k_resid_restrict(LevelV<TF> L, const TF* __restrict__ b, const TF* __restrict__ x,
-                                 GridV gc, const uint8_t* __restrict__ mc, TC* __restrict__ bc) {
+__global__ void __launch_bounds__(RR_THREADS)
+    k_resid_restrict(LevelV<TF> L, const TF* __restrict__ b, const TF* __restrict__ x, GridV gc,
+                     const uint8_t* __restrict__ mc, TC* __restrict__ bc) {
     if (L.gate && *L.gate) return;
+    __shared__ TF rs[RR_THREADS * NC];
     long Nc = (long)gc.n[0] * gc.n[1] * gc.n[2];
-    long c = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    if (c >= Nc) return;
-    int i, j, k;
-    cell_coords(gc, c, i, j, k);
-    TF s[NC];
+    int a, cl, bq, cq;
+    rr_child(threadIdx.x, a, cl, bq, cq);
+    long c = (long)blockIdx.x * RR_COARSE + cl;
+    TF r[NC];
 #pragma unroll
-    for (int m = 0; m < NC; m++) s[m] = (TF)0;
-    for (int q = 0; q < 8; q++) {
-        int fi = 2 * i + (q & 1), fj = 2 * j + ((q >> 1) & 1), fk = 2 * k + (q >> 2);
+    for (int m = 0; m < NC; m++) r[m] = (TF)0;
+    if (c < Nc) {
+        int i, j, k;
+        cell_coords(gc, c, i, j, k);
+        int fi = 2 * i + a, fj = 2 * j + bq, fk = 2 * k + cq;
         long f = cell_index(L.grid, fi, fj, fk);
-        if (!L.mask[f]) continue;
-        TF acc[NC];
+        if (L.mask[f]) {
+            TF acc[NC];
 #pragma unroll
-        for (int m = 0; m < NC; m++) acc[m] = (TF)0;
-        offdiag<TF, NC>(L, x, fi, fj, fk, acc);
-        TF dg = L.D[f];
+            for (int m = 0; m < NC; m++) acc[m] = (TF)0;
+            offdiag<TF, NC>(L, x, fi, fj, fk, acc);
+            TF dg = L.D[f];
 #pragma unroll
-        for (int m = 0; m < NC; m++) s[m] += b[m * L.N + f] - (dg * x[m * L.N + f] - acc[m]);
+            for (int m = 0; m < NC; m++) r[m] = b[m * L.N + f] - (dg * x[m * L.N + f] - acc[m]);
+        }
     }
 #pragma unroll
-    for (int m = 0; m < NC; m++) bc[m * Nc + c] = mc[c] ? (TC)(s[m] / (TF)8) : (TC)0;
+    for (int m = 0; m < NC; m++) rs[threadIdx.x * NC + m] = r[m];
+    __syncthreads();
+    if (threadIdx.x < RR_COARSE) {
+        long cc = (long)blockIdx.x * RR_COARSE + threadIdx.x;
+        if (cc >= Nc) return;
+        TF sum[NC];
+#pragma unroll
+        for (int m = 0; m < NC; m++) sum[m] = (TF)0;
+        for (int q = 0; q < 8; q++) {
+            int t = rr_thread(threadIdx.x, q);
+#pragma unroll
+            for (int m = 0; m < NC; m++) sum[m] += rs[t * NC + m];
+        }
+#pragma unroll
+        for (int m = 0; m < NC; m++) bc[m * Nc + cc] = mc[cc] ? (TC)(sum[m] / (TF)8) : (TC)0;
+    }
 }
 
 template <typename T, int NC>
@@ -307,13 +346,270 @@ __global__ void k_prolong(GridV gf, GridV gc, const uint8_t* __restrict__ mf,
 }
 
 // ------------------------------------------------------------------------------------------
+// finest level in colour-split storage.  Vectors of level 0 are kept as [component][colour]
+// [cell of that colour in natural order]: cell c = (i, j, k) of colour (i+j+k) mod 2 sits at
+// colour * N/2 + c/2 (nx is even).  A half sweep then reads one colour of the iterate and the
+// right-hand side contiguously and writes the other contiguously.  Coefficients of regular
+// cells (all six apertures 1) are recomputed from eta with the same expressions, in the same
+// order, as the stored operator, so results are bitwise those of the stored coefficients;
+// cut cells read the stored faces and diagonal.
+// ------------------------------------------------------------------------------------------
+struct Rb0V {
+    GridV grid;
+    long N;
+    const uint8_t* flag;
+    const double* eta;
+    const float* etaf;
+    const double* K[3];
+    const double* D;
+    int sys;
+    double rho, dt, beta;
+    const int* gate;
+};
+
+__device__ __forceinline__ long rb_slot(long N, int i, int j, int k, long c) {
+    return (long)((i + j + k) & 1) * (N >> 1) + (c >> 1);
+}
+
+// the operator row of cell c: K and neighbours (natural index, -1 = none) of the six faces in
+// the order (d, lower), (d, upper); returns false when the cell is not smoothed.  In FP64 a
+// regular cell's coefficients are bitwise the stored ones; the FP32 smoother forms them in
+// FP32 from an FP32 copy of eta (cut cells round the stored FP64 values).
+template <typename T>
+__device__ __forceinline__ const T* eta_of(const Rb0V& L);
+template <>
+__device__ __forceinline__ const double* eta_of<double>(const Rb0V& L) { return L.eta; }
+template <>
+__device__ __forceinline__ const float* eta_of<float>(const Rb0V& L) { return L.etaf; }
+
+template <typename T>
+__device__ __forceinline__ bool rb0_row(const Rb0V& L, long c, int i, int j, int k, T K[6],
+                                        long nb[6], T& D) {
+    uint8_t fl = L.flag[c];
+    if (fl == 0) return false;
+    const GridV& g = L.grid;
+    if (fl == 2) {
+        const T* eta = eta_of<T>(L);
+        T h = (T)g.h, h2 = h * h;
+        T dt = (T)L.dt;
+        T s = L.sys == EB_SYS_VISC ? (T)1 * (T)L.rho : (T)0;
+        T ec = L.sys == EB_SYS_VISC ? eta[c] : (T)0;
+#pragma unroll
+        for (int d = 0; d < 3; d++)
+#pragma unroll
+            for (int side = 0; side < 2; side++) {
+                int q[3] = {i, j, k};
+                q[d] += side ? 1 : -1;
+                long n = cell_at(g, q[0], q[1], q[2]);
+                T kf;
+                if (L.sys == EB_SYS_VISC)
+                    kf = n >= 0 ? dt * (T)1 * (T)0.5 * (ec + eta[n]) / h2
+                                : (T)2 * dt * (T)1 * ec / h2;
+                else
+                    kf = n >= 0 ? (T)L.beta * (T)1 / (h * h) : (T)0;
+                s += kf;
+                K[2 * d + side] = kf;
+                nb[2 * d + side] = n;
+            }
+        D = s;
+        return D > (T)0;
+    }
+#pragma unroll
+    for (int d = 0; d < 3; d++)
+#pragma unroll
+        for (int side = 0; side < 2; side++) {
+            int f[3] = {i, j, k};
+            f[d] += side;
+            K[2 * d + side] = (T)L.K[d][face_index(g, d, f[0], f[1], f[2])];
+            int q[3] = {i, j, k};
+            q[d] += side ? 1 : -1;
+            nb[2 * d + side] = cell_at(g, q[0], q[1], q[2]);
+        }
+    D = (T)L.D[c];
+    return D > (T)0;
+}
+
+// cell coordinates of the t-th cell of colour col
+__device__ __forceinline__ void rb_cell(const GridV& g, unsigned t, int col, int& i, int& j,
+                                        int& k) {
+    unsigned nxh = (unsigned)g.n[0] >> 1;
+    unsigned row = t / nxh;
+    unsigned ih = t - row * nxh;
+    j = (int)(row % (unsigned)g.n[1]);
+    k = (int)(row / (unsigned)g.n[1]);
+    i = 2 * (int)ih + ((j + k + col) & 1);
+}
+
+template <typename T, int NC>
+__global__ void k_smooth_rb(Rb0V L, const T* __restrict__ b, T* __restrict__ x, int col) {
+    if (L.gate && *L.gate) return;
+    long N = L.N, Nh = N >> 1;
+    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t >= Nh) return;
+    int i, j, k;
+    rb_cell(L.grid, (unsigned)t, col, i, j, k);
+    long c = cell_index(L.grid, i, j, k);
+    T K[6], dg;
+    long nb[6];
+    if (!rb0_row<T>(L, c, i, j, k, K, nb, dg)) return;
+    long own = (long)col * Nh + t, oth = (long)(1 - col) * Nh;
+    T acc[NC];
+#pragma unroll
+    for (int m = 0; m < NC; m++) acc[m] = b[m * N + own];
+#pragma unroll
+    for (int f = 0; f < 6; f++) {
+        T kf = K[f];
+        if (kf == (T)0 || nb[f] < 0) continue;
+        long q = oth + (nb[f] >> 1);
+#pragma unroll
+        for (int m = 0; m < NC; m++) acc[m] += kf * x[m * N + q];
+    }
+#pragma unroll
+    for (int m = 0; m < NC; m++) x[m * N + own] = acc[m] / dg;
+}
+
+// first half sweep (colour 0) from a zero iterate over both colours: colour 0 gets b/D, colour 1
+// is zeroed
+template <typename T, int NC>
+__global__ void k_smooth_first_rb(Rb0V L, const T* __restrict__ b, T* __restrict__ x) {
+    if (L.gate && *L.gate) return;
+    long N = L.N, Nh = N >> 1;
+    long u = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (u >= N) return;
+    int col = u >= Nh ? 1 : 0;
+    long t = u - col * Nh;
+    bool upd = false;
+    T Dd = (T)1;
+    if (col == 0) {
+        int i, j, k;
+        rb_cell(L.grid, (unsigned)t, 0, i, j, k);
+        long c = cell_index(L.grid, i, j, k);
+        T K[6];
+        long nb[6];
+        upd = rb0_row<T>(L, c, i, j, k, K, nb, Dd);
+    }
+    T dg = upd ? Dd : (T)1;
+#pragma unroll
+    for (int m = 0; m < NC; m++) x[m * N + u] = upd ? (b[m * N + u] + (T)0) / dg : (T)0;
+}
+
+// residual of level 0 restricted to the coarse right-hand side (natural storage there), with
+// the thread layout and summation order of k_resid_restrict
+template <typename TF, typename TC, int NC>
+__global__ void __launch_bounds__(RR_THREADS)
+    k_resid_restrict_rb(Rb0V L, const TF* __restrict__ b, const TF* __restrict__ x, GridV gc,
+                        const uint8_t* __restrict__ mc, TC* __restrict__ bc) {
+    if (L.gate && *L.gate) return;
+    __shared__ TF rs[RR_THREADS * NC];
+    long N = L.N;
+    long Nc = (long)gc.n[0] * gc.n[1] * gc.n[2];
+    int a, cl, bq, cq;
+    rr_child(threadIdx.x, a, cl, bq, cq);
+    long c = (long)blockIdx.x * RR_COARSE + cl;
+    TF r[NC];
+#pragma unroll
+    for (int m = 0; m < NC; m++) r[m] = (TF)0;
+    if (c < Nc) {
+        int ci, cj, ck;
+        cell_coords(gc, c, ci, cj, ck);
+        int fi = 2 * ci + a, fj = 2 * cj + bq, fk = 2 * ck + cq;
+        long f = cell_index(L.grid, fi, fj, fk);
+        if (L.flag[f] != 0) {
+            TF K[6], dg;
+            long nb[6];
+            rb0_row<TF>(L, f, fi, fj, fk, K, nb, dg);
+            TF acc[NC];
+#pragma unroll
+            for (int m = 0; m < NC; m++) acc[m] = (TF)0;
+            long oth = (long)(1 - ((fi + fj + fk) & 1)) * (N >> 1);
+#pragma unroll
+            for (int e = 0; e < 6; e++) {
+                TF kf = K[e];
+                if (kf == (TF)0 || nb[e] < 0) continue;
+                long qn = oth + (nb[e] >> 1);
+#pragma unroll
+                for (int m = 0; m < NC; m++) acc[m] += kf * x[m * N + qn];
+            }
+            long qf = rb_slot(N, fi, fj, fk, f);
+#pragma unroll
+            for (int m = 0; m < NC; m++) r[m] = b[m * N + qf] - (dg * x[m * N + qf] - acc[m]);
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < NC; m++) rs[threadIdx.x * NC + m] = r[m];
+    __syncthreads();
+    if (threadIdx.x < RR_COARSE) {
+        long cc = (long)blockIdx.x * RR_COARSE + threadIdx.x;
+        if (cc >= Nc) return;
+        TF sum[NC];
+#pragma unroll
+        for (int m = 0; m < NC; m++) sum[m] = (TF)0;
+        for (int q = 0; q < 8; q++) {
+            int t = rr_thread(threadIdx.x, q);
+#pragma unroll
+            for (int m = 0; m < NC; m++) sum[m] += rs[t * NC + m];
+        }
+#pragma unroll
+        for (int m = 0; m < NC; m++) bc[m * Nc + cc] = mc[cc] ? (TC)(sum[m] / (TF)8) : (TC)0;
+    }
+}
+
+// piecewise-constant prolongation onto the open cells of level 0 (colour-split storage)
+template <typename TC, typename TF, int NC>
+__global__ void k_prolong_rb(Rb0V L, GridV gc, const TC* __restrict__ ec, TF* __restrict__ x) {
+    if (L.gate && *L.gate) return;
+    long N = L.N, Nh = N >> 1;
+    long Nc = (long)gc.n[0] * gc.n[1] * gc.n[2];
+    long u = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (u >= N) return;
+    int col = u >= Nh ? 1 : 0;
+    int i, j, k;
+    rb_cell(L.grid, (unsigned)(u - col * Nh), col, i, j, k);
+    long f = cell_index(L.grid, i, j, k);
+    if (L.flag[f] == 0) return;
+    long c = cell_index(gc, i >> 1, j >> 1, k >> 1);
+#pragma unroll
+    for (int m = 0; m < NC; m++) x[m * N + u] += (TF)ec[m * Nc + c];
+}
+
+// natural -> colour-split (with a precision change)
+template <typename TS, typename TD, int NC>
+__global__ void k_to_rb(GridV g, long N, const TS* __restrict__ a, TD* __restrict__ r,
+                        const int* gate) {
+    if (gate && *gate) return;
+    long Nh = N >> 1;
+    long u = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (u >= N) return;
+    int col = u >= Nh ? 1 : 0;
+    int i, j, k;
+    rb_cell(g, (unsigned)(u - col * Nh), col, i, j, k);
+    long c = cell_index(g, i, j, k);
+#pragma unroll
+    for (int m = 0; m < NC; m++) r[m * N + u] = (TD)a[m * N + c];
+}
+
+// colour-split -> natural (with a precision change)
+template <typename TS, typename TD, int NC>
+__global__ void k_from_rb(GridV g, long N, const TS* __restrict__ r, TD* __restrict__ a,
+                          const int* gate) {
+    if (gate && *gate) return;
+    long c = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (c >= N) return;
+    int i, j, k;
+    cell_coords(g, c, i, j, k);
+    long u = rb_slot(N, i, j, k, c);
+#pragma unroll
+    for (int m = 0; m < NC; m++) a[m * N + c] = (TD)r[m * N + u];
+}
+
+// ------------------------------------------------------------------------------------------
 // the small coarse levels of a V-cycle, all in one work-group (one launch instead of ~100):
 // the same operations in the same order as the per-level kernels, separated by barriers.  The
 // operators, right-hand sides and iterates of these levels are staged in LDS, so each of the
 // ~100 barrier-separated phases costs LDS latency instead of a global-memory round trip.
 // ------------------------------------------------------------------------------------------
 constexpr int TAIL_MAXL = 8;
-constexpr int TAIL_THREADS = 1024;
+constexpr int TAIL_THREADS = 256;
 constexpr size_t TAIL_LDS_BYTES = 65536;
 
 struct TailArgs {
@@ -351,6 +647,170 @@ __device__ void tail_sweep(const LevelV<double>& L, const double* b, double* x, 
     __syncthreads();
 }
 
+// ---- levels of at most one wavefront of cells, run by wave 0 alone: lane = cell, the other
+// ---- colour's values come through cross-lane shuffles, so no barrier is needed
+constexpr int WAVE_MAXL = 3;
+
+struct WaveRow {
+    double K[6];
+    int nb[6];     // neighbour lane (cell index), -1 where there is none
+    double D;
+    bool open;
+    int colour;
+};
+
+__device__ __forceinline__ void wave_row(const LevelV<double>& L, int lane, WaveRow& r) {
+#pragma unroll
+    for (int f = 0; f < 6; f++) {
+        r.K[f] = 0.0;
+        r.nb[f] = -1;
+    }
+    r.D = 0.0;
+    r.open = false;
+    r.colour = 0;
+    if (lane >= L.N) return;
+    int i, j, k;
+    cell_coords(L.grid, lane, i, j, k);
+    r.colour = (i + j + k) & 1;
+    r.open = L.mask[lane] != 0;
+    r.D = L.D[lane];
+#pragma unroll
+    for (int d = 0; d < 3; d++)
+#pragma unroll
+        for (int side = 0; side < 2; side++) {
+            int f[3] = {i, j, k};
+            f[d] += side;
+            r.K[2 * d + side] = L.K[d][face_index(L.grid, d, f[0], f[1], f[2])];
+            int q[3] = {i, j, k};
+            q[d] += side ? 1 : -1;
+            r.nb[2 * d + side] = (int)cell_at(L.grid, q[0], q[1], q[2]);
+        }
+}
+
+// acc = sum_f K_f x_nb(f) in face order (faces with K = 0 or no neighbour skipped)
+template <int NC>
+__device__ __forceinline__ void wave_offdiag(const WaveRow& r, int lane, const double x[NC],
+                                             double acc[NC]) {
+#pragma unroll
+    for (int f = 0; f < 6; f++) {
+        int src = r.nb[f] >= 0 ? r.nb[f] : lane;
+        bool use = r.K[f] != 0.0 && r.nb[f] >= 0;
+#pragma unroll
+        for (int m = 0; m < NC; m++) {
+            double v = __shfl(x[m], src, 64);
+            if (use) acc[m] += r.K[f] * v;
+        }
+    }
+}
+
+template <int NC>
+__device__ __forceinline__ void wave_sweep(const WaveRow& r, int lane, const double b[NC],
+                                           double x[NC], int col) {
+    double acc[NC];
+#pragma unroll
+    for (int m = 0; m < NC; m++) acc[m] = b[m];
+    wave_offdiag<NC>(r, lane, x, acc);
+    bool upd = r.open && r.colour == col && r.D > 0.0;
+#pragma unroll
+    for (int m = 0; m < NC; m++)
+        if (upd) x[m] = acc[m] / r.D;
+}
+
+// levels [w0, w0 + nw) of the tail (each at most 64 cells) by wave 0: b of level w0 is read
+// from LDS, its correction x written back to LDS; same operations and order as the
+// barrier-separated version
+template <int NC>
+__device__ void wave_levels(const LevelV<double>* Lw, int nw, int nu1, int nu2, int nbottom,
+                            const double* b0, double* x0) {
+    int lane = threadIdx.x;
+    WaveRow R[WAVE_MAXL];
+    double xs[WAVE_MAXL][NC], bs[WAVE_MAXL][NC];
+#pragma unroll
+    for (int v = 0; v < WAVE_MAXL; v++) {
+        if (v < nw) wave_row(Lw[v], lane, R[v]);
+#pragma unroll
+        for (int m = 0; m < NC; m++) {
+            xs[v][m] = 0.0;
+            bs[v][m] = 0.0;
+        }
+    }
+    if (lane < Lw[0].N)
+#pragma unroll
+        for (int m = 0; m < NC; m++) bs[0][m] = b0[m * Lw[0].N + lane];
+#pragma unroll
+    for (int v = 0; v < WAVE_MAXL; v++) {
+        if (v == nw - 1) {
+            for (int s = 0; s < nbottom; s++) {
+                wave_sweep<NC>(R[v], lane, bs[v], xs[v], 0);
+                wave_sweep<NC>(R[v], lane, bs[v], xs[v], 1);
+            }
+            for (int s = 0; s < nbottom; s++) {
+                wave_sweep<NC>(R[v], lane, bs[v], xs[v], 1);
+                wave_sweep<NC>(R[v], lane, bs[v], xs[v], 0);
+            }
+        }
+        if (v >= nw - 1) continue;
+        for (int s = 0; s < nu1; s++) {
+            wave_sweep<NC>(R[v], lane, bs[v], xs[v], 0);
+            wave_sweep<NC>(R[v], lane, bs[v], xs[v], 1);
+        }
+        if (v + 1 < WAVE_MAXL) {
+            // residual of this level, then the mean of the eight children on the next
+            double r[NC];
+            {
+                double acc[NC];
+#pragma unroll
+                for (int m = 0; m < NC; m++) acc[m] = 0.0;
+                wave_offdiag<NC>(R[v], lane, xs[v], acc);
+#pragma unroll
+                for (int m = 0; m < NC; m++)
+                    r[m] = R[v].open ? bs[v][m] - (R[v].D * xs[v][m] - acc[m]) : 0.0;
+            }
+            const LevelV<double>& F = Lw[v];
+            const LevelV<double>& C = Lw[v + 1];
+            int ci = 0, cj = 0, ck = 0;
+            if (lane < C.N) cell_coords(C.grid, lane, ci, cj, ck);
+            double sum[NC];
+#pragma unroll
+            for (int m = 0; m < NC; m++) sum[m] = 0.0;
+            for (int q = 0; q < 8; q++) {
+                int src = lane < C.N ? (int)cell_index(F.grid, 2 * ci + (q & 1),
+                                                       2 * cj + ((q >> 1) & 1), 2 * ck + (q >> 2))
+                                     : lane;
+#pragma unroll
+                for (int m = 0; m < NC; m++) sum[m] += __shfl(r[m], src, 64);
+            }
+            bool copen = lane < C.N && C.mask[lane];
+#pragma unroll
+            for (int m = 0; m < NC; m++) bs[v + 1][m] = copen ? sum[m] / 8.0 : 0.0;
+        }
+    }
+#pragma unroll
+    for (int v = WAVE_MAXL - 2; v >= 0; v--) {
+        if (v >= nw - 1) continue;
+        const LevelV<double>& F = Lw[v];
+        const LevelV<double>& C = Lw[v + 1];
+        int src = lane;
+        if (lane < F.N) {
+            int i, j, k;
+            cell_coords(F.grid, lane, i, j, k);
+            src = (int)cell_index(C.grid, i >> 1, j >> 1, k >> 1);
+        }
+#pragma unroll
+        for (int m = 0; m < NC; m++) {
+            double e = __shfl(xs[v + 1][m], src, 64);
+            if (lane < F.N && R[v].open) xs[v][m] += e;
+        }
+        for (int s = 0; s < nu2; s++) {
+            wave_sweep<NC>(R[v], lane, bs[v], xs[v], 1);
+            wave_sweep<NC>(R[v], lane, bs[v], xs[v], 0);
+        }
+    }
+    if (lane < Lw[0].N)
+#pragma unroll
+        for (int m = 0; m < NC; m++) x0[m * Lw[0].N + lane] = xs[0][m];
+}
+
 template <int NC>
 __global__ void __launch_bounds__(TAIL_THREADS) k_vcycle_tail(TailArgs A) {
     if (A.gate && *A.gate) return;
@@ -379,6 +839,7 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_vcycle_tail(TailArgs A) {
     __syncthreads();
     auto lv = [&](int l) {
         LevelV<double> v = A.L[l];
+#pragma unroll
         for (int d = 0; d < 3; d++) v.K[d] = reinterpret_cast<const double*>(lds + A.oK[l][d]);
         v.D = reinterpret_cast<const double*>(lds + A.oD[l]);
         v.mask = reinterpret_cast<const uint8_t*>(lds + A.om[l]);
@@ -386,7 +847,10 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_vcycle_tail(TailArgs A) {
     };
     auto X = [&](int l) { return reinterpret_cast<double*>(lds + A.ox[l]); };
     auto B = [&](int l) { return reinterpret_cast<double*>(lds + A.ob[l]); };
-    for (int l = 0; l < nl; l++) {
+    // first level small enough for one wavefront (all coarser ones are smaller)
+    int w0 = nl;
+    while (w0 > 0 && A.L[w0 - 1].N <= 64 && nl - (w0 - 1) <= WAVE_MAXL) w0--;
+    for (int l = 0; l < w0; l++) {
         LevelV<double> L = lv(l);
         double* x = X(l);
         double* b = B(l);
@@ -429,7 +893,15 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_vcycle_tail(TailArgs A) {
         }
         __syncthreads();
     }
-    for (int l = nl - 2; l >= 0; l--) {
+    if (w0 < nl) {
+        if (threadIdx.x < 64) {
+            LevelV<double> Lw[WAVE_MAXL];
+            for (int v = 0; v < WAVE_MAXL; v++) Lw[v] = lv(w0 + (w0 + v < nl ? v : 0));
+            wave_levels<NC>(Lw, nl - w0, A.nu1, A.nu2, A.nbottom, B(w0), X(w0));
+        }
+        __syncthreads();
+    }
+    for (int l = (w0 < nl ? w0 : nl - 1) - 1; l >= 0; l--) {
         LevelV<double> L = lv(l);
         LevelV<double> C = lv(l + 1);
         double* x = X(l);
@@ -474,15 +946,16 @@ size_t tail_layout(const Level* lev, int nlev, int t, int nc, TailArgs* A) {
 // ------------------------------------------------------------------------------------------
 // exact EB viscous Helmholtz operator (Eq. implicit-viscous with the wall flux of Eq. dudn)
 // ------------------------------------------------------------------------------------------
-__global__ void k_visc_apply(GeomV g, double rho, double dt, const double* __restrict__ eta,
+__global__ void __launch_bounds__(EB_BLOCK) k_visc_apply(GeomV g, double rho, double dt,
+                                                         const double* __restrict__ eta,
                              const double* __restrict__ eta_eb, const double* __restrict__ u,
                              double* __restrict__ out, int homog, const int* gate) {
     if (gate && *gate) return;
     long N = g.N;
     long c = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (c >= N) return;
-    double al = g.alpha[c];
-    if (!(al > 0.0)) {
+    uint8_t fl = g.flag[c];
+    if (fl == 0) {
         for (int m = 0; m < 3; m++) out[m * N + c] = 0.0;
         return;
     }
@@ -490,9 +963,36 @@ __global__ void k_visc_apply(GeomV g, double rho, double dt, const double* __res
     cell_coords(g.grid, c, i, j, k);
     double h2 = g.grid.h * g.grid.h;
     double acc[3];
-    for (int m = 0; m < 3; m++) acc[m] = al * rho * u[m * N + c];
     double ec = eta[c];
+    if (fl == 2) {
+        // regular cell: volume fraction and all six apertures are 1, no wall flux
+        for (int m = 0; m < 3; m++) acc[m] = 1.0 * rho * u[m * N + c];
+#pragma unroll
+        for (int d = 0; d < 3; d++)
+#pragma unroll
+            for (int side = 0; side < 2; side++) {
+                int q[3] = {i, j, k};
+                q[d] += side ? 1 : -1;
+                long nb = cell_at(g.grid, q[0], q[1], q[2]);
+                if (nb >= 0) {
+                    double K = dt * 1.0 * 0.5 * (ec + eta[nb]) / h2;
+                    for (int m = 0; m < 3; m++) acc[m] -= K * (u[m * N + nb] - u[m * N + c]);
+                } else {
+                    double K = 2.0 * dt * 1.0 * ec / h2;
+                    for (int m = 0; m < 3; m++) {
+                        double uw = homog ? 0.0 : g.wall[2 * d + side][m];
+                        acc[m] -= K * (uw - u[m * N + c]);
+                    }
+                }
+            }
+        for (int m = 0; m < 3; m++) out[m * N + c] = acc[m];
+        return;
+    }
+    double al = g.alpha[c];
+    for (int m = 0; m < 3; m++) acc[m] = al * rho * u[m * N + c];
+#pragma unroll
     for (int d = 0; d < 3; d++)
+#pragma unroll
         for (int side = 0; side < 2; side++) {
             int f[3] = {i, j, k};
             f[d] += side;
@@ -518,6 +1018,7 @@ __global__ void k_visc_apply(GeomV g, double rho, double dt, const double* __res
         double d1 = g.dd[q], d2 = g.dd[nc + q];
         double den = d1 * d2 * (d2 - d1) * g.grid.h;
         double coef = dt * g.aeb[q] * eta_eb[q] / g.grid.h;
+#pragma unroll
         for (int m = 0; m < 3; m++) {
             double ue = homog ? 0.0 : g.ueb[m];
             double s1 = 0.0, s2 = 0.0;
@@ -704,7 +1205,7 @@ __global__ void k_mask_rhs(GeomV g, const double* __restrict__ psi, const double
     long N = g.N;
     long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (t >= 3 * N) return;
-    long c = t % N;
+    long c = (long)((unsigned)t % (unsigned)N);  // 3N < 2^32
     double al = g.alpha[c];
     b[t] = al > 0.0 ? al * psi[t] - a0[t] : 0.0;
 }
@@ -766,12 +1267,13 @@ void first_pass(const Level& L, int nc, const T* b, T* x, hipStream_t s) {
 template <typename TF, typename TC>
 void resid_restrict_pass(const Level& F, const Level& C, int nc, const TF* b, const TF* x,
                          TC* bc, hipStream_t s) {
+    unsigned gr = grid_for(C.N, RR_COARSE);
     if (nc == 3)
-        k_resid_restrict<TF, TC, 3><<<grid_for(C.N), EB_BLOCK, 0, s>>>(level_view<TF>(F), b, x,
-                                                                      C.grid, C.mask, bc);
+        k_resid_restrict<TF, TC, 3><<<gr, RR_THREADS, 0, s>>>(level_view<TF>(F), b, x, C.grid,
+                                                              C.mask, bc);
     else
-        k_resid_restrict<TF, TC, 1><<<grid_for(C.N), EB_BLOCK, 0, s>>>(level_view<TF>(F), b, x,
-                                                                      C.grid, C.mask, bc);
+        k_resid_restrict<TF, TC, 1><<<gr, RR_THREADS, 0, s>>>(level_view<TF>(F), b, x, C.grid,
+                                                              C.mask, bc);
 }
 template <typename TC, typename TF>
 void prolong_pass(const Level& F, const Level& C, int nc, const TC* ec, TF* xf, hipStream_t s) {
@@ -779,6 +1281,30 @@ void prolong_pass(const Level& F, const Level& C, int nc, const TC* ec, TF* xf, 
         k_prolong<TC, TF, 3><<<grid_for(F.N), EB_BLOCK, 0, s>>>(F.grid, C.grid, F.mask, ec, xf, F.gate);
     else
         k_prolong<TC, TF, 1><<<grid_for(F.N), EB_BLOCK, 0, s>>>(F.grid, C.grid, F.mask, ec, xf, F.gate);
+}
+
+Rb0V rb0_view(const Level& L) {
+    Rb0V v;
+    v.grid = L.grid;
+    v.N = L.N;
+    v.flag = L.flag;
+    v.eta = L.eta;
+    v.etaf = L.etaf;
+    for (int d = 0; d < 3; d++) v.K[d] = L.K[d];
+    v.D = L.D;
+    v.sys = L.sys;
+    v.rho = L.rho;
+    v.dt = L.dt;
+    v.beta = L.beta;
+    v.gate = L.gate;
+    return v;
+}
+
+template <typename T>
+void smooth_rb_pass(const Level& L, int nc, const T* b, T* x, int col, hipStream_t s) {
+    unsigned gb = grid_for(L.N / 2);
+    if (nc == 3) k_smooth_rb<T, 3><<<gb, EB_BLOCK, 0, s>>>(rb0_view(L), b, x, col);
+    else k_smooth_rb<T, 1><<<gb, EB_BLOCK, 0, s>>>(rb0_view(L), b, x, col);
 }
 
 // first level handled by the one-work-group tail: the largest set of coarsest levels whose
@@ -880,6 +1406,60 @@ void vcycle_rec(const VArgs& a, int l) {
     else vcycle_level<double>(a, l);
 }
 
+// level 0 of a V-cycle in colour-split storage (it is neither the coarsest nor a tail level):
+// b and x are the level's own colour-split arrays
+template <typename T>
+void vcycle_level0_rb(const VArgs& a, T* b, T* x) {
+    Level& L = a.lev[0];
+    Level& C = a.lev[1];
+    Rb0V v = rb0_view(L);
+    int nc = a.nc;
+    for (int t = 0; t < a.nu1; t++) {
+        if (t == 0) {
+            if (nc == 3) k_smooth_first_rb<T, 3><<<grid_for(L.N), EB_BLOCK, 0, a.s>>>(v, b, x);
+            else k_smooth_first_rb<T, 1><<<grid_for(L.N), EB_BLOCK, 0, a.s>>>(v, b, x);
+        } else {
+            smooth_rb_pass<T>(L, nc, b, x, 0, a.s);
+        }
+        smooth_rb_pass<T>(L, nc, b, x, 1, a.s);
+    }
+    if (a.nu1 < 1) k_zero<T><<<grid_for(nc * L.N), EB_BLOCK, 0, a.s>>>(nc * L.N, x, L.gate);
+    bool cf32 = level_f32(a, 1);
+    unsigned gc = grid_for(C.N, RR_COARSE);
+    if (cf32) {
+        if (nc == 3) k_resid_restrict_rb<T, float, 3><<<gc, RR_THREADS, 0, a.s>>>(v, b, x, C.grid, C.mask, C.bf);
+        else k_resid_restrict_rb<T, float, 1><<<gc, RR_THREADS, 0, a.s>>>(v, b, x, C.grid, C.mask, C.bf);
+    } else {
+        if (nc == 3) k_resid_restrict_rb<T, double, 3><<<gc, RR_THREADS, 0, a.s>>>(v, b, x, C.grid, C.mask, C.b);
+        else k_resid_restrict_rb<T, double, 1><<<gc, RR_THREADS, 0, a.s>>>(v, b, x, C.grid, C.mask, C.b);
+    }
+    vcycle_rec(a, 1);
+    unsigned gf = grid_for(L.N);
+    if (cf32) {
+        if (nc == 3) k_prolong_rb<float, T, 3><<<gf, EB_BLOCK, 0, a.s>>>(v, C.grid, C.xf, x);
+        else k_prolong_rb<float, T, 1><<<gf, EB_BLOCK, 0, a.s>>>(v, C.grid, C.xf, x);
+    } else {
+        if (nc == 3) k_prolong_rb<double, T, 3><<<gf, EB_BLOCK, 0, a.s>>>(v, C.grid, C.x, x);
+        else k_prolong_rb<double, T, 1><<<gf, EB_BLOCK, 0, a.s>>>(v, C.grid, C.x, x);
+    }
+    for (int t = 0; t < a.nu2; t++) {
+        smooth_rb_pass<T>(L, nc, b, x, 1, a.s);
+        smooth_rb_pass<T>(L, nc, b, x, 0, a.s);
+    }
+}
+
+template <typename T>
+void vcycle_rb(const VArgs& a, const double* b, double* x, T* brb, T* xrb, const int* gate) {
+    Level& L0 = a.lev[0];
+    long N = L0.N;
+    unsigned g = grid_for(N);
+    if (a.nc == 3) k_to_rb<double, T, 3><<<g, EB_BLOCK, 0, a.s>>>(L0.grid, N, b, brb, gate);
+    else k_to_rb<double, T, 1><<<g, EB_BLOCK, 0, a.s>>>(L0.grid, N, b, brb, gate);
+    vcycle_level0_rb<T>(a, brb, xrb);
+    if (a.nc == 3) k_from_rb<T, double, 3><<<g, EB_BLOCK, 0, a.s>>>(L0.grid, N, xrb, x, gate);
+    else k_from_rb<T, double, 1><<<g, EB_BLOCK, 0, a.s>>>(L0.grid, N, xrb, x, gate);
+}
+
 void finish_operator(Level* lev, int nlev, bool mixed, hipStream_t s) {
     int tail = tail_level(lev, nlev);
     for (int l = 1; l < nlev; l++) {
@@ -906,6 +1486,10 @@ void finish_operator(Level* lev, int nlev, bool mixed, hipStream_t s) {
 
 void mg_build_poisson(Level* lev, int nlev, const GeomV& g, double beta, bool mixed,
                       hipStream_t s) {
+    lev[0].flag = g.flag;
+    lev[0].eta = nullptr;
+    lev[0].sys = EB_SYS_POISSON;
+    lev[0].beta = beta;
     for (int d = 0; d < 3; d++)
         k_K_poisson<<<grid_for(face_count(g.grid, d)), EB_BLOCK, 0, s>>>(g, d, beta, lev[0].K[d]);
     k_zero<double><<<grid_for(g.N), EB_BLOCK, 0, s>>>(g.N, lev[0].S);
@@ -914,6 +1498,13 @@ void mg_build_poisson(Level* lev, int nlev, const GeomV& g, double beta, bool mi
 
 void mg_build_visc(Level* lev, int nlev, const GeomV& g, double rho, double dt,
                    const double* eta, const double* eta_eb, bool mixed, hipStream_t s) {
+    lev[0].flag = g.flag;
+    lev[0].eta = eta;
+    lev[0].sys = EB_SYS_VISC;
+    lev[0].rho = rho;
+    lev[0].dt = dt;
+    if (mixed && lev[0].etaf)
+        k_to_float<<<grid_for(g.N), EB_BLOCK, 0, s>>>(g.N, eta, lev[0].etaf);
     for (int d = 0; d < 3; d++)
         k_K_visc<<<grid_for(face_count(g.grid, d)), EB_BLOCK, 0, s>>>(g, d, dt, eta, lev[0].K[d]);
     k_S_visc<<<grid_for(g.N), EB_BLOCK, 0, s>>>(g, rho, dt, eta_eb, lev[0].S);
@@ -928,6 +1519,13 @@ void mg_vcycle(Level* lev, int nlev, int ncomp, bool mixed, const double* b, dou
             tail_layout(lev, nlev, tl, ncomp, nullptr) <= TAIL_LDS_BYTES};
     Level& L0 = lev[0];
     long n = (long)ncomp * L0.N;
+    if (nlev > 1 && !(a.tail == 0 && a.tail_fits) && L0.flag) {
+        // the finest level in colour-split storage (its own arrays)
+        if (level_f32(a, 0)) vcycle_rb<float>(a, b, x, L0.bf, L0.xf, gate);
+        else vcycle_rb<double>(a, b, x, L0.b, L0.x, gate);
+        for (int l = 0; l < nlev; l++) lev[l].gate = nullptr;
+        return;
+    }
     // level 0 works on the caller's arrays in FP64 mode; in mixed mode on FP32 copies
     double* keep_b = L0.b;
     double* keep_x = L0.x;
@@ -948,9 +1546,9 @@ void mg_vcycle(Level* lev, int nlev, int ncomp, bool mixed, const double* b, dou
 void mg_sweep_level0(const Level& L, int ncomp, bool f32, const void* b, void* x, int colour,
                      hipStream_t s) {
     if (f32)
-        smooth_pass<float>(L, ncomp, (const float*)b, (float*)x, colour, s);
+        smooth_rb_pass<float>(L, ncomp, (const float*)b, (float*)x, colour, s);
     else
-        smooth_pass<double>(L, ncomp, (const double*)b, (double*)x, colour, s);
+        smooth_rb_pass<double>(L, ncomp, (const double*)b, (double*)x, colour, s);
 }
 
 void mg_apply_level0(const Level& L, int ncomp, const double* x, double* y, hipStream_t s,

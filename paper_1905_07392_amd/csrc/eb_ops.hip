@@ -364,7 +364,7 @@ __global__ void k_axpy_open(GeomV g, double a, const double* __restrict__ x,
     long N = g.N;
     long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (t >= N * ncomp) return;
-    long c = t % N;
+    long c = (long)((unsigned)t % (unsigned)N);  // 3N < 2^32
     if (g.alpha[c] > 0.0) y[t] += a * x[t];
 }
 

@@ -246,3 +246,50 @@ def test_bench_size_properties():
     eta_g, eb_g = P.api.eb_apparent_viscosity(P.ctx, P.rheo, u)
     assert rel_l2(cpu(eta_g), eta_ref, P.open) <= 1e-12
     assert rel_l2(cpu(eb_g), eb_ref) <= 1e-12
+
+
+def test_graph_replay_matches_eager():
+    """Solver iterations replayed from captured graphs give bitwise the results of launching
+    every kernel: four steps each way from the same state, with eager work (drag, pressure
+    gradient) and synchronisations between the replays, compared after every step; then both
+    precisions and the transposed solves of the adjoint."""
+    import paper_1905_07392_amd as pkg
+    from paper_1905_07392_amd import api
+
+    _require_gpu()
+    w = I.sphere_n(32, 0.2)
+    box, body, rheo, opts = pkg.from_workload(w)
+    ctx = api.eb_geometry_build(box, body, "cuda:0")
+    from oracle import oracle as O
+
+    og = O.Geometry(w)
+    u0, p0 = O.prepare_state(w, og, O.make_opts(w))
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")  # noqa: E731
+    for precision in (0, 1):
+        opts.precision = precision
+        runs = []
+        for graphs in (True, False):
+            ctx.set_graphs(graphs)
+            u, p = dev(u0), dev(p0)
+            outs = []
+            for s in range(4):
+                u, p, st = api.eb_rk2_step(ctx, rheo, w.dt, opts, u, p)
+                api.eb_drag(ctx, rheo, u, p)
+                api.eb_pressure_gradient(ctx, p)
+                torch.cuda.synchronize()
+                outs.append((u.clone(), p.clone(), st["vcycles"]))
+            runs.append(outs)
+        for (ua, pa, va), (ub, pb, vb) in zip(*runs):
+            assert torch.equal(ua, ub) and torch.equal(pa, pb) and va == vb
+    opts.precision = 0
+    res = []
+    for graphs in (True, False):
+        ctx.set_graphs(graphs)
+        tape = api.new_tape(ctx)
+        u1, p1, _ = api.eb_rk2_step_taped(ctx, rheo, w.dt, opts, dev(u0), dev(p0), tape)
+        ub = torch.ones_like(u1)
+        pb = torch.ones_like(p1)
+        res.append(api.eb_rk2_step_adjoint(ctx, rheo, w.dt, opts, dev(u0), tape, ub, pb)[:3])
+    for a, b in zip(*res):
+        assert torch.equal(a, b)
+    ctx.set_graphs(True)
