@@ -40,6 +40,11 @@ def parse():
     ap.add_argument("--adjoint-steps", type=int, default=20,
                     help="steps of the adjoint/forward ratio run (0 skips it)")
     ap.add_argument("--ckpt-every", type=int, default=5)
+    ap.add_argument("--adjoint-fd", type=int, default=0,
+                    help="also check the adjoint against central finite differences in Bi and "
+                         "in this many seeded cells next to the body")
+    ap.add_argument("--adjoint-fd-steps", type=int, default=5,
+                    help="horizon of the finite-difference check (steps of the same run)")
     return ap.parse_args()
 
 
@@ -51,6 +56,28 @@ def smoother_bytes_per_launch(N, ncomp, w):
     formed from (w) and the cell-type flag (1 byte): 10 w + 1 bytes for three components
     (81 in FP64, 41 in FP32)."""
     return (N // 2) * (3 * ncomp * w + w + 1)
+
+
+def counted_traffic(tag):
+    """HBM bytes per launch of the finest-level smoother from the committed byte-counter summary
+    (profiles/), or None when there is none for this precision or the kernel source has changed
+    since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"k_smooth_rb_sphere128_{tag}_counters.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("#", "|", " ", "`")):
+            key, _, val = line.partition(":")
+            fields[key.strip()] = val.strip()
+    csrc = os.path.join(ROOT, "paper_1905_07392_amd", "csrc")
+    src = b"".join(open(os.path.join(csrc, f), "rb").read() for f in ("eb_mg.hip", "eb_internal.hpp"))
+    if fields.get("source_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    val = fields.get(f"traffic_bytes_per_launch_{tag}")
+    return int(val) if val else None
 
 
 def time_smoother(api, ctx, precision, sweeps, torch):
@@ -74,7 +101,7 @@ def time_smoother(api, ctx, precision, sweeps, torch):
     return e0.elapsed_time(e1) / sweeps
 
 
-def adjoint_ratio(api, AG, ctx, w, opts, nsteps, every, torch, I):
+def adjoint_ratio(api, AG, ctx, w, opts, nsteps, every, torch, I, fd_cells=0, fd_steps=5):
     """Adjoint run: the 128^3 sphere with tau0_c = Bi theta_c (theta = 1 + 0.05 U(-1,1), seed 1,
     Bi = 10), u starting at the wall velocity, nsteps steps with checkpoints every `every`;
     loss = z-force on the sphere.  Returns wall times of the forward (nsteps steps + drag) and of
@@ -98,10 +125,85 @@ def adjoint_ratio(api, AG, ctx, w, opts, nsteps, every, torch, I):
     fz.backward()
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    return {"steps": nsteps, "ckpt_every": every, "fwd_s": round(t1 - t0, 4),
-            "bwd_s": round(t2 - t1, 4), "ratio": round((t2 - t1) / (t1 - t0), 3),
-            "Fz": fz.item(), "dFz_dBi": bi.grad.item(),
-            "dFz_dtheta_maxabs": theta.grad.abs().max().item()}
+    out = {"steps": nsteps, "ckpt_every": every, "fwd_s": round(t1 - t0, 4),
+           "bwd_s": round(t2 - t1, 4), "ratio": round((t2 - t1) / (t1 - t0), 3),
+           "Fz": fz.item(), "dFz_dBi": bi.grad.item(),
+           "dFz_dtheta_maxabs": theta.grad.abs().max().item()}
+    if fd_cells > 0:
+        # the gradient checked is that of the run with the finite differences' tolerance
+        o2 = copy.copy(o)
+        o2.rtol_visc = o2.rtol_mac = o2.rtol_proj = 10 * FD_RTOL
+        th2 = theta.detach().clone().requires_grad_(True)
+        bi2 = torch.tensor(float(w.tau0), dtype=torch.float64, device=dev, requires_grad=True)
+        u, p = AG.rollout(ctx, rheo, w.dt, o2, u0, p0, th2, bi2, fd_steps, ckpt_every=every)
+        AG.drag(ctx, rheo, u, p, th2, bi2)[2].backward()
+        out["fd"] = adjoint_fd(api, ctx, w, o, rheo, u0, p0, theta.detach(), bi2.grad.item(),
+                               th2.grad.detach(), fd_steps, fd_cells, torch, I)
+    return out
+
+
+FD_RTOL = 1e-14   # forward solves of the finite-difference runs
+FD_BI_STEP = 1e-6  # relative step in Bi
+FD_CELL_STEP = 1e-3  # relative step in one cell's yield-stress multiplier
+
+
+def adjoint_fd(api, ctx, w, o, rheo, u0, p0, theta, g_bi, g_theta, nsteps, ncells, torch, I):
+    """Central differences of the same loss in Bi and in the yield-stress multiplier of `ncells`
+    fluid cells within 3h of the body (drawn with seed 2), against the adjoint.  Each entry states
+    the floors of the difference: rounding eps |L| / (step |g|) and solver tolerance
+    rtol |L| / (step |g|).  One cell moves the loss by |g| step ~ 1e-10 |L| for a 1e-6 step, below
+    the solver floor, so cells take a larger step (their response stays linear over it)."""
+    import copy
+
+    import numpy as np
+
+    fo = copy.copy(o)
+    fo.rtol_visc = fo.rtol_mac = fo.rtol_proj = FD_RTOL
+
+    def loss(bi, th):
+        r = api.make_rheology(rheo.law, rheo.mu, bi, rheo.eps, rheo.rho)
+        u, p = u0.clone(), p0.clone()
+        for _ in range(nsteps):
+            # near 1e-14 a solve may stagnate one notch above rtol; its result is kept
+            api.eb_rk2_step(ctx, r, w.dt, fo, u, p, theta=th, inplace=True, allow_noconv=True)
+        return api.eb_drag(ctx, r, u, p, theta=th)[2]
+
+    L0 = loss(w.tau0, theta)
+    eps = 2.2e-16
+    h = FD_BI_STEP * w.tau0
+    fd = (loss(w.tau0 + h, theta) - loss(w.tau0 - h, theta)) / (2 * h)
+    res = {"steps": nsteps, "rtol": FD_RTOL, "bi_step_rel": FD_BI_STEP,
+           "cell_step_rel": FD_CELL_STEP,
+           "bi": {"adjoint": g_bi, "fd": fd, "rel_err": abs(fd - g_bi) / abs(g_bi),
+                  "floor_round": eps * abs(L0) / (h * abs(g_bi)),
+                  "floor_solver": FD_RTOL * abs(L0) / (h * abs(g_bi))}}
+    # candidate cells: open, centre within 3h of the sphere surface
+    nz, ny, nx = ctx.shape
+    zz, yy, xx = np.meshgrid(*[(np.arange(n) + 0.5) * w.h for n in (nz, ny, nx)], indexing="ij")
+    c = w.body["center"]
+    dist = np.sqrt((xx - c[0]) ** 2 + (yy - c[1]) ** 2 + (zz - c[2]) ** 2) - w.body["radius"]
+    _, alpha, _, _, _ = api.eb_geometry_export(ctx)
+    cand = np.flatnonzero((alpha.cpu().numpy() > 0).ravel() & (np.abs(dist).ravel() < 3 * w.h))
+    picks = I.rng(2).choice(cand, size=ncells, replace=False)
+    gt = g_theta.cpu().numpy().ravel()
+    cells = []
+    for cidx in picks:
+        t0 = float(theta.view(-1)[cidx])
+        hc = FD_CELL_STEP * t0
+        tp, tm = theta.clone().view(-1), theta.clone().view(-1)
+        tp[cidx] += hc
+        tm[cidx] -= hc
+        fdc = (loss(w.tau0, tp.view(theta.shape)) - loss(w.tau0, tm.view(theta.shape))) / (2 * hc)
+        g = float(gt[cidx])
+        ga = max(abs(g), 1e-300)
+        cells.append({"cell": int(cidx), "adjoint": g, "fd": fdc, "rel_err": abs(fdc - g) / ga,
+                      "floor_round": eps * abs(L0) / (hc * ga),
+                      "floor_solver": FD_RTOL * abs(L0) / (hc * ga)})
+        print(f"[bench] fd cell {cidx}: adjoint {g:.9e} fd {fdc:.9e}", file=sys.stderr,
+              flush=True)
+    res["cells"] = cells
+    res["max_rel_err_cells"] = max(x["rel_err"] for x in cells)
+    return res
 
 
 def cpu_baseline(w, u0, p0, n_steps=1):
@@ -157,7 +259,15 @@ def main():
         api.eb_mg_vcycle(ctx, api.EB_SYS_VISC, r, opts, precision=prec, rho=w.rho, dt=w.dt,
                          eta=eta, eta_eb=eta_eb)
         ms = time_smoother(api, ctx, prec, args.sweeps, torch)
-        print(json.dumps({"kernel": "k_smooth_rb<3> finest level", "avg_ms": ms}))
+        # a plain device copy of known size (3N doubles read, 3N written) calibrates the
+        # hardware byte counters read by a profiler over this run
+        src = torch.randn((3,) + ctx.shape, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(args.sweeps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"kernel": "k_smooth_rb<3> finest level", "avg_ms": ms,
+                          "copy_bytes_each_way": src.numel() * 8}))
         return
 
     print(f"[bench] {w.name} n={w.n} precision={args.precision} warmup={args.warmup} "
@@ -189,8 +299,9 @@ def main():
     wbytes = 4 if prec == api.EB_MIXED else 8
     algo = smoother_bytes_per_launch(ctx.N, 3, wbytes)
     achieved = algo / (ms_k * 1e-3) / 1e9
+    traffic = counted_traffic("fp64" if prec == api.EB_FP64 else "mixed") if args.n == 128 else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "k_smooth_rb (finest level, 3 components, one colour)",
                 "kernel_ms": round(ms_k, 5), "bytes_per_launch": int(algo)}
 
@@ -208,7 +319,8 @@ def main():
     if args.adjoint_steps > 0:
         from paper_1905_07392_amd import autograd as AG
 
-        adj = adjoint_ratio(api, AG, ctx, w, opts, args.adjoint_steps, args.ckpt_every, torch, I)
+        adj = adjoint_ratio(api, AG, ctx, w, opts, args.adjoint_steps, args.ckpt_every, torch, I,
+                            fd_cells=args.adjoint_fd, fd_steps=args.adjoint_fd_steps)
         out["adjoint"] = adj
         print(f"[bench] adjoint: {adj}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:

@@ -99,6 +99,15 @@ __host__ __device__ inline void cell_coords(const GridV& g, long c, int& i, int&
     k = (int)k2;
 }
 
+// Work-group index remapped so that each of the 8 XCDs, which receive work-groups round-robin,
+// processes one contiguous range of tiles: vertically neighbouring rows and planes of a stencil
+// then share that XCD's L2 instead of being fetched again by another XCD.
+__device__ __forceinline__ unsigned xcd_block() {
+    unsigned nb = gridDim.x, b = blockIdx.x;
+    unsigned q = nb >> 3, r = nb & 7, x = b & 7, i = b >> 3;
+    return x * q + (x < r ? x : r) + i;
+}
+
 inline unsigned grid_for(long n, int block = EB_BLOCK) {
     long b = (n + block - 1) / block;
     return (unsigned)(b > 0 ? b : 1);

@@ -363,7 +363,8 @@ struct Rb0V {
     const double* K[3];
     const double* D;
     int sys;
-    double rho, dt, beta;
+    double rho;
+    double kin, kwall, kpois;  // dt/(2h^2), 2dt/h^2, beta/h^2
     const int* gate;
 };
 
@@ -389,10 +390,11 @@ __device__ __forceinline__ bool rb0_row(const Rb0V& L, long c, int i, int j, int
     if (fl == 0) return false;
     const GridV& g = L.grid;
     if (fl == 2) {
+        // all six apertures are 1: K = dt (eta_c + eta_n)/(2 h^2) inside, 2 dt eta_c/h^2 on a
+        // domain wall (viscous); beta/h^2 inside, 0 on a wall (Poisson)
         const T* eta = eta_of<T>(L);
-        T h = (T)g.h, h2 = h * h;
-        T dt = (T)L.dt;
-        T s = L.sys == EB_SYS_VISC ? (T)1 * (T)L.rho : (T)0;
+        T kin = (T)L.kin, kwall = (T)L.kwall, kp = (T)L.kpois;
+        T s = L.sys == EB_SYS_VISC ? (T)L.rho : (T)0;
         T ec = L.sys == EB_SYS_VISC ? eta[c] : (T)0;
 #pragma unroll
         for (int d = 0; d < 3; d++)
@@ -402,11 +404,8 @@ __device__ __forceinline__ bool rb0_row(const Rb0V& L, long c, int i, int j, int
                 q[d] += side ? 1 : -1;
                 long n = cell_at(g, q[0], q[1], q[2]);
                 T kf;
-                if (L.sys == EB_SYS_VISC)
-                    kf = n >= 0 ? dt * (T)1 * (T)0.5 * (ec + eta[n]) / h2
-                                : (T)2 * dt * (T)1 * ec / h2;
-                else
-                    kf = n >= 0 ? (T)L.beta * (T)1 / (h * h) : (T)0;
+                if (L.sys == EB_SYS_VISC) kf = n >= 0 ? kin * (ec + eta[n]) : kwall * ec;
+                else kf = n >= 0 ? kp : (T)0;
                 s += kf;
                 K[2 * d + side] = kf;
                 nb[2 * d + side] = n;
@@ -444,7 +443,7 @@ template <typename T, int NC>
 __global__ void k_smooth_rb(Rb0V L, const T* __restrict__ b, T* __restrict__ x, int col) {
     if (L.gate && *L.gate) return;
     long N = L.N, Nh = N >> 1;
-    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    long t = xcd_block() * (long)blockDim.x + threadIdx.x;
     if (t >= Nh) return;
     int i, j, k;
     rb_cell(L.grid, (unsigned)t, col, i, j, k);
@@ -464,8 +463,9 @@ __global__ void k_smooth_rb(Rb0V L, const T* __restrict__ b, T* __restrict__ x, 
 #pragma unroll
         for (int m = 0; m < NC; m++) acc[m] += kf * x[m * N + q];
     }
+    T inv = (T)1 / dg;
 #pragma unroll
-    for (int m = 0; m < NC; m++) x[m * N + own] = acc[m] / dg;
+    for (int m = 0; m < NC; m++) x[m * N + own] = acc[m] * inv;
 }
 
 // first half sweep (colour 0) from a zero iterate over both colours: colour 0 gets b/D, colour 1
@@ -488,9 +488,81 @@ __global__ void k_smooth_first_rb(Rb0V L, const T* __restrict__ b, T* __restrict
         long nb[6];
         upd = rb0_row<T>(L, c, i, j, k, K, nb, Dd);
     }
-    T dg = upd ? Dd : (T)1;
+    T inv = upd ? (T)1 / Dd : (T)0;
 #pragma unroll
-    for (int m = 0; m < NC; m++) x[m * N + u] = upd ? (b[m * N + u] + (T)0) / dg : (T)0;
+    for (int m = 0; m < NC; m++) x[m * N + u] = upd ? b[m * N + u] * inv : (T)0;
+}
+
+// k_smooth_first_rb fused with the conversion of the right-hand side: reads b in natural
+// order (FP64), stores its colour-split copy (precision T) and the first iterate
+template <typename T, int NC>
+__global__ void k_smooth_first_rb_from(Rb0V L, const double* __restrict__ bnat,
+                                       T* __restrict__ b, T* __restrict__ x) {
+    if (L.gate && *L.gate) return;
+    long N = L.N, Nh = N >> 1;
+    long u = xcd_block() * (long)blockDim.x + threadIdx.x;
+    if (u >= N) return;
+    int col = u >= Nh ? 1 : 0;
+    long t = u - col * Nh;
+    int i, j, k;
+    rb_cell(L.grid, (unsigned)t, col, i, j, k);
+    long c = cell_index(L.grid, i, j, k);
+    bool upd = false;
+    T Dd = (T)1;
+    if (col == 0) {
+        T K[6];
+        long nb[6];
+        upd = rb0_row<T>(L, c, i, j, k, K, nb, Dd);
+    }
+    T inv = upd ? (T)1 / Dd : (T)0;
+#pragma unroll
+    for (int m = 0; m < NC; m++) {
+        T bv = (T)bnat[m * N + c];
+        b[m * N + u] = bv;
+        x[m * N + u] = upd ? bv * inv : (T)0;
+    }
+}
+
+// the last half sweep (colour 0) fused with the conversion of the iterate back to natural
+// order (FP64): a thread updates its colour-0 cell and also copies the colour-1 cell next to it
+// in x, so every cell of the natural output is written once
+template <typename T, int NC>
+__global__ void k_smooth_last_rb_to(Rb0V L, const T* __restrict__ b, const T* __restrict__ x,
+                                    double* __restrict__ xnat) {
+    if (L.gate && *L.gate) return;
+    long N = L.N, Nh = N >> 1;
+    long t = xcd_block() * (long)blockDim.x + threadIdx.x;
+    if (t >= Nh) return;
+    int i, j, k;
+    rb_cell(L.grid, (unsigned)t, 0, i, j, k);
+    long c = cell_index(L.grid, i, j, k);
+    long c1 = cell_index(L.grid, i ^ 1, j, k);
+    T K[6], dg;
+    long nb[6];
+    bool upd = rb0_row<T>(L, c, i, j, k, K, nb, dg);
+    T val[NC];
+#pragma unroll
+    for (int m = 0; m < NC; m++) val[m] = x[m * N + t];
+    if (upd) {
+#pragma unroll
+        for (int m = 0; m < NC; m++) val[m] = b[m * N + t];
+#pragma unroll
+        for (int f = 0; f < 6; f++) {
+            T kf = K[f];
+            if (kf == (T)0 || nb[f] < 0) continue;
+            long q = Nh + (nb[f] >> 1);
+#pragma unroll
+            for (int m = 0; m < NC; m++) val[m] += kf * x[m * N + q];
+        }
+        T inv = (T)1 / dg;
+#pragma unroll
+        for (int m = 0; m < NC; m++) val[m] = val[m] * inv;
+    }
+#pragma unroll
+    for (int m = 0; m < NC; m++) {
+        xnat[m * N + c] = (double)val[m];
+        xnat[m * N + c1] = (double)x[m * N + Nh + (c1 >> 1)];
+    }
 }
 
 // residual of level 0 restricted to the coarse right-hand side (natural storage there), with
@@ -505,7 +577,8 @@ __global__ void __launch_bounds__(RR_THREADS)
     long Nc = (long)gc.n[0] * gc.n[1] * gc.n[2];
     int a, cl, bq, cq;
     rr_child(threadIdx.x, a, cl, bq, cq);
-    long c = (long)blockIdx.x * RR_COARSE + cl;
+    unsigned blk = xcd_block();
+    long c = (long)blk * RR_COARSE + cl;
     TF r[NC];
 #pragma unroll
     for (int m = 0; m < NC; m++) r[m] = (TF)0;
@@ -539,7 +612,7 @@ __global__ void __launch_bounds__(RR_THREADS)
     for (int m = 0; m < NC; m++) rs[threadIdx.x * NC + m] = r[m];
     __syncthreads();
     if (threadIdx.x < RR_COARSE) {
-        long cc = (long)blockIdx.x * RR_COARSE + threadIdx.x;
+        long cc = (long)blk * RR_COARSE + threadIdx.x;
         if (cc >= Nc) return;
         TF sum[NC];
 #pragma unroll
@@ -560,7 +633,7 @@ __global__ void k_prolong_rb(Rb0V L, GridV gc, const TC* __restrict__ ec, TF* __
     if (L.gate && *L.gate) return;
     long N = L.N, Nh = N >> 1;
     long Nc = (long)gc.n[0] * gc.n[1] * gc.n[2];
-    long u = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    long u = xcd_block() * (long)blockDim.x + threadIdx.x;
     if (u >= N) return;
     int col = u >= Nh ? 1 : 0;
     int i, j, k;
@@ -952,7 +1025,7 @@ __global__ void __launch_bounds__(EB_BLOCK) k_visc_apply(GeomV g, double rho, do
                              double* __restrict__ out, int homog, const int* gate) {
     if (gate && *gate) return;
     long N = g.N;
-    long c = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    long c = xcd_block() * (long)blockDim.x + threadIdx.x;
     if (c >= N) return;
     uint8_t fl = g.flag[c];
     if (fl == 0) {
@@ -1012,27 +1085,38 @@ __global__ void __launch_bounds__(EB_BLOCK) k_visc_apply(GeomV g, double rho, do
                 }
             }
         }
-    int q = g.cutid[c];
-    if (q >= 0) {
-        int nc = g.ncut;
-        double d1 = g.dd[q], d2 = g.dd[nc + q];
-        double den = d1 * d2 * (d2 - d1) * g.grid.h;
-        double coef = dt * g.aeb[q] * eta_eb[q] / g.grid.h;
-#pragma unroll
-        for (int m = 0; m < 3; m++) {
-            double ue = homog ? 0.0 : g.ueb[m];
-            double s1 = 0.0, s2 = 0.0;
-            for (int t = 0; t < 9; t++) {
-                int c1 = g.sidx[(long)t * nc + q];
-                s1 += g.sw[(long)t * nc + q] * (c1 >= 0 ? u[m * N + c1] : ue);
-                int c2 = g.sidx[(long)(t + 9) * nc + q];
-                s2 += g.sw[(long)(t + 9) * nc + q] * (c2 >= 0 ? u[m * N + c2] : ue);
-            }
-            double gn = (d2 * d2 * (s1 - ue) - d1 * d1 * (s2 - ue)) / den;
-            acc[m] += coef * gn;
-        }
-    }
     for (int m = 0; m < 3; m++) out[m * N + c] = acc[m];
+}
+
+// the wall-flux term of the cut-cell rows, added after k_visc_apply (one thread per cut cell,
+// each writing only its own row): dt A_EB eta_EB (du/dn of Eq. dudn) / h
+__global__ void __launch_bounds__(EB_BLOCK) k_visc_apply_eb(GeomV g, double dt,
+                                                            const double* __restrict__ eta_eb,
+                                                            const double* __restrict__ u,
+                                                            double* __restrict__ out, int homog,
+                                                            const int* gate) {
+    if (gate && *gate) return;
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    int nc = g.ncut;
+    if (q >= nc) return;
+    long N = g.N;
+    long c = g.cut[q];
+    double d1 = g.dd[q], d2 = g.dd[nc + q];
+    double den = d1 * d2 * (d2 - d1) * g.grid.h;
+    double coef = dt * g.aeb[q] * eta_eb[q] / g.grid.h;
+#pragma unroll
+    for (int m = 0; m < 3; m++) {
+        double ue = homog ? 0.0 : g.ueb[m];
+        double s1 = 0.0, s2 = 0.0;
+        for (int t = 0; t < 9; t++) {
+            int c1 = g.sidx[(long)t * nc + q];
+            s1 += g.sw[(long)t * nc + q] * (c1 >= 0 ? u[m * N + c1] : ue);
+            int c2 = g.sidx[(long)(t + 9) * nc + q];
+            s2 += g.sw[(long)(t + 9) * nc + q] * (c2 >= 0 ? u[m * N + c2] : ue);
+        }
+        double gn = (d2 * d2 * (s1 - ue) - d1 * d1 * (s2 - ue)) / den;
+        out[m * N + c] += coef * gn;
+    }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1294,8 +1378,10 @@ Rb0V rb0_view(const Level& L) {
     v.D = L.D;
     v.sys = L.sys;
     v.rho = L.rho;
-    v.dt = L.dt;
-    v.beta = L.beta;
+    double h2 = L.grid.h * L.grid.h;
+    v.kin = L.dt * 0.5 / h2;
+    v.kwall = 2.0 * L.dt / h2;
+    v.kpois = L.beta / h2;
     v.gate = L.gate;
     return v;
 }
@@ -1408,22 +1494,29 @@ void vcycle_rec(const VArgs& a, int l) {
 
 // level 0 of a V-cycle in colour-split storage (it is neither the coarsest nor a tail level):
 // b and x are the level's own colour-split arrays
+// b0, x0: the caller's natural-order FP64 right-hand side and output; b, x: the level's
+// colour-split arrays (precision T).  The conversions ride on the first and last passes.
 template <typename T>
-void vcycle_level0_rb(const VArgs& a, T* b, T* x) {
+void vcycle_level0_rb(const VArgs& a, const double* b0, double* x0, T* b, T* x) {
     Level& L = a.lev[0];
     Level& C = a.lev[1];
     Rb0V v = rb0_view(L);
     int nc = a.nc;
+    unsigned g = grid_for(L.N);
+    if (a.nu1 < 1) {
+        if (nc == 3) k_to_rb<double, T, 3><<<g, EB_BLOCK, 0, a.s>>>(L.grid, L.N, b0, b, L.gate);
+        else k_to_rb<double, T, 1><<<g, EB_BLOCK, 0, a.s>>>(L.grid, L.N, b0, b, L.gate);
+        k_zero<T><<<grid_for(nc * L.N), EB_BLOCK, 0, a.s>>>(nc * L.N, x, L.gate);
+    }
     for (int t = 0; t < a.nu1; t++) {
         if (t == 0) {
-            if (nc == 3) k_smooth_first_rb<T, 3><<<grid_for(L.N), EB_BLOCK, 0, a.s>>>(v, b, x);
-            else k_smooth_first_rb<T, 1><<<grid_for(L.N), EB_BLOCK, 0, a.s>>>(v, b, x);
+            if (nc == 3) k_smooth_first_rb_from<T, 3><<<g, EB_BLOCK, 0, a.s>>>(v, b0, b, x);
+            else k_smooth_first_rb_from<T, 1><<<g, EB_BLOCK, 0, a.s>>>(v, b0, b, x);
         } else {
             smooth_rb_pass<T>(L, nc, b, x, 0, a.s);
         }
         smooth_rb_pass<T>(L, nc, b, x, 1, a.s);
     }
-    if (a.nu1 < 1) k_zero<T><<<grid_for(nc * L.N), EB_BLOCK, 0, a.s>>>(nc * L.N, x, L.gate);
     bool cf32 = level_f32(a, 1);
     unsigned gc = grid_for(C.N, RR_COARSE);
     if (cf32) {
@@ -1444,20 +1537,23 @@ void vcycle_level0_rb(const VArgs& a, T* b, T* x) {
     }
     for (int t = 0; t < a.nu2; t++) {
         smooth_rb_pass<T>(L, nc, b, x, 1, a.s);
-        smooth_rb_pass<T>(L, nc, b, x, 0, a.s);
+        if (t < a.nu2 - 1) {
+            smooth_rb_pass<T>(L, nc, b, x, 0, a.s);
+        } else {
+            unsigned gh = grid_for(L.N / 2);
+            if (nc == 3) k_smooth_last_rb_to<T, 3><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, x0);
+            else k_smooth_last_rb_to<T, 1><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, x0);
+        }
+    }
+    if (a.nu2 < 1) {
+        if (nc == 3) k_from_rb<T, double, 3><<<g, EB_BLOCK, 0, a.s>>>(L.grid, L.N, x, x0, L.gate);
+        else k_from_rb<T, double, 1><<<g, EB_BLOCK, 0, a.s>>>(L.grid, L.N, x, x0, L.gate);
     }
 }
 
 template <typename T>
-void vcycle_rb(const VArgs& a, const double* b, double* x, T* brb, T* xrb, const int* gate) {
-    Level& L0 = a.lev[0];
-    long N = L0.N;
-    unsigned g = grid_for(N);
-    if (a.nc == 3) k_to_rb<double, T, 3><<<g, EB_BLOCK, 0, a.s>>>(L0.grid, N, b, brb, gate);
-    else k_to_rb<double, T, 1><<<g, EB_BLOCK, 0, a.s>>>(L0.grid, N, b, brb, gate);
-    vcycle_level0_rb<T>(a, brb, xrb);
-    if (a.nc == 3) k_from_rb<T, double, 3><<<g, EB_BLOCK, 0, a.s>>>(L0.grid, N, xrb, x, gate);
-    else k_from_rb<T, double, 1><<<g, EB_BLOCK, 0, a.s>>>(L0.grid, N, xrb, x, gate);
+void vcycle_rb(const VArgs& a, const double* b, double* x, T* brb, T* xrb) {
+    vcycle_level0_rb<T>(a, b, x, brb, xrb);
 }
 
 void finish_operator(Level* lev, int nlev, bool mixed, hipStream_t s) {
@@ -1521,8 +1617,8 @@ void mg_vcycle(Level* lev, int nlev, int ncomp, bool mixed, const double* b, dou
     long n = (long)ncomp * L0.N;
     if (nlev > 1 && !(a.tail == 0 && a.tail_fits) && L0.flag) {
         // the finest level in colour-split storage (its own arrays)
-        if (level_f32(a, 0)) vcycle_rb<float>(a, b, x, L0.bf, L0.xf, gate);
-        else vcycle_rb<double>(a, b, x, L0.b, L0.x, gate);
+        if (level_f32(a, 0)) vcycle_rb<float>(a, b, x, L0.bf, L0.xf);
+        else vcycle_rb<double>(a, b, x, L0.b, L0.x);
         for (int l = 0; l < nlev; l++) lev[l].gate = nullptr;
         return;
     }
@@ -1563,6 +1659,9 @@ void op_visc_apply(const GeomV& g, double rho, double dt, const double* eta,
                    hipStream_t s, const int* gate) {
     k_visc_apply<<<grid_for(g.N), EB_BLOCK, 0, s>>>(g, rho, dt, eta, eta_eb, u, out, homogeneous,
                                                     gate);
+    if (g.ncut > 0)
+        k_visc_apply_eb<<<grid_for(g.ncut), EB_BLOCK, 0, s>>>(g, dt, eta_eb, u, out, homogeneous,
+                                                            gate);
 }
 
 // ------------------------------------------------------------------------------------------

@@ -227,6 +227,38 @@ def test_rk2_step_mixed_precision(s32):
     _step_parity(P, steps=1, tol=1e-8)
 
 
+def test_mixed_precision_bench_size():
+    """128^3 sphere: three mixed-precision steps against three FP64 steps from the same
+    developed state (the FP64 step is itself checked against the oracle above): relative L2
+    error of every output field and of the drag, each within 1e-8."""
+    import paper_1905_07392_amd as pkg
+    from paper_1905_07392_amd import api
+
+    _require_gpu()
+    w = I.sphere128()
+    outs = {}
+    for prec in (0, 1):
+        box, body, rheo, opts = pkg.from_workload(w, precision=prec)
+        ctx = api.eb_geometry_build(box, body, "cuda:0")
+        u = torch.from_numpy(I.initial_velocity(w)).to("cuda:0")
+        p = ctx.scalar()
+        for _ in range(3):
+            u, p, st = api.eb_rk2_step(ctx, rheo, w.dt, opts, u, p)
+        eta, eta_eb = api.eb_apparent_viscosity(ctx, rheo, u)
+        F = api.eb_drag(ctx, rheo, u, p)
+        _, alpha, _, _, _ = api.eb_geometry_export(ctx)
+        outs[prec] = (cpu(u), cpu(p), cpu(eta), cpu(eta_eb), F, cpu(alpha) > 0, st)
+    u64, p64, e64, eb64, F64, op, st64 = outs[0]
+    u32, p32, e32, eb32, F32, _, st32 = outs[1]
+    errs = {"u": rel_l2(u32[0], u64[0], op), "v": rel_l2(u32[1], u64[1], op),
+            "w": rel_l2(u32[2], u64[2], op), "p": rel_l2(p32, p64, op),
+            "eta": rel_l2(e32, e64, op), "eta_eb": rel_l2(eb32, eb64),
+            "drag_z": abs(F32[2] - F64[2]) / abs(F64[2])}
+    print(f"[mixed] 128^3 3 steps, mixed vs FP64 relative errors {errs}; iterations fp64 "
+          f"{st64} mixed {st32}", flush=True)
+    assert max(errs.values()) <= 1e-8, errs
+
+
 def test_bench_size_properties():
     """128^3 sphere in the launch configuration the bench times: divergence at tolerance,
     mirror symmetry of the noiseless flow, and the viscosity recomputed by the oracle from the
