@@ -56,7 +56,16 @@ enum { EB_BODY_NONE = 0, EB_BODY_SPHERE = 1, EB_BODY_ELLIPSOID = 2, EB_BODY_ZSLA
  *   PAPANASTASIOU  eta = mu + tau0 (1 - exp(-|gamma|/eps))/|gamma|   (mu + tau0/eps at 0) */
 enum { EB_LAW_NEWTONIAN = 0, EB_LAW_BINGHAM_REG = 1, EB_LAW_PAPANASTASIOU = 2 };
 
-enum { EB_FP64 = 0, EB_MIXED = 1 };            /* precision of the multigrid preconditioner */
+/* Precision of the multigrid preconditioner.  EB_MIXED smooths, restricts and prolongates in
+ * FP32 on every level above the in-wave tail; the Krylov iteration, its residual with the full
+ * EB operator, the tail levels with the coarsest solve, the wall stencils and the divergence
+ * checks stay FP64, so the result meets the same FP64 residual target.  A mixed solve whose
+ * residual has not fallen tenfold within 6 iterations, or that has not converged within
+ * max(20, max_iter/10), has an operator too ill-conditioned for an FP32 V-cycle (e.g. a
+ * viscosity contrast of 1e6 between a plug and a sheared layer); it is then solved again from
+ * the same starting iterate with the FP64 V-cycle, giving the FP64 solve's result
+ * (eb_step_stats.fp64_fallbacks counts these). */
+enum { EB_FP64 = 0, EB_MIXED = 1 };
 enum { EB_SYS_POISSON = 0, EB_SYS_VISC = 1 };  /* system for eb_mg_vcycle */
 
 typedef struct {
@@ -97,6 +106,10 @@ typedef struct {
     double div_proj[2];                     /* max |div| of the projected face field */
     int vcycles;                            /* V-cycles executed in the step */
     int status;                             /* worst return code of the step's solves */
+    int fp64_fallbacks;                     /* mixed precision: solves of the step that
+                                               gave up the FP32 V-cycle and were solved again
+                                               with the FP64 one (iteration counts include
+                                               both attempts) */
 } eb_step_stats;
 
 typedef struct eb_ctx eb_ctx;

@@ -42,7 +42,8 @@ class EbStepOpts(C.Structure):
 
 class EbStepStats(C.Structure):
     _fields_ = [("it_mac", C.c_int * 2), ("it_visc", C.c_int * 2), ("it_proj", C.c_int * 2),
-                ("div_proj", C.c_double * 2), ("vcycles", C.c_int), ("status", C.c_int)]
+                ("div_proj", C.c_double * 2), ("vcycles", C.c_int), ("status", C.c_int),
+                ("fp64_fallbacks", C.c_int)]
 
 
 _P = C.c_void_p

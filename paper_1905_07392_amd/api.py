@@ -285,7 +285,7 @@ def eb_rk2_step(ctx: EbContext, rheo: EbRheology, dt, opts: EbStepOpts, u, p, th
 def _stats(st):
     return {"it_mac": list(st.it_mac), "it_visc": list(st.it_visc),
             "it_proj": list(st.it_proj), "div_proj": list(st.div_proj),
-            "vcycles": st.vcycles, "status": st.status}
+            "vcycles": st.vcycles, "status": st.status, "fp64_fallbacks": st.fp64_fallbacks}
 
 
 def eb_drag(ctx: EbContext, rheo: EbRheology, u, p, theta=None):

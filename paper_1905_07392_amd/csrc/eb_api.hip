@@ -51,6 +51,16 @@ struct Carver {
 
 }  // namespace
 
+namespace {
+constexpr int NSLOT = 8;
+}
+
+// one read-back of a solve's progress: its (state, count) slot and its residual max-norm
+struct PollWord {
+    int st[2];
+    double rn;
+};
+
 struct eb_ctx {
     eb_box box;
     eb_body body;
@@ -74,15 +84,15 @@ struct eb_ctx {
         *gp, *u1, *p1, *div, *phi, *pb;
     double* f[3];
     double* kv[10];
-    double* pk[4];
+    double* pk[5];
     int built_sys;    // operator currently held by the levels (-1 none)
     bool built_mixed;
     // device Krylov scalars, per-solve (state, count) slots, per-solve divergence norms
     double* ks;
     int* kst;
     double* divs;
-    // pinned host words for the lagged convergence poll, and their events
-    int* pin;
+    // pinned host words for the lagged convergence poll (two buffers), and their events
+    struct PollWord* pin;
     hipEvent_t ev[2];
     // the library's own stream (fenced to the caller's with two events) and the captured
     // Krylov iterations replayed on it
@@ -96,11 +106,12 @@ struct eb_ctx {
     double *Gb, *ubm, *lam, *ehb, *ebhb, *rX, *rY, *gwb;
     double* ufb[3];
     LRV lr;
+    // mixed precision: iterations a solve ran with the FP32 V-cycle before it continued with
+    // the FP64 one (per slot, in the slot's count units), and such switches since the last
+    // reset (host side)
+    int slot_off[NSLOT];
+    int fp64_fallbacks;
 };
-
-namespace {
-constexpr int NSLOT = 8;
-}
 
 namespace {
 
@@ -205,7 +216,7 @@ size_t carve(eb_ctx* c, char* base, bool dry) {
     c->pb = cv.take<double>(N);
     for (int d = 0; d < 3; d++) c->f[d] = cv.take<double>(face_count(g, d));
     for (int t = 0; t < 10; t++) c->kv[t] = cv.take<double>(3 * N);
-    for (int t = 0; t < 4; t++) c->pk[t] = cv.take<double>(N);
+    for (int t = 0; t < 5; t++) c->pk[t] = cv.take<double>(N);
     c->wt_map = cv.take<int>(N);
     c->wt_ptr = cv.take<int>(18 * M + 1);
     c->wt_ent = cv.take<int>(18 * M);
@@ -477,20 +488,83 @@ void vcyc(eb_ctx* c, int ncomp, const SolveCfg& k, const double* b, double* x, c
 
 // lagged convergence test: enqueue the read-back of the slot's state after iteration it and
 // wait for the one of iteration it-1 (already executed or about to be)
-bool poll_done(eb_ctx* c, int slot, int it) {
+// (the state word: 0 while running); with rn non-null, *rn receives the residual max-norm
+// after iteration it-1
+int poll_done(eb_ctx* c, int slot, int it, double* rn) {
     int b = it & 1;
-    hipMemcpyAsync(&c->pin[2 * b], c->kst + 2 * slot, 2 * sizeof(int), hipMemcpyDeviceToHost,
+    hipMemcpyAsync(c->pin[b].st, c->kst + 2 * slot, 2 * sizeof(int), hipMemcpyDeviceToHost,
                    c->s);
+    if (rn)
+        hipMemcpyAsync(&c->pin[b].rn, c->ks + KS_RN, sizeof(double), hipMemcpyDeviceToHost,
+                       c->s);
     hipEventRecord(c->ev[b], c->s);
-    if (it < 2) return false;
+    if (it < 2) return 0;
     int pb = (it - 1) & 1;
     hipEventSynchronize(c->ev[pb]);
-    return c->pin[2 * pb] != 0;
+    if (rn) *rn = c->pin[pb].rn;
+    return c->pin[pb].st[0];
 }
 
-// preconditioned CG for M x = b on level 0 (operator already built), state in `slot`;
-// ks[KS_RTOL] and ks[KS_SCALE] must be set
-void pcg(eb_ctx* c, const double* b, double* x, const SolveCfg& k, int slot) {
+// state word of `slot` once the stream has drained
+int slot_state(eb_ctx* c, int slot) {
+    int sl[2] = {0, 0};
+    hipMemcpyAsync(sl, c->kst + 2 * slot, 2 * sizeof(int), hipMemcpyDeviceToHost, c->s);
+    hipStreamSynchronize(c->s);
+    return sl[0];
+}
+
+// preconditioner applications made so far by the solve in `slot` (its device iteration
+// counter: CG iterations; BiCGSTAB iterations, two applications each), stream drained
+int slot_count_now(eb_ctx* c, int slot) {
+    int n = 0;
+    hipMemcpyAsync(&n, c->kst + 2 * NSLOT + slot, sizeof(int), hipMemcpyDeviceToHost, c->s);
+    hipStreamSynchronize(c->s);
+    return n;
+}
+
+// Mixed precision keeps the FP32 V-cycle as long as it works as a preconditioner, i.e. while
+// the conditioning of the level operators times the FP32 unit roundoff stays well below one
+// (high viscosity contrast, as in a nearly rigid plug next to a sheared layer, breaks this).
+// A mixed solve is given up when its residual max-norm has not fallen tenfold within
+// STALL_WINDOW iterations (a working V-cycle gains that in two or three), or when it has not
+// converged within mixed_budget iterations; the caller then solves again from the same
+// starting iterate with the FP64 V-cycle, so the result is the FP64 solve's.  The step's
+// stats count such switches.
+constexpr int STALL_WINDOW = 6;
+
+int mixed_budget(const SolveCfg& k) {
+    int b = k.max_iter / 10 > 20 ? k.max_iter / 10 : 20;
+    return b < k.max_iter ? b : k.max_iter;
+}
+
+// up to max_iter iterations of a solve whose state lives in `slot`; returns the final state
+// (2 converged, 3 non-finite, 0 not converged: iterations exhausted, or stalled when `watch`)
+template <class Body>
+int iterate(eb_ctx* c, const GraphKey& key, int slot, int max_iter, Body& body, bool watch) {
+    double best_old = INFINITY, recent[STALL_WINDOW];
+    for (int it = 1; it <= max_iter; it++) {
+        run_iteration(c, key, body);
+        double rn = 0.0;
+        if (int s = poll_done(c, slot, it, watch ? &rn : nullptr)) return s == 1 ? 2 : s;
+        if (!watch || it < 2) continue;
+        int j = it - 1;  // the iteration rn belongs to
+        if (j > STALL_WINDOW) {
+            double gone = recent[j % STALL_WINDOW];  // iteration j - STALL_WINDOW
+            best_old = gone < best_old ? gone : best_old;
+        }
+        recent[j % STALL_WINDOW] = rn;
+        if (j > STALL_WINDOW) {
+            double best_new = INFINITY;
+            for (double r : recent) best_new = r < best_new ? r : best_new;
+            if (!(best_new <= 0.1 * best_old)) break;
+        }
+    }
+    return slot_state(c, slot);
+}
+
+// preconditioned CG for M x = b on level 0 (operator already built), state in `slot`, from
+// the iterate in x; ks[KS_RTOL] and ks[KS_SCALE] must be set.  Returns the final state.
+int pcg(eb_ctx* c, const double* b, double* x, const SolveCfg& k, int slot) {
     long N = c->N;
     double *r = c->pk[0], *z = c->pk[1], *pd = c->pk[2], *q = c->pk[3];
     double* ks = c->ks;
@@ -534,10 +608,7 @@ void pcg(eb_ctx* c, const double* b, double* x, const SolveCfg& k, int slot) {
         ks_op(KS_CG_BETA, ks, st, itc, c->s);
         ks_cg_p(N, pd, z, ks, st, c->s);
     };
-    for (int it = 1; it <= k.max_iter; it++) {
-        run_iteration(c, key, body);
-        if (poll_done(c, slot, it)) break;
-    }
+    return iterate(c, key, slot, k.max_iter, body, k.mixed);
 }
 
 // Poisson solve for the projections: M p = -(D w - mean), then p normalised to zero mean
@@ -548,7 +619,23 @@ void poisson_solve(eb_ctx* c, double beta, const double* div, double* p, const S
     c->built_mixed = k.mixed;
     red_sum_open(c->g, div, c->part, c->ks + KS_SUM, c->s);
     op_poisson_rhs(c->g, div, c->ks + KS_SUM, c->pb, c->s);
-    pcg(c, c->pb, p, k, slot);
+    c->slot_off[slot] = 0;
+    SolveCfg kk = k;
+    if (k.mixed) {
+        kk.max_iter = mixed_budget(k);
+        vec_copy(c->N, p, c->pk[4], c->s);  // the starting iterate, for a switch to FP64
+    }
+    int state = pcg(c, c->pb, p, kk, slot);
+    if (state != 2 && k.mixed) {
+        vec_copy(c->N, c->pk[4], p, c->s);
+        c->slot_off[slot] = slot_count_now(c, slot);
+        c->fp64_fallbacks++;
+        kk.mixed = false;
+        kk.max_iter = k.max_iter;
+        mg_build_poisson(c->lev, c->nlev, c->g, beta, false, c->s);
+        c->built_mixed = false;
+        pcg(c, c->pb, p, kk, slot);
+    }
     red_sum_open(c->g, p, c->part, c->ks + KS_SUM, c->s);
     op_shift_open(c->g, p, c->ks + KS_SUM, c->s);
 }
@@ -583,19 +670,15 @@ void cc_project(eb_ctx* c, double beta, double* u, double* p, double rtol, const
 // transposed: solve A^T x = psi instead (psi is then the right-hand side itself, already zero
 // on covered cells; x starts from zero).  The V-cycle preconditioner is symmetric, so the same
 // hierarchy serves both systems.
+int bicgstab(eb_ctx* c, double rho, double dt, const double* eta, const double* eta_eb,
+             double* x, const SolveCfg& k, int slot, bool transposed);
+
 void visc_solve(eb_ctx* c, double rho, double dt, const double* eta, const double* eta_eb,
                 const double* psi, double* x, double rtol, const SolveCfg& k, int slot,
                 bool transposed = false) {
     long N3 = 3 * c->N;
-    double *r = c->kv[0], *rh = c->kv[1], *p = c->kv[2], *v = c->kv[3], *ph = c->kv[4],
-           *sv = c->kv[5], *sh = c->kv[6], *t = c->kv[7], *b = c->kv[8], *a0 = c->kv[9];
+    double *t = c->kv[7], *b = c->kv[8], *a0 = c->kv[9];
     double* ks = c->ks;
-    int* st = c->kst + 2 * slot;
-    int* itc = c->kst + 2 * NSLOT + slot;
-    auto apply = [&](const double* in, double* out, const int* gate) {
-        if (transposed) adj_visc_apply_T(c->g, rho, dt, eta, eta_eb, c->wt, in, out, c->s, gate);
-        else op_visc_apply(c->g, rho, dt, eta, eta_eb, in, out, 1, c->s, gate);
-    };
     mg_build_visc(c->lev, c->nlev, c->g, rho, dt, eta, eta_eb, k.mixed, c->s);
     c->built_sys = EB_SYS_VISC;
     c->built_mixed = k.mixed;
@@ -611,6 +694,39 @@ void visc_solve(eb_ctx* c, double rho, double dt, const double* eta, const doubl
     red_maxabs(N3, 1, b, c->part, ks + KS_BN, c->s);
     ks_set(ks, KS_SCALE, 0.0, c->s);
     ks_set(ks, KS_RTOL, rtol, c->s);
+    c->slot_off[slot] = 0;
+    SolveCfg kk = k;
+    if (k.mixed) {
+        kk.max_iter = mixed_budget(k);
+        vec_copy(N3, x, a0, c->s);  // the starting iterate, for a switch to FP64
+    }
+    int state = bicgstab(c, rho, dt, eta, eta_eb, x, kk, slot, transposed);
+    if (state != 2 && k.mixed) {
+        vec_copy(N3, a0, x, c->s);
+        c->slot_off[slot] = 2 * slot_count_now(c, slot);
+        c->fp64_fallbacks++;
+        kk.mixed = false;
+        kk.max_iter = k.max_iter;
+        mg_build_visc(c->lev, c->nlev, c->g, rho, dt, eta, eta_eb, false, c->s);
+        c->built_mixed = false;
+        bicgstab(c, rho, dt, eta, eta_eb, x, kk, slot, transposed);
+    }
+}
+
+// the BiCGSTAB iterations of visc_solve from the iterate in x (right-hand side in kv[8], tol
+// scalars set); returns the final state
+int bicgstab(eb_ctx* c, double rho, double dt, const double* eta, const double* eta_eb,
+             double* x, const SolveCfg& k, int slot, bool transposed) {
+    long N3 = 3 * c->N;
+    double *r = c->kv[0], *rh = c->kv[1], *p = c->kv[2], *v = c->kv[3], *ph = c->kv[4],
+           *sv = c->kv[5], *sh = c->kv[6], *t = c->kv[7], *b = c->kv[8];
+    double* ks = c->ks;
+    int* st = c->kst + 2 * slot;
+    int* itc = c->kst + 2 * NSLOT + slot;
+    auto apply = [&](const double* in, double* out, const int* gate) {
+        if (transposed) adj_visc_apply_T(c->g, rho, dt, eta, eta_eb, c->wt, in, out, c->s, gate);
+        else op_visc_apply(c->g, rho, dt, eta, eta_eb, in, out, 1, c->s, gate);
+    };
     // r = b - A_lin(x)
     apply(x, t, nullptr);
     vec_sub_scaled(N3, b, 1.0, t, r, c->s);
@@ -661,10 +777,7 @@ void visc_solve(eb_ctx* c, double rho, double dt, const double* eta, const doubl
         red_maxabs(N3, 1, r, c->part, ks + KS_RN, c->s, st);
         ks_op(KS_BI_CHECK_R, ks, st, itc, c->s);
     };
-    for (int it = 1; it <= k.max_iter; it++) {
-        run_iteration(c, key, body);
-        if (poll_done(c, slot, it)) break;
-    }
+    return iterate(c, key, slot, k.max_iter, body, k.mixed);
 }
 
 // reads `n` solve slots (state, count) after the stream drains
@@ -672,6 +785,8 @@ int read_slots(eb_ctx* c, int n, int* host) {
     hipMemcpyAsync(host, c->kst, 2 * n * sizeof(int), hipMemcpyDeviceToHost, c->s);
     hipError_t e = hipStreamSynchronize(c->s);
     if (e != hipSuccess) return set_err(EB_EHIP, "sync: %s", hipGetErrorString(e));
+    for (int q = 0; q < n; q++)  // counts include the FP32 phase of a solve that switched
+        if (host[2 * q] == 2) host[2 * q + 1] += c->slot_off[q];
     return EB_OK;
 }
 
@@ -841,7 +956,7 @@ int eb_geometry_build(const eb_box* box, const eb_body* body, void* ws, size_t w
         for (int q = 0; q < ncut; q++) c->nfallback += tmp[q];
         delete[] tmp;
     }
-    if (hipHostMalloc((void**)&c->pin, 4 * sizeof(int), hipHostMallocDefault) != hipSuccess ||
+    if (hipHostMalloc((void**)&c->pin, 2 * sizeof(PollWord), hipHostMallocDefault) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev[0], hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev[1], hipEventDisableTiming) != hipSuccess) {
         eb_ctx_destroy(c);
@@ -1097,6 +1212,7 @@ int step_status(eb_ctx* c, const SolveCfg& k, eb_step_stats* stats, bool adjoint
             status = slot_code(&sl[2 * q], names[adjoint][kind], k.max_iter);
     }
     st.status = status;
+    st.fp64_fallbacks = c->fp64_fallbacks;
     if (stats) *stats = st;
     return status;
 }
@@ -1110,6 +1226,7 @@ int rk2_impl(eb_ctx* c, const eb_rheology* rheo, const double* theta, double dt,
     int nc = c->ncut;
     double rho = rheo->rho, beta = dt / rho;
     int h;
+    c->fp64_fallbacks = 0;
     // slots: 0/3 MAC projection, 1/4 viscous solve, 2/5 end-of-stage projection
     // predictor: derived quantities at u^m
     if ((h = derived(c, *rheo, theta, u, o, c->C0, c->eta0, c->eb0, c->V0, 0))) return h;
@@ -1189,6 +1306,7 @@ int eb_rk2_step_adjoint(eb_ctx* c, const eb_rheology* rheo, const double* theta,
     TapeV t;
     tape_carve(c, (char*)const_cast<void*>(tape), &t);
     SolveCfg k = cfg_of(o);
+    c->fp64_fallbacks = 0;
     const GeomV& g = c->g;
     long N = c->N, N3 = 3 * N;
     int nc = c->ncut;

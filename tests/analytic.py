@@ -29,7 +29,8 @@ def lambertw_exp(L):
     x = np.exp(L[small])
     out[small] = x - x * x + 1.5 * x ** 3
     Lb = L[~small]
-    w = np.where(Lb > 1.0, Lb - np.log(np.maximum(Lb, 1.0)), np.exp(Lb) / (1.0 + np.exp(Lb)))
+    eL = np.exp(np.minimum(Lb, 1.0))  # the start below needs exp(L) only where L <= 1
+    w = np.where(Lb > 1.0, Lb - np.log(np.maximum(Lb, 1.0)), eL / (1.0 + eL))
     for _ in range(100):
         f = w + np.log(w) - Lb
         fp = 1.0 + 1.0 / w

@@ -1,0 +1,149 @@
+"""GPU checks on the large single-box workload: 256^3 cells, a rotated ellipsoid (semi-axes
+0.15, 0.10, 0.08, seeded Euler angles), walls moving at (0, 0, -1), Papanastasiou law with
+eps = 1e-4 and tau0 = 100, rho = 1, dt = 2.5e-4, mixed precision.
+
+A full oracle step at this size takes minutes, so the checks are the ones the oracle can make
+cell by cell (geometry, and the viscosity recomputed from the GPU velocity), the mixed step
+against the FP64 step (itself checked against the oracle at smaller sizes), and the Bingham-
+number gradient of the drag against central finite differences.
+"""
+import numpy as np
+import pytest
+
+import eb_inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _require_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def cpu(t):
+    return t.detach().cpu().numpy()
+
+
+def rel_l2(a, b, mask=None):
+    if mask is not None:
+        a, b = a[..., mask], b[..., mask]
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+@pytest.fixture(scope="module")
+def large():
+    import paper_1905_07392_amd as pkg
+    from paper_1905_07392_amd import api
+
+    _require_gpu()
+    w = I.ellipsoid256()
+    print(f"[large] {w.name} n={w.n}", flush=True)
+    box, body, rheo, opts = pkg.from_workload(w, precision=api.EB_MIXED)
+    ctx = api.eb_geometry_build(box, body, "cuda:0")
+    return w, ctx, rheo, opts
+
+
+def test_ellipsoid256_geometry_and_viscosity(large):
+    from oracle import oracle as O
+    from paper_1905_07392_amd import api
+
+    w, ctx, rheo, opts = large
+    og = O.Geometry(w)
+    assert og.err == 0
+    flag, alpha, _ = og.export()
+    gflag, galpha, _, gcell, gdata = api.eb_geometry_export(ctx)
+    assert np.array_equal(cpu(gflag), flag)
+    assert np.abs(cpu(galpha) - alpha).max() <= 1e-13
+    cell, data = og.cut()
+    assert np.array_equal(cpu(gcell), cell)
+    assert np.abs(cpu(gdata) - data).max() <= 1e-11
+    # one mixed-precision step, then the viscosity at every cell from the GPU velocity
+    u = torch.from_numpy(I.initial_velocity(w)).to("cuda:0")
+    p = ctx.scalar()
+    u, p, st = api.eb_rk2_step(ctx, rheo, w.dt, opts, u, p)
+    print(f"[large] step stats {st}", flush=True)
+    eta_ref, eb_ref = og.viscosity(cpu(u), O.make_rheo(w))
+    eta_g, eb_g = api.eb_apparent_viscosity(ctx, rheo, u)
+    open_ = alpha > 0
+    # exp/expm1 of the law may differ by an ulp between the host and device libraries
+    assert rel_l2(cpu(eta_g), eta_ref, open_) <= 1e-13
+    assert rel_l2(cpu(eb_g), eb_ref) <= 1e-13
+    assert max(st["div_proj"]) <= 1e-11 / w.h
+
+
+def test_ellipsoid256_mixed_matches_fp64(large):
+    """Three mixed-precision steps against three FP64 steps from the wall-velocity start:
+    relative L2 error of u, v, w, p over open cells, of eta over yielded cells, of eta_EB and of
+    the drag, each within 1e-8."""
+    from paper_1905_07392_amd import api
+
+    w, ctx, rheo, opts = large
+    outs = {}
+    for prec in (api.EB_FP64, api.EB_MIXED):
+        opts.precision = prec
+        u = torch.from_numpy(I.initial_velocity(w)).to("cuda:0")
+        p = ctx.scalar()
+        for _ in range(3):
+            u, p, st = api.eb_rk2_step(ctx, rheo, w.dt, opts, u, p)
+        eta, eta_eb, sr = api.eb_apparent_viscosity(ctx, rheo, u, with_sr=True)
+        F = api.eb_drag(ctx, rheo, u, p)
+        outs[prec] = (cpu(u), cpu(p), cpu(eta), cpu(eta_eb), F, st, cpu(sr))
+    opts.precision = api.EB_MIXED
+    _, alpha, _, _, _ = api.eb_geometry_export(ctx)
+    op = cpu(alpha) > 0
+    u64, p64, e64, eb64, F64, st64, sr64 = outs[api.EB_FP64]
+    u32, p32, e32, eb32, F32, st32, _ = outs[api.EB_MIXED]
+    # the viscosity is judged on yielded cells (strain rate above 10 eps); in the nearly rigid
+    # cells the law amplifies velocity differences by ~|grad u| / eps, and the viscosity there
+    # is reported only
+    yielded = op & (sr64 > 10 * w.eps)
+    errs = {"u": rel_l2(u32[0], u64[0], op), "v": rel_l2(u32[1], u64[1], op),
+            "w": rel_l2(u32[2], u64[2], op), "p": rel_l2(p32, p64, op),
+            "eta_yielded": rel_l2(e32, e64, yielded), "eta_eb": rel_l2(eb32, eb64),
+            "drag_z": abs(F32[2] - F64[2]) / abs(F64[2])}
+    info = {"eta_all": rel_l2(e32, e64, op), "eta_plug": rel_l2(e32, e64, op & ~yielded),
+            "yielded_fraction": yielded.sum() / op.sum()}
+    print(f"[large] 256^3 3 steps, mixed vs FP64 relative errors {errs}; reported {info}; "
+          f"iterations fp64 {st64} mixed {st32}", flush=True)
+    assert max(errs.values()) <= 1e-8, errs
+
+
+def test_ellipsoid256_bi_gradient_fd(large):
+    """d(F_z)/d(Bi) through the checkpointed autograd rollout (mixed-precision forward, two
+    steps, solves at rtol 1e-13) against central finite differences of the same steps (relative
+    step 1e-6, solves at rtol 1e-14)."""
+    import copy
+
+    from paper_1905_07392_amd import api
+    from paper_1905_07392_amd import autograd as AG
+
+    w, ctx, rheo, opts = large
+    o = copy.copy(opts)  # the differentiated run
+    o.rtol_visc = o.rtol_mac = o.rtol_proj = 1e-13
+    ofd = copy.copy(opts)  # the finite-difference runs, one decade tighter
+    ofd.rtol_visc = ofd.rtol_mac = ofd.rtol_proj = 1e-14
+    nsteps = 2
+    u0 = torch.from_numpy(I.initial_velocity(w)).to("cuda:0")
+    p0 = ctx.scalar()
+    theta = torch.ones(ctx.shape, dtype=torch.float64, device="cuda:0")
+    bi = torch.tensor(float(w.tau0), dtype=torch.float64, device="cuda:0", requires_grad=True)
+    u, p = AG.rollout(ctx, rheo, w.dt, o, u0, p0, theta, bi, nsteps, ckpt_every=1)
+    fz = AG.drag(ctx, rheo, u, p, theta, bi)[2]
+    fz.backward()
+    g = bi.grad.item()
+
+    def loss(tau0):
+        r = api.make_rheology(w.law, w.mu, tau0, w.eps, w.rho)
+        uu, pp = u0.clone(), p0.clone()
+        for _ in range(nsteps):
+            uu, pp, _ = api.eb_rk2_step(ctx, r, w.dt, ofd, uu, pp, allow_noconv=True)
+        return api.eb_drag(ctx, r, uu, pp)[2]
+
+    hstep = 1e-6 * w.tau0
+    fd = (loss(w.tau0 + hstep) - loss(w.tau0 - hstep)) / (2 * hstep)
+    rel = abs(fd - g) / abs(g)
+    print(f"[large] dFz/dBi adjoint {g:.10e} fd {fd:.10e} rel {rel:.3e}", flush=True)
+    assert rel <= 1e-5
