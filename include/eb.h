@@ -110,6 +110,10 @@ typedef struct {
                                                gave up the FP32 V-cycle and were solved again
                                                with the FP64 one (iteration counts include
                                                both attempts) */
+    double dt_stable;                       /* eb_stable_dt of the step's input state with
+                                               C_CFL = 0.5 and the step's force (forward
+                                               steps; 0 in the adjoint): a dt above it is
+                                               outside the paper's stability rule */
 } eb_step_stats;
 
 typedef struct eb_ctx eb_ctx;
@@ -132,6 +136,24 @@ void eb_ctx_destroy(eb_ctx* ctx);
  * default; the environment variable EB_GRAPHS=0 turns it off for new contexts).  enable = 0
  * launches every kernel individually instead; results are identical either way.  Host only. */
 int eb_ctx_set_graphs(eb_ctx* ctx, int enable);
+
+/* Branch record and replay of the step's non-smooth switches, for checking the reverse mode
+ * against finite differences (the adjoint differentiates the step with every switch frozen
+ * at its forward value).  The switches are those of the derived quantities (Sec. III.A.3,
+ * Sec. III.B.2): the branch of each monotonised-central slope (per component, direction and
+ * cell), the normal upwind side of each face velocity, and the upwind side of each face's
+ * convective flux.  Every derived-quantities evaluation (two per RK2 step, one per
+ * eb_derived) takes the next eb_switch_bytes(ctx) bytes of `buf` (device, caller-owned):
+ *   EB_SWITCH_RECORD  evaluates the switches as usual and writes them there;
+ *   EB_SWITCH_REPLAY  reads them from there instead of evaluating them, so a perturbed run
+ *                     stays on the recorded pieces of smoothness;
+ *   EB_SWITCH_OFF     (default) neither.
+ * Setting a mode rewinds to the start of `buf`; an evaluation beyond `bytes` fails with
+ * EB_EINVAL.  Comparing two records byte by byte counts the switches two runs took
+ * differently.  Host only. */
+enum { EB_SWITCH_OFF = 0, EB_SWITCH_RECORD = 1, EB_SWITCH_REPLAY = 2 };
+size_t eb_switch_bytes(const eb_ctx* ctx);
+int eb_ctx_set_switches(eb_ctx* ctx, int mode, void* buf, size_t bytes);
 
 /* Number of cut cells, multigrid levels, and wall stencils that needed the covered-node
  * fallback.  Host only. */
@@ -232,6 +254,17 @@ int eb_rk2_step(eb_ctx* ctx, const eb_rheology* rheo, const double* theta, doubl
  * p_EB = p + h b.G p.  n points from the body into the fluid.  F (host) [3]. */
 int eb_drag(const eb_ctx* ctx, const eb_rheology* rheo, const double* theta, const double* u,
             const double* p, double F[3], void* stream);
+
+/* Time step of the paper's stability rule (Sec. II.C.1) for the state u (device) [3][N]:
+ * Eq. cfl:dt combining the convective coefficient max over open cells of (|u|+|v|+|w|)/h
+ * (Eq. cfl:convective), the forcing coefficient sqrt(sum_d |force_d| / h) (Eq. cfl:forcing;
+ * force on the host) and the viscous one 2 mu (Bi + 1) / rho * 3 / h^2 (Eq. cfl:viscous:new),
+ * with Bi the largest tau0 * theta over open cells (theta nullable = 1; 0 for a Newtonian
+ * law) and c_cfl in (0, 1] (the paper's default 0.5).  Writes *dt (host); synchronises
+ * `stream`.  The step does not limit its dt by this; it reports it (eb_step_stats). */
+int eb_stable_dt(const eb_ctx* ctx, const eb_rheology* rheo, const double* theta,
+                 const double* u, const double force[3], double c_cfl, double* dt,
+                 void* stream);
 
 /* Cell-centred pressure gradient G p (aperture-weighted mean of the two face gradients in
  * each direction; domain-wall faces carry a zero gradient).  p (device) [N], gp (device) [3][N]. */

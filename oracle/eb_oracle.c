@@ -1818,6 +1818,30 @@ int or_rk2_step(const or_geom* g, const or_rheo* rh, const double* theta, double
 /* ------------------------------------------------------------------------------------------ */
 /* drag on the embedded body (Eq. drag-force): sum over cut cells of (tau - p I) n A_EB h^2     */
 /* ------------------------------------------------------------------------------------------ */
+/* Time step of the stability rule (Sec. II.C.1): the convective coefficient (Eq.
+ * cfl:convective) is the largest |u|/dx + |v|/dy + |w|/dz over fluid cells, the forcing one
+ * (Eq. cfl:forcing) sqrt(sum_d |f_d| / dx_d), the viscous one (Eq. cfl:viscous:new)
+ * 2 mu (Bi + 1) / rho * sum_d 1/dx_d^2 with the regularisation left out, and they combine by
+ * Eq. cfl:dt.  Bi is the largest yield stress tau0 * theta_c over fluid cells (tau0 itself is
+ * the Bingham number when mu, U and L are 1); a Newtonian law has Bi = 0. */
+double or_stable_dt(const or_geom* g, const or_rheo* r, const double* theta, const double* u,
+                    const double force[3], double c_cfl) {
+    long N = g->N;
+    double h = g->box.h;
+    double cc = 0.0, bi = 0.0;
+    for (long c = 0; c < N; c++) {
+        if (!(g->alpha[c] > 0.0)) continue;
+        double s = (fabs(u[c]) + fabs(u[N + c]) + fabs(u[2 * N + c])) / h;
+        if (s > cc) cc = s;
+        double t = r->law == OR_LAW_NEWTONIAN ? 0.0 : r->tau0 * (theta ? theta[c] : 1.0);
+        if (t > bi) bi = t;
+    }
+    double cf = sqrt((fabs(force[0]) + fabs(force[1]) + fabs(force[2])) / h);
+    double cv = 2.0 * r->mu / r->rho * (bi + 1.0) * (3.0 / (h * h));
+    double a = cc + cv;
+    return c_cfl / (0.5 * (a + sqrt(a * a + 4.0 * cf * cf)));
+}
+
 void or_drag(const or_geom* g, const or_rheo* r, const double* theta, const double* u,
              const double* p, double F[3]) {
     long N = g->N;

@@ -115,6 +115,9 @@ int or_derived(const or_geom* g, const or_rheo* r, const double* theta, const do
                int* iters);
 int or_rk2_step(const or_geom* g, const or_rheo* r, const double* theta, double dt,
                 const or_opts* o, double* u, double* p, or_stats* st);
+/* Time step of the stability rule (Sec. II.C.1, Eqs. cfl:dt ... cfl:viscous:new). */
+double or_stable_dt(const or_geom* g, const or_rheo* r, const double* theta, const double* u,
+                    const double force[3], double c_cfl);
 void or_drag(const or_geom* g, const or_rheo* r, const double* theta, const double* u,
              const double* p, double F[3]);
 

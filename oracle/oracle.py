@@ -84,6 +84,7 @@ def lib():
             "or_derived": (_I, [_P, _P, _P, _P, _P, _P, _P, _P, _P, C.POINTER(C.c_int)]),
             "or_rk2_step": (_I, [_P, _P, _P, _D, _P, _P, _P, _P]),
             "or_drag": (None, [_P, _P, _P, _P, _P, _P]),
+            "or_stable_dt": (C.c_double, [_P, _P, _P, _P, _P, C.c_double]),
             "or_wall_gradient_adj": (None, [_P, _P, _P]),
             "or_cell_gradient_adj": (None, [_P, _P, _P, _P]),
             "or_redistribute_adj": (None, [_P, _I, _P, _P]),
@@ -363,6 +364,11 @@ class Geometry:
         stats = {"it_mac": list(st.it_mac), "it_visc": list(st.it_visc),
                  "it_proj": list(st.it_proj), "div_proj": list(st.div_proj)}
         return u, p, stats
+
+    def stable_dt(self, u, rheo, force=(0.0, 0.0, 0.0), c_cfl=0.5, theta=None):
+        f = np.ascontiguousarray(np.asarray(force, dtype=np.float64))
+        return lib().or_stable_dt(self.g, C.byref(rheo), _ptr(theta),
+                                  _ptr(np.ascontiguousarray(u)), _ptr(f), float(c_cfl))
 
     def drag(self, u, p, rheo, theta=None):
         F = np.zeros(3)

@@ -14,6 +14,7 @@ EB_OK, EB_EINVAL, EB_EGEOM, EB_ENOCONV, EB_ENAN, EB_EHIP, EB_ENOMEM = 0, -1, -2,
 EB_FP64, EB_MIXED = 0, 1
 EB_SYS_POISSON, EB_SYS_VISC = 0, 1
 EB_OP_HELMHOLTZ, EB_OP_HELMHOLTZ_H, EB_OP_TRANSPOSE = 0, 1, 2
+EB_SWITCH_OFF, EB_SWITCH_RECORD, EB_SWITCH_REPLAY = 0, 1, 2
 ERRNAMES = {0: "EB_OK", -1: "EB_EINVAL", -2: "EB_EGEOM", -3: "EB_ENOCONV", -4: "EB_ENAN",
             -5: "EB_EHIP", -6: "EB_ENOMEM"}
 
@@ -43,7 +44,7 @@ class EbStepOpts(C.Structure):
 class EbStepStats(C.Structure):
     _fields_ = [("it_mac", C.c_int * 2), ("it_visc", C.c_int * 2), ("it_proj", C.c_int * 2),
                 ("div_proj", C.c_double * 2), ("vcycles", C.c_int), ("status", C.c_int),
-                ("fp64_fallbacks", C.c_int)]
+                ("fp64_fallbacks", C.c_int), ("dt_stable", C.c_double)]
 
 
 _P = C.c_void_p
@@ -58,6 +59,9 @@ SIGNATURES = {
     "eb_ctx_destroy": (None, [_P]),
     "eb_ctx_info": (_I, [_P, _IP, _IP, _IP]),
     "eb_ctx_set_graphs": (_I, [_P, _I]),
+    "eb_switch_bytes": (C.c_size_t, [_P]),
+    "eb_stable_dt": (_I, [_P, _P, _P, _P, _P, _D, _DP, _P]),
+    "eb_ctx_set_switches": (_I, [_P, _I, _P, C.c_size_t]),
     "eb_geometry_export": (_I, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "eb_apparent_viscosity": (_I, [_P, _P, _P, _P, _P, _P, _P, _P]),
     "eb_viscous_apply": (_I, [_P, _I, _D, _D, _P, _P, _P, _P, _P]),

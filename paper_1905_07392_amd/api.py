@@ -12,17 +12,18 @@ import torch
 
 from . import _lib as L
 from ._lib import (EB_FP64, EB_MIXED, EB_OP_HELMHOLTZ, EB_OP_HELMHOLTZ_H, EB_OP_TRANSPOSE,
-                   EB_SYS_POISSON, EB_SYS_VISC, EbBody, EbBox, EbRheology, EbStepOpts,
-                   EbStepStats, check)
+                   EB_SWITCH_OFF, EB_SWITCH_RECORD, EB_SWITCH_REPLAY, EB_SYS_POISSON, EB_SYS_VISC,
+                   EbBody, EbBox, EbRheology, EbStepOpts, EbStepStats, check)
 
 __all__ = ["EbContext", "make_box", "make_body", "make_rheology", "make_opts",
            "eb_workspace_bytes", "eb_geometry_build", "eb_geometry_export",
            "eb_apparent_viscosity", "eb_viscous_apply", "eb_mg_vcycle", "eb_visc_solve",
            "eb_mac_project", "eb_cc_project", "eb_derived", "eb_rk2_step", "eb_drag",
-           "eb_pressure_gradient", "eb_tape_bytes", "eb_rk2_step_taped", "eb_rk2_step_adjoint",
-           "eb_drag_adjoint", "eb_mac_project_adjoint", "eb_cc_project_adjoint",
+           "eb_pressure_gradient", "eb_stable_dt", "eb_tape_bytes", "eb_rk2_step_taped",
+           "eb_rk2_step_adjoint", "eb_drag_adjoint", "eb_mac_project_adjoint", "eb_cc_project_adjoint",
            "eb_visc_solve_adjoint", "eb_derived_adjoint", "EB_FP64", "EB_MIXED", "EB_OP_HELMHOLTZ",
-           "EB_OP_HELMHOLTZ_H", "EB_OP_TRANSPOSE", "EB_SYS_POISSON", "EB_SYS_VISC"]
+           "EB_OP_HELMHOLTZ_H", "EB_OP_TRANSPOSE", "EB_SYS_POISSON", "EB_SYS_VISC",
+           "EB_SWITCH_OFF", "EB_SWITCH_RECORD", "EB_SWITCH_REPLAY"]
 
 
 def _stream(device=None):
@@ -141,6 +142,23 @@ class EbContext:
     def set_graphs(self, enable: bool):
         """Replay captured solver iterations (default) or launch every kernel individually."""
         check(L.lib().eb_ctx_set_graphs(self.ptr, int(bool(enable))), "eb_ctx_set_graphs")
+
+    def switch_record(self, evaluations: int):
+        """A zeroed uint8 device buffer for the branch records of `evaluations` derived-
+        quantities evaluations (two per RK2 step)."""
+        nb = int(L.lib().eb_switch_bytes(self.ptr))
+        return torch.zeros(nb * int(evaluations), dtype=torch.uint8, device=self.device)
+
+    def set_switches(self, mode: int, record=None):
+        """EB_SWITCH_RECORD / EB_SWITCH_REPLAY the step's switches into / from `record` (from
+        its start), or EB_SWITCH_OFF."""
+        if mode == L.EB_SWITCH_OFF:
+            check(L.lib().eb_ctx_set_switches(self.ptr, 0, None, 0), "eb_ctx_set_switches")
+            return
+        assert record is not None and record.dtype == torch.uint8 and record.is_contiguous()
+        assert record.device == self.device
+        check(L.lib().eb_ctx_set_switches(self.ptr, int(mode), C.c_void_p(record.data_ptr()),
+                                          record.numel()), "eb_ctx_set_switches")
 
     def zeros(self, *shape):
         return torch.zeros(shape, dtype=torch.float64, device=self.device)
@@ -285,7 +303,19 @@ def eb_rk2_step(ctx: EbContext, rheo: EbRheology, dt, opts: EbStepOpts, u, p, th
 def _stats(st):
     return {"it_mac": list(st.it_mac), "it_visc": list(st.it_visc),
             "it_proj": list(st.it_proj), "div_proj": list(st.div_proj),
-            "vcycles": st.vcycles, "status": st.status, "fp64_fallbacks": st.fp64_fallbacks}
+            "vcycles": st.vcycles, "status": st.status, "fp64_fallbacks": st.fp64_fallbacks,
+            "dt_stable": st.dt_stable}
+
+
+def eb_stable_dt(ctx: EbContext, rheo: EbRheology, u, force=(0.0, 0.0, 0.0), c_cfl=0.5,
+                 theta=None):
+    """Time step of the paper's stability rule for the state u (host float)."""
+    dt = C.c_double(0.0)
+    f = (C.c_double * 3)(*[float(x) for x in force])
+    th = _f64(theta, ctx.shape, "theta") if theta is not None else None
+    check(L.lib().eb_stable_dt(ctx.ptr, C.byref(rheo), th, _f64(u, (3,) + ctx.shape, "u"), f,
+                               float(c_cfl), C.byref(dt), _stream(ctx.device)), "eb_stable_dt")
+    return dt.value
 
 
 def eb_drag(ctx: EbContext, rheo: EbRheology, u, p, theta=None):

@@ -111,6 +111,11 @@ struct eb_ctx {
     // reset (host side)
     int slot_off[NSLOT];
     int fp64_fallbacks;
+    // branch record/replay of the derived quantities (eb_ctx_set_switches): mode, the caller's
+    // buffer and the offset of the next evaluation's record in it
+    int sw_mode;
+    uint8_t* sw_buf;
+    size_t sw_bytes, sw_cur;
 };
 
 namespace {
@@ -797,16 +802,50 @@ int slot_code(const int* sl, const char* what, int max_iter) {
     return set_err(EB_ENOCONV, "%s: no convergence in %d iterations", what, max_iter);
 }
 
+// bytes of one evaluation's branch record: slopes [3][3][N], then the normal and the
+// transverse upwind sides per face of each direction
+size_t switch_bytes(const eb_ctx* c) {
+    size_t nf = 0;
+    for (int d = 0; d < 3; d++) nf += (size_t)face_count(c->grid, d);
+    return 9 * (size_t)c->N + 2 * nf;
+}
+
+// the branch record of the next derived-quantities evaluation (mode 0: none)
+int next_switches(eb_ctx* c, SwitchV* sw) {
+    *sw = SwitchV{};
+    if (c->sw_mode == 0) return EB_OK;
+    size_t blk = switch_bytes(c);
+    if (c->sw_cur + blk > c->sw_bytes)
+        return set_err(EB_EINVAL, "branch record buffer of %zu bytes holds no evaluation at "
+                                  "offset %zu (%zu bytes each)", c->sw_bytes, c->sw_cur, blk);
+    uint8_t* b = c->sw_buf + c->sw_cur;
+    sw->mode = c->sw_mode;
+    sw->slope = b;
+    b += 9 * (size_t)c->N;
+    for (int d = 0; d < 3; d++) {
+        sw->norm[d] = b;
+        b += face_count(c->grid, d);
+    }
+    for (int d = 0; d < 3; d++) {
+        sw->tr[d] = b;
+        b += face_count(c->grid, d);
+    }
+    c->sw_cur += blk;
+    return EB_OK;
+}
+
 // DerivedQuantities; the MAC projection reports into `slot`
 int derived(eb_ctx* c, const eb_rheology& rh, const double* theta, const double* u,
             const eb_step_opts* o, double* C, double* eta, double* eta_eb, double* V,
             int slot) {
     SolveCfg k = cfg_of(o);
     double rtol = o && o->rtol_mac > 0 ? o->rtol_mac : 1e-12;
-    op_face_extrap(c->g, u, c->f, c->s);
+    SwitchV sw;
+    if (int h = next_switches(c, &sw)) return h;
+    op_face_extrap(c->g, u, c->f, sw, c->s);
     vec_fill(c->N, 0.0, c->phi, c->s);
     mac_project(c, 1.0, c->f, c->phi, rtol, k, slot, false);
-    op_conv_dc(c->g, u, c->f, c->DC, c->s);
+    op_conv_dc(c->g, u, c->f, c->DC, sw, c->s);
     op_redistribute(c->g, c->DC, c->DH, c->rS, c->rdD, C, c->s);
     op_wall_grad(c->g, u, c->gw, c->s);
     op_grad_eta(c->g, rh, u, c->gw, theta, c->G9, eta, nullptr, c->s);
@@ -1002,6 +1041,22 @@ int eb_ctx_set_graphs(eb_ctx* c, int enable) {
     return EB_OK;
 }
 
+size_t eb_switch_bytes(const eb_ctx* c) { return c ? switch_bytes(c) : 0; }
+
+int eb_ctx_set_switches(eb_ctx* c, int mode, void* buf, size_t bytes) {
+    if (!c) return set_err(EB_EINVAL, "null context");
+    if (mode != EB_SWITCH_OFF && mode != EB_SWITCH_RECORD && mode != EB_SWITCH_REPLAY)
+        return set_err(EB_EINVAL, "unknown branch record mode %d", mode);
+    if (mode != EB_SWITCH_OFF && (!buf || bytes < switch_bytes(c)))
+        return set_err(EB_EINVAL, "branch record buffer of %zu bytes < %zu", bytes,
+                       switch_bytes(c));
+    c->sw_mode = mode;
+    c->sw_buf = mode == EB_SWITCH_OFF ? nullptr : (uint8_t*)buf;
+    c->sw_bytes = mode == EB_SWITCH_OFF ? 0 : bytes;
+    c->sw_cur = 0;
+    return EB_OK;
+}
+
 int eb_ctx_info(const eb_ctx* c, int* ncut, int* nlevels, int* nfallback) {
     if (!c) return set_err(EB_EINVAL, "null context");
     if (ncut) *ncut = c->ncut;
@@ -1185,13 +1240,30 @@ int eb_derived(eb_ctx* c, const eb_rheology* rheo, const double* theta, const do
 
 namespace {
 
-// stats and return code of a step (forward or reverse) from its six solve slots
-int step_status(eb_ctx* c, const SolveCfg& k, eb_step_stats* stats, bool adjoint) {
+// the time step of the stability rule (Sec. II.C.1: Eqs. cfl:convective, cfl:forcing,
+// cfl:viscous:new combined by Eq. cfl:dt) from umax = max over open cells of |u|+|v|+|w| and
+// tmax = the largest yield-stress multiplier there
+double stable_dt_of(const eb_ctx* c, const eb_rheology& r, double umax, double tmax,
+                    const double force[3], double c_cfl) {
+    double h = c->box.h;
+    double cc = umax / h;
+    double bi = r.law == EB_LAW_NEWTONIAN ? 0.0 : r.tau0 * tmax;
+    if (bi < 0.0) bi = 0.0;
+    double cf = sqrt((fabs(force[0]) + fabs(force[1]) + fabs(force[2])) / h);
+    double cv = 2.0 * r.mu / r.rho * (bi + 1.0) * (3.0 / (h * h));
+    double a = cc + cv;
+    return c_cfl / (0.5 * (a + sqrt(a * a + 4.0 * cf * cf)));
+}
+
+// stats and return code of a step (forward or reverse) from its six solve slots; a forward
+// step also reports the stability-rule time step of its input state (reduced into divs[6..7])
+int step_status(eb_ctx* c, const SolveCfg& k, eb_step_stats* stats, bool adjoint,
+                const eb_rheology* rheo = nullptr, const eb_step_opts* o = nullptr) {
     int sl[12];
-    double dv[6];
+    double dv[8];
     int h;
     if ((h = read_slots(c, 6, sl))) return h;
-    hipMemcpy(dv, c->divs, 6 * sizeof(double), hipMemcpyDeviceToHost);
+    hipMemcpy(dv, c->divs, 8 * sizeof(double), hipMemcpyDeviceToHost);
     eb_step_stats st;
     memset(&st, 0, sizeof(st));
     int status = EB_OK;
@@ -1213,6 +1285,8 @@ int step_status(eb_ctx* c, const SolveCfg& k, eb_step_stats* stats, bool adjoint
     }
     st.status = status;
     st.fp64_fallbacks = c->fp64_fallbacks;
+    st.dt_stable = (!adjoint && rheo && o) ? stable_dt_of(c, *rheo, dv[6], dv[7], o->force, 0.5)
+                                           : 0.0;
     if (stats) *stats = st;
     return status;
 }
@@ -1227,6 +1301,7 @@ int rk2_impl(eb_ctx* c, const eb_rheology* rheo, const double* theta, double dt,
     double rho = rheo->rho, beta = dt / rho;
     int h;
     c->fp64_fallbacks = 0;
+    red_cfl(c->g, u, theta, c->part, c->divs + 6, c->s);  // for the stats' stable time step
     // slots: 0/3 MAC projection, 1/4 viscous solve, 2/5 end-of-stage projection
     // predictor: derived quantities at u^m
     if ((h = derived(c, *rheo, theta, u, o, c->C0, c->eta0, c->eb0, c->V0, 0))) return h;
@@ -1265,7 +1340,7 @@ int rk2_impl(eb_ctx* c, const eb_rheology* rheo, const double* theta, double dt,
     op_finalize_state(c->g, u, p, c->s);
     if ((h = hip_check("eb_rk2_step"))) return h;
     // one read-back for the whole step
-    return step_status(c, k, stats, false);
+    return step_status(c, k, stats, false, rheo, o);
 }
 
 }  // namespace
@@ -1438,7 +1513,7 @@ int eb_derived_adjoint(eb_ctx* c, const eb_rheology* rheo, const double* theta, 
     SolveCfg k = cfg_of(opts);
     double rtol = opts && opts->rtol_mac > 0 ? opts->rtol_mac : 1e-12;
     // the forward face velocities: extrapolate and project (slot 1), keep a copy
-    op_face_extrap(c->g, u, c->f, c->s);
+    op_face_extrap(c->g, u, c->f, SwitchV{}, c->s);
     vec_fill(c->N, 0.0, c->phi, c->s);
     mac_project(c, 1.0, c->f, c->phi, rtol, k, 1, false);
     double* uf[3];
@@ -1454,6 +1529,22 @@ int eb_derived_adjoint(eb_ctx* c, const eb_rheology* rheo, const double* theta, 
     if (iters) *iters = sl[1];
     if (sl[2] != 2) return slot_code(sl + 2, "MAC projection", k.max_iter);
     return slot_code(sl, "adjoint MAC projection", k.max_iter);
+}
+
+int eb_stable_dt(const eb_ctx* cc, const eb_rheology* rheo, const double* theta,
+                 const double* u, const double force[3], double c_cfl, double* dt,
+                 void* stream) {
+    if (!cc || !rheo || !u || !force || !dt) return set_err(EB_EINVAL, "null argument");
+    if (!(c_cfl > 0.0) || !(rheo->rho > 0.0)) return set_err(EB_EINVAL, "c_cfl and rho must be > 0");
+    eb_ctx* c = const_cast<eb_ctx*>(cc);
+    hipStream_t s = (hipStream_t)stream;
+    double m[2];
+    red_cfl(c->g, u, theta, c->part, c->red, s);
+    hipMemcpyAsync(m, c->red, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return set_err(EB_EHIP, "eb_stable_dt: %s", hipGetErrorString(e));
+    *dt = stable_dt_of(c, *rheo, m[0], m[1], force, c_cfl);
+    return EB_OK;
 }
 
 int eb_pressure_gradient(const eb_ctx* cc, const double* p, double* gp, void* stream) {

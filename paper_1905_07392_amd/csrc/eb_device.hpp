@@ -29,6 +29,35 @@ __device__ __forceinline__ long nbr(const GridV& g, int i, int j, int k, int d, 
 }
 
 // monotonised-central limited slope of component uj along d at cell c
+// branch of the monotonised-central slope of uj at c in direction d: 0 zero (a wall or covered
+// neighbour, or an extremum), else which of |dc|, 2|dl|, 2|dr| is least (1, 2, 3)
+__device__ inline int mc_branch(const GeomV& g, const double* __restrict__ uj, long c, int d) {
+    int i, j, k;
+    cell_coords(g.grid, c, i, j, k);
+    long lo = nbr(g.grid, i, j, k, d, -1), hi = nbr(g.grid, i, j, k, d, 1);
+    if (lo < 0 || hi < 0) return 0;
+    if (!(g.alpha[lo] > 0.0) || !(g.alpha[hi] > 0.0)) return 0;
+    double uc = uj[c];
+    double dl = uc - uj[lo], dr = uj[hi] - uc, dc = 0.5 * (uj[hi] - uj[lo]);
+    if (dl * dr <= 0.0) return 0;
+    double a = fabs(dc), b = 2.0 * fabs(dl), e = 2.0 * fabs(dr);
+    if (a <= b && a <= e) return 1;
+    return b <= e ? 2 : 3;
+}
+
+// the slope on a given branch; on the branch mc_branch picks it equals mc_slope bit for bit
+// (the three differences share their sign there)
+__device__ inline double mc_eval(const GeomV& g, const double* __restrict__ uj, long c, int d,
+                                 int code) {
+    if (code == 0) return 0.0;
+    int i, j, k;
+    cell_coords(g.grid, c, i, j, k);
+    long lo = nbr(g.grid, i, j, k, d, -1), hi = nbr(g.grid, i, j, k, d, 1);
+    if (lo < 0 || hi < 0) return 0.0;
+    if (code == 1) return 0.5 * (uj[hi] - uj[lo]);
+    return code == 2 ? 2.0 * (uj[c] - uj[lo]) : 2.0 * (uj[hi] - uj[c]);
+}
+
 __device__ inline double mc_slope(const GeomV& g, const double* __restrict__ uj, long c, int d) {
     int i, j, k;
     cell_coords(g.grid, c, i, j, k);

@@ -186,9 +186,20 @@ void op_eta_eb(const GeomV& g, const eb_rheology& r, const double* gw, const dou
                double* eta_eb, hipStream_t s);
 void op_transpose_dc(const GeomV& g, const double* u, const double* G9, const double* eta,
                      const double* eta_eb, const double* gw, double* DC, hipStream_t s);
-void op_face_extrap(const GeomV& g, const double* u, double* f[3], hipStream_t s);
+// Branch record of the derived quantities' switches (the limited slope's branch, the normal
+// upwind side, the transverse upwind side): mode 0 computes them, 1 computes and records them,
+// 2 evaluates the recorded ones (the step frozen on its pieces of smoothness).
+struct SwitchV {
+    int mode;
+    uint8_t* slope;    // [component][direction][N]: 0 zero, 1 central, 2 twice left, 3 twice right
+    uint8_t* norm[3];  // per face of each direction: 0 zero, 1 left state, 2 right state
+    uint8_t* tr[3];    // per face: 1 left state, 2 right state, 3 their mean
+};
+void op_face_extrap(const GeomV& g, const double* u, double* f[3], const SwitchV& sw,
+                    hipStream_t s);
 void op_divergence(const GeomV& g, double* const f[3], double* div, hipStream_t s);
-void op_conv_dc(const GeomV& g, const double* u, double* const f[3], double* DC, hipStream_t s);
+void op_conv_dc(const GeomV& g, const double* u, double* const f[3], double* DC,
+                const SwitchV& sw, hipStream_t s);
 void op_redistribute(const GeomV& g, const double* DC, double* DH, double* S, double* dD,
                      double* D, hipStream_t s);
 void op_gcc(const GeomV& g, const double* p, double* gp, hipStream_t s);
@@ -255,6 +266,9 @@ void red_dots(long n, int npairs, const double* const a[4], const double* const 
 void red_maxabs(long n, int ncomp, const double* x, double* part, double* out, hipStream_t s,
                 const int* gate = nullptr);
 void red_sum_open(const GeomV& g, const double* x, double* part, double* out, hipStream_t s);
+// out[0] = max over open cells of |u|+|v|+|w|, out[1] = max of theta there (1 if null)
+void red_cfl(const GeomV& g, const double* u, const double* theta, double* part, double* out,
+             hipStream_t s);
 void red_sum(long n, int nrow, const double* x, double* part, double* out, hipStream_t s);
 void op_face_flux_max(const GeomV& g, double* const f[3], double* part, double* out,
                       hipStream_t s);

@@ -1180,6 +1180,25 @@ __global__ void k_maxabs(long n, int ncomp, const double* __restrict__ x,
     }
 }
 
+// over open cells: the largest |u| + |v| + |w| (row 0) and the largest yield-stress multiplier
+// (row 1; 1 without a field), per block
+__global__ void k_cfl_max(GeomV g, const double* __restrict__ u, const double* __restrict__ theta,
+                          double* __restrict__ part) {
+    __shared__ double sh[EB_BLOCK];
+    long N = g.N;
+    double a = 0.0, t = 0.0;
+    for (long c = blockIdx.x * (long)blockDim.x + threadIdx.x; c < N;
+         c += (long)gridDim.x * blockDim.x)
+        if (g.alpha[c] > 0.0) {
+            a = fmax(a, fabs(u[c]) + fabs(u[N + c]) + fabs(u[2 * N + c]));
+            t = fmax(t, theta ? theta[c] : 1.0);
+        }
+    a = block_max(a, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = a;
+    t = block_max(t, sh);
+    if (threadIdx.x == 0) part[gridDim.x + blockIdx.x] = t;
+}
+
 __global__ void k_sum_open(GeomV g, const double* __restrict__ x, double* __restrict__ part) {
     __shared__ double sh[EB_BLOCK];
     double s = 0.0, cnt = 0.0;
@@ -1690,6 +1709,13 @@ void red_maxabs(long n, int ncomp, const double* x, double* part, double* out, h
     int nb = red_blocks(n);
     k_maxabs<<<nb, EB_BLOCK, 0, s>>>(n, ncomp, x, part, gate);
     k_final<<<1, EB_BLOCK, 0, s>>>(part, nb, ncomp, 1, out, gate);
+}
+
+void red_cfl(const GeomV& g, const double* u, const double* theta, double* part, double* out,
+             hipStream_t s) {
+    int nb = red_blocks(g.N);
+    k_cfl_max<<<nb, EB_BLOCK, 0, s>>>(g, u, theta, part);
+    k_final<<<1, EB_BLOCK, 0, s>>>(part, nb, 2, 1, out, nullptr);
 }
 
 void red_sum_open(const GeomV& g, const double* x, double* part, double* out, hipStream_t s) {

@@ -163,8 +163,19 @@ __global__ void k_transpose_dc(GeomV g, const double* __restrict__ u,
 // ------------------------------------------------------------------------------------------
 // limited slopes and face states (Sec. III.A.3)
 // ------------------------------------------------------------------------------------------
+// limited slope of component j at c in direction d, computed, recorded or taken from the
+// record (duplicate records of one slope by several threads carry the same value)
+__device__ inline double slope_sw(const GeomV& g, const double* __restrict__ uj, long c, int d,
+                                  int j, const SwitchV& sw) {
+    if (sw.mode == 0) return mc_slope(g, uj, c, d);
+    long at = (long)(3 * j + d) * g.N + c;
+    int code = sw.mode == 2 ? (int)sw.slope[at] : mc_branch(g, uj, c, d);
+    if (sw.mode == 1) sw.slope[at] = (uint8_t)code;
+    return mc_eval(g, uj, c, d, code);
+}
+
 __global__ void k_face_extrap(GeomV g, int d, const double* __restrict__ u,
-                              double* __restrict__ w) {
+                              double* __restrict__ w, SwitchV sw) {
     long nf = face_count(g.grid, d);
     long f = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (f >= nf) return;
@@ -177,10 +188,13 @@ __global__ void k_face_extrap(GeomV g, int d, const double* __restrict__ u,
         val = g.wall[2 * d + (lo >= 0)][d];
     } else if (g.ap[d][f] > 0.0) {
         const double* ud = u + (long)d * g.N;
-        double uL = ud[lo] + 0.5 * mc_slope(g, ud, lo, d);
-        double uR = ud[hi] - 0.5 * mc_slope(g, ud, hi, d);
-        if (uL > 0.0 && uL + uR > 0.0) val = uL;
-        else if (uR < 0.0 && uL + uR < 0.0) val = uR;
+        double uL = ud[lo] + 0.5 * slope_sw(g, ud, lo, d, d, sw);
+        double uR = ud[hi] - 0.5 * slope_sw(g, ud, hi, d, d, sw);
+        int side;  // normal upwinding: 1 left, 2 right, 0 neither
+        if (sw.mode == 2) side = sw.norm[d][f];
+        else side = (uL > 0.0 && uL + uR > 0.0) ? 1 : ((uR < 0.0 && uL + uR < 0.0) ? 2 : 0);
+        if (sw.mode == 1) sw.norm[d][f] = (uint8_t)side;
+        val = side == 1 ? uL : (side == 2 ? uR : 0.0);
     }
     w[f] = val;
 }
@@ -217,7 +231,7 @@ __global__ void k_divergence(GeomV g, const double* __restrict__ fx,
 // convective flux divergence -(1/(alpha h)) sum_f A_f w_f u_up (upwinded by w_f)
 __global__ void k_conv_dc(GeomV g, const double* __restrict__ u, const double* __restrict__ fx,
                           const double* __restrict__ fy, const double* __restrict__ fz,
-                          double* __restrict__ DC) {
+                          double* __restrict__ DC, SwitchV sw) {
     long N = g.N;
     long c = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (c >= N) return;
@@ -240,15 +254,21 @@ __global__ void k_conv_dc(GeomV g, const double* __restrict__ u, const double* _
             long lo, hi;
             face_cells(g.grid, d, f[0], f[1], f[2], lo, hi);
             double w = fo[d][fi];
+            int ups = 0;  // upwind side by the face velocity: 1 left, 2 right, 3 the mean
+            if (lo >= 0 && hi >= 0) {
+                if (sw.mode == 2) ups = sw.tr[d][fi];
+                else ups = w > 0.0 ? 1 : (w < 0.0 ? 2 : 3);
+                if (sw.mode == 1) sw.tr[d][fi] = (uint8_t)ups;
+            }
             for (int j = 0; j < 3; j++) {
                 double up;
                 if (lo < 0 || hi < 0) {
                     up = g.wall[2 * d + (lo >= 0)][j];
                 } else {
                     const double* uj = u + (long)j * N;
-                    double uL = uj[lo] + 0.5 * mc_slope(g, uj, lo, d);
-                    double uR = uj[hi] - 0.5 * mc_slope(g, uj, hi, d);
-                    up = w > 0.0 ? uL : (w < 0.0 ? uR : 0.5 * (uL + uR));
+                    double uL = uj[lo] + 0.5 * slope_sw(g, uj, lo, d, j, sw);
+                    double uR = uj[hi] - 0.5 * slope_sw(g, uj, hi, d, j, sw);
+                    up = ups == 1 ? uL : (ups == 2 ? uR : 0.5 * (uL + uR));
                 }
                 acc[j] += side * A * w * up;
             }
@@ -488,15 +508,17 @@ void op_transpose_dc(const GeomV& g, const double* u, const double* G9, const do
                      const double* eta_eb, const double* gw, double* DC, hipStream_t s) {
     k_transpose_dc<<<grid_for(g.N), EB_BLOCK, 0, s>>>(g, u, G9, eta, eta_eb, gw, DC);
 }
-void op_face_extrap(const GeomV& g, const double* u, double* f[3], hipStream_t s) {
+void op_face_extrap(const GeomV& g, const double* u, double* f[3], const SwitchV& sw,
+                    hipStream_t s) {
     for (int d = 0; d < 3; d++)
-        k_face_extrap<<<grid_for(face_count(g.grid, d)), EB_BLOCK, 0, s>>>(g, d, u, f[d]);
+        k_face_extrap<<<grid_for(face_count(g.grid, d)), EB_BLOCK, 0, s>>>(g, d, u, f[d], sw);
 }
 void op_divergence(const GeomV& g, double* const f[3], double* div, hipStream_t s) {
     k_divergence<<<grid_for(g.N), EB_BLOCK, 0, s>>>(g, f[0], f[1], f[2], div);
 }
-void op_conv_dc(const GeomV& g, const double* u, double* const f[3], double* DC, hipStream_t s) {
-    k_conv_dc<<<grid_for(g.N), EB_BLOCK, 0, s>>>(g, u, f[0], f[1], f[2], DC);
+void op_conv_dc(const GeomV& g, const double* u, double* const f[3], double* DC,
+                const SwitchV& sw, hipStream_t s) {
+    k_conv_dc<<<grid_for(g.N), EB_BLOCK, 0, s>>>(g, u, f[0], f[1], f[2], DC, sw);
 }
 void op_redistribute(const GeomV& g, const double* DC, double* DH, double* S, double* dD,
                      double* D, hipStream_t s) {

@@ -260,3 +260,124 @@ def test_bench_size_adjoint_bi_fd():
     fd = (loss(w.tau0 + e) - loss(w.tau0 - e)) / (2 * e)
     print(f"[adjoint] 128^3 dFz/dBi adjoint {g_bi:.12e} fd {fd:.12e} stats {st}", flush=True)
     assert abs(fd - g_bi) <= 1e-5 * abs(g_bi)
+
+
+def test_switch_record_replay():
+    """Recording the step's switches leaves its results bitwise unchanged; replaying the record
+    from the same state reproduces them bitwise; a record too small for the run is refused."""
+    import paper_1905_07392_amd as pkg
+    from paper_1905_07392_amd import api
+
+    _require_gpu()
+    w = I.sphere32()
+    box, body, rheo, opts = pkg.from_workload(w)
+    ctx = api.eb_geometry_build(box, body, "cuda:0")
+    u0 = torch.from_numpy(I.initial_velocity(w)).to("cuda:0")
+    u0[2] += 0.2 * torch.from_numpy(I.random_field(ctx.shape, seed=4)).to("cuda:0")
+    theta = torch.from_numpy(I.yield_field(w)).to("cuda:0")
+
+    def run(mode=None, rec=None, nsteps=3):
+        if mode is not None:
+            ctx.set_switches(mode, rec)
+        try:
+            u, p = u0.clone(), ctx.scalar()
+            for _ in range(nsteps):
+                u, p, _ = api.eb_rk2_step(ctx, rheo, w.dt, opts, u, p, theta=theta)
+        finally:
+            ctx.set_switches(api.EB_SWITCH_OFF)
+        return u, p
+
+    u_off, p_off = run()
+    rec = ctx.switch_record(6)
+    u_rec, p_rec = run(api.EB_SWITCH_RECORD, rec)
+    assert torch.equal(u_rec, u_off) and torch.equal(p_rec, p_off)
+    nb = rec.numel() // 6
+    for e in range(6):  # every evaluation wrote its record: slopes of all three kinds occur
+        blk = rec[e * nb:(e + 1) * nb]
+        assert all(int((blk == v).sum()) > 0 for v in (1, 2, 3))
+    u_rep, p_rep = run(api.EB_SWITCH_REPLAY, rec)
+    assert torch.equal(u_rep, u_off) and torch.equal(p_rep, p_off)
+    small = ctx.switch_record(5)
+    with pytest.raises(Exception, match="branch record"):
+        run(api.EB_SWITCH_RECORD, small)
+
+
+@pytest.mark.parametrize("n,nsteps", [(128, 5), (32, 20)])
+def test_adjoint_workload_fd(n, nsteps):
+    """The adjoint workload (sphere r = 0.125, Bi = 10, theta seeded, rho = 4e-3, dt = 5e-4)
+    at n^3: the checkpointed autograd gradients of F_z in Bi and in the two most sensitive of
+    16 seeded cells near the body against central differences of the forward run with its
+    switches replayed from the unperturbed run (the derivative the adjoint computes), bar
+    1e-5; the plain differences and the switches each perturbed run flips are printed.  At
+    128^3 the horizon is 5 steps: beyond it this dt, 2.7e5 times the stability rule's, lets
+    perturbations near the body grow about 2.5-fold per step (the bench reports the 20-step
+    differences); at 32^3 they stay bounded and 20 steps are checked."""
+    import copy
+
+    import paper_1905_07392_amd as pkg
+    from paper_1905_07392_amd import api
+    from paper_1905_07392_amd import autograd as AG
+
+    _require_gpu()
+    w = I.sphere128()
+    if n != 128:
+        w = w.replace(n=(n, n, n), h=1.0 / n, name=f"sphere{n}")
+    box, body, rheo, opts = pkg.from_workload(w, max_iter=1000)
+    ctx = api.eb_geometry_build(box, body, "cuda:0")
+    print(f"[adjoint] fd workload {w.name}, {nsteps} steps", flush=True)
+    u0 = torch.from_numpy(I.initial_velocity(w)).to("cuda:0")
+    p0 = ctx.scalar()
+    theta = torch.from_numpy(I.yield_field(w, seed=1)).to("cuda:0")
+    o = copy.copy(opts)
+    o.rtol_visc = o.rtol_mac = o.rtol_proj = 1e-13
+    th = theta.clone().requires_grad_(True)
+    bi = torch.tensor(float(w.tau0), dtype=torch.float64, device="cuda:0", requires_grad=True)
+    u, p = AG.rollout(ctx, rheo, w.dt, o, u0, p0, th, bi, nsteps, ckpt_every=5)
+    AG.drag(ctx, rheo, u, p, th, bi)[2].backward()
+    g_bi, g_th = float(bi.grad), cpu(th.grad).ravel()
+
+    base, other = ctx.switch_record(2 * nsteps), ctx.switch_record(2 * nsteps)
+
+    def loss(tau0, thv, mode, rec):
+        r = api.make_rheology(rheo.law, rheo.mu, tau0, rheo.eps, rheo.rho)
+        uu, pp = u0.clone(), p0.clone()
+        ctx.set_switches(mode, rec)
+        try:
+            for _ in range(nsteps):
+                api.eb_rk2_step(ctx, r, w.dt, o, uu, pp, theta=thv, inplace=True,
+                                allow_noconv=True)
+        finally:
+            ctx.set_switches(api.EB_SWITCH_OFF)
+        return api.eb_drag(ctx, r, uu, pp, theta=thv)[2]
+
+    loss(w.tau0, theta, api.EB_SWITCH_RECORD, base)
+
+    def check(name, ap, am, h, g):
+        lp = loss(*ap, api.EB_SWITCH_RECORD, other)
+        flips = [int((other != base).sum())]
+        lm = loss(*am, api.EB_SWITCH_RECORD, other)
+        flips.append(int((other != base).sum()))
+        fdf = (loss(*ap, api.EB_SWITCH_REPLAY, base)
+               - loss(*am, api.EB_SWITCH_REPLAY, base)) / (2 * h)
+        fd = (lp - lm) / (2 * h)
+        print(f"[adjoint] {name}: adjoint {g:.10e} frozen fd {fdf:.10e} "
+              f"(rel {abs(fdf - g) / abs(g):.2e}); plain fd {fd:.10e} "
+              f"(rel {abs(fd - g) / abs(g):.2e}), switches flipped {flips}", flush=True)
+        assert abs(fdf - g) <= 1e-5 * abs(g)
+
+    h = 1e-6 * w.tau0
+    check("Bi", (w.tau0 + h, theta), (w.tau0 - h, theta), h, g_bi)
+    nz, ny, nx = ctx.shape
+    zz, yy, xx = np.meshgrid(*[(np.arange(m) + 0.5) * w.h for m in (nz, ny, nx)], indexing="ij")
+    c = w.body["center"]
+    dist = np.sqrt((xx - c[0]) ** 2 + (yy - c[1]) ** 2 + (zz - c[2]) ** 2) - w.body["radius"]
+    _, alpha, _, _, _ = api.eb_geometry_export(ctx)
+    cand = np.flatnonzero((cpu(alpha) > 0).ravel() & (np.abs(dist).ravel() < 3 * w.h))
+    picks = I.rng(2).choice(cand, size=16, replace=False)
+    for cidx in picks[np.argsort(-np.abs(g_th[picks]))[:2]]:
+        hc = 1e-3 * float(theta.view(-1)[cidx])
+        tp, tm = theta.clone().view(-1), theta.clone().view(-1)
+        tp[cidx] += hc
+        tm[cidx] -= hc
+        check(f"cell {cidx}", (w.tau0, tp.view(theta.shape)), (w.tau0, tm.view(theta.shape)),
+              hc, float(g_th[cidx]))

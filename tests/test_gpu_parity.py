@@ -198,6 +198,22 @@ def _step_parity(P, steps=1, tol=1e-10, theta=None):
     return u, p, ug, pg
 
 
+def test_stable_dt_matches(s32):
+    """The stability-rule time step (Sec. II.C.1) equals the oracle's bit for bit, with and
+    without a yield-stress field and a body force; a step reports the rule for its input."""
+    P = s32
+    u = I.initial_velocity(P.w) + 0.3 * I.random_field((3,) + P.og.shape, seed=6)
+    theta = I.yield_field(P.w, seed=1)
+    for th, f, c in [(None, (0.0, 0.0, 0.0), 0.5), (theta, (1.0, -2.0, 0.5), 0.9)]:
+        ref = P.og.stable_dt(u, P.orheo, force=f, c_cfl=c, theta=th)
+        got = P.api.eb_stable_dt(P.ctx, P.rheo, P.dev(u), force=f, c_cfl=c,
+                                 theta=None if th is None else P.dev(th))
+        assert got == ref, (got, ref)
+    ud = P.dev(u)
+    _, _, st = P.api.eb_rk2_step(P.ctx, P.rheo, P.w.dt, P.opts, ud, P.ctx.scalar())
+    assert st["dt_stable"] == P.api.eb_stable_dt(P.ctx, P.rheo, ud, force=tuple(P.opts.force))
+
+
 def test_rk2_step_sphere32(s32):
     P = s32
     u, p, ug, pg = _step_parity(P, steps=1)
