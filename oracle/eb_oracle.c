@@ -1198,10 +1198,8 @@ static void build_operator(or_geom* g, int sys, double beta, double rho, double 
         if (sys == SYS_VISC && g->alpha[c] > 0.0) {
             s = g->alpha[c] * rho;
             long cid = g->cutid[c];
-            if (cid >= 0) {
-                double del = g->delta[cid] > 0.5 ? g->delta[cid] : 0.5;
-                s += dt * g->aeb[cid] * eta_eb[cid] / (del * h * h);
-            }
+            if (cid >= 0)  /* the wall flux of a linear profile seen two cells from the wall */
+                s += dt * g->aeb[cid] * eta_eb[cid] / (2.0 * h * h);
         }
         L0->S[c] = s;
     }

@@ -205,6 +205,9 @@ def test_rk2_step_adjoint_fd(sph):
     v, q, dth = _rnd(s, (3,) + g.shape, 25), _rnd(s, g.shape, 26), _rnd(s, g.shape, 27)
     e = 1e-7
     assert _rel((L(u0 + e * v, p0, th) - L(u0 - e * v, p0, th)) / (2 * e), (ui * v).sum()) < 1e-6
+    # p enters the predictor linearly and the step only through u* otherwise, so the response
+    # to p is nearly linear: a larger step keeps the solvers' tolerance out of the difference
+    e = 1e-5
     assert _rel((L(u0, p0 + e * q, th) - L(u0, p0 - e * q, th)) / (2 * e), (pi * q).sum()) < 1e-6
     e = 1e-6
     assert _rel((L(u0, p0, th + e * dth) - L(u0, p0, th - e * dth)) / (2 * e),
@@ -226,8 +229,11 @@ def test_drag_adjoint_fd(sph):
     e = 1e-6
     assert _rel((D(u + e * v, p, th) - D(u - e * v, p, th)) / (2 * e), (ub * v).sum()) < 1e-6
     assert _rel((D(u, p + e * q, th) - D(u, p - e * q, th)) / (2 * e), (pb * q).sum()) < 1e-6
+    # the yield stress moves the drag by ~1e-3 of its size per unit theta: a 1e-6 step would
+    # sit at the rounding floor eps |D| / (e |g|) ~ 1e-5, a 1e-3 step at ~1e-8
+    e = 1e-3
     assert _rel((D(u, p, th + e * dth) - D(u, p, th - e * dth)) / (2 * e),
-                (tb * rh.tau0 * dth).sum()) < 1e-5
+                (tb * rh.tau0 * dth).sum()) < 1e-6
 
 
 def test_rollout_bingham_number_gradient_fd(oracle_lib, sph):
