@@ -697,8 +697,9 @@ struct TailArgs {
     double* x0;        // iterate of the first tail level (global, written back)
     const int* gate;
     const double* b0;  // right-hand side of the first tail level (global)
-    // LDS byte offsets per level: x, b, K[3], D, mask
+    // LDS byte offsets per level: x, b, K[3], D, mask; and the first level's residual
     unsigned ox[TAIL_MAXL], ob[TAIL_MAXL], oK[TAIL_MAXL][3], oD[TAIL_MAXL], om[TAIL_MAXL];
+    unsigned orr;
 };
 
 // residual b - M x at fine cell f (0 outside the open cells)
@@ -890,6 +891,92 @@ __device__ __forceinline__ void wave_levels(const LevelV<double>* Lw, int nw, in
         for (int m = 0; m < NC; m++) x0[m * Lw[0].N + lane] = xs[0][m];
 }
 
+// ---- a block level of at most two cells per thread (thread t owns cells 2t and 2t + 1, one of
+// ---- each colour since nx is even): the rows (face coefficients with their neighbours, the
+// ---- diagonal) are built once per V-cycle into registers, so a half sweep costs its LDS reads
+struct BlockRow {
+    double K[6];
+    int nb[6];  // neighbour cell, or the cell itself where the face has no coupling (K = 0)
+    double D;
+    int c;      // the cell, -1 if the thread has none
+    bool upd;   // open with a positive diagonal (updated by the smoother)
+    bool open;
+};
+
+__device__ __forceinline__ void block_row(const LevelV<double>& L, long c, BlockRow& r) {
+    r.c = c < L.N ? (int)c : -1;
+    r.open = r.c >= 0 && L.mask[c] != 0;
+    r.D = r.c >= 0 ? L.D[c] : 0.0;
+    r.upd = r.open && r.D > 0.0;
+    int i = 0, j = 0, k = 0;
+    if (r.c >= 0) cell_coords(L.grid, c, i, j, k);
+#pragma unroll
+    for (int d = 0; d < 3; d++)
+#pragma unroll
+        for (int side = 0; side < 2; side++) {
+            double K = 0.0;
+            long nb = -1;
+            if (r.c >= 0) {
+                int f[3] = {i, j, k};
+                f[d] += side;
+                K = L.K[d][face_index(L.grid, d, f[0], f[1], f[2])];
+                int q[3] = {i, j, k};
+                q[d] += side ? 1 : -1;
+                nb = cell_at(L.grid, q[0], q[1], q[2]);
+            }
+            bool use = K != 0.0 && nb >= 0;
+            r.K[2 * d + side] = use ? K : 0.0;
+            r.nb[2 * d + side] = use ? (int)nb : (r.c >= 0 ? r.c : 0);
+        }
+}
+
+// sum_f K_f x_nb(f) in the face order of offdiag (absent couplings add exactly zero)
+template <int NC>
+__device__ __forceinline__ void block_offdiag(const BlockRow& r, const double* x, long N,
+                                              double acc[NC]) {
+#pragma unroll
+    for (int f = 0; f < 6; f++)
+#pragma unroll
+        for (int m = 0; m < NC; m++) acc[m] += r.K[f] * x[m * N + r.nb[f]];
+}
+
+template <int NC>
+__device__ __forceinline__ void block_update(const BlockRow& r, const double* b, double* x,
+                                             long N) {
+    if (!r.upd) return;
+    double acc[NC];
+#pragma unroll
+    for (int m = 0; m < NC; m++) acc[m] = b[m * N + r.c];
+    block_offdiag<NC>(r, x, N, acc);
+#pragma unroll
+    for (int m = 0; m < NC; m++) x[m * N + r.c] = acc[m] / r.D;
+}
+
+// one half sweep of colour col: the thread's cell of that colour
+template <int NC>
+__device__ __forceinline__ void block_sweep(const BlockRow& r0, const BlockRow& r1, int col0,
+                                            const double* b, double* x, long N, int col) {
+    block_update<NC>(col0 == col ? r0 : r1, b, x, N);
+    __syncthreads();
+}
+
+template <int NC>
+__device__ __forceinline__ void block_resid(const BlockRow& r, const double* b, const double* x,
+                                            long N, double* res) {
+    if (r.c < 0) return;
+    if (!r.open) {
+#pragma unroll
+        for (int m = 0; m < NC; m++) res[m * N + r.c] = 0.0;
+        return;
+    }
+    double acc[NC];
+#pragma unroll
+    for (int m = 0; m < NC; m++) acc[m] = 0.0;
+    block_offdiag<NC>(r, x, N, acc);
+#pragma unroll
+    for (int m = 0; m < NC; m++) res[m * N + r.c] = b[m * N + r.c] - (r.D * x[m * N + r.c] - acc[m]);
+}
+
 template <int NC>
 __global__ void __launch_bounds__(TAIL_THREADS) k_vcycle_tail(TailArgs A) {
     if (A.gate && *A.gate) return;
@@ -929,6 +1016,76 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_vcycle_tail(TailArgs A) {
     // first level small enough for one wavefront (all coarser ones are smaller)
     int w0 = nl;
     while (w0 > 0 && A.L[w0 - 1].N <= 64 && nl - (w0 - 1) <= WAVE_MAXL) w0--;
+    if (w0 == 1 && nl > 1 && A.L[0].N <= 2 * (long)blockDim.x && (A.L[0].grid.n[0] & 1) == 0) {
+        // one block level above the in-wave levels, its rows in registers
+        LevelV<double> L = lv(0);
+        LevelV<double> C = lv(1);
+        long N = L.N;
+        double* x = X(0);
+        double* b = B(0);
+        BlockRow r0, r1;
+        block_row(L, 2 * (long)threadIdx.x, r0);
+        block_row(L, 2 * (long)threadIdx.x + 1, r1);
+        int col0 = 0;
+        if (r0.c >= 0) {
+            int i, j, k;
+            cell_coords(L.grid, r0.c, i, j, k);
+            col0 = (i + j + k) & 1;
+        }
+        for (long t = threadIdx.x; t < NC * N; t += blockDim.x) x[t] = 0.0;
+        __syncthreads();
+        for (int s = 0; s < A.nu1; s++) {
+            block_sweep<NC>(r0, r1, col0, b, x, N, 0);
+            block_sweep<NC>(r0, r1, col0, b, x, N, 1);
+        }
+        // residuals of both cells, then the coarse right-hand side as the mean of the eight
+        // children in the order q = 0..7
+        double* res = reinterpret_cast<double*>(lds + A.orr);
+        block_resid<NC>(r0, b, x, N, res);
+        block_resid<NC>(r1, b, x, N, res);
+        __syncthreads();
+        double* bc = B(1);
+        for (long c = threadIdx.x; c < C.N; c += blockDim.x) {
+            int i, j, k;
+            cell_coords(C.grid, c, i, j, k);
+            double sm[NC];
+#pragma unroll
+            for (int m = 0; m < NC; m++) sm[m] = 0.0;
+            for (int q = 0; q < 8; q++) {
+                long f = cell_index(L.grid, 2 * i + (q & 1), 2 * j + ((q >> 1) & 1),
+                                    2 * k + (q >> 2));
+#pragma unroll
+                for (int m = 0; m < NC; m++) sm[m] += res[m * N + f];
+            }
+#pragma unroll
+            for (int m = 0; m < NC; m++) bc[m * C.N + c] = C.mask[c] ? sm[m] / 8.0 : 0.0;
+        }
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            LevelV<double> Lw[WAVE_MAXL];
+            for (int v = 0; v < WAVE_MAXL; v++) Lw[v] = lv(1 + (1 + v < nl ? v : 0));
+            wave_levels<NC>(Lw, nl - 1, A.nu1, A.nu2, A.nbottom, B(1), X(1));
+        }
+        __syncthreads();
+        // prolongation of the coarse correction to the thread's open cells
+        const double* xc = X(1);
+        for (int h = 0; h < 2; h++) {
+            const BlockRow& r = h ? r1 : r0;
+            if (r.c < 0 || !r.open) continue;
+            int i, j, k;
+            cell_coords(L.grid, r.c, i, j, k);
+            long pc = cell_index(C.grid, i >> 1, j >> 1, k >> 1);
+#pragma unroll
+            for (int m = 0; m < NC; m++) x[m * N + r.c] += xc[m * C.N + pc];
+        }
+        __syncthreads();
+        for (int s = 0; s < A.nu2; s++) {
+            block_sweep<NC>(r0, r1, col0, b, x, N, 1);
+            block_sweep<NC>(r0, r1, col0, b, x, N, 0);
+        }
+        for (long t = threadIdx.x; t < NC * N; t += blockDim.x) A.x0[t] = x[t];
+        return;
+    }
     for (int l = 0; l < w0; l++) {
         LevelV<double> L = lv(l);
         double* x = X(l);
@@ -1011,12 +1168,14 @@ size_t tail_layout(const Level* lev, int nlev, int t, int nc, TailArgs* A) {
         unsigned oK[3];
         for (int d = 0; d < 3; d++) oK[d] = take(face_count(L.grid, d) * 8);
         unsigned oD = take(L.N * 8), om = take(L.N);
+        unsigned orr = q == 0 ? take(nc * L.N * 8) : 0;
         if (A) {
             A->ox[q] = ox;
             A->ob[q] = ob;
             for (int d = 0; d < 3; d++) A->oK[q][d] = oK[d];
             A->oD[q] = oD;
             A->om[q] = om;
+            if (q == 0) A->orr = orr;
         }
     }
     return off;
@@ -1367,6 +1526,8 @@ template <>
 LevelV<double> level_view<double>(const Level& L) { return L.v64(); }
 template <>
 LevelV<float> level_view<float>(const Level& L) { return L.v32(); }
+
+
 
 template <typename T>
 void first_pass(const Level& L, int nc, const T* b, T* x, hipStream_t s) {
