@@ -1598,8 +1598,14 @@ struct VArgs {
     bool tail_fits;  // the tail levels fit the LDS budget (else per-level kernels)
 };
 
-// levels above the tail run in FP32 in mixed mode; the tail (and so the coarsest solve) is FP64
-bool level_f32(const VArgs& a, int l) { return a.mixed && l < a.tail; }
+// In mixed mode the levels whose sweeps move enough bytes to be bandwidth-bound run in FP32;
+// below that size a sweep costs its launch and latency whatever the precision, and FP64 keeps the
+// preconditioner closer to the FP64 one (fewer Krylov iterations).  The tail (and so the
+// coarsest solve) is always FP64.
+constexpr long F32_MIN_CELLS = 1L << 18;  // 64^3
+bool level_f32(const VArgs& a, int l) {
+    return a.mixed && l < a.tail && a.lev[l].N >= F32_MIN_CELLS;
+}
 
 void launch_tail(const VArgs& a) {
     TailArgs T;
@@ -1754,7 +1760,7 @@ void finish_operator(Level* lev, int nlev, bool mixed, hipStream_t s) {
         Level& L = lev[l];
         k_diag<<<grid_for(L.N), EB_BLOCK, 0, s>>>(L.grid, L.K[0], L.K[1], L.K[2], L.S, L.mask,
                                                   L.D);
-        if (mixed && l < tail) {
+        if (mixed && l < tail && L.N >= F32_MIN_CELLS) {
             for (int d = 0; d < 3; d++) {
                 long nf = face_count(L.grid, d);
                 k_to_float<<<grid_for(nf), EB_BLOCK, 0, s>>>(nf, L.K[d], L.Kf[d]);
