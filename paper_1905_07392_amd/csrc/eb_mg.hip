@@ -445,29 +445,70 @@ __device__ __forceinline__ void rb_cell(const GridV& g, unsigned t, int col, int
     i = 2 * (int)ih + ((j + k + col) & 1);
 }
 
+// Every load of a cell (flag, right-hand side, the other colour's six neighbours, the seven
+// viscosities of a regular cell) is issued before the first one is needed, so a thread waits for
+// memory once; the row and the update are then rb0_row's and the order of the sums is unchanged.
 template <typename T, int NC>
-__global__ void k_smooth_rb(Rb0V L, const T* __restrict__ b, T* __restrict__ x, int col) {
+__global__ void __launch_bounds__(EB_BLOCK)
+    k_smooth_rb(Rb0V L, const T* __restrict__ b, T* __restrict__ x, int col) {
     if (L.gate && *L.gate) return;
     long N = L.N, Nh = N >> 1;
     long t = xcd_block() * (long)blockDim.x + threadIdx.x;
     if (t >= Nh) return;
     int i, j, k;
     rb_cell(L.grid, (unsigned)t, col, i, j, k);
-    long c = cell_index(L.grid, i, j, k);
-    T K[6], dg;
-    long nb[6];
-    if (!rb0_row<T>(L, c, i, j, k, K, nb, dg)) return;
+    const GridV& g = L.grid;
+    long c = cell_index(g, i, j, k);
     long own = (long)col * Nh + t, oth = (long)(1 - col) * Nh;
-    T acc[NC];
+    long nb[6];
+#pragma unroll
+    for (int d = 0; d < 3; d++)
+#pragma unroll
+        for (int side = 0; side < 2; side++) {
+            int q[3] = {i, j, k};
+            q[d] += side ? 1 : -1;
+            nb[2 * d + side] = cell_at(g, q[0], q[1], q[2]);
+        }
+    uint8_t fl = L.flag[c];
+    T acc[NC], xn[6][NC];
 #pragma unroll
     for (int m = 0; m < NC; m++) acc[m] = b[m * N + own];
+#pragma unroll
+    for (int f = 0; f < 6; f++)
+#pragma unroll
+        for (int m = 0; m < NC; m++)
+            xn[f][m] = nb[f] >= 0 ? x[m * N + oth + (nb[f] >> 1)] : (T)0;
+    const T* eta = eta_of<T>(L);
+    bool visc = L.sys == EB_SYS_VISC;
+    T ec = visc ? eta[c] : (T)0, en[6];
+#pragma unroll
+    for (int f = 0; f < 6; f++) en[f] = (visc && nb[f] >= 0) ? eta[nb[f]] : (T)0;
+    if (fl == 0) return;
+    T K[6], dg;
+    if (fl == 2) {
+        // rb0_row's regular row from the loaded viscosities
+        T kin = (T)L.kin, kwall = (T)L.kwall, kp = (T)L.kpois;
+        T s = visc ? (T)L.rho : (T)0;
+#pragma unroll
+        for (int f = 0; f < 6; f++) {
+            T kf;
+            if (visc) kf = nb[f] >= 0 ? kin * (ec + en[f]) : kwall * ec;
+            else kf = nb[f] >= 0 ? kp : (T)0;
+            s += kf;
+            K[f] = kf;
+        }
+        dg = s;
+        if (!(dg > (T)0)) return;
+    } else {
+        long nb2[6];
+        if (!rb0_row<T>(L, c, i, j, k, K, nb2, dg)) return;
+    }
 #pragma unroll
     for (int f = 0; f < 6; f++) {
         T kf = K[f];
         if (kf == (T)0 || nb[f] < 0) continue;
-        long q = oth + (nb[f] >> 1);
 #pragma unroll
-        for (int m = 0; m < NC; m++) acc[m] += kf * x[m * N + q];
+        for (int m = 0; m < NC; m++) acc[m] += kf * xn[f][m];
     }
     T inv = (T)1 / dg;
 #pragma unroll
