@@ -57,9 +57,11 @@ enum { EB_BODY_NONE = 0, EB_BODY_SPHERE = 1, EB_BODY_ELLIPSOID = 2, EB_BODY_ZSLA
 enum { EB_LAW_NEWTONIAN = 0, EB_LAW_BINGHAM_REG = 1, EB_LAW_PAPANASTASIOU = 2 };
 
 /* Precision of the multigrid preconditioner.  EB_MIXED smooths, restricts and prolongates in
- * FP32 on every level above the in-wave tail; the Krylov iteration, its residual with the full
- * EB operator, the tail levels with the coarsest solve, the wall stencils and the divergence
- * checks stay FP64, so the result meets the same FP64 residual target.  A mixed solve whose
+ * FP32 on the levels of at least 64^3 cells (those whose sweeps are bound by memory traffic;
+ * smaller levels cost their launch latency whatever the precision and stay FP64); the Krylov
+ * iteration, its residual with the full EB operator, the coarse levels with the coarsest solve,
+ * the wall stencils and the divergence checks stay FP64, so the result meets the same FP64
+ * residual target.  A mixed solve whose
  * residual has not fallen tenfold within 6 iterations, or that has not converged within
  * max(20, max_iter/10), has an operator too ill-conditioned for an FP32 V-cycle (e.g. a
  * viscosity contrast of 1e6 between a plug and a sheared layer); it is then solved again from
@@ -207,7 +209,7 @@ int eb_mg_vcycle(eb_ctx* ctx, int system, int precision, double beta, double rho
  * c = (i,j,k) sits at ((i+j+k) mod 2) * N/2 + c/2.  Regular cells recompute their coefficients
  * from the viscosity array the operator was built from, which must still be valid.  The
  * multigrid smoother in isolation, for timing and tests; EB_EINVAL if no operator of that kind
- * has been built. */
+ * has been built, or for EB_MIXED if the finest level runs in FP64 (fewer than 64^3 cells). */
 int eb_mg_sweep(eb_ctx* ctx, int system, int precision, int colour, const void* b, void* x,
                 void* stream);
 

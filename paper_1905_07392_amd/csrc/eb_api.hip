@@ -601,16 +601,12 @@ int pcg(eb_ctx* c, const double* b, double* x, const SolveCfg& k, int slot) {
         const double* A[4] = {pd, nullptr, nullptr, nullptr};
         const double* B[4] = {q, nullptr, nullptr, nullptr};
         mg_apply_level0(c->lev[0], 1, pd, q, c->s, st);
-        red_dots(N, 1, A, B, c->part, ks + KS_PQ, c->s, st);
-        ks_op(KS_CG_ALPHA, ks, st, itc, c->s);
-        ks_cg_xr(N, x, r, pd, q, ks, st, c->s);
-        red_maxabs(N, 1, r, c->part, ks + KS_RN, c->s, st);
-        ks_op(KS_CHECK_R, ks, st, itc, c->s);
+        red_dots_op(N, 1, A, B, c->part, KS_PQ, KS_CG_ALPHA, ks, st, itc, c->s);
+        ks_cg_xr_op(N, x, r, pd, q, c->part, ks, st, itc, c->s);
         vcyc(c, 1, k, r, z, st);
         A[0] = r;
         B[0] = z;
-        red_dots(N, 1, A, B, c->part, ks + KS_RZN, c->s, st);
-        ks_op(KS_CG_BETA, ks, st, itc, c->s);
+        red_dots_op(N, 1, A, B, c->part, KS_RZN, KS_CG_BETA, ks, st, itc, c->s);
         ks_cg_p(N, pd, z, ks, st, c->s);
     };
     return iterate(c, key, slot, k.max_iter, body, k.mixed);
@@ -758,29 +754,20 @@ int bicgstab(eb_ctx* c, double rho, double dt, const double* eta, const double* 
     key.v[0] = rho;
     key.v[1] = dt;
     auto body = [&]() {
-        ks_op(KS_BI_BETA, ks, st, itc, c->s);
         ks_bi_p(N3, p, r, v, ks, st, c->s);
         vcyc(c, 3, k, p, ph, st);
         apply(ph, v, st);
         const double* Av[4] = {rh, nullptr, nullptr, nullptr};
         const double* Bv[4] = {v, nullptr, nullptr, nullptr};
-        red_dots(N3, 1, Av, Bv, c->part, ks + KS_RV, c->s, st);
-        ks_op(KS_BI_ALPHA, ks, st, itc, c->s);
-        ks_bi_s(N3, sv, r, v, ks, st, c->s);
-        red_maxabs(N3, 1, sv, c->part, ks + KS_SN, c->s, st);
-        ks_op(KS_BI_CHECK_S, ks, st, itc, c->s);
+        red_dots_op(N3, 1, Av, Bv, c->part, KS_RV, KS_BI_ALPHA, ks, st, itc, c->s);
+        ks_bi_s_op(N3, sv, r, v, c->part, ks, st, itc, c->s);
         ks_bi_xs(N3, x, ph, ks, st, c->s);
-        ks_op(KS_BI_FINISH_S, ks, st, itc, c->s);
         vcyc(c, 3, k, sv, sh, st);
         apply(sh, t, st);
         const double* A2[4] = {t, t, nullptr, nullptr};
         const double* B2[4] = {sv, t, nullptr, nullptr};
-        red_dots(N3, 2, A2, B2, c->part, ks + KS_TS, c->s, st);
-        ks_op(KS_BI_OMEGA, ks, st, itc, c->s);
-        ks_bi_xr(N3, x, r, ph, sh, sv, t, ks, st, c->s);
-        red_dots(N3, 1, A1, B1, c->part, ks + KS_RRN, c->s, st);
-        red_maxabs(N3, 1, r, c->part, ks + KS_RN, c->s, st);
-        ks_op(KS_BI_CHECK_R, ks, st, itc, c->s);
+        red_dots_op(N3, 2, A2, B2, c->part, KS_TS, KS_BI_OMEGA, ks, st, itc, c->s);
+        ks_bi_xr_op(N3, x, r, ph, sh, sv, t, rh, c->part, ks, st, itc, c->s);
     };
     return iterate(c, key, slot, k.max_iter, body, k.mixed);
 }
@@ -1167,8 +1154,8 @@ int eb_mg_sweep(eb_ctx* c, int system, int precision, int colour, const void* b,
     if (c->built_sys != system || c->built_mixed != f32)
         return set_err(EB_EINVAL, "no operator for system %d precision %d is built", system,
                        precision);
-    if (f32 && mg_tail_level(c->lev, c->nlev) == 0)
-        return set_err(EB_EINVAL, "this hierarchy runs entirely in FP64");
+    if (f32 && !mg_level0_f32(c->lev, c->nlev))
+        return set_err(EB_EINVAL, "the finest level of this hierarchy runs in FP64");
     mg_sweep_level0(c->lev[0], system == EB_SYS_VISC ? 3 : 1, f32, b, x, colour & 1,
                     (hipStream_t)stream);
     return hip_check("eb_mg_sweep");

@@ -223,23 +223,91 @@ enum {
     KS_RZN, KS_PQ, KS_RR, KS_RV, KS_TS, KS_TT, KS_SUM, KS_CNT, KS_RRN, KS_COUNT = 24
 };
 enum {
-    KS_INIT, KS_CG_ALPHA, KS_CHECK_R, KS_CG_BETA, KS_BI_BETA, KS_BI_ALPHA, KS_BI_CHECK_S,
-    KS_BI_FINISH_S, KS_BI_OMEGA, KS_BI_CHECK_R
+    KS_INIT, KS_CG_ALPHA, KS_CHECK_R, KS_CG_BETA, KS_BI_ALPHA, KS_BI_CHECK_S, KS_BI_OMEGA,
+    KS_BI_CHECK_R
 };
+// One Krylov scalar update, run by a single thread: op on the scalars ks of the solve whose
+// state word and count are st[0], st[1] and whose device iteration counter is *itc.  The state
+// is 0 while the solve runs, 1 when it converged at BiCGSTAB's half step (x update pending), 2
+// converged, 3 non-finite residual; once it leaves 0 the ops do nothing more.
+__device__ inline void ks_scalar_op(int op, double* __restrict__ ks, int* __restrict__ st,
+                                    int* __restrict__ itc) {
+    int s = *st;
+    // the first scalar op of each iteration advances the count while the solve runs
+    if (s == 0 && (op == KS_CG_ALPHA || op == KS_BI_ALPHA)) *itc += 1;
+    int it = *itc;
+    switch (op) {
+    case KS_INIT: {  // tol = rtol * max(bn, scale); converged already if rn <= tol
+        double bn = ks[KS_BN] > ks[KS_SCALE] ? ks[KS_BN] : ks[KS_SCALE];
+        ks[KS_TOL] = ks[KS_RTOL] * bn;
+        st[1] = 0;
+        *itc = 0;
+        if (!isfinite(ks[KS_RN])) *st = 3;
+        else if (bn == 0.0 || ks[KS_RN] <= ks[KS_TOL]) *st = 2;
+        else *st = 0;
+        ks[KS_RHO_OLD] = 1.0;
+        ks[KS_AL] = 1.0;
+        ks[KS_OM] = 1.0;
+        break;
+    }
+    case KS_CG_ALPHA:
+        if (s == 0) ks[KS_AL] = ks[KS_RZ] / ks[KS_PQ];
+        break;
+    case KS_CHECK_R:  // after the x, r update (CG)
+        if (s == 0) {
+            if (!isfinite(ks[KS_RN])) *st = 3;
+            else if (ks[KS_RN] <= ks[KS_TOL]) {
+                *st = 2;
+                st[1] = it;
+            }
+        }
+        break;
+    case KS_CG_BETA:
+        if (s == 0) {
+            ks[KS_BE] = ks[KS_RZN] / ks[KS_RZ];
+            ks[KS_RZ] = ks[KS_RZN];
+        }
+        break;
+    case KS_BI_ALPHA:
+        if (s == 0) ks[KS_AL] = ks[KS_RR] / ks[KS_RV];
+        break;
+    case KS_BI_CHECK_S:  // the count is in half iterations (= preconditioner applications)
+        if (s == 0) {
+            if (!isfinite(ks[KS_SN])) *st = 3;
+            else if (ks[KS_SN] <= ks[KS_TOL]) {
+                *st = 1;
+                st[1] = 2 * it - 1;
+            }
+        }
+        break;
+    case KS_BI_CHECK_R:
+        if (s == 0) {
+            ks[KS_RHO_OLD] = ks[KS_RR];
+            ks[KS_RR] = ks[KS_RRN];
+            if (!isfinite(ks[KS_RN])) *st = 3;
+            else if (ks[KS_RN] <= ks[KS_TOL]) {
+                *st = 2;
+                st[1] = 2 * it;
+            }
+        }
+        break;
+    case KS_BI_OMEGA:  // also completes a convergence at the half step, whose x update is done
+        if (s == 0) ks[KS_OM] = ks[KS_TS] / ks[KS_TT];
+        else if (s == 1) *st = 2;
+        break;
+    default:
+        break;
+    }
+}
+
 // st: the solve's (state, count) pair; itc: its device iteration counter
 void ks_op(int op, double* ks, int* st, int* itc, hipStream_t s);
 void ks_set(double* ks, int idx, double v, hipStream_t s);
-void ks_cg_xr(long n, double* x, double* r, const double* p, const double* q, const double* ks,
-              const int* st, hipStream_t s);
 void ks_cg_p(long n, double* p, const double* z, const double* ks, const int* st, hipStream_t s);
 void ks_bi_p(long n, double* p, const double* r, const double* v, const double* ks,
              const int* st, hipStream_t s);
-void ks_bi_s(long n, double* sv, const double* r, const double* v, const double* ks,
-             const int* st, hipStream_t s);
 void ks_bi_xs(long n, double* x, const double* ph, const double* ks, const int* st,
               hipStream_t s);
-void ks_bi_xr(long n, double* x, double* r, const double* ph, const double* sh, const double* sv,
-              const double* t, const double* ks, const int* st, hipStream_t s);
 
 // multigrid and Krylov
 void mg_build_poisson(Level* lev, int nlev, const GeomV& g, double beta, bool mixed,
@@ -250,13 +318,30 @@ void mg_vcycle(Level* lev, int nlev, int ncomp, bool mixed, const double* b, dou
                int nu1, int nu2, int nbottom, hipStream_t s, const int* gate = nullptr);
 void mg_apply_level0(const Level& L, int ncomp, const double* x, double* y, hipStream_t s,
                      const int* gate = nullptr);
-// first multigrid level run by the one-work-group tail (FP32 copies exist only above it)
-int mg_tail_level(const Level* lev, int nlev);
+// whether a mixed-precision hierarchy runs its finest level in FP32 (levels of at least 64^3
+// cells above the one-work-group tail do)
+bool mg_level0_f32(const Level* lev, int nlev);
 void mg_sweep_level0(const Level& L, int ncomp, bool f32, const void* b, void* x, int colour,
                      hipStream_t s);
 void op_visc_apply(const GeomV& g, double rho, double dt, const double* eta,
                    const double* eta_eb, const double* u, double* out, int homogeneous,
                    hipStream_t s, const int* gate = nullptr);
+
+// Krylov steps fused with their reductions and the scalar update that follows (results bit for
+// bit those of the separate calls): red_dots_op reduces into ks[out_idx + p] then runs op;
+// ks_bi_s_op is s = r - alpha v, max |s| -> KS_SN, KS_BI_CHECK_S; ks_bi_xr_op is the x and r
+// update with rh . r -> KS_RRN, max |r| -> KS_RN, KS_BI_CHECK_R; ks_cg_xr_op is CG's x and r
+// update with max |r| -> KS_RN, KS_CHECK_R
+void red_dots_op(long n, int np, const double* const a[4], const double* const b[4],
+                 double* part, int out_idx, int op, double* ks, int* st, int* itc,
+                 hipStream_t s);
+void ks_bi_s_op(long n, double* sv, const double* r, const double* v, double* part, double* ks,
+                int* st, int* itc, hipStream_t s);
+void ks_bi_xr_op(long n, double* x, double* r, const double* ph, const double* sh,
+                 const double* sv, const double* t, const double* rh, double* part, double* ks,
+                 int* st, int* itc, hipStream_t s);
+void ks_cg_xr_op(long n, double* x, double* r, const double* p, const double* q, double* part,
+                 double* ks, int* st, int* itc, hipStream_t s);
 
 // reductions: per-block partials (part, >= 4*1024 doubles) then one fixed-order final pass
 // into out (device)

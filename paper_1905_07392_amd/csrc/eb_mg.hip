@@ -148,11 +148,38 @@ __device__ __forceinline__ void offdiag(const LevelV<T>& L, const T* __restrict_
     }
 }
 
+// Prolongation carried by the first post-smoothing sweeps instead of a pass of its own: the
+// coarse correction ec (on grid gc) is added on the fly where the separate pass would have
+// stored it.  PRO_NBR: to every neighbour's value read by the update (the other colour, whose
+// correction is still pending) and to the cell's own value where the cell is open but its row
+// is degenerate (it is not updated); PRO_OWN: only the latter.  The Gauss-Seidel update itself
+// does not read the cell's own value, so an updated cell needs no correction, and the sums are
+// bit for bit those of the separate prolongation (the same addition, in the same precision).
+enum { PRO_NONE = 0, PRO_OWN = 1, PRO_NBR = 2 };
+template <typename TC>
+struct ProV {
+    GridV gc;
+    const TC* ec;
+};
+
+// coarse cell under the neighbour across face f = 2d + side of fine cell (i, j, k), which
+// exists: its coordinates wrapped as cell_at wraps them, then halved
+__device__ __forceinline__ long nb_parent(const GridV& gf, const GridV& gc, int i, int j, int k,
+                                          int f) {
+    int q[3] = {i, j, k};
+    int d = f >> 1;
+    q[d] += (f & 1) ? 1 : -1;
+    if (q[d] < 0) q[d] += gf.n[d];
+    else if (q[d] >= gf.n[d]) q[d] -= gf.n[d];
+    return cell_index(gc, q[0] >> 1, q[1] >> 1, q[2] >> 1);
+}
+
 // one Gauss-Seidel update of the t-th cell of colour col (cells of a colour are numbered row by
-// row, nx/2 per row)
-template <typename T, int NC>
+// row, nx/2 per row), with the prolongation PRO fused in
+template <typename T, int NC, int PRO = PRO_NONE, typename TC = T>
 __device__ __forceinline__ void smooth_cell(const LevelV<T>& L, const T* __restrict__ b,
-                                            T* __restrict__ x, long t, int col) {
+                                            T* __restrict__ x, long t, int col,
+                                            const ProV<TC>* P = nullptr) {
     const GridV& g = L.grid;
     unsigned nxh = (unsigned)g.n[0] >> 1, ny = (unsigned)g.n[1];
     unsigned row = (unsigned)t / nxh;
@@ -162,13 +189,61 @@ __device__ __forceinline__ void smooth_cell(const LevelV<T>& L, const T* __restr
     int k = (int)kk;
     int i = 2 * ih + ((j + k + col) & 1);
     long c = cell_index(g, i, j, k);
-    if (!L.mask[c]) return;
+    // every load before the first use (offdiag's terms, in its order)
+    long nb[6];
+    T K[6], xn[6][NC], acc[NC];
+#pragma unroll
+    for (int d = 0; d < 3; d++)
+#pragma unroll
+        for (int side = 0; side < 2; side++) {
+            int f[3] = {i, j, k};
+            f[d] += side;
+            K[2 * d + side] = L.K[d][face_index(g, d, f[0], f[1], f[2])];
+            int q[3] = {i, j, k};
+            q[d] += side ? 1 : -1;
+            nb[2 * d + side] = cell_at(g, q[0], q[1], q[2]);
+        }
+    uint8_t msk = L.mask[c];
     T dg = L.D[c];
-    if (!(dg > (T)0)) return;
-    T acc[NC];
 #pragma unroll
     for (int m = 0; m < NC; m++) acc[m] = b[m * L.N + c];
-    offdiag<T, NC>(L, x, i, j, k, acc);
+#pragma unroll
+    for (int f = 0; f < 6; f++)
+#pragma unroll
+        for (int m = 0; m < NC; m++) xn[f][m] = nb[f] >= 0 ? x[m * L.N + nb[f]] : (T)0;
+    long Nc = 0;
+    if (PRO != PRO_NONE) Nc = (long)P->gc.n[0] * P->gc.n[1] * P->gc.n[2];
+    T pe[6][NC];
+    if (PRO == PRO_NBR) {
+#pragma unroll
+        for (int f = 0; f < 6; f++) {
+            bool on = nb[f] >= 0 && L.mask[nb[f] >= 0 ? nb[f] : 0];
+            long pc = on ? nb_parent(g, P->gc, i, j, k, f) : 0;
+#pragma unroll
+            for (int m = 0; m < NC; m++) pe[f][m] = on ? (T)P->ec[m * Nc + pc] : (T)0;
+        }
+    }
+    if (!msk) return;
+    if (!(dg > (T)0)) {
+        if (PRO != PRO_NONE) {
+            long pc = cell_index(P->gc, i >> 1, j >> 1, k >> 1);
+#pragma unroll
+            for (int m = 0; m < NC; m++) x[m * L.N + c] += (T)P->ec[m * Nc + pc];
+        }
+        return;
+    }
+    if (PRO == PRO_NBR) {
+#pragma unroll
+        for (int f = 0; f < 6; f++)
+#pragma unroll
+            for (int m = 0; m < NC; m++) xn[f][m] = xn[f][m] + pe[f][m];
+    }
+#pragma unroll
+    for (int f = 0; f < 6; f++) {
+        if (K[f] == (T)0 || nb[f] < 0) continue;
+#pragma unroll
+        for (int m = 0; m < NC; m++) acc[m] += K[f] * xn[f][m];
+    }
 #pragma unroll
     for (int m = 0; m < NC; m++) x[m * L.N + c] = acc[m] / dg;
 }
@@ -270,6 +345,7 @@ __device__ __forceinline__ int rr_thread(int cl, int q) {
     return ((q >> 2) * 2 + ((q >> 1) & 1)) * (2 * RR_COARSE) + cl * 2 + (q & 1);
 }
 
+
 template <typename TF, typename TC, int NC>
 __global__ void __launch_bounds__(RR_THREADS)
     k_resid_restrict(LevelV<TF> L, const TF* __restrict__ b, const TF* __restrict__ x, GridV gc,
@@ -288,14 +364,44 @@ __global__ void __launch_bounds__(RR_THREADS)
         cell_coords(gc, c, i, j, k);
         int fi = 2 * i + a, fj = 2 * j + bq, fk = 2 * k + cq;
         long f = cell_index(L.grid, fi, fj, fk);
-        if (L.mask[f]) {
+        // every load before the first use (offdiag's terms, in its order)
+        const GridV& g = L.grid;
+        long nb[6];
+        TF K[6], xn[6][NC], bv[NC], xv[NC];
+#pragma unroll
+        for (int d = 0; d < 3; d++)
+#pragma unroll
+            for (int side = 0; side < 2; side++) {
+                int e[3] = {fi, fj, fk};
+                e[d] += side;
+                K[2 * d + side] = L.K[d][face_index(g, d, e[0], e[1], e[2])];
+                int q[3] = {fi, fj, fk};
+                q[d] += side ? 1 : -1;
+                nb[2 * d + side] = cell_at(g, q[0], q[1], q[2]);
+            }
+        uint8_t msk = L.mask[f];
+        TF dg = L.D[f];
+#pragma unroll
+        for (int m = 0; m < NC; m++) {
+            bv[m] = b[m * L.N + f];
+            xv[m] = x[m * L.N + f];
+        }
+#pragma unroll
+        for (int e = 0; e < 6; e++)
+#pragma unroll
+            for (int m = 0; m < NC; m++) xn[e][m] = nb[e] >= 0 ? x[m * L.N + nb[e]] : (TF)0;
+        if (msk) {
             TF acc[NC];
 #pragma unroll
             for (int m = 0; m < NC; m++) acc[m] = (TF)0;
-            offdiag<TF, NC>(L, x, fi, fj, fk, acc);
-            TF dg = L.D[f];
 #pragma unroll
-            for (int m = 0; m < NC; m++) r[m] = b[m * L.N + f] - (dg * x[m * L.N + f] - acc[m]);
+            for (int e = 0; e < 6; e++) {
+                if (K[e] == (TF)0 || nb[e] < 0) continue;
+#pragma unroll
+                for (int m = 0; m < NC; m++) acc[m] += K[e] * xn[e][m];
+            }
+#pragma unroll
+            for (int m = 0; m < NC; m++) r[m] = bv[m] - (dg * xv[m] - acc[m]);
         }
     }
 #pragma unroll
@@ -322,6 +428,15 @@ __global__ void k_smooth(LevelV<T> L, const T* __restrict__ b, T* __restrict__ x
     if (L.gate && *L.gate) return;
     long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (t < L.N / 2) smooth_cell<T, NC>(L, b, x, t, col);
+}
+
+// a half sweep with the prolongation of ec fused in (PRO_NBR or PRO_OWN)
+template <typename T, typename TC, int NC, int PRO>
+__global__ void k_smooth_pro(LevelV<T> L, const T* __restrict__ b, T* __restrict__ x, int col,
+                             ProV<TC> P) {
+    if (L.gate && *L.gate) return;
+    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t < L.N / 2) smooth_cell<T, NC, PRO, TC>(L, b, x, t, col, &P);
 }
 
 template <typename T, int NC>
@@ -448,19 +563,15 @@ __device__ __forceinline__ void rb_cell(const GridV& g, unsigned t, int col, int
 // Every load of a cell (flag, right-hand side, the other colour's six neighbours, the seven
 // viscosities of a regular cell) is issued before the first one is needed, so a thread waits for
 // memory once; the row and the update are then rb0_row's and the order of the sums is unchanged.
-template <typename T, int NC>
-__global__ void __launch_bounds__(EB_BLOCK)
-    k_smooth_rb(Rb0V L, const T* __restrict__ b, T* __restrict__ x, int col) {
-    if (L.gate && *L.gate) return;
-    long N = L.N, Nh = N >> 1;
-    long t = xcd_block() * (long)blockDim.x + threadIdx.x;
-    if (t >= Nh) return;
-    int i, j, k;
-    rb_cell(L.grid, (unsigned)t, col, i, j, k);
+// rb0_row with every load issued before the first is needed: the flag, the seven viscosities of
+// a regular cell and, with NBR, the NC values of the six neighbours from the other colour's half
+// xo (xn[f] = 0 where there is none).  The row is rb0_row's bit for bit.
+template <typename T, int NC, bool NBR>
+__device__ __forceinline__ bool rb0_row_ld(const Rb0V& L, long c, int i, int j, int k,
+                                           const T* __restrict__ xo, T K[6], long nb[6], T& D,
+                                           T xn[6][NC]) {
     const GridV& g = L.grid;
-    long c = cell_index(g, i, j, k);
-    long own = (long)col * Nh + t, oth = (long)(1 - col) * Nh;
-    long nb[6];
+    long N = L.N;
 #pragma unroll
     for (int d = 0; d < 3; d++)
 #pragma unroll
@@ -470,38 +581,77 @@ __global__ void __launch_bounds__(EB_BLOCK)
             nb[2 * d + side] = cell_at(g, q[0], q[1], q[2]);
         }
     uint8_t fl = L.flag[c];
-    T acc[NC], xn[6][NC];
+    if (NBR)
 #pragma unroll
-    for (int m = 0; m < NC; m++) acc[m] = b[m * N + own];
+        for (int f = 0; f < 6; f++)
 #pragma unroll
-    for (int f = 0; f < 6; f++)
-#pragma unroll
-        for (int m = 0; m < NC; m++)
-            xn[f][m] = nb[f] >= 0 ? x[m * N + oth + (nb[f] >> 1)] : (T)0;
+            for (int m = 0; m < NC; m++) xn[f][m] = nb[f] >= 0 ? xo[m * N + (nb[f] >> 1)] : (T)0;
     const T* eta = eta_of<T>(L);
     bool visc = L.sys == EB_SYS_VISC;
     T ec = visc ? eta[c] : (T)0, en[6];
 #pragma unroll
     for (int f = 0; f < 6; f++) en[f] = (visc && nb[f] >= 0) ? eta[nb[f]] : (T)0;
-    if (fl == 0) return;
-    T K[6], dg;
+    if (fl == 0) return false;
     if (fl == 2) {
-        // rb0_row's regular row from the loaded viscosities
         T kin = (T)L.kin, kwall = (T)L.kwall, kp = (T)L.kpois;
-        T s = visc ? (T)L.rho : (T)0;
+        T sd = visc ? (T)L.rho : (T)0;
 #pragma unroll
         for (int f = 0; f < 6; f++) {
             T kf;
             if (visc) kf = nb[f] >= 0 ? kin * (ec + en[f]) : kwall * ec;
             else kf = nb[f] >= 0 ? kp : (T)0;
-            s += kf;
+            sd += kf;
             K[f] = kf;
         }
-        dg = s;
-        if (!(dg > (T)0)) return;
-    } else {
-        long nb2[6];
-        if (!rb0_row<T>(L, c, i, j, k, K, nb2, dg)) return;
+        D = sd;
+        return D > (T)0;
+    }
+    long nb2[6];
+    return rb0_row<T>(L, c, i, j, k, K, nb2, D);
+}
+
+// one colour-split Gauss-Seidel update of the t-th cell of colour col, with the prolongation PRO
+// fused in (the open cells of level 0 are those with a nonzero flag)
+template <typename T, int NC, int PRO, typename TC>
+__device__ __forceinline__ void smooth_rb_cell(const Rb0V& L, const T* __restrict__ b,
+                                               T* __restrict__ x, int col, long t,
+                                               const ProV<TC>* P) {
+    long N = L.N, Nh = N >> 1;
+    int i, j, k;
+    rb_cell(L.grid, (unsigned)t, col, i, j, k);
+    long c = cell_index(L.grid, i, j, k);
+    long own = (long)col * Nh + t, oth = (long)(1 - col) * Nh;
+    T acc[NC];
+#pragma unroll
+    for (int m = 0; m < NC; m++) acc[m] = b[m * N + own];
+    T K[6], dg, xn[6][NC];
+    long nb[6];
+    long Nc = 0;
+    if (PRO != PRO_NONE) Nc = (long)P->gc.n[0] * P->gc.n[1] * P->gc.n[2];
+    T pe[6][NC];
+    bool upd = rb0_row_ld<T, NC, true>(L, c, i, j, k, x + oth, K, nb, dg, xn);
+    if (PRO == PRO_NBR) {
+#pragma unroll
+        for (int f = 0; f < 6; f++) {
+            bool on = nb[f] >= 0 && L.flag[nb[f] >= 0 ? nb[f] : 0] != 0;
+            long pc = on ? nb_parent(L.grid, P->gc, i, j, k, f) : 0;
+#pragma unroll
+            for (int m = 0; m < NC; m++) pe[f][m] = on ? (T)P->ec[m * Nc + pc] : (T)0;
+        }
+    }
+    if (!upd) {
+        if (PRO != PRO_NONE && L.flag[c] != 0) {
+            long pc = cell_index(P->gc, i >> 1, j >> 1, k >> 1);
+#pragma unroll
+            for (int m = 0; m < NC; m++) x[m * N + own] += (T)P->ec[m * Nc + pc];
+        }
+        return;
+    }
+    if (PRO == PRO_NBR) {
+#pragma unroll
+        for (int f = 0; f < 6; f++)
+#pragma unroll
+            for (int m = 0; m < NC; m++) xn[f][m] = xn[f][m] + pe[f][m];
     }
 #pragma unroll
     for (int f = 0; f < 6; f++) {
@@ -513,6 +663,24 @@ __global__ void __launch_bounds__(EB_BLOCK)
     T inv = (T)1 / dg;
 #pragma unroll
     for (int m = 0; m < NC; m++) x[m * N + own] = acc[m] * inv;
+}
+
+template <typename T, int NC>
+__global__ void __launch_bounds__(EB_BLOCK)
+    k_smooth_rb(Rb0V L, const T* __restrict__ b, T* __restrict__ x, int col) {
+    if (L.gate && *L.gate) return;
+    long t = xcd_block() * (long)blockDim.x + threadIdx.x;
+    if (t >= (L.N >> 1)) return;
+    smooth_rb_cell<T, NC, PRO_NONE, T>(L, b, x, col, t, nullptr);
+}
+
+template <typename T, typename TC, int NC, int PRO>
+__global__ void __launch_bounds__(EB_BLOCK)
+    k_smooth_rb_pro(Rb0V L, const T* __restrict__ b, T* __restrict__ x, int col, ProV<TC> P) {
+    if (L.gate && *L.gate) return;
+    long t = xcd_block() * (long)blockDim.x + threadIdx.x;
+    if (t >= (L.N >> 1)) return;
+    smooth_rb_cell<T, NC, PRO, TC>(L, b, x, col, t, &P);
 }
 
 // first half sweep (colour 0) from a zero iterate over both colours: colour 0 gets b/D, colour 1
@@ -554,28 +722,30 @@ __global__ void k_smooth_first_rb_from(Rb0V L, const double* __restrict__ bnat,
     int i, j, k;
     rb_cell(L.grid, (unsigned)t, col, i, j, k);
     long c = cell_index(L.grid, i, j, k);
+    T bv[NC];
+#pragma unroll
+    for (int m = 0; m < NC; m++) bv[m] = (T)bnat[m * N + c];
     bool upd = false;
     T Dd = (T)1;
     if (col == 0) {
-        T K[6];
+        T K[6], xn[6][NC];
         long nb[6];
-        upd = rb0_row<T>(L, c, i, j, k, K, nb, Dd);
+        upd = rb0_row_ld<T, NC, false>(L, c, i, j, k, x, K, nb, Dd, xn);
     }
     T inv = upd ? (T)1 / Dd : (T)0;
 #pragma unroll
     for (int m = 0; m < NC; m++) {
-        T bv = (T)bnat[m * N + c];
-        b[m * N + u] = bv;
-        x[m * N + u] = upd ? bv * inv : (T)0;
+        b[m * N + u] = bv[m];
+        x[m * N + u] = upd ? bv[m] * inv : (T)0;
     }
 }
 
 // the last half sweep (colour 0) fused with the conversion of the iterate back to natural
 // order (FP64): a thread updates its colour-0 cell and also copies the colour-1 cell next to it
 // in x, so every cell of the natural output is written once
-template <typename T, int NC>
+template <typename T, int NC, int PRO = PRO_NONE, typename TC = T>
 __global__ void k_smooth_last_rb_to(Rb0V L, const T* __restrict__ b, const T* __restrict__ x,
-                                    double* __restrict__ xnat) {
+                                    double* __restrict__ xnat, ProV<TC> P) {
     if (L.gate && *L.gate) return;
     long N = L.N, Nh = N >> 1;
     long t = xcd_block() * (long)blockDim.x + threadIdx.x;
@@ -584,31 +754,39 @@ __global__ void k_smooth_last_rb_to(Rb0V L, const T* __restrict__ b, const T* __
     rb_cell(L.grid, (unsigned)t, 0, i, j, k);
     long c = cell_index(L.grid, i, j, k);
     long c1 = cell_index(L.grid, i ^ 1, j, k);
-    T K[6], dg;
-    long nb[6];
-    bool upd = rb0_row<T>(L, c, i, j, k, K, nb, dg);
-    T val[NC];
+    T val[NC], bv[NC], x1[NC];
 #pragma unroll
-    for (int m = 0; m < NC; m++) val[m] = x[m * N + t];
+    for (int m = 0; m < NC; m++) {
+        val[m] = x[m * N + t];
+        bv[m] = b[m * N + t];
+        x1[m] = x[m * N + Nh + (c1 >> 1)];
+    }
+    T K[6], dg, xn[6][NC];
+    long nb[6];
+    bool upd = rb0_row_ld<T, NC, true>(L, c, i, j, k, x + Nh, K, nb, dg, xn);
     if (upd) {
 #pragma unroll
-        for (int m = 0; m < NC; m++) val[m] = b[m * N + t];
+        for (int m = 0; m < NC; m++) val[m] = bv[m];
 #pragma unroll
         for (int f = 0; f < 6; f++) {
             T kf = K[f];
             if (kf == (T)0 || nb[f] < 0) continue;
-            long q = Nh + (nb[f] >> 1);
 #pragma unroll
-            for (int m = 0; m < NC; m++) val[m] += kf * x[m * N + q];
+            for (int m = 0; m < NC; m++) val[m] += kf * xn[f][m];
         }
         T inv = (T)1 / dg;
 #pragma unroll
         for (int m = 0; m < NC; m++) val[m] = val[m] * inv;
+    } else if (PRO != PRO_NONE && L.flag[c] != 0) {
+        long Nc = (long)P.gc.n[0] * P.gc.n[1] * P.gc.n[2];
+        long pc = cell_index(P.gc, i >> 1, j >> 1, k >> 1);
+#pragma unroll
+        for (int m = 0; m < NC; m++) val[m] += (T)P.ec[m * Nc + pc];
     }
 #pragma unroll
     for (int m = 0; m < NC; m++) {
         xnat[m * N + c] = (double)val[m];
-        xnat[m * N + c1] = (double)x[m * N + Nh + (c1 >> 1)];
+        xnat[m * N + c1] = (double)x1[m];
     }
 }
 
@@ -634,25 +812,31 @@ __global__ void __launch_bounds__(RR_THREADS)
         cell_coords(gc, c, ci, cj, ck);
         int fi = 2 * ci + a, fj = 2 * cj + bq, fk = 2 * ck + cq;
         long f = cell_index(L.grid, fi, fj, fk);
-        if (L.flag[f] != 0) {
-            TF K[6], dg;
-            long nb[6];
-            rb0_row<TF>(L, f, fi, fj, fk, K, nb, dg);
+        long oth = (long)(1 - ((fi + fj + fk) & 1)) * (N >> 1);
+        long qf = rb_slot(N, fi, fj, fk, f);
+        TF bv[NC], xv[NC];
+#pragma unroll
+        for (int m = 0; m < NC; m++) {
+            bv[m] = b[m * N + qf];
+            xv[m] = x[m * N + qf];
+        }
+        TF K[6], dg, xn[6][NC];
+        long nb[6];
+        bool open = L.flag[f] != 0;
+        rb0_row_ld<TF, NC, true>(L, f, fi, fj, fk, x + oth, K, nb, dg, xn);
+        if (open) {
             TF acc[NC];
 #pragma unroll
             for (int m = 0; m < NC; m++) acc[m] = (TF)0;
-            long oth = (long)(1 - ((fi + fj + fk) & 1)) * (N >> 1);
 #pragma unroll
             for (int e = 0; e < 6; e++) {
                 TF kf = K[e];
                 if (kf == (TF)0 || nb[e] < 0) continue;
-                long qn = oth + (nb[e] >> 1);
 #pragma unroll
-                for (int m = 0; m < NC; m++) acc[m] += kf * x[m * N + qn];
+                for (int m = 0; m < NC; m++) acc[m] += kf * xn[e][m];
             }
-            long qf = rb_slot(N, fi, fj, fk, f);
 #pragma unroll
-            for (int m = 0; m < NC; m++) r[m] = b[m * N + qf] - (dg * x[m * N + qf] - acc[m]);
+            for (int m = 0; m < NC; m++) r[m] = bv[m] - (dg * xv[m] - acc[m]);
         }
     }
 #pragma unroll
@@ -1225,6 +1409,8 @@ size_t tail_layout(const Level* lev, int nlev, int t, int nc, TailArgs* A) {
 // ------------------------------------------------------------------------------------------
 // exact EB viscous Helmholtz operator (Eq. implicit-viscous with the wall flux of Eq. dudn)
 // ------------------------------------------------------------------------------------------
+// Every load of a cell (flag, its velocity, the six neighbours' velocities and viscosities) is
+// issued before the first is needed; the arithmetic and its order are unchanged.
 __global__ void __launch_bounds__(EB_BLOCK) k_visc_apply(GeomV g, double rho, double dt,
                                                          const double* __restrict__ eta,
                              const double* __restrict__ eta_eb, const double* __restrict__ u,
@@ -1233,34 +1419,50 @@ __global__ void __launch_bounds__(EB_BLOCK) k_visc_apply(GeomV g, double rho, do
     long N = g.N;
     long c = xcd_block() * (long)blockDim.x + threadIdx.x;
     if (c >= N) return;
+    int i, j, k;
+    cell_coords(g.grid, c, i, j, k);
+    long nb[6];
+#pragma unroll
+    for (int d = 0; d < 3; d++)
+#pragma unroll
+        for (int side = 0; side < 2; side++) {
+            int q[3] = {i, j, k};
+            q[d] += side ? 1 : -1;
+            nb[2 * d + side] = cell_at(g.grid, q[0], q[1], q[2]);
+        }
     uint8_t fl = g.flag[c];
+    double uc[3], un[6][3], en[6];
+#pragma unroll
+    for (int m = 0; m < 3; m++) uc[m] = u[m * N + c];
+#pragma unroll
+    for (int f = 0; f < 6; f++) {
+        en[f] = nb[f] >= 0 ? eta[nb[f]] : 0.0;
+#pragma unroll
+        for (int m = 0; m < 3; m++) un[f][m] = nb[f] >= 0 ? u[m * N + nb[f]] : 0.0;
+    }
+    double ec = eta[c];
     if (fl == 0) {
         for (int m = 0; m < 3; m++) out[m * N + c] = 0.0;
         return;
     }
-    int i, j, k;
-    cell_coords(g.grid, c, i, j, k);
     double h2 = g.grid.h * g.grid.h;
     double acc[3];
-    double ec = eta[c];
     if (fl == 2) {
         // regular cell: volume fraction and all six apertures are 1, no wall flux
-        for (int m = 0; m < 3; m++) acc[m] = 1.0 * rho * u[m * N + c];
+        for (int m = 0; m < 3; m++) acc[m] = 1.0 * rho * uc[m];
 #pragma unroll
         for (int d = 0; d < 3; d++)
 #pragma unroll
             for (int side = 0; side < 2; side++) {
-                int q[3] = {i, j, k};
-                q[d] += side ? 1 : -1;
-                long nb = cell_at(g.grid, q[0], q[1], q[2]);
-                if (nb >= 0) {
-                    double K = dt * 1.0 * 0.5 * (ec + eta[nb]) / h2;
-                    for (int m = 0; m < 3; m++) acc[m] -= K * (u[m * N + nb] - u[m * N + c]);
+                int f = 2 * d + side;
+                if (nb[f] >= 0) {
+                    double K = dt * 1.0 * 0.5 * (ec + en[f]) / h2;
+                    for (int m = 0; m < 3; m++) acc[m] -= K * (un[f][m] - uc[m]);
                 } else {
                     double K = 2.0 * dt * 1.0 * ec / h2;
                     for (int m = 0; m < 3; m++) {
                         double uw = homog ? 0.0 : g.wall[2 * d + side][m];
-                        acc[m] -= K * (uw - u[m * N + c]);
+                        acc[m] -= K * (uw - uc[m]);
                     }
                 }
             }
@@ -1268,26 +1470,24 @@ __global__ void __launch_bounds__(EB_BLOCK) k_visc_apply(GeomV g, double rho, do
         return;
     }
     double al = g.alpha[c];
-    for (int m = 0; m < 3; m++) acc[m] = al * rho * u[m * N + c];
+    for (int m = 0; m < 3; m++) acc[m] = al * rho * uc[m];
 #pragma unroll
     for (int d = 0; d < 3; d++)
 #pragma unroll
         for (int side = 0; side < 2; side++) {
-            int f[3] = {i, j, k};
-            f[d] += side;
-            double A = g.ap[d][face_index(g.grid, d, f[0], f[1], f[2])];
+            int fi[3] = {i, j, k};
+            fi[d] += side;
+            double A = g.ap[d][face_index(g.grid, d, fi[0], fi[1], fi[2])];
             if (A == 0.0) continue;
-            int q[3] = {i, j, k};
-            q[d] += side ? 1 : -1;
-            long nb = cell_at(g.grid, q[0], q[1], q[2]);
-            if (nb >= 0) {
-                double K = dt * A * 0.5 * (ec + eta[nb]) / h2;
-                for (int m = 0; m < 3; m++) acc[m] -= K * (u[m * N + nb] - u[m * N + c]);
+            int f = 2 * d + side;
+            if (nb[f] >= 0) {
+                double K = dt * A * 0.5 * (ec + en[f]) / h2;
+                for (int m = 0; m < 3; m++) acc[m] -= K * (un[f][m] - uc[m]);
             } else {
                 double K = 2.0 * dt * A * ec / h2;
                 for (int m = 0; m < 3; m++) {
                     double uw = homog ? 0.0 : g.wall[2 * d + side][m];
-                    acc[m] -= K * (uw - u[m * N + c]);
+                    acc[m] -= K * (uw - uc[m]);
                 }
             }
         }
@@ -1306,22 +1506,40 @@ __global__ void __launch_bounds__(EB_BLOCK) k_visc_apply_eb(GeomV g, double dt,
     int nc = g.ncut;
     if (q >= nc) return;
     long N = g.N;
+    const int* __restrict__ sidx = g.sidx;
+    const double* __restrict__ sw = g.sw;
+    // every load first: the stencil's 18 indices and weights, then the 54 velocity values and
+    // the three rows being added to
     long c = g.cut[q];
+    int ci[18];
+    double wi[18];
+#pragma unroll
+    for (int t = 0; t < 18; t++) {
+        ci[t] = sidx[(long)t * nc + q];
+        wi[t] = sw[(long)t * nc + q];
+    }
     double d1 = g.dd[q], d2 = g.dd[nc + q];
-    double den = d1 * d2 * (d2 - d1) * g.grid.h;
     double coef = dt * g.aeb[q] * eta_eb[q] / g.grid.h;
+    double uv[3][18], o[3];
+#pragma unroll
+    for (int m = 0; m < 3; m++) {
+        double ue = homog ? 0.0 : g.ueb[m];
+#pragma unroll
+        for (int t = 0; t < 18; t++) uv[m][t] = ci[t] >= 0 ? u[m * N + ci[t]] : ue;
+        o[m] = out[m * N + c];
+    }
+    double den = d1 * d2 * (d2 - d1) * g.grid.h;
 #pragma unroll
     for (int m = 0; m < 3; m++) {
         double ue = homog ? 0.0 : g.ueb[m];
         double s1 = 0.0, s2 = 0.0;
+#pragma unroll
         for (int t = 0; t < 9; t++) {
-            int c1 = g.sidx[(long)t * nc + q];
-            s1 += g.sw[(long)t * nc + q] * (c1 >= 0 ? u[m * N + c1] : ue);
-            int c2 = g.sidx[(long)(t + 9) * nc + q];
-            s2 += g.sw[(long)(t + 9) * nc + q] * (c2 >= 0 ? u[m * N + c2] : ue);
+            s1 += wi[t] * uv[m][t];
+            s2 += wi[t + 9] * uv[m][t + 9];
         }
         double gn = (d2 * d2 * (s1 - ue) - d1 * d1 * (s2 - ue)) / den;
-        out[m * N + c] += coef * gn;
+        out[m * N + c] = o[m] + coef * gn;
     }
 }
 
@@ -1384,6 +1602,93 @@ __global__ void k_maxabs(long n, int ncomp, const double* __restrict__ x,
         v = block_max(v, sh);
         if (threadIdx.x == 0) part[m * gridDim.x + blockIdx.x] = v;
     }
+}
+
+// ---- Krylov steps fused with the reductions that follow them (same grid, same per-thread
+// ---- order and the same final pass as k_dots / k_maxabs, so the scalars are bit for bit those
+// ---- of the separate kernels), and final passes that go on to the scalar update
+struct OpOut {
+    int idx[4];   // ks slot receiving each reduced row
+    int maxmask;  // bit p set: row p is a maximum (else a sum)
+};
+
+// rows of per-block partials reduced into ks[idx[p]], then the scalar update op; the rows are
+// skipped once the solve has stopped (the op itself then does nothing)
+__global__ void k_final_op(const double* __restrict__ part, int nb, int nrow, OpOut o, int op,
+                           double* __restrict__ ks, int* __restrict__ st, int* __restrict__ itc) {
+    __shared__ double sh[EB_BLOCK];
+    if (*st == 0) {
+        for (int p = 0; p < nrow; p++) {
+            bool mx = (o.maxmask >> p) & 1;
+            double v = 0.0;
+            for (int t = threadIdx.x; t < nb; t += blockDim.x)
+                v = mx ? fmax(v, part[p * nb + t]) : v + part[p * nb + t];
+            v = mx ? block_max(v, sh) : block_sum(v, sh);
+            if (threadIdx.x == 0) ks[o.idx[p]] = v;
+        }
+    }
+    if (threadIdx.x == 0) ks_scalar_op(op, ks, st, itc);
+}
+
+// BiCGSTAB: s = r - alpha v, with the per-block max |s|
+__global__ void k_bi_s_max(long n, double* __restrict__ sv, const double* __restrict__ r,
+                           const double* __restrict__ v, const double* __restrict__ ks,
+                           const int* __restrict__ st, double* __restrict__ part) {
+    if (*st != 0) return;
+    __shared__ double sh[EB_BLOCK];
+    double al = ks[KS_AL], m = 0.0;
+    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n;
+         t += (long)gridDim.x * blockDim.x) {
+        double s = r[t] - al * v[t];
+        sv[t] = s;
+        m = fmax(m, fabs(s));
+    }
+    m = block_max(m, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = m;
+}
+
+// BiCGSTAB: x += alpha ph + omega sh, r = s - omega t, with the per-block partials of rh . r
+// (row 0) and max |r| (row 1)
+__global__ void k_bi_xr_red(long n, double* __restrict__ x, double* __restrict__ r,
+                            const double* __restrict__ ph, const double* __restrict__ sh_,
+                            const double* __restrict__ sv, const double* __restrict__ tv,
+                            const double* __restrict__ rh, const double* __restrict__ ks,
+                            const int* __restrict__ st, double* __restrict__ part) {
+    if (*st != 0) return;
+    __shared__ double sh[EB_BLOCK];
+    double al = ks[KS_AL], om = ks[KS_OM];
+    double dot = 0.0, m = 0.0;
+    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n;
+         t += (long)gridDim.x * blockDim.x) {
+        x[t] += al * ph[t] + om * sh_[t];
+        double rn = sv[t] - om * tv[t];
+        r[t] = rn;
+        dot += rh[t] * rn;
+        m = fmax(m, fabs(rn));
+    }
+    dot = block_sum(dot, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = dot;
+    m = block_max(m, sh);
+    if (threadIdx.x == 0) part[gridDim.x + blockIdx.x] = m;
+}
+
+// CG: x += alpha p, r -= alpha q, with the per-block max |r|
+__global__ void k_cg_xr_max(long n, double* __restrict__ x, double* __restrict__ r,
+                            const double* __restrict__ p, const double* __restrict__ q,
+                            const double* __restrict__ ks, const int* __restrict__ st,
+                            double* __restrict__ part) {
+    if (*st != 0) return;
+    __shared__ double sh[EB_BLOCK];
+    double a = ks[KS_AL], m = 0.0;
+    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n;
+         t += (long)gridDim.x * blockDim.x) {
+        x[t] += a * p[t];
+        double rn = r[t] - a * q[t];
+        r[t] = rn;
+        m = fmax(m, fabs(rn));
+    }
+    m = block_max(m, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = m;
 }
 
 // over open cells: the largest |u| + |v| + |w| (row 0) and the largest yield-stress multiplier
@@ -1586,6 +1891,22 @@ void resid_restrict_pass(const Level& F, const Level& C, int nc, const TF* b, co
         k_resid_restrict<TF, TC, 1><<<gr, RR_THREADS, 0, s>>>(level_view<TF>(F), b, x, C.grid,
                                                               C.mask, bc);
 }
+// the first post-smoothing pair (colour 1, then colour 0) with the prolongation of ec fused in
+template <typename T, typename TC>
+void smooth_pro_pair(const Level& L, const Level& C, int nc, const T* b, T* x, const TC* ec,
+                     hipStream_t s) {
+    unsigned gb = grid_for(L.N / 2);
+    ProV<TC> P{C.grid, ec};
+    LevelV<T> v = level_view<T>(L);
+    if (nc == 3) {
+        k_smooth_pro<T, TC, 3, PRO_NBR><<<gb, EB_BLOCK, 0, s>>>(v, b, x, 1, P);
+        k_smooth_pro<T, TC, 3, PRO_OWN><<<gb, EB_BLOCK, 0, s>>>(v, b, x, 0, P);
+    } else {
+        k_smooth_pro<T, TC, 1, PRO_NBR><<<gb, EB_BLOCK, 0, s>>>(v, b, x, 1, P);
+        k_smooth_pro<T, TC, 1, PRO_OWN><<<gb, EB_BLOCK, 0, s>>>(v, b, x, 0, P);
+    }
+}
+
 template <typename TC, typename TF>
 void prolong_pass(const Level& F, const Level& C, int nc, const TC* ec, TF* xf, hipStream_t s) {
     if (nc == 3)
@@ -1711,9 +2032,17 @@ void vcycle_level(const VArgs& a, int l) {
     if (level_f32(a, l + 1)) resid_restrict_pass<T, float>(L, C, a.nc, b, x, C.bf, a.s);
     else resid_restrict_pass<T, double>(L, C, a.nc, b, x, C.b, a.s);
     vcycle_rec(a, l + 1);
-    if (level_f32(a, l + 1)) prolong_pass<float, T>(L, C, a.nc, C.xf, x, a.s);
-    else prolong_pass<double, T>(L, C, a.nc, C.x, x, a.s);
+    bool cf32 = level_f32(a, l + 1);
+    if (a.nu2 < 1) {
+        if (cf32) prolong_pass<float, T>(L, C, a.nc, C.xf, x, a.s);
+        else prolong_pass<double, T>(L, C, a.nc, C.x, x, a.s);
+    }
     for (int t = 0; t < a.nu2; t++) {
+        if (t == 0) {
+            if (cf32) smooth_pro_pair<T, float>(L, C, a.nc, b, x, C.xf, a.s);
+            else smooth_pro_pair<T, double>(L, C, a.nc, b, x, C.x, a.s);
+            continue;
+        }
         smooth_pass<T>(L, a.nc, b, x, 1, a.s);
         smooth_pass<T>(L, a.nc, b, x, 0, a.s);
     }
@@ -1723,6 +2052,47 @@ void vcycle_rec(const VArgs& a, int l) {
     if (l == a.tail && a.tail_fits) launch_tail(a);
     else if (level_f32(a, l)) vcycle_level<float>(a, l);
     else vcycle_level<double>(a, l);
+}
+
+// level 0's prolongation and post-smoothing: the prolongation of ec rides on the first pair of
+// half sweeps (a pass of its own only without post-smoothing); the last half sweep writes the
+// natural-order FP64 result x0
+template <typename T, typename TC>
+void up_leg_rb(const VArgs& a, const Rb0V& v, const GridV& gc, const TC* ec, const T* b, T* x,
+               double* x0) {
+    int nc = a.nc;
+    long N = v.N;
+    unsigned gh = grid_for(N / 2);
+    ProV<TC> P{gc, ec}, none{gc, nullptr};
+    if (a.nu2 < 1) {
+        unsigned gf = grid_for(N);
+        if (nc == 3) k_prolong_rb<TC, T, 3><<<gf, EB_BLOCK, 0, a.s>>>(v, gc, ec, x);
+        else k_prolong_rb<TC, T, 1><<<gf, EB_BLOCK, 0, a.s>>>(v, gc, ec, x);
+        return;
+    }
+    for (int t = 0; t < a.nu2; t++) {
+        bool first = t == 0, last = t == a.nu2 - 1;
+        if (first) {
+            if (nc == 3) k_smooth_rb_pro<T, TC, 3, PRO_NBR><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, 1, P);
+            else k_smooth_rb_pro<T, TC, 1, PRO_NBR><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, 1, P);
+        } else {
+            if (nc == 3) k_smooth_rb<T, 3><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, 1);
+            else k_smooth_rb<T, 1><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, 1);
+        }
+        if (last && first) {
+            if (nc == 3) k_smooth_last_rb_to<T, 3, PRO_OWN, TC><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, x0, P);
+            else k_smooth_last_rb_to<T, 1, PRO_OWN, TC><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, x0, P);
+        } else if (last) {
+            if (nc == 3) k_smooth_last_rb_to<T, 3, PRO_NONE, TC><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, x0, none);
+            else k_smooth_last_rb_to<T, 1, PRO_NONE, TC><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, x0, none);
+        } else if (first) {
+            if (nc == 3) k_smooth_rb_pro<T, TC, 3, PRO_OWN><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, 0, P);
+            else k_smooth_rb_pro<T, TC, 1, PRO_OWN><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, 0, P);
+        } else {
+            if (nc == 3) k_smooth_rb<T, 3><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, 0);
+            else k_smooth_rb<T, 1><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, 0);
+        }
+    }
 }
 
 // level 0 of a V-cycle in colour-split storage (it is neither the coarsest nor a tail level):
@@ -1760,24 +2130,8 @@ void vcycle_level0_rb(const VArgs& a, const double* b0, double* x0, T* b, T* x) 
         else k_resid_restrict_rb<T, double, 1><<<gc, RR_THREADS, 0, a.s>>>(v, b, x, C.grid, C.mask, C.b);
     }
     vcycle_rec(a, 1);
-    unsigned gf = grid_for(L.N);
-    if (cf32) {
-        if (nc == 3) k_prolong_rb<float, T, 3><<<gf, EB_BLOCK, 0, a.s>>>(v, C.grid, C.xf, x);
-        else k_prolong_rb<float, T, 1><<<gf, EB_BLOCK, 0, a.s>>>(v, C.grid, C.xf, x);
-    } else {
-        if (nc == 3) k_prolong_rb<double, T, 3><<<gf, EB_BLOCK, 0, a.s>>>(v, C.grid, C.x, x);
-        else k_prolong_rb<double, T, 1><<<gf, EB_BLOCK, 0, a.s>>>(v, C.grid, C.x, x);
-    }
-    for (int t = 0; t < a.nu2; t++) {
-        smooth_rb_pass<T>(L, nc, b, x, 1, a.s);
-        if (t < a.nu2 - 1) {
-            smooth_rb_pass<T>(L, nc, b, x, 0, a.s);
-        } else {
-            unsigned gh = grid_for(L.N / 2);
-            if (nc == 3) k_smooth_last_rb_to<T, 3><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, x0);
-            else k_smooth_last_rb_to<T, 1><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, x0);
-        }
-    }
+    if (cf32) up_leg_rb<T, float>(a, v, C.grid, C.xf, b, x, x0);
+    else up_leg_rb<T, double>(a, v, C.grid, C.x, b, x, x0);
     if (a.nu2 < 1) {
         if (nc == 3) k_from_rb<T, double, 3><<<g, EB_BLOCK, 0, a.s>>>(L.grid, L.N, x, x0, L.gate);
         else k_from_rb<T, double, 1><<<g, EB_BLOCK, 0, a.s>>>(L.grid, L.N, x, x0, L.gate);
@@ -1918,6 +2272,47 @@ void red_dots(long n, int np, const double* const a[4], const double* const b[4]
     k_final<<<1, EB_BLOCK, 0, s>>>(part, nb, np, 0, out, gate);
 }
 
+void red_dots_op(long n, int np, const double* const a[4], const double* const b[4],
+                 double* part, int out_idx, int op, double* ks, int* st, int* itc,
+                 hipStream_t s) {
+    DotArgs args;
+    OpOut o;
+    for (int p = 0; p < 4; p++) {
+        args.a[p] = p < np ? a[p] : nullptr;
+        args.b[p] = p < np ? b[p] : nullptr;
+        o.idx[p] = out_idx + p;
+    }
+    o.maxmask = 0;
+    int nb = red_blocks(n);
+    k_dots<<<nb, EB_BLOCK, 0, s>>>(n, np, args, part, st);
+    k_final_op<<<1, EB_BLOCK, 0, s>>>(part, nb, np, o, op, ks, st, itc);
+}
+
+void ks_bi_s_op(long n, double* sv, const double* r, const double* v, double* part, double* ks,
+                int* st, int* itc, hipStream_t s) {
+    OpOut o = {{KS_SN, 0, 0, 0}, 1};
+    int nb = red_blocks(n);
+    k_bi_s_max<<<nb, EB_BLOCK, 0, s>>>(n, sv, r, v, ks, st, part);
+    k_final_op<<<1, EB_BLOCK, 0, s>>>(part, nb, 1, o, KS_BI_CHECK_S, ks, st, itc);
+}
+
+void ks_bi_xr_op(long n, double* x, double* r, const double* ph, const double* sh,
+                 const double* sv, const double* t, const double* rh, double* part, double* ks,
+                 int* st, int* itc, hipStream_t s) {
+    OpOut o = {{KS_RRN, KS_RN, 0, 0}, 2};
+    int nb = red_blocks(n);
+    k_bi_xr_red<<<nb, EB_BLOCK, 0, s>>>(n, x, r, ph, sh, sv, t, rh, ks, st, part);
+    k_final_op<<<1, EB_BLOCK, 0, s>>>(part, nb, 2, o, KS_BI_CHECK_R, ks, st, itc);
+}
+
+void ks_cg_xr_op(long n, double* x, double* r, const double* p, const double* q, double* part,
+                 double* ks, int* st, int* itc, hipStream_t s) {
+    OpOut o = {{KS_RN, 0, 0, 0}, 1};
+    int nb = red_blocks(n);
+    k_cg_xr_max<<<nb, EB_BLOCK, 0, s>>>(n, x, r, p, q, ks, st, part);
+    k_final_op<<<1, EB_BLOCK, 0, s>>>(part, nb, 1, o, KS_CHECK_R, ks, st, itc);
+}
+
 void red_maxabs(long n, int ncomp, const double* x, double* part, double* out, hipStream_t s,
                 const int* gate) {
     int nb = red_blocks(n);
@@ -1978,4 +2373,6 @@ void vec_mask_rhs(const GeomV& g, const double* psi, const double* a0, double* b
     k_mask_rhs<<<grid_for(3 * g.N), EB_BLOCK, 0, s>>>(g, psi, a0, b);
 }
 
-int mg_tail_level(const Level* lev, int nlev) { return tail_level(lev, nlev); }
+bool mg_level0_f32(const Level* lev, int nlev) {
+    return tail_level(lev, nlev) > 0 && lev[0].N >= F32_MIN_CELLS;
+}

@@ -143,6 +143,20 @@ def test_vcycles_match(s32):
         assert rel_l2(cpu(got3)[j], ref3[j], P.open) <= 1e-12
 
 
+def test_fp32_sweep_needs_an_fp32_finest_level(s32):
+    """A mixed hierarchy keeps levels below 64^3 cells in FP64, so on the 32^3 box the FP32
+    sweep entry point has no FP32 operator to run and says so."""
+    P = s32
+    from paper_1905_07392_amd._lib import EbError
+
+    r = torch.zeros((1,) + P.og.shape, dtype=torch.float64, device="cuda:0")
+    P.api.eb_mg_vcycle(P.ctx, P.api.EB_SYS_POISSON, r, P.opts, precision=P.api.EB_MIXED)
+    b = torch.zeros(P.og.shape, dtype=torch.float32, device="cuda:0")
+    with pytest.raises(EbError, match="runs in FP64"):
+        P.api.eb_mg_sweep(P.ctx, P.api.EB_SYS_POISSON, 0, b, b.clone(), P.api.EB_MIXED)
+    torch.cuda.synchronize()
+
+
 def test_solvers_and_projections(s32):
     P = s32
     u0, p0 = P.O.prepare_state(P.w, P.og, P.oopts)
