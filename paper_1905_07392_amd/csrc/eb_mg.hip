@@ -174,6 +174,53 @@ __device__ __forceinline__ long nb_parent(const GridV& gf, const GridV& gc, int 
     return cell_index(gc, q[0] >> 1, q[1] >> 1, q[2] >> 1);
 }
 
+// The corrections a fused prolongation adds to the six neighbour values of fine cell (i, j, k)
+// (0 for a missing or closed neighbour; open: the level's open-cell bytes).  In each direction
+// one neighbour shares the cell's coarse parent and the other lies in the adjacent parent, so
+// four coarse values are read.  nbr_load issues the loads (before anything waits on memory),
+// nbr_corrections forms the corrections once they are needed.
+template <int NC, typename TC>
+struct NbrE {
+    TC e0[NC], eo[3][NC];
+    uint8_t fo[6];
+};
+template <int NC, typename TC>
+__device__ __forceinline__ void nbr_load(const GridV& gf, const ProV<TC>& P, int i, int j, int k,
+                                         const long nb[6], const uint8_t* __restrict__ open,
+                                         NbrE<NC, TC>& E) {
+    long Nc = (long)P.gc.n[0] * P.gc.n[1] * P.gc.n[2];
+    const TC* __restrict__ ec = P.ec;
+    int q[3] = {i, j, k};
+    long p0 = cell_index(P.gc, i >> 1, j >> 1, k >> 1);
+#pragma unroll
+    for (int m = 0; m < NC; m++) E.e0[m] = ec[m * Nc + p0];
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        int f = 2 * d + (q[d] & 1);
+        long po = nb[f] >= 0 ? nb_parent(gf, P.gc, i, j, k, f) : p0;
+#pragma unroll
+        for (int m = 0; m < NC; m++) E.eo[d][m] = ec[m * Nc + po];
+    }
+#pragma unroll
+    for (int f = 0; f < 6; f++) E.fo[f] = nb[f] >= 0 ? open[nb[f]] : (uint8_t)0;
+}
+template <typename T, int NC, typename TC>
+__device__ __forceinline__ void nbr_corrections(const NbrE<NC, TC>& E, int i, int j, int k,
+                                                const long nb[6], T pe[6][NC]) {
+    int q[3] = {i, j, k};
+#pragma unroll
+    for (int d = 0; d < 3; d++)
+#pragma unroll
+        for (int side = 0; side < 2; side++) {
+            int f = 2 * d + side;
+            bool on = nb[f] >= 0 && E.fo[f] != 0;
+            bool outer = side == (q[d] & 1);
+#pragma unroll
+            for (int m = 0; m < NC; m++)
+                pe[f][m] = on ? (T)(outer ? E.eo[d][m] : E.e0[m]) : (T)0;
+        }
+}
+
 // one Gauss-Seidel update of the t-th cell of colour col (cells of a colour are numbered row by
 // row, nx/2 per row), with the prolongation PRO fused in
 template <typename T, int NC, int PRO = PRO_NONE, typename TC = T>
@@ -214,14 +261,10 @@ __device__ __forceinline__ void smooth_cell(const LevelV<T>& L, const T* __restr
     long Nc = 0;
     if (PRO != PRO_NONE) Nc = (long)P->gc.n[0] * P->gc.n[1] * P->gc.n[2];
     T pe[6][NC];
+    NbrE<NC, TC> E;
     if (PRO == PRO_NBR) {
-#pragma unroll
-        for (int f = 0; f < 6; f++) {
-            bool on = nb[f] >= 0 && L.mask[nb[f] >= 0 ? nb[f] : 0];
-            long pc = on ? nb_parent(g, P->gc, i, j, k, f) : 0;
-#pragma unroll
-            for (int m = 0; m < NC; m++) pe[f][m] = on ? (T)P->ec[m * Nc + pc] : (T)0;
-        }
+        nbr_load<NC, TC>(g, *P, i, j, k, nb, L.mask, E);
+        nbr_corrections<T, NC, TC>(E, i, j, k, nb, pe);
     }
     if (!msk) return;
     if (!(dg > (T)0)) {
@@ -345,11 +388,42 @@ __device__ __forceinline__ int rr_thread(int cl, int q) {
     return ((q >> 2) * 2 + ((q >> 1) & 1)) * (2 * RR_COARSE) + cl * 2 + (q & 1);
 }
 
+// The coarse level's first pre-smoothing pass carried by the restriction into it: with x set,
+// the thread that stores a coarse right-hand side also stores k_smooth_first's iterate for that
+// cell (b / D on open colour-0 cells with a positive diagonal, 0 elsewhere), computed from the
+// stored right-hand side exactly as k_smooth_first computes it.
+template <typename TC>
+struct FirstV {
+    TC* x;          // null: no fused first pass
+    const TC* D;    // the coarse level's diagonal, in its precision
+};
+
+template <typename TF, typename TC, int NC>
+__device__ __forceinline__ void rr_store(const GridV& gc, long Nc, long cc,
+                                         const uint8_t* __restrict__ mc, const TF sum[NC],
+                                         TC* __restrict__ bc, const FirstV<TC>& F1) {
+    bool open = mc[cc] != 0;
+    TC bcv[NC];
+#pragma unroll
+    for (int m = 0; m < NC; m++) {
+        bcv[m] = open ? (TC)(sum[m] / (TF)8) : (TC)0;
+        bc[m * Nc + cc] = bcv[m];
+    }
+    if (F1.x) {
+        int i, j, k;
+        cell_coords(gc, cc, i, j, k);
+        bool upd = ((i + j + k) & 1) == 0 && open && F1.D[cc] > (TC)0;
+        TC dg = upd ? F1.D[cc] : (TC)1;
+#pragma unroll
+        for (int m = 0; m < NC; m++) F1.x[m * Nc + cc] = upd ? (bcv[m] + (TC)0) / dg : (TC)0;
+    }
+}
+
 
 template <typename TF, typename TC, int NC>
 __global__ void __launch_bounds__(RR_THREADS)
     k_resid_restrict(LevelV<TF> L, const TF* __restrict__ b, const TF* __restrict__ x, GridV gc,
-                     const uint8_t* __restrict__ mc, TC* __restrict__ bc) {
+                     const uint8_t* __restrict__ mc, TC* __restrict__ bc, FirstV<TC> F1) {
     if (L.gate && *L.gate) return;
     __shared__ TF rs[RR_THREADS * NC];
     long Nc = (long)gc.n[0] * gc.n[1] * gc.n[2];
@@ -418,8 +492,7 @@ __global__ void __launch_bounds__(RR_THREADS)
 #pragma unroll
             for (int m = 0; m < NC; m++) sum[m] += rs[t * NC + m];
         }
-#pragma unroll
-        for (int m = 0; m < NC; m++) bc[m * Nc + cc] = mc[cc] ? (TC)(sum[m] / (TF)8) : (TC)0;
+        rr_store<TF, TC, NC>(gc, Nc, cc, mc, sum, bc, F1);
     }
 }
 
@@ -629,16 +702,21 @@ __device__ __forceinline__ void smooth_rb_cell(const Rb0V& L, const T* __restric
     long Nc = 0;
     if (PRO != PRO_NONE) Nc = (long)P->gc.n[0] * P->gc.n[1] * P->gc.n[2];
     T pe[6][NC];
-    bool upd = rb0_row_ld<T, NC, true>(L, c, i, j, k, x + oth, K, nb, dg, xn);
+    NbrE<NC, TC> E;
     if (PRO == PRO_NBR) {
+        // the neighbours' indices (rb0_row_ld forms the same ones) and the coarse loads first
 #pragma unroll
-        for (int f = 0; f < 6; f++) {
-            bool on = nb[f] >= 0 && L.flag[nb[f] >= 0 ? nb[f] : 0] != 0;
-            long pc = on ? nb_parent(L.grid, P->gc, i, j, k, f) : 0;
+        for (int d = 0; d < 3; d++)
 #pragma unroll
-            for (int m = 0; m < NC; m++) pe[f][m] = on ? (T)P->ec[m * Nc + pc] : (T)0;
-        }
+            for (int side = 0; side < 2; side++) {
+                int q[3] = {i, j, k};
+                q[d] += side ? 1 : -1;
+                nb[2 * d + side] = cell_at(L.grid, q[0], q[1], q[2]);
+            }
+        nbr_load<NC, TC>(L.grid, *P, i, j, k, nb, L.flag, E);
     }
+    bool upd = rb0_row_ld<T, NC, true>(L, c, i, j, k, x + oth, K, nb, dg, xn);
+    if (PRO == PRO_NBR) nbr_corrections<T, NC, TC>(E, i, j, k, nb, pe);
     if (!upd) {
         if (PRO != PRO_NONE && L.flag[c] != 0) {
             long pc = cell_index(P->gc, i >> 1, j >> 1, k >> 1);
@@ -663,6 +741,54 @@ __device__ __forceinline__ void smooth_rb_cell(const Rb0V& L, const T* __restric
     T inv = (T)1 / dg;
 #pragma unroll
     for (int m = 0; m < NC; m++) x[m * N + own] = acc[m] * inv;
+}
+
+// y = M x on level 0 in natural order, the regular cells' coefficients formed on the fly as the
+// colour-split smoother forms them (bit for bit the stored ones), so only x, the flags and y
+// move: every load is issued first, and y is resid_cell's (without b) bit for bit
+template <int NC>
+__global__ void __launch_bounds__(EB_BLOCK)
+    k_apply0(Rb0V L, const double* __restrict__ x, double* __restrict__ y) {
+    if (L.gate && *L.gate) return;
+    long N = L.N;
+    long c = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (c >= N) return;
+    int i, j, k;
+    cell_coords(L.grid, c, i, j, k);
+    long nb[6];
+#pragma unroll
+    for (int d = 0; d < 3; d++)
+#pragma unroll
+        for (int side = 0; side < 2; side++) {
+            int q[3] = {i, j, k};
+            q[d] += side ? 1 : -1;
+            nb[2 * d + side] = cell_at(L.grid, q[0], q[1], q[2]);
+        }
+    double xv[NC], xn[6][NC];
+#pragma unroll
+    for (int m = 0; m < NC; m++) xv[m] = x[m * N + c];
+#pragma unroll
+    for (int f = 0; f < 6; f++)
+#pragma unroll
+        for (int m = 0; m < NC; m++) xn[f][m] = nb[f] >= 0 ? x[m * N + nb[f]] : 0.0;
+    double K[6], dg, unused[6][NC];
+    rb0_row_ld<double, NC, false>(L, c, i, j, k, x, K, nb, dg, unused);
+    if (L.flag[c] == 0) {
+#pragma unroll
+        for (int m = 0; m < NC; m++) y[m * N + c] = 0.0;
+        return;
+    }
+    double acc[NC];
+#pragma unroll
+    for (int m = 0; m < NC; m++) acc[m] = 0.0;
+#pragma unroll
+    for (int f = 0; f < 6; f++) {
+        if (K[f] == 0.0 || nb[f] < 0) continue;
+#pragma unroll
+        for (int m = 0; m < NC; m++) acc[m] += K[f] * xn[f][m];
+    }
+#pragma unroll
+    for (int m = 0; m < NC; m++) y[m * N + c] = dg * xv[m] - acc[m];
 }
 
 template <typename T, int NC>
@@ -795,7 +921,7 @@ __global__ void k_smooth_last_rb_to(Rb0V L, const T* __restrict__ b, const T* __
 template <typename TF, typename TC, int NC>
 __global__ void __launch_bounds__(RR_THREADS)
     k_resid_restrict_rb(Rb0V L, const TF* __restrict__ b, const TF* __restrict__ x, GridV gc,
-                        const uint8_t* __restrict__ mc, TC* __restrict__ bc) {
+                        const uint8_t* __restrict__ mc, TC* __restrict__ bc, FirstV<TC> F1) {
     if (L.gate && *L.gate) return;
     __shared__ TF rs[RR_THREADS * NC];
     long N = L.N;
@@ -853,8 +979,7 @@ __global__ void __launch_bounds__(RR_THREADS)
 #pragma unroll
             for (int m = 0; m < NC; m++) sum[m] += rs[t * NC + m];
         }
-#pragma unroll
-        for (int m = 0; m < NC; m++) bc[m * Nc + cc] = mc[cc] ? (TC)(sum[m] / (TF)8) : (TC)0;
+        rr_store<TF, TC, NC>(gc, Nc, cc, mc, sum, bc, F1);
     }
 }
 
@@ -1882,14 +2007,14 @@ void first_pass(const Level& L, int nc, const T* b, T* x, hipStream_t s) {
 }
 template <typename TF, typename TC>
 void resid_restrict_pass(const Level& F, const Level& C, int nc, const TF* b, const TF* x,
-                         TC* bc, hipStream_t s) {
+                         TC* bc, FirstV<TC> F1, hipStream_t s) {
     unsigned gr = grid_for(C.N, RR_COARSE);
     if (nc == 3)
         k_resid_restrict<TF, TC, 3><<<gr, RR_THREADS, 0, s>>>(level_view<TF>(F), b, x, C.grid,
-                                                              C.mask, bc);
+                                                              C.mask, bc, F1);
     else
         k_resid_restrict<TF, TC, 1><<<gr, RR_THREADS, 0, s>>>(level_view<TF>(F), b, x, C.grid,
-                                                              C.mask, bc);
+                                                              C.mask, bc, F1);
 }
 // the first post-smoothing pair (colour 1, then colour 0) with the prolongation of ec fused in
 template <typename T, typename TC>
@@ -2005,6 +2130,25 @@ float* rl<float>(Level& L) { return L.rf; }
 
 void vcycle_rec(const VArgs& a, int l);
 
+// whether level l's first pre-smoothing pass is carried by the restriction into it (a level
+// with pre-smoothing below level 0 that is neither the coarsest nor run by the tail kernel)
+bool first_fused(const VArgs& a, int l) {
+    return l >= 1 && l < a.nlev - 1 && a.nu1 >= 1 && !(l >= a.tail && a.tail_fits);
+}
+// the fused first pass into level l (in level l's precision), or none
+template <typename TC>
+FirstV<TC> first_into(const VArgs& a, int l);
+template <>
+FirstV<double> first_into<double>(const VArgs& a, int l) {
+    if (!first_fused(a, l)) return FirstV<double>{nullptr, nullptr};
+    return FirstV<double>{a.lev[l].x, a.lev[l].D};
+}
+template <>
+FirstV<float> first_into<float>(const VArgs& a, int l) {
+    if (!first_fused(a, l)) return FirstV<float>{nullptr, nullptr};
+    return FirstV<float>{a.lev[l].xf, a.lev[l].Df};
+}
+
 template <typename T>
 void vcycle_level(const VArgs& a, int l) {
     Level& L = a.lev[l];
@@ -2024,13 +2168,18 @@ void vcycle_level(const VArgs& a, int l) {
         return;
     }
     for (int t = 0; t < a.nu1; t++) {
-        if (t == 0) first_pass<T>(L, a.nc, b, x, a.s);
-        else smooth_pass<T>(L, a.nc, b, x, 0, a.s);
+        if (t == 0) {
+            if (!first_fused(a, l)) first_pass<T>(L, a.nc, b, x, a.s);
+        } else {
+            smooth_pass<T>(L, a.nc, b, x, 0, a.s);
+        }
         smooth_pass<T>(L, a.nc, b, x, 1, a.s);
     }
     Level& C = a.lev[l + 1];
-    if (level_f32(a, l + 1)) resid_restrict_pass<T, float>(L, C, a.nc, b, x, C.bf, a.s);
-    else resid_restrict_pass<T, double>(L, C, a.nc, b, x, C.b, a.s);
+    if (level_f32(a, l + 1))
+        resid_restrict_pass<T, float>(L, C, a.nc, b, x, C.bf, first_into<float>(a, l + 1), a.s);
+    else
+        resid_restrict_pass<T, double>(L, C, a.nc, b, x, C.b, first_into<double>(a, l + 1), a.s);
     vcycle_rec(a, l + 1);
     bool cf32 = level_f32(a, l + 1);
     if (a.nu2 < 1) {
@@ -2123,11 +2272,13 @@ void vcycle_level0_rb(const VArgs& a, const double* b0, double* x0, T* b, T* x) 
     bool cf32 = level_f32(a, 1);
     unsigned gc = grid_for(C.N, RR_COARSE);
     if (cf32) {
-        if (nc == 3) k_resid_restrict_rb<T, float, 3><<<gc, RR_THREADS, 0, a.s>>>(v, b, x, C.grid, C.mask, C.bf);
-        else k_resid_restrict_rb<T, float, 1><<<gc, RR_THREADS, 0, a.s>>>(v, b, x, C.grid, C.mask, C.bf);
+        FirstV<float> F1 = first_into<float>(a, 1);
+        if (nc == 3) k_resid_restrict_rb<T, float, 3><<<gc, RR_THREADS, 0, a.s>>>(v, b, x, C.grid, C.mask, C.bf, F1);
+        else k_resid_restrict_rb<T, float, 1><<<gc, RR_THREADS, 0, a.s>>>(v, b, x, C.grid, C.mask, C.bf, F1);
     } else {
-        if (nc == 3) k_resid_restrict_rb<T, double, 3><<<gc, RR_THREADS, 0, a.s>>>(v, b, x, C.grid, C.mask, C.b);
-        else k_resid_restrict_rb<T, double, 1><<<gc, RR_THREADS, 0, a.s>>>(v, b, x, C.grid, C.mask, C.b);
+        FirstV<double> F1 = first_into<double>(a, 1);
+        if (nc == 3) k_resid_restrict_rb<T, double, 3><<<gc, RR_THREADS, 0, a.s>>>(v, b, x, C.grid, C.mask, C.b, F1);
+        else k_resid_restrict_rb<T, double, 1><<<gc, RR_THREADS, 0, a.s>>>(v, b, x, C.grid, C.mask, C.b, F1);
     }
     vcycle_rec(a, 1);
     if (cf32) up_leg_rb<T, float>(a, v, C.grid, C.xf, b, x, x0);
@@ -2236,9 +2387,10 @@ void mg_sweep_level0(const Level& L, int ncomp, bool f32, const void* b, void* x
 
 void mg_apply_level0(const Level& L, int ncomp, const double* x, double* y, hipStream_t s,
                      const int* gate) {
-    Level G = L;
-    G.gate = gate;
-    resid_pass<double>(G, ncomp, nullptr, x, y, s);
+    Rb0V v = rb0_view(L);
+    v.gate = gate;
+    if (ncomp == 3) k_apply0<3><<<grid_for(L.N), EB_BLOCK, 0, s>>>(v, x, y);
+    else k_apply0<1><<<grid_for(L.N), EB_BLOCK, 0, s>>>(v, x, y);
 }
 
 void op_visc_apply(const GeomV& g, double rho, double dt, const double* eta,
