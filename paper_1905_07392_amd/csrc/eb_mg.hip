@@ -983,6 +983,98 @@ __global__ void __launch_bounds__(RR_THREADS)
     }
 }
 
+// residual b - M x of level-0 cell (fi, fj, fk) (0 on a covered cell), every load first
+template <typename TF, int NC>
+__device__ __forceinline__ void rb_resid(const Rb0V& L, const TF* __restrict__ b,
+                                         const TF* __restrict__ x, int fi, int fj, int fk,
+                                         TF r[NC]) {
+    long N = L.N;
+    long f = cell_index(L.grid, fi, fj, fk);
+    long oth = (long)(1 - ((fi + fj + fk) & 1)) * (N >> 1);
+    long qf = rb_slot(N, fi, fj, fk, f);
+    TF bv[NC], xv[NC];
+#pragma unroll
+    for (int m = 0; m < NC; m++) {
+        bv[m] = b[m * N + qf];
+        xv[m] = x[m * N + qf];
+    }
+    TF K[6], dg, xn[6][NC];
+    long nb[6];
+    bool open = L.flag[f] != 0;
+    rb0_row_ld<TF, NC, true>(L, f, fi, fj, fk, x + oth, K, nb, dg, xn);
+#pragma unroll
+    for (int m = 0; m < NC; m++) r[m] = (TF)0;
+    if (!open) return;
+    TF acc[NC];
+#pragma unroll
+    for (int m = 0; m < NC; m++) acc[m] = (TF)0;
+#pragma unroll
+    for (int e = 0; e < 6; e++) {
+        TF kf = K[e];
+        if (kf == (TF)0 || nb[e] < 0) continue;
+#pragma unroll
+        for (int m = 0; m < NC; m++) acc[m] += kf * xn[e][m];
+    }
+#pragma unroll
+    for (int m = 0; m < NC; m++) r[m] = bv[m] - (dg * xv[m] - acc[m]);
+}
+
+// k_resid_restrict_rb after a pre-smoothing that ended with a colour-1 half sweep: the residual
+// of every colour-1 cell that sweep updated is zero in exact arithmetic (its row was just
+// solved with the current colour-0 neighbours), so it is taken as 0 and only colour-0 cells,
+// and colour-1 cells the sweep skipped, are evaluated.  A block handles RR_COARSE coarse cells
+// with one thread per colour-0 child (x fastest: the colour-0 children of consecutive coarse
+// cells are consecutive in the colour-split order); the thread also owns the colour-1 child
+// next to it in x.  The eight children are summed in the order q = 0..7 as before.
+constexpr int RR0_THREADS = 4 * RR_COARSE;
+template <typename TF, typename TC, int NC>
+__global__ void __launch_bounds__(RR0_THREADS)
+    k_resid_restrict_rb0(Rb0V L, const TF* __restrict__ b, const TF* __restrict__ x, GridV gc,
+                         const uint8_t* __restrict__ mc, TC* __restrict__ bc, FirstV<TC> F1) {
+    if (L.gate && *L.gate) return;
+    __shared__ TF rs[RR_COARSE * 8 * NC];
+    long Nc = (long)gc.n[0] * gc.n[1] * gc.n[2];
+    int cl = threadIdx.x & (RR_COARSE - 1);
+    int bq = (threadIdx.x / RR_COARSE) & 1, cq = threadIdx.x / (2 * RR_COARSE);
+    int a0 = (bq + cq) & 1;  // x bit of the colour-0 child in row (bq, cq)
+    unsigned blk = xcd_block();
+    long c = (long)blk * RR_COARSE + cl;
+    TF r0[NC], r1[NC];
+#pragma unroll
+    for (int m = 0; m < NC; m++) {
+        r0[m] = (TF)0;
+        r1[m] = (TF)0;
+    }
+    if (c < Nc) {
+        int ci, cj, ck;
+        cell_coords(gc, c, ci, cj, ck);
+        int fj = 2 * cj + bq, fk = 2 * ck + cq;
+        int f0i = 2 * ci + a0, f1i = 2 * ci + (1 - a0);
+        uint8_t fl1 = L.flag[cell_index(L.grid, f1i, fj, fk)];
+        rb_resid<TF, NC>(L, b, x, f0i, fj, fk, r0);
+        // a cut colour-1 child: the sweep may have skipped it, so evaluate it
+        if (fl1 == 1) rb_resid<TF, NC>(L, b, x, f1i, fj, fk, r1);
+    }
+    int q0 = a0 + 2 * bq + 4 * cq, q1 = (1 - a0) + 2 * bq + 4 * cq;
+#pragma unroll
+    for (int m = 0; m < NC; m++) {
+        rs[(cl * 8 + q0) * NC + m] = r0[m];
+        rs[(cl * 8 + q1) * NC + m] = r1[m];
+    }
+    __syncthreads();
+    if (threadIdx.x < RR_COARSE) {
+        long cc = (long)blk * RR_COARSE + threadIdx.x;
+        if (cc >= Nc) return;
+        TF sum[NC];
+#pragma unroll
+        for (int m = 0; m < NC; m++) sum[m] = (TF)0;
+        for (int q = 0; q < 8; q++)
+#pragma unroll
+            for (int m = 0; m < NC; m++) sum[m] += rs[(threadIdx.x * 8 + q) * NC + m];
+        rr_store<TF, TC, NC>(gc, Nc, cc, mc, sum, bc, F1);
+    }
+}
+
 // piecewise-constant prolongation onto the open cells of level 0 (colour-split storage)
 template <typename TC, typename TF, int NC>
 __global__ void k_prolong_rb(Rb0V L, GridV gc, const TC* __restrict__ ec, TF* __restrict__ x) {
@@ -2203,6 +2295,22 @@ void vcycle_rec(const VArgs& a, int l) {
     else vcycle_level<double>(a, l);
 }
 
+// level 0's residual restricted to level 1 (with level 1's fused first pass): after
+// pre-smoothing, which ends with a colour-1 half sweep, only colour-0 cells are evaluated
+template <typename T, typename TC>
+void resid_restrict_rb(const VArgs& a, const Rb0V& v, const Level& C, const T* b, const T* x,
+                       TC* bc, FirstV<TC> F1) {
+    unsigned gc = grid_for(C.N, RR_COARSE);
+    int nc = a.nc;
+    if (a.nu1 >= 1) {
+        if (nc == 3) k_resid_restrict_rb0<T, TC, 3><<<gc, RR0_THREADS, 0, a.s>>>(v, b, x, C.grid, C.mask, bc, F1);
+        else k_resid_restrict_rb0<T, TC, 1><<<gc, RR0_THREADS, 0, a.s>>>(v, b, x, C.grid, C.mask, bc, F1);
+    } else {
+        if (nc == 3) k_resid_restrict_rb<T, TC, 3><<<gc, RR_THREADS, 0, a.s>>>(v, b, x, C.grid, C.mask, bc, F1);
+        else k_resid_restrict_rb<T, TC, 1><<<gc, RR_THREADS, 0, a.s>>>(v, b, x, C.grid, C.mask, bc, F1);
+    }
+}
+
 // level 0's prolongation and post-smoothing: the prolongation of ec rides on the first pair of
 // half sweeps (a pass of its own only without post-smoothing); the last half sweep writes the
 // natural-order FP64 result x0
@@ -2270,16 +2378,8 @@ void vcycle_level0_rb(const VArgs& a, const double* b0, double* x0, T* b, T* x) 
         smooth_rb_pass<T>(L, nc, b, x, 1, a.s);
     }
     bool cf32 = level_f32(a, 1);
-    unsigned gc = grid_for(C.N, RR_COARSE);
-    if (cf32) {
-        FirstV<float> F1 = first_into<float>(a, 1);
-        if (nc == 3) k_resid_restrict_rb<T, float, 3><<<gc, RR_THREADS, 0, a.s>>>(v, b, x, C.grid, C.mask, C.bf, F1);
-        else k_resid_restrict_rb<T, float, 1><<<gc, RR_THREADS, 0, a.s>>>(v, b, x, C.grid, C.mask, C.bf, F1);
-    } else {
-        FirstV<double> F1 = first_into<double>(a, 1);
-        if (nc == 3) k_resid_restrict_rb<T, double, 3><<<gc, RR_THREADS, 0, a.s>>>(v, b, x, C.grid, C.mask, C.b, F1);
-        else k_resid_restrict_rb<T, double, 1><<<gc, RR_THREADS, 0, a.s>>>(v, b, x, C.grid, C.mask, C.b, F1);
-    }
+    if (cf32) resid_restrict_rb<T, float>(a, v, C, b, x, C.bf, first_into<float>(a, 1));
+    else resid_restrict_rb<T, double>(a, v, C, b, x, C.b, first_into<double>(a, 1));
     vcycle_rec(a, 1);
     if (cf32) up_leg_rb<T, float>(a, v, C.grid, C.xf, b, x, x0);
     else up_leg_rb<T, double>(a, v, C.grid, C.x, b, x, x0);
