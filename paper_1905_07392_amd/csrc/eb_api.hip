@@ -164,6 +164,7 @@ size_t carve(eb_ctx* c, char* base, bool dry) {
     c->ks = cv.take<double>(KS_COUNT);
     c->kst = cv.take<int>(3 * NSLOT);  // (state, count) per slot, then the iteration counters
     c->divs = cv.take<double>(NSLOT);
+    char* pack = cv.take<char>(MG_PACK_BYTES);
     // levels
     int m[3] = {g.n[0], g.n[1], g.n[2]};
     double h = g.h;
@@ -182,6 +183,7 @@ size_t carve(eb_ctx* c, char* base, bool dry) {
             L.alpha = cv.take<double>(L.N);
             for (int d = 0; d < 3; d++) L.ap[d] = cv.take<double>(face_count(L.grid, d));
         }
+        L.pack = pack;
         L.mask = cv.take<uint8_t>(L.N);
         for (int d = 0; d < 3; d++) L.K[d] = cv.take<double>(face_count(L.grid, d));
         L.S = cv.take<double>(L.N);

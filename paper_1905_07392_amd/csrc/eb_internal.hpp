@@ -116,6 +116,8 @@ inline unsigned grid_for(long n, int block = EB_BLOCK) {
 // ------------------------------------------------------------------------------------------
 // host-side level storage
 // ------------------------------------------------------------------------------------------
+constexpr size_t MG_PACK_BYTES = 65536;  // the tail kernel's LDS budget
+
 struct Level {
     GridV grid;
     long N;
@@ -129,6 +131,9 @@ struct Level {
     float* Df;
     double *x, *b, *r;  // 3 components each
     float *xf, *bf, *rf;
+    // the one-work-group tail's operator arrays in its LDS layout (MG_PACK_BYTES, shared by all
+    // levels; filled when an operator is built)
+    char* pack = nullptr;
     const int* gate = nullptr;
     // finest level only: what its operator was built from, so the smoother can recompute the
     // coefficients of regular cells instead of reading them (flag: 0 covered, 1 cut, 2 regular)

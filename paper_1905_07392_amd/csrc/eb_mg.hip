@@ -1131,7 +1131,7 @@ __global__ void k_from_rb(GridV g, long N, const TS* __restrict__ r, TD* __restr
 // ------------------------------------------------------------------------------------------
 constexpr int TAIL_MAXL = 8;
 constexpr int TAIL_THREADS = 256;
-constexpr size_t TAIL_LDS_BYTES = 65536;
+constexpr size_t TAIL_LDS_BYTES = MG_PACK_BYTES;
 
 struct TailArgs {
     int nl, nu1, nu2, nbottom;
@@ -1139,9 +1139,13 @@ struct TailArgs {
     double* x0;        // iterate of the first tail level (global, written back)
     const int* gate;
     const double* b0;  // right-hand side of the first tail level (global)
-    // LDS byte offsets per level: x, b, K[3], D, mask; and the first level's residual
+    // LDS byte offsets per level: x, b, K[3], D, mask; and the first level's residual.  The
+    // operator arrays (K, D, mask of every tail level) come first, in [0, nstatic), and are
+    // staged from pack, a copy with exactly that layout made when the operator is built
     unsigned ox[TAIL_MAXL], ob[TAIL_MAXL], oK[TAIL_MAXL][3], oD[TAIL_MAXL], om[TAIL_MAXL];
     unsigned orr;
+    unsigned nstatic;
+    const char* pack;
 };
 
 // residual b - M x at fine cell f (0 outside the open cells)
@@ -1425,24 +1429,39 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_vcycle_tail(TailArgs A) {
     extern __shared__ double lds_d[];
     char* lds = reinterpret_cast<char*>(lds_d);
     int nl = A.nl;
-    // stage the operators and the first right-hand side in LDS
-    for (int l = 0; l < nl; l++) {
-        const LevelV<double>& G = A.L[l];
-        for (int d = 0; d < 3; d++) {
-            long nf = face_count(G.grid, d);
-            double* dst = reinterpret_cast<double*>(lds + A.oK[l][d]);
-            for (long t = threadIdx.x; t < nf; t += blockDim.x) dst[t] = G.K[d][t];
-        }
-        double* Dd = reinterpret_cast<double*>(lds + A.oD[l]);
-        uint8_t* md = reinterpret_cast<uint8_t*>(lds + A.om[l]);
-        for (long t = threadIdx.x; t < G.N; t += blockDim.x) {
-            Dd[t] = G.D[t];
-            md[t] = G.mask[t];
-        }
-    }
+    // stage the operators (one contiguous copy of the pack) and the first right-hand side in
+    // LDS: every thread issues all of its loads, then stores them
     {
+        const uint4* __restrict__ ps = reinterpret_cast<const uint4*>(A.pack);
+        uint4* pd = reinterpret_cast<uint4*>(lds);
+        const double* __restrict__ bs = A.b0;
         double* bd = reinterpret_cast<double*>(lds + A.ob[0]);
-        for (long t = threadIdx.x; t < NC * A.L[0].N; t += blockDim.x) bd[t] = A.b0[t];
+        unsigned n16 = A.nstatic / 16, nb = NC * (unsigned)A.L[0].N;
+        constexpr int PS = 8, BS = 8;
+        uint4 pv[PS];
+        double bv[BS];
+#pragma unroll
+        for (int u = 0; u < PS; u++) {
+            unsigned t = u * blockDim.x + threadIdx.x;
+            if (t < n16) pv[u] = ps[t];
+        }
+#pragma unroll
+        for (int u = 0; u < BS; u++) {
+            unsigned t = u * blockDim.x + threadIdx.x;
+            if (t < nb) bv[u] = bs[t];
+        }
+#pragma unroll
+        for (int u = 0; u < PS; u++) {
+            unsigned t = u * blockDim.x + threadIdx.x;
+            if (t < n16) pd[t] = pv[u];
+        }
+#pragma unroll
+        for (int u = 0; u < BS; u++) {
+            unsigned t = u * blockDim.x + threadIdx.x;
+            if (t < nb) bd[t] = bv[u];
+        }
+        for (unsigned t = PS * blockDim.x + threadIdx.x; t < n16; t += blockDim.x) pd[t] = ps[t];
+        for (unsigned t = BS * blockDim.x + threadIdx.x; t < nb; t += blockDim.x) bd[t] = bs[t];
     }
     __syncthreads();
     auto lv = [&](int l) {
@@ -1603,24 +1622,55 @@ size_t tail_layout(const Level* lev, int nlev, int t, int nc, TailArgs* A) {
         off = (off + bytes + 15) & ~size_t(15);
         return (unsigned)o;
     };
+    // the operator arrays of every level first (the pack's layout), then the vectors
+    for (int l = t; l < nlev; l++) {
+        const Level& L = lev[l];
+        int q = l - t;
+        unsigned oK[3];
+        for (int d = 0; d < 3; d++) oK[d] = take(face_count(L.grid, d) * 8);
+        unsigned oD = take(L.N * 8), om = take(L.N);
+        if (A) {
+            for (int d = 0; d < 3; d++) A->oK[q][d] = oK[d];
+            A->oD[q] = oD;
+            A->om[q] = om;
+        }
+    }
+    if (A) A->nstatic = (unsigned)off;
     for (int l = t; l < nlev; l++) {
         const Level& L = lev[l];
         int q = l - t;
         unsigned ox = take(nc * L.N * 8), ob = take(nc * L.N * 8);
-        unsigned oK[3];
-        for (int d = 0; d < 3; d++) oK[d] = take(face_count(L.grid, d) * 8);
-        unsigned oD = take(L.N * 8), om = take(L.N);
         unsigned orr = q == 0 ? take(nc * L.N * 8) : 0;
         if (A) {
             A->ox[q] = ox;
             A->ob[q] = ob;
-            for (int d = 0; d < 3; d++) A->oK[q][d] = oK[d];
-            A->oD[q] = oD;
-            A->om[q] = om;
             if (q == 0) A->orr = orr;
         }
     }
     return off;
+}
+
+// the pack: the tail levels' K, D and mask copied into the LDS layout of tail_layout, once per
+// operator build (one work-group per array)
+constexpr int PACK_SEGS = 5 * TAIL_MAXL;
+struct PackArgs {
+    int nseg;
+    const char* src[PACK_SEGS];
+    unsigned dst[PACK_SEGS], bytes[PACK_SEGS];
+    char* pack;
+};
+__global__ void k_tail_pack(PackArgs P) {
+    int sg = blockIdx.x;
+    if (sg >= P.nseg) return;
+    const char* __restrict__ src = P.src[sg];
+    char* dst = P.pack + P.dst[sg];
+    unsigned n = P.bytes[sg];
+    if ((n & 7) == 0) {
+        for (unsigned t = threadIdx.x; t < n / 8; t += blockDim.x)
+            reinterpret_cast<double*>(dst)[t] = reinterpret_cast<const double*>(src)[t];
+    } else {
+        for (unsigned t = threadIdx.x; t < n; t += blockDim.x) dst[t] = src[t];
+    }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -2196,6 +2246,7 @@ void launch_tail(const VArgs& a) {
     T.x0 = a.lev[a.tail].x;
     T.gate = a.lev[a.tail].gate;
     T.b0 = a.lev[a.tail].b;
+    T.pack = a.lev[a.tail].pack;
     size_t bytes = tail_layout(a.lev, a.nlev, a.tail, a.nc, &T);
     if (a.nc == 3) k_vcycle_tail<3><<<1, TAIL_THREADS, bytes, a.s>>>(T);
     else k_vcycle_tail<1><<<1, TAIL_THREADS, bytes, a.s>>>(T);
@@ -2394,6 +2445,33 @@ void vcycle_rb(const VArgs& a, const double* b, double* x, T* brb, T* xrb) {
     vcycle_level0_rb<T>(a, b, x, brb, xrb);
 }
 
+void tail_pack(const Level* lev, int nlev, hipStream_t s) {
+    int t = tail_level(lev, nlev);
+    TailArgs A;
+    tail_layout(lev, nlev, t, 1, &A);
+    // a tail kernel runs only when its whole layout fits, so its operator part always does
+    if (A.nstatic > MG_PACK_BYTES || !lev[t].pack) return;
+    PackArgs P;
+    P.nseg = 0;
+    P.pack = lev[t].pack;
+    for (int l = t; l < nlev; l++) {
+        const Level& L = lev[l];
+        int q = l - t;
+        for (int d = 0; d < 3; d++) {
+            P.src[P.nseg] = reinterpret_cast<const char*>(L.K[d]);
+            P.dst[P.nseg] = A.oK[q][d];
+            P.bytes[P.nseg++] = (unsigned)(face_count(L.grid, d) * 8);
+        }
+        P.src[P.nseg] = reinterpret_cast<const char*>(L.D);
+        P.dst[P.nseg] = A.oD[q];
+        P.bytes[P.nseg++] = (unsigned)(L.N * 8);
+        P.src[P.nseg] = reinterpret_cast<const char*>(L.mask);
+        P.dst[P.nseg] = A.om[q];
+        P.bytes[P.nseg++] = (unsigned)L.N;
+    }
+    k_tail_pack<<<P.nseg, EB_BLOCK, 0, s>>>(P);
+}
+
 void finish_operator(Level* lev, int nlev, bool mixed, hipStream_t s) {
     int tail = tail_level(lev, nlev);
     for (int l = 1; l < nlev; l++) {
@@ -2414,6 +2492,7 @@ void finish_operator(Level* lev, int nlev, bool mixed, hipStream_t s) {
             k_to_float<<<grid_for(L.N), EB_BLOCK, 0, s>>>(L.N, L.D, L.Df);
         }
     }
+    tail_pack(lev, nlev, s);
 }
 
 }  // namespace
