@@ -1242,6 +1242,64 @@ __device__ __forceinline__ void wave_sweep(const WaveRow& r, int lane, const dou
         if (upd) x[m] = acc[m] / r.D;
 }
 
+// The coarsest solve (nbottom red-black pairs, then nbottom black-red pairs) on a 2 x 2 x 2
+// level.  There both faces of a direction d couple cell c to the same cell, c ^ (1 << d) (or
+// one face is a wall), so with lane L = c + 8 m holding component m of cell c (the
+// preconditioner's components are uncoupled) a half sweep needs three cross-lane exchanges,
+// L ^ 1, L ^ 2 and L ^ 4, instead of one per face and component.  Every update is wave_sweep's
+// (b plus the K x terms in face order, then / D), so the result is bit for bit the same.  On
+// entry lane c < 8 holds b[m] and x[m] of cell c (its row in r), and on return x[m] again.
+template <int NC>
+__device__ __forceinline__ void bottom_cube2(const WaveRow& r, int lane, const double b[NC],
+                                             double x[NC], int nbottom) {
+    int c = lane & 7, m = lane >> 3;
+    double K[6];
+    bool use[6];
+#pragma unroll
+    for (int f = 0; f < 6; f++) {
+        K[f] = __shfl(r.K[f], c, 64);
+        int nbf = __shfl(r.nb[f], c, 64);
+        use[f] = K[f] != 0.0 && nbf >= 0;
+    }
+    double D = __shfl(r.D, c, 64);
+    bool open = __shfl(r.open ? 1 : 0, c, 64) != 0;
+    int colour = __shfl(r.colour, c, 64);
+    double bb = 0.0, xx = 0.0;
+#pragma unroll
+    for (int q = 0; q < NC; q++) {
+        double tb = __shfl(b[q], c, 64), tx = __shfl(x[q], c, 64);
+        if (m == q) {
+            bb = tb;
+            xx = tx;
+        }
+    }
+    bool upd0 = open && colour == 0 && D > 0.0, upd1 = open && colour == 1 && D > 0.0;
+    auto half = [&](bool upd) {
+        double v[3];
+        v[0] = __shfl_xor(xx, 1, 64);
+        v[1] = __shfl_xor(xx, 2, 64);
+        v[2] = __shfl_xor(xx, 4, 64);
+        double acc = bb;
+#pragma unroll
+        for (int f = 0; f < 6; f++)
+            if (use[f]) acc += K[f] * v[f >> 1];
+        if (upd) xx = acc / D;
+    };
+    for (int s = 0; s < nbottom; s++) {
+        half(upd0);
+        half(upd1);
+    }
+    for (int s = 0; s < nbottom; s++) {
+        half(upd1);
+        half(upd0);
+    }
+#pragma unroll
+    for (int q = 0; q < NC; q++) {
+        double t = __shfl(xx, c + 8 * q, 64);
+        if (lane < 8) x[q] = t;
+    }
+}
+
 // levels [w0, w0 + nw) of the tail (each at most 64 cells) by wave 0: b of level w0 is read
 // from LDS, its correction x written back to LDS; same operations and order as the
 // barrier-separated version
@@ -1266,13 +1324,18 @@ __device__ __forceinline__ void wave_levels(const LevelV<double>* Lw, int nw, in
 #pragma unroll
     for (int v = 0; v < WAVE_MAXL; v++) {
         if (v == nw - 1) {
-            for (int s = 0; s < nbottom; s++) {
-                wave_sweep<NC>(R[v], lane, bs[v], xs[v], 0);
-                wave_sweep<NC>(R[v], lane, bs[v], xs[v], 1);
-            }
-            for (int s = 0; s < nbottom; s++) {
-                wave_sweep<NC>(R[v], lane, bs[v], xs[v], 1);
-                wave_sweep<NC>(R[v], lane, bs[v], xs[v], 0);
+            const GridV& gb = Lw[v].grid;
+            if (gb.n[0] == 2 && gb.n[1] == 2 && gb.n[2] == 2) {
+                bottom_cube2<NC>(R[v], lane, bs[v], xs[v], nbottom);
+            } else {
+                for (int s = 0; s < nbottom; s++) {
+                    wave_sweep<NC>(R[v], lane, bs[v], xs[v], 0);
+                    wave_sweep<NC>(R[v], lane, bs[v], xs[v], 1);
+                }
+                for (int s = 0; s < nbottom; s++) {
+                    wave_sweep<NC>(R[v], lane, bs[v], xs[v], 1);
+                    wave_sweep<NC>(R[v], lane, bs[v], xs[v], 0);
+                }
             }
         }
         if (v >= nw - 1) continue;
