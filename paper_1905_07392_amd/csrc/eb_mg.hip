@@ -1131,6 +1131,7 @@ __global__ void k_from_rb(GridV g, long N, const TS* __restrict__ r, TD* __restr
 // ------------------------------------------------------------------------------------------
 constexpr int TAIL_MAXL = 8;
 constexpr int TAIL_THREADS = 256;
+static_assert(TAIL_THREADS >= 3 * 64, "the in-wave levels need one wavefront per component");
 constexpr size_t TAIL_LDS_BYTES = MG_PACK_BYTES;
 
 struct TailArgs {
@@ -1300,13 +1301,13 @@ __device__ __forceinline__ void bottom_cube2(const WaveRow& r, int lane, const d
     }
 }
 
-// levels [w0, w0 + nw) of the tail (each at most 64 cells) by wave 0: b of level w0 is read
-// from LDS, its correction x written back to LDS; same operations and order as the
-// barrier-separated version
+// levels [w0, w0 + nw) of the tail (each at most 64 cells) by one wavefront (lane = cell; the
+// tail runs one wavefront per component): b of level w0 is read from LDS, its correction x
+// written back to LDS; same operations and order as the barrier-separated version
 template <int NC>
 __device__ __forceinline__ void wave_levels(const LevelV<double>* Lw, int nw, int nu1, int nu2, int nbottom,
                             const double* b0, double* x0) {
-    int lane = threadIdx.x;
+    int lane = threadIdx.x & 63;
     WaveRow R[WAVE_MAXL];
     double xs[WAVE_MAXL][NC], bs[WAVE_MAXL][NC];
 #pragma unroll
@@ -1585,10 +1586,13 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_vcycle_tail(TailArgs A) {
             for (int m = 0; m < NC; m++) bc[m * C.N + c] = C.mask[c] ? sm[m] / 8.0 : 0.0;
         }
         __syncthreads();
-        if (threadIdx.x < 64) {
+        // the in-wave levels: wave m runs component m (the components are uncoupled)
+        int wv = threadIdx.x >> 6;
+        if (wv < NC) {
             LevelV<double> Lw[WAVE_MAXL];
             for (int v = 0; v < WAVE_MAXL; v++) Lw[v] = lv(1 + (1 + v < nl ? v : 0));
-            wave_levels<NC>(Lw, nl - 1, A.nu1, A.nu2, A.nbottom, B(1), X(1));
+            long off = wv * A.L[1].N;
+            wave_levels<1>(Lw, nl - 1, A.nu1, A.nu2, A.nbottom, B(1) + off, X(1) + off);
         }
         __syncthreads();
         // prolongation of the coarse correction to the thread's open cells
@@ -1654,10 +1658,12 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_vcycle_tail(TailArgs A) {
         __syncthreads();
     }
     if (w0 < nl) {
-        if (threadIdx.x < 64) {
+        int wv = threadIdx.x >> 6;
+        if (wv < NC) {
             LevelV<double> Lw[WAVE_MAXL];
             for (int v = 0; v < WAVE_MAXL; v++) Lw[v] = lv(w0 + (w0 + v < nl ? v : 0));
-            wave_levels<NC>(Lw, nl - w0, A.nu1, A.nu2, A.nbottom, B(w0), X(w0));
+            long off = wv * A.L[w0].N;
+            wave_levels<1>(Lw, nl - w0, A.nu1, A.nu2, A.nbottom, B(w0) + off, X(w0) + off);
         }
         __syncthreads();
     }
