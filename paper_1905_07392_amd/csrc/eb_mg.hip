@@ -155,7 +155,9 @@ __device__ __forceinline__ void offdiag(const LevelV<T>& L, const T* __restrict_
 // is degenerate (it is not updated); PRO_OWN: only the latter.  The Gauss-Seidel update itself
 // does not read the cell's own value, so an updated cell needs no correction, and the sums are
 // bit for bit those of the separate prolongation (the same addition, in the same precision).
-enum { PRO_NONE = 0, PRO_OWN = 1, PRO_NBR = 2 };
+// (PRO_ZERO, for the colour-split finest level only: no prolongation; a cell that is not updated
+// is set to 0, so the pass before it need not zero this colour)
+enum { PRO_NONE = 0, PRO_OWN = 1, PRO_NBR = 2, PRO_ZERO = 3 };
 template <typename TC>
 struct ProV {
     GridV gc;
@@ -175,19 +177,20 @@ __device__ __forceinline__ long nb_parent(const GridV& gf, const GridV& gc, int 
 }
 
 // The corrections a fused prolongation adds to the six neighbour values of fine cell (i, j, k)
-// (0 for a missing or closed neighbour; open: the level's open-cell bytes).  In each direction
-// one neighbour shares the cell's coarse parent and the other lies in the adjacent parent, so
-// four coarse values are read.  nbr_load issues the loads (before anything waits on memory),
+// (0 where there is no neighbour).  The separate pass adds e only to open cells, but a closed
+// neighbour's value is never used: every face of a covered cell has aperture 0 (that is how
+// cells are classified), so its coupling K is 0, and on a coarse level a nonzero K is a sum of
+// open fine faces, whose cells make both coarse cells open.  In each direction one neighbour
+// shares the cell's coarse parent and the other lies in the adjacent parent, so four coarse
+// values are read.  nbr_load issues the loads (before anything waits on memory),
 // nbr_corrections forms the corrections once they are needed.
 template <int NC, typename TC>
 struct NbrE {
     TC e0[NC], eo[3][NC];
-    uint8_t fo[6];
 };
 template <int NC, typename TC>
 __device__ __forceinline__ void nbr_load(const GridV& gf, const ProV<TC>& P, int i, int j, int k,
-                                         const long nb[6], const uint8_t* __restrict__ open,
-                                         NbrE<NC, TC>& E) {
+                                         const long nb[6], NbrE<NC, TC>& E) {
     long Nc = (long)P.gc.n[0] * P.gc.n[1] * P.gc.n[2];
     const TC* __restrict__ ec = P.ec;
     int q[3] = {i, j, k};
@@ -201,8 +204,6 @@ __device__ __forceinline__ void nbr_load(const GridV& gf, const ProV<TC>& P, int
 #pragma unroll
         for (int m = 0; m < NC; m++) E.eo[d][m] = ec[m * Nc + po];
     }
-#pragma unroll
-    for (int f = 0; f < 6; f++) E.fo[f] = nb[f] >= 0 ? open[nb[f]] : (uint8_t)0;
 }
 template <typename T, int NC, typename TC>
 __device__ __forceinline__ void nbr_corrections(const NbrE<NC, TC>& E, int i, int j, int k,
@@ -213,7 +214,7 @@ __device__ __forceinline__ void nbr_corrections(const NbrE<NC, TC>& E, int i, in
 #pragma unroll
         for (int side = 0; side < 2; side++) {
             int f = 2 * d + side;
-            bool on = nb[f] >= 0 && E.fo[f] != 0;
+            bool on = nb[f] >= 0;
             bool outer = side == (q[d] & 1);
 #pragma unroll
             for (int m = 0; m < NC; m++)
@@ -263,7 +264,7 @@ __device__ __forceinline__ void smooth_cell(const LevelV<T>& L, const T* __restr
     T pe[6][NC];
     NbrE<NC, TC> E;
     if (PRO == PRO_NBR) {
-        nbr_load<NC, TC>(g, *P, i, j, k, nb, L.mask, E);
+        nbr_load<NC, TC>(g, *P, i, j, k, nb, E);
         nbr_corrections<T, NC, TC>(E, i, j, k, nb, pe);
     }
     if (!msk) return;
@@ -700,7 +701,8 @@ __device__ __forceinline__ void smooth_rb_cell(const Rb0V& L, const T* __restric
     T K[6], dg, xn[6][NC];
     long nb[6];
     long Nc = 0;
-    if (PRO != PRO_NONE) Nc = (long)P->gc.n[0] * P->gc.n[1] * P->gc.n[2];
+    constexpr bool PROL = PRO == PRO_OWN || PRO == PRO_NBR;
+    if (PROL) Nc = (long)P->gc.n[0] * P->gc.n[1] * P->gc.n[2];
     T pe[6][NC];
     NbrE<NC, TC> E;
     if (PRO == PRO_NBR) {
@@ -713,12 +715,15 @@ __device__ __forceinline__ void smooth_rb_cell(const Rb0V& L, const T* __restric
                 q[d] += side ? 1 : -1;
                 nb[2 * d + side] = cell_at(L.grid, q[0], q[1], q[2]);
             }
-        nbr_load<NC, TC>(L.grid, *P, i, j, k, nb, L.flag, E);
+        nbr_load<NC, TC>(L.grid, *P, i, j, k, nb, E);
     }
     bool upd = rb0_row_ld<T, NC, true>(L, c, i, j, k, x + oth, K, nb, dg, xn);
     if (PRO == PRO_NBR) nbr_corrections<T, NC, TC>(E, i, j, k, nb, pe);
     if (!upd) {
-        if (PRO != PRO_NONE && L.flag[c] != 0) {
+        if (PRO == PRO_ZERO) {
+#pragma unroll
+            for (int m = 0; m < NC; m++) x[m * N + own] = (T)0;
+        } else if (PROL && L.flag[c] != 0) {
             long pc = cell_index(P->gc, i >> 1, j >> 1, k >> 1);
 #pragma unroll
             for (int m = 0; m < NC; m++) x[m * N + own] += (T)P->ec[m * Nc + pc];
@@ -835,7 +840,8 @@ __global__ void k_smooth_first_rb(Rb0V L, const T* __restrict__ b, T* __restrict
 }
 
 // k_smooth_first_rb fused with the conversion of the right-hand side: reads b in natural
-// order (FP64), stores its colour-split copy (precision T) and the first iterate
+// order (FP64), stores its colour-split copy (precision T) and the first iterate's colour 0;
+// colour 1 is left to the colour-1 half sweep that follows (PRO_ZERO: it writes every cell)
 template <typename T, int NC>
 __global__ void k_smooth_first_rb_from(Rb0V L, const double* __restrict__ bnat,
                                        T* __restrict__ b, T* __restrict__ x) {
@@ -862,7 +868,7 @@ __global__ void k_smooth_first_rb_from(Rb0V L, const double* __restrict__ bnat,
 #pragma unroll
     for (int m = 0; m < NC; m++) {
         b[m * N + u] = bv[m];
-        x[m * N + u] = upd ? bv[m] * inv : (T)0;
+        if (col == 0) x[m * N + u] = upd ? bv[m] * inv : (T)0;
     }
 }
 
@@ -2492,9 +2498,14 @@ void vcycle_level0_rb(const VArgs& a, const double* b0, double* x0, T* b, T* x) 
         if (t == 0) {
             if (nc == 3) k_smooth_first_rb_from<T, 3><<<g, EB_BLOCK, 0, a.s>>>(v, b0, b, x);
             else k_smooth_first_rb_from<T, 1><<<g, EB_BLOCK, 0, a.s>>>(v, b0, b, x);
-        } else {
-            smooth_rb_pass<T>(L, nc, b, x, 0, a.s);
+            // colour 1 of the first iterate is still unset: this sweep writes all of it
+            ProV<T> Z{L.grid, nullptr};
+            unsigned gh = grid_for(L.N / 2);
+            if (nc == 3) k_smooth_rb_pro<T, T, 3, PRO_ZERO><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, 1, Z);
+            else k_smooth_rb_pro<T, T, 1, PRO_ZERO><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, 1, Z);
+            continue;
         }
+        smooth_rb_pass<T>(L, nc, b, x, 0, a.s);
         smooth_rb_pass<T>(L, nc, b, x, 1, a.s);
     }
     bool cf32 = level_f32(a, 1);
