@@ -97,9 +97,10 @@ typedef struct {
 typedef struct {
     int precision;        /* EB_FP64 or EB_MIXED */
     double rtol_visc, rtol_mac, rtol_proj;  /* max-norm relative residual targets */
-    int max_iter;         /* per solve */
-    int nu1, nu2;         /* pre/post red-black Gauss-Seidel pairs per level */
-    int nbottom;          /* sweep pairs on the coarsest level */
+    int max_iter;         /* per solve (<= 0: the default 400) */
+    int nu1, nu2;         /* pre/post red-black Gauss-Seidel pairs per level (0: none on
+                             that leg; negative: the default 2) */
+    int nbottom;          /* sweep pairs on the coarsest level (<= 0: the default 16) */
     double force[3];      /* body force per unit volume (host values) */
 } eb_step_opts;
 

@@ -482,8 +482,8 @@ struct SolveCfg {
 SolveCfg cfg_of(const eb_step_opts* o) {
     SolveCfg k;
     k.mixed = o && o->precision == EB_MIXED;
-    k.nu1 = o && o->nu1 > 0 ? o->nu1 : 2;
-    k.nu2 = o && o->nu2 > 0 ? o->nu2 : 2;
+    k.nu1 = o && o->nu1 >= 0 ? o->nu1 : 2;
+    k.nu2 = o && o->nu2 >= 0 ? o->nu2 : 2;
     k.nbottom = o && o->nbottom > 0 ? o->nbottom : 16;
     k.max_iter = o && o->max_iter > 0 ? o->max_iter : 400;
     return k;

@@ -143,6 +143,35 @@ def test_vcycles_match(s32):
         assert rel_l2(cpu(got3)[j], ref3[j], P.open) <= 1e-12
 
 
+@pytest.mark.parametrize("nu1,nu2,nbottom",
+                         [(1, 1, 16), (0, 2, 16), (2, 0, 16), (0, 1, 8), (2, 2, 8), (3, 1, 4)])
+def test_vcycle_smoothing_variants(s32, nu1, nu2, nbottom):
+    """V(nu1, nu2) cycles other than V(2, 2): no pre- or no post-smoothing take the separate
+    zero-fill, restriction and prolongation passes instead of the fused ones, and an odd number
+    of pairs changes which half sweep carries the fused prolongation and the final reorder."""
+    P = s32
+    oopts = P.O.make_opts(P.w, nu1=nu1, nu2=nu2, nbottom=nbottom)
+    gopts = P.opts
+    keep = (gopts.nu1, gopts.nu2, gopts.nbottom)
+    gopts.nu1, gopts.nu2, gopts.nbottom = nu1, nu2, nbottom
+    try:
+        print(f"[parity] vcycle nu1={nu1} nu2={nu2} nbottom={nbottom}", flush=True)
+        r = I.random_field(P.og.shape, 31) * P.open
+        ref = P.og.vcycle(0, r, oopts, beta=0.37)
+        got = P.api.eb_mg_vcycle(P.ctx, P.api.EB_SYS_POISSON, P.dev(r), gopts, beta=0.37)
+        assert rel_l2(cpu(got), ref, P.open) <= 1e-12
+        u0, _ = P.O.prepare_state(P.w, P.og, P.oopts)
+        eta, eta_eb = P.og.viscosity(u0, P.orheo)
+        r3 = I.random_field((3,) + P.og.shape, 32) * P.open
+        ref3 = P.og.vcycle(1, r3, oopts, rho=P.w.rho, dt=P.w.dt, eta=eta, eta_eb=eta_eb)
+        got3 = P.api.eb_mg_vcycle(P.ctx, P.api.EB_SYS_VISC, P.dev(r3), gopts, rho=P.w.rho,
+                                  dt=P.w.dt, eta=P.dev(eta), eta_eb=P.dev(eta_eb))
+        for j in range(3):
+            assert rel_l2(cpu(got3)[j], ref3[j], P.open) <= 1e-12
+    finally:
+        gopts.nu1, gopts.nu2, gopts.nbottom = keep
+
+
 def test_fp32_sweep_needs_an_fp32_finest_level(s32):
     """A mixed hierarchy keeps levels below 64^3 cells in FP64, so on the 32^3 box the FP32
     sweep entry point has no FP32 operator to run and says so."""
