@@ -229,6 +229,29 @@ __global__ void k_divergence(GeomV g, const double* __restrict__ fx,
 }
 
 // convective flux divergence -(1/(alpha h)) sum_f A_f w_f u_up (upwinded by w_f)
+// branch (0 zero, 1 central, 2 twice left, 3 twice right) and value of the
+// monotonised-central slope from the three values along a line; ok: both neighbours exist and
+// are open.  Together they are mc_branch / mc_eval (and mc_slope) on values already loaded.
+__device__ __forceinline__ int mc_code(bool ok, double ul, double uc, double ur) {
+    if (!ok) return 0;
+    double dl = uc - ul, dr = ur - uc, dc = 0.5 * (ur - ul);
+    if (dl * dr <= 0.0) return 0;
+    double a = fabs(dc), b = 2.0 * fabs(dl), e = 2.0 * fabs(dr);
+    if (a <= b && a <= e) return 1;
+    return b <= e ? 2 : 3;
+}
+__device__ __forceinline__ double mc_val(int code, bool both, double ul, double uc, double ur) {
+    if (code == 0 || !both) return 0.0;
+    if (code == 1) return 0.5 * (ur - ul);
+    return code == 2 ? 2.0 * (uc - ul) : 2.0 * (ur - uc);
+}
+
+// The convective term D^C of Eq. divergence_conservative for one cell: the six faces' upwind
+// states from the extrapolations u +- slope/2 of the cells on either side.  Each thread loads
+// its cell's five-cell line in every direction once (the cell, its neighbours and theirs) and
+// forms the three slopes its two faces in that direction need, instead of every slope
+// reloading its own stencil.  The slope branches are recorded (own cell) or replayed through
+// sw like slope_sw, and every sum is in the order of the face loop, so D^C is unchanged.
 __global__ void k_conv_dc(GeomV g, const double* __restrict__ u, const double* __restrict__ fx,
                           const double* __restrict__ fy, const double* __restrict__ fz,
                           double* __restrict__ DC, SwitchV sw) {
@@ -244,35 +267,73 @@ __global__ void k_conv_dc(GeomV g, const double* __restrict__ u, const double* _
     cell_coords(g.grid, c, i, j0, k);
     const double* fo[3] = {fx, fy, fz};
     double acc[3] = {0.0, 0.0, 0.0};
-    for (int d = 0; d < 3; d++)
+    for (int d = 0; d < 3; d++) {
+        // the line c-2 .. c+2 along d (index -1 past a wall), its open flags and values
+        long id[5];
+        bool ex[5], op[5];
+        double uv[3][5];
+#pragma unroll
+        for (int p = 0; p < 5; p++) {
+            int q[3] = {i, j0, k};
+            q[d] += p - 2;
+            id[p] = p == 2 ? c : cell_at(g.grid, q[0], q[1], q[2]);
+        }
+#pragma unroll
+        for (int p = 0; p < 5; p++) {
+            ex[p] = id[p] >= 0;
+            op[p] = p == 2 ? true : (ex[p] && g.alpha[ex[p] ? id[p] : c] > 0.0);
+#pragma unroll
+            for (int m = 0; m < 3; m++) uv[m][p] = ex[p] ? u[(long)m * N + id[p]] : 0.0;
+        }
+        // slopes at positions 1, 2, 3 (cells c-1, c, c+1) of each component
+        double sl[3][3];
+#pragma unroll
+        for (int s3 = 0; s3 < 3; s3++) {
+            int p = s3 + 1;
+            bool both = ex[p - 1] && ex[p + 1];
+            bool ok = both && op[p - 1] && op[p + 1];
+#pragma unroll
+            for (int m = 0; m < 3; m++) {
+                double ul = uv[m][p - 1], uc = uv[m][p], ur = uv[m][p + 1];
+                if (sw.mode == 0 || !ex[p]) {
+                    sl[m][s3] = mc_val(mc_code(ok, ul, uc, ur), both, ul, uc, ur);
+                    continue;
+                }
+                long at = (long)(3 * m + d) * N + id[p];
+                int code = sw.mode == 2 ? (int)sw.slope[at] : mc_code(ok, ul, uc, ur);
+                if (sw.mode == 1 && p == 2) sw.slope[at] = (uint8_t)code;
+                sl[m][s3] = mc_val(code, both, ul, uc, ur);
+            }
+        }
         for (int side = -1; side <= 1; side += 2) {
             int f[3] = {i, j0, k};
             if (side > 0) f[d] += 1;
             long fi = face_index(g.grid, d, f[0], f[1], f[2]);
             double A = g.ap[d][fi];
             if (A == 0.0) continue;
-            long lo, hi;
-            face_cells(g.grid, d, f[0], f[1], f[2], lo, hi);
+            // lo and hi: positions 1 and 2 (side -1) or 2 and 3 (side +1)
+            int pl = side < 0 ? 1 : 2, ph = pl + 1;
+            bool lo_ok = ex[pl], hi_ok = ex[ph];
             double w = fo[d][fi];
             int ups = 0;  // upwind side by the face velocity: 1 left, 2 right, 3 the mean
-            if (lo >= 0 && hi >= 0) {
+            if (lo_ok && hi_ok) {
                 if (sw.mode == 2) ups = sw.tr[d][fi];
                 else ups = w > 0.0 ? 1 : (w < 0.0 ? 2 : 3);
                 if (sw.mode == 1) sw.tr[d][fi] = (uint8_t)ups;
             }
-            for (int j = 0; j < 3; j++) {
+            for (int m = 0; m < 3; m++) {
                 double up;
-                if (lo < 0 || hi < 0) {
-                    up = g.wall[2 * d + (lo >= 0)][j];
+                if (!lo_ok || !hi_ok) {
+                    up = g.wall[2 * d + (lo_ok ? 1 : 0)][m];
                 } else {
-                    const double* uj = u + (long)j * N;
-                    double uL = uj[lo] + 0.5 * slope_sw(g, uj, lo, d, j, sw);
-                    double uR = uj[hi] - 0.5 * slope_sw(g, uj, hi, d, j, sw);
+                    double uL = uv[m][pl] + 0.5 * sl[m][pl - 1];
+                    double uR = uv[m][ph] - 0.5 * sl[m][ph - 1];
                     up = ups == 1 ? uL : (ups == 2 ? uR : 0.5 * (uL + uR));
                 }
-                acc[j] += side * A * w * up;
+                acc[m] += side * A * w * up;
             }
         }
+    }
     int cq = g.cutid[c];
     if (cq >= 0) {
         int nc = g.ncut;
