@@ -120,6 +120,30 @@ __global__ void k_transpose_dc(GeomV g, const double* __restrict__ u,
     cell_coords(g.grid, c, i, j0, k);
     double h = g.grid.h;
     int q = g.cutid[c];
+    // every value the six faces need, loaded once: apertures, neighbours' viscosity and normal
+    // velocity, and the two tangential gradient entries of the cell and of each neighbour
+    long nb[6];
+    double A[6], en[6], un[6], uc[3], gc[3][3], gn[6][3];
+    double ec = eta[c];
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        uc[d] = u[(long)d * N + c];
+#pragma unroll
+        for (int jj = 0; jj < 3; jj++) gc[jj][d] = jj == d ? 0.0 : G9[(jj * 3 + d) * N + c];
+#pragma unroll
+        for (int side = 0; side < 2; side++) {
+            int f[3] = {i, j0, k};
+            if (side) f[d] += 1;
+            int fs = 2 * d + side;
+            A[fs] = g.ap[d][face_index(g.grid, d, f[0], f[1], f[2])];
+            nb[fs] = nbr(g.grid, i, j0, k, d, side ? 1 : -1);
+            long n = nb[fs] >= 0 ? nb[fs] : c;
+            en[fs] = eta[n];
+            un[fs] = u[(long)d * N + n];
+#pragma unroll
+            for (int jj = 0; jj < 3; jj++) gn[fs][jj] = jj == d ? 0.0 : G9[(jj * 3 + d) * N + n];
+        }
+    }
     double ng = 0.0;
     if (q >= 0) {
         int nc = g.ncut;
@@ -128,31 +152,27 @@ __global__ void k_transpose_dc(GeomV g, const double* __restrict__ u,
     for (int j = 0; j < 3; j++) {
         double acc = 0.0;
         for (int d = 0; d < 3; d++) {
-            const double* ud = u + (long)d * N;
             for (int side = -1; side <= 1; side += 2) {
-                int f[3] = {i, j0, k};
-                if (side > 0) f[d] += 1;
-                double A = g.ap[d][face_index(g.grid, d, f[0], f[1], f[2])];
-                if (A == 0.0) continue;
-                long nb = nbr(g.grid, i, j0, k, d, side);
+                int fs = 2 * d + (side > 0);
+                if (A[fs] == 0.0) continue;
                 double F;
-                if (nb >= 0) {
-                    double ef = 0.5 * (eta[c] + eta[nb]);
+                if (nb[fs] >= 0) {
+                    double ef = 0.5 * (ec + en[fs]);
                     double der;
                     if (j == d)
-                        der = side > 0 ? (ud[nb] - ud[c]) / h : (ud[c] - ud[nb]) / h;
+                        der = side > 0 ? (un[fs] - uc[d]) / h : (uc[d] - un[fs]) / h;
                     else
-                        der = 0.5 * (G9[(j * 3 + d) * N + c] + G9[(j * 3 + d) * N + nb]);
+                        der = 0.5 * (gc[j][d] + gn[fs][j]);
                     F = ef * der;
                 } else {
                     double der = 0.0;
                     if (j == d) {
                         double uw = g.wall[2 * d + (side > 0)][d];
-                        der = side > 0 ? (uw - ud[c]) / (0.5 * h) : (ud[c] - uw) / (0.5 * h);
+                        der = side > 0 ? (uw - uc[d]) / (0.5 * h) : (uc[d] - uw) / (0.5 * h);
                     }
-                    F = eta[c] * der;
+                    F = ec * der;
                 }
-                acc += side * A * F;
+                acc += side * A[fs] * F;
             }
         }
         if (q >= 0) acc -= g.aeb[q] * eta_eb[q] * g.nrm[(long)j * g.ncut + q] * ng;
