@@ -516,12 +516,7 @@ __global__ void k_coarsen_alpha(GridV gc, GridV gf, const double* af, double* ac
     long Nc = (long)gc.n[0] * gc.n[1] * gc.n[2];
     long c = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (c >= Nc) return;
-    int i, j, k;
-    cell_coords(gc, c, i, j, k);
-    double s = 0.0;
-    for (int q = 0; q < 8; q++)
-        s += af[cell_index(gf, 2 * i + (q & 1), 2 * j + ((q >> 1) & 1), 2 * k + (q >> 2))];
-    ac[c] = s / 8.0;
+    ac[c] = coarsen_cell_value(gc, gf, af, c);
 }
 
 __global__ void k_coarsen_face(GridV gc, GridV gf, int d, const double* ff, double* fc,
@@ -529,22 +524,7 @@ __global__ void k_coarsen_face(GridV gc, GridV gf, int d, const double* ff, doub
     long nf = face_count(gc, d);
     long f = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (f >= nf) return;
-    int m0 = gc.n[0] + (d == 0), m1 = gc.n[1] + (d == 1);
-    int q[3];
-    q[0] = (int)(f % m0);
-    long r = f / m0;
-    q[1] = (int)(r % m1);
-    q[2] = (int)(r / m1);
-    int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-    double s = 0.0;
-    for (int o = 0; o < 4; o++) {
-        int p[3];
-        p[d] = 2 * q[d];
-        p[t1] = 2 * q[t1] + (o & 1);
-        p[t2] = 2 * q[t2] + (o >> 1);
-        s += ff[face_index(gf, d, p[0], p[1], p[2])];
-    }
-    fc[f] = s * scale;
+    fc[f] = coarsen_face_value(gc, gf, d, ff, f, scale);
 }
 
 __global__ void k_mask(long N, const double* alpha, uint8_t* mask) {
@@ -607,13 +587,3 @@ void level_mask(Level& L, hipStream_t s) {
     k_mask<<<grid_for(L.N), EB_BLOCK, 0, s>>>(L.N, L.alpha, L.mask);
 }
 
-// coarse face coefficients for the multigrid operators share the face-averaging kernel
-void level_coarsen_faces(const GridV& gc, const GridV& gf, int d, const double* ff, double* fc,
-                         double scale, hipStream_t s) {
-    k_coarsen_face<<<grid_for(face_count(gc, d)), EB_BLOCK, 0, s>>>(gc, gf, d, ff, fc, scale);
-}
-void level_coarsen_cells(const GridV& gc, const GridV& gf, const double* f, double* c,
-                         hipStream_t s) {
-    long Nc = (long)gc.n[0] * gc.n[1] * gc.n[2];
-    k_coarsen_alpha<<<grid_for(Nc), EB_BLOCK, 0, s>>>(gc, gf, f, c);
-}

@@ -99,6 +99,37 @@ __host__ __device__ inline void cell_coords(const GridV& g, long c, int& i, int&
     k = (int)k2;
 }
 
+// coarse face f of direction d: scale x the sum of the four fine faces it covers (o = 0..3)
+__device__ inline double coarsen_face_value(const GridV& gc, const GridV& gf, int d,
+                                            const double* ff, long f, double scale) {
+    int m0 = gc.n[0] + (d == 0), m1 = gc.n[1] + (d == 1);
+    int q[3];
+    q[0] = (int)(f % m0);
+    long r = f / m0;
+    q[1] = (int)(r % m1);
+    q[2] = (int)(r / m1);
+    int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+    double s = 0.0;
+    for (int o = 0; o < 4; o++) {
+        int p[3];
+        p[d] = 2 * q[d];
+        p[t1] = 2 * q[t1] + (o & 1);
+        p[t2] = 2 * q[t2] + (o >> 1);
+        s += ff[face_index(gf, d, p[0], p[1], p[2])];
+    }
+    return s * scale;
+}
+// coarse cell c: the mean of its eight children (q = 0..7)
+__device__ inline double coarsen_cell_value(const GridV& gc, const GridV& gf, const double* af,
+                                            long c) {
+    int i, j, k;
+    cell_coords(gc, c, i, j, k);
+    double s = 0.0;
+    for (int q = 0; q < 8; q++)
+        s += af[cell_index(gf, 2 * i + (q & 1), 2 * j + ((q >> 1) & 1), 2 * k + (q >> 2))];
+    return s / 8.0;
+}
+
 // Work-group index remapped so that each of the 8 XCDs, which receive work-groups round-robin,
 // processes one contiguous range of tiles: vertically neighbouring rows and planes of a stencil
 // then share that XCD's L2 instead of being fetched again by another XCD.
@@ -178,10 +209,6 @@ void geom_wall_stencil(const GeomV& g, double* dd, int* sidx, double* sw, int* n
                        int* err_dev, hipStream_t s);
 void level_coarsen_geometry(const Level& F, Level& C, hipStream_t s);
 void level_mask(Level& L, hipStream_t s);
-void level_coarsen_faces(const GridV& gc, const GridV& gf, int d, const double* ff, double* fc,
-                         double scale, hipStream_t s);
-void level_coarsen_cells(const GridV& gc, const GridV& gf, const double* f, double* c,
-                         hipStream_t s);
 
 // pointwise and stencil operators
 void op_wall_grad(const GeomV& g, const double* u, double* gw, hipStream_t s);

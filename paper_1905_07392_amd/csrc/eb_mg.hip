@@ -86,19 +86,12 @@ __global__ void k_S_visc(GeomV g, double rho, double dt, const double* __restric
     S[c] = v;
 }
 
-__global__ void k_diag(GridV g, const double* __restrict__ Kx, const double* __restrict__ Ky,
-                       const double* __restrict__ Kz, const double* __restrict__ S,
-                       const uint8_t* __restrict__ mask, double* __restrict__ D) {
-    long N = (long)g.n[0] * g.n[1] * g.n[2];
-    long c = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    if (c >= N) return;
-    if (!mask[c]) {
-        D[c] = 0.0;
-        return;
-    }
+// diagonal of cell c: S plus the six face coefficients (0 on a closed cell)
+__device__ __forceinline__ double diag_value(const GridV& g, const double* const K[3],
+                                             const double* S, const uint8_t* mask, long c) {
+    if (!mask[c]) return 0.0;
     int i, j, k;
     cell_coords(g, c, i, j, k);
-    const double* K[3] = {Kx, Ky, Kz};
     double s = S ? S[c] : 0.0;
     for (int d = 0; d < 3; d++) {
         int q[3] = {i, j, k};
@@ -106,7 +99,48 @@ __global__ void k_diag(GridV g, const double* __restrict__ Kx, const double* __r
         q[d] += 1;
         s += K[d][face_index(g, d, q[0], q[1], q[2])];
     }
-    D[c] = s;
+    return s;
+}
+
+__global__ void k_diag(GridV g, const double* __restrict__ Kx, const double* __restrict__ Ky,
+                       const double* __restrict__ Kz, const double* __restrict__ S,
+                       const uint8_t* __restrict__ mask, double* __restrict__ D) {
+    long N = (long)g.n[0] * g.n[1] * g.n[2];
+    long c = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (c >= N) return;
+    const double* K[3] = {Kx, Ky, Kz};
+    D[c] = diag_value(g, K, S, mask, c);
+}
+
+// One operator-build launch per level: the coarse level's face coefficients (scale x the four
+// fine faces) and cell terms (mean of the eight children) from the fine level, and the fine
+// level's diagonal, which is complete by then.  Threads are dealt to the five parts in turn.
+struct CoarsenArgs {
+    GridV gc, gf;
+    const double* Kf[3];
+    double* Kc[3];
+    const double* Sf;
+    double* Sc;
+    double scale;
+    const uint8_t* maskf;
+    double* Df;
+    long n[5];  // coarse faces per direction, coarse cells, fine cells
+};
+__global__ void k_coarsen_level(CoarsenArgs A) {
+    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    for (int d = 0; d < 3; d++) {
+        if (t < A.n[d]) {
+            A.Kc[d][t] = coarsen_face_value(A.gc, A.gf, d, A.Kf[d], t, A.scale);
+            return;
+        }
+        t -= A.n[d];
+    }
+    if (t < A.n[3]) {
+        A.Sc[t] = coarsen_cell_value(A.gc, A.gf, A.Sf, t);
+        return;
+    }
+    t -= A.n[3];
+    if (t < A.n[4]) A.Df[t] = diag_value(A.gf, A.Kf, A.Sf, A.maskf, t);
 }
 
 __global__ void k_to_float(long n, const double* __restrict__ a, float* __restrict__ b) {
@@ -292,53 +326,6 @@ __device__ __forceinline__ void smooth_cell(const LevelV<T>& L, const T* __restr
     for (int m = 0; m < NC; m++) x[m * L.N + c] = acc[m] / dg;
 }
 
-// r = b - M x at cell c (b null: r = M x)
-template <typename T, int NC>
-__device__ __forceinline__ void resid_cell(const LevelV<T>& L, const T* __restrict__ b,
-                                           const T* __restrict__ x, T* __restrict__ r, long c) {
-    if (!L.mask[c]) {
-#pragma unroll
-        for (int m = 0; m < NC; m++) r[m * L.N + c] = (T)0;
-        return;
-    }
-    int i, j, k;
-    cell_coords(L.grid, c, i, j, k);
-    T acc[NC];
-#pragma unroll
-    for (int m = 0; m < NC; m++) acc[m] = (T)0;
-    offdiag<T, NC>(L, x, i, j, k, acc);
-    T dg = L.D[c];
-#pragma unroll
-    for (int m = 0; m < NC; m++) {
-        T mx = dg * x[m * L.N + c] - acc[m];
-        r[m * L.N + c] = b ? b[m * L.N + c] - mx : mx;
-    }
-}
-
-// coarse right-hand side: mean of the eight children (rows are already alpha-weighted)
-template <typename TF, typename TC, int NC>
-__device__ __forceinline__ void restrict_cell(const GridV& gf, const GridV& gc,
-                                              const uint8_t* __restrict__ mf,
-                                              const uint8_t* __restrict__ mc,
-                                              const TF* __restrict__ rf, TC* __restrict__ bc,
-                                              long c) {
-    long Nc = (long)gc.n[0] * gc.n[1] * gc.n[2];
-    long Nf = (long)gf.n[0] * gf.n[1] * gf.n[2];
-    int i, j, k;
-    cell_coords(gc, c, i, j, k);
-    TF s[NC];
-#pragma unroll
-    for (int m = 0; m < NC; m++) s[m] = (TF)0;
-    for (int q = 0; q < 8; q++) {
-        long f = cell_index(gf, 2 * i + (q & 1), 2 * j + ((q >> 1) & 1), 2 * k + (q >> 2));
-        if (!mf[f]) continue;
-#pragma unroll
-        for (int m = 0; m < NC; m++) s[m] += rf[m * Nf + f];
-    }
-#pragma unroll
-    for (int m = 0; m < NC; m++) bc[m * Nc + c] = mc[c] ? (TC)(s[m] / (TF)8) : (TC)0;
-}
-
 // piecewise-constant prolongation of the coarse correction to open children
 template <typename TC, typename TF, int NC>
 __device__ __forceinline__ void prolong_cell(const GridV& gf, const GridV& gc,
@@ -511,24 +498,6 @@ __global__ void k_smooth_pro(LevelV<T> L, const T* __restrict__ b, T* __restrict
     if (L.gate && *L.gate) return;
     long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (t < L.N / 2) smooth_cell<T, NC, PRO, TC>(L, b, x, t, col, &P);
-}
-
-template <typename T, int NC>
-__global__ void k_resid(LevelV<T> L, const T* __restrict__ b, const T* __restrict__ x,
-                        T* __restrict__ r) {
-    if (L.gate && *L.gate) return;
-    long c = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    if (c < L.N) resid_cell<T, NC>(L, b, x, r, c);
-}
-
-template <typename TF, typename TC, int NC>
-__global__ void k_restrict(GridV gf, GridV gc, const uint8_t* __restrict__ mf,
-                           const uint8_t* __restrict__ mc, const TF* __restrict__ rf,
-                           TC* __restrict__ bc, const int* gate) {
-    if (gate && *gate) return;
-    long Nc = (long)gc.n[0] * gc.n[1] * gc.n[2];
-    long c = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    if (c < Nc) restrict_cell<TF, TC, NC>(gf, gc, mf, mc, rf, bc, c);
 }
 
 template <typename TC, typename TF, int NC>
@@ -812,31 +781,6 @@ __global__ void __launch_bounds__(EB_BLOCK)
     long t = xcd_block() * (long)blockDim.x + threadIdx.x;
     if (t >= (L.N >> 1)) return;
     smooth_rb_cell<T, NC, PRO, TC>(L, b, x, col, t, &P);
-}
-
-// first half sweep (colour 0) from a zero iterate over both colours: colour 0 gets b/D, colour 1
-// is zeroed
-template <typename T, int NC>
-__global__ void k_smooth_first_rb(Rb0V L, const T* __restrict__ b, T* __restrict__ x) {
-    if (L.gate && *L.gate) return;
-    long N = L.N, Nh = N >> 1;
-    long u = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    if (u >= N) return;
-    int col = u >= Nh ? 1 : 0;
-    long t = u - col * Nh;
-    bool upd = false;
-    T Dd = (T)1;
-    if (col == 0) {
-        int i, j, k;
-        rb_cell(L.grid, (unsigned)t, 0, i, j, k);
-        long c = cell_index(L.grid, i, j, k);
-        T K[6];
-        long nb[6];
-        upd = rb0_row<T>(L, c, i, j, k, K, nb, Dd);
-    }
-    T inv = upd ? (T)1 / Dd : (T)0;
-#pragma unroll
-    for (int m = 0; m < NC; m++) x[m * N + u] = upd ? b[m * N + u] * inv : (T)0;
 }
 
 // k_smooth_first_rb fused with the conversion of the right-hand side: reads b in natural
@@ -2186,29 +2130,6 @@ void smooth_pass<float>(const Level& L, int nc, const float* b, float* x, int co
     else k_smooth<float, 1><<<gb, EB_BLOCK, 0, s>>>(L.v32(), b, x, col);
 }
 template <typename T>
-void resid_pass(const Level& L, int nc, const T* b, const T* x, T* r, hipStream_t s);
-template <>
-void resid_pass<double>(const Level& L, int nc, const double* b, const double* x, double* r,
-                        hipStream_t s) {
-    if (nc == 3) k_resid<double, 3><<<grid_for(L.N), EB_BLOCK, 0, s>>>(L.v64(), b, x, r);
-    else k_resid<double, 1><<<grid_for(L.N), EB_BLOCK, 0, s>>>(L.v64(), b, x, r);
-}
-template <>
-void resid_pass<float>(const Level& L, int nc, const float* b, const float* x, float* r,
-                       hipStream_t s) {
-    if (nc == 3) k_resid<float, 3><<<grid_for(L.N), EB_BLOCK, 0, s>>>(L.v32(), b, x, r);
-    else k_resid<float, 1><<<grid_for(L.N), EB_BLOCK, 0, s>>>(L.v32(), b, x, r);
-}
-template <typename TF, typename TC>
-void restrict_pass(const Level& F, const Level& C, int nc, const TF* rf, TC* bc, hipStream_t s) {
-    if (nc == 3)
-        k_restrict<TF, TC, 3><<<grid_for(C.N), EB_BLOCK, 0, s>>>(F.grid, C.grid, F.mask, C.mask,
-                                                                rf, bc, F.gate);
-    else
-        k_restrict<TF, TC, 1><<<grid_for(C.N), EB_BLOCK, 0, s>>>(F.grid, C.grid, F.mask, C.mask,
-                                                                rf, bc, F.gate);
-}
-template <typename T>
 LevelV<T> level_view(const Level& L);
 template <>
 LevelV<double> level_view<double>(const Level& L) { return L.v64(); }
@@ -2339,12 +2260,6 @@ template <>
 double* bl<double>(Level& L) { return L.b; }
 template <>
 float* bl<float>(Level& L) { return L.bf; }
-template <typename T>
-T* rl(Level& L);
-template <>
-double* rl<double>(Level& L) { return L.r; }
-template <>
-float* rl<float>(Level& L) { return L.rf; }
 
 void vcycle_rec(const VArgs& a, int l);
 
@@ -2555,15 +2470,32 @@ void tail_pack(const Level* lev, int nlev, hipStream_t s) {
 void finish_operator(Level* lev, int nlev, bool mixed, hipStream_t s) {
     int tail = tail_level(lev, nlev);
     for (int l = 1; l < nlev; l++) {
-        for (int d = 0; d < 3; d++)
-            level_coarsen_faces(lev[l].grid, lev[l - 1].grid, d, lev[l - 1].K[d], lev[l].K[d],
-                                1.0 / 16.0, s);
-        level_coarsen_cells(lev[l].grid, lev[l - 1].grid, lev[l - 1].S, lev[l].S, s);
+        const Level& F = lev[l - 1];
+        Level& C = lev[l];
+        CoarsenArgs A;
+        A.gc = C.grid;
+        A.gf = F.grid;
+        for (int d = 0; d < 3; d++) {
+            A.Kf[d] = F.K[d];
+            A.Kc[d] = C.K[d];
+            A.n[d] = face_count(C.grid, d);
+        }
+        A.Sf = F.S;
+        A.Sc = C.S;
+        A.scale = 1.0 / 16.0;
+        A.maskf = F.mask;
+        A.Df = F.D;
+        A.n[3] = C.N;
+        A.n[4] = F.N;
+        k_coarsen_level<<<grid_for(A.n[0] + A.n[1] + A.n[2] + A.n[3] + A.n[4]), EB_BLOCK, 0, s>>>(A);
+    }
+    {
+        Level& L = lev[nlev - 1];
+        k_diag<<<grid_for(L.N), EB_BLOCK, 0, s>>>(L.grid, L.K[0], L.K[1], L.K[2], L.S, L.mask,
+                                                  L.D);
     }
     for (int l = 0; l < nlev; l++) {
         Level& L = lev[l];
-        k_diag<<<grid_for(L.N), EB_BLOCK, 0, s>>>(L.grid, L.K[0], L.K[1], L.K[2], L.S, L.mask,
-                                                  L.D);
         if (mixed && l < tail && L.N >= F32_MIN_CELLS) {
             for (int d = 0; d < 3; d++) {
                 long nf = face_count(L.grid, d);
