@@ -277,9 +277,8 @@ def cpu_baseline(w, u0, p0, n_steps=1):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only; the step is a single box per GPU "
-              "and the multi-GPU domain decomposition is not built (see DESIGN.md).",
-              file=sys.stderr)
+        print("bench.py: runs on one GPU only; the step is a single box on one GPU and the "
+              "multi-GPU domain decomposition is not built.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

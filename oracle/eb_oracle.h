@@ -12,7 +12,7 @@
  *   Sec. III.B (cut-cell geometry, Eqs. divergence_conservative ... divergence_final,
  *               Eqs. interpolation_distances and dudn, one-sided quadratic gradients),
  *   App. A (Lagrange interpolation).
- * Where the paper is silent the oracle takes the documented readings listed in the design doc.
+ * Where the paper is silent, the comment at the function that decides states the reading taken.
  *
  * Layout: cell (i,j,k) -> i + nx*(j + ny*k); vectors are component-major [3][N];
  * faces normal to x: [nz][ny][nx+1], to y: [nz][ny+1][nx], to z: [nz+1][ny][nx].
