@@ -190,6 +190,10 @@ __global__ void k_redist_adj_gather(GeomV g, const double* __restrict__ Db,
     int qc = g.flag[c] == 1 ? g.cutid[c] : -1;
     double acc[3];
     for (int m = 0; m < 3; m++) acc[m] = qc >= 0 ? Y[(long)m * nc + qc] : Db[m * N + c];
+    if (!g.near[c]) {  // no cut cell in the 3x3x3 block: nothing to gather
+        for (int m = 0; m < 3; m++) DCb[m * N + c] = acc[m];
+        return;
+    }
     for (int dz = -1; dz <= 1; dz++)
         for (int dy = -1; dy <= 1; dy++)
             for (int dx = -1; dx <= 1; dx++) {

@@ -76,6 +76,7 @@ struct eb_ctx {
     double* alpha;
     double* ap[3];
     int *cutid, *cut, *sidx, *nfb, *blockcount, *errdev;
+    uint8_t* near;
     double *nrm, *aeb, *bc, *delta, *dd, *sw, *psi_nodes;
     // reductions
     double *part, *red;
@@ -148,6 +149,7 @@ size_t carve(eb_ctx* c, char* base, bool dry) {
     c->alpha = cv.take<double>(N);
     for (int d = 0; d < 3; d++) c->ap[d] = cv.take<double>(face_count(g, d));
     c->cutid = cv.take<int>(N);
+    c->near = cv.take<uint8_t>(N);
     c->cut = cv.take<int>(M);
     c->nrm = cv.take<double>(3 * M);
     c->aeb = cv.take<double>(M);
@@ -381,6 +383,7 @@ void fill_geomv(eb_ctx* c) {
     g.dd = c->dd;
     g.sidx = c->sidx;
     g.sw = c->sw;
+    g.near = c->near;
 }
 
 // host copy of `n` reduced values
@@ -957,6 +960,7 @@ int eb_geometry_build(const eb_box* box, const eb_body* body, void* ws, size_t w
     // per-cut arrays are [component][ncut]: rebase the strided views on the real count
     fill_geomv(c);
     geom_wall_stencil(c->g, c->dd, c->sidx, c->sw, c->nfb, c->errdev, c->s);
+    geom_mark_near(c->grid, c->cut, ncut, c->near, c->s);
     for (int l = 1; l < c->nlev; l++) level_coarsen_geometry(c->lev[l - 1], c->lev[l], c->s);
     for (int l = 0; l < c->nlev; l++) level_mask(c->lev[l], c->s);
     int err = 0;

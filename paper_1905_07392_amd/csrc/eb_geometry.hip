@@ -527,6 +527,20 @@ __global__ void k_coarsen_face(GridV gc, GridV gf, int d, const double* ff, doub
     fc[f] = coarsen_face_value(gc, gf, d, ff, f, scale);
 }
 
+__global__ void k_mark_near(GridV g, const int* __restrict__ cut, int ncut,
+                            uint8_t* __restrict__ near) {
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= ncut) return;
+    int i, j, k;
+    cell_coords(g, cut[q], i, j, k);
+    for (int dz = -1; dz <= 1; dz++)
+        for (int dy = -1; dy <= 1; dy++)
+            for (int dx = -1; dx <= 1; dx++) {
+                long cc = cell_at(g, i + dx, j + dy, k + dz);
+                if (cc >= 0) near[cc] = 1;  // every writer stores the same value
+            }
+}
+
 __global__ void k_mask(long N, const double* alpha, uint8_t* mask) {
     long c = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (c < N) mask[c] = alpha[c] > 0.0 ? 1 : 0;
@@ -581,6 +595,12 @@ void level_coarsen_geometry(const Level& F, Level& C, hipStream_t s) {
     for (int d = 0; d < 3; d++)
         k_coarsen_face<<<grid_for(face_count(C.grid, d)), EB_BLOCK, 0, s>>>(
             C.grid, F.grid, d, F.ap[d], C.ap[d], 0.25);
+}
+
+void geom_mark_near(const GridV& g, const int* cut, int ncut, uint8_t* near, hipStream_t s) {
+    long N = (long)g.n[0] * g.n[1] * g.n[2];
+    hipMemsetAsync(near, 0, N, s);
+    if (ncut > 0) k_mark_near<<<grid_for(ncut), EB_BLOCK, 0, s>>>(g, cut, ncut, near);
 }
 
 void level_mask(Level& L, hipStream_t s) {

@@ -51,6 +51,7 @@ struct GeomV {
     const double* dd;   // [2][ncut]
     const int* sidx;    // [18][ncut]
     const double* sw;   // [18][ncut]
+    const uint8_t* near;  // per cell: 1 if it or one of its 26 neighbours is a cut cell
 };
 
 template <typename T>
@@ -209,6 +210,8 @@ void geom_wall_stencil(const GeomV& g, double* dd, int* sidx, double* sw, int* n
                        int* err_dev, hipStream_t s);
 void level_coarsen_geometry(const Level& F, Level& C, hipStream_t s);
 void level_mask(Level& L, hipStream_t s);
+// near[c] = 1 for every cut cell and each of its 26 neighbours, 0 elsewhere
+void geom_mark_near(const GridV& g, const int* cut, int ncut, uint8_t* near, hipStream_t s);
 
 // pointwise and stencil operators
 void op_wall_grad(const GeomV& g, const double* u, double* gw, hipStream_t s);

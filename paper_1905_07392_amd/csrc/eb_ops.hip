@@ -415,6 +415,11 @@ __global__ void k_redist_gather(GeomV g, const double* __restrict__ DC,
     double acc[3];
     for (int m = 0; m < 3; m++) acc[m] = qc >= 0 ? DH[(long)m * nc + qc] : DC[m * N + c];
     double extra[3] = {0.0, 0.0, 0.0};
+    // a cell with no cut cell in its 3x3x3 block receives nothing: skip the neighbour scan
+    if (!g.near[c]) {
+        for (int m = 0; m < 3; m++) D[m * N + c] = acc[m] + extra[m];
+        return;
+    }
     for (int dz = -1; dz <= 1; dz++)
         for (int dy = -1; dy <= 1; dy++)
             for (int dx = -1; dx <= 1; dx++) {
