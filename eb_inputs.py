@@ -29,6 +29,7 @@ import numpy as np
 
 BODY_NONE, BODY_SPHERE, BODY_ELLIPSOID, BODY_ZSLAB, BODY_PLANE = 0, 1, 2, 3, 4
 LAW_NEWTONIAN, LAW_BINGHAM_REG, LAW_PAPANASTASIOU = 0, 1, 2
+LAW_POWER, LAW_HERSCHEL_BULKLEY, LAW_SOUZA_MENDES_DUTRA = 3, 4, 5
 
 
 @dataclass
@@ -45,6 +46,9 @@ class Workload:
     tau0: float = 0.0
     eps: float = 1e-6
     rho: float = 1.0
+    kappa: float = 1.0            # consistency of the power-law laws
+    flow_n: float = 1.0           # their flow index n
+    eta0: float = 1.0             # Souza Mendes-Dutra zero-strain viscosity
     dt: float = 1e-3
     force: tuple = (0.0, 0.0, 0.0)
     rtol: float = 1e-12

@@ -796,12 +796,43 @@ static double strain_norm(const double Gm[3][3]) {
     return sqrt(0.5 * s);
 }
 
-/* apparent viscosity laws (Table rheology, Eq. papabing:viscosity) */
+/* the power-law term kappa s^(n-1) of Table rheology (Ostwald-de Waele); for n < 1 it grows
+ * without bound as the strain rate goes to zero, and s = max(sr, eps) caps it (a reading: the
+ * paper does not say how its code bounds the term); for n >= 1, s = sr */
+static double power_term(const or_rheo* r, double sr) {
+    double s = (r->n < 1.0 && sr < r->eps) ? r->eps : sr;
+    return r->kappa * pow(s, r->n - 1.0);
+}
+
+/* apparent viscosity laws (Table rheology, Eq. papabing:viscosity).  The Papanastasiou factor
+ * (1 - exp(-x))/sr is written -expm1(-x)/sr, with its limit at sr = 0; Herschel-Bulkley adds it
+ * (x = sr/eps) to the power-law term, Souza Mendes-Dutra uses x = eta0 sr/tau0 (limit eta0). */
 static double law_eta(const or_rheo* r, double tau0, double sr) {
-    if (r->law == OR_LAW_NEWTONIAN || tau0 == 0.0) return r->mu;
-    if (r->law == OR_LAW_BINGHAM_REG) return r->mu + tau0 / (sr + r->eps);
-    if (sr == 0.0) return r->mu + tau0 / r->eps;
-    return r->mu + tau0 * (-expm1(-sr / r->eps)) / sr;
+    switch (r->law) {
+    case OR_LAW_NEWTONIAN:
+        return r->mu;
+    case OR_LAW_BINGHAM_REG:
+        if (tau0 == 0.0) return r->mu;
+        return r->mu + tau0 / (sr + r->eps);
+    case OR_LAW_PAPANASTASIOU:
+        if (tau0 == 0.0) return r->mu;
+        if (sr == 0.0) return r->mu + tau0 / r->eps;
+        return r->mu + tau0 * (-expm1(-sr / r->eps)) / sr;
+    case OR_LAW_POWER:
+        return power_term(r, sr);
+    case OR_LAW_HERSCHEL_BULKLEY: {
+        double pw = power_term(r, sr);
+        if (tau0 == 0.0) return pw;
+        if (sr == 0.0) return pw + tau0 / r->eps;
+        return pw + tau0 * (-expm1(-sr / r->eps)) / sr;
+    }
+    default: { /* OR_LAW_SOUZA_MENDES_DUTRA */
+        double pw = power_term(r, sr);
+        if (tau0 == 0.0) return pw;
+        if (sr == 0.0) return pw + r->eta0;
+        return pw + tau0 * (-expm1(-r->eta0 * sr / tau0)) / sr;
+    }
+    }
 }
 
 static void viscosity_from(const or_geom* g, const or_rheo* r, const double* theta,
@@ -1821,12 +1852,14 @@ int or_rk2_step(const or_geom* g, const or_rheo* rh, const double* theta, double
  * (Eq. cfl:forcing) sqrt(sum_d |f_d| / dx_d), the viscous one (Eq. cfl:viscous:new)
  * 2 mu (Bi + 1) / rho * sum_d 1/dx_d^2 with the regularisation left out, and they combine by
  * Eq. cfl:dt.  Bi is the largest yield stress tau0 * theta_c over fluid cells (tau0 itself is
- * the Bingham number when mu, U and L are 1); a Newtonian law has Bi = 0. */
+ * the Bingham number when mu, U and L are 1); a Newtonian law has Bi = 0.  The rule is stated
+ * for the Newtonian and Bingham laws; for the power-law laws this returns 0. */
 double or_stable_dt(const or_geom* g, const or_rheo* r, const double* theta, const double* u,
                     const double force[3], double c_cfl) {
     long N = g->N;
     double h = g->box.h;
     double cc = 0.0, bi = 0.0;
+    if (r->law >= OR_LAW_POWER) return 0.0;
     for (long c = 0; c < N; c++) {
         if (!(g->alpha[c] > 0.0)) continue;
         double s = (fabs(u[c]) + fabs(u[N + c]) + fabs(u[2 * N + c])) / h;
@@ -1961,29 +1994,47 @@ void or_cell_gradient_adj(const or_geom* g, const double* Gb, double* ub, double
     }
 }
 
-/* d eta / d(strain-rate norm) and d eta / d tau0 of the law in law_eta */
+/* g'(x) for g(x) = (1 - e^-x)/x: (x e^-x + expm1(-x))/x^2, or below x = 1e-2 its Taylor series
+ * -1/2 + x/3 - x^2/8 + x^3/30 - x^4/144, which avoids the cancellation */
+static double gexp_prime(double x) {
+    if (x < 1e-2) return -0.5 + x * (1.0 / 3.0 + x * (-1.0 / 8.0 + x * (1.0 / 30.0 - x / 144.0)));
+    return (x * exp(-x) + expm1(-x)) / (x * x);
+}
+
+/* d eta / d(strain-rate norm) and d eta / d tau0 of the law in law_eta.  Where the strain
+ * rate is zero (|.| is not differentiable there) or below the power-law cap, the power-law
+ * term's derivative is taken as 0. */
 static void law_deriv(const or_rheo* r, double tau0, double sr, double* d_sr, double* d_tau0) {
-    if (r->law == OR_LAW_NEWTONIAN) {
-        *d_sr = 0.0;
-        *d_tau0 = 0.0;
-        return;
-    }
+    *d_sr = 0.0;
+    *d_tau0 = 0.0;
+    if (r->law == OR_LAW_NEWTONIAN) return;
     if (r->law == OR_LAW_BINGHAM_REG) {
         double q = 1.0 / (sr + r->eps);
         *d_tau0 = q;
         *d_sr = -tau0 * q * q;
         return;
     }
-    /* Papanastasiou: eta = mu + tau0 f(sr), f(s) = (1 - exp(-s/eps))/s; with x = s/eps,
-     * f'(s) = g'(x)/eps^2, g(x) = (1 - e^-x)/x, g'(x) = (x e^-x + expm1(-x))/x^2, whose Taylor
-     * series -1/2 + x/3 - x^2/8 + x^3/30 - x^4/144 avoids the cancellation for small x. */
-    double e = r->eps, x = sr / e, gp;
-    if (x < 1e-2)
-        gp = -0.5 + x * (1.0 / 3.0 + x * (-1.0 / 8.0 + x * (1.0 / 30.0 - x / 144.0)));
-    else
-        gp = (x * exp(-x) + expm1(-x)) / (x * x);
+    if (r->law >= OR_LAW_POWER && sr > 0.0 && !(r->n < 1.0 && sr < r->eps) && r->n != 1.0)
+        *d_sr = r->kappa * (r->n - 1.0) * pow(sr, r->n - 2.0);
+    if (r->law == OR_LAW_POWER) return;
+    if (r->law == OR_LAW_SOUZA_MENDES_DUTRA) {
+        /* tau0 (1 - e^-x)/sr = eta0 g(x) with x = eta0 sr/tau0: d/d sr = eta0^2 g'(x)/tau0 and
+         * d/d tau0 = -eta0 x g'(x)/tau0; at tau0 = 0 the term is 0 and its tau0-derivative is
+         * the limit 1/sr (0 at sr = 0) */
+        if (tau0 == 0.0) {
+            *d_tau0 = sr > 0.0 ? 1.0 / sr : 0.0;
+            return;
+        }
+        double x = r->eta0 * sr / tau0, gp = gexp_prime(x);
+        *d_sr += r->eta0 * r->eta0 * gp / tau0;
+        *d_tau0 = -r->eta0 * x * gp / tau0;
+        return;
+    }
+    /* Papanastasiou and Herschel-Bulkley: tau0 f(sr), f(s) = (1 - exp(-s/eps))/s; with
+     * x = s/eps, f'(s) = g'(x)/eps^2 */
+    double e = r->eps, x = sr / e;
     *d_tau0 = sr == 0.0 ? 1.0 / e : -expm1(-x) / sr;
-    *d_sr = tau0 * gp / (e * e);
+    *d_sr += tau0 * gexp_prime(x) / (e * e);
 }
 
 /* strain_norm backward: d sr / d G_ab = (G_ab + G_ba)/sr (zero at sr = 0) */

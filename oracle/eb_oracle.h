@@ -48,11 +48,16 @@ typedef struct {
     double u_eb[3];       /* velocity of the embedded wall */
 } or_body;
 
-enum { OR_LAW_NEWTONIAN = 0, OR_LAW_BINGHAM_REG = 1, OR_LAW_PAPANASTASIOU = 2 };
+/* Table rheology: Newtonian, regularised Bingham (two forms), power law, Herschel-Bulkley and
+ * Souza Mendes-Dutra; kappa and n are the power-law consistency and flow index, eta0 the Souza
+ * Mendes-Dutra viscosity at zero strain rate. */
+enum { OR_LAW_NEWTONIAN = 0, OR_LAW_BINGHAM_REG = 1, OR_LAW_PAPANASTASIOU = 2, OR_LAW_POWER = 3,
+       OR_LAW_HERSCHEL_BULKLEY = 4, OR_LAW_SOUZA_MENDES_DUTRA = 5 };
 
 typedef struct {
     int law;
     double mu, tau0, eps, rho;
+    double kappa, n, eta0;
 } or_rheo;
 
 typedef struct {

@@ -30,7 +30,8 @@ class OrBody(C.Structure):
 
 class OrRheo(C.Structure):
     _fields_ = [("law", C.c_int), ("mu", C.c_double), ("tau0", C.c_double),
-                ("eps", C.c_double), ("rho", C.c_double)]
+                ("eps", C.c_double), ("rho", C.c_double), ("kappa", C.c_double),
+                ("n", C.c_double), ("eta0", C.c_double)]
 
 
 class OrOpts(C.Structure):
@@ -155,6 +156,9 @@ def make_rheo(w, tau0=None) -> OrRheo:
     r.tau0 = float(w.tau0 if tau0 is None else tau0)
     r.eps = float(w.eps)
     r.rho = float(w.rho)
+    r.kappa = float(w.kappa)
+    r.n = float(w.flow_n)
+    r.eta0 = float(w.eta0)
     return r
 
 

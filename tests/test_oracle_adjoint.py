@@ -132,7 +132,16 @@ def _derived_loss(g, u, th, rh, opts, bars):
     return (Cb * Cv).sum() + (etb * et).sum() + (ebb * eb).sum() + (Vb * V).sum()
 
 
-@pytest.mark.parametrize("case", ["bingham_sphere", "papanastasiou_channel"])
+# the power-law family of Table rheology on the channel: the cap of n < 1 kept out of reach
+# (eps = 1e-12) where eps is not the yield regularisation; Herschel-Bulkley shear-thickening;
+# Souza Mendes-Dutra with eta0 = tau0/0.05, so that eta0 |gamma|/tau0 spans the small-x series
+_LAWS = {"power_channel": dict(law=I.LAW_POWER, kappa=1.3, flow_n=0.6, eps=1e-12),
+         "herschel_bulkley_channel": dict(law=I.LAW_HERSCHEL_BULKLEY, kappa=0.9, flow_n=1.3),
+         "smd_channel": dict(law=I.LAW_SOUZA_MENDES_DUTRA, kappa=1.1, flow_n=0.7, eps=1e-12,
+                             eta0=0.8 / 0.05)}
+
+
+@pytest.mark.parametrize("case", ["bingham_sphere", "papanastasiou_channel"] + list(_LAWS))
 def test_derived_adjoint_fd(oracle_lib, sph, case):
     """Derived quantities (Alg. derived): velocity and per-cell yield-stress gradients."""
     O = oracle_lib
@@ -143,7 +152,7 @@ def test_derived_adjoint_fd(oracle_lib, sph, case):
     else:
         # Papanastasiou law with eps such that |gamma|/eps spans both sides of the small-x
         # series of the law derivative
-        w = I.channel64(tau0=0.8, eps=0.05, n=16, nxy=8)
+        w = I.channel64(tau0=0.8, eps=0.05, n=16, nxy=8).replace(**_LAWS.get(case, {}))
         g = O.Geometry(w)
         _, alpha, _ = g.export()
         op = alpha > 0
@@ -155,8 +164,10 @@ def test_derived_adjoint_fd(oracle_lib, sph, case):
         u0[:, ~op] = 0.0
         th = I.yield_field(w)
         _, _, sr = g.viscosity(u0, rh, th, with_sr=True)
-        x = sr[op] / w.eps
-        assert (x < 1e-2).any() and (x > 1e-2).any()
+        scale = w.eta0 / w.tau0 if w.law == I.LAW_SOUZA_MENDES_DUTRA else 1.0 / w.eps
+        x = sr[op] * scale
+        if w.law != I.LAW_POWER:
+            assert (x < 1e-2).any() and (x > 1e-2).any()
     r = I.rng(21)
     bars = [r.standard_normal((3,) + g.shape), r.standard_normal(g.shape),
             r.standard_normal(g.ncut), r.standard_normal((3,) + g.shape)]
