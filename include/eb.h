@@ -50,11 +50,21 @@ enum {
 enum { EB_BODY_NONE = 0, EB_BODY_SPHERE = 1, EB_BODY_ELLIPSOID = 2, EB_BODY_ZSLAB = 3,
        EB_BODY_PLANE = 4 };
 
-/* Apparent-viscosity laws (Sec. II.B, Table rheology; Eq. papabing:viscosity):
- *   NEWTONIAN      eta = mu
- *   BINGHAM_REG    eta = mu + tau0/(|gamma| + eps)
- *   PAPANASTASIOU  eta = mu + tau0 (1 - exp(-|gamma|/eps))/|gamma|   (mu + tau0/eps at 0) */
-enum { EB_LAW_NEWTONIAN = 0, EB_LAW_BINGHAM_REG = 1, EB_LAW_PAPANASTASIOU = 2 };
+/* Apparent-viscosity laws (Sec. II.B, Table rheology; Eq. papabing:viscosity), with
+ * g = |gamma| the strain-rate norm and P(g) = kappa s^(n-1) the power-law term, where s = g, or
+ * s = max(g, eps) when n < 1 (the term is unbounded at g = 0 there; for n >= 1, s = g):
+ *   NEWTONIAN          eta = mu
+ *   BINGHAM_REG        eta = mu + tau0/(g + eps)
+ *   PAPANASTASIOU      eta = mu + tau0 (1 - exp(-g/eps))/g            (mu + tau0/eps at g = 0)
+ *   POWER              eta = P(g)                                     (Ostwald-de Waele)
+ *   HERSCHEL_BULKLEY   eta = P(g) + tau0 (1 - exp(-g/eps))/g          (P(0) + tau0/eps at 0)
+ *   SOUZA_MENDES_DUTRA eta = P(g) + tau0 (1 - exp(-eta0 g/tau0))/g    (P(0) + eta0 at 0)
+ * A zero yield stress leaves mu (the first three laws) or P(g) (the last two).  mu, eps, rho
+ * > 0 where used; kappa > 0, n > 0 for the power-law laws; eta0 > 0 for Souza Mendes-Dutra.
+ * Covered cells hold eta = mu under every law.  The time-step rule (eb_stable_dt) is stated
+ * for the first three laws only. */
+enum { EB_LAW_NEWTONIAN = 0, EB_LAW_BINGHAM_REG = 1, EB_LAW_PAPANASTASIOU = 2,
+       EB_LAW_POWER = 3, EB_LAW_HERSCHEL_BULKLEY = 4, EB_LAW_SOUZA_MENDES_DUTRA = 5 };
 
 /* Precision of the multigrid preconditioner.  EB_MIXED smooths, restricts and prolongates in
  * FP32 on the levels of at least 64^3 cells (those whose sweeps are bound by memory traffic;
@@ -92,6 +102,8 @@ typedef struct {
 typedef struct {
     int law;              /* EB_LAW_* */
     double mu, tau0, eps, rho;
+    double kappa, n;      /* consistency and flow index of the power-law term */
+    double eta0;          /* Souza Mendes-Dutra: the viscosity at zero strain rate */
 } eb_rheology;
 
 typedef struct {
@@ -115,8 +127,9 @@ typedef struct {
                                                both attempts) */
     double dt_stable;                       /* eb_stable_dt of the step's input state with
                                                C_CFL = 0.5 and the step's force (forward
-                                               steps; 0 in the adjoint): a dt above it is
-                                               outside the paper's stability rule */
+                                               steps; 0 in the adjoint and for the
+                                               power-law laws): a dt above it is outside
+                                               the paper's stability rule */
 } eb_step_stats;
 
 typedef struct eb_ctx eb_ctx;
@@ -264,7 +277,8 @@ int eb_drag(const eb_ctx* ctx, const eb_rheology* rheo, const double* theta, con
  * force on the host) and the viscous one 2 mu (Bi + 1) / rho * 3 / h^2 (Eq. cfl:viscous:new),
  * with Bi the largest tau0 * theta over open cells (theta nullable = 1; 0 for a Newtonian
  * law) and c_cfl in (0, 1] (the paper's default 0.5).  Writes *dt (host); synchronises
- * `stream`.  The step does not limit its dt by this; it reports it (eb_step_stats). */
+ * `stream`.  The step does not limit its dt by this; it reports it (eb_step_stats).  The rule
+ * is stated for the Newtonian and Bingham laws: the power-law laws return EB_EINVAL. */
 int eb_stable_dt(const eb_ctx* ctx, const eb_rheology* rheo, const double* theta,
                  const double* u, const double force[3], double c_cfl, double* dt,
                  void* stream);

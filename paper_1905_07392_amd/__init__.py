@@ -20,7 +20,7 @@ def from_workload(w, precision=0, rtol=None, max_iter=400):
                          zlo=bd.get("zlo", 0.0), zhi=bd.get("zhi", 1.0),
                          plane_n=bd.get("plane_n", (0.0, 0.0, 1.0)),
                          plane_d=bd.get("plane_d", 0.0), u_eb=bd.get("u_eb", (0.0, 0.0, 0.0)))
-    rheo = api.make_rheology(w.law, w.mu, w.tau0, w.eps, w.rho)
+    rheo = api.make_rheology(w.law, w.mu, w.tau0, w.eps, w.rho, w.kappa, w.flow_n, w.eta0)
     opts = api.make_opts(precision=precision, rtol=w.rtol if rtol is None else rtol,
                          max_iter=max_iter, force=w.force)
     return box, body, rheo, opts

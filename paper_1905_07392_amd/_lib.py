@@ -32,7 +32,8 @@ class EbBody(C.Structure):
 
 class EbRheology(C.Structure):
     _fields_ = [("law", C.c_int), ("mu", C.c_double), ("tau0", C.c_double),
-                ("eps", C.c_double), ("rho", C.c_double)]
+                ("eps", C.c_double), ("rho", C.c_double), ("kappa", C.c_double),
+                ("n", C.c_double), ("eta0", C.c_double)]
 
 
 class EbStepOpts(C.Structure):

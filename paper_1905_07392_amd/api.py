@@ -83,9 +83,11 @@ def make_body(kind=0, center=(0.5, 0.5, 0.5), radius=None, radii=None, euler_zyx
     return b
 
 
-def make_rheology(law, mu, tau0, eps, rho) -> EbRheology:
+def make_rheology(law, mu, tau0, eps, rho, kappa=1.0, n=1.0, eta0=1.0) -> EbRheology:
+    """Law parameters (Table rheology); kappa, n and eta0 serve the power-law laws."""
     r = EbRheology()
     r.law, r.mu, r.tau0, r.eps, r.rho = int(law), float(mu), float(tau0), float(eps), float(rho)
+    r.kappa, r.n, r.eta0 = float(kappa), float(n), float(eta0)
     return r
 
 

@@ -22,6 +22,7 @@ from . import api
 def _rheo_with(rheo, tau0: float):
     r = api.EbRheology()
     r.law, r.mu, r.eps, r.rho = rheo.law, rheo.mu, rheo.eps, rheo.rho
+    r.kappa, r.n, r.eta0 = rheo.kappa, rheo.n, rheo.eta0
     r.tau0 = float(tau0)
     return r
 

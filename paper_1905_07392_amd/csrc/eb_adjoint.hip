@@ -14,30 +14,48 @@
 
 namespace {
 
-// d eta / d(strain-rate norm) and d eta / d tau0 of eta_law
-__device__ __forceinline__ void law_deriv(int law, double eps, double tau0, double sr,
+// g'(x) of g(x) = (1 - e^-x)/x, i.e. (x e^-x + expm1(-x))/x^2; below x = 1e-2 the Taylor
+// polynomial of g' replaces the cancelling quotient
+__device__ __forceinline__ double dg_exp(double x) {
+    if (x < 1e-2)
+        return -0.5 + x * (1.0 / 3.0 + x * (-1.0 / 8.0 + x * (1.0 / 30.0 - x / 144.0)));
+    return (x * exp(-x) + expm1(-x)) / (x * x);
+}
+
+// d eta / d(strain-rate norm) and d eta / d tau0 of eta_law.  The power-law term contributes
+// kappa (n-1) sr^(n-2) where it follows the rate (not at sr = 0, where |.| has no derivative,
+// nor below the cap of n < 1).  The yield term tau0 (1 - e^-x)/sr equals tau0 g(x)/sr:
+// Papanastasiou and Herschel-Bulkley (x = sr/eps) give tau0 g'(x)/eps^2 and (1 - e^-x)/sr
+// (1/eps at sr = 0); Souza Mendes-Dutra writes it eta0 g(x) with x = eta0 sr/tau0, giving
+// eta0^2 g'(x)/tau0 and -eta0 x g'(x)/tau0, and at tau0 = 0 the tau0-limit 1/sr (0 at sr = 0).
+__device__ __forceinline__ void law_deriv(const eb_rheology& r, double tau0, double sr,
                                           double& d_sr, double& d_tau0) {
-    if (law == EB_LAW_NEWTONIAN) {
-        d_sr = 0.0;
-        d_tau0 = 0.0;
-        return;
-    }
+    const int law = r.law;
+    d_sr = 0.0;
+    d_tau0 = 0.0;
+    if (law == EB_LAW_NEWTONIAN) return;
     if (law == EB_LAW_BINGHAM_REG) {
-        double q = 1.0 / (sr + eps);
+        double q = 1.0 / (sr + r.eps);
         d_tau0 = q;
         d_sr = -tau0 * q * q;
         return;
     }
-    // Papanastasiou: eta = mu + tau0 (1 - exp(-x))/sr with x = sr/eps.  With g(x) = (1-e^-x)/x,
-    // d eta/d sr = tau0 g'(x)/eps^2 and g'(x) = (x e^-x + expm1(-x))/x^2; below x = 1e-2 the
-    // Taylor polynomial of g' replaces the cancelling quotient.
-    double x = sr / eps, gp;
-    if (x < 1e-2)
-        gp = -0.5 + x * (1.0 / 3.0 + x * (-1.0 / 8.0 + x * (1.0 / 30.0 - x / 144.0)));
-    else
-        gp = (x * exp(-x) + expm1(-x)) / (x * x);
-    d_tau0 = sr == 0.0 ? 1.0 / eps : -expm1(-x) / sr;
-    d_sr = tau0 * gp / (eps * eps);
+    if (law >= EB_LAW_POWER && r.n != 1.0 && sr > 0.0 && power_rate(r, sr) == sr)
+        d_sr = r.kappa * (r.n - 1.0) * pow(sr, r.n - 2.0);
+    if (law == EB_LAW_POWER) return;
+    if (law == EB_LAW_SOUZA_MENDES_DUTRA) {
+        if (tau0 == 0.0) {
+            d_tau0 = sr > 0.0 ? 1.0 / sr : 0.0;
+            return;
+        }
+        double x = r.eta0 * sr / tau0, gp = dg_exp(x);
+        d_sr += r.eta0 * r.eta0 * gp / tau0;
+        d_tau0 = -r.eta0 * x * gp / tau0;
+        return;
+    }
+    double x = sr / r.eps;
+    d_tau0 = sr == 0.0 ? 1.0 / r.eps : -expm1(-x) / sr;
+    d_sr += tau0 * dg_exp(x) / (r.eps * r.eps);
 }
 
 // coefficient of wall-stencil entry e (flat index slot * ncut + cut) in the wall gradient
@@ -280,7 +298,7 @@ __global__ void k_visc_terms_adj(GeomV g, eb_rheology rh, const double* __restri
         for (int b = 0; b < 3; b++) G[a][b] = G9[(a * 3 + b) * N + c];
     double t0 = rh.tau0 * (theta ? theta[c] : 1.0);
     double s = strain_rate(G), dsr, dt0;
-    law_deriv(rh.law, rh.eps, t0, s, dsr, dt0);
+    law_deriv(rh, t0, s, dsr, dt0);
     double tb = dt0 * etab;
     if (s > 0.0) {
         double sb = dsr * etab / s;
@@ -309,7 +327,7 @@ __global__ void k_visc_terms_adj(GeomV g, eb_rheology rh, const double* __restri
         for (int a = 0; a < 3; a++)
             for (int b = 0; b < 3; b++) Ge[a][b] = nv[a] * gv[b];
         double se = strain_rate(Ge), dsre, dt0e;
-        law_deriv(rh.law, rh.eps, t0, se, dsre, dt0e);
+        law_deriv(rh, t0, se, dsre, dt0e);
         tb += dt0e * eebb;
         if (se > 0.0) {
             double sb = dsre * eebb / se;
@@ -804,8 +822,8 @@ __global__ void k_drag_adj(GeomV g, eb_rheology rh, const double* __restrict__ t
         for (int b = 0; b < 3; b++) G[a][b] = nv[a] * gv[b];
     double t0 = rh.tau0 * (theta ? theta[c] : 1.0);
     double sr = strain_rate(G);
-    double e = eta_law(rh.law, rh.mu, rh.eps, t0, sr), dsr, dt0;
-    law_deriv(rh.law, rh.eps, t0, sr, dsr, dt0);
+    double e = eta_law(rh, t0, sr), dsr, dt0;
+    law_deriv(rh, t0, sr, dsr, dt0);
     double area = g.aeb[q] * h * h;
     double w[3] = {fb0 * area, fb1 * area, fb2 * area};
     double eb = 0.0, peb = 0.0;

@@ -49,6 +49,21 @@ struct Carver {
     }
 };
 
+// rejects an unknown law, or parameters its formula cannot use (Table rheology)
+int check_rheology(const eb_rheology& r) {
+    if (r.law < EB_LAW_NEWTONIAN || r.law > EB_LAW_SOUZA_MENDES_DUTRA)
+        return set_err(EB_EINVAL, "unknown viscosity law %d", r.law);
+    bool pl = r.law >= EB_LAW_POWER;
+    if (pl && !(r.kappa > 0.0 && r.n > 0.0))
+        return set_err(EB_EINVAL, "the power-law laws need kappa > 0 and n > 0");
+    bool uses_eps = r.law == EB_LAW_BINGHAM_REG || r.law == EB_LAW_PAPANASTASIOU ||
+                    r.law == EB_LAW_HERSCHEL_BULKLEY || (pl && r.n < 1.0);
+    if (uses_eps && !(r.eps > 0.0)) return set_err(EB_EINVAL, "this viscosity law needs eps > 0");
+    if (r.law == EB_LAW_SOUZA_MENDES_DUTRA && !(r.eta0 > 0.0))
+        return set_err(EB_EINVAL, "the Souza Mendes-Dutra law needs eta0 > 0");
+    return EB_OK;
+}
+
 }  // namespace
 
 namespace {
@@ -1102,6 +1117,7 @@ int eb_apparent_viscosity(const eb_ctx* cc, const eb_rheology* rheo, const doubl
     eb_ctx* c = const_cast<eb_ctx*>(cc);
     if (!c || !rheo || !u || !eta || (!eta_eb && c->ncut > 0))
         return set_err(EB_EINVAL, "null argument");
+    if (int e_ = check_rheology(*rheo)) return e_;
     hipStream_t s = (hipStream_t)stream;
     op_wall_grad(c->g, u, c->gw, s);
     op_grad_eta(c->g, *rheo, u, c->gw, theta, c->G9, eta, sr, s);
@@ -1220,6 +1236,7 @@ int eb_derived(eb_ctx* c, const eb_rheology* rheo, const double* theta, const do
                int* iters, void* stream) {
     if (!c || !rheo || !u || !C || !eta || !V || (!eta_eb && c->ncut > 0))
         return set_err(EB_EINVAL, "null argument");
+    if (int e_ = check_rheology(*rheo)) return e_;
     StreamScope scope_(c, stream);
     int h = derived(c, *rheo, theta, u, opts, C, eta, eta_eb, V, 0);
     if (h) return h;
@@ -1240,6 +1257,7 @@ double stable_dt_of(const eb_ctx* c, const eb_rheology& r, double umax, double t
                     const double force[3], double c_cfl) {
     double h = c->box.h;
     double cc = umax / h;
+    if (r.law >= EB_LAW_POWER) return 0.0;  // the rule covers the first three laws only
     double bi = r.law == EB_LAW_NEWTONIAN ? 0.0 : r.tau0 * tmax;
     if (bi < 0.0) bi = 0.0;
     double cf = sqrt((fabs(force[0]) + fabs(force[1]) + fabs(force[2])) / h);
@@ -1287,6 +1305,7 @@ int step_status(eb_ctx* c, const SolveCfg& k, eb_step_stats* stats, bool adjoint
 int rk2_impl(eb_ctx* c, const eb_rheology* rheo, const double* theta, double dt,
              const eb_step_opts* o, double* u, double* p, eb_step_stats* stats, TapeV* tp) {
     if (!c || !rheo || !o || !u || !p) return set_err(EB_EINVAL, "null argument");
+    if (int e_ = check_rheology(*rheo)) return e_;
     if (!(rheo->rho > 0.0) || !(dt > 0.0)) return set_err(EB_EINVAL, "rho and dt must be > 0");
     SolveCfg k = cfg_of(o);
     long N = c->N, N3 = 3 * N;
@@ -1369,6 +1388,7 @@ int eb_rk2_step_adjoint(eb_ctx* c, const eb_rheology* rheo, const double* theta,
                         double* pb, double* tau0b, eb_step_stats* stats, void* stream) {
     if (!c || !rheo || !o || !u0 || !tape || !ub || !pb || !tau0b)
         return set_err(EB_EINVAL, "null argument");
+    if (int e_ = check_rheology(*rheo)) return e_;
     if (!(rheo->rho > 0.0) || !(dt > 0.0)) return set_err(EB_EINVAL, "rho and dt must be > 0");
     StreamScope scope_(c, stream);
     TapeV t;
@@ -1416,6 +1436,7 @@ int eb_drag(const eb_ctx* cc, const eb_rheology* rheo, const double* theta, cons
             const double* p, double F[3], void* stream) {
     eb_ctx* c = const_cast<eb_ctx*>(cc);
     if (!c || !rheo || !u || !p || !F) return set_err(EB_EINVAL, "null argument");
+    if (int e_ = check_rheology(*rheo)) return e_;
     StreamScope scope_(c, stream);
     F[0] = F[1] = F[2] = 0.0;
     if (c->ncut == 0) return EB_OK;
@@ -1434,6 +1455,7 @@ int eb_drag_adjoint(const eb_ctx* cc, const eb_rheology* rheo, const double* the
     eb_ctx* c = const_cast<eb_ctx*>(cc);
     if (!c || !rheo || !u || !fbar || !ub || !pb || !tau0b)
         return set_err(EB_EINVAL, "null argument");
+    if (int e_ = check_rheology(*rheo)) return e_;
     StreamScope scope_(c, stream);
     if (c->ncut == 0) return EB_OK;
     op_wall_grad(c->g, u, c->gw, c->s);
@@ -1502,6 +1524,7 @@ int eb_derived_adjoint(eb_ctx* c, const eb_rheology* rheo, const double* theta, 
     if (!c || !rheo || !u || !Cb || !etab || !Vb || !ub || !tau0b ||
         (!etaebb && c->ncut > 0))
         return set_err(EB_EINVAL, "null argument");
+    if (int e_ = check_rheology(*rheo)) return e_;
     StreamScope scope_(c, stream);
     SolveCfg k = cfg_of(opts);
     double rtol = opts && opts->rtol_mac > 0 ? opts->rtol_mac : 1e-12;
@@ -1528,7 +1551,10 @@ int eb_stable_dt(const eb_ctx* cc, const eb_rheology* rheo, const double* theta,
                  const double* u, const double force[3], double c_cfl, double* dt,
                  void* stream) {
     if (!cc || !rheo || !u || !force || !dt) return set_err(EB_EINVAL, "null argument");
+    if (int e_ = check_rheology(*rheo)) return e_;
     if (!(c_cfl > 0.0) || !(rheo->rho > 0.0)) return set_err(EB_EINVAL, "c_cfl and rho must be > 0");
+    if (rheo->law >= EB_LAW_POWER)
+        return set_err(EB_EINVAL, "the time-step rule is stated for the Newtonian and Bingham laws");
     eb_ctx* c = const_cast<eb_ctx*>(cc);
     hipStream_t s = (hipStream_t)stream;
     double m[2];

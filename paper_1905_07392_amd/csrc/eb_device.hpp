@@ -2,13 +2,27 @@
 #pragma once
 #include "eb_internal.hpp"
 
-// apparent viscosity (Table rheology, Eq. papabing:viscosity)
-__device__ __forceinline__ double eta_law(int law, double mu, double eps, double tau0,
-                                          double sr) {
-    if (law == EB_LAW_NEWTONIAN || tau0 == 0.0) return mu;
-    if (law == EB_LAW_BINGHAM_REG) return mu + tau0 / (sr + eps);
-    if (sr == 0.0) return mu + tau0 / eps;
-    return mu + tau0 * (-expm1(-sr / eps)) / sr;
+// strain rate at which the power-law term kappa s^(n-1) is evaluated: for n < 1 the term is
+// unbounded at zero strain rate, and rates below eps are raised to eps
+__device__ __forceinline__ double power_rate(const eb_rheology& r, double sr) {
+    return (r.n < 1.0 && sr < r.eps) ? r.eps : sr;
+}
+
+// apparent viscosity (Table rheology, Eq. papabing:viscosity): a base term (mu, or the power-law
+// term of the last three laws) plus the yield term tau0 * (1 - exp(-x))/sr, with x = sr/eps
+// (Papanastasiou, Herschel-Bulkley) or x = eta0 sr/tau0 (Souza Mendes-Dutra), and its sr -> 0
+// limit; a zero tau0 leaves the base term
+__device__ __forceinline__ double eta_law(const eb_rheology& r, double tau0, double sr) {
+    const int law = r.law;
+    if (law == EB_LAW_NEWTONIAN) return r.mu;
+    bool pl = law >= EB_LAW_POWER;
+    double base = pl ? r.kappa * pow(power_rate(r, sr), r.n - 1.0) : r.mu;
+    if (law == EB_LAW_POWER || tau0 == 0.0) return base;
+    if (law == EB_LAW_BINGHAM_REG) return base + tau0 / (sr + r.eps);
+    bool smd = law == EB_LAW_SOUZA_MENDES_DUTRA;
+    if (sr == 0.0) return base + (smd ? r.eta0 : tau0 / r.eps);
+    double x = smd ? r.eta0 * sr / tau0 : sr / r.eps;
+    return base + tau0 * (-expm1(-x)) / sr;
 }
 
 // sqrt(tr(gamma gamma^T)/2), gamma = G + G^T

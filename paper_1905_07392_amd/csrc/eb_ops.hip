@@ -85,7 +85,7 @@ __global__ void k_grad_eta(GeomV g, eb_rheology rh, const double* __restrict__ u
         for (int b = 0; b < 3; b++) G9[(a * 3 + b) * N + c] = G[a][b];
     double s = strain_rate(G);
     double t0 = rh.tau0 * (theta ? theta[c] : 1.0);
-    eta[c] = eta_law(rh.law, rh.mu, rh.eps, t0, s);
+    eta[c] = eta_law(rh, t0, s);
     if (sr) sr[c] = s;
 }
 
@@ -98,7 +98,7 @@ __global__ void k_eta_eb(GeomV g, eb_rheology rh, const double* __restrict__ gw,
     for (int a = 0; a < 3; a++)
         for (int b = 0; b < 3; b++) G[a][b] = g.nrm[(long)a * nc + q] * gw[(long)b * nc + q];
     double t0 = rh.tau0 * (theta ? theta[g.cut[q]] : 1.0);
-    eta_eb[q] = eta_law(rh.law, rh.mu, rh.eps, t0, strain_rate(G));
+    eta_eb[q] = eta_law(rh, t0, strain_rate(G));
 }
 
 // ------------------------------------------------------------------------------------------
@@ -548,7 +548,7 @@ __global__ void k_drag_terms(GeomV g, eb_rheology rh, const double* __restrict__
     for (int a = 0; a < 3; a++)
         for (int b = 0; b < 3; b++) G[a][b] = nv[a] * gv[b];
     double t0 = rh.tau0 * (theta ? theta[c] : 1.0);
-    double e = eta_law(rh.law, rh.mu, rh.eps, t0, strain_rate(G));
+    double e = eta_law(rh, t0, strain_rate(G));
     double h = g.grid.h;
     double pe = p[c];
     for (int d = 0; d < 3; d++) pe += h * g.bc[(long)d * nc + q] * gp[d * N + c];

@@ -381,3 +381,26 @@ def test_adjoint_workload_fd(n, nsteps):
         tm[cidx] -= hc
         check(f"cell {cidx}", (w.tau0, tp.view(theta.shape)), (w.tau0, tm.view(theta.shape)),
               hc, float(g_th[cidx]))
+
+
+@pytest.mark.parametrize("law", [
+    dict(law=I.LAW_POWER, kappa=1.0, flow_n=0.5, eps=1e-3),
+    dict(law=I.LAW_HERSCHEL_BULKLEY, kappa=1.0, flow_n=1.3, tau0=1.0, eps=1e-3),
+    dict(law=I.LAW_SOUZA_MENDES_DUTRA, kappa=1.0, flow_n=0.7, tau0=1.0, eta0=100.0, eps=1e-3),
+], ids=["power", "herschel_bulkley", "souza_mendes_dutra"])
+def test_derived_adjoint_laws(s32, law):
+    """The reverse of the derived quantities under the power-law family of Table rheology."""
+    P = s32
+    w = P.w.replace(**law)
+    orh = P.O.make_rheo(w)
+    grh = P.api.make_rheology(w.law, w.mu, w.tau0, w.eps, w.rho, w.kappa, w.flow_n, w.eta0)
+    sh = P.og.shape
+    Cb, Vb = P.rnd((3,) + sh, 56), P.rnd((3,) + sh, 57)
+    etb = P.rnd(sh, 58)
+    ebb = I.rng(59).standard_normal(P.og.ncut)
+    ru, rt = P.og.derived_adj(P.u0, orh, P.oopts, Cb, etb, ebb, Vb, theta=P.theta)
+    gu, gt, _ = P.api.eb_derived_adjoint(P.ctx, grh, P.dev(P.u0), P.opts, P.dev(Cb),
+                                         P.dev(etb), P.dev(ebb), P.dev(Vb),
+                                         theta=P.dev(P.theta))
+    assert rel_l2(cpu(gu), ru, P.open) < 1e-10
+    assert rel_l2(cpu(gt), rt, P.open) < 1e-10

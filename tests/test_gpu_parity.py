@@ -433,3 +433,59 @@ def test_graph_replay_matches_eager():
     for a, b in zip(*res):
         assert torch.equal(a, b)
     ctx.set_graphs(True)
+
+
+# The power-law family of Table rheology on the 32^3 sphere state: shear thinning and
+# thickening, Herschel-Bulkley, Souza Mendes-Dutra (eps = 1e-3 caps the n < 1 power-law term)
+_LAWS = {
+    "power_thinning": dict(law=I.LAW_POWER, kappa=1.0, flow_n=0.5, eps=1e-3),
+    "power_thickening": dict(law=I.LAW_POWER, kappa=1.0, flow_n=1.5, eps=1e-3),
+    "herschel_bulkley": dict(law=I.LAW_HERSCHEL_BULKLEY, kappa=1.0, flow_n=0.7, tau0=1.0,
+                             eps=1e-3),
+    "souza_mendes_dutra": dict(law=I.LAW_SOUZA_MENDES_DUTRA, kappa=1.0, flow_n=0.7, tau0=1.0,
+                               eta0=100.0, eps=1e-3),
+}
+
+
+@pytest.mark.parametrize("law", list(_LAWS))
+def test_rheology_laws_match(s32, law):
+    """eta, eta_EB, the derived quantities and one RK2 step under each law, with a per-cell
+    yield-stress field, against the oracle."""
+    P = s32
+    w = P.w.replace(**_LAWS[law])
+    orh = P.O.make_rheo(w)
+    grh = P.api.make_rheology(w.law, w.mu, w.tau0, w.eps, w.rho, w.kappa, w.flow_n, w.eta0)
+    theta = I.yield_field(w, seed=1)
+    u0, p0 = P.O.prepare_state(P.w, P.og, P.oopts)
+    eta, eeb = P.og.viscosity(u0, orh, theta)
+    geta, geeb = P.api.eb_apparent_viscosity(P.ctx, grh, P.dev(u0), theta=P.dev(theta))
+    assert rel_l2(cpu(geta), eta, P.open) <= 1e-12
+    assert rel_l2(cpu(geeb), eeb) <= 1e-12
+    C_ref, _, _, V_ref = P.og.derived(u0, orh, P.oopts, theta)
+    C_gpu, _, _, V_gpu = P.api.eb_derived(P.ctx, grh, P.dev(u0), P.opts, theta=P.dev(theta))
+    for j in range(3):
+        assert rel_l2(cpu(C_gpu)[j], C_ref[j], P.open) <= 1e-10
+        assert rel_l2(cpu(V_gpu)[j], V_ref[j], P.open) <= 1e-10
+    u1, p1, st = P.og.rk2_step(u0, p0, orh, w.dt, P.oopts, theta=theta)
+    ug, pg, gst = P.api.eb_rk2_step(P.ctx, grh, w.dt, P.opts, P.dev(u0), P.dev(p0),
+                                    theta=P.dev(theta))
+    errs = [rel_l2(cpu(ug)[j], u1[j], P.open) for j in range(3)]
+    errs.append(rel_l2(cpu(pg), p1, P.open))
+    print(f"[parity] law={law} rel L2 u,v,w,p = {errs} oracle {st} gpu {gst}", flush=True)
+    assert max(errs) <= 1e-10, errs
+    assert gst["dt_stable"] == 0.0
+
+
+def test_rheology_parameters_rejected(s32):
+    P = s32
+    u = P.dev(I.initial_velocity(P.w))
+    bad = [P.api.make_rheology(9, 1.0, 0.0, 1e-3, 1.0),
+           P.api.make_rheology(I.LAW_POWER, 1.0, 0.0, 1e-3, 1.0, kappa=0.0, n=0.5),
+           P.api.make_rheology(I.LAW_POWER, 1.0, 0.0, 0.0, 1.0, kappa=1.0, n=0.5),
+           P.api.make_rheology(I.LAW_SOUZA_MENDES_DUTRA, 1.0, 1.0, 1e-3, 1.0, eta0=0.0)]
+    for r in bad:
+        with pytest.raises(Exception):
+            P.api.eb_apparent_viscosity(P.ctx, r, u)
+    ok = P.api.make_rheology(I.LAW_POWER, 1.0, 0.0, 1e-3, 1.0, kappa=1.0, n=0.5)
+    with pytest.raises(Exception):
+        P.api.eb_stable_dt(P.ctx, ok, u)
