@@ -27,7 +27,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-BODY_NONE, BODY_SPHERE, BODY_ELLIPSOID, BODY_ZSLAB, BODY_PLANE = 0, 1, 2, 3, 4
+BODY_NONE, BODY_SPHERE, BODY_ELLIPSOID, BODY_ZSLAB, BODY_PLANE, BODY_CYLINDER = 0, 1, 2, 3, 4, 5
 LAW_NEWTONIAN, LAW_BINGHAM_REG, LAW_PAPANASTASIOU = 0, 1, 2
 LAW_POWER, LAW_HERSCHEL_BULKLEY, LAW_SOUZA_MENDES_DUTRA = 3, 4, 5
 
@@ -108,6 +108,22 @@ def ellipsoid256() -> Workload:
                           "radii": (0.15, 0.10, 0.08), "euler_zyx": tuple(ang)},
                     law=LAW_PAPANASTASIOU, mu=1.0, tau0=100.0, eps=1e-4, rho=1.0, dt=2.5e-4,
                     noise=0.0, seed=3, steps=50)
+
+
+def cylinder(npd: int, bi: float = 0.0) -> Workload:
+    """The cylinder of Sec. V.C with D = U = mu = 1: domain [0, 4D] x [0, D/2] x [0, 6D], periodic
+    along the axis (y), u = U e_z at the start and on every other wall, Re = rho U D / mu = 1e-3,
+    npd cells per diameter, tau0 = Bi (Papanastasiou, eps = 1e-3; Newtonian for bi = 0).  The
+    paper does not state the time step; dt = rho D^2 / mu = 1e-3 is taken, far below the
+    convective limit, since the step lags the pressure and in creeping flow the lag decays per
+    step by about 1 - rho/(mu dt) (the steady state is the same for any dt)."""
+    assert npd % 8 == 0
+    h = 1.0 / npd
+    return Workload(name=f"cylinder{npd}", n=(4 * npd, npd // 2, 6 * npd), h=h,
+                    periodic=(0, 1, 0), wall_u=_moving_walls((0.0, 0.0, 1.0)),
+                    body={"kind": BODY_CYLINDER, "center": (2.0, 0.25, 3.0), "radius": 0.5},
+                    law=LAW_PAPANASTASIOU if bi > 0 else LAW_NEWTONIAN, mu=1.0, tau0=bi,
+                    eps=1e-3, rho=1e-3, dt=1e-3, noise=0.0, seed=0, steps=1)
 
 
 def sphere_n(n: int, radius: float = 0.2, **kw) -> Workload:

@@ -138,6 +138,9 @@ static double levelset(const or_geom* g, const double x[3]) {
         return (x[2] - b->zlo) * (b->zhi - x[2]);
     case OR_BODY_PLANE:
         return b->plane_n[0] * x[0] + b->plane_n[1] * x[1] + b->plane_n[2] * x[2] - b->plane_d;
+    case OR_BODY_CYLINDER: /* axis along y through the centre */
+        return (x[0] - b->center[0]) * (x[0] - b->center[0]) +
+               (x[2] - b->center[2]) * (x[2] - b->center[2]) - b->radii[0] * b->radii[0];
     default:
         return 1.0;
     }
@@ -171,6 +174,12 @@ static void levelset_edge(const or_geom* g, const double x0[3], int d, double* A
         break;
     case OR_BODY_PLANE:
         *B = h * b->plane_n[d];
+        break;
+    case OR_BODY_CYLINDER:
+        if (d != 1) {
+            *A = h * h;
+            *B = 2 * h * (x0[d] - b->center[d]);
+        }
         break;
     default:
         break;

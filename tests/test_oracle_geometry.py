@@ -176,3 +176,28 @@ def test_sphere_on_nodes(oracle_lib):
     cell, data = g.cut()
     assert np.abs((data[:, 0:3] * data[:, 3:4]).sum(0)).max() < 1e-12
     assert np.abs(alpha - np.flip(alpha, axis=0)).max() < 1e-14
+
+
+def test_cylinder_geometry(oracle_lib):
+    """The cylinder of Sec. V.C (axis along y, periodic): fluid volume 4D * D/2 * 6D minus
+    pi D^2/4 * D/2 converging at second order, a closed wall surface (sum A_EB n = 0), no
+    variation along the axis, and mirror symmetry about the cylinder's centre planes."""
+    O = oracle_lib
+    exact = 4.0 * 0.5 * 6.0 - math.pi * 0.25 * 0.5
+    errs = []
+    for npd in (8, 16, 32):
+        w = I.cylinder(npd)
+        g = O.Geometry(w)
+        assert g.err == 0
+        flag, alpha, _ = g.export()
+        errs.append(abs(alpha.sum() * w.h ** 3 - exact) / exact)
+        assert np.array_equal(alpha, alpha[:, :1, :].repeat(alpha.shape[1], axis=1))
+        # mirror images to rounding (the two halves take their cuts from opposite corners)
+        assert np.allclose(alpha, alpha[::-1, :, :], rtol=0, atol=1e-12)
+        assert np.allclose(alpha, alpha[:, :, ::-1], rtol=0, atol=1e-12)
+        _, data = g.cut()  # columns: n (3), A_EB, ...
+        m = (data[:, 3:4] * data[:, 0:3]).sum(axis=0)
+        assert np.abs(m).max() < 1e-12 * data[:, 3].sum()
+        assert np.abs(data[:, 1]).max() == 0.0
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert min(rates) > 1.7 and errs[-1] < 1e-4, (errs, rates)
