@@ -47,8 +47,11 @@ enum {
     EB_ENOMEM = -6    /* workspace smaller than eb_workspace_bytes() */
 };
 
+/* Bodies (the fluid is where the level set is > 0).  CYLINDER: an infinitely long circular
+ * cylinder of radius radii[0] whose axis runs along y through `center` (the body of Sec. V.C,
+ * "Cylinder moving through Bingham fluid"). */
 enum { EB_BODY_NONE = 0, EB_BODY_SPHERE = 1, EB_BODY_ELLIPSOID = 2, EB_BODY_ZSLAB = 3,
-       EB_BODY_PLANE = 4 };
+       EB_BODY_PLANE = 4, EB_BODY_CYLINDER = 5 };
 
 /* Apparent-viscosity laws (Sec. II.B, Table rheology; Eq. papabing:viscosity), with
  * g = |gamma| the strain-rate norm and P(g) = kappa s^(n-1) the power-law term, where s = g, or

@@ -346,7 +346,7 @@ int init_ctx(eb_ctx* c, const eb_box* box, const eb_body* body) {
         if (box->n[d] < 2 || box->n[d] % 2)
             return set_err(EB_EINVAL, "n[%d]=%d must be an even number >= 2", d, box->n[d]);
     if (!(box->h > 0.0)) return set_err(EB_EINVAL, "h must be positive");
-    if (body->kind < EB_BODY_NONE || body->kind > EB_BODY_PLANE)
+    if (body->kind < EB_BODY_NONE || body->kind > EB_BODY_CYLINDER)
         return set_err(EB_EINVAL, "unknown body kind %d", body->kind);
     memset(c, 0, sizeof(*c));
     c->built_sys = -1;
@@ -365,7 +365,8 @@ int init_ctx(eb_ctx* c, const eb_box* box, const eb_body* body) {
     for (int d = 0; d < 3; d++) {
         b.lo[d] = box->lo[d];
         b.c[d] = body->center[d];
-        b.r[d] = body->kind == EB_BODY_SPHERE ? body->radii[0] : body->radii[d];
+        b.r[d] = (body->kind == EB_BODY_SPHERE || body->kind == EB_BODY_CYLINDER)
+                     ? body->radii[0] : body->radii[d];
         b.pn[d] = body->plane_n[d];
     }
     b.zlo = body->zlo;

@@ -37,6 +37,10 @@ __device__ double body_psi(const BodyV& b, double x, double y, double z) {
         return (z - b.zlo) * (b.zhi - z);
     case EB_BODY_PLANE:
         return b.pn[0] * x + b.pn[1] * y + b.pn[2] * z - b.pd;
+    case EB_BODY_CYLINDER: {
+        double dx = x - b.c[0], dz = z - b.c[2];
+        return dx * dx + dz * dz - b.r[0] * b.r[0];
+    }
     default:
         return 1.0;
     }
@@ -65,6 +69,9 @@ __device__ void body_edge_poly(const BodyV& b, const double x0[3], int d, double
         }
     } else if (b.kind == EB_BODY_PLANE) {
         qb = h * b.pn[d];
+    } else if (b.kind == EB_BODY_CYLINDER && d != 1) {
+        qa = h * h;
+        qb = 2.0 * h * (x0[d] - b.c[d]);
     }
 }
 

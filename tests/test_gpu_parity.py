@@ -82,11 +82,13 @@ def test_geometry_matches(s32):
     assert P.ctx.nfallback == P.og.nfallback
 
 
-@pytest.mark.parametrize("wl", ["channel64", "ellipsoid48", "sphere128"])
+@pytest.mark.parametrize("wl", ["channel64", "ellipsoid48", "sphere128", "cylinder16"])
 def test_geometry_other_bodies(wl):
     _require_gpu()
     if wl == "channel64":
         w = I.channel64()
+    elif wl == "cylinder16":
+        w = I.cylinder(16)
     elif wl == "ellipsoid48":
         w = I.ellipsoid256().replace(n=(48, 48, 48), h=1.0 / 48, name="ellipsoid48")
     else:
@@ -489,3 +491,54 @@ def test_rheology_parameters_rejected(s32):
     ok = P.api.make_rheology(I.LAW_POWER, 1.0, 0.0, 1e-3, 1.0, kappa=1.0, n=0.5)
     with pytest.raises(Exception):
         P.api.eb_stable_dt(P.ctx, ok, u)
+
+
+def test_cylinder_step_matches():
+    """One step of the cylinder workload of Sec. V.C (64 x 8 x 96, periodic along the axis,
+    non-cubic multigrid levels down to 16 x 2 x 24) against the oracle.  In this creeping flow
+    the Helmholtz operator is nearly the Laplacian (rho/dt = 1 against 12 mu/h^2 ~ 3e3), so two
+    solves that both stop at a max-norm relative residual of 1e-12 may differ by up to ~3e-9
+    relative in their solutions, and a tighter stop is below the residual's rounding floor
+    (~1e-16 * 3e3); the step is held to 1e-9 here instead of 1e-10."""
+    _step_parity(Pair(I.cylinder(16)), steps=2, tol=1e-9)
+
+
+def _cylinder_drag(npd, tol=1e-9, maxsteps=600):
+    import paper_1905_07392_amd as pkg
+    from paper_1905_07392_amd import api
+
+    w = I.cylinder(npd)
+    box, body, rheo, opts = pkg.from_workload(w)
+    ctx = api.eb_geometry_build(box, body, "cuda:0")
+    print(f"[drag] cylinder npd={npd} n={w.n}", flush=True)
+    u = torch.from_numpy(I.initial_velocity(w)).to("cuda:0")
+    p = ctx.scalar()
+    for s in range(maxsteps):
+        u1, p, st = api.eb_rk2_step(ctx, rheo, w.dt, opts, u, p)
+        du = (u1 - u).abs().max().item()
+        u = u1
+        if du < tol:
+            break
+    F = api.eb_drag(ctx, rheo, u, p)
+    cd = F[2] / (1.0 * 1.0 * 0.5)  # C_D = F_D / (mu U L), L = D/2
+    print(f"[drag] npd={npd} steps={s + 1} du={du:.3e} C_D={cd:.6f}", flush=True)
+    assert du < tol, (s, du)
+    return cd
+
+
+def test_cylinder_newtonian_drag_approaches_faxen():
+    """Drag validation of Sec. V.C: a Newtonian fluid past the fixed cylinder centred between
+    walls 4D apart, driven to steady state; Faxen's formula (App., Eq. faxen, with D/W = 1/4)
+    gives C_D = 21.9642 (the paper's own run, at 64 cells per D, 21.8128).  The steady drag
+    must approach it as the grid is refined: closer at 32 than at 16 cells per D, and within
+    5% at 32."""
+    _require_gpu()
+    r = 0.25
+    faxen = 4 * np.pi / (np.log(1 / r) - 0.9157 + 1.7244 * r ** 2 - 1.7302 * r ** 4
+                         + 2.4056 * r ** 6 - 4.5913 * r ** 8)
+    assert abs(faxen - 21.9642) < 1e-4  # the paper prints 21.9642; the formula gives 21.96426
+    cd16, cd32 = _cylinder_drag(16), _cylinder_drag(32)
+    e16, e32 = abs(cd16 - faxen) / faxen, abs(cd32 - faxen) / faxen
+    print(f"[drag] Faxen {faxen:.4f}: C_D {cd16:.4f} (16/D, {e16:.2%}), {cd32:.4f} (32/D, "
+          f"{e32:.2%})", flush=True)
+    assert e32 < e16 and e32 < 0.05, (cd16, cd32, faxen)
