@@ -126,6 +126,15 @@ def cylinder(npd: int, bi: float = 0.0) -> Workload:
                     eps=1e-3, rho=1e-3, dt=1e-3, noise=0.0, seed=0, steps=1)
 
 
+def taylor_green(n: int) -> Workload:
+    """The Taylor-Green vortex of Sec. IV.A (Eq. taylor-green): the unit square periodic in x and
+    y, extruded over n/4 cells along z (periodic, uniform), Re = rho U L / mu = 100 with
+    rho = U = L = 1; dt = h/(2U), so t = 1 takes 2n steps."""
+    return Workload(name=f"taylor_green{n}", n=(n, n, n // 4), h=1.0 / n, periodic=(1, 1, 1),
+                    law=LAW_NEWTONIAN, mu=0.01, rho=1.0, dt=0.5 / n, noise=0.0, seed=0,
+                    steps=2 * n)
+
+
 def sphere_n(n: int, radius: float = 0.2, **kw) -> Workload:
     """A sphere32-like workload at another resolution (parity sizes with ragged tiles)."""
     w = sphere32().replace(name=f"sphere{n}", n=(n, n, n), h=1.0 / n)

@@ -1,0 +1,78 @@
+"""Validation of the GPU step against an exact solution of the equations (Sec. IV.A): the
+Taylor-Green vortex (Eq. taylor-green) advanced to t = 1 at Re = 100 on N x N cells.  The paper's
+Table convergence reports errors falling at rates that approach 2 (1.28, 1.82, 1.94 from
+N = 32 to 256); these are soft values for a different projection (reading A1) and time step, so
+the bars are: rates above 1.5 between N = 64 and 128 in every norm, and errors within a factor
+of three of the paper's at each N.  The step does not meet them yet (the test is an expected
+failure that records the measured errors).
+"""
+import numpy as np
+import pytest
+
+import eb_inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+# Table convergence: N -> (L1, L2, Linf)
+PAPER = {32: (0.000446166, 0.000568385, 0.00127935),
+         64: (0.000184199, 0.000229894, 0.000472784),
+         128: (5.22399e-05, 6.47553e-05, 0.000130564)}
+
+
+def _tg(x, y, t, re):
+    d = np.exp(-8 * np.pi ** 2 * t / re)
+    u = np.sin(2 * np.pi * x) * np.cos(2 * np.pi * y) * d
+    v = -np.cos(2 * np.pi * x) * np.sin(2 * np.pi * y) * d
+    p = 0.25 * (np.cos(4 * np.pi * x) + np.cos(4 * np.pi * y)) * d * d
+    return u, v, p
+
+
+def _run(n, dt_div=1):
+    import paper_1905_07392_amd as pkg
+    from paper_1905_07392_amd import api
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    w = I.taylor_green(n)
+    w = w.replace(dt=w.dt / dt_div, steps=w.steps * dt_div)
+    re = w.rho * 1.0 * 1.0 / w.mu
+    box, body, rheo, opts = pkg.from_workload(w)
+    ctx = api.eb_geometry_build(box, body, "cuda:0")
+    print(f"[tg] n={w.n} steps={w.steps}", flush=True)
+    nz, ny, nx = w.shape
+    xc = (np.arange(nx) + 0.5) * w.h
+    x = np.broadcast_to(xc[None, None, :], w.shape)
+    y = np.broadcast_to(xc[None, :, None], w.shape)
+    u0, v0, p0 = _tg(x, y, 0.0, re)
+    u = np.zeros((3,) + w.shape)
+    u[0], u[1] = u0, v0
+    ug = torch.from_numpy(u).to("cuda:0")
+    pg = torch.from_numpy(np.ascontiguousarray(p0)).to("cuda:0")
+    for _ in range(w.steps):
+        ug, pg, _ = api.eb_rk2_step(ctx, rheo, w.dt, opts, ug, pg)
+    ue, ve, _ = _tg(x, y, w.steps * w.dt, re)
+    r = ug.cpu().numpy()
+    err = np.sqrt((r[0] - ue) ** 2 + (r[1] - ve) ** 2 + r[2] ** 2)
+    # norms per unit depth of the extruded box (the 2D norms of Eq. norms)
+    vol = w.h ** 3 / (nz * w.h)
+    nm = (err.sum() * vol, np.sqrt((err ** 2).sum() * vol), err.max())
+    print(f"[tg] N={n} dt={w.dt:.3e} L1 {nm[0]:.6e} L2 {nm[1]:.6e} Linf {nm[2]:.6e} paper {PAPER.get(n)}",
+          flush=True)
+    return nm
+
+
+@pytest.mark.xfail(strict=False, reason=(
+    "known gap: with dt = h/2 the L1 error falls from 1.94e-3 (N = 32) to 2.92e-4 (64) and then "
+    "stays at 3.05e-4 (128); at N = 128 halving dt lowers it to 1.33e-4, and at a fixed dt of "
+    "1.95e-3 it is larger at N = 128 than at 64, so a time-stepping error that grows as h falls "
+    "dominates; not yet explained"))
+def test_taylor_green_convergence():
+    e = {n: _run(n) for n in (32, 64, 128)}
+    for k in range(3):
+        rate = np.log2(e[64][k] / e[128][k])
+        print(f"[tg] norm {k}: rates {np.log2(e[32][k] / e[64][k]):.3f} {rate:.3f}", flush=True)
+        assert rate > 1.5, (k, e)
+        for n in e:
+            assert PAPER[n][k] / 3 < e[n][k] < 3 * PAPER[n][k], (n, k, e[n], PAPER[n])
