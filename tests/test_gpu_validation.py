@@ -67,7 +67,8 @@ def _run(n, dt_div=1):
     "known gap: with dt = h/2 the L1 error falls from 1.94e-3 (N = 32) to 2.92e-4 (64) and then "
     "stays at 3.05e-4 (128); at N = 128 halving dt lowers it to 1.33e-4, and at a fixed dt of "
     "1.95e-3 it is larger at N = 128 than at 64, so a time-stepping error that grows as h falls "
-    "dominates; not yet explained"))
+    "dominates; the oracle gives the same errors, so it lies in the step as read, not in the "
+    "kernels"))
 def test_taylor_green_convergence():
     e = {n: _run(n) for n in (32, 64, 128)}
     for k in range(3):
