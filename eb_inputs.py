@@ -28,6 +28,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 BODY_NONE, BODY_SPHERE, BODY_ELLIPSOID, BODY_ZSLAB, BODY_PLANE, BODY_CYLINDER = 0, 1, 2, 3, 4, 5
+BODY_CAVITY = 6  # fluid inside a sphere (body outside)
 LAW_NEWTONIAN, LAW_BINGHAM_REG, LAW_PAPANASTASIOU = 0, 1, 2
 LAW_POWER, LAW_HERSCHEL_BULKLEY, LAW_SOUZA_MENDES_DUTRA = 3, 4, 5
 

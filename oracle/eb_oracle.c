@@ -141,6 +141,11 @@ static double levelset(const or_geom* g, const double x[3]) {
     case OR_BODY_CYLINDER: /* axis along y through the centre */
         return (x[0] - b->center[0]) * (x[0] - b->center[0]) +
                (x[2] - b->center[2]) * (x[2] - b->center[2]) - b->radii[0] * b->radii[0];
+    case OR_BODY_CAVITY: { /* fluid inside the sphere, body outside */
+        double s = 0;
+        for (int d = 0; d < 3; d++) s += (x[d] - b->center[d]) * (x[d] - b->center[d]);
+        return b->radii[0] * b->radii[0] - s;
+    }
     default:
         return 1.0;
     }
@@ -180,6 +185,10 @@ static void levelset_edge(const or_geom* g, const double x0[3], int d, double* A
             *A = h * h;
             *B = 2 * h * (x0[d] - b->center[d]);
         }
+        break;
+    case OR_BODY_CAVITY:
+        *A = -h * h;
+        *B = -2 * h * (x0[d] - b->center[d]);
         break;
     default:
         break;

@@ -36,7 +36,8 @@ typedef struct {
 
 /* CYLINDER: circular, radius radii[0], axis along y through the centre (Sec. V.C) */
 enum { OR_BODY_NONE = 0, OR_BODY_SPHERE = 1, OR_BODY_ELLIPSOID = 2, OR_BODY_ZSLAB = 3,
-       OR_BODY_PLANE = 4, OR_BODY_CYLINDER = 5 };
+       OR_BODY_PLANE = 4, OR_BODY_CYLINDER = 5,
+       OR_BODY_CAVITY = 6 };
 
 typedef struct {
     int kind;

@@ -132,3 +132,123 @@ def test_newtonian_limit_bitwise(oracle_lib):
     for law in (I.LAW_BINGHAM_REG, I.LAW_PAPANASTASIOU):
         eta, eta_eb = g.viscosity(u, O.make_rheo(w.replace(law=law), tau0=0.0))
         assert np.all(eta == w.mu) and np.all(eta_eb == w.mu)
+
+
+# ----------------------------------------------------------------------------------------------
+# the covered-node fallback of the wall stencil (reading A5)
+# ----------------------------------------------------------------------------------------------
+def _others(d):
+    return (1, 2) if d == 0 else ((0, 2) if d == 1 else (0, 1))
+
+
+def _a5_fallback_nodes(open_, q, nv, b):
+    """Covered nodes that the two stencil planes of the cut cell at q = (i, j, k) still hold after
+    the one shift of reading A5, as offsets from the cell centre in cells.  Planes: i_d* + k s for
+    k = 1, 2, with d* the largest |n_d| (lowest index on ties) and s its sign; the 3 x 3 nodes
+    centred at round-half-up of the transverse coordinates of b + d_k n, d_k = (k s - b_d*)/n_d*,
+    shifted once by sign(n_t) in each transverse direction t when one of them is covered."""
+    ds = int(np.argmax(np.abs(nv)))
+    s = 1 if nv[ds] > 0 else -1
+    t1, t2 = _others(ds)
+    nz, ny, nx = open_.shape
+
+    def covered(plane, c1, c2):
+        out = []
+        for m1 in (-1, 0, 1):
+            for m2 in (-1, 0, 1):
+                off = np.zeros(3, int)
+                off[ds], off[t1], off[t2] = plane, c1 + m1, c2 + m2
+                r = np.array(q) + off
+                assert 0 <= r[0] < nx and 0 <= r[1] < ny and 0 <= r[2] < nz
+                if not open_[r[2], r[1], r[0]]:
+                    out.append(off.astype(float))
+        return out
+
+    nodes = []
+    for kk in (1, 2):
+        dk = (kk * s - b[ds]) / nv[ds]
+        p = b + dk * nv
+        c1, c2 = int(np.floor(p[t1] + 0.5)), int(np.floor(p[t2] + 0.5))
+        cov = covered(kk * s, c1, c2)
+        if cov:
+            c1 += int(np.sign(nv[t1]))
+            c2 += int(np.sign(nv[t2]))
+            cov = covered(kk * s, c1, c2)
+        nodes += cov
+    return nodes
+
+
+def _quad_monomials(xi):
+    x, y, z = xi
+    return np.array([1.0, x, y, z, x * x, y * y, z * z, x * y, y * z, x * z])
+
+
+def _quad_grad(coef, xi):
+    x, y, z = xi
+    c = coef
+    return np.array([c[1] + 2 * c[4] * x + c[7] * y + c[9] * z,
+                     c[2] + 2 * c[5] * y + c[7] * x + c[8] * z,
+                     c[3] + 2 * c[6] * z + c[8] * y + c[9] * x])
+
+
+@pytest.mark.parametrize("n,radius,center", [(20, 0.25, (0.5, 0.5, 0.5)),
+                                             (12, 0.15, (0.5, 0.53, 0.46)),
+                                             (12, 0.15, (0.47, 0.52, 0.5))])
+def test_wall_gradient_fallback_exact_where_covered_nodes_vanish(oracle_lib, n, radius, center):
+    """Reading A5 replaces the still-covered nodes of a shifted stencil by the wall value u_EB.
+    The biquadratic interpolation and Eq. dudn are exact for quadratics, so the fallback
+    gradient is exact for every quadratic field q that is zero at the wall centroid b (with
+    u_EB = 0) and at each substituted node: there the substitution changes nothing.  Such q
+    exist when the covered nodes and b impose fewer than ten conditions on the ten quadratic
+    monomials; each is drawn at random from that null space, so a wrong weight, distance,
+    sign or plane, or a read of the covered cell's own value (set to 1e3 here), breaks the
+    equality.  A fluid cavity (fluid inside a sphere) at coarse resolution is the geometry:
+    its stencil planes reach across the cavity, so the fallback is taken.  What this cannot fix
+    is which 3 x 3 node set the reading picks: in these geometries every substituted node lies
+    in one stencil plane, in a line or in six or more points of it, so each such q vanishes on
+    that whole plane and the shift direction does not change the result (the choice of nodes is
+    a reading, compared only between the two implementations)."""
+    O = oracle_lib
+    w = I.Workload(name="cavity", n=(n, n, n), h=1.0 / n,
+                   body={"kind": I.BODY_CAVITY, "center": center, "radius": radius})
+    g = O.Geometry(w)
+    assert g.nfallback > 0
+    flag, alpha, _ = g.export()
+    open_ = alpha > 0
+    cell, data = g.cut()
+    h = w.h
+    nz, ny, nx = g.shape
+    K, J, Ii = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    rng = np.random.default_rng(11)
+    checked = skipped = 0
+    for cid, (c, row) in enumerate(zip(cell, data)):
+        if row[8] == 0:
+            continue
+        k, rem = divmod(int(c), nx * ny)
+        j, i = divmod(rem, nx)
+        nv, b = row[0:3], row[4:7]
+        nodes = _a5_fallback_nodes(open_, (i, j, k), nv, b)
+        assert nodes, "the oracle reports a fallback that reading A5 does not take"
+        A = np.array([_quad_monomials(b)] + [_quad_monomials(z) for z in nodes])
+        _, sv, vt = np.linalg.svd(A)
+        rank = int(np.sum(sv > 1e-10 * sv[0]))
+        null = vt[rank:]
+        if null.shape[0] == 0:
+            skipped += 1
+            continue
+        coefs = [null.T @ rng.standard_normal(null.shape[0]) for _ in range(3)]
+        exact = np.array([_quad_grad(cf, b) @ nv / h for cf in coefs])
+        if np.max(np.abs(exact)) < 1e-3 * max(np.max(np.abs(cf)) for cf in coefs) / h:
+            skipped += 1
+            continue
+        xi = np.stack([Ii - i, J - j, K - k]).astype(float)
+        mons = [np.ones_like(xi[0]), xi[0], xi[1], xi[2], xi[0] ** 2, xi[1] ** 2, xi[2] ** 2,
+                xi[0] * xi[1], xi[1] * xi[2], xi[0] * xi[2]]
+        u = np.stack([sum(cf[m] * mons[m] for m in range(10)) for cf in coefs])
+        u[:, ~open_] = 1e3
+        gw = g.wall_gradient(np.ascontiguousarray(u))
+        scale = np.max(np.abs(exact))
+        assert np.allclose(gw[cid], exact, rtol=0, atol=1e-10 * scale), (cid, gw[cid], exact)
+        checked += 1
+    print("fallback cells checked", checked, "skipped", skipped)
+    assert checked >= 2, (checked, skipped)
