@@ -1213,6 +1213,41 @@ void or_gcc(const or_geom* g, const double* p, double* gp) {
 /* ------------------------------------------------------------------------------------------ */
 enum { SYS_POISSON = 0, SYS_VISC = 1 };
 
+/* The viscous system's coarse face coefficient for one of the four fine faces f2 (at fine face
+ * position r) that make up a coarse face normal to d.  The line of fine faces normal to the coarse
+ * face through the two coarse cells it separates, f1 (inside the lower coarse cell), f2 and f3
+ * (inside the upper one), joins the two coarse centres, so its viscosity acts in series: the
+ * weighted harmonic mean H = W / sum(w_i / g_i), W = sum(w_i), of g_i = K_i / A_i (the face
+ * coefficient without its aperture) over the open faces of the line, with weights 1/2, 1, 1/2
+ * for the half of f1, all of f2 and the half of f3 that lie between the two centres.  A domain
+ * wall face f2 has the inner face only, weights 1/2 and 1/2, and g_2 = K_2 / (2 A_2) (the ghost
+ * factor of the wall flux removed).  The line contributes K_2 H / g_2: its aperture and spacing
+ * as before, its viscosity in series.  With a uniform viscosity every g_i is g_2 and the line
+ * contributes K_2, the plain sum of the four fine faces. */
+static double series_line(const or_geom* g, const level_t* F, int d, const int r[3], int wall) {
+    long f2 = fidx(F->n, d, r[0], r[1], r[2]);
+    double K2 = F->K[d][f2], A2 = F->ap[d][f2];
+    if (K2 == 0.0 || A2 == 0.0) return K2;
+    double g2 = wall ? K2 / (2.0 * A2) : K2 / A2;
+    double W = wall ? 0.5 : 1.0, R = W / g2;
+    int per = g->box.periodic[d];
+    for (int side = -1; side <= 1; side += 2) {
+        int q[3] = {r[0], r[1], r[2]};
+        q[d] += side;
+        if (q[d] < 0 || q[d] > F->n[d]) {
+            if (!per) continue; /* beyond a domain wall: the wall face has no outer neighbour */
+            q[d] = q[d] < 0 ? q[d] + F->n[d] : q[d] - F->n[d];
+        }
+        long fi = fidx(F->n, d, q[0], q[1], q[2]);
+        double K = F->K[d][fi], A = F->ap[d][fi];
+        if (K > 0.0 && A > 0.0) {
+            W += 0.5;
+            R += 0.5 / (K / A);
+        }
+    }
+    return K2 * (W / R) / g2;
+}
+
 /* level-0 face coefficients and cell shifts, then coarse levels by averaging */
 static void build_operator(or_geom* g, int sys, double beta, double rho, double dt,
                            const double* eta, const double* eta_eb) {
@@ -1264,13 +1299,15 @@ static void build_operator(or_geom* g, int sys, double beta, double rho, double 
                     for (int i = 0; i < m[0]; i++) {
                         int q[3] = {i, j, k};
                         double s = 0;
+                        int wall = !g->box.periodic[d] && (q[d] == 0 || q[d] == C->n[d]);
                         for (int o1 = 0; o1 < 2; o1++)
                             for (int o2 = 0; o2 < 2; o2++) {
                                 int r[3];
                                 r[d] = 2 * q[d];
                                 r[t1] = 2 * q[t1] + o1;
                                 r[t2] = 2 * q[t2] + o2;
-                                s += F->K[d][fidx(F->n, d, r[0], r[1], r[2])];
+                                s += sys == SYS_VISC ? series_line(g, F, d, r, wall)
+                                                     : F->K[d][fidx(F->n, d, r[0], r[1], r[2])];
                             }
                         C->K[d][fidx(C->n, d, i, j, k)] = s / 16.0;
                     }
@@ -1479,10 +1516,13 @@ void or_visc_apply(const or_geom* g, double rho, double dt, const double* eta,
 /* ------------------------------------------------------------------------------------------ */
 /* Krylov drivers around the V-cycle                                                            */
 /* ------------------------------------------------------------------------------------------ */
+/* max |x|, or NaN when any entry is NaN (a non-finite residual must reach the stop test) */
 static double vmaxabs(const double* x, long n) {
     double m = 0;
-    for (long t = 0; t < n; t++)
+    for (long t = 0; t < n; t++) {
+        if (isnan(x[t])) return NAN;
         if (fabs(x[t]) > m) m = fabs(x[t]);
+    }
     return m;
 }
 static double vdot(const double* x, const double* y, long n) {
@@ -1491,7 +1531,27 @@ static double vdot(const double* x, const double* y, long n) {
     return s;
 }
 
-/* preconditioned CG on the symmetric Poisson system M p = b (operator already built) */
+/* z minus its mean over open cells.  The Poisson system is singular (constants on the fluid are
+ * its null space) and the V-cycle's output carries a constant component, which in exact
+ * arithmetic only adds a constant to the iterate (removed by the final normalisation) and changes
+ * no CG coefficient (the residual is mean-free).  In floating point, once the residual is near
+ * the tolerance that component dominates the search direction, whose A-product is then rounding
+ * noise times a huge step, and CG breaks down; removing it keeps the iteration in the range. */
+static void open_mean_free(const or_geom* g, double* z) {
+    double s = 0;
+    long cnt = 0;
+    for (long c = 0; c < g->N; c++)
+        if (g->alpha[c] > 0.0) {
+            s += z[c];
+            cnt++;
+        }
+    double mean = cnt ? s / cnt : 0.0;
+    for (long c = 0; c < g->N; c++)
+        if (g->alpha[c] > 0.0) z[c] -= mean;
+}
+
+/* preconditioned CG on the symmetric Poisson system M p = b (operator already built); the
+ * preconditioned residual is made mean-free over open cells after every V-cycle */
 static int pcg(or_geom* g, const double* b, double* x, double rtol, double scale, int maxit,
                const or_opts* o, int* iters) {
     long N = g->N;
@@ -1506,11 +1566,17 @@ static int pcg(or_geom* g, const double* b, double* x, double rtol, double scale
     for (long t = 0; t < N; t++) r[t] = b[t] - r[t];
     double bn = vmaxabs(b, N);
     if (scale > bn) bn = scale;
-    if (bn == 0.0 || vmaxabs(r, N) <= rtol * bn) {
+    double rn0 = vmaxabs(r, N);
+    if (!isfinite(rn0) || !isfinite(bn)) {
+        ret = OR_ENAN;
+        goto done;
+    }
+    if (bn == 0.0 || rn0 <= rtol * bn) {
         ret = OR_OK;
         goto done;
     }
     vcycle_level(g, 0, 1, r, z, o);
+    open_mean_free(g, z);
     memcpy(p, z, N * sizeof(double));
     double rz = vdot(r, z, N);
     for (int it = 1; it <= maxit; it++) {
@@ -1521,11 +1587,17 @@ static int pcg(or_geom* g, const double* b, double* x, double rtol, double scale
             r[t] -= a * q[t];
         }
         *iters = it;
-        if (vmaxabs(r, N) <= rtol * bn) {
+        double rn = vmaxabs(r, N);
+        if (!isfinite(rn)) {
+            ret = OR_ENAN;
+            break;
+        }
+        if (rn <= rtol * bn) {
             ret = OR_OK;
             break;
         }
         vcycle_level(g, 0, 1, r, z, o);
+        open_mean_free(g, z);
         double rzn = vdot(r, z, N);
         double be = rzn / rz;
         rz = rzn;
@@ -1598,7 +1670,12 @@ int or_visc_solve(const or_geom* g_in, double rho, double dt, const double* eta,
         double b = g->alpha[c] > 0.0 ? g->alpha[c] * psi[q] : 0.0;
         r[q] = b - t[q];
     }
-    if (bn == 0.0 || vmaxabs(r, N3) <= tol) {
+    double rn0 = vmaxabs(r, N3);
+    if (!isfinite(rn0) || !isfinite(bn)) {
+        ret = OR_ENAN;
+        goto done;
+    }
+    if (bn == 0.0 || rn0 <= tol) {
         ret = OR_OK;
         goto done;
     }
@@ -1613,7 +1690,12 @@ int or_visc_solve(const or_geom* g_in, double rho, double dt, const double* eta,
         al = rr / vdot(rh, v, N3);
         for (long q = 0; q < N3; q++) s[q] = r[q] - al * v[q];
         *iters = it;
-        if (vmaxabs(s, N3) <= tol) {
+        double sn = vmaxabs(s, N3);
+        if (!isfinite(sn)) {
+            ret = OR_ENAN;
+            break;
+        }
+        if (sn <= tol) {
             for (long q = 0; q < N3; q++) x[q] += al * ph[q];
             ret = OR_OK;
             break;
@@ -1625,7 +1707,12 @@ int or_visc_solve(const or_geom* g_in, double rho, double dt, const double* eta,
             x[q] += al * ph[q] + om * sh[q];
             r[q] = s[q] - om * t[q];
         }
-        if (vmaxabs(r, N3) <= tol) {
+        double rn = vmaxabs(r, N3);
+        if (!isfinite(rn)) {
+            ret = OR_ENAN;
+            break;
+        }
+        if (rn <= tol) {
             ret = OR_OK;
             break;
         }
@@ -2536,6 +2623,10 @@ static int visc_solve_T(or_geom* g, double rho, double dt, const double* eta,
     memset(x, 0, N3 * sizeof(double));
     memcpy(r, rhs, N3 * sizeof(double));
     double bn = vmaxabs(rhs, N3), tol = rtol * bn;
+    if (!isfinite(bn)) {
+        ret = OR_ENAN;
+        goto done;
+    }
     if (bn == 0.0) {
         ret = OR_OK;
         goto done;
@@ -2551,7 +2642,12 @@ static int visc_solve_T(or_geom* g, double rho, double dt, const double* eta,
         al = rr / vdot(rh, v, N3);
         for (long q = 0; q < N3; q++) s[q] = r[q] - al * v[q];
         *iters = it;
-        if (vmaxabs(s, N3) <= tol) {
+        double sn = vmaxabs(s, N3);
+        if (!isfinite(sn)) {
+            ret = OR_ENAN;
+            break;
+        }
+        if (sn <= tol) {
             for (long q = 0; q < N3; q++) x[q] += al * ph[q];
             ret = OR_OK;
             break;
@@ -2563,7 +2659,12 @@ static int visc_solve_T(or_geom* g, double rho, double dt, const double* eta,
             x[q] += al * ph[q] + om * sh[q];
             r[q] = s[q] - om * t[q];
         }
-        if (vmaxabs(r, N3) <= tol) {
+        double rn = vmaxabs(r, N3);
+        if (!isfinite(rn)) {
+            ret = OR_ENAN;
+            break;
+        }
+        if (rn <= tol) {
             ret = OR_OK;
             break;
         }

@@ -74,7 +74,7 @@ typedef struct {
     double div_proj[2];
 } or_stats;
 
-enum { OR_OK = 0, OR_EINVAL = -1, OR_EGEOM = -2, OR_ENOCONV = -3 };
+enum { OR_OK = 0, OR_EINVAL = -1, OR_EGEOM = -2, OR_ENOCONV = -3, OR_ENAN = -4 };
 
 typedef struct or_geom or_geom;
 
