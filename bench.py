@@ -7,9 +7,12 @@ steps advance the flow, then K steps are timed with the state resident in HBM; e
 the whole path (derived quantities with the MAC projection, the implicit viscous multigrid solve
 and the end-of-stage projection, twice).  MLUPS = n^3 * K / t / 1e6.
 
-Also reported: the roofline of the dominant kernel (the finest-level red-black smoother of the
-viscous multigrid), timed live with HIP events on the stream it runs on, and the FP64 oracle
-timed on the host cores on a bounded sample.  Prints one JSON line.
+Also reported: the same steps in the other precision (mixed: FP32 multigrid inside the FP64
+Krylov iteration) from the same start state, with its difference from the FP64 run; the roofline
+of the dominant kernel (the finest-level red-black smoother of the viscous multigrid), timed live
+with HIP events on the stream it runs on, and of the whole step from the bytes of the passes it
+executed; and the FP64 oracle timed on the host cores on a bounded sample (all threads, and one
+thread on the 64^3 version).  Prints one JSON line.
 """
 import argparse
 import json
@@ -32,6 +35,10 @@ def parse():
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--n", type=int, default=128, help="cells per direction (default 128)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-single-thread", action="store_true",
+                    help="skip the single-thread oracle figure of the CPU baseline")
+    ap.add_argument("--single-precision", action="store_true",
+                    help="time only the --precision run (default: also the other precision)")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only the smoother timing loop (for the profiler)")
     ap.add_argument("--sweeps", type=int, default=40)
@@ -254,11 +261,24 @@ def adjoint_fd(api, ctx, w, o, rheo, u0, p0, theta, g_bi, g_theta, nsteps, ncell
     return res
 
 
+def cpu_model():
+    """The host CPU's model name (lscpu), or the platform's processor string."""
+    import platform
+    import subprocess
+
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except Exception:  # noqa: BLE001 - a missing lscpu only loses the label
+        pass
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(w, u0, p0, n_steps=1):
     """The FP64 oracle (as it stands) on the host cores: one RK2 step of the same workload from
-    the same state.  Returns MLUPS and the thread count it used."""
-    import numpy as np  # noqa: F401
-
+    the same state.  Returns MLUPS, the thread count it used and the seconds it took."""
     from oracle import oracle as O
 
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
@@ -272,6 +292,114 @@ def cpu_baseline(w, u0, p0, n_steps=1):
         u, p, st = og.rk2_step(u, p, rh, w.dt, opts)
     t = time.perf_counter() - t0
     return w.ncell * n_steps / t / 1e6, threads, t
+
+
+def cpu_baseline_single_thread(w):
+    """The oracle on one host thread, one step of the 64^3 version of the workload (same body,
+    law and time step) from the uniform start: about 20 s.  Runs in a child process because the
+    oracle's OpenMP runtime fixes its thread count when it first starts."""
+    import subprocess
+
+    n = 64
+    code = ("import sys, time, json; sys.path.insert(0, %r)\n"
+            "import numpy as np, eb_inputs as I\n"
+            "from oracle import oracle as O\n"
+            "w = I.sphere128().replace(n=(%d,)*3, h=1.0/%d, name='sphere%d')\n"
+            "g = O.Geometry(w); u = I.initial_velocity(w); p = np.zeros(g.shape)\n"
+            "t = time.perf_counter(); g.rk2_step(u, p, O.make_rheo(w), w.dt, O.make_opts(w))\n"
+            "print(json.dumps({'s': time.perf_counter() - t, 'cells': w.ncell}))\n"
+            % (ROOT, n, n, n))
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
+                       timeout=600)
+    res = json.loads(r.stdout.strip().splitlines()[-1])
+    return res["cells"] / res["s"] / 1e6, res["s"], n
+
+
+# Algorithmic bytes per fine cell of the passes one step executes (the scope table's byte model,
+# with the Krylov vector passes counted as well); w = 8 (FP64) or 4 (FP32).  A multigrid V(2,2)
+# over all levels: 553 B (viscous, three components) and 174 B (Poisson) in FP64.  In mixed
+# precision the levels of at least 64^3 cells run in FP32 (484 -> 245 and 152 -> 79 B per cell
+# of the level) and the smaller ones in FP64, which gives 284 and 91 B at 128^3.  Per BiCGSTAB
+# half iteration (one V-cycle): an EB operator application (u in, eta, flag, out: 7w + 1) and
+# its share of the vector updates and dot products (s = r - alpha v, x and r updates, p update,
+# four dot products over 3-component vectors): 285 B.  Per CG iteration (one V-cycle): the
+# Poisson application (2w + 1), x and r updates, p update, two dot products: 121 B.  Per step,
+# outside the solves: face extrapolation, the derived quantities, psi assembly and the
+# projection wrap of both stages, about 1100 B.
+VCYCLE_BYTES = {"fp64": {"visc": 553.0, "poisson": 174.0},
+                "mixed": {"visc": 284.0, "poisson": 91.0}}
+KRYLOV_BYTES = {"visc": 285.0, "poisson": 121.0}
+STEP_FIXED_BYTES = 1100.0
+
+
+def step_bytes(stats, ncell, tag):
+    """Algorithmic bytes of one step from its executed V-cycle counts."""
+    n_poisson = sum(stats["it_mac"]) + sum(stats["it_proj"])
+    n_visc = stats["vcycles"] - n_poisson
+    per_cell = (n_visc * (VCYCLE_BYTES[tag]["visc"] + KRYLOV_BYTES["visc"])
+                + n_poisson * (VCYCLE_BYTES[tag]["poisson"] + KRYLOV_BYTES["poisson"])
+                + STEP_FIXED_BYTES)
+    return per_cell * ncell, n_visc, n_poisson
+
+
+def run_steps(api, torch, I, pkg, w, prec, args, start=None):
+    """Builds a context for `prec`, runs the warm-up steps from the workload's start, then times
+    args.steps steps from `start` (the warm-up's end state when None).  Returns the timing, the
+    stats of every timed step, the start and end states and the context."""
+    box, body, rheo, opts = pkg.from_workload(w, precision=prec)
+    opts.nu1 = opts.nu2 = args.nu
+    opts.nbottom = args.nbottom
+    dev = torch.device("cuda:0")
+    ctx = api.eb_geometry_build(box, body, dev)
+    u = torch.from_numpy(I.initial_velocity(w)).to(dev)
+    p = torch.zeros(ctx.shape, dtype=torch.float64, device=dev)
+    tag = "fp64" if prec == api.EB_FP64 else "mixed"
+    for s in range(args.warmup):
+        u, p, st = api.eb_rk2_step(ctx, rheo, w.dt, opts, u, p, inplace=True)
+        print(f"[bench] {tag} warmup step {s}: {st}", file=sys.stderr, flush=True)
+    if start is not None:
+        u.copy_(start[0])
+        p.copy_(start[1])
+    u0, p0 = u.clone(), p.clone()
+    stats = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        u, p, st = api.eb_rk2_step(ctx, rheo, w.dt, opts, u, p, inplace=True)
+        stats.append(st)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    ms_step = 1e3 * t / args.steps
+    mlups = w.ncell * args.steps / t / 1e6
+    print(f"[bench] {tag} timed {args.steps} steps: {ms_step:.2f} ms/step, {mlups:.1f} MLUPS; "
+          f"last stats {stats[-1]}", file=sys.stderr, flush=True)
+    bsum = nv = npo = 0
+    for st in stats:
+        b, a, c = step_bytes(st, w.ncell, tag)
+        bsum, nv, npo = bsum + b, nv + a, npo + c
+    bstep = bsum / args.steps
+    step_roof = {"bytes_per_step": int(bstep),
+                 "vcycles_per_step": {"viscous": nv / args.steps, "poisson": npo / args.steps},
+                 "achieved": round(bstep / (ms_step * 1e-3) / 1e9, 1),
+                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                 "frac": round(bstep / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    return {"ms_step": ms_step, "mlups": mlups, "stats": stats, "u0": u0, "p0": p0, "u": u,
+            "p": p, "ctx": ctx, "rheo": rheo, "opts": opts, "step_roofline": step_roof}
+
+
+def smoother_roofline(api, torch, run, w, prec, args):
+    """The finest-level viscous smoother with the operator of the run's final state: average
+    launch time (HIP events) and the fraction of HBM peak on algorithmic bytes."""
+    ctx, rheo, opts, u = run["ctx"], run["rheo"], run["opts"], run["u"]
+    eta, eta_eb = api.eb_apparent_viscosity(ctx, rheo, u)
+    api.eb_mg_vcycle(ctx, api.EB_SYS_VISC, torch.zeros_like(u), opts, precision=prec, rho=w.rho,
+                     dt=w.dt, eta=eta, eta_eb=eta_eb)
+    ms_k = time_smoother(api, ctx, prec, args.sweeps, torch)
+    wbytes = 4 if prec == api.EB_MIXED else 8
+    algo = smoother_bytes_per_launch(ctx.N, 3, wbytes)
+    achieved = algo / (ms_k * 1e-3) / 1e9
+    return ms_k, algo, achieved
 
 
 def main():
@@ -291,16 +419,13 @@ def main():
     if args.n != 128:
         w = w.replace(n=(args.n,) * 3, h=1.0 / args.n, name=f"sphere{args.n}")
     prec = api.EB_MIXED if args.precision == "mixed" else api.EB_FP64
-    box, body, rheo, opts = pkg.from_workload(w, precision=prec)
-    opts.nu1 = opts.nu2 = args.nu
-    opts.nbottom = args.nbottom
     dev = torch.device("cuda:0")
-    ctx = api.eb_geometry_build(box, body, dev)
-    u = torch.from_numpy(I.initial_velocity(w)).to(dev)
-    p = torch.zeros(ctx.shape, dtype=torch.float64, device=dev)
 
     if args.kernel_only:
         # build the viscous operator of the start state, then only the smoother loop
+        box, body, rheo, opts = pkg.from_workload(w, precision=prec)
+        ctx = api.eb_geometry_build(box, body, dev)
+        u = torch.from_numpy(I.initial_velocity(w)).to(dev)
         eta, eta_eb = api.eb_apparent_viscosity(ctx, rheo, u)
         r = torch.zeros_like(u)
         api.eb_mg_vcycle(ctx, api.EB_SYS_VISC, r, opts, precision=prec, rho=w.rho, dt=w.dt,
@@ -319,59 +444,76 @@ def main():
 
     print(f"[bench] {w.name} n={w.n} precision={args.precision} warmup={args.warmup} "
           f"steps={args.steps}", file=sys.stderr, flush=True)
-    stats = []
-    for s in range(args.warmup):
-        u, p, st = api.eb_rk2_step(ctx, rheo, w.dt, opts, u, p, inplace=True)
-        print(f"[bench] warmup step {s}: {st}", file=sys.stderr, flush=True)
-    u0_host = u.cpu().numpy().copy()
-    p0_host = p.cpu().numpy().copy()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(args.steps):
-        u, p, st = api.eb_rk2_step(ctx, rheo, w.dt, opts, u, p, inplace=True)
-        stats.append(st)
-    torch.cuda.synchronize()
-    t = time.perf_counter() - t0
-    ms_step = 1e3 * t / args.steps
-    mlups = w.ncell * args.steps / t / 1e6
-    print(f"[bench] timed {args.steps} steps: {ms_step:.2f} ms/step, {mlups:.1f} MLUPS; "
-          f"last stats {stats[-1]}", file=sys.stderr, flush=True)
+    main_run = run_steps(api, torch, I, pkg, w, prec, args)
+    other_prec = api.EB_FP64 if prec == api.EB_MIXED else api.EB_MIXED
+    other = None
+    if not args.single_precision:
+        # the other precision, timed over the same steps from the same start state
+        other = run_steps(api, torch, I, pkg, w, other_prec, args,
+                          start=(main_run["u0"], main_run["p0"]))
+    u0_host = main_run["u0"].cpu().numpy().copy()
+    p0_host = main_run["p0"].cpu().numpy().copy()
 
-    # roofline of the dominant kernel: the finest-level viscous smoother, with the viscous
-    # operator of the final state (one V-cycle builds it)
-    eta, eta_eb = api.eb_apparent_viscosity(ctx, rheo, u)
-    api.eb_mg_vcycle(ctx, api.EB_SYS_VISC, torch.zeros_like(u), opts, precision=prec, rho=w.rho,
-                     dt=w.dt, eta=eta, eta_eb=eta_eb)
-    ms_k = time_smoother(api, ctx, prec, args.sweeps, torch)
-    wbytes = 4 if prec == api.EB_MIXED else 8
-    algo = smoother_bytes_per_launch(ctx.N, 3, wbytes)
-    achieved = algo / (ms_k * 1e-3) / 1e9
+    # roofline of the dominant kernel: the finest-level viscous smoother
+    ms_k, algo, achieved = smoother_roofline(api, torch, main_run, w, prec, args)
     traffic = counted_traffic("fp64" if prec == api.EB_FP64 else "mixed") if args.n == 128 else None
-    copy_gbs = copy_bandwidth(ctx, torch)
+    copy_gbs = copy_bandwidth(main_run["ctx"], torch)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "k_smooth_rb (finest level, 3 components, one colour)",
                 "kernel_ms": round(ms_k, 5), "bytes_per_launch": int(algo),
                 "device_copy_gbs": round(copy_gbs, 1),
-                "frac_of_device_copy": round(achieved / copy_gbs, 4)}
-
-    out = {"metric": METRIC, "value": round(mlups, 3), "unit": "MLUPS", "n_gpus": 1,
-           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+                "frac_of_device_copy": round(achieved / copy_gbs, 4),
+                "step": main_run["step_roofline"]}
+    st_last = main_run["stats"][-1]
+    out = {"metric": METRIC, "value": round(main_run["mlups"], 3), "unit": "MLUPS", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(main_run["ms_step"], 3),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f64" if prec == api.EB_FP64 else "f64+f32-mg",
            "data": "synthetic",
            "config": {"workload": f"{w.name}: {w.n[0]}^3 box, EB sphere r=0.125, walls (0,0,-1),"
                                   f" eta=1+10/(|g|+1e-6), rho=4e-3, dt=5e-4, rtol=1e-12",
                       "cells": w.ncell, "precision": args.precision,
-                      "dt": w.dt, "dt_stability_rule": stats[-1]["dt_stable"],
-                      "iterations_last_step": {k: stats[-1][k] for k in
+                      "dt": w.dt, "dt_stability_rule": st_last["dt_stable"],
+                      "iterations_last_step": {k: st_last[k] for k in
                                                ("it_mac", "it_visc", "it_proj", "vcycles")}},
            "roofline": roofline}
+    if other is not None:
+        # the other precision's line: speed, step roofline, smoother, and its difference from
+        # the headline run after the same steps from the same state (relative L2 over open cells)
+        ms_o, algo_o, ach_o = smoother_roofline(api, torch, other, w, other_prec, args)
+        _, alpha, _, _, _ = api.eb_geometry_export(main_run["ctx"])
+        op = alpha > 0
+        a, b = (other, main_run) if other_prec == api.EB_MIXED else (main_run, other)
+        errs = {}
+        for j, name in enumerate("uvw"):
+            errs[name] = (torch.linalg.norm((a["u"][j] - b["u"][j])[op])
+                          / torch.linalg.norm(b["u"][j][op])).item()
+        errs["p"] = (torch.linalg.norm((a["p"] - b["p"])[op]) / torch.linalg.norm(b["p"][op])).item()
+        Fa = api.eb_drag(a["ctx"], a["rheo"], a["u"], a["p"])
+        Fb = api.eb_drag(b["ctx"], b["rheo"], b["u"], b["p"])
+        errs["F_z"] = abs(Fa[2] - Fb[2]) / abs(Fb[2])
+        tag = "mixed" if other_prec == api.EB_MIXED else "fp64"
+        so = other["stats"][-1]
+        out[tag] = {"ms_per_step": round(other["ms_step"], 3), "value": round(other["mlups"], 3),
+                    "unit": "MLUPS", "speedup_vs_headline": round(main_run["ms_step"]
+                                                                  / other["ms_step"], 4),
+                    "step_roofline": other["step_roofline"],
+                    "smoother": {"kernel_ms": round(ms_o, 5), "bytes_per_launch": int(algo_o),
+                                 "achieved": round(ach_o, 1),
+                                 "frac": round(ach_o / HBM_PEAK_GBS, 4)},
+                    "rel_err_mixed_vs_fp64": errs, "fp64_fallbacks": so["fp64_fallbacks"],
+                    "iterations_last_step": {k: so[k] for k in
+                                             ("it_mac", "it_visc", "it_proj", "vcycles")}}
+        print(f"[bench] {tag}: {out[tag]}", file=sys.stderr, flush=True)
+    ctx = main_run["ctx"]
     if args.adjoint_steps > 0:
         from paper_1905_07392_amd import autograd as AG
 
-        adj = adjoint_ratio(api, AG, ctx, w, opts, args.adjoint_steps, args.ckpt_every, torch, I,
-                            fd_cells=args.adjoint_fd, fd_steps=args.adjoint_fd_steps)
+        adj = adjoint_ratio(api, AG, ctx, w, main_run["opts"], args.adjoint_steps,
+                            args.ckpt_every, torch, I, fd_cells=args.adjoint_fd,
+                            fd_steps=args.adjoint_fd_steps)
         out["adjoint"] = adj
         print(f"[bench] adjoint: {adj}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
@@ -379,7 +521,14 @@ def main():
         out["cpu_baseline"] = {"value": round(val, 4), "unit": "MLUPS", "cores": cores,
                                "kind": "oracle",
                                "sample": f"one FP64 RK2 step of the same {w.n[0]}^3 workload "
-                                         f"from the same state ({tcpu:.1f} s)"}
+                                         f"from the same state ({tcpu:.1f} s)",
+                               "cpu_model": cpu_model()}
+        if not args.no_single_thread:
+            v1, t1, n1 = cpu_baseline_single_thread(w)
+            out["cpu_baseline"]["single_thread"] = {
+                "value": round(v1, 4), "unit": "MLUPS", "cores": 1,
+                "sample": f"one FP64 RK2 step of the {n1}^3 version of the workload from the "
+                          f"uniform start on one thread ({t1:.1f} s)"}
     print(json.dumps(out), flush=True)
 
 

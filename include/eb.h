@@ -49,9 +49,11 @@ enum {
 
 /* Bodies (the fluid is where the level set is > 0).  CYLINDER: an infinitely long circular
  * cylinder of radius radii[0] whose axis runs along y through `center` (the body of Sec. V.C,
- * "Cylinder moving through Bingham fluid"). */
+ * "Cylinder moving through Bingham fluid").  CAVITY: the fluid fills a sphere of radius
+ * radii[0] about `center` and the body is everything outside it (a concave wall: its wall-flux
+ * stencils reach across the cavity and take the covered-node fallback at coarse resolution). */
 enum { EB_BODY_NONE = 0, EB_BODY_SPHERE = 1, EB_BODY_ELLIPSOID = 2, EB_BODY_ZSLAB = 3,
-       EB_BODY_PLANE = 4, EB_BODY_CYLINDER = 5 };
+       EB_BODY_PLANE = 4, EB_BODY_CYLINDER = 5, EB_BODY_CAVITY = 6 };
 
 /* Apparent-viscosity laws (Sec. II.B, Table rheology; Eq. papabing:viscosity), with
  * g = |gamma| the strain-rate norm and P(g) = kappa s^(n-1) the power-law term, where s = g, or
@@ -316,19 +318,27 @@ int eb_rk2_step_taped(eb_ctx* ctx, const eb_rheology* rheo, const double* theta,
 /* Adjoint of one RK2 step (Alg. advance).  u0 (device) [3][N]: the step's input velocity;
  * tape: recorded by eb_rk2_step_taped from u0 with the same rheo, theta, dt and opts.
  * ub [3][N], pb [N]: in, the adjoints of the step's output (u, p); out, those of its input
- * (overwritten).  tau0b [N]: accumulated.  stats (host, nullable): iterations of the six
- * transposed solves (it_mac: adjoint MAC projections, it_visc: transposed viscous solves,
- * it_proj: adjoint end-of-stage projections).  Errors as eb_rk2_step. */
+ * (overwritten).  The step's yield-stress adjoint, with tau0_c = rheo->tau0 * theta_c
+ * (theta null = 1), is added into whichever of these is not null:
+ *   tau0b   (device) [N]  d(loss)/d(tau0_c) per cell;
+ *   thetab  (device) [N]  d(loss)/d(theta_c) = tau0 * tau0b_c;
+ *   tau0bar (host) [1]    d(loss)/d(tau0) = sum_c theta_c tau0b_c, a fixed-order reduction
+ *                         (the Bingham-number derivative when mu, U and L are 1); the call
+ *                         then waits for its work.
+ * stats (host, nullable): iterations of the six transposed solves (it_mac: adjoint MAC
+ * projections, it_visc: transposed viscous solves, it_proj: adjoint end-of-stage projections).
+ * Errors as eb_rk2_step. */
 int eb_rk2_step_adjoint(eb_ctx* ctx, const eb_rheology* rheo, const double* theta, double dt,
                         const eb_step_opts* opts, const double* u0, const void* tape,
-                        double* ub, double* pb, double* tau0b, eb_step_stats* stats,
-                        void* stream);
+                        double* ub, double* pb, double* tau0b, double* thetab,
+                        double* tau0bar, eb_step_stats* stats, void* stream);
 
-/* Adjoint of eb_drag (Eq. drag-force) at (u, p): fbar (host) [3] = d(loss)/dF; ub [3][N],
- * pb [N] and tau0b [N] accumulate (pb is set to zero on covered cells). */
+/* Adjoint of eb_drag (Eq. drag-force) at (u, p): fbar (host) [3] = d(loss)/dF; ub [3][N] and
+ * pb [N] accumulate (pb is set to zero on covered cells); the yield-stress adjoint goes to
+ * tau0b, thetab and tau0bar (each nullable, accumulated) as in eb_rk2_step_adjoint. */
 int eb_drag_adjoint(const eb_ctx* ctx, const eb_rheology* rheo, const double* theta,
                     const double* u, const double fbar[3], double* ub, double* pb,
-                    double* tau0b, void* stream);
+                    double* tau0b, double* thetab, double* tau0bar, void* stream);
 
 /* Adjoint of eb_mac_project on its face field: fbx, fby, fbz (device) in, the adjoint of the
  * projected field; out, that of the input field.  One Poisson solve to rtol. */

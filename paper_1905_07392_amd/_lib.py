@@ -77,8 +77,8 @@ SIGNATURES = {
     "eb_pressure_gradient": (_I, [_P, _P, _P, _P]),
     "eb_tape_bytes": (C.c_size_t, [_P]),
     "eb_rk2_step_taped": (_I, [_P, _P, _P, _D, _P, _P, _P, _P, _P, _P]),
-    "eb_rk2_step_adjoint": (_I, [_P, _P, _P, _D, _P, _P, _P, _P, _P, _P, _P, _P]),
-    "eb_drag_adjoint": (_I, [_P, _P, _P, _P, _DP, _P, _P, _P, _P]),
+    "eb_rk2_step_adjoint": (_I, [_P, _P, _P, _D, _P, _P, _P, _P, _P, _P, _P, _DP, _P, _P]),
+    "eb_drag_adjoint": (_I, [_P, _P, _P, _P, _DP, _P, _P, _P, _P, _DP, _P]),
     "eb_mac_project_adjoint": (_I, [_P, _D, _P, _P, _P, _D, _P, _IP, _P]),
     "eb_cc_project_adjoint": (_I, [_P, _D, _P, _P, _D, _P, _IP, _P]),
     "eb_visc_solve_adjoint": (_I, [_P, _D, _D, _P, _P, _P, _P, _D, _P, _P, _P, _P, _IP, _P]),

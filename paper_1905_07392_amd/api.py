@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import ctypes as C
 
+import numpy as np
 import torch
 
 from . import _lib as L
@@ -363,36 +364,58 @@ def eb_rk2_step_taped(ctx: EbContext, rheo: EbRheology, dt, opts: EbStepOpts, u,
     return u, p, _stats(st)
 
 
+def _host_acc(acc):
+    """A float64 numpy array of one element that the library adds d(loss)/d(tau0) into."""
+    if acc is None:
+        acc = np.zeros(1)
+    if not (isinstance(acc, np.ndarray) and acc.dtype == np.float64 and acc.size == 1
+            and acc.flags["C_CONTIGUOUS"]):
+        raise ValueError("tau0bar must be a contiguous float64 numpy array of one element")
+    return acc, acc.ctypes.data_as(C.POINTER(C.c_double))
+
+
 def eb_rk2_step_adjoint(ctx: EbContext, rheo: EbRheology, dt, opts: EbStepOpts, u0, tape, ub,
-                        pb, theta=None, tau0b=None):
-    """Adjoint of the step taped from u0.  Returns (ub_in, pb_in, tau0b, stats); tau0b is
-    accumulated into the given tensor when one is passed."""
+                        pb, theta=None, tau0b=None, thetab=None, tau0bar=None):
+    """Adjoint of the step taped from u0.  Returns (ub_in, pb_in, tau0b, stats).  The step's
+    yield-stress adjoint is added into tau0b (per cell; a new zero tensor when None), into
+    thetab (d/d theta per cell, when given) and into tau0bar (a one-element float64 numpy
+    array, d/d tau0, when given); stats["tau0bar"] is that array's value after the call."""
     ub = ub.clone().contiguous()
     pb = pb.clone().contiguous()
     tb = ctx.scalar() if tau0b is None else tau0b
     st = EbStepStats()
     th = _f64(theta, ctx.shape, "theta") if theta is not None else None
+    thb = _f64(thetab, ctx.shape, "thetab") if thetab is not None else None
+    acc, accp = _host_acc(tau0bar)
     check(L.lib().eb_rk2_step_adjoint(ctx.ptr, C.byref(rheo), th, float(dt), C.byref(opts),
                                       _f64(u0, (3,) + ctx.shape, "u0"), _p(tape),
                                       _f64(ub, (3,) + ctx.shape, "ub"),
                                       _f64(pb, ctx.shape, "pb"), _f64(tb, ctx.shape, "tau0b"),
-                                      C.byref(st), _stream(ctx.device)), "eb_rk2_step_adjoint")
-    return ub, pb, tb, _stats(st)
+                                      thb, accp, C.byref(st), _stream(ctx.device)),
+          "eb_rk2_step_adjoint")
+    stats = _stats(st)
+    stats["tau0bar"] = float(acc[0])
+    return ub, pb, tb, stats
 
 
 def eb_drag_adjoint(ctx: EbContext, rheo: EbRheology, u, fbar, theta=None, ub=None, pb=None,
-                    tau0b=None):
-    """Adjoint of eb_drag at u; (ub, pb, tau0b) accumulate into the tensors given (or zeros)."""
+                    tau0b=None, thetab=None, tau0bar=None):
+    """Adjoint of eb_drag at u; (ub, pb, tau0b) accumulate into the tensors given (or zeros),
+    thetab (d/d theta per cell) and tau0bar (one-element float64 numpy array, d/d tau0) when
+    given.  Returns (ub, pb, tau0b, d/d tau0 after the call)."""
     ub = ctx.vec() if ub is None else ub
     pb = ctx.scalar() if pb is None else pb
     tb = ctx.scalar() if tau0b is None else tau0b
     fb = (C.c_double * 3)(*[float(x) for x in fbar])
     th = _f64(theta, ctx.shape, "theta") if theta is not None else None
+    thb = _f64(thetab, ctx.shape, "thetab") if thetab is not None else None
+    acc, accp = _host_acc(tau0bar)
     check(L.lib().eb_drag_adjoint(ctx.ptr, C.byref(rheo), th, _f64(u, (3,) + ctx.shape, "u"), fb,
                                   _f64(ub, (3,) + ctx.shape, "ub"), _f64(pb, ctx.shape, "pb"),
-                                  _f64(tb, ctx.shape, "tau0b"), _stream(ctx.device)),
+                                  _f64(tb, ctx.shape, "tau0b"), thb, accp,
+                                  _stream(ctx.device)),
           "eb_drag_adjoint")
-    return ub, pb, tb
+    return ub, pb, tb, float(acc[0])
 
 
 def eb_mac_project_adjoint(ctx: EbContext, fb, beta, opts: EbStepOpts, rtol=None):

@@ -3,8 +3,9 @@
 The reverse sweep is the library's own hand-written adjoint (eb_rk2_step_adjoint,
 eb_drag_adjoint); these classes only route tensors.  The yield stress is split as
 tau0_c = tau0 * theta_c: `tau0` is a 0-d float64 tensor (the Bingham number when mu, U and L are
-1) and `theta` the per-cell multiplier, so autograd returns d/d tau0 = sum_c theta_c tau0b_c and
-d/d theta_c = tau0 tau0b_c from the library's per-cell yield-stress adjoint tau0b.
+1) and `theta` the per-cell multiplier (None means 1 everywhere; its gradient is then None).  The
+library itself forms d/d tau0 = sum_c theta_c tau0b_c (into a host accumulator) and
+d/d theta_c = tau0 tau0b_c (into a device tensor) from its per-cell yield-stress adjoint tau0b.
 
 * ``EbRK2Step``  one step; keeps that step's tape (eb_tape_bytes of device memory) until backward.
 * ``EbRollout``  n steps with step checkpointing: forward keeps (u, p) every ``ckpt_every`` steps;
@@ -14,6 +15,7 @@ d/d theta_c = tau0 tau0b_c from the library's per-cell yield-stress adjoint tau0
 """
 from __future__ import annotations
 
+import numpy as np
 import torch
 
 from . import api
@@ -29,6 +31,17 @@ def _rheo_with(rheo, tau0: float):
 
 def _zeros_like_or(g, like):
     return torch.zeros_like(like) if g is None else g.contiguous()
+
+
+def _yield_outputs(theta, tau0):
+    """The buffers the library adds the yield-stress gradients into: d/d theta (a device
+    tensor, or None without a theta field) and d/d tau0 (a one-element host array)."""
+    thetab = torch.zeros_like(theta) if theta is not None else None
+    return thetab, np.zeros(1)
+
+
+def _tau0_grad(acc, tau0):
+    return torch.from_numpy(acc.reshape(())).to(dtype=torch.float64, device=tau0.device)
 
 
 class EbRK2Step(torch.autograd.Function):
@@ -47,10 +60,12 @@ class EbRK2Step(torch.autograd.Function):
         u, theta, tau0 = fctx.saved_tensors
         ub = _zeros_like_or(gu, u)
         pb = _zeros_like_or(gp, u[0])
-        ub, pb, tb, _ = api.eb_rk2_step_adjoint(fctx.ectx, fctx.rh, fctx.dt, fctx.opts, u,
-                                                fctx.tape, ub, pb, theta=theta)
+        thetab, acc = _yield_outputs(theta, tau0)
+        ub, pb, _, _ = api.eb_rk2_step_adjoint(fctx.ectx, fctx.rh, fctx.dt, fctx.opts, u,
+                                               fctx.tape, ub, pb, theta=theta, thetab=thetab,
+                                               tau0bar=acc)
         fctx.tape = None
-        return ub, pb, tau0 * tb, (theta * tb).sum(), None, None, None, None
+        return ub, pb, thetab, _tau0_grad(acc, tau0), None, None, None, None
 
 
 class EbRollout(torch.autograd.Function):
@@ -75,7 +90,8 @@ class EbRollout(torch.autograd.Function):
         n, every = fctx.nsteps, fctx.every
         ub = _zeros_like_or(gu, fctx.ckpts[0][0])
         pb = _zeros_like_or(gp, fctx.ckpts[0][1])
-        tb = ectx.scalar()
+        thetab, acc = _yield_outputs(theta, tau0)
+        tb = ectx.scalar()  # per-cell adjoint the library accumulates; not returned
         tapes = [api.new_tape(ectx) for _ in range(min(every, n))]
         for seg in range(len(fctx.ckpts) - 1, -1, -1):
             s0 = seg * every
@@ -89,9 +105,9 @@ class EbRollout(torch.autograd.Function):
             for s in range(s1 - 1, s0 - 1, -1):
                 ub, pb, _, _ = api.eb_rk2_step_adjoint(ectx, rh, dt, opts, inputs[s - s0],
                                                        tapes[s - s0], ub, pb, theta=theta,
-                                                       tau0b=tb)
+                                                       tau0b=tb, thetab=thetab, tau0bar=acc)
         fctx.ckpts = None
-        return ub, pb, tau0 * tb, (theta * tb).sum(), None, None, None, None, None, None
+        return ub, pb, thetab, _tau0_grad(acc, tau0), None, None, None, None, None, None
 
 
 class EbDrag(torch.autograd.Function):
@@ -107,8 +123,10 @@ class EbDrag(torch.autograd.Function):
     def backward(fctx, gF):
         u, theta, tau0 = fctx.saved_tensors
         fbar = [float(x) for x in gF.detach().cpu()]
-        ub, pb, tb = api.eb_drag_adjoint(fctx.ectx, fctx.rh, u, fbar, theta=theta)
-        return ub, pb, tau0 * tb, (theta * tb).sum(), None, None
+        thetab, acc = _yield_outputs(theta, tau0)
+        ub, pb, _, _ = api.eb_drag_adjoint(fctx.ectx, fctx.rh, u, fbar, theta=theta,
+                                           thetab=thetab, tau0bar=acc)
+        return ub, pb, thetab, _tau0_grad(acc, tau0), None, None
 
 
 def rk2_step(ectx, rheo, dt, opts, u, p, theta, tau0):

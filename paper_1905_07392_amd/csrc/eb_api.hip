@@ -30,8 +30,18 @@ int set_err(int code, const char* fmt, ...) {
     return code;
 }
 
+thread_local hipError_t g_hip_first = hipSuccess;
+thread_local const char* g_hip_first_what = "";
+
+// reports (and clears) the first failed runtime call noted since the last check, else the
+// last kernel-launch error
 int hip_check(const char* where) {
     hipError_t e = hipGetLastError();
+    if (g_hip_first != hipSuccess) {
+        hipError_t f = g_hip_first;
+        g_hip_first = hipSuccess;
+        return set_err(EB_EHIP, "%s: %s in %s", where, hipGetErrorString(f), g_hip_first_what);
+    }
     if (e != hipSuccess) return set_err(EB_EHIP, "%s: %s", where, hipGetErrorString(e));
     return EB_OK;
 }
@@ -65,6 +75,15 @@ int check_rheology(const eb_rheology& r) {
 }
 
 }  // namespace
+
+void hip_note(hipError_t e, const char* what) {
+    if (e != hipSuccess && g_hip_first == hipSuccess) {
+        g_hip_first = e;
+        g_hip_first_what = what;
+    }
+}
+
+bool hip_failed() { return g_hip_first != hipSuccess; }
 
 namespace {
 constexpr int NSLOT = 8;
@@ -120,6 +139,7 @@ struct eb_ctx {
     int *wt_map, *wt_ptr, *wt_ent;
     WallT wt;
     double *Gb, *ubm, *lam, *ehb, *ebhb, *rX, *rY, *gwb;
+    double* tbs;  // the per-cell yield-stress adjoint of one reverse call, before it is handed out
     double* ufb[3];
     LRV lr;
     // mixed precision: iterations a solve ran with the FP32 V-cycle before it continued with
@@ -252,6 +272,7 @@ size_t carve(eb_ctx* c, char* base, bool dry) {
     c->rX = cv.take<double>(3 * M);
     c->rY = cv.take<double>(3 * M);
     c->gwb = cv.take<double>(3 * M);
+    c->tbs = cv.take<double>(N);
     for (int d = 0; d < 3; d++) {
         c->ufb[d] = cv.take<double>(face_count(g, d));
         c->lr.L[d] = cv.take<double>(3 * face_count(g, d));
@@ -294,7 +315,7 @@ int build_wall_transpose(eb_ctx* c) {
     std::vector<int> map(N, -1);
     std::vector<int> ptr(1, 0), ent;
     if (nc > 0) {
-        (void)hipMemcpy(sidx.data(), c->sidx, sidx.size() * sizeof(int), hipMemcpyDeviceToHost);
+        HIPN(hipMemcpy(sidx.data(), c->sidx, sidx.size() * sizeof(int), hipMemcpyDeviceToHost));
         std::vector<std::pair<int, int>> pairs;
         pairs.reserve(sidx.size());
         for (size_t e = 0; e < sidx.size(); e++)
@@ -311,10 +332,10 @@ int build_wall_transpose(eb_ctx* c) {
         ptr.push_back((int)pairs.size());
         if (pairs.empty()) ptr.assign(1, 0);
     }
-    (void)hipMemcpy(c->wt_map, map.data(), N * sizeof(int), hipMemcpyHostToDevice);
-    (void)hipMemcpy(c->wt_ptr, ptr.data(), ptr.size() * sizeof(int), hipMemcpyHostToDevice);
+    HIPN(hipMemcpy(c->wt_map, map.data(), N * sizeof(int), hipMemcpyHostToDevice));
+    HIPN(hipMemcpy(c->wt_ptr, ptr.data(), ptr.size() * sizeof(int), hipMemcpyHostToDevice));
     if (!ent.empty())
-        (void)hipMemcpy(c->wt_ent, ent.data(), ent.size() * sizeof(int), hipMemcpyHostToDevice);
+        HIPN(hipMemcpy(c->wt_ent, ent.data(), ent.size() * sizeof(int), hipMemcpyHostToDevice));
     c->wt.map = c->wt_map;
     c->wt.ptr = c->wt_ptr;
     c->wt.ent = c->wt_ent;
@@ -346,7 +367,7 @@ int init_ctx(eb_ctx* c, const eb_box* box, const eb_body* body) {
         if (box->n[d] < 2 || box->n[d] % 2)
             return set_err(EB_EINVAL, "n[%d]=%d must be an even number >= 2", d, box->n[d]);
     if (!(box->h > 0.0)) return set_err(EB_EINVAL, "h must be positive");
-    if (body->kind < EB_BODY_NONE || body->kind > EB_BODY_CYLINDER)
+    if (body->kind < EB_BODY_NONE || body->kind > EB_BODY_CAVITY)
         return set_err(EB_EINVAL, "unknown body kind %d", body->kind);
     memset(c, 0, sizeof(*c));
     c->built_sys = -1;
@@ -365,7 +386,8 @@ int init_ctx(eb_ctx* c, const eb_box* box, const eb_body* body) {
     for (int d = 0; d < 3; d++) {
         b.lo[d] = box->lo[d];
         b.c[d] = body->center[d];
-        b.r[d] = (body->kind == EB_BODY_SPHERE || body->kind == EB_BODY_CYLINDER)
+        b.r[d] = (body->kind == EB_BODY_SPHERE || body->kind == EB_BODY_CYLINDER ||
+                  body->kind == EB_BODY_CAVITY)
                      ? body->radii[0] : body->radii[d];
         b.pn[d] = body->plane_n[d];
     }
@@ -404,9 +426,31 @@ void fill_geomv(eb_ctx* c) {
 
 // host copy of `n` reduced values
 int fetch(eb_ctx* c, double* host, int n) {
-    hipMemcpyAsync(host, c->red, n * sizeof(double), hipMemcpyDeviceToHost, c->s);
-    hipError_t e = hipStreamSynchronize(c->s);
-    if (e != hipSuccess) return set_err(EB_EHIP, "sync: %s", hipGetErrorString(e));
+    HIPN(hipMemcpyAsync(host, c->red, n * sizeof(double), hipMemcpyDeviceToHost, c->s));
+    HIPN(hipStreamSynchronize(c->s));
+    return hip_check("read-back");
+}
+
+// Hands out the yield-stress adjoint tbs of one reverse call (tau0_c = tau0 theta_c):
+// tau0b += tbs per cell, thetab += tau0 tbs (d loss / d theta_c), and *tau0bar (host) +=
+// sum_c theta_c tbs_c (d loss / d tau0; theta null = 1), a fixed-order reduction.
+int yield_adjoint_out(eb_ctx* c, double tau0, const double* theta, double* tau0b,
+                      double* thetab, double* tau0bar) {
+    long N = c->N;
+    if (tau0b) vec_axpby(N, 1.0, c->tbs, 1.0, tau0b, c->s);
+    if (thetab) vec_axpby(N, tau0, c->tbs, 1.0, thetab, c->s);
+    if (tau0bar) {
+        if (theta) {
+            const double* a[4] = {theta, nullptr, nullptr, nullptr};
+            const double* b[4] = {c->tbs, nullptr, nullptr, nullptr};
+            red_dots(N, 1, a, b, c->part, c->red, c->s);
+        } else {
+            red_sum(N, 1, c->tbs, c->part, c->red, c->s);
+        }
+        double v = 0.0;
+        if (int e = fetch(c, &v, 1)) return e;
+        *tau0bar += v;
+    }
     return EB_OK;
 }
 
@@ -456,7 +500,7 @@ void run_iteration(eb_ctx* c, const GraphKey& key, F&& body) {
     }
     for (auto& e : c->graphs->entries)
         if (memcmp(&e.first, &key, sizeof(GraphKey)) == 0) {
-            if (e.second) (void)hipGraphLaunch(e.second, c->s);
+            if (e.second) HIPN(hipGraphLaunch(e.second, c->s));
             else body();
             return;
         }
@@ -472,7 +516,7 @@ void run_iteration(eb_ctx* c, const GraphKey& key, F&& body) {
     }
     (void)hipGetLastError();  // a failed capture leaves no sticky error; run eagerly instead
     c->graphs->entries.emplace_back(key, exec);
-    if (exec) (void)hipGraphLaunch(exec, c->s);
+    if (exec) HIPN(hipGraphLaunch(exec, c->s));
     else body();
 }
 
@@ -482,13 +526,13 @@ struct StreamScope {
     eb_ctx* c;
     hipStream_t user;
     StreamScope(eb_ctx* ctx, void* stream) : c(ctx), user((hipStream_t)stream) {
-        hipEventRecord(c->fence_in, user);
-        hipStreamWaitEvent(c->own, c->fence_in, 0);
+        HIPN(hipEventRecord(c->fence_in, user));
+        HIPN(hipStreamWaitEvent(c->own, c->fence_in, 0));
         c->s = c->own;
     }
     ~StreamScope() {
-        hipEventRecord(c->fence_out, c->own);
-        hipStreamWaitEvent(user, c->fence_out, 0);
+        HIPN(hipEventRecord(c->fence_out, c->own));
+        HIPN(hipStreamWaitEvent(user, c->fence_out, 0));
         c->s = user;
     }
 };
@@ -518,15 +562,16 @@ void vcyc(eb_ctx* c, int ncomp, const SolveCfg& k, const double* b, double* x, c
 // after iteration it-1
 int poll_done(eb_ctx* c, int slot, int it, double* rn) {
     int b = it & 1;
-    hipMemcpyAsync(c->pin[b].st, c->kst + 2 * slot, 2 * sizeof(int), hipMemcpyDeviceToHost,
-                   c->s);
+    HIPN(hipMemcpyAsync(c->pin[b].st, c->kst + 2 * slot, 2 * sizeof(int), hipMemcpyDeviceToHost,
+                   c->s));
     if (rn)
-        hipMemcpyAsync(&c->pin[b].rn, c->ks + KS_RN, sizeof(double), hipMemcpyDeviceToHost,
-                       c->s);
-    hipEventRecord(c->ev[b], c->s);
+        HIPN(hipMemcpyAsync(&c->pin[b].rn, c->ks + KS_RN, sizeof(double), hipMemcpyDeviceToHost,
+                       c->s));
+    HIPN(hipEventRecord(c->ev[b], c->s));
     if (it < 2) return 0;
     int pb = (it - 1) & 1;
-    hipEventSynchronize(c->ev[pb]);
+    HIPN(hipEventSynchronize(c->ev[pb]));
+    if (hip_failed()) return 3;  // the runtime failed: stop; the entry point reports EB_EHIP
     if (rn) *rn = c->pin[pb].rn;
     return c->pin[pb].st[0];
 }
@@ -534,8 +579,8 @@ int poll_done(eb_ctx* c, int slot, int it, double* rn) {
 // state word of `slot` once the stream has drained
 int slot_state(eb_ctx* c, int slot) {
     int sl[2] = {0, 0};
-    hipMemcpyAsync(sl, c->kst + 2 * slot, 2 * sizeof(int), hipMemcpyDeviceToHost, c->s);
-    hipStreamSynchronize(c->s);
+    HIPN(hipMemcpyAsync(sl, c->kst + 2 * slot, 2 * sizeof(int), hipMemcpyDeviceToHost, c->s));
+    HIPN(hipStreamSynchronize(c->s));
     return sl[0];
 }
 
@@ -543,8 +588,8 @@ int slot_state(eb_ctx* c, int slot) {
 // counter: CG iterations; BiCGSTAB iterations, two applications each), stream drained
 int slot_count_now(eb_ctx* c, int slot) {
     int n = 0;
-    hipMemcpyAsync(&n, c->kst + 2 * NSLOT + slot, sizeof(int), hipMemcpyDeviceToHost, c->s);
-    hipStreamSynchronize(c->s);
+    HIPN(hipMemcpyAsync(&n, c->kst + 2 * NSLOT + slot, sizeof(int), hipMemcpyDeviceToHost, c->s));
+    HIPN(hipStreamSynchronize(c->s));
     return n;
 }
 
@@ -588,6 +633,17 @@ int iterate(eb_ctx* c, const GraphKey& key, int slot, int max_iter, Body& body, 
     return slot_state(c, slot);
 }
 
+// The preconditioned residual z minus its mean over open cells.  The Poisson system is singular
+// (constants on the fluid are its null space) and the V-cycle's output carries a constant
+// component, which in exact arithmetic only shifts the iterate by a constant (removed by the
+// final normalisation) and changes no CG coefficient; in floating point, near the tolerance it
+// dominates the search direction, whose A-product is then rounding noise times a huge step, and
+// CG breaks down.  (KS_SUM, KS_CNT are free during the iterations.)
+void cg_mean_free(eb_ctx* c, double* z, const int* gate) {
+    red_sum_open(c->g, z, c->part, c->ks + KS_SUM, c->s, gate);
+    op_shift_open(c->g, z, c->ks + KS_SUM, c->s, gate);
+}
+
 // preconditioned CG for M x = b on level 0 (operator already built), state in `slot`, from
 // the iterate in x; ks[KS_RTOL] and ks[KS_SCALE] must be set.  Returns the final state.
 int pcg(eb_ctx* c, const double* b, double* x, const SolveCfg& k, int slot) {
@@ -604,6 +660,7 @@ int pcg(eb_ctx* c, const double* b, double* x, const SolveCfg& k, int slot) {
     red_maxabs(N, 1, r, c->part, ks + KS_RN, c->s);
     ks_op(KS_INIT, ks, st, itc, c->s);
     vcyc(c, 1, k, r, z, st);
+    cg_mean_free(c, z, st);
     vec_copy(N, z, pd, c->s);
     A1[0] = r;
     B1[0] = z;
@@ -625,6 +682,7 @@ int pcg(eb_ctx* c, const double* b, double* x, const SolveCfg& k, int slot) {
         red_dots_op(N, 1, A, B, c->part, KS_PQ, KS_CG_ALPHA, ks, st, itc, c->s);
         ks_cg_xr_op(N, x, r, pd, q, c->part, ks, st, itc, c->s);
         vcyc(c, 1, k, r, z, st);
+        cg_mean_free(c, z, st);
         A[0] = r;
         B[0] = z;
         red_dots_op(N, 1, A, B, c->part, KS_RZN, KS_CG_BETA, ks, st, itc, c->s);
@@ -795,9 +853,9 @@ int bicgstab(eb_ctx* c, double rho, double dt, const double* eta, const double* 
 
 // reads `n` solve slots (state, count) after the stream drains
 int read_slots(eb_ctx* c, int n, int* host) {
-    hipMemcpyAsync(host, c->kst, 2 * n * sizeof(int), hipMemcpyDeviceToHost, c->s);
-    hipError_t e = hipStreamSynchronize(c->s);
-    if (e != hipSuccess) return set_err(EB_EHIP, "sync: %s", hipGetErrorString(e));
+    HIPN(hipMemcpyAsync(host, c->kst, 2 * n * sizeof(int), hipMemcpyDeviceToHost, c->s));
+    HIPN(hipStreamSynchronize(c->s));
+    if (int h = hip_check("solver state read-back")) return h;
     for (int q = 0; q < n; q++)  // counts include the FP32 phase of a solve that switched
         if (host[2 * q] == 2) host[2 * q + 1] += c->slot_off[q];
     return EB_OK;
@@ -980,7 +1038,7 @@ int eb_geometry_build(const eb_box* box, const eb_body* body, void* ws, size_t w
     for (int l = 1; l < c->nlev; l++) level_coarsen_geometry(c->lev[l - 1], c->lev[l], c->s);
     for (int l = 0; l < c->nlev; l++) level_mask(c->lev[l], c->s);
     int err = 0;
-    hipMemcpyAsync(&err, c->errdev, sizeof(int), hipMemcpyDeviceToHost, c->s);
+    HIPN(hipMemcpyAsync(&err, c->errdev, sizeof(int), hipMemcpyDeviceToHost, c->s));
     hipError_t he = hipStreamSynchronize(c->s);
     if (he != hipSuccess) {
         delete c;
@@ -999,8 +1057,8 @@ int eb_geometry_build(const eb_box* box, const eb_body* body, void* ws, size_t w
     c->nfallback = 0;
     if (ncut > 0) {
         int* tmp = new int[ncut];
-        hipMemcpyAsync(tmp, c->nfb, ncut * sizeof(int), hipMemcpyDeviceToHost, c->s);
-        hipStreamSynchronize(c->s);
+        HIPN(hipMemcpyAsync(tmp, c->nfb, ncut * sizeof(int), hipMemcpyDeviceToHost, c->s));
+        HIPN(hipStreamSynchronize(c->s));
         for (int q = 0; q < ncut; q++) c->nfallback += tmp[q];
         delete[] tmp;
     }
@@ -1011,8 +1069,12 @@ int eb_geometry_build(const eb_box* box, const eb_body* body, void* ws, size_t w
         return set_err(EB_EHIP, "pinned polling buffer or events: %s",
                        hipGetErrorString(hipGetLastError()));
     }
-    hipMemsetAsync(c->kst, 0, 3 * NSLOT * sizeof(int), c->s);
-    hipStreamSynchronize(c->s);
+    HIPN(hipMemsetAsync(c->kst, 0, 3 * NSLOT * sizeof(int), c->s));
+    HIPN(hipStreamSynchronize(c->s));
+    if ((e = hip_check("geometry"))) {
+        eb_ctx_destroy(c);
+        return e;
+    }
     if (hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->fence_in, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->fence_out, hipEventDisableTiming) != hipSuccess) {
@@ -1033,14 +1095,15 @@ int eb_geometry_build(const eb_box* box, const eb_body* body, void* ws, size_t w
 
 void eb_ctx_destroy(eb_ctx* ctx) {
     if (!ctx) return;
-    if (ctx->own) hipStreamSynchronize(ctx->own);
+    // teardown has no caller to report to: failures here are dropped on purpose
+    if (ctx->own) (void)hipStreamSynchronize(ctx->own);
     delete ctx->graphs;
-    if (ctx->own) hipStreamDestroy(ctx->own);
-    if (ctx->fence_in) hipEventDestroy(ctx->fence_in);
-    if (ctx->fence_out) hipEventDestroy(ctx->fence_out);
-    if (ctx->pin) hipHostFree(ctx->pin);
+    if (ctx->own) (void)hipStreamDestroy(ctx->own);
+    if (ctx->fence_in) (void)hipEventDestroy(ctx->fence_in);
+    if (ctx->fence_out) (void)hipEventDestroy(ctx->fence_out);
+    if (ctx->pin) (void)hipHostFree(ctx->pin);
     for (int b = 0; b < 2; b++)
-        if (ctx->ev[b]) hipEventDestroy(ctx->ev[b]);
+        if (ctx->ev[b]) (void)hipEventDestroy(ctx->ev[b]);
     delete ctx;
 }
 
@@ -1100,13 +1163,13 @@ int eb_geometry_export(const eb_ctx* c, uint8_t* flag, double* alpha, double* ax
                        double* az, int64_t* cut_cell, double* cut_data, void* stream) {
     if (!c) return set_err(EB_EINVAL, "null context");
     hipStream_t s = (hipStream_t)stream;
-    if (flag) hipMemcpyAsync(flag, c->flag, c->N, hipMemcpyDeviceToDevice, s);
-    if (alpha) hipMemcpyAsync(alpha, c->alpha, c->N * 8, hipMemcpyDeviceToDevice, s);
+    if (flag) HIPN(hipMemcpyAsync(flag, c->flag, c->N, hipMemcpyDeviceToDevice, s));
+    if (alpha) HIPN(hipMemcpyAsync(alpha, c->alpha, c->N * 8, hipMemcpyDeviceToDevice, s));
     double* dst[3] = {ax, ay, az};
     for (int d = 0; d < 3; d++)
         if (dst[d])
-            hipMemcpyAsync(dst[d], c->ap[d], face_count(c->grid, d) * 8, hipMemcpyDeviceToDevice,
-                           s);
+            HIPN(hipMemcpyAsync(dst[d], c->ap[d], face_count(c->grid, d) * 8, hipMemcpyDeviceToDevice,
+                           s));
     if (c->ncut > 0 && (cut_cell || cut_data))
         k_export_cut<<<grid_for(c->ncut), EB_BLOCK, 0, s>>>(c->g, c->nfb, cut_cell, cut_data);
     return hip_check("eb_geometry_export");
@@ -1213,7 +1276,8 @@ int eb_mac_project(eb_ctx* c, double beta, double* fx, double* fy, double* fz, d
     int sl[2];
     if ((h = read_slots(c, 1, sl))) return h;
     if (iters) *iters = sl[1];
-    if (div_inf) hipMemcpy(div_inf, c->divs, sizeof(double), hipMemcpyDeviceToHost);
+    if (div_inf) HIPN(hipMemcpy(div_inf, c->divs, sizeof(double), hipMemcpyDeviceToHost));
+    if ((h = hip_check("divergence read-back"))) return h;
     return slot_code(sl, "MAC projection", k.max_iter);
 }
 
@@ -1228,7 +1292,8 @@ int eb_cc_project(eb_ctx* c, double beta, double* u, double* p, double rtol,
     int sl[2];
     if ((h = read_slots(c, 1, sl))) return h;
     if (iters) *iters = sl[1];
-    if (div_inf) hipMemcpy(div_inf, c->divs, sizeof(double), hipMemcpyDeviceToHost);
+    if (div_inf) HIPN(hipMemcpy(div_inf, c->divs, sizeof(double), hipMemcpyDeviceToHost));
+    if ((h = hip_check("divergence read-back"))) return h;
     return slot_code(sl, "projection", k.max_iter);
 }
 
@@ -1275,7 +1340,8 @@ int step_status(eb_ctx* c, const SolveCfg& k, eb_step_stats* stats, bool adjoint
     double dv[8];
     int h;
     if ((h = read_slots(c, 6, sl))) return h;
-    hipMemcpy(dv, c->divs, 8 * sizeof(double), hipMemcpyDeviceToHost);
+    HIPN(hipMemcpy(dv, c->divs, 8 * sizeof(double), hipMemcpyDeviceToHost));
+    if ((h = hip_check("step statistics"))) return h;
     eb_step_stats st;
     memset(&st, 0, sizeof(st));
     int status = EB_OK;
@@ -1386,8 +1452,9 @@ int eb_rk2_step_taped(eb_ctx* c, const eb_rheology* rheo, const double* theta, d
 
 int eb_rk2_step_adjoint(eb_ctx* c, const eb_rheology* rheo, const double* theta, double dt,
                         const eb_step_opts* o, const double* u0, const void* tape, double* ub,
-                        double* pb, double* tau0b, eb_step_stats* stats, void* stream) {
-    if (!c || !rheo || !o || !u0 || !tape || !ub || !pb || !tau0b)
+                        double* pb, double* tau0b, double* thetab, double* tau0bar,
+                        eb_step_stats* stats, void* stream) {
+    if (!c || !rheo || !o || !u0 || !tape || !ub || !pb)
         return set_err(EB_EINVAL, "null argument");
     if (int e_ = check_rheology(*rheo)) return e_;
     if (!(rheo->rho > 0.0) || !(dt > 0.0)) return set_err(EB_EINVAL, "rho and dt must be > 0");
@@ -1406,6 +1473,7 @@ int eb_rk2_step_adjoint(eb_ctx* c, const eb_rheology* rheo, const double* theta,
     vec_fill(N3, 0.0, Cb, c->s);
     vec_fill(N3, 0.0, Vb, c->s);
     vec_fill(N, 0.0, c->ehb, c->s);
+    vec_fill(N, 0.0, c->tbs, c->s);
     if (nc > 0) vec_fill(nc, 0.0, c->ebhb, c->s);
     adj_mask_open(g, 3, ub, x, c->s);
     adj_mask_open(g, 1, pb, pbs, c->s);
@@ -1419,17 +1487,18 @@ int eb_rk2_step_adjoint(eb_ctx* c, const eb_rheology* rheo, const double* theta,
     adj_scale(N, 0.5, c->ehb, c->s);
     adj_scale(nc, 0.5, c->ebhb, c->s);
     vec_fill(N3, 0.0, x, c->s);
-    derived_adj(c, *rheo, theta, t.u1, t.uf1, Cb, c->ehb, c->ebhb, Vb, x, tau0b, rt_mac, k, 3);
+    derived_adj(c, *rheo, theta, t.u1, t.uf1, Cb, c->ehb, c->ebhb, Vb, x, c->tbs, rt_mac, k, 3);
     // predictor
     cc_project_adj(c, beta, x, pbs, o->rtol_proj, k, 2);
     visc_solve_adj(c, rho, dt, t.em, t.ebm, t.us1, x, o->rtol_visc, k, 1, c->ehb, c->ebhb);
     psi_adj(c, rho, dt, c->ubm, Cb, Vb, pbs);
-    derived_adj(c, *rheo, theta, u0, t.ufm, Cb, c->ehb, c->ebhb, Vb, c->ubm, tau0b, rt_mac, k,
+    derived_adj(c, *rheo, theta, u0, t.ufm, Cb, c->ehb, c->ebhb, Vb, c->ubm, c->tbs, rt_mac, k,
                 0);
     adj_mask_open(g, 3, c->ubm, ub, c->s);
     adj_mask_open(g, 1, pbs, pb, c->s);
     int h;
     if ((h = hip_check("eb_rk2_step_adjoint"))) return h;
+    if ((h = yield_adjoint_out(c, rheo->tau0, theta, tau0b, thetab, tau0bar))) return h;
     return step_status(c, k, stats, true);
 }
 
@@ -1452,19 +1521,20 @@ int eb_drag(const eb_ctx* cc, const eb_rheology* rheo, const double* theta, cons
 
 int eb_drag_adjoint(const eb_ctx* cc, const eb_rheology* rheo, const double* theta,
                     const double* u, const double fbar[3], double* ub, double* pb,
-                    double* tau0b, void* stream) {
+                    double* tau0b, double* thetab, double* tau0bar, void* stream) {
     eb_ctx* c = const_cast<eb_ctx*>(cc);
-    if (!c || !rheo || !u || !fbar || !ub || !pb || !tau0b)
-        return set_err(EB_EINVAL, "null argument");
+    if (!c || !rheo || !u || !fbar || !ub || !pb) return set_err(EB_EINVAL, "null argument");
     if (int e_ = check_rheology(*rheo)) return e_;
     StreamScope scope_(c, stream);
     if (c->ncut == 0) return EB_OK;
     op_wall_grad(c->g, u, c->gw, c->s);
     vec_fill(3 * c->N, 0.0, c->gp, c->s);
-    adj_drag(c->g, *rheo, theta, c->gw, fbar, c->gwb, tau0b, pb, c->gp, c->s);
+    vec_fill(c->N, 0.0, c->tbs, c->s);
+    adj_drag(c->g, *rheo, theta, c->gw, fbar, c->gwb, c->tbs, pb, c->gp, c->s);
     adj_grad_gather(c->g, c->wt, nullptr, c->gwb, ub, c->s);
     adj_gcc_T(c->g, 1.0, c->gp, pb, pb, c->s);
-    return hip_check("eb_drag_adjoint");
+    if (int h = hip_check("eb_drag_adjoint")) return h;
+    return yield_adjoint_out(c, rheo->tau0, theta, tau0b, thetab, tau0bar);
 }
 
 int eb_mac_project_adjoint(eb_ctx* c, double beta, double* fbx, double* fby, double* fbz,
@@ -1560,9 +1630,9 @@ int eb_stable_dt(const eb_ctx* cc, const eb_rheology* rheo, const double* theta,
     hipStream_t s = (hipStream_t)stream;
     double m[2];
     red_cfl(c->g, u, theta, c->part, c->red, s);
-    hipMemcpyAsync(m, c->red, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
-    hipError_t e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return set_err(EB_EHIP, "eb_stable_dt: %s", hipGetErrorString(e));
+    HIPN(hipMemcpyAsync(m, c->red, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPN(hipStreamSynchronize(s));
+    if (int h = hip_check("eb_stable_dt")) return h;
     *dt = stable_dt_of(c, *rheo, m[0], m[1], force, c_cfl);
     return EB_OK;
 }

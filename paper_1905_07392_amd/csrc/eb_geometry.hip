@@ -41,6 +41,10 @@ __device__ double body_psi(const BodyV& b, double x, double y, double z) {
         double dx = x - b.c[0], dz = z - b.c[2];
         return dx * dx + dz * dz - b.r[0] * b.r[0];
     }
+    case EB_BODY_CAVITY: {
+        double dx = x - b.c[0], dy = y - b.c[1], dz = z - b.c[2];
+        return b.r[0] * b.r[0] - (dx * dx + dy * dy + dz * dz);
+    }
     default:
         return 1.0;
     }
@@ -72,6 +76,9 @@ __device__ void body_edge_poly(const BodyV& b, const double x0[3], int d, double
     } else if (b.kind == EB_BODY_CYLINDER && d != 1) {
         qa = h * h;
         qb = 2.0 * h * (x0[d] - b.c[d]);
+    } else if (b.kind == EB_BODY_CAVITY) {
+        qa = -h * h;
+        qb = -2.0 * h * (x0[d] - b.c[d]);
     }
 }
 
@@ -560,7 +567,7 @@ int geom_build_device(const GridV& grid, const BodyV& body, double* psi, uint8_t
                       int ncut_max, int* ncut_out, int* err_dev, hipStream_t s) {
     long nn = (long)(grid.n[0] + 1) * (grid.n[1] + 1) * (grid.n[2] + 1);
     long N = (long)grid.n[0] * grid.n[1] * grid.n[2];
-    hipMemsetAsync(err_dev, 0, sizeof(int), s);
+    HIPN(hipMemsetAsync(err_dev, 0, sizeof(int), s));
     k_node_psi<<<grid_for(nn), EB_BLOCK, 0, s>>>(grid, body, psi);
     for (int d = 0; d < 3; d++) {
         k_face_aperture<<<grid_for(face_count(grid, d)), EB_BLOCK, 0, s>>>(grid, body, psi, d,
@@ -577,8 +584,8 @@ int geom_build_device(const GridV& grid, const BodyV& body, double* psi, uint8_t
     k_scan_counts<<<1, 1024, 0, s>>>(blockcount, nb, blockcount + nb);
     k_scatter_cut<<<nb, EB_BLOCK, 0, s>>>(N, flag, blockcount, cut, ncut_max);
     int tot = 0;
-    hipMemcpyAsync(&tot, blockcount + nb, sizeof(int), hipMemcpyDeviceToHost, s);
-    hipStreamSynchronize(s);
+    HIPN(hipMemcpyAsync(&tot, blockcount + nb, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPN(hipStreamSynchronize(s));
     *ncut_out = tot;
     return 0;
 }
@@ -606,7 +613,7 @@ void level_coarsen_geometry(const Level& F, Level& C, hipStream_t s) {
 
 void geom_mark_near(const GridV& g, const int* cut, int ncut, uint8_t* near, hipStream_t s) {
     long N = (long)g.n[0] * g.n[1] * g.n[2];
-    hipMemsetAsync(near, 0, N, s);
+    HIPN(hipMemsetAsync(near, 0, N, s));
     if (ncut > 0) k_mark_near<<<grid_for(ncut), EB_BLOCK, 0, s>>>(g, cut, ncut, near);
 }
 

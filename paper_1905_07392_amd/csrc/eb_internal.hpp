@@ -12,6 +12,13 @@
 #define EB_MAXLEV 16
 #define EB_BLOCK 256
 
+// Records the first failing HIP runtime call (copy, event, stream or graph call) since the entry
+// point's last error check; that check reports it as EB_EHIP with the call's text, and the
+// solver loops stop polling once one has failed.
+void hip_note(hipError_t e, const char* what);
+bool hip_failed();
+#define HIPN(call) hip_note((call), #call)
+
 // ------------------------------------------------------------------------------------------
 // views passed by value to kernels
 // ------------------------------------------------------------------------------------------
@@ -120,6 +127,57 @@ __device__ inline double coarsen_face_value(const GridV& gc, const GridV& gf, in
     }
     return s * scale;
 }
+// Viscous coarse face f of direction d: scale x the sum over the four fine faces f2 it covers of
+// each one's line contribution.  The line of fine faces normal to the coarse face through the two
+// coarse cells it separates (f1 inside the lower coarse cell, f2, f3 inside the upper) joins the
+// two coarse centres, so its viscosity acts in series: the weighted harmonic mean
+// H = W / sum(w_i / g_i) of g_i = K_i / A_i over the open faces of the line (weights 1/2, 1, 1/2;
+// a domain-wall f2 has weight 1/2, no outer face, and g_2 = K_2 / (2 A_2), its ghost factor
+// removed); the line contributes K_2 H / g_2.  A uniform viscosity gives the plain sum of K_2.
+__device__ inline double coarsen_face_series(const GridV& gc, const GridV& gf, int d,
+                                             const double* Kf, const double* apf, long f,
+                                             double scale) {
+    int m0 = gc.n[0] + (d == 0), m1 = gc.n[1] + (d == 1);
+    int q[3];
+    q[0] = (int)(f % m0);
+    long r = f / m0;
+    q[1] = (int)(r % m1);
+    q[2] = (int)(r / m1);
+    int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+    bool per = gf.per[d] != 0;
+    bool wall = !per && (q[d] == 0 || q[d] == gc.n[d]);
+    double s = 0.0;
+    for (int o = 0; o < 4; o++) {
+        int p[3];
+        p[d] = 2 * q[d];
+        p[t1] = 2 * q[t1] + (o & 1);
+        p[t2] = 2 * q[t2] + (o >> 1);
+        long f2 = face_index(gf, d, p[0], p[1], p[2]);
+        double K2 = Kf[f2], A2 = apf[f2];
+        if (K2 == 0.0 || A2 == 0.0) {
+            s += K2;
+            continue;
+        }
+        double g2 = wall ? K2 / (2.0 * A2) : K2 / A2;
+        double W = wall ? 0.5 : 1.0, R = W / g2;
+        for (int side = -1; side <= 1; side += 2) {
+            int e[3] = {p[0], p[1], p[2]};
+            e[d] += side;
+            if (e[d] < 0 || e[d] > gf.n[d]) {
+                if (!per) continue;
+                e[d] = e[d] < 0 ? e[d] + gf.n[d] : e[d] - gf.n[d];
+            }
+            long fi = face_index(gf, d, e[0], e[1], e[2]);
+            double K = Kf[fi], A = apf[fi];
+            if (K > 0.0 && A > 0.0) {
+                W += 0.5;
+                R += 0.5 / (K / A);
+            }
+        }
+        s += K2 * (W / R) / g2;
+    }
+    return s * scale;
+}
 // coarse cell c: the mean of its eight children (q = 0..7)
 __device__ inline double coarsen_cell_value(const GridV& gc, const GridV& gf, const double* af,
                                             long c) {
@@ -129,6 +187,12 @@ __device__ inline double coarsen_cell_value(const GridV& gc, const GridV& gf, co
     for (int q = 0; q < 8; q++)
         s += af[cell_index(gf, 2 * i + (q & 1), 2 * j + ((q >> 1) & 1), 2 * k + (q >> 2))];
     return s / 8.0;
+}
+
+// max that keeps a NaN (fmax returns the other operand): the max-norms of the stop tests must
+// see a non-finite residual so the solve can report it
+__host__ __device__ __forceinline__ double nan_max(double a, double b) {
+    return (a > b || a != a) ? a : b;
 }
 
 // Work-group index remapped so that each of the 8 XCDs, which receive work-groups round-robin,
@@ -250,7 +314,8 @@ void op_drag_terms(const GeomV& g, const eb_rheology& r, const double* theta, co
                    const double* p, const double* gp, double* terms, hipStream_t s);
 void op_poisson_rhs(const GeomV& g, const double* div, const double* sumcnt, double* b,
                     hipStream_t s);
-void op_shift_open(const GeomV& g, double* x, const double* sumcnt, hipStream_t s);
+void op_shift_open(const GeomV& g, double* x, const double* sumcnt, hipStream_t s,
+                   const int* gate = nullptr);
 
 // device-resident Krylov scalars (slots of a double array) and scalar updates
 enum {
@@ -385,7 +450,8 @@ void red_dots(long n, int npairs, const double* const a[4], const double* const 
               double* part, double* out, hipStream_t s, const int* gate = nullptr);
 void red_maxabs(long n, int ncomp, const double* x, double* part, double* out, hipStream_t s,
                 const int* gate = nullptr);
-void red_sum_open(const GeomV& g, const double* x, double* part, double* out, hipStream_t s);
+void red_sum_open(const GeomV& g, const double* x, double* part, double* out, hipStream_t s,
+                  const int* gate = nullptr);
 // out[0] = max over open cells of |u|+|v|+|w|, out[1] = max of theta there (1 if null)
 void red_cfl(const GeomV& g, const double* u, const double* theta, double* part, double* out,
              hipStream_t s);

@@ -5,7 +5,9 @@
 // face on a Dirichlet domain wall only adds its K to D.  Level 0 takes its face coefficients
 // from the apertures (Poisson) or apertures and face viscosities (viscous); coarse levels
 // average four child faces (and rescale by 1/4 for the doubled spacing) and eight child
-// cell shifts.  Smoothing is red-black Gauss-Seidel; within a colour every update depends only
+// cell shifts, the viscous faces with the viscosity along each child face's normal line taken
+// in series (coarsen_face_series), which keeps the coarse operators faithful across the
+// 1e7 viscosity contrast of a plug next to a sheared layer.  Smoothing is red-black Gauss-Seidel; within a colour every update depends only
 // on the other colour, so the result does not depend on thread order.
 #include "eb_internal.hpp"
 
@@ -118,6 +120,8 @@ __global__ void k_diag(GridV g, const double* __restrict__ Kx, const double* __r
 struct CoarsenArgs {
     GridV gc, gf;
     const double* Kf[3];
+    const double* apf[3];  // fine apertures (the viscous system's series coarsening)
+    int series;
     double* Kc[3];
     const double* Sf;
     double* Sc;
@@ -130,7 +134,9 @@ __global__ void k_coarsen_level(CoarsenArgs A) {
     long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
     for (int d = 0; d < 3; d++) {
         if (t < A.n[d]) {
-            A.Kc[d][t] = coarsen_face_value(A.gc, A.gf, d, A.Kf[d], t, A.scale);
+            A.Kc[d][t] = A.series
+                             ? coarsen_face_series(A.gc, A.gf, d, A.Kf[d], A.apf[d], t, A.scale)
+                             : coarsen_face_value(A.gc, A.gf, d, A.Kf[d], t, A.scale);
             return;
         }
         t -= A.n[d];
@@ -1849,7 +1855,7 @@ __device__ __forceinline__ double block_max(double v, double* sh) {
     sh[threadIdx.x] = v;
     __syncthreads();
     for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < (unsigned)o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+        if (threadIdx.x < (unsigned)o) sh[threadIdx.x] = nan_max(sh[threadIdx.x], sh[threadIdx.x + o]);
         __syncthreads();
     }
     double r = sh[0];
@@ -1884,7 +1890,7 @@ __global__ void k_maxabs(long n, int ncomp, const double* __restrict__ x,
         double v = 0.0;
         for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n;
              t += (long)gridDim.x * blockDim.x)
-            v = fmax(v, fabs(x[m * n + t]));
+            v = nan_max(v, fabs(x[m * n + t]));
         v = block_max(v, sh);
         if (threadIdx.x == 0) part[m * gridDim.x + blockIdx.x] = v;
     }
@@ -1908,7 +1914,7 @@ __global__ void k_final_op(const double* __restrict__ part, int nb, int nrow, Op
             bool mx = (o.maxmask >> p) & 1;
             double v = 0.0;
             for (int t = threadIdx.x; t < nb; t += blockDim.x)
-                v = mx ? fmax(v, part[p * nb + t]) : v + part[p * nb + t];
+                v = mx ? nan_max(v, part[p * nb + t]) : v + part[p * nb + t];
             v = mx ? block_max(v, sh) : block_sum(v, sh);
             if (threadIdx.x == 0) ks[o.idx[p]] = v;
         }
@@ -1927,7 +1933,7 @@ __global__ void k_bi_s_max(long n, double* __restrict__ sv, const double* __rest
          t += (long)gridDim.x * blockDim.x) {
         double s = r[t] - al * v[t];
         sv[t] = s;
-        m = fmax(m, fabs(s));
+        m = nan_max(m, fabs(s));
     }
     m = block_max(m, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = m;
@@ -1950,7 +1956,7 @@ __global__ void k_bi_xr_red(long n, double* __restrict__ x, double* __restrict__
         double rn = sv[t] - om * tv[t];
         r[t] = rn;
         dot += rh[t] * rn;
-        m = fmax(m, fabs(rn));
+        m = nan_max(m, fabs(rn));
     }
     dot = block_sum(dot, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = dot;
@@ -1971,7 +1977,7 @@ __global__ void k_cg_xr_max(long n, double* __restrict__ x, double* __restrict__
         x[t] += a * p[t];
         double rn = r[t] - a * q[t];
         r[t] = rn;
-        m = fmax(m, fabs(rn));
+        m = nan_max(m, fabs(rn));
     }
     m = block_max(m, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = m;
@@ -1987,8 +1993,8 @@ __global__ void k_cfl_max(GeomV g, const double* __restrict__ u, const double* _
     for (long c = blockIdx.x * (long)blockDim.x + threadIdx.x; c < N;
          c += (long)gridDim.x * blockDim.x)
         if (g.alpha[c] > 0.0) {
-            a = fmax(a, fabs(u[c]) + fabs(u[N + c]) + fabs(u[2 * N + c]));
-            t = fmax(t, theta ? theta[c] : 1.0);
+            a = nan_max(a, fabs(u[c]) + fabs(u[N + c]) + fabs(u[2 * N + c]));
+            t = nan_max(t, theta ? theta[c] : 1.0);
         }
     a = block_max(a, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = a;
@@ -1996,7 +2002,9 @@ __global__ void k_cfl_max(GeomV g, const double* __restrict__ u, const double* _
     if (threadIdx.x == 0) part[gridDim.x + blockIdx.x] = t;
 }
 
-__global__ void k_sum_open(GeomV g, const double* __restrict__ x, double* __restrict__ part) {
+__global__ void k_sum_open(GeomV g, const double* __restrict__ x, double* __restrict__ part,
+                           const int* gate) {
+    if (gate && *gate) return;
     __shared__ double sh[EB_BLOCK];
     double s = 0.0, cnt = 0.0;
     for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < g.N;
@@ -2037,7 +2045,7 @@ __global__ void k_face_flux_max(GeomV g, const double* __restrict__ fx,
         long nf = face_count(g.grid, d);
         for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < nf;
              t += (long)gridDim.x * blockDim.x)
-            v = fmax(v, fabs(g.ap[d][t] * fo[d][t]));
+            v = nan_max(v, fabs(g.ap[d][t] * fo[d][t]));
     }
     v = block_max(v, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = v / g.grid.h;
@@ -2051,7 +2059,7 @@ __global__ void k_final(const double* __restrict__ part, int nb, int nrow, int m
     for (int p = 0; p < nrow; p++) {
         double v = 0.0;
         for (int t = threadIdx.x; t < nb; t += blockDim.x)
-            v = mode ? fmax(v, part[p * nb + t]) : v + part[p * nb + t];
+            v = mode ? nan_max(v, part[p * nb + t]) : v + part[p * nb + t];
         v = mode ? block_max(v, sh) : block_sum(v, sh);
         if (threadIdx.x == 0) out[p] = v;
     }
@@ -2477,9 +2485,11 @@ void finish_operator(Level* lev, int nlev, bool mixed, hipStream_t s) {
         A.gf = F.grid;
         for (int d = 0; d < 3; d++) {
             A.Kf[d] = F.K[d];
+            A.apf[d] = F.ap[d];
             A.Kc[d] = C.K[d];
             A.n[d] = face_count(C.grid, d);
         }
+        A.series = lev[0].sys == EB_SYS_VISC;
         A.Sf = F.S;
         A.Sc = C.S;
         A.scale = 1.0 / 16.0;
@@ -2670,10 +2680,11 @@ void red_cfl(const GeomV& g, const double* u, const double* theta, double* part,
     k_final<<<1, EB_BLOCK, 0, s>>>(part, nb, 2, 1, out, nullptr);
 }
 
-void red_sum_open(const GeomV& g, const double* x, double* part, double* out, hipStream_t s) {
+void red_sum_open(const GeomV& g, const double* x, double* part, double* out, hipStream_t s,
+                  const int* gate) {
     int nb = red_blocks(g.N);
-    k_sum_open<<<nb, EB_BLOCK, 0, s>>>(g, x, part);
-    k_final<<<1, EB_BLOCK, 0, s>>>(part, nb, 2, 0, out, nullptr);
+    k_sum_open<<<nb, EB_BLOCK, 0, s>>>(g, x, part, gate);
+    k_final<<<1, EB_BLOCK, 0, s>>>(part, nb, 2, 0, out, gate);
 }
 
 void red_sum(long n, int nrow, const double* x, double* part, double* out, hipStream_t s) {

@@ -570,7 +570,9 @@ __global__ void k_poisson_rhs(GeomV g, const double* __restrict__ div,
 }
 
 // x -= mean on open cells (0 elsewhere)
-__global__ void k_shift_open(GeomV g, double* __restrict__ x, const double* __restrict__ sumcnt) {
+__global__ void k_shift_open(GeomV g, double* __restrict__ x, const double* __restrict__ sumcnt,
+                             const int* gate) {
+    if (gate && *gate) return;
     long c = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (c >= g.N) return;
     double mean = sumcnt[1] > 0.0 ? sumcnt[0] / sumcnt[1] : 0.0;
@@ -646,6 +648,7 @@ void op_poisson_rhs(const GeomV& g, const double* div, const double* sumcnt, dou
                     hipStream_t s) {
     k_poisson_rhs<<<grid_for(g.N), EB_BLOCK, 0, s>>>(g, div, sumcnt, b);
 }
-void op_shift_open(const GeomV& g, double* x, const double* sumcnt, hipStream_t s) {
-    k_shift_open<<<grid_for(g.N), EB_BLOCK, 0, s>>>(g, x, sumcnt);
+void op_shift_open(const GeomV& g, double* x, const double* sumcnt, hipStream_t s,
+                   const int* gate) {
+    k_shift_open<<<grid_for(g.N), EB_BLOCK, 0, s>>>(g, x, sumcnt, gate);
 }

@@ -128,10 +128,17 @@ def test_drag_adjoint(s32):
     P = s32
     Fb = [0.3, -0.2, 1.0]
     ru, rp, rt = P.og.drag_adj(P.u0, P.orheo, Fb, theta=P.theta)
-    gu, gp, gt = P.api.eb_drag_adjoint(P.ctx, P.rheo, P.dev(P.u0), Fb, theta=P.dev(P.theta))
+    thb = torch.zeros_like(P.dev(P.theta))
+    gu, gp, gt, gbi = P.api.eb_drag_adjoint(P.ctx, P.rheo, P.dev(P.u0), Fb,
+                                            theta=P.dev(P.theta), thetab=thb,
+                                            tau0bar=np.zeros(1))
     assert rel_l2(cpu(gu), ru, P.open) < 1e-12
     assert rel_l2(cpu(gp), rp, P.open) < 1e-12
     assert rel_l2(cpu(gt), rt, P.open) < 1e-12
+    # the library's own yield-stress reductions: d/d theta = tau0 tau0b, d/d tau0 = sum theta tau0b
+    assert rel_l2(cpu(thb), P.w.tau0 * rt, P.open) < 1e-12
+    ref_bi = float(np.sum(P.theta * rt))
+    assert abs(gbi - ref_bi) <= 1e-12 * abs(ref_bi)
 
 
 @pytest.mark.parametrize("law", ["bingham", "papanastasiou"])
@@ -151,12 +158,17 @@ def test_rk2_step_adjoint(s32, law):
     th = P.dev(P.theta)
     u1, p1, _ = P.api.eb_rk2_step_taped(P.ctx, P.rheo, w.dt, P.opts, P.dev(P.u0), P.dev(P.p0),
                                         tape, theta=th)
+    thb = torch.zeros_like(th)
     gu, gp, gt, gst = P.api.eb_rk2_step_adjoint(P.ctx, P.rheo, w.dt, P.opts, P.dev(P.u0), tape,
-                                                P.dev(ub), P.dev(pb), theta=th)
+                                                P.dev(ub), P.dev(pb), theta=th, thetab=thb,
+                                                tau0bar=np.zeros(1))
     print(f"[adjoint] oracle iters {rst} gpu iters {gst}", flush=True)
     assert rel_l2(cpu(gu), ru, P.open) < 1e-8
     assert rel_l2(cpu(gp), rp, P.open) < 1e-8
     assert rel_l2(cpu(gt), rt, P.open) < 1e-8
+    assert rel_l2(cpu(thb), w.tau0 * rt, P.open) < 1e-8
+    ref_bi = float(np.sum(P.theta * rt))
+    assert abs(gst["tau0bar"] - ref_bi) <= 1e-8 * abs(ref_bi)
     # the taped step is the plain step
     u2, p2, _ = P.api.eb_rk2_step(P.ctx, P.rheo, w.dt, P.opts, P.dev(P.u0), P.dev(P.p0),
                                   theta=th)
@@ -228,6 +240,26 @@ def test_autograd_rollout_matches_step_chain_and_fd():
         assert abs(fd - gt[c]) <= 1e-4 * abs(gt[c])
 
 
+def test_autograd_without_theta_field():
+    """theta = None means a uniform yield stress: the backward passes no theta gradient and
+    d/d tau0 equals the one with theta = 1 everywhere."""
+    from paper_1905_07392_amd import autograd as AG
+
+    w, ctx, rheo, opts, u0, p0, theta, og = _loss_fd_setup(n=16, radius=0.3)
+    grads = []
+    for th in (None, torch.ones_like(theta).requires_grad_(True)):
+        tau0 = torch.tensor(float(w.tau0), dtype=torch.float64, device="cuda:0",
+                            requires_grad=True)
+        u, p = AG.rollout(ctx, rheo, w.dt, opts, u0, p0, th, tau0, 2, ckpt_every=1)
+        u, p = AG.rk2_step(ctx, rheo, w.dt, opts, u, p, th, tau0)
+        AG.drag(ctx, rheo, u, p, th, tau0)[2].backward()
+        grads.append(float(tau0.grad))
+        if th is not None:
+            assert th.grad is not None and torch.isfinite(th.grad).all()
+    assert grads[0] != 0.0
+    assert abs(grads[0] - grads[1]) <= 1e-13 * abs(grads[1])
+
+
 def test_bench_size_adjoint_bi_fd():
     """128^3 sphere (the bench workload): one step + drag, adjoint d/dBi vs central FD."""
     import paper_1905_07392_amd as pkg
@@ -245,11 +277,13 @@ def test_bench_size_adjoint_bi_fd():
     u, p, _ = api.eb_rk2_step(ctx, rheo, w.dt, opts, u, p, theta=theta)  # developed start
     tape = api.new_tape(ctx)
     u1, p1, _ = api.eb_rk2_step_taped(ctx, rheo, w.dt, opts, u, p, tape, theta=theta)
-    ub, pb, tb = api.eb_drag_adjoint(ctx, rheo, u1, [0.0, 0.0, 1.0], theta=theta)
+    acc = np.zeros(1)
+    ub, pb, tb, _ = api.eb_drag_adjoint(ctx, rheo, u1, [0.0, 0.0, 1.0], theta=theta,
+                                        tau0bar=acc)
     ub, pb, tb, st = api.eb_rk2_step_adjoint(ctx, rheo, w.dt, opts, u, tape, ub, pb,
-                                             theta=theta, tau0b=tb)
+                                             theta=theta, tau0b=tb, tau0bar=acc)
     assert torch.isfinite(ub).all() and torch.isfinite(tb).all()
-    g_bi = float((theta * tb).sum())
+    g_bi = float(acc[0])
 
     def loss(bi):
         r = api.make_rheology(rheo.law, rheo.mu, bi, rheo.eps, rheo.rho)

@@ -3,8 +3,9 @@
 Bars (per field, over open cells): geometry to rounding; pointwise operators to 1e-12 relative;
 solver outputs and the full RK2 step to 1e-10 relative in the L2 norm (the FP64 bar); the
 mixed-precision step to 1e-8.  Sizes: 32^3 sphere (the parity workload), a 40^3 sphere (ragged
-last block, three-level hierarchy), a 64^3 channel with Bingham walls, and property checks on the
-128^3 bench workload.
+last block, three-level hierarchy), a 64^3 channel with Bingham walls, fluid cavities whose wall
+stencils take the covered-node fallback, and property checks on the 128^3 bench workload (its
+step-by-step oracle parity is in test_gpu_headline.py).
 """
 import numpy as np
 import pytest
@@ -101,6 +102,40 @@ def test_geometry_other_bodies(wl):
     cell, data = P.og.cut()
     assert np.array_equal(cpu(gcell), cell)
     assert np.abs(cpu(gdata) - data).max() <= 1e-11
+
+
+@pytest.mark.parametrize("n,radius,center", [(20, 0.25, (0.5, 0.5, 0.5)),
+                                             (12, 0.15, (0.5, 0.53, 0.46))])
+def test_cavity_fallback_stencils_match(n, radius, center):
+    """The covered-node fallback of the wall-flux stencil (reading A5), which no sphere,
+    ellipsoid, channel or cylinder workload takes: a fluid cavity at coarse resolution, whose
+    stencil planes reach across it.  The GPU geometry (flags, cut list, stencil data, the
+    fallback count), the wall-gradient viscosity and the EB Helmholtz operator equal the
+    oracle's, whose fallback is pinned against quadratic fields on the CPU."""
+    _require_gpu()
+    w = I.Workload(name=f"cavity{n}", n=(n, n, n), h=1.0 / n, law=I.LAW_BINGHAM_REG, tau0=1.0,
+                   body={"kind": I.BODY_CAVITY, "center": center, "radius": radius})
+    P = Pair(w)
+    assert P.og.nfallback > 0 and P.ctx.nfallback == P.og.nfallback
+    flag, alpha, ap = P.og.export()
+    gflag, galpha, gap, gcell, gdata = P.api.eb_geometry_export(P.ctx)
+    assert np.array_equal(cpu(gflag), flag)
+    assert np.abs(cpu(galpha) - alpha).max() <= 1e-13
+    cell, data = P.og.cut()
+    assert np.array_equal(cpu(gcell), cell)
+    assert np.abs(cpu(gdata) - data).max() <= 1e-11
+    u = I.random_field((3,) + P.og.shape, 31) * P.open
+    eta, eta_eb = P.og.viscosity(u, P.orheo)
+    geta, geta_eb = P.api.eb_apparent_viscosity(P.ctx, P.rheo, P.dev(u))
+    fb = data[:, 8] > 0
+    assert rel_l2(cpu(geta), eta, P.open) <= 1e-12
+    assert rel_l2(cpu(geta_eb), eta_eb) <= 1e-12
+    assert rel_l2(cpu(geta_eb)[fb], eta_eb[fb]) <= 1e-12
+    ref = P.og.visc_apply(1.0, 1e-2, eta, eta_eb, u)
+    got = P.api.eb_viscous_apply(P.ctx, P.api.EB_OP_HELMHOLTZ, 1.0, 1e-2, geta, geta_eb,
+                                 P.dev(u))
+    for j in range(3):
+        assert rel_l2(cpu(got)[j], ref[j], P.open) <= 1e-12
 
 
 def test_viscosity_and_operators(s32):
@@ -323,14 +358,10 @@ def test_channel64_steady_state(bi, precision):
     assert np.abs(un[1:]).max() <= 1e-12 * U
 
 
-def test_rk2_step_mixed_precision(s32):
-    P = Pair(I.sphere32(), precision=1)
-    _step_parity(P, steps=1, tol=1e-8)
-
-
 def test_mixed_precision_bench_size():
     """128^3 sphere: three mixed-precision steps against three FP64 steps from the same
-    developed state (the FP64 step is itself checked against the oracle above): relative L2
+    start (both are checked step by step against the oracle over the first two steps in
+    test_gpu_headline.py): relative L2
     error of u, v, w, p, eta_EB and the drag, each within 1e-8.  The viscosity is held to 1e-8
     or, if larger, ten times the difference between two FP64 runs whose solves stop at rtol
     1e-12 and 1e-13 (the law turns a strain-rate error into the same relative viscosity error,
