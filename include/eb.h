@@ -276,6 +276,18 @@ int eb_rk2_step(eb_ctx* ctx, const eb_rheology* rheo, const double* theta, doubl
 int eb_drag(const eb_ctx* ctx, const eb_rheology* rheo, const double* theta, const double* u,
             const double* p, double F[3], void* stream);
 
+/* eb_drag for callers that cannot allocate device memory or touch the context's workspace
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same force, bit for bit, with its scratch (wall gradients and drag terms of the cut cells,
+ * reduction partials) in a file-scope device array of 3.2 MB that each GPU the library runs on
+ * holds until the process ends.  Calls no hipMalloc or hipFree and writes nothing into ctx's
+ * workspace; enqueues on `stream` itself and waits for it to return F (host).  Limit: at most
+ * 65536 cut cells (EB_EINVAL beyond).  Every call on one GPU shares that GPU's array, so calls
+ * that overlap on one GPU (from several threads or streams) race; nothing in it needs to start
+ * at zero (each call writes every entry it reads). */
+int eb_drag_noalloc(const eb_ctx* ctx, const eb_rheology* rheo, const double* theta,
+                    const double* u, const double* p, double F[3], void* stream);
+
 /* Time step of the paper's stability rule (Sec. II.C.1) for the state u (device) [3][N]:
  * Eq. cfl:dt combining the convective coefficient max over open cells of (|u|+|v|+|w|)/h
  * (Eq. cfl:convective), the forcing coefficient sqrt(sum_d |force_d| / h) (Eq. cfl:forcing;

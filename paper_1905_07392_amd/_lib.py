@@ -74,6 +74,7 @@ SIGNATURES = {
     "eb_derived": (_I, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _IP, _P]),
     "eb_rk2_step": (_I, [_P, _P, _P, _D, _P, _P, _P, _P, _P]),
     "eb_drag": (_I, [_P, _P, _P, _P, _P, _DP, _P]),
+    "eb_drag_noalloc": (_I, [_P, _P, _P, _P, _P, _DP, _P]),
     "eb_pressure_gradient": (_I, [_P, _P, _P, _P]),
     "eb_tape_bytes": (C.c_size_t, [_P]),
     "eb_rk2_step_taped": (_I, [_P, _P, _P, _D, _P, _P, _P, _P, _P, _P]),

@@ -20,7 +20,7 @@ __all__ = ["EbContext", "make_box", "make_body", "make_rheology", "make_opts",
            "eb_workspace_bytes", "eb_geometry_build", "eb_geometry_export",
            "eb_apparent_viscosity", "eb_viscous_apply", "eb_mg_vcycle", "eb_visc_solve",
            "eb_mac_project", "eb_cc_project", "eb_derived", "eb_rk2_step", "eb_drag",
-           "eb_pressure_gradient", "eb_stable_dt", "eb_tape_bytes", "eb_rk2_step_taped",
+           "eb_pressure_gradient", "eb_drag_noalloc", "eb_stable_dt", "eb_tape_bytes", "eb_rk2_step_taped",
            "eb_rk2_step_adjoint", "eb_drag_adjoint", "eb_mac_project_adjoint", "eb_cc_project_adjoint",
            "eb_visc_solve_adjoint", "eb_derived_adjoint", "EB_FP64", "EB_MIXED", "EB_OP_HELMHOLTZ",
            "EB_OP_HELMHOLTZ_H", "EB_OP_TRANSPOSE", "EB_SYS_POISSON", "EB_SYS_VISC",
@@ -326,6 +326,16 @@ def eb_drag(ctx: EbContext, rheo: EbRheology, u, p, theta=None):
     th = _f64(theta, ctx.shape, "theta") if theta is not None else None
     check(L.lib().eb_drag(ctx.ptr, C.byref(rheo), th, _f64(u, (3,) + ctx.shape, "u"),
                           _f64(p, ctx.shape, "p"), F, _stream(ctx.device)), "eb_drag")
+    return [F[0], F[1], F[2]]
+
+
+def eb_drag_noalloc(ctx: EbContext, rheo: EbRheology, u, p, theta=None):
+    """eb_drag with the library's static device scratch (no allocation, workspace untouched)."""
+    F = (C.c_double * 3)()
+    th = _f64(theta, ctx.shape, "theta") if theta is not None else None
+    check(L.lib().eb_drag_noalloc(ctx.ptr, C.byref(rheo), th, _f64(u, (3,) + ctx.shape, "u"),
+                                  _f64(p, ctx.shape, "p"), F, _stream(ctx.device)),
+          "eb_drag_noalloc")
     return [F[0], F[1], F[2]]
 
 

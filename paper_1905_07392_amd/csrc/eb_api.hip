@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -990,6 +991,44 @@ void psi_adj(eb_ctx* c, double rho, double dt, double* ub, double* Cb, double* V
 // ------------------------------------------------------------------------------------------
 // C ABI
 // ------------------------------------------------------------------------------------------
+// Device scratch of eb_drag_noalloc: a file-scope device array (each GPU the library runs on
+// holds its own copy until the process ends), so that entry point needs no allocation and writes
+// nothing into the caller's workspace.  Layout (doubles): wall gradients [3][NOALLOC_NCUT], drag
+// terms [3][NOALLOC_NCUT], reduction partials [4096], reduced forces [8].  Host code uses only
+// the address hipGetSymbolAddress returns for the current device, taken once per device at
+// set-up (eb_geometry_build), never the array's name.
+// ------------------------------------------------------------------------------------------
+namespace {
+constexpr long NOALLOC_NCUT = 65536;
+constexpr long NOALLOC_DOUBLES = 6 * NOALLOC_NCUT + 4096 + 8;
+__device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+constexpr int NOALLOC_MAX_DEV = 64;
+std::mutex g_noalloc_mu;
+double* g_noalloc_ptr[NOALLOC_MAX_DEV] = {nullptr};
+
+// the current device's scratch address (looked up on its first use on that device)
+int noalloc_scratch(double** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return set_err(EB_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEV)
+        return set_err(EB_EINVAL, "device %d beyond the %d the library tracks", dev,
+                       NOALLOC_MAX_DEV);
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return set_err(EB_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_noalloc_ptr[dev] = static_cast<double*>(ptr);
+    }
+    *out = g_noalloc_ptr[dev];
+    return EB_OK;
+}
+}  // namespace
+
+// ------------------------------------------------------------------------------------------
 extern "C" {
 
 const char* eb_last_error(void) { return g_err.c_str(); }
@@ -1016,6 +1055,11 @@ int eb_geometry_build(const eb_box* box, const eb_body* body, void* ws, size_t w
     }
     carve(c, (char*)ws, false);
     c->s = (hipStream_t)stream;
+    double* scr = nullptr;  // eb_drag_noalloc's scratch address on this device, looked up once
+    if ((e = noalloc_scratch(&scr))) {
+        delete c;
+        return e;
+    }
     int ncut = 0;
     geom_build_device(c->grid, c->bodyv, c->psi_nodes, c->flag, c->alpha, c->ap, c->cutid,
                       c->cut, c->blockcount, c->ncut_max, &ncut, c->errdev, c->s);
@@ -1517,6 +1561,31 @@ int eb_drag(const eb_ctx* cc, const eb_rheology* rheo, const double* theta, cons
     int e = fetch(c, F, 3);
     if (e) return e;
     return hip_check("eb_drag");
+}
+
+int eb_drag_noalloc(const eb_ctx* c, const eb_rheology* rheo, const double* theta,
+                    const double* u, const double* p, double F[3], void* stream) {
+    if (!c || !rheo || !u || !p || !F) return set_err(EB_EINVAL, "null argument");
+    if (int e_ = check_rheology(*rheo)) return e_;
+    if (c->ncut > NOALLOC_NCUT)
+        return set_err(EB_EINVAL, "eb_drag_noalloc: %d cut cells exceed its scratch limit of %ld",
+                       c->ncut, NOALLOC_NCUT);
+    F[0] = F[1] = F[2] = 0.0;
+    if (c->ncut == 0) return EB_OK;
+    double* scr = nullptr;
+    if (int e = noalloc_scratch(&scr)) return e;
+    hipStream_t s = (hipStream_t)stream;
+    // views of the scratch for this geometry: per-cut arrays are [component][ncut]
+    double* gw = scr;
+    double* terms = scr + 3 * NOALLOC_NCUT;
+    double* part = scr + 6 * NOALLOC_NCUT;
+    double* out = part + 4096;
+    op_wall_grad(c->g, u, gw, s);
+    op_drag_terms(c->g, *rheo, theta, gw, p, nullptr, terms, s);
+    red_sum(c->ncut, 3, terms, part, out, s);
+    HIPN(hipMemcpyAsync(F, out, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPN(hipStreamSynchronize(s));
+    return hip_check("eb_drag_noalloc");
 }
 
 int eb_drag_adjoint(const eb_ctx* cc, const eb_rheology* rheo, const double* theta,

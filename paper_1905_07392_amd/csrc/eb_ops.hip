@@ -437,6 +437,26 @@ __global__ void k_redist_gather(GeomV g, const double* __restrict__ DC,
 // ------------------------------------------------------------------------------------------
 // projections, pressure gradient, RHS assembly
 // ------------------------------------------------------------------------------------------
+// component d of the cell-centred pressure gradient of open cell c = (i, j, k): the
+// aperture-weighted mean of its two face gradients (a domain-wall face carries 0)
+__device__ inline double gcc_cell(const GeomV& g, const double* __restrict__ p, long c, int i,
+                                  int j, int k, int d) {
+    double h = g.grid.h;
+    double num = 0.0, den = 0.0;
+    for (int side = -1; side <= 1; side += 2) {
+        int f[3] = {i, j, k};
+        if (side > 0) f[d] += 1;
+        double A = g.ap[d][face_index(g.grid, d, f[0], f[1], f[2])];
+        if (A == 0.0) continue;
+        long nb = nbr(g.grid, i, j, k, d, side);
+        double gf = 0.0;
+        if (nb >= 0) gf = side > 0 ? (p[nb] - p[c]) / h : (p[c] - p[nb]) / h;
+        num += A * gf;
+        den += A;
+    }
+    return den > 0.0 ? num / den : 0.0;
+}
+
 __global__ void k_gcc(GeomV g, const double* __restrict__ p, double* __restrict__ gp) {
     long N = g.N;
     long c = blockIdx.x * (long)blockDim.x + threadIdx.x;
@@ -447,22 +467,7 @@ __global__ void k_gcc(GeomV g, const double* __restrict__ p, double* __restrict_
     }
     int i, j, k;
     cell_coords(g.grid, c, i, j, k);
-    double h = g.grid.h;
-    for (int d = 0; d < 3; d++) {
-        double num = 0.0, den = 0.0;
-        for (int side = -1; side <= 1; side += 2) {
-            int f[3] = {i, j, k};
-            if (side > 0) f[d] += 1;
-            double A = g.ap[d][face_index(g.grid, d, f[0], f[1], f[2])];
-            if (A == 0.0) continue;
-            long nb = nbr(g.grid, i, j, k, d, side);
-            double gf = 0.0;
-            if (nb >= 0) gf = side > 0 ? (p[nb] - p[c]) / h : (p[c] - p[nb]) / h;
-            num += A * gf;
-            den += A;
-        }
-        gp[d * N + c] = den > 0.0 ? num / den : 0.0;
-    }
+    for (int d = 0; d < 3; d++) gp[d * N + c] = gcc_cell(g, p, c, i, j, k, d);
 }
 
 __global__ void k_axpy_open(GeomV g, double a, const double* __restrict__ x,
@@ -531,6 +536,8 @@ __global__ void k_finalize_state(GeomV g, double* __restrict__ u, double* __rest
     }
 }
 
+// gp null: the pressure gradient of each cut cell is formed here (gcc_cell, the same
+// arithmetic as k_gcc) instead of being read from a full [3][N] array
 __global__ void k_drag_terms(GeomV g, eb_rheology rh, const double* __restrict__ theta,
                              const double* __restrict__ gw, const double* __restrict__ p,
                              const double* __restrict__ gp, double* __restrict__ terms) {
@@ -539,6 +546,8 @@ __global__ void k_drag_terms(GeomV g, eb_rheology rh, const double* __restrict__
     if (q >= nc) return;
     long N = g.N;
     long c = g.cut[q];
+    int ci, cj, ck;
+    cell_coords(g.grid, c, ci, cj, ck);
     double nv[3], gv[3];
     for (int a = 0; a < 3; a++) {
         nv[a] = g.nrm[(long)a * nc + q];
@@ -551,7 +560,8 @@ __global__ void k_drag_terms(GeomV g, eb_rheology rh, const double* __restrict__
     double e = eta_law(rh, t0, strain_rate(G));
     double h = g.grid.h;
     double pe = p[c];
-    for (int d = 0; d < 3; d++) pe += h * g.bc[(long)d * nc + q] * gp[d * N + c];
+    for (int d = 0; d < 3; d++)
+        pe += h * g.bc[(long)d * nc + q] * (gp ? gp[d * N + c] : gcc_cell(g, p, c, ci, cj, ck, d));
     double area = g.aeb[q] * h * h;
     for (int a = 0; a < 3; a++) {
         double tn = 0.0;
