@@ -1870,6 +1870,8 @@ typedef struct {
     double* us2;    /* corrector solve, before its projection */
 } rk2_tape;
 
+static long nd_count(const or_geom* g); /* nodes of the nodal projection (below) */
+
 static int rk2_impl(const or_geom* g_in, const or_rheo* rh, const double* theta, double dt,
                     const or_opts* o, double* u, double* p, or_stats* st, rk2_tape* tp) {
     or_geom* g = (or_geom*)g_in;
@@ -1879,7 +1881,9 @@ static int rk2_impl(const or_geom* g_in, const or_rheo* rh, const double* theta,
     double *Cm = malloc(N3 * 8), *Vm = malloc(N3 * 8), *em = malloc(N * 8), *ebm = malloc(nc * 8);
     double *Cs = malloc(N3 * 8), *Vs = malloc(N3 * 8), *es = malloc(N * 8), *ebs = malloc(nc * 8);
     double *psi = malloc(N3 * 8), *gp = malloc(N3 * 8), *ut = malloc(N3 * 8);
-    double *ps = malloc(N * 8);
+    int nodal = o->projection == OR_PROJ_NODAL;
+    long NP = nodal ? nd_count(g) : N; /* the pressure's storage: nodes or cells */
+    double *ps = malloc(NP * 8);
     int err = OR_OK, e, it;
     or_stats loc;
     memset(&loc, 0, sizeof(loc));
@@ -1887,7 +1891,8 @@ static int rk2_impl(const or_geom* g_in, const or_rheo* rh, const double* theta,
     e = derived_impl(g, rh, theta, u, o, Cm, em, ebm, Vm, &it, tp ? tp->ufm : NULL);
     loc.it_mac[0] = it;
     if (e) err = e;
-    or_gcc(g, p, gp);
+    if (nodal) or_nodal_grad(g, p, gp);
+    else or_gcc(g, p, gp);
     for (long q = 0; q < N3; q++) {
         int d = (int)(q / N);
         psi[q] = rho * u[q] + dt * (rho * Cm[q] + Vm[q] - gp[q] + o->force[d]);
@@ -1901,8 +1906,11 @@ static int rk2_impl(const or_geom* g_in, const or_rheo* rh, const double* theta,
         memcpy(tp->ebm, ebm, nc * 8);
         memcpy(tp->us1, ut, N3 * 8);
     }
-    memcpy(ps, p, N * 8);
-    e = or_cc_project(g, beta, ut, ps, o->rtol_proj, o->max_iter, o, &loc.div_proj[0], &it);
+    memcpy(ps, p, NP * 8);
+    if (nodal)
+        e = or_nodal_project(g, beta, ut, ps, o->rtol_proj, o->max_iter, &loc.div_proj[0], &it);
+    else
+        e = or_cc_project(g, beta, ut, ps, o->rtol_proj, o->max_iter, o, &loc.div_proj[0], &it);
     loc.it_proj[0] = it;
     if (e) err = e;
     /* corrector: derived quantities at u*, averaged with those at u^m */
@@ -1916,7 +1924,8 @@ static int rk2_impl(const or_geom* g_in, const or_rheo* rh, const double* theta,
     }
     for (long c = 0; c < N; c++) em[c] = 0.5 * (em[c] + es[c]);
     for (int c = 0; c < g->ncut; c++) ebm[c] = 0.5 * (ebm[c] + ebs[c]);
-    or_gcc(g, ps, gp);
+    if (nodal) or_nodal_grad(g, ps, gp);
+    else or_gcc(g, ps, gp);
     for (long q = 0; q < N3; q++) {
         int d = (int)(q / N);
         psi[q] = rho * u[q] + dt * (rho * Cm[q] + Vm[q] - gp[q] + o->force[d]);
@@ -1929,14 +1938,19 @@ static int rk2_impl(const or_geom* g_in, const or_rheo* rh, const double* theta,
         memcpy(tp->eba, ebm, nc * 8);
         memcpy(tp->us2, ut, N3 * 8);
     }
-    e = or_cc_project(g, beta, ut, ps, o->rtol_proj, o->max_iter, o, &loc.div_proj[1], &it);
+    if (nodal)
+        e = or_nodal_project(g, beta, ut, ps, o->rtol_proj, o->max_iter, &loc.div_proj[1], &it);
+    else
+        e = or_cc_project(g, beta, ut, ps, o->rtol_proj, o->max_iter, o, &loc.div_proj[1], &it);
     loc.it_proj[1] = it;
     if (e) err = e;
     for (long q = 0; q < N3; q++) {
         long c = q % N;
         u[q] = g->alpha[c] > 0.0 ? ut[q] : g->body.u_eb[q / N];
     }
-    for (long c = 0; c < N; c++) p[c] = g->alpha[c] > 0.0 ? ps[c] : 0.0;
+    if (nodal) memcpy(p, ps, NP * 8);
+    else
+        for (long c = 0; c < N; c++) p[c] = g->alpha[c] > 0.0 ? ps[c] : 0.0;
     if (st) *st = loc;
     free(Cm); free(Vm); free(em); free(ebm);
     free(Cs); free(Vs); free(es); free(ebs);
@@ -1947,6 +1961,334 @@ static int rk2_impl(const or_geom* g_in, const or_rheo* rh, const double* theta,
 int or_rk2_step(const or_geom* g, const or_rheo* rh, const double* theta, double dt,
                 const or_opts* o, double* u, double* p, or_stats* st) {
     return rk2_impl(g, rh, theta, dt, o, u, p, st, NULL);
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* nodal projection (Sec. III.A.4 "Incompressibility constraint"; Alg. advance NodalProjection):  */
+/* velocities on cell centres, the pressure on the nodes (cell corners), an approximate          */
+/* projection.  The paper leaves the discrete operators to its library's nodal solver; this is   */
+/* the trilinear finite-element form of that projection, each cell weighted by its volume        */
+/* fraction:                                                                                     */
+/*  - D(w)_n: the weak divergence of a cell field w against the hat function of node n,          */
+/*    sum over the cells c at n of alpha_c h^2/4 sum_d s_d w_{d,c} (s_d = +1 when n is on c's    */
+/*    upper side in d, else -1), minus the boundary flux B_n of the given normal velocity:       */
+/*    A_f h^2/4 (u_wall . n_out) per domain-wall face at n, A_EB h^2/8 (u_EB . n_out) per cut    */
+/*    cell at n (n_out = -n_EB, the EB area shared equally by the cell's 8 nodes);               */
+/*  - L: the stiffness matrix of those elements, L_nm = sum_c alpha_c h Khat(a, b);              */
+/*  - G(q)_c: the cell average of the gradient of the trilinear interpolant of q;                */
+/*  - solve L phi = D(w) - B on the nodes of open cells, CG with the diagonal as preconditioner  */
+/*    (mean-free over those nodes: L is singular), phi normalised to zero mean there.            */
+/* ------------------------------------------------------------------------------------------ */
+static long nd_index(const or_geom* g, int i, int j, int k) {
+    const int* n = g->box.n;
+    return (long)i + (long)(n[0] + 1) * ((long)j + (long)(n[1] + 1) * (long)k);
+}
+static long nd_count(const or_geom* g) {
+    const int* n = g->box.n;
+    return (long)(n[0] + 1) * (n[1] + 1) * (n[2] + 1);
+}
+/* node of corner a (bit d set: upper side in d) of cell (i, j, k); in a periodic direction the
+ * last node is the first */
+static long nd_corner(const or_geom* g, const int q[3], int a) {
+    int r[3];
+    for (int d = 0; d < 3; d++) {
+        r[d] = q[d] + ((a >> d) & 1);
+        if (g->box.periodic[d] && r[d] == g->box.n[d]) r[d] = 0;
+    }
+    return nd_index(g, r[0], r[1], r[2]);
+}
+/* the trilinear stiffness of the unit cube between corners a and b: sum over d of the 1D
+ * derivative term (+1 same side, -1 opposite) times the 1D mass terms of the other two
+ * directions (1/3 same side, 1/6 opposite) */
+static double khat(int a, int b) {
+    double s = 0.0;
+    for (int d = 0; d < 3; d++) {
+        double t = (((a ^ b) >> d) & 1) ? -1.0 : 1.0;
+        for (int e = 0; e < 3; e++)
+            if (e != d) t *= (((a ^ b) >> e) & 1) ? 1.0 / 6.0 : 1.0 / 3.0;
+        s += t;
+    }
+    return s;
+}
+/* periodic copies: the last node of a periodic direction takes the first node's value */
+static void nd_sync(const or_geom* g, double* x) {
+    const int* n = g->box.n;
+    for (int k = 0; k <= n[2]; k++)
+        for (int j = 0; j <= n[1]; j++)
+            for (int i = 0; i <= n[0]; i++) {
+                int r[3] = {i, j, k};
+                for (int d = 0; d < 3; d++)
+                    if (g->box.periodic[d] && r[d] == n[d]) r[d] = 0;
+                x[nd_index(g, i, j, k)] = x[nd_index(g, r[0], r[1], r[2])];
+            }
+}
+
+void or_nodal_div(const or_geom* g, const double* w, double* dn) {
+    const int* n = g->box.n;
+    long N = g->N, M = nd_count(g);
+    double h = g->box.h;
+    memset(dn, 0, M * sizeof(double));
+    for (long c = 0; c < N; c++) {
+        double al = g->alpha[c];
+        if (al <= 0.0) continue;
+        int q[3];
+        cell_ijk(n, c, q);
+        for (int a = 0; a < 8; a++) {
+            double s = 0.0;
+            for (int d = 0; d < 3; d++) s += (((a >> d) & 1) ? 1.0 : -1.0) * w[d * N + c];
+            dn[nd_corner(g, q, a)] += al * h * h / 4.0 * s;
+        }
+    }
+    nd_sync(g, dn);
+}
+
+void or_nodal_bflux(const or_geom* g, double* bn) {
+    const int* n = g->box.n;
+    long N = g->N, M = nd_count(g);
+    double h = g->box.h;
+    memset(bn, 0, M * sizeof(double));
+    for (int d = 0; d < 3; d++) {
+        if (g->box.periodic[d]) continue;
+        for (int side = 0; side < 2; side++) {
+            double un = g->box.wall_u[2 * d + side][d] * (side ? 1.0 : -1.0);
+            for (long c = 0; c < N; c++) {
+                int q[3];
+                cell_ijk(n, c, q);
+                if (q[d] != (side ? n[d] - 1 : 0)) continue;
+                int f[3] = {q[0], q[1], q[2]};
+                f[d] += side;
+                double A = g->ap[d][fidx(n, d, f[0], f[1], f[2])];
+                if (A == 0.0) continue;
+                for (int a = 0; a < 8; a++)
+                    if (((a >> d) & 1) == side) bn[nd_corner(g, q, a)] += A * h * h / 4.0 * un;
+            }
+        }
+    }
+    for (int cid = 0; cid < g->ncut; cid++) {
+        int q[3];
+        cell_ijk(n, g->cut[cid], q);
+        double un = 0.0;
+        for (int d = 0; d < 3; d++) un -= g->body.u_eb[d] * g->nrm[3 * cid + d];
+        for (int a = 0; a < 8; a++) bn[nd_corner(g, q, a)] += g->aeb[cid] * h * h / 8.0 * un;
+    }
+    nd_sync(g, bn);
+}
+
+void or_nodal_apply(const or_geom* g, const double* x, double* y) {
+    const int* n = g->box.n;
+    long N = g->N, M = nd_count(g);
+    double h = g->box.h;
+    memset(y, 0, M * sizeof(double));
+    for (long c = 0; c < N; c++) {
+        double al = g->alpha[c];
+        if (al <= 0.0) continue;
+        int q[3];
+        cell_ijk(n, c, q);
+        long nodes[8];
+        for (int a = 0; a < 8; a++) nodes[a] = nd_corner(g, q, a);
+        for (int a = 0; a < 8; a++) {
+            double s = 0.0;
+            for (int b = 0; b < 8; b++) s += khat(a, b) * x[nodes[b]];
+            y[nodes[a]] += al * h * s;
+        }
+    }
+    nd_sync(g, y);
+}
+
+void or_nodal_grad(const or_geom* g, const double* qn, double* gp) {
+    const int* n = g->box.n;
+    long N = g->N;
+    double h = g->box.h;
+    for (long c = 0; c < N; c++) {
+        int q[3];
+        cell_ijk(n, c, q);
+        for (int d = 0; d < 3; d++) {
+            double s = 0.0;
+            for (int a = 0; a < 8; a++)
+                s += (((a >> d) & 1) ? 1.0 : -1.0) * qn[nd_corner(g, q, a)];
+            gp[d * N + c] = g->alpha[c] > 0.0 ? s / (4.0 * h) : 0.0;
+        }
+    }
+}
+
+/* nodes touching an open cell (the unknowns of the nodal solve) */
+static void nd_active(const or_geom* g, uint8_t* act) {
+    const int* n = g->box.n;
+    memset(act, 0, nd_count(g));
+    for (long c = 0; c < g->N; c++) {
+        if (g->alpha[c] <= 0.0) continue;
+        int q[3];
+        cell_ijk(n, c, q);
+        for (int a = 0; a < 8; a++) act[nd_corner(g, q, a)] = 1;
+    }
+}
+static void nd_mean_free(const or_geom* g, const uint8_t* act, double* x) {
+    long M = nd_count(g);
+    double s = 0.0;
+    long cnt = 0;
+    for (long m = 0; m < M; m++)
+        if (act[m]) {
+            s += x[m];
+            cnt++;
+        }
+    double mean = cnt ? s / cnt : 0.0;
+    for (long m = 0; m < M; m++) x[m] = act[m] ? x[m] - mean : 0.0;
+}
+
+/* CG for L x = b on the active nodes, the diagonal as preconditioner and the preconditioned
+ * residual mean-free; stop when max|r| <= rtol max(max|b|, scale) */
+static int nd_cg(const or_geom* g, const uint8_t* act, const double* b, double* x, double rtol,
+                 double scale, int maxit, int* iters) {
+    const int* n = g->box.n;
+    long M = nd_count(g);
+    double h = g->box.h;
+    double *r = malloc(M * 8), *z = malloc(M * 8), *p = malloc(M * 8), *q = malloc(M * 8);
+    double* dg = calloc(M, 8);
+    for (long c = 0; c < g->N; c++) {
+        if (g->alpha[c] <= 0.0) continue;
+        int qq[3];
+        cell_ijk(n, c, qq);
+        for (int a = 0; a < 8; a++) dg[nd_corner(g, qq, a)] += g->alpha[c] * h * khat(a, a);
+    }
+    int ret = OR_ENOCONV;
+    *iters = 0;
+    or_nodal_apply(g, x, q);
+    for (long m = 0; m < M; m++) r[m] = act[m] ? b[m] - q[m] : 0.0;
+    double bn = vmaxabs(b, M);
+    if (scale > bn) bn = scale;
+    double rn0 = vmaxabs(r, M);
+    if (!isfinite(rn0) || !isfinite(bn)) {
+        ret = OR_ENAN;
+        goto done;
+    }
+    if (bn == 0.0 || rn0 <= rtol * bn) {
+        ret = OR_OK;
+        goto done;
+    }
+    for (long m = 0; m < M; m++) z[m] = act[m] ? r[m] / dg[m] : 0.0;
+    nd_mean_free(g, act, z);
+    memcpy(p, z, M * 8);
+    double rz = vdot(r, z, M);
+    for (int it = 1; it <= maxit; it++) {
+        or_nodal_apply(g, p, q);
+        for (long m = 0; m < M; m++)
+            if (!act[m]) q[m] = 0.0;
+        double al = rz / vdot(p, q, M);
+        for (long m = 0; m < M; m++) {
+            x[m] += al * p[m];
+            r[m] -= al * q[m];
+        }
+        *iters = it;
+        double rn = vmaxabs(r, M);
+        if (!isfinite(rn)) {
+            ret = OR_ENAN;
+            break;
+        }
+        if (rn <= rtol * bn) {
+            ret = OR_OK;
+            break;
+        }
+        for (long m = 0; m < M; m++) z[m] = act[m] ? r[m] / dg[m] : 0.0;
+        nd_mean_free(g, act, z);
+        double rzn = vdot(r, z, M);
+        double be = rzn / rz;
+        rz = rzn;
+        for (long m = 0; m < M; m++) p[m] = z[m] + be * p[m];
+    }
+done:
+    free(r);
+    free(z);
+    free(p);
+    free(q);
+    free(dg);
+    return ret;
+}
+
+int or_nodal_project(const or_geom* g, double beta, double* u, double* pn, double rtol,
+                     int maxit, double* div_inf, int* iters) {
+    const int* n = g->box.n;
+    long N = g->N, N3 = 3 * N, M = nd_count(g);
+    double h = g->box.h;
+    double *w = malloc(N3 * 8), *gp = malloc(N3 * 8), *rhs = malloc(M * 8), *bf = malloc(M * 8);
+    double *phi = malloc(M * 8), *tsum = calloc(M, 8);
+    uint8_t* act = malloc(M);
+    nd_active(g, act);
+    /* w = u + beta G p_old */
+    or_nodal_grad(g, pn, gp);
+    for (long t = 0; t < N3; t++) w[t] = u[t] + beta * gp[t];
+    or_nodal_div(g, w, rhs);
+    or_nodal_bflux(g, bf);
+    for (long m = 0; m < M; m++) rhs[m] = act[m] ? rhs[m] - bf[m] : 0.0;
+    /* the size of the terms summed into D(w)_n: the stop test's second scale */
+    for (long c = 0; c < N; c++) {
+        if (g->alpha[c] <= 0.0) continue;
+        int q[3];
+        cell_ijk(n, c, q);
+        double s = 0.0;
+        for (int d = 0; d < 3; d++) s += fabs(w[d * N + c]);
+        for (int a = 0; a < 8; a++) tsum[nd_corner(g, q, a)] += g->alpha[c] * h * h / 4.0 * s;
+    }
+    double scale = vmaxabs(tsum, M);
+    nd_mean_free(g, act, rhs); /* the rounding part of an incompatible right-hand side */
+    for (long m = 0; m < M; m++) phi[m] = act[m] ? beta * pn[m] : 0.0;
+    int ret = nd_cg(g, act, rhs, phi, rtol, scale, maxit, iters);
+    nd_mean_free(g, act, phi);
+    nd_sync(g, phi);
+    or_nodal_grad(g, phi, gp);
+    for (long t = 0; t < N3; t++) {
+        long c = t % N;
+        u[t] = g->alpha[c] > 0.0 ? w[t] - gp[t] : g->body.u_eb[t / N];
+    }
+    for (long m = 0; m < M; m++) pn[m] = phi[m] / beta;
+    if (div_inf) { /* the weak divergence left in the projected field (not zero: approximate) */
+        or_nodal_div(g, u, rhs);
+        for (long m = 0; m < M; m++) rhs[m] = act[m] ? rhs[m] - bf[m] : 0.0;
+        *div_inf = vmaxabs(rhs, M);
+    }
+    free(w);
+    free(gp);
+    free(rhs);
+    free(bf);
+    free(phi);
+    free(tsum);
+    free(act);
+    return ret;
+}
+
+void or_drag_nodal(const or_geom* g, const or_rheo* r, const double* theta, const double* u,
+                   const double* pn, double F[3]) {
+    const int* n = g->box.n;
+    double h = g->box.h;
+    double* gw = calloc(3 * (g->ncut + 1), sizeof(double));
+    or_wall_gradient(g, u, gw);
+    F[0] = F[1] = F[2] = 0.0;
+    for (int cid = 0; cid < g->ncut; cid++) {
+        long c = g->cut[cid];
+        int q[3];
+        cell_ijk(n, c, q);
+        const double* nv = &g->nrm[3 * cid];
+        const double* gg = &gw[3 * cid];
+        double Gm[3][3];
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) Gm[a][b] = nv[a] * gg[b];
+        double eeb = law_eta(r, r->tau0 * (theta ? theta[c] : 1.0), strain_norm(Gm));
+        /* trilinear interpolation of the nodal pressure at the wall centroid */
+        double pe = 0.0;
+        for (int a = 0; a < 8; a++) {
+            double wgt = 1.0;
+            for (int d = 0; d < 3; d++) {
+                double xi = g->bc[3 * cid + d] + 0.5;
+                wgt *= ((a >> d) & 1) ? xi : 1.0 - xi;
+            }
+            pe += wgt * pn[nd_corner(g, q, a)];
+        }
+        for (int a = 0; a < 3; a++) {
+            double tn = 0;
+            for (int b = 0; b < 3; b++) tn += eeb * (Gm[a][b] + Gm[b][a]) * nv[b];
+            F[a] += g->aeb[cid] * h * h * (tn - pe * nv[a]);
+        }
+    }
+    free(gw);
 }
 
 /* ------------------------------------------------------------------------------------------ */

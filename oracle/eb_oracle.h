@@ -67,7 +67,11 @@ typedef struct {
     int max_iter;
     int nu1, nu2, nbottom;   /* V(nu1,nu2) smoothing; bottom sweeps on the coarsest level */
     double force[3];         /* body force per unit volume */
+    int projection;          /* end-of-stage projection: OR_PROJ_CELL (cell-centred pressure) or
+                                OR_PROJ_NODAL (Sec. III.A.4: pressure on the nodes) */
 } or_opts;
+
+enum { OR_PROJ_CELL = 0, OR_PROJ_NODAL = 1 };
 
 typedef struct {
     int it_mac[2], it_visc[2], it_proj[2];
@@ -127,6 +131,23 @@ double or_stable_dt(const or_geom* g, const or_rheo* r, const double* theta, con
                     const double force[3], double c_cfl);
 void or_drag(const or_geom* g, const or_rheo* r, const double* theta, const double* u,
              const double* p, double F[3]);
+
+/* ---- nodal projection (Sec. III.A.4).  Nodal arrays are [nz+1][ny+1][nx+1] (x fastest); in a
+ * periodic direction the last node is a copy of the first. ---- */
+/* weak nodal divergence of a cell field w [3][N] (boundary flux not included) */
+void or_nodal_div(const or_geom* g, const double* w, double* dn);
+/* the boundary flux B of the domain walls and the embedded wall */
+void or_nodal_bflux(const or_geom* g, double* bn);
+/* the volume-fraction-weighted trilinear stiffness matrix applied to a nodal field */
+void or_nodal_apply(const or_geom* g, const double* x, double* y);
+/* cell average of the gradient of the trilinear interpolant: gp [3][N] */
+void or_nodal_grad(const or_geom* g, const double* q, double* gp);
+/* end-of-stage projection with a nodal pressure pn (in: old, out: new) */
+int or_nodal_project(const or_geom* g, double beta, double* u, double* pn, double rtol,
+                     int maxit, double* div_inf, int* iters);
+/* drag with a nodal pressure (trilinear interpolation of pn at the wall centroid) */
+void or_drag_nodal(const or_geom* g, const or_rheo* r, const double* theta, const double* u,
+                   const double* pn, double F[3]);
 
 /* ---- adjoint (reverse mode): exact transposes of the linearised forward routines, solves taken
  * as exact, switches frozen at their forward values.  Arguments ending in b are adjoints

@@ -37,7 +37,10 @@ class OrRheo(C.Structure):
 class OrOpts(C.Structure):
     _fields_ = [("rtol_visc", C.c_double), ("rtol_mac", C.c_double), ("rtol_proj", C.c_double),
                 ("max_iter", C.c_int), ("nu1", C.c_int), ("nu2", C.c_int),
-                ("nbottom", C.c_int), ("force", C.c_double * 3)]
+                ("nbottom", C.c_int), ("force", C.c_double * 3), ("projection", C.c_int)]
+
+
+PROJ_CELL, PROJ_NODAL = 0, 1
 
 
 class OrStats(C.Structure):
@@ -99,6 +102,12 @@ def lib():
                                     C.POINTER(C.c_int)]),
             "or_rk2_step_adjoint": (_I, [_P, _P, _P, _D, _P, _P, _P, _P, _P, _P, _P]),
             "or_drag_adj": (None, [_P, _P, _P, _P, _P, _P, _P, _P]),
+            "or_nodal_div": (None, [_P, _P, _P]),
+            "or_nodal_bflux": (None, [_P, _P]),
+            "or_nodal_apply": (None, [_P, _P, _P]),
+            "or_nodal_grad": (None, [_P, _P, _P]),
+            "or_nodal_project": (_I, [_P, _D, _P, _P, _D, _I, C.POINTER(_D), C.POINTER(C.c_int)]),
+            "or_drag_nodal": (None, [_P, _P, _P, _P, _P, _P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -162,8 +171,10 @@ def make_rheo(w, tau0=None) -> OrRheo:
     return r
 
 
-def make_opts(w=None, rtol=None, max_iter=400, nu1=2, nu2=2, nbottom=16) -> OrOpts:
+def make_opts(w=None, rtol=None, max_iter=400, nu1=2, nu2=2, nbottom=16,
+              projection=PROJ_CELL) -> OrOpts:
     o = OrOpts()
+    o.projection = int(projection)
     rt = rtol if rtol is not None else (w.rtol if w is not None else 1e-12)
     o.rtol_visc = o.rtol_mac = o.rtol_proj = float(rt)
     o.max_iter = int(max_iter)
@@ -378,6 +389,49 @@ class Geometry:
         F = np.zeros(3)
         lib().or_drag(self.g, C.byref(rheo), _ptr(theta), _ptr(np.ascontiguousarray(u)),
                       _ptr(np.ascontiguousarray(p)), _ptr(F))
+        return F
+
+    # ---------------------------------------------------------------- nodal projection
+    @property
+    def node_shape(self):
+        nz, ny, nx = self.shape
+        return (nz + 1, ny + 1, nx + 1)
+
+    def nodal_div(self, w):
+        out = np.zeros(self.node_shape)
+        lib().or_nodal_div(self.g, _ptr(self._c(w)), _ptr(out))
+        return out
+
+    def nodal_bflux(self):
+        out = np.zeros(self.node_shape)
+        lib().or_nodal_bflux(self.g, _ptr(out))
+        return out
+
+    def nodal_apply(self, x):
+        out = np.zeros(self.node_shape)
+        lib().or_nodal_apply(self.g, _ptr(self._c(x)), _ptr(out))
+        return out
+
+    def nodal_grad(self, q):
+        out = np.zeros((3,) + self.shape)
+        lib().or_nodal_grad(self.g, _ptr(self._c(q)), _ptr(out))
+        return out
+
+    def nodal_project(self, u, pn, beta, opts):
+        u = self._c(u)
+        pn = self._c(pn)
+        div = C.c_double(0.0)
+        it = C.c_int(0)
+        e = lib().or_nodal_project(self.g, float(beta), _ptr(u), _ptr(pn), opts.rtol_proj,
+                                   opts.max_iter, C.byref(div), C.byref(it))
+        if e:
+            raise OracleError(f"or_nodal_project: {e}")
+        return u, pn, div.value, it.value
+
+    def drag_nodal(self, u, pn, rheo, theta=None):
+        F = np.zeros(3)
+        lib().or_drag_nodal(self.g, C.byref(rheo), _ptr(theta), _ptr(np.ascontiguousarray(u)),
+                            _ptr(np.ascontiguousarray(pn)), _ptr(F))
         return F
 
 
