@@ -119,7 +119,12 @@ typedef struct {
                              that leg; negative: the default 2) */
     int nbottom;          /* sweep pairs on the coarsest level (<= 0: the default 16) */
     double force[3];      /* body force per unit volume (host values) */
+    int projection;       /* end-of-stage projection: EB_PROJ_CELL (default; cell-centred
+                             pressure [N]) or EB_PROJ_NODAL (Sec. III.A.4: the pressure on the
+                             nodes [nz+1][ny+1][nx+1]; no adjoint) */
 } eb_step_opts;
+
+enum { EB_PROJ_CELL = 0, EB_PROJ_NODAL = 1 };
 
 typedef struct {
     int it_mac[2], it_visc[2], it_proj[2];  /* Krylov iterations, predictor / corrector */
@@ -254,6 +259,25 @@ int eb_mac_project(eb_ctx* ctx, double beta, double* fx, double* fy, double* fz,
  * u (device) [3][N] in/out; p (device) [N] in: old pressure, out: new pressure. */
 int eb_cc_project(eb_ctx* ctx, double beta, double* u, double* p, double rtol,
                   const eb_step_opts* opts, double* div_inf, int* iters, void* stream);
+
+/* The nodal end-of-stage projection (Sec. III.A.4, Alg. advance NodalProjection): velocities on
+ * cell centres, the pressure on the nodes, an approximate projection.  Trilinear finite elements
+ * on each cell weighted by its volume fraction: u += beta G(pn); solve L phi = D(u) - B, where
+ * D is the weak nodal divergence, B the flux of the wall and embedded-wall velocities and L the
+ * elements' stiffness matrix (singular: phi is normalised to zero mean over the nodes of open
+ * cells), by CG with the diagonal as preconditioner (at most max(max_iter, 10 max n_d)
+ * iterations) to max|r| <= rtol max(max|D - B|, the largest sum of |terms| of D at a node);
+ * u -= G(phi) on open cells, with G(q) the cell average of the gradient of q's trilinear
+ * interpolant; pn = phi / beta.  u (device) [3][N] in/out; pn (device) [nz+1][ny+1][nx+1]
+ * in: old, out: new (in a periodic direction the last node is a copy of the first).
+ * *div_inf (host, nullable) = max |D(u) - B| left (not zero: the projection is approximate). */
+int eb_nodal_project(eb_ctx* ctx, double beta, double* u, double* pn, double rtol,
+                     const eb_step_opts* opts, double* div_inf, int* iters, void* stream);
+
+/* eb_drag with a nodal pressure pn (device) [nz+1][ny+1][nx+1] (a step with EB_PROJ_NODAL):
+ * the wall pressure p_EB is the trilinear interpolation of pn at the EB centroid. */
+int eb_drag_nodal(const eb_ctx* ctx, const eb_rheology* rheo, const double* theta,
+                  const double* u, const double* pn, double F[3], void* stream);
 
 /* DerivedQuantities (Alg. derived): limited slopes, face extrapolation and upwinding, the
  * MAC projection, convective term C = -div(u (x) u^F), eta and eta_eb, and the explicit term

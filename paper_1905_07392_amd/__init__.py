@@ -7,7 +7,7 @@ entry point.
 from __future__ import annotations
 
 
-def from_workload(w, precision=0, rtol=None, max_iter=400):
+def from_workload(w, precision=0, rtol=None, max_iter=400, projection=0):
     """(box, body, rheology, opts) structs for an object with the workload attributes
     (n, h, lo, periodic, wall_u, body dict, law, mu, tau0, eps, rho, force, rtol)."""
     from . import api
@@ -22,5 +22,5 @@ def from_workload(w, precision=0, rtol=None, max_iter=400):
                          plane_d=bd.get("plane_d", 0.0), u_eb=bd.get("u_eb", (0.0, 0.0, 0.0)))
     rheo = api.make_rheology(w.law, w.mu, w.tau0, w.eps, w.rho, w.kappa, w.flow_n, w.eta0)
     opts = api.make_opts(precision=precision, rtol=w.rtol if rtol is None else rtol,
-                         max_iter=max_iter, force=w.force)
+                         max_iter=max_iter, force=w.force, projection=projection)
     return box, body, rheo, opts

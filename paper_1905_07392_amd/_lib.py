@@ -39,7 +39,11 @@ class EbRheology(C.Structure):
 class EbStepOpts(C.Structure):
     _fields_ = [("precision", C.c_int), ("rtol_visc", C.c_double), ("rtol_mac", C.c_double),
                 ("rtol_proj", C.c_double), ("max_iter", C.c_int), ("nu1", C.c_int),
-                ("nu2", C.c_int), ("nbottom", C.c_int), ("force", C.c_double * 3)]
+                ("nu2", C.c_int), ("nbottom", C.c_int), ("force", C.c_double * 3),
+                ("projection", C.c_int)]
+
+
+EB_PROJ_CELL, EB_PROJ_NODAL = 0, 1
 
 
 class EbStepStats(C.Structure):
@@ -75,6 +79,8 @@ SIGNATURES = {
     "eb_rk2_step": (_I, [_P, _P, _P, _D, _P, _P, _P, _P, _P]),
     "eb_drag": (_I, [_P, _P, _P, _P, _P, _DP, _P]),
     "eb_drag_noalloc": (_I, [_P, _P, _P, _P, _P, _DP, _P]),
+    "eb_drag_nodal": (_I, [_P, _P, _P, _P, _P, _DP, _P]),
+    "eb_nodal_project": (_I, [_P, _D, _P, _P, _D, _P, _DP, _IP, _P]),
     "eb_pressure_gradient": (_I, [_P, _P, _P, _P]),
     "eb_tape_bytes": (C.c_size_t, [_P]),
     "eb_rk2_step_taped": (_I, [_P, _P, _P, _D, _P, _P, _P, _P, _P, _P]),

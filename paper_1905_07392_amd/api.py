@@ -13,6 +13,7 @@ import torch
 
 from . import _lib as L
 from ._lib import (EB_FP64, EB_MIXED, EB_OP_HELMHOLTZ, EB_OP_HELMHOLTZ_H, EB_OP_TRANSPOSE,
+                   EB_PROJ_CELL, EB_PROJ_NODAL,
                    EB_SWITCH_OFF, EB_SWITCH_RECORD, EB_SWITCH_REPLAY, EB_SYS_POISSON, EB_SYS_VISC,
                    EbBody, EbBox, EbRheology, EbStepOpts, EbStepStats, check)
 
@@ -20,11 +21,12 @@ __all__ = ["EbContext", "make_box", "make_body", "make_rheology", "make_opts",
            "eb_workspace_bytes", "eb_geometry_build", "eb_geometry_export",
            "eb_apparent_viscosity", "eb_viscous_apply", "eb_mg_vcycle", "eb_visc_solve",
            "eb_mac_project", "eb_cc_project", "eb_derived", "eb_rk2_step", "eb_drag",
-           "eb_pressure_gradient", "eb_drag_noalloc", "eb_stable_dt", "eb_tape_bytes", "eb_rk2_step_taped",
+           "eb_pressure_gradient", "eb_drag_noalloc", "eb_nodal_project", "eb_drag_nodal", "eb_stable_dt", "eb_tape_bytes", "eb_rk2_step_taped",
            "eb_rk2_step_adjoint", "eb_drag_adjoint", "eb_mac_project_adjoint", "eb_cc_project_adjoint",
            "eb_visc_solve_adjoint", "eb_derived_adjoint", "EB_FP64", "EB_MIXED", "EB_OP_HELMHOLTZ",
            "EB_OP_HELMHOLTZ_H", "EB_OP_TRANSPOSE", "EB_SYS_POISSON", "EB_SYS_VISC",
-           "EB_SWITCH_OFF", "EB_SWITCH_RECORD", "EB_SWITCH_REPLAY"]
+           "EB_SWITCH_OFF", "EB_SWITCH_RECORD", "EB_SWITCH_REPLAY", "EB_PROJ_CELL",
+           "EB_PROJ_NODAL"]
 
 
 def _stream(device=None):
@@ -93,9 +95,11 @@ def make_rheology(law, mu, tau0, eps, rho, kappa=1.0, n=1.0, eta0=1.0) -> EbRheo
 
 
 def make_opts(precision=EB_FP64, rtol=1e-12, max_iter=400, nu1=2, nu2=2, nbottom=16,
-              force=(0.0, 0.0, 0.0), rtol_visc=None, rtol_mac=None, rtol_proj=None) -> EbStepOpts:
+              force=(0.0, 0.0, 0.0), rtol_visc=None, rtol_mac=None, rtol_proj=None,
+              projection=EB_PROJ_CELL) -> EbStepOpts:
     o = EbStepOpts()
     o.precision = int(precision)
+    o.projection = int(projection)
     o.rtol_visc = float(rtol if rtol_visc is None else rtol_visc)
     o.rtol_mac = float(rtol if rtol_mac is None else rtol_mac)
     o.rtol_proj = float(rtol if rtol_proj is None else rtol_proj)
@@ -129,6 +133,7 @@ class EbContext:
         self.N = nx * ny * nz
         self.shape = (nz, ny, nx)
         self.face_shapes = [(nz, ny, nx + 1), (nz, ny + 1, nx), (nz + 1, ny, nx)]
+        self.node_shape = (nz + 1, ny + 1, nx + 1)
         self.h = box.h
 
     def close(self):
@@ -295,8 +300,9 @@ def eb_rk2_step(ctx: EbContext, rheo: EbRheology, dt, opts: EbStepOpts, u, p, th
         p = p.clone().contiguous()
     st = EbStepStats()
     th = _f64(theta, ctx.shape, "theta") if theta is not None else None
+    pshape = ctx.node_shape if opts.projection == EB_PROJ_NODAL else ctx.shape
     code = L.lib().eb_rk2_step(ctx.ptr, C.byref(rheo), th, float(dt), C.byref(opts),
-                               _f64(u, (3,) + ctx.shape, "u"), _f64(p, ctx.shape, "p"),
+                               _f64(u, (3,) + ctx.shape, "u"), _f64(p, pshape, "p"),
                                C.byref(st), _stream(ctx.device))
     if not (allow_noconv and code == L.EB_ENOCONV):
         check(code, "eb_rk2_step")
@@ -326,6 +332,31 @@ def eb_drag(ctx: EbContext, rheo: EbRheology, u, p, theta=None):
     th = _f64(theta, ctx.shape, "theta") if theta is not None else None
     check(L.lib().eb_drag(ctx.ptr, C.byref(rheo), th, _f64(u, (3,) + ctx.shape, "u"),
                           _f64(p, ctx.shape, "p"), F, _stream(ctx.device)), "eb_drag")
+    return [F[0], F[1], F[2]]
+
+
+def eb_nodal_project(ctx: EbContext, u, pn, beta, opts: EbStepOpts, rtol=None):
+    """Nodal end-of-stage projection of u with the nodal pressure pn (node_shape): returns
+    (u, pn, max |D(u) - B| left, CG iterations), new tensors."""
+    u = u.clone().contiguous()
+    pn = pn.clone().contiguous()
+    div = C.c_double(0.0)
+    it = C.c_int(0)
+    rt = opts.rtol_proj if rtol is None else rtol
+    check(L.lib().eb_nodal_project(ctx.ptr, float(beta), _f64(u, (3,) + ctx.shape, "u"),
+                                   _f64(pn, ctx.node_shape, "pn"), float(rt), C.byref(opts),
+                                   C.byref(div), C.byref(it), _stream(ctx.device)),
+          "eb_nodal_project")
+    return u, pn, div.value, it.value
+
+
+def eb_drag_nodal(ctx: EbContext, rheo: EbRheology, u, pn, theta=None):
+    """Force on the body with a nodal pressure pn (node_shape)."""
+    F = (C.c_double * 3)()
+    th = _f64(theta, ctx.shape, "theta") if theta is not None else None
+    check(L.lib().eb_drag_nodal(ctx.ptr, C.byref(rheo), th, _f64(u, (3,) + ctx.shape, "u"),
+                                _f64(pn, ctx.node_shape, "pn"), F, _stream(ctx.device)),
+          "eb_drag_nodal")
     return [F[0], F[1], F[2]]
 
 

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libeb.so")
 OBJ = os.path.join(HERE, "_build")
 SOURCES = ["eb_geometry.hip", "eb_ops.hip", "eb_mg.hip", "eb_krylov.hip", "eb_adjoint.hip",
-           "eb_api.hip"]
+           "eb_nodal.hip", "eb_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",

@@ -141,6 +141,10 @@ struct eb_ctx {
     WallT wt;
     double *Gb, *ubm, *lam, *ehb, *ebhb, *rX, *rY, *gwb;
     double* tbs;  // the per-cell yield-stress adjoint of one reverse call, before it is handed out
+    // nodal projection: boundary flux, diagonal of L and mask of the unknowns (per geometry),
+    // the step's nodal pressure, the wall pressures of the drag
+    double *nd_bflux, *nd_dg, *pn1, *peb;
+    uint8_t* nd_mask;
     double* ufb[3];
     LRV lr;
     // mixed precision: iterations a solve ran with the FP32 V-cycle before it continued with
@@ -274,6 +278,12 @@ size_t carve(eb_ctx* c, char* base, bool dry) {
     c->rY = cv.take<double>(3 * M);
     c->gwb = cv.take<double>(3 * M);
     c->tbs = cv.take<double>(N);
+    long NM = (long)(g.n[0] + 1) * (g.n[1] + 1) * (g.n[2] + 1);
+    c->nd_bflux = cv.take<double>(NM);
+    c->nd_dg = cv.take<double>(NM);
+    c->pn1 = cv.take<double>(NM);
+    c->nd_mask = cv.take<uint8_t>(NM);
+    c->peb = cv.take<double>(M);
     for (int d = 0; d < 3; d++) {
         c->ufb[d] = cv.take<double>(face_count(g, d));
         c->lr.L[d] = cv.take<double>(3 * face_count(g, d));
@@ -745,6 +755,87 @@ void cc_project(eb_ctx* c, double beta, double* u, double* p, double rtol, const
     op_axpy_open(c->g, -beta, c->gp, u, 3, c->s);
 }
 
+// the iteration cap of a nodal solve: max_iter, or ten times the largest cell count along an
+// axis if that is more (the diagonally preconditioned CG needs a number of iterations that grows
+// with the grid)
+int nodal_max_iter(const eb_ctx* c, const SolveCfg& k) {
+    int nmax = std::max(c->grid.n[0], std::max(c->grid.n[1], c->grid.n[2]));
+    return std::max(k.max_iter, 10 * nmax);
+}
+
+// CG for L x = b on the nodal unknowns, the diagonal as preconditioner and the preconditioned
+// residual mean-free over the unknowns (L is singular: constants); state in `slot`; KS_RTOL and
+// KS_SCALE must be set.  Vectors: the Krylov scratch (idle during a projection).
+int nodal_pcg(eb_ctx* c, const double* b, double* x, const SolveCfg& k, int slot) {
+    long M = nd_count(c->grid);
+    double *r = c->kv[0], *z = c->kv[1], *pd = c->kv[2], *q = c->kv[3];
+    double* ks = c->ks;
+    int* st = c->kst + 2 * slot;
+    int* itc = c->kst + 2 * NSLOT + slot;
+    const uint8_t* mk = c->nd_mask;
+    nd_apply(c->g, x, mk, q, c->s);
+    vec_sub_scaled(M, b, 1.0, q, r, c->s);  // zero off the unknowns: b and q are
+    red_maxabs(M, 1, b, c->part, ks + KS_BN, c->s);
+    red_maxabs(M, 1, r, c->part, ks + KS_RN, c->s);
+    ks_op(KS_INIT, ks, st, itc, c->s);
+    nd_jacobi(M, r, c->nd_dg, mk, z, c->s, st);
+    nd_mean_free(M, z, mk, c->part, ks + KS_SUM, c->s, st);
+    vec_copy(M, z, pd, c->s);
+    const double* A1[4] = {r, nullptr, nullptr, nullptr};
+    const double* B1[4] = {z, nullptr, nullptr, nullptr};
+    red_dots(M, 1, A1, B1, c->part, ks + KS_RZ, c->s, st);
+    GraphKey key = make_key();
+    key.kind = 3;
+    key.slot = slot;
+    key.nc = 1;
+    key.p[0] = x;
+    key.p[1] = b;
+    auto body = [&]() {
+        const double* A[4] = {pd, nullptr, nullptr, nullptr};
+        const double* B[4] = {q, nullptr, nullptr, nullptr};
+        nd_apply(c->g, pd, mk, q, c->s, st);
+        red_dots_op(M, 1, A, B, c->part, KS_PQ, KS_CG_ALPHA, ks, st, itc, c->s);
+        ks_cg_xr_op(M, x, r, pd, q, c->part, ks, st, itc, c->s);
+        nd_jacobi(M, r, c->nd_dg, mk, z, c->s, st);
+        nd_mean_free(M, z, mk, c->part, ks + KS_SUM, c->s, st);
+        A[0] = r;
+        B[0] = z;
+        red_dots_op(M, 1, A, B, c->part, KS_RZN, KS_CG_BETA, ks, st, itc, c->s);
+        ks_cg_p(M, pd, z, ks, st, c->s);
+    };
+    return iterate(c, key, slot, nodal_max_iter(c, k), body, false);
+}
+
+// The nodal end-of-stage projection (Sec. III.A.4): u += beta G(pn_old); solve
+// L phi = D(u) - B (the right-hand side made mean-free over the unknowns), from phi = beta pn_old;
+// phi normalised to zero mean; u -= G(phi) on open cells; pn = phi / beta.  want_div: the
+// largest |D(u) - B| left over the unknowns into divs[slot] (not zero: the projection is
+// approximate).
+void nodal_project(eb_ctx* c, double beta, double* u, double* pn, double rtol, const SolveCfg& k,
+                   int slot, bool want_div) {
+    long M = nd_count(c->grid);
+    double *phi = c->kv[4], *rhs = c->kv[5], *tsum = c->kv[6];
+    const uint8_t* mk = c->nd_mask;
+    nd_grad(c->g, pn, c->gp, c->s);
+    op_axpy_open(c->g, beta, c->gp, u, 3, c->s);
+    nd_div(c->g, u, c->nd_bflux, mk, rhs, tsum, c->s);
+    red_maxabs(M, 1, tsum, c->part, c->ks + KS_SCALE, c->s);
+    ks_set(c->ks, KS_RTOL, rtol, c->s);
+    nd_mean_free(M, rhs, mk, c->part, c->ks + KS_SUM, c->s);
+    nd_scale_masked(M, beta, pn, mk, phi, c->s);
+    c->slot_off[slot] = 0;
+    nodal_pcg(c, rhs, phi, k, slot);
+    nd_mean_free(M, phi, mk, c->part, c->ks + KS_SUM, c->s);
+    nd_sync(c->grid, phi, c->s);
+    nd_grad(c->g, phi, c->gp, c->s);
+    op_axpy_open(c->g, -1.0, c->gp, u, 3, c->s);
+    vec_axpby(M, 1.0 / beta, phi, 0.0, pn, c->s);
+    if (want_div) {
+        nd_div(c->g, u, c->nd_bflux, mk, rhs, nullptr, c->s);
+        red_maxabs(M, 1, rhs, c->part, c->divs + slot, c->s);
+    }
+}
+
 // BiCGSTAB on the three-component system, right-preconditioned by the viscous V-cycle; the
 // slot's count holds half-iterations (= V-cycles)
 //
@@ -1079,6 +1170,7 @@ int eb_geometry_build(const eb_box* box, const eb_body* body, void* ws, size_t w
     fill_geomv(c);
     geom_wall_stencil(c->g, c->dd, c->sidx, c->sw, c->nfb, c->errdev, c->s);
     geom_mark_near(c->grid, c->cut, ncut, c->near, c->s);
+    nd_setup(c->g, c->nd_bflux, c->nd_dg, c->nd_mask, c->s);
     for (int l = 1; l < c->nlev; l++) level_coarsen_geometry(c->lev[l - 1], c->lev[l], c->s);
     for (int l = 0; l < c->nlev; l++) level_mask(c->lev[l], c->s);
     int err = 0;
@@ -1341,6 +1433,23 @@ int eb_cc_project(eb_ctx* c, double beta, double* u, double* p, double rtol,
     return slot_code(sl, "projection", k.max_iter);
 }
 
+int eb_nodal_project(eb_ctx* c, double beta, double* u, double* pn, double rtol,
+                     const eb_step_opts* opts, double* div_inf, int* iters, void* stream) {
+    if (!c || !u || !pn) return set_err(EB_EINVAL, "null argument");
+    if (!(beta > 0.0)) return set_err(EB_EINVAL, "beta must be > 0");
+    StreamScope scope_(c, stream);
+    SolveCfg k = cfg_of(opts);
+    nodal_project(c, beta, u, pn, rtol, k, 0, true);
+    int h = hip_check("eb_nodal_project");
+    if (h) return h;
+    int sl[2];
+    if ((h = read_slots(c, 1, sl))) return h;
+    if (iters) *iters = sl[1];
+    if (div_inf) HIPN(hipMemcpy(div_inf, c->divs, sizeof(double), hipMemcpyDeviceToHost));
+    if ((h = hip_check("divergence read-back"))) return h;
+    return slot_code(sl, "nodal projection", nodal_max_iter(c, k));
+}
+
 int eb_derived(eb_ctx* c, const eb_rheology* rheo, const double* theta, const double* u,
                const eb_step_opts* opts, double* C, double* eta, double* eta_eb, double* V,
                int* iters, void* stream) {
@@ -1427,19 +1536,31 @@ int rk2_impl(eb_ctx* c, const eb_rheology* rheo, const double* theta, double dt,
     red_cfl(c->g, u, theta, c->part, c->divs + 6, c->s);  // for the stats' stable time step
     // slots: 0/3 MAC projection, 1/4 viscous solve, 2/5 end-of-stage projection
     // predictor: derived quantities at u^m
+    bool nodal = o->projection == EB_PROJ_NODAL;
+    if (nodal && tp) return set_err(EB_EINVAL, "the adjoint covers the cell-centred projection only");
+    long NP = nodal ? nd_count(c->grid) : N;  // the pressure's storage: nodes or cells
+    double* pw = nodal ? c->pn1 : c->p1;
+    auto grad_p = [&](const double* q) {
+        if (nodal) nd_grad(c->g, q, c->gp, c->s);
+        else op_gcc(c->g, q, c->gp, c->s);
+    };
+    auto project = [&](int slot) {
+        if (nodal) nodal_project(c, beta, c->u1, pw, o->rtol_proj, k, slot, true);
+        else cc_project(c, beta, c->u1, pw, o->rtol_proj, k, slot, true);
+    };
     if ((h = derived(c, *rheo, theta, u, o, c->C0, c->eta0, c->eb0, c->V0, 0))) return h;
     if (tp) {
         for (int d = 0; d < 3; d++) vec_copy(face_count(c->grid, d), c->f[d], tp->ufm[d], c->s);
         vec_copy(N, c->eta0, tp->em, c->s);
         if (nc > 0) vec_copy(nc, c->eb0, tp->ebm, c->s);
     }
-    op_gcc(c->g, p, c->gp, c->s);
+    grad_p(p);
     op_psi(c->g, rho, dt, u, c->C0, c->V0, c->gp, o->force, c->psi, c->s);
     vec_copy(N3, u, c->u1, c->s);
     visc_solve(c, rho, dt, c->eta0, c->eb0, c->psi, c->u1, o->rtol_visc, k, 1);
     if (tp) vec_copy(N3, c->u1, tp->us1, c->s);
-    vec_copy(N, p, c->p1, c->s);
-    cc_project(c, beta, c->u1, c->p1, o->rtol_proj, k, 2, true);
+    vec_copy(NP, p, pw, c->s);
+    project(2);
     if (tp) vec_copy(N3, c->u1, tp->u1, c->s);
     // corrector: derived quantities at u*, averaged with the predictor's
     if ((h = derived(c, *rheo, theta, c->u1, o, c->C1, c->eta1, c->eb1, c->V1, 3))) return h;
@@ -1453,14 +1574,14 @@ int rk2_impl(eb_ctx* c, const eb_rheology* rheo, const double* theta, double dt,
         vec_copy(N, c->eta0, tp->ea, c->s);
         if (nc > 0) vec_copy(nc, c->eb0, tp->eba, c->s);
     }
-    op_gcc(c->g, c->p1, c->gp, c->s);
+    grad_p(pw);
     op_psi(c->g, rho, dt, u, c->C0, c->V0, c->gp, o->force, c->psi, c->s);
     visc_solve(c, rho, dt, c->eta0, c->eb0, c->psi, c->u1, o->rtol_visc, k, 4);
     if (tp) vec_copy(N3, c->u1, tp->us2, c->s);
-    cc_project(c, beta, c->u1, c->p1, o->rtol_proj, k, 5, true);
+    project(5);
     vec_copy(N3, c->u1, u, c->s);
-    vec_copy(N, c->p1, p, c->s);
-    op_finalize_state(c->g, u, p, c->s);
+    vec_copy(NP, pw, p, c->s);
+    op_finalize_state(c->g, u, nodal ? nullptr : p, c->s);
     if ((h = hip_check("eb_rk2_step"))) return h;
     // one read-back for the whole step
     return step_status(c, k, stats, false, rheo, o);
@@ -1500,6 +1621,8 @@ int eb_rk2_step_adjoint(eb_ctx* c, const eb_rheology* rheo, const double* theta,
                         eb_step_stats* stats, void* stream) {
     if (!c || !rheo || !o || !u0 || !tape || !ub || !pb)
         return set_err(EB_EINVAL, "null argument");
+    if (o->projection == EB_PROJ_NODAL)
+        return set_err(EB_EINVAL, "the adjoint covers the cell-centred projection only");
     if (int e_ = check_rheology(*rheo)) return e_;
     if (!(rheo->rho > 0.0) || !(dt > 0.0)) return set_err(EB_EINVAL, "rho and dt must be > 0");
     StreamScope scope_(c, stream);
@@ -1561,6 +1684,23 @@ int eb_drag(const eb_ctx* cc, const eb_rheology* rheo, const double* theta, cons
     int e = fetch(c, F, 3);
     if (e) return e;
     return hip_check("eb_drag");
+}
+
+int eb_drag_nodal(const eb_ctx* cc, const eb_rheology* rheo, const double* theta,
+                  const double* u, const double* pn, double F[3], void* stream) {
+    eb_ctx* c = const_cast<eb_ctx*>(cc);
+    if (!c || !rheo || !u || !pn || !F) return set_err(EB_EINVAL, "null argument");
+    if (int e_ = check_rheology(*rheo)) return e_;
+    StreamScope scope_(c, stream);
+    F[0] = F[1] = F[2] = 0.0;
+    if (c->ncut == 0) return EB_OK;
+    op_wall_grad(c->g, u, c->gw, c->s);
+    nd_peb(c->g, pn, c->peb, c->s);
+    op_drag_terms(c->g, *rheo, theta, c->gw, nullptr, nullptr, c->DC, c->s, c->peb);
+    red_sum(c->ncut, 3, c->DC, c->part, c->red, c->s);
+    int e = fetch(c, F, 3);
+    if (e) return e;
+    return hip_check("eb_drag_nodal");
 }
 
 int eb_drag_noalloc(const eb_ctx* c, const eb_rheology* rheo, const double* theta,

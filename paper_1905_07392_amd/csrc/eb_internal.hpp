@@ -311,7 +311,8 @@ void op_psi(const GeomV& g, double rho, double dt, const double* u, const double
 void op_average(long n, const double* a, double* b, hipStream_t s);  // b = (a+b)/2
 void op_finalize_state(const GeomV& g, double* u, double* p, hipStream_t s);
 void op_drag_terms(const GeomV& g, const eb_rheology& r, const double* theta, const double* gw,
-                   const double* p, const double* gp, double* terms, hipStream_t s);
+                   const double* p, const double* gp, double* terms, hipStream_t s,
+                   const double* peb = nullptr);
 void op_poisson_rhs(const GeomV& g, const double* div, const double* sumcnt, double* b,
                     hipStream_t s);
 void op_shift_open(const GeomV& g, double* x, const double* sumcnt, hipStream_t s,
@@ -458,6 +459,31 @@ void red_cfl(const GeomV& g, const double* u, const double* theta, double* part,
 void red_sum(long n, int nrow, const double* x, double* part, double* out, hipStream_t s);
 void op_face_flux_max(const GeomV& g, double* const f[3], double* part, double* out,
                       hipStream_t s);
+
+// fixed-order final pass of nrow rows of nb per-block partials (mode 0 sum, 1 max) into out
+void red_final(const double* part, int nb, int nrow, int mode, double* out, hipStream_t s,
+               const int* gate = nullptr);
+
+// nodal projection (eb_nodal.hip): nodal arrays [nz+1][ny+1][nx+1]; mask marks the unknowns
+long nd_count(const GridV& g);
+// out = D(w) - bflux (bflux nullable) on masked nodes (mask nullable: all); tsum (nullable): the
+// sum of the sizes of D's terms per node
+void nd_div(const GeomV& g, const double* w, const double* bflux, const uint8_t* mask,
+            double* out, double* tsum, hipStream_t s);
+// once per geometry: the boundary flux, the diagonal of L and the mask of the unknowns
+void nd_setup(const GeomV& g, double* bflux, double* dg, uint8_t* mask, hipStream_t s);
+void nd_apply(const GeomV& g, const double* x, const uint8_t* mask, double* y, hipStream_t s,
+              const int* gate = nullptr);
+void nd_grad(const GeomV& g, const double* q, double* gp, hipStream_t s);
+void nd_jacobi(long M, const double* r, const double* dg, const uint8_t* mask, double* z,
+               hipStream_t s, const int* gate = nullptr);
+// x minus its mean over the unknowns (0 elsewhere); sumcnt: two device doubles
+void nd_mean_free(long M, double* x, const uint8_t* mask, double* part, double* sumcnt,
+                  hipStream_t s, const int* gate = nullptr);
+void nd_scale_masked(long M, double a, const double* x, const uint8_t* mask, double* y,
+                     hipStream_t s);
+void nd_sync(const GridV& g, double* x, hipStream_t s);
+void nd_peb(const GeomV& g, const double* pn, double* peb, hipStream_t s);
 
 // vector kernels
 void vec_copy(long n, const double* x, double* y, hipStream_t s);

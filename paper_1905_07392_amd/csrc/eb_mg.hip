@@ -2687,6 +2687,11 @@ void red_sum_open(const GeomV& g, const double* x, double* part, double* out, hi
     k_final<<<1, EB_BLOCK, 0, s>>>(part, nb, 2, 0, out, gate);
 }
 
+void red_final(const double* part, int nb, int nrow, int mode, double* out, hipStream_t s,
+               const int* gate) {
+    k_final<<<1, EB_BLOCK, 0, s>>>(part, nb, nrow, mode, out, gate);
+}
+
 void red_sum(long n, int nrow, const double* x, double* part, double* out, hipStream_t s) {
     int nb = red_blocks(n);
     k_rowsum<<<nb, EB_BLOCK, 0, s>>>(n, nrow, x, part);

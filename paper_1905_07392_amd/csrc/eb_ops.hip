@@ -532,15 +532,18 @@ __global__ void k_finalize_state(GeomV g, double* __restrict__ u, double* __rest
     if (c >= N) return;
     if (!(g.alpha[c] > 0.0)) {
         for (int d = 0; d < 3; d++) u[d * N + c] = g.ueb[d];
-        p[c] = 0.0;
+        if (p) p[c] = 0.0;  // null for a nodal pressure
     }
 }
 
 // gp null: the pressure gradient of each cut cell is formed here (gcc_cell, the same
 // arithmetic as k_gcc) instead of being read from a full [3][N] array
+// peb non-null: the wall pressure of each cut cell is given (the nodal projection's pressure
+// interpolated at the wall centroid) and p, gp are not read
 __global__ void k_drag_terms(GeomV g, eb_rheology rh, const double* __restrict__ theta,
                              const double* __restrict__ gw, const double* __restrict__ p,
-                             const double* __restrict__ gp, double* __restrict__ terms) {
+                             const double* __restrict__ gp, double* __restrict__ terms,
+                             const double* __restrict__ peb) {
     int q = blockIdx.x * blockDim.x + threadIdx.x;
     int nc = g.ncut;
     if (q >= nc) return;
@@ -559,9 +562,15 @@ __global__ void k_drag_terms(GeomV g, eb_rheology rh, const double* __restrict__
     double t0 = rh.tau0 * (theta ? theta[c] : 1.0);
     double e = eta_law(rh, t0, strain_rate(G));
     double h = g.grid.h;
-    double pe = p[c];
-    for (int d = 0; d < 3; d++)
-        pe += h * g.bc[(long)d * nc + q] * (gp ? gp[d * N + c] : gcc_cell(g, p, c, ci, cj, ck, d));
+    double pe;
+    if (peb) {
+        pe = peb[q];
+    } else {
+        pe = p[c];
+        for (int d = 0; d < 3; d++)
+            pe += h * g.bc[(long)d * nc + q] *
+                  (gp ? gp[d * N + c] : gcc_cell(g, p, c, ci, cj, ck, d));
+    }
     double area = g.aeb[q] * h * h;
     for (int a = 0; a < 3; a++) {
         double tn = 0.0;
@@ -650,9 +659,10 @@ void op_finalize_state(const GeomV& g, double* u, double* p, hipStream_t s) {
     k_finalize_state<<<grid_for(g.N), EB_BLOCK, 0, s>>>(g, u, p);
 }
 void op_drag_terms(const GeomV& g, const eb_rheology& r, const double* theta, const double* gw,
-                   const double* p, const double* gp, double* terms, hipStream_t s) {
+                   const double* p, const double* gp, double* terms, hipStream_t s,
+                   const double* peb) {
     if (g.ncut > 0)
-        k_drag_terms<<<grid_for(g.ncut), EB_BLOCK, 0, s>>>(g, r, theta, gw, p, gp, terms);
+        k_drag_terms<<<grid_for(g.ncut), EB_BLOCK, 0, s>>>(g, r, theta, gw, p, gp, terms, peb);
 }
 void op_poisson_rhs(const GeomV& g, const double* div, const double* sumcnt, double* b,
                     hipStream_t s) {
