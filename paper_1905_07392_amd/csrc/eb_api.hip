@@ -234,10 +234,8 @@ size_t carve(eb_ctx* c, char* base, bool dry) {
         L.Df = cv.take<float>(L.N);
         L.x = cv.take<double>(3 * L.N);
         L.b = cv.take<double>(3 * L.N);
-        L.r = cv.take<double>(3 * L.N);
         L.xf = cv.take<float>(3 * L.N);
         L.bf = cv.take<float>(3 * L.N);
-        L.rf = cv.take<float>(3 * L.N);
         if (l == 0) L.etaf = cv.take<float>(L.N);
         for (int d = 0; d < 3; d++) m[d] /= 2;
         h *= 2.0;

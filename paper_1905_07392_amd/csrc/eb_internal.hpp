@@ -225,8 +225,8 @@ struct Level {
     double* D;
     float* Kf[3];
     float* Df;
-    double *x, *b, *r;  // 3 components each
-    float *xf, *bf, *rf;
+    double *x, *b;  // 3 components each
+    float *xf, *bf;
     // the one-work-group tail's operator arrays in its LDS layout (MG_PACK_BYTES, shared by all
     // levels; filled when an operator is built)
     char* pack = nullptr;

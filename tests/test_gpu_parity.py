@@ -209,6 +209,33 @@ def test_vcycle_smoothing_variants(s32, nu1, nu2, nbottom):
         gopts.nu1, gopts.nu2, gopts.nbottom = keep
 
 
+@pytest.mark.parametrize("n", [40, 64])
+@pytest.mark.parametrize("nu1,nu2", [(2, 2), (1, 1), (1, 2), (2, 1)])
+def test_vcycle_deeper_hierarchies(n, nu1, nu2):
+    """V-cycles with more levels between the finest and the tail than the 32^3 sphere has: the
+    64^3 sphere (32^3 and 16^3 levels) and the 40^3 sphere (20^3 and 10^3, odd block counts),
+    for V(2,2), V(1,1), V(1,2) and V(2,1)."""
+    P = Pair(I.sphere_n(n))
+    oopts = P.O.make_opts(P.w, nu1=nu1, nu2=nu2)
+    gopts = P.opts
+    gopts.nu1, gopts.nu2 = nu1, nu2
+    print(f"[parity] vcycle n={n} nu1={nu1} nu2={nu2}", flush=True)
+    r = I.random_field(P.og.shape, 41) * P.open
+    ref = P.og.vcycle(0, r, oopts, beta=0.37)
+    got = P.api.eb_mg_vcycle(P.ctx, P.api.EB_SYS_POISSON, P.dev(r), gopts, beta=0.37)
+    e1 = rel_l2(cpu(got), ref, P.open)
+    u0, _ = P.O.prepare_state(P.w, P.og, P.oopts)
+    eta, eta_eb = P.og.viscosity(u0, P.orheo)
+    r3 = I.random_field((3,) + P.og.shape, 42) * P.open
+    ref3 = P.og.vcycle(1, r3, oopts, rho=P.w.rho, dt=P.w.dt, eta=eta, eta_eb=eta_eb)
+    got3 = P.api.eb_mg_vcycle(P.ctx, P.api.EB_SYS_VISC, P.dev(r3), gopts, rho=P.w.rho,
+                              dt=P.w.dt, eta=P.dev(eta), eta_eb=P.dev(eta_eb))
+    e3 = [rel_l2(cpu(got3)[j], ref3[j], P.open) for j in range(3)]
+    print(f"[parity] vcycle n={n} nu=({nu1},{nu2}): poisson {e1:.2e} visc {e3}",
+          flush=True)
+    assert e1 <= 1e-12 and max(e3) <= 1e-12, (e1, e3)
+
+
 def test_fp32_sweep_needs_an_fp32_finest_level(s32):
     """A mixed hierarchy keeps levels below 64^3 cells in FP64, so on the 32^3 box the FP32
     sweep entry point has no FP32 operator to run and says so."""
