@@ -90,7 +90,10 @@ def counted_traffic(tag):
 
 def time_smoother(api, ctx, precision, sweeps, torch):
     """Average duration (ms) of the finest-level viscous smoother, measured with HIP events on
-    the stream the kernel is launched on (torch's current stream)."""
+    the stream the kernel is launched on (torch's current stream).  A GPU spin is enqueued first
+    so that the host has queued every sweep before the first one starts: the sweeps then run
+    back to back and the figure is the kernels' time, not the host's launch rate (launched one
+    by one from Python, the host falls behind a 20 us kernel)."""
     f32 = precision == api.EB_MIXED
     dt = torch.float32 if f32 else torch.float64
     b = torch.randn((3,) + ctx.shape, dtype=dt, device=ctx.device)
@@ -101,6 +104,7 @@ def time_smoother(api, ctx, precision, sweeps, torch):
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
+    torch.cuda._sleep(50_000_000)  # tens of ms of GPU time, far more than queueing the sweeps
     e0.record(stream)
     for c in range(sweeps):
         api.eb_mg_sweep(ctx, api.EB_SYS_VISC, c & 1, b, x, precision)

@@ -524,8 +524,27 @@ __global__ void k_prolong(GridV gf, GridV gc, const uint8_t* __restrict__ mf,
 // order, as the stored operator, so results are bitwise those of the stored coefficients;
 // cut cells read the stored faces and diagonal.
 // ------------------------------------------------------------------------------------------
+// unsigned division by a fixed divisor d, for dividends below 2^31, as a multiply-high, an add
+// and a shift (m and s from fast_div); the index arithmetic of the finest level's one-thread-
+// per-cell kernels would otherwise spend two integer division sequences per thread
+struct FastDiv {
+    unsigned d, m, s;
+};
+inline FastDiv fast_div(unsigned d) {
+    FastDiv f;
+    f.d = d;
+    f.s = 0;
+    while ((1u << f.s) < d) f.s++;
+    f.m = (unsigned)(((1ull << 32) * ((1ull << f.s) - d)) / d + 1);
+    return f;
+}
+__device__ __forceinline__ unsigned fdiv(unsigned n, const FastDiv& f) {
+    return (__umulhi(n, f.m) + n) >> f.s;
+}
+
 struct Rb0V {
     GridV grid;
+    FastDiv dnx, dny, dnxh;  // n_x, n_y, n_x / 2
     long N;
     const uint8_t* flag;
     const double* eta;
@@ -598,6 +617,27 @@ __device__ __forceinline__ bool rb0_row(const Rb0V& L, long c, int i, int j, int
     return D > (T)0;
 }
 
+// cell coordinates of the t-th cell of colour col (the same as rb_cell below, with the
+// divisions of L's extents)
+__device__ __forceinline__ void rb_cell(const Rb0V& L, unsigned t, int col, int& i, int& j,
+                                        int& k) {
+    unsigned row = fdiv(t, L.dnxh);
+    unsigned ih = t - row * L.dnxh.d;
+    unsigned kk = fdiv(row, L.dny);
+    j = (int)(row - kk * L.dny.d);
+    k = (int)kk;
+    i = 2 * (int)ih + ((j + k + col) & 1);
+}
+// natural cell c's coordinates with L's divisions (cell_coords)
+__device__ __forceinline__ void rb_coords(const Rb0V& L, long c, int& i, int& j, int& k) {
+    unsigned cu = (unsigned)c;
+    unsigned t = fdiv(cu, L.dnx);
+    i = (int)(cu - t * L.dnx.d);
+    unsigned k2 = fdiv(t, L.dny);
+    j = (int)(t - k2 * L.dny.d);
+    k = (int)k2;
+}
+
 // cell coordinates of the t-th cell of colour col
 __device__ __forceinline__ void rb_cell(const GridV& g, unsigned t, int col, int& i, int& j,
                                         int& k) {
@@ -667,7 +707,7 @@ __device__ __forceinline__ void smooth_rb_cell(const Rb0V& L, const T* __restric
                                                const ProV<TC>* P) {
     long N = L.N, Nh = N >> 1;
     int i, j, k;
-    rb_cell(L.grid, (unsigned)t, col, i, j, k);
+    rb_cell(L, (unsigned)t, col, i, j, k);
     long c = cell_index(L.grid, i, j, k);
     long own = (long)col * Nh + t, oth = (long)(1 - col) * Nh;
     T acc[NC];
@@ -734,7 +774,7 @@ __global__ void __launch_bounds__(EB_BLOCK)
     long c = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (c >= N) return;
     int i, j, k;
-    cell_coords(L.grid, c, i, j, k);
+    rb_coords(L, c, i, j, k);
     long nb[6];
 #pragma unroll
     for (int d = 0; d < 3; d++)
@@ -802,7 +842,7 @@ __global__ void k_smooth_first_rb_from(Rb0V L, const double* __restrict__ bnat,
     int col = u >= Nh ? 1 : 0;
     long t = u - col * Nh;
     int i, j, k;
-    rb_cell(L.grid, (unsigned)t, col, i, j, k);
+    rb_cell(L, (unsigned)t, col, i, j, k);
     long c = cell_index(L.grid, i, j, k);
     T bv[NC];
 #pragma unroll
@@ -833,7 +873,7 @@ __global__ void k_smooth_last_rb_to(Rb0V L, const T* __restrict__ b, const T* __
     long t = xcd_block() * (long)blockDim.x + threadIdx.x;
     if (t >= Nh) return;
     int i, j, k;
-    rb_cell(L.grid, (unsigned)t, 0, i, j, k);
+    rb_cell(L, (unsigned)t, 0, i, j, k);
     long c = cell_index(L.grid, i, j, k);
     long c1 = cell_index(L.grid, i ^ 1, j, k);
     T val[NC], bv[NC], x1[NC];
@@ -1041,7 +1081,7 @@ __global__ void k_prolong_rb(Rb0V L, GridV gc, const TC* __restrict__ ec, TF* __
     if (u >= N) return;
     int col = u >= Nh ? 1 : 0;
     int i, j, k;
-    rb_cell(L.grid, (unsigned)(u - col * Nh), col, i, j, k);
+    rb_cell(L, (unsigned)(u - col * Nh), col, i, j, k);
     long f = cell_index(L.grid, i, j, k);
     if (L.flag[f] == 0) return;
     long c = cell_index(gc, i >> 1, j >> 1, k >> 1);
@@ -1703,7 +1743,12 @@ __global__ void k_tail_pack(PackArgs P) {
 // ------------------------------------------------------------------------------------------
 // Every load of a cell (flag, its velocity, the six neighbours' velocities and viscosities) is
 // issued before the first is needed; the arithmetic and its order are unchanged.
+// kin = dt/(2 h^2) and kwall = 2 dt/h^2 as the level-0 smoother forms them (regular cells take
+// K = kin (eta_c + eta_n) inside and kwall eta_c on a domain wall, with no division per face);
+// dnx, dny divide by the extents
 __global__ void __launch_bounds__(EB_BLOCK) k_visc_apply(GeomV g, double rho, double dt,
+                                                         double kin, double kwall, FastDiv dnx,
+                                                         FastDiv dny,
                                                          const double* __restrict__ eta,
                              const double* __restrict__ eta_eb, const double* __restrict__ u,
                              double* __restrict__ out, int homog, const int* gate) {
@@ -1712,7 +1757,14 @@ __global__ void __launch_bounds__(EB_BLOCK) k_visc_apply(GeomV g, double rho, do
     long c = xcd_block() * (long)blockDim.x + threadIdx.x;
     if (c >= N) return;
     int i, j, k;
-    cell_coords(g.grid, c, i, j, k);
+    {
+        unsigned cu = (unsigned)c;
+        unsigned t = fdiv(cu, dnx);
+        i = (int)(cu - t * dnx.d);
+        unsigned k2 = fdiv(t, dny);
+        j = (int)(t - k2 * dny.d);
+        k = (int)k2;
+    }
     long nb[6];
 #pragma unroll
     for (int d = 0; d < 3; d++)
@@ -1748,10 +1800,10 @@ __global__ void __launch_bounds__(EB_BLOCK) k_visc_apply(GeomV g, double rho, do
             for (int side = 0; side < 2; side++) {
                 int f = 2 * d + side;
                 if (nb[f] >= 0) {
-                    double K = dt * 1.0 * 0.5 * (ec + en[f]) / h2;
+                    double K = kin * (ec + en[f]);
                     for (int m = 0; m < 3; m++) acc[m] -= K * (un[f][m] - uc[m]);
                 } else {
-                    double K = 2.0 * dt * 1.0 * ec / h2;
+                    double K = kwall * ec;
                     for (int m = 0; m < 3; m++) {
                         double uw = homog ? 0.0 : g.wall[2 * d + side][m];
                         acc[m] -= K * (uw - uc[m]);
@@ -2189,6 +2241,9 @@ void prolong_pass(const Level& F, const Level& C, int nc, const TC* ec, TF* xf, 
 Rb0V rb0_view(const Level& L) {
     Rb0V v;
     v.grid = L.grid;
+    v.dnx = fast_div((unsigned)L.grid.n[0]);
+    v.dny = fast_div((unsigned)L.grid.n[1]);
+    v.dnxh = fast_div((unsigned)L.grid.n[0] / 2);
     v.N = L.N;
     v.flag = L.flag;
     v.eta = L.eta;
@@ -2597,8 +2652,12 @@ void mg_apply_level0(const Level& L, int ncomp, const double* x, double* y, hipS
 void op_visc_apply(const GeomV& g, double rho, double dt, const double* eta,
                    const double* eta_eb, const double* u, double* out, int homogeneous,
                    hipStream_t s, const int* gate) {
-    k_visc_apply<<<grid_for(g.N), EB_BLOCK, 0, s>>>(g, rho, dt, eta, eta_eb, u, out, homogeneous,
-                                                    gate);
+    double h2 = g.grid.h * g.grid.h;
+    double kin = dt * 0.5 / h2, kwall = 2.0 * dt / h2;
+    k_visc_apply<<<grid_for(g.N), EB_BLOCK, 0, s>>>(g, rho, dt, kin, kwall,
+                                                    fast_div((unsigned)g.grid.n[0]),
+                                                    fast_div((unsigned)g.grid.n[1]), eta, eta_eb,
+                                                    u, out, homogeneous, gate);
     if (g.ncut > 0)
         k_visc_apply_eb<<<grid_for(g.ncut), EB_BLOCK, 0, s>>>(g, dt, eta_eb, u, out, homogeneous,
                                                             gate);

@@ -4,8 +4,9 @@ eps = 1e-4 and tau0 = 100, rho = 1, dt = 2.5e-4, mixed precision.
 
 A full oracle step at this size takes minutes, so the checks are the ones the oracle can make
 cell by cell (geometry, and the viscosity recomputed from the GPU velocity), the mixed step
-against the FP64 step (itself checked against the oracle at smaller sizes), and the Bingham-
-number gradient of the drag against central finite differences.
+against the FP64 step (itself checked against the oracle at smaller sizes) over 3 and over the
+specified 50 steps, and the Bingham-number gradient of the drag against central finite
+differences after 2 and 20 steps (after 50 it is ill-conditioned: see the skipped test).
 """
 import numpy as np
 import pytest
@@ -155,4 +156,117 @@ def test_ellipsoid256_bi_gradient_fd(large):
     fd = (loss(w.tau0 + hstep) - loss(w.tau0 - hstep)) / (2 * hstep)
     rel = abs(fd - g) / abs(g)
     print(f"[large] dFz/dBi adjoint {g:.10e} fd {fd:.10e} rel {rel:.3e}", flush=True)
+    assert rel <= 1e-5
+
+
+def test_ellipsoid256_fifty_steps_mixed_matches_fp64(large):
+    """The large run as specified: 50 RK2 steps (dt = 2.5e-4) in mixed precision from the
+    wall-velocity start, against the same 50 steps in FP64: the drag at every step and the
+    fields at the end to 1e-8 relative, the velocity as one vector field (the solver tolerances
+    bound the residual's max over all three components, so a component much smaller than the
+    others carries a larger relative error of its own: reported, each held through the field's
+    norm)."""
+    import copy
+    import time
+
+    from paper_1905_07392_amd import api
+
+    w, ctx, rheo, opts = large
+    nsteps = 50
+    u0 = torch.from_numpy(I.initial_velocity(w)).to("cuda:0")
+    p0 = ctx.scalar()
+    _, alpha, _, _, _ = api.eb_geometry_export(ctx)
+    op = cpu(alpha) > 0
+    runs = {}
+    for key, prec in (("fp64", api.EB_FP64), ("mixed", api.EB_MIXED)):
+        o = copy.copy(opts)
+        o.precision = prec
+        u, p = u0.clone(), p0.clone()
+        fz = []
+        t0 = time.time()
+        for s in range(nsteps):
+            u, p, st = api.eb_rk2_step(ctx, rheo, w.dt, o, u, p)
+            fz.append(api.eb_drag(ctx, rheo, u, p)[2])
+            if s % 10 == 9:
+                print(f"[large] {key} step {s + 1}: F_z {fz[-1]:.12e} {st}", flush=True)
+        torch.cuda.synchronize()
+        runs[key] = (cpu(u), cpu(p), np.array(fz), time.time() - t0, st)
+    u64, p64, f64, t64, st64 = runs["fp64"]
+    u32, p32, f32, t32, st32 = runs["mixed"]
+    drag_err = np.abs(f32 - f64) / np.abs(f64)
+    vnorm = np.linalg.norm(u64[:, op])
+    errs = {"velocity": np.linalg.norm((u32 - u64)[:, op]) / vnorm,
+            "p": rel_l2(p32, p64, op)}
+    comp = {c: (np.linalg.norm((u32[j] - u64[j])[op]) / vnorm, rel_l2(u32[j], u64[j], op),
+                np.linalg.norm(u64[j][op]) / vnorm) for j, c in enumerate("uvw")}
+    print(f"[large] 256^3 {nsteps} steps: FP64 {t64:.1f} s, mixed {t32:.1f} s; worst drag "
+          f"error {drag_err.max():.3e} (step {int(drag_err.argmax()) + 1}); fields {errs}; per "
+          f"component (error / |velocity|, error / |component|, |component| / |velocity|) {comp}"
+          f"; F_z(50) {f64[-1]:.12e}", flush=True)
+    assert drag_err.max() <= 1e-8, drag_err
+    assert max(errs.values()) <= 1e-8, errs
+    assert max(c[0] for c in comp.values()) <= 1e-8, comp
+
+
+def _bi_gradient(large, nsteps, ckpt_every=5):
+    """dF_z/dBi after nsteps through the checkpointed autograd rollout of the mixed run, and
+    central finite differences of the same steps (relative step 1e-6, solves one decade
+    tighter)."""
+    import copy
+    import time
+
+    from paper_1905_07392_amd import api
+    from paper_1905_07392_amd import autograd as AG
+
+    w, ctx, rheo, opts = large
+    u0 = torch.from_numpy(I.initial_velocity(w)).to("cuda:0")
+    p0 = ctx.scalar()
+    o = copy.copy(opts)
+    ofd = copy.copy(opts)
+    ofd.rtol_visc = ofd.rtol_mac = ofd.rtol_proj = 0.1 * opts.rtol_visc
+    theta = torch.ones(ctx.shape, dtype=torch.float64, device="cuda:0")
+    bi = torch.tensor(float(w.tau0), dtype=torch.float64, device="cuda:0", requires_grad=True)
+    t0 = time.time()
+    u, p = AG.rollout(ctx, rheo, w.dt, o, u0, p0, theta, bi, nsteps, ckpt_every=ckpt_every)
+    fz = AG.drag(ctx, rheo, u, p, theta, bi)[2]
+    fz.backward()
+    g = bi.grad.item()
+    t_adj = time.time() - t0
+
+    def loss(tau0):
+        r = api.make_rheology(w.law, w.mu, tau0, w.eps, w.rho)
+        uu, pp = u0.clone(), p0.clone()
+        for _ in range(nsteps):
+            uu, pp, _ = api.eb_rk2_step(ctx, r, w.dt, ofd, uu, pp, allow_noconv=True)
+        return api.eb_drag(ctx, r, uu, pp)[2]
+
+    hstep = 1e-6 * w.tau0
+    fd = (loss(w.tau0 + hstep) - loss(w.tau0 - hstep)) / (2 * hstep)
+    rel = abs(fd - g) / abs(g)
+    print(f"[large] {nsteps} steps dFz/dBi adjoint {g:.10e} ({t_adj:.1f} s with the forward) "
+          f"fd {fd:.10e} rel {rel:.3e}", flush=True)
+    return g, fd, rel
+
+
+def test_ellipsoid256_bi_gradient_twenty_steps(large):
+    """dF_z/dBi after 20 steps of the large run (mixed forward, checkpoints every 5 steps)
+    against central finite differences, to 1e-5 (measured: the same seven digits, -0.4871630)."""
+    _, _, rel = _bi_gradient(large, 20)
+    assert rel <= 1e-5
+
+
+@pytest.mark.skip(reason=(
+    "the 50-step derivative of this configuration is ill-conditioned: the adjoint equals central "
+    "differences to seven digits after 2, 5, 10 and 20 steps (-0.2992138, -0.4916400, -0.4972684, "
+    "-0.4871630), but after about 30 steps a perturbation of Bi grows by about 1.37x per step "
+    "(max |du|/dBi is 3.6e-3 at step 20 and 46 at step 50 with a relative step of 1e-6): at step "
+    "50 differences with relative steps 1e-6 and 1e-4 give -1.49 and -0.51 and the exact "
+    "derivative of the discrete map (the adjoint) +414 in mixed precision, +377 in FP64 with a "
+    "checkpoint at every step.  The growth is the discrete step's own (mixed and FP64 adjoints and "
+    "FP64 differences show it alike) at a dt 2e4 times the step's stability rule (eb_stable_dt "
+    "1.26e-8), where the explicitly treated part of the viscous term, with coefficients up to "
+    "eta = 1 + Bi m = 1e6 in the plug, is presumably what stops damping perturbations; the "
+    "20-step check is test_ellipsoid256_bi_gradient_twenty_steps"))
+def test_ellipsoid256_bi_gradient_fifty_steps(large):
+    _, _, rel = _bi_gradient(large, 50)
     assert rel <= 1e-5
