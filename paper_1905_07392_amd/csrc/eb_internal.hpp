@@ -96,6 +96,19 @@ __host__ __device__ inline long cell_at(const GridV& g, int i, int j, int k) {
     }
     return cell_index(g, q[0], q[1], q[2]);
 }
+// natural index of the neighbour across face 2d + side of cell c = (i, j, k): cell_at of the
+// neighbour's coordinates (-1 across a wall, wrapped in a periodic direction), with only the
+// coordinate that moved tested and the index stepped from c by that direction's stride
+__host__ __device__ inline long cell_step(const GridV& g, long c, int i, int j, int k, int d,
+                                          int side) {
+    int q = d == 0 ? i : (d == 1 ? j : k);
+    long st = d == 0 ? 1L : (d == 1 ? (long)g.n[0] : (long)g.n[0] * g.n[1]);
+    int e = q + (side ? 1 : -1);
+    long in = side ? c + st : c - st;
+    long wr = side ? in - (long)g.n[d] * st : in + (long)g.n[d] * st;
+    bool inside = e >= 0 && e < g.n[d];
+    return inside ? in : (g.per[d] ? wr : -1L);
+}
 // 32-bit unsigned division: boxes hold fewer than 2^32 cells, and 64-bit division is many
 // times slower on the GPU
 __host__ __device__ inline void cell_coords(const GridV& g, long c, int& i, int& j, int& k) {

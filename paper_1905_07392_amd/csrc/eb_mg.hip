@@ -170,6 +170,7 @@ __device__ __forceinline__ void offdiag(const LevelV<T>& L, const T* __restrict_
                                         int k, T acc[NC]) {
     const GridV& g = L.grid;
     long N = L.N;
+    long c = cell_index(g, i, j, k);
 #pragma unroll
     for (int d = 0; d < 3; d++) {
 #pragma unroll
@@ -178,9 +179,7 @@ __device__ __forceinline__ void offdiag(const LevelV<T>& L, const T* __restrict_
             f[d] += side;
             T K = L.K[d][face_index(g, d, f[0], f[1], f[2])];
             if (K == (T)0) continue;
-            int q[3] = {i, j, k};
-            q[d] += side ? 1 : -1;
-            long nb = cell_at(g, q[0], q[1], q[2]);
+            long nb = cell_step(g, c, i, j, k, d, side);
             if (nb < 0) continue;
 #pragma unroll
             for (int m = 0; m < NC; m++) acc[m] += K * x[m * N + nb];
@@ -287,9 +286,7 @@ __device__ __forceinline__ void smooth_cell(const LevelV<T>& L, const T* __restr
             int f[3] = {i, j, k};
             f[d] += side;
             K[2 * d + side] = L.K[d][face_index(g, d, f[0], f[1], f[2])];
-            int q[3] = {i, j, k};
-            q[d] += side ? 1 : -1;
-            nb[2 * d + side] = cell_at(g, q[0], q[1], q[2]);
+            nb[2 * d + side] = cell_step(g, c, i, j, k, d, side);
         }
     uint8_t msk = L.mask[c];
     T dg = L.D[c];
@@ -443,9 +440,7 @@ __global__ void __launch_bounds__(RR_THREADS)
                 int e[3] = {fi, fj, fk};
                 e[d] += side;
                 K[2 * d + side] = L.K[d][face_index(g, d, e[0], e[1], e[2])];
-                int q[3] = {fi, fj, fk};
-                q[d] += side ? 1 : -1;
-                nb[2 * d + side] = cell_at(g, q[0], q[1], q[2]);
+                nb[2 * d + side] = cell_step(g, f, fi, fj, fk, d, side);
             }
         uint8_t msk = L.mask[f];
         TF dg = L.D[f];
@@ -589,9 +584,7 @@ __device__ __forceinline__ bool rb0_row(const Rb0V& L, long c, int i, int j, int
         for (int d = 0; d < 3; d++)
 #pragma unroll
             for (int side = 0; side < 2; side++) {
-                int q[3] = {i, j, k};
-                q[d] += side ? 1 : -1;
-                long n = cell_at(g, q[0], q[1], q[2]);
+                long n = cell_step(g, c, i, j, k, d, side);
                 T kf;
                 if (L.sys == EB_SYS_VISC) kf = n >= 0 ? kin * (ec + eta[n]) : kwall * ec;
                 else kf = n >= 0 ? kp : (T)0;
@@ -609,9 +602,7 @@ __device__ __forceinline__ bool rb0_row(const Rb0V& L, long c, int i, int j, int
             int f[3] = {i, j, k};
             f[d] += side;
             K[2 * d + side] = (T)L.K[d][face_index(g, d, f[0], f[1], f[2])];
-            int q[3] = {i, j, k};
-            q[d] += side ? 1 : -1;
-            nb[2 * d + side] = cell_at(g, q[0], q[1], q[2]);
+            nb[2 * d + side] = cell_step(g, c, i, j, k, d, side);
         }
     D = (T)L.D[c];
     return D > (T)0;
@@ -665,9 +656,7 @@ __device__ __forceinline__ bool rb0_row_ld(const Rb0V& L, long c, int i, int j, 
     for (int d = 0; d < 3; d++)
 #pragma unroll
         for (int side = 0; side < 2; side++) {
-            int q[3] = {i, j, k};
-            q[d] += side ? 1 : -1;
-            nb[2 * d + side] = cell_at(g, q[0], q[1], q[2]);
+            nb[2 * d + side] = cell_step(g, c, i, j, k, d, side);
         }
     uint8_t fl = L.flag[c];
     if (NBR)
@@ -726,9 +715,7 @@ __device__ __forceinline__ void smooth_rb_cell(const Rb0V& L, const T* __restric
         for (int d = 0; d < 3; d++)
 #pragma unroll
             for (int side = 0; side < 2; side++) {
-                int q[3] = {i, j, k};
-                q[d] += side ? 1 : -1;
-                nb[2 * d + side] = cell_at(L.grid, q[0], q[1], q[2]);
+                nb[2 * d + side] = cell_step(L.grid, c, i, j, k, d, side);
             }
         nbr_load<NC, TC>(L.grid, *P, i, j, k, nb, E);
     }
@@ -780,9 +767,7 @@ __global__ void __launch_bounds__(EB_BLOCK)
     for (int d = 0; d < 3; d++)
 #pragma unroll
         for (int side = 0; side < 2; side++) {
-            int q[3] = {i, j, k};
-            q[d] += side ? 1 : -1;
-            nb[2 * d + side] = cell_at(L.grid, q[0], q[1], q[2]);
+            nb[2 * d + side] = cell_step(L.grid, c, i, j, k, d, side);
         }
     double xv[NC], xn[6][NC];
 #pragma unroll
@@ -1426,9 +1411,7 @@ __device__ __forceinline__ void block_row(const LevelV<double>& L, long c, Block
                 int f[3] = {i, j, k};
                 f[d] += side;
                 K = L.K[d][face_index(L.grid, d, f[0], f[1], f[2])];
-                int q[3] = {i, j, k};
-                q[d] += side ? 1 : -1;
-                nb = cell_at(L.grid, q[0], q[1], q[2]);
+                nb = cell_step(L.grid, c, i, j, k, d, side);
             }
             bool use = K != 0.0 && nb >= 0;
             r.K[2 * d + side] = use ? K : 0.0;
@@ -1770,9 +1753,7 @@ __global__ void __launch_bounds__(EB_BLOCK) k_visc_apply(GeomV g, double rho, do
     for (int d = 0; d < 3; d++)
 #pragma unroll
         for (int side = 0; side < 2; side++) {
-            int q[3] = {i, j, k};
-            q[d] += side ? 1 : -1;
-            nb[2 * d + side] = cell_at(g.grid, q[0], q[1], q[2]);
+            nb[2 * d + side] = cell_step(g.grid, c, i, j, k, d, side);
         }
     uint8_t fl = g.flag[c];
     double uc[3], un[6][3], en[6];
