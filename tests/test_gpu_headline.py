@@ -11,6 +11,8 @@
   steps), so eta is compared with the oracle's law evaluated at the GPU's own velocity (1e-12:
   the viscosity computation itself), and its difference from the oracle's trajectory is
   reported on yielded cells (|gamma| > 10 eps), plug cells and all cells.
+* The 100-step drag history of the same workload in FP64 and in mixed precision against the
+  oracle's stored run (tests/golden/sphere128_history_oracle.txt).
 * A 64^3 sphere (the parity physics of the 32^3 workload) in mixed precision, whose finest
   (64^3) multigrid level really runs in FP32: one step against the oracle at 1e-8.
 """
@@ -150,3 +152,71 @@ def test_sphere64_mixed_fp32_levels_match_oracle():
           flush=True)
     assert st["fp64_fallbacks"] == 0
     assert max(errs) <= 1e-8, errs
+
+
+def _oracle_history():
+    """tests/golden/sphere128_history_oracle.txt (written by make_sphere128_history.py from the
+    oracle alone): per step (F, norms of u, v, w, p, iterations) and the sampled cell values."""
+    import os
+
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "sphere128_history_oracle.txt")
+    rows, samples = [], {}
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        t = line.split()
+        if t[0] == "S":
+            samples.setdefault(int(t[1]), []).append((int(t[2]), [float(x) for x in t[3:7]]))
+        else:
+            rows.append([float(x) for x in t])
+    return np.array(rows), samples
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_sphere128_drag_history_100_steps(precision):
+    """The 100 RK2 steps of the 128^3 translating sphere against the oracle's stored run: per
+    step the drag F_z and the L2 norms of u, v, w, p over open cells, and at steps 1, 2, 10, 50
+    and 100 the values of u, v, w, p at 64 seeded open cells (half of them within 3h of the
+    body).  Bars, relative: 1e-10 in FP64 and 1e-8 in mixed precision for F_z and the norms;
+    the sampled values against the largest value of their field at that step, the same bars."""
+    import paper_1905_07392_amd as pkg
+    from paper_1905_07392_amd import api
+
+    _require_gpu()
+    rows, samples = _oracle_history()
+    w = I.sphere128()
+    prec = api.EB_MIXED if precision == "mixed" else api.EB_FP64
+    tol = 1e-8 if precision == "mixed" else 1e-10
+    box, body, rheo, opts = pkg.from_workload(w, precision=prec)
+    ctx = api.eb_geometry_build(box, body, "cuda:0")
+    _, alpha, _, _, _ = api.eb_geometry_export(ctx)
+    op = cpu(alpha) > 0
+    opt = torch.from_numpy(op).to("cuda:0")
+    u = torch.from_numpy(I.initial_velocity(w)).to("cuda:0")
+    p = ctx.scalar()
+    worst = {"F_z": (0.0, 0), "norms": (0.0, 0), "samples": (0.0, 0)}
+    for s in range(1, len(rows) + 1):
+        u, p, st = api.eb_rk2_step(ctx, rheo, w.dt, opts, u, p)
+        F = api.eb_drag(ctx, rheo, u, p)
+        ref = rows[s - 1]
+        assert int(ref[0]) == s
+        ef = abs(F[2] - ref[3]) / abs(ref[3])
+        norms = [torch.linalg.vector_norm(u[j][opt]).item() for j in range(3)]
+        norms.append(torch.linalg.vector_norm(p[opt]).item())
+        en = max(abs(a - b) / abs(b) for a, b in zip(norms, ref[4:8]))
+        worst["F_z"] = max(worst["F_z"], (ef, s))
+        worst["norms"] = max(worst["norms"], (en, s))
+        if s in samples:
+            cells = np.array([c for c, _ in samples[s]])
+            refv = np.array([v for _, v in samples[s]])  # [64][u v w p]
+            un, pn = cpu(u), cpu(p)
+            got = np.stack([un[j].ravel()[cells] for j in range(3)] + [pn.ravel()[cells]], 1)
+            scale = np.array([np.abs(un[j][op]).max() for j in range(3)] + [np.abs(pn[op]).max()])
+            es = float((np.abs(got - refv) / scale).max())
+            worst["samples"] = max(worst["samples"], (es, s))
+            print(f"[history] {precision} step {s}: F_z {F[2]:.15e} (oracle {ref[3]:.15e}, rel "
+                  f"{ef:.2e}), norms {en:.2e}, samples {es:.2e}; {st}", flush=True)
+    print(f"[history] {precision} worst relative errors (value, step): {worst}", flush=True)
+    for key, (e, s) in worst.items():
+        assert e <= tol, (key, e, s)
