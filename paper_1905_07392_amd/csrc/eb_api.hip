@@ -922,21 +922,38 @@ int bicgstab(eb_ctx* c, double rho, double dt, const double* eta, const double* 
     key.p[2] = eta_eb;
     key.v[0] = rho;
     key.v[1] = dt;
+    // With an FP32 finest level the preconditioner's results are FP32 values, so ph and sh are
+    // kept in FP32 storage (the first half of their FP64 buffers) and widened where they are
+    // read (the operator, the x update): the same numbers, half the bytes.
+    bool f32 = k.mixed && !transposed &&
+               mg_vcycle_f32_out(c->lev, c->nlev, 3, true, k.nu1, k.nu2);
+    float* phf = reinterpret_cast<float*>(ph);
+    float* shf = reinterpret_cast<float*>(sh);
+    auto precond = [&](const double* in, double* out, float* out32) {
+        if (f32)
+            mg_vcycle(c->lev, c->nlev, 3, true, in, out32, k.nu1, k.nu2, k.nbottom, c->s, st);
+        else
+            vcyc(c, 3, k, in, out, st);
+    };
     auto body = [&]() {
         ks_bi_p(N3, p, r, v, ks, st, c->s);
-        vcyc(c, 3, k, p, ph, st);
-        apply(ph, v, st);
+        precond(p, ph, phf);
+        if (f32) op_visc_apply(c->g, rho, dt, eta, eta_eb, phf, v, 1, c->s, st);
+        else apply(ph, v, st);
         const double* Av[4] = {rh, nullptr, nullptr, nullptr};
         const double* Bv[4] = {v, nullptr, nullptr, nullptr};
         red_dots_op(N3, 1, Av, Bv, c->part, KS_RV, KS_BI_ALPHA, ks, st, itc, c->s);
         ks_bi_s_op(N3, sv, r, v, c->part, ks, st, itc, c->s);
-        ks_bi_xs(N3, x, ph, ks, st, c->s);
-        vcyc(c, 3, k, sv, sh, st);
-        apply(sh, t, st);
+        if (f32) ks_bi_xs(N3, x, phf, ks, st, c->s);
+        else ks_bi_xs(N3, x, ph, ks, st, c->s);
+        precond(sv, sh, shf);
+        if (f32) op_visc_apply(c->g, rho, dt, eta, eta_eb, shf, t, 1, c->s, st);
+        else apply(sh, t, st);
         const double* A2[4] = {t, t, nullptr, nullptr};
         const double* B2[4] = {sv, t, nullptr, nullptr};
         red_dots_op(N3, 2, A2, B2, c->part, KS_TS, KS_BI_OMEGA, ks, st, itc, c->s);
-        ks_bi_xr_op(N3, x, r, ph, sh, sv, t, rh, c->part, ks, st, itc, c->s);
+        if (f32) ks_bi_xr_op(N3, x, r, phf, shf, sv, t, rh, c->part, ks, st, itc, c->s);
+        else ks_bi_xr_op(N3, x, r, ph, sh, sv, t, rh, c->part, ks, st, itc, c->s);
     };
     return iterate(c, key, slot, k.max_iter, body, k.mixed);
 }

@@ -422,6 +422,8 @@ void ks_bi_p(long n, double* p, const double* r, const double* v, const double* 
              const int* st, hipStream_t s);
 void ks_bi_xs(long n, double* x, const double* ph, const double* ks, const int* st,
               hipStream_t s);
+void ks_bi_xs(long n, double* x, const float* ph, const double* ks, const int* st,
+              hipStream_t s);
 
 // multigrid and Krylov
 void mg_build_poisson(Level* lev, int nlev, const GeomV& g, double beta, bool mixed,
@@ -430,6 +432,11 @@ void mg_build_visc(Level* lev, int nlev, const GeomV& g, double rho, double dt,
                    const double* eta, const double* eta_eb, bool mixed, hipStream_t s);
 void mg_vcycle(Level* lev, int nlev, int ncomp, bool mixed, const double* b, double* x,
                int nu1, int nu2, int nbottom, hipStream_t s, const int* gate = nullptr);
+// whether a V-cycle can hand its result over in FP32 without rounding (its finest level runs in
+// FP32 in colour-split storage), and that V-cycle with an FP32 result
+bool mg_vcycle_f32_out(Level* lev, int nlev, int ncomp, bool mixed, int nu1, int nu2);
+void mg_vcycle(Level* lev, int nlev, int ncomp, bool mixed, const double* b, float* x, int nu1,
+               int nu2, int nbottom, hipStream_t s, const int* gate = nullptr);
 void mg_apply_level0(const Level& L, int ncomp, const double* x, double* y, hipStream_t s,
                      const int* gate = nullptr);
 // whether a mixed-precision hierarchy runs its finest level in FP32 (levels of at least 64^3
@@ -439,6 +446,9 @@ void mg_sweep_level0(const Level& L, int ncomp, bool f32, const void* b, void* x
                      hipStream_t s);
 void op_visc_apply(const GeomV& g, double rho, double dt, const double* eta,
                    const double* eta_eb, const double* u, double* out, int homogeneous,
+                   hipStream_t s, const int* gate = nullptr);
+void op_visc_apply(const GeomV& g, double rho, double dt, const double* eta,
+                   const double* eta_eb, const float* u, double* out, int homogeneous,
                    hipStream_t s, const int* gate = nullptr);
 
 // Krylov steps fused with their reductions and the scalar update that follows (results bit for
@@ -452,6 +462,9 @@ void red_dots_op(long n, int np, const double* const a[4], const double* const b
 void ks_bi_s_op(long n, double* sv, const double* r, const double* v, double* part, double* ks,
                 int* st, int* itc, hipStream_t s);
 void ks_bi_xr_op(long n, double* x, double* r, const double* ph, const double* sh,
+                 const double* sv, const double* t, const double* rh, double* part, double* ks,
+                 int* st, int* itc, hipStream_t s);
+void ks_bi_xr_op(long n, double* x, double* r, const float* ph, const float* sh,
                  const double* sv, const double* t, const double* rh, double* part, double* ks,
                  int* st, int* itc, hipStream_t s);
 void ks_cg_xr_op(long n, double* x, double* r, const double* p, const double* q, double* part,

@@ -36,13 +36,14 @@ __global__ void k_bi_p(long n, double* __restrict__ p, const double* __restrict_
 }
 // converged at the half step: x += alpha ph (grid-stride over a small grid: almost every launch
 // returns at once, and a small grid returns sooner)
-__global__ void k_bi_xs(long n, double* __restrict__ x, const double* __restrict__ ph,
+template <typename TP>
+__global__ void k_bi_xs(long n, double* __restrict__ x, const TP* __restrict__ ph,
                         const double* __restrict__ ks, const int* __restrict__ st) {
     if (*st != 1) return;
     double al = ks[KS_AL];
     for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n;
          t += (long)gridDim.x * blockDim.x)
-        x[t] += al * ph[t];
+        x[t] += al * (double)ph[t];
 }
 
 __global__ void k_set(double* __restrict__ ks, int idx, double v) {
@@ -64,5 +65,9 @@ void ks_bi_p(long n, double* p, const double* r, const double* v, const double* 
 }
 void ks_bi_xs(long n, double* x, const double* ph, const double* ks, const int* st,
               hipStream_t s) {
-    k_bi_xs<<<red_blocks(n), EB_BLOCK, 0, s>>>(n, x, ph, ks, st);
+    k_bi_xs<double><<<red_blocks(n), EB_BLOCK, 0, s>>>(n, x, ph, ks, st);
+}
+void ks_bi_xs(long n, double* x, const float* ph, const double* ks, const int* st,
+              hipStream_t s) {
+    k_bi_xs<float><<<red_blocks(n), EB_BLOCK, 0, s>>>(n, x, ph, ks, st);
 }

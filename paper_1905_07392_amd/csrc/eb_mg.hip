@@ -848,11 +848,11 @@ __global__ void k_smooth_first_rb_from(Rb0V L, const double* __restrict__ bnat,
 }
 
 // the last half sweep (colour 0) fused with the conversion of the iterate back to natural
-// order (FP64): a thread updates its colour-0 cell and also copies the colour-1 cell next to it
+// order (FP64, or FP32 from an FP32 level, which loses nothing): a thread updates its colour-0 cell and also copies the colour-1 cell next to it
 // in x, so every cell of the natural output is written once
-template <typename T, int NC, int PRO = PRO_NONE, typename TC = T>
+template <typename T, int NC, int PRO = PRO_NONE, typename TC = T, typename TD = double>
 __global__ void k_smooth_last_rb_to(Rb0V L, const T* __restrict__ b, const T* __restrict__ x,
-                                    double* __restrict__ xnat, ProV<TC> P) {
+                                    TD* __restrict__ xnat, ProV<TC> P) {
     if (L.gate && *L.gate) return;
     long N = L.N, Nh = N >> 1;
     long t = xcd_block() * (long)blockDim.x + threadIdx.x;
@@ -892,8 +892,8 @@ __global__ void k_smooth_last_rb_to(Rb0V L, const T* __restrict__ b, const T* __
     }
 #pragma unroll
     for (int m = 0; m < NC; m++) {
-        xnat[m * N + c] = (double)val[m];
-        xnat[m * N + c1] = (double)x1[m];
+        xnat[m * N + c] = (TD)val[m];
+        xnat[m * N + c1] = (TD)x1[m];
     }
 }
 
@@ -1729,11 +1729,13 @@ __global__ void k_tail_pack(PackArgs P) {
 // kin = dt/(2 h^2) and kwall = 2 dt/h^2 as the level-0 smoother forms them (regular cells take
 // K = kin (eta_c + eta_n) inside and kwall eta_c on a domain wall, with no division per face);
 // dnx, dny divide by the extents
+// (TU: the input's type; FP32 input is widened exactly)
+template <typename TU>
 __global__ void __launch_bounds__(EB_BLOCK) k_visc_apply(GeomV g, double rho, double dt,
                                                          double kin, double kwall, FastDiv dnx,
                                                          FastDiv dny,
                                                          const double* __restrict__ eta,
-                             const double* __restrict__ eta_eb, const double* __restrict__ u,
+                             const double* __restrict__ eta_eb, const TU* __restrict__ u,
                              double* __restrict__ out, int homog, const int* gate) {
     if (gate && *gate) return;
     long N = g.N;
@@ -1758,12 +1760,12 @@ __global__ void __launch_bounds__(EB_BLOCK) k_visc_apply(GeomV g, double rho, do
     uint8_t fl = g.flag[c];
     double uc[3], un[6][3], en[6];
 #pragma unroll
-    for (int m = 0; m < 3; m++) uc[m] = u[m * N + c];
+    for (int m = 0; m < 3; m++) uc[m] = (double)u[m * N + c];
 #pragma unroll
     for (int f = 0; f < 6; f++) {
         en[f] = nb[f] >= 0 ? eta[nb[f]] : 0.0;
 #pragma unroll
-        for (int m = 0; m < 3; m++) un[f][m] = nb[f] >= 0 ? u[m * N + nb[f]] : 0.0;
+        for (int m = 0; m < 3; m++) un[f][m] = nb[f] >= 0 ? (double)u[m * N + nb[f]] : 0.0;
     }
     double ec = eta[c];
     if (fl == 0) {
@@ -1821,9 +1823,10 @@ __global__ void __launch_bounds__(EB_BLOCK) k_visc_apply(GeomV g, double rho, do
 
 // the wall-flux term of the cut-cell rows, added after k_visc_apply (one thread per cut cell,
 // each writing only its own row): dt A_EB eta_EB (du/dn of Eq. dudn) / h
+template <typename TU>
 __global__ void __launch_bounds__(EB_BLOCK) k_visc_apply_eb(GeomV g, double dt,
                                                             const double* __restrict__ eta_eb,
-                                                            const double* __restrict__ u,
+                                                            const TU* __restrict__ u,
                                                             double* __restrict__ out, int homog,
                                                             const int* gate) {
     if (gate && *gate) return;
@@ -1850,7 +1853,7 @@ __global__ void __launch_bounds__(EB_BLOCK) k_visc_apply_eb(GeomV g, double dt,
     for (int m = 0; m < 3; m++) {
         double ue = homog ? 0.0 : g.ueb[m];
 #pragma unroll
-        for (int t = 0; t < 18; t++) uv[m][t] = ci[t] >= 0 ? u[m * N + ci[t]] : ue;
+        for (int t = 0; t < 18; t++) uv[m][t] = ci[t] >= 0 ? (double)u[m * N + ci[t]] : ue;
         o[m] = out[m * N + c];
     }
     double den = d1 * d2 * (d2 - d1) * g.grid.h;
@@ -1974,8 +1977,9 @@ __global__ void k_bi_s_max(long n, double* __restrict__ sv, const double* __rest
 
 // BiCGSTAB: x += alpha ph + omega sh, r = s - omega t, with the per-block partials of rh . r
 // (row 0) and max |r| (row 1)
+template <typename TP>
 __global__ void k_bi_xr_red(long n, double* __restrict__ x, double* __restrict__ r,
-                            const double* __restrict__ ph, const double* __restrict__ sh_,
+                            const TP* __restrict__ ph, const TP* __restrict__ sh_,
                             const double* __restrict__ sv, const double* __restrict__ tv,
                             const double* __restrict__ rh, const double* __restrict__ ks,
                             const int* __restrict__ st, double* __restrict__ part) {
@@ -1985,7 +1989,7 @@ __global__ void k_bi_xr_red(long n, double* __restrict__ x, double* __restrict__
     double dot = 0.0, m = 0.0;
     for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n;
          t += (long)gridDim.x * blockDim.x) {
-        x[t] += al * ph[t] + om * sh_[t];
+        x[t] += al * (double)ph[t] + om * (double)sh_[t];
         double rn = sv[t] - om * tv[t];
         r[t] = rn;
         dot += rh[t] * rn;
@@ -2399,9 +2403,9 @@ void resid_restrict_rb(const VArgs& a, const Rb0V& v, const Level& C, const T* b
 // level 0's prolongation and post-smoothing: the prolongation of ec rides on the first pair of
 // half sweeps (a pass of its own only without post-smoothing); the last half sweep writes the
 // natural-order FP64 result x0
-template <typename T, typename TC>
+template <typename T, typename TC, typename TD>
 void up_leg_rb(const VArgs& a, const Rb0V& v, const GridV& gc, const TC* ec, const T* b, T* x,
-               double* x0) {
+               TD* x0) {
     int nc = a.nc;
     long N = v.N;
     unsigned gh = grid_for(N / 2);
@@ -2422,11 +2426,11 @@ void up_leg_rb(const VArgs& a, const Rb0V& v, const GridV& gc, const TC* ec, con
             else k_smooth_rb<T, 1><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, 1);
         }
         if (last && first) {
-            if (nc == 3) k_smooth_last_rb_to<T, 3, PRO_OWN, TC><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, x0, P);
-            else k_smooth_last_rb_to<T, 1, PRO_OWN, TC><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, x0, P);
+            if (nc == 3) k_smooth_last_rb_to<T, 3, PRO_OWN, TC, TD><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, x0, P);
+            else k_smooth_last_rb_to<T, 1, PRO_OWN, TC, TD><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, x0, P);
         } else if (last) {
-            if (nc == 3) k_smooth_last_rb_to<T, 3, PRO_NONE, TC><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, x0, none);
-            else k_smooth_last_rb_to<T, 1, PRO_NONE, TC><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, x0, none);
+            if (nc == 3) k_smooth_last_rb_to<T, 3, PRO_NONE, TC, TD><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, x0, none);
+            else k_smooth_last_rb_to<T, 1, PRO_NONE, TC, TD><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, x0, none);
         } else if (first) {
             if (nc == 3) k_smooth_rb_pro<T, TC, 3, PRO_OWN><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, 0, P);
             else k_smooth_rb_pro<T, TC, 1, PRO_OWN><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, 0, P);
@@ -2441,8 +2445,8 @@ void up_leg_rb(const VArgs& a, const Rb0V& v, const GridV& gc, const TC* ec, con
 // b and x are the level's own colour-split arrays
 // b0, x0: the caller's natural-order FP64 right-hand side and output; b, x: the level's
 // colour-split arrays (precision T).  The conversions ride on the first and last passes.
-template <typename T>
-void vcycle_level0_rb(const VArgs& a, const double* b0, double* x0, T* b, T* x) {
+template <typename T, typename TD>
+void vcycle_level0_rb(const VArgs& a, const double* b0, TD* x0, T* b, T* x) {
     Level& L = a.lev[0];
     Level& C = a.lev[1];
     Rb0V v = rb0_view(L);
@@ -2471,17 +2475,17 @@ void vcycle_level0_rb(const VArgs& a, const double* b0, double* x0, T* b, T* x) 
     if (cf32) resid_restrict_rb<T, float>(a, v, C, b, x, C.bf, first_into<float>(a, 1));
     else resid_restrict_rb<T, double>(a, v, C, b, x, C.b, first_into<double>(a, 1));
     vcycle_rec(a, 1);
-    if (cf32) up_leg_rb<T, float>(a, v, C.grid, C.xf, b, x, x0);
-    else up_leg_rb<T, double>(a, v, C.grid, C.x, b, x, x0);
+    if (cf32) up_leg_rb<T, float, TD>(a, v, C.grid, C.xf, b, x, x0);
+    else up_leg_rb<T, double, TD>(a, v, C.grid, C.x, b, x, x0);
     if (a.nu2 < 1) {
-        if (nc == 3) k_from_rb<T, double, 3><<<g, EB_BLOCK, 0, a.s>>>(L.grid, L.N, x, x0, L.gate);
-        else k_from_rb<T, double, 1><<<g, EB_BLOCK, 0, a.s>>>(L.grid, L.N, x, x0, L.gate);
+        if (nc == 3) k_from_rb<T, TD, 3><<<g, EB_BLOCK, 0, a.s>>>(L.grid, L.N, x, x0, L.gate);
+        else k_from_rb<T, TD, 1><<<g, EB_BLOCK, 0, a.s>>>(L.grid, L.N, x, x0, L.gate);
     }
 }
 
-template <typename T>
-void vcycle_rb(const VArgs& a, const double* b, double* x, T* brb, T* xrb) {
-    vcycle_level0_rb<T>(a, b, x, brb, xrb);
+template <typename T, typename TD>
+void vcycle_rb(const VArgs& a, const double* b, TD* x, T* brb, T* xrb) {
+    vcycle_level0_rb<T, TD>(a, b, x, brb, xrb);
 }
 
 void tail_pack(const Level* lev, int nlev, hipStream_t s) {
@@ -2592,8 +2596,8 @@ void mg_vcycle(Level* lev, int nlev, int ncomp, bool mixed, const double* b, dou
     long n = (long)ncomp * L0.N;
     if (nlev > 1 && !(a.tail == 0 && a.tail_fits) && L0.flag) {
         // the finest level in colour-split storage (its own arrays)
-        if (level_f32(a, 0)) vcycle_rb<float>(a, b, x, L0.bf, L0.xf);
-        else vcycle_rb<double>(a, b, x, L0.b, L0.x);
+        if (level_f32(a, 0)) vcycle_rb<float, double>(a, b, x, L0.bf, L0.xf);
+        else vcycle_rb<double, double>(a, b, x, L0.b, L0.x);
         for (int l = 0; l < nlev; l++) lev[l].gate = nullptr;
         return;
     }
@@ -2614,6 +2618,27 @@ void mg_vcycle(Level* lev, int nlev, int ncomp, bool mixed, const double* b, dou
     for (int l = 0; l < nlev; l++) lev[l].gate = nullptr;
 }
 
+// the V-cycle's VArgs as mg_vcycle forms them
+VArgs vargs(Level* lev, int nlev, int ncomp, bool mixed, int nu1, int nu2, int nbottom,
+            hipStream_t s) {
+    int tl = tail_level(lev, nlev);
+    return VArgs{lev, nlev, ncomp, nu1, nu2, nbottom, mixed, s, tl,
+                 tail_layout(lev, nlev, tl, ncomp, nullptr) <= TAIL_LDS_BYTES};
+}
+
+bool mg_vcycle_f32_out(Level* lev, int nlev, int ncomp, bool mixed, int nu1, int nu2) {
+    VArgs a = vargs(lev, nlev, ncomp, mixed, nu1, nu2, 0, nullptr);
+    return nlev > 1 && !(a.tail == 0 && a.tail_fits) && lev[0].flag && level_f32(a, 0);
+}
+
+void mg_vcycle(Level* lev, int nlev, int ncomp, bool mixed, const double* b, float* x, int nu1,
+               int nu2, int nbottom, hipStream_t s, const int* gate) {
+    for (int l = 0; l < nlev; l++) lev[l].gate = gate;
+    VArgs a = vargs(lev, nlev, ncomp, mixed, nu1, nu2, nbottom, s);
+    vcycle_rb<float, float>(a, b, x, lev[0].bf, lev[0].xf);
+    for (int l = 0; l < nlev; l++) lev[l].gate = nullptr;
+}
+
 void mg_sweep_level0(const Level& L, int ncomp, bool f32, const void* b, void* x, int colour,
                      hipStream_t s) {
     if (f32)
@@ -2630,18 +2655,29 @@ void mg_apply_level0(const Level& L, int ncomp, const double* x, double* y, hipS
     else k_apply0<1><<<grid_for(L.N), EB_BLOCK, 0, s>>>(v, x, y);
 }
 
+template <typename TU>
+void op_visc_apply_t(const GeomV& g, double rho, double dt, const double* eta,
+                     const double* eta_eb, const TU* u, double* out, int homogeneous,
+                     hipStream_t s, const int* gate) {
+    double h2 = g.grid.h * g.grid.h;
+    double kin = dt * 0.5 / h2, kwall = 2.0 * dt / h2;
+    k_visc_apply<TU><<<grid_for(g.N), EB_BLOCK, 0, s>>>(g, rho, dt, kin, kwall,
+                                                        fast_div((unsigned)g.grid.n[0]),
+                                                        fast_div((unsigned)g.grid.n[1]), eta,
+                                                        eta_eb, u, out, homogeneous, gate);
+    if (g.ncut > 0)
+        k_visc_apply_eb<TU><<<grid_for(g.ncut), EB_BLOCK, 0, s>>>(g, dt, eta_eb, u, out,
+                                                                homogeneous, gate);
+}
 void op_visc_apply(const GeomV& g, double rho, double dt, const double* eta,
                    const double* eta_eb, const double* u, double* out, int homogeneous,
                    hipStream_t s, const int* gate) {
-    double h2 = g.grid.h * g.grid.h;
-    double kin = dt * 0.5 / h2, kwall = 2.0 * dt / h2;
-    k_visc_apply<<<grid_for(g.N), EB_BLOCK, 0, s>>>(g, rho, dt, kin, kwall,
-                                                    fast_div((unsigned)g.grid.n[0]),
-                                                    fast_div((unsigned)g.grid.n[1]), eta, eta_eb,
-                                                    u, out, homogeneous, gate);
-    if (g.ncut > 0)
-        k_visc_apply_eb<<<grid_for(g.ncut), EB_BLOCK, 0, s>>>(g, dt, eta_eb, u, out, homogeneous,
-                                                            gate);
+    op_visc_apply_t<double>(g, rho, dt, eta, eta_eb, u, out, homogeneous, s, gate);
+}
+void op_visc_apply(const GeomV& g, double rho, double dt, const double* eta,
+                   const double* eta_eb, const float* u, double* out, int homogeneous,
+                   hipStream_t s, const int* gate) {
+    op_visc_apply_t<float>(g, rho, dt, eta, eta_eb, u, out, homogeneous, s, gate);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -2689,13 +2725,24 @@ void ks_bi_s_op(long n, double* sv, const double* r, const double* v, double* pa
     k_final_op<<<1, EB_BLOCK, 0, s>>>(part, nb, 1, o, KS_BI_CHECK_S, ks, st, itc);
 }
 
+template <typename TP>
+void ks_bi_xr_op_t(long n, double* x, double* r, const TP* ph, const TP* sh, const double* sv,
+                   const double* t, const double* rh, double* part, double* ks, int* st,
+                   int* itc, hipStream_t s) {
+    OpOut o = {{KS_RRN, KS_RN, 0, 0}, 2};
+    int nb = red_blocks(n);
+    k_bi_xr_red<TP><<<nb, EB_BLOCK, 0, s>>>(n, x, r, ph, sh, sv, t, rh, ks, st, part);
+    k_final_op<<<1, EB_BLOCK, 0, s>>>(part, nb, 2, o, KS_BI_CHECK_R, ks, st, itc);
+}
 void ks_bi_xr_op(long n, double* x, double* r, const double* ph, const double* sh,
                  const double* sv, const double* t, const double* rh, double* part, double* ks,
                  int* st, int* itc, hipStream_t s) {
-    OpOut o = {{KS_RRN, KS_RN, 0, 0}, 2};
-    int nb = red_blocks(n);
-    k_bi_xr_red<<<nb, EB_BLOCK, 0, s>>>(n, x, r, ph, sh, sv, t, rh, ks, st, part);
-    k_final_op<<<1, EB_BLOCK, 0, s>>>(part, nb, 2, o, KS_BI_CHECK_R, ks, st, itc);
+    ks_bi_xr_op_t<double>(n, x, r, ph, sh, sv, t, rh, part, ks, st, itc, s);
+}
+void ks_bi_xr_op(long n, double* x, double* r, const float* ph, const float* sh,
+                 const double* sv, const double* t, const double* rh, double* part, double* ks,
+                 int* st, int* itc, hipStream_t s) {
+    ks_bi_xr_op_t<float>(n, x, r, ph, sh, sv, t, rh, part, ks, st, itc, s);
 }
 
 void ks_cg_xr_op(long n, double* x, double* r, const double* p, const double* q, double* part,
