@@ -18,6 +18,25 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+CHECK = os.path.join(HERE, "_build", "sanitize_check")
+
+
+def build_sanitize_check(verbose: bool = False) -> str:
+    """The sanitizer driver (sanitize_check.c with the oracle, -fsanitize=address,undefined):
+    built here so that a build compiles every C source of the oracle; tests/
+    test_oracle_sanitized.py builds and runs its own copy."""
+    os.makedirs(os.path.dirname(CHECK), exist_ok=True)
+    cmd = ["gcc", "-O1", "-g", "-std=c99", "-Wall", "-Wno-unknown-pragmas", "-ffp-contract=off",
+           "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+           "-I", HERE, os.path.join(HERE, "eb_oracle.c"), os.path.join(HERE, "sanitize_check.c"),
+           "-o", CHECK, "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.check_call(cmd)
+    return CHECK
+
+
 if __name__ == "__main__":
     build(verbose="-v" in sys.argv)
+    build_sanitize_check(verbose="-v" in sys.argv)
     print(LIB)
