@@ -86,7 +86,7 @@ enum { EB_FP64 = 0, EB_MIXED = 1 };
 enum { EB_SYS_POISSON = 0, EB_SYS_VISC = 1 };  /* system for eb_mg_vcycle */
 
 typedef struct {
-    int n[3];             /* cells per direction; each a multiple of 2 */
+    int n[3];             /* cells per direction; each a multiple of 2, fewer than 2^31 cells */
     double h;             /* cell size (> 0) */
     double lo[3];         /* lower domain corner */
     int periodic[3];      /* 1 = periodic in that direction */

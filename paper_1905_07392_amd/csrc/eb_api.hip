@@ -376,6 +376,10 @@ int init_ctx(eb_ctx* c, const eb_box* box, const eb_body* body) {
         if (box->n[d] < 2 || box->n[d] % 2)
             return set_err(EB_EINVAL, "n[%d]=%d must be an even number >= 2", d, box->n[d]);
     if (!(box->h > 0.0)) return set_err(EB_EINVAL, "h must be positive");
+    // cell indices are taken apart with 32-bit arithmetic (multiply-high divisions of indices
+    // below 2^31): far beyond what one GPU's memory holds anyway
+    if ((long long)box->n[0] * box->n[1] * box->n[2] >= (1LL << 31))
+        return set_err(EB_EINVAL, "a box holds fewer than 2^31 cells");
     if (body->kind < EB_BODY_NONE || body->kind > EB_BODY_CAVITY)
         return set_err(EB_EINVAL, "unknown body kind %d", body->kind);
     memset(c, 0, sizeof(*c));
