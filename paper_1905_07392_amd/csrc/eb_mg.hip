@@ -1904,14 +1904,20 @@ struct DotArgs {
     const double* b[4];
 };
 
-__global__ void k_dots(long n, int np, DotArgs args, double* __restrict__ part, const int* gate) {
+template <int NP>
+__global__ void k_dots(long n, DotArgs args, double* __restrict__ part, const int* gate) {
     if (gate && *gate) return;
     __shared__ double sh[EB_BLOCK];
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    double s[NP];
+#pragma unroll
+    for (int p = 0; p < NP; p++) s[p] = 0.0;
+#pragma unroll 4
     for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n;
          t += (long)gridDim.x * blockDim.x)
-        for (int p = 0; p < np; p++) s[p] += args.a[p][t] * args.b[p][t];
-    for (int p = 0; p < np; p++) {
+#pragma unroll
+        for (int p = 0; p < NP; p++) s[p] += args.a[p][t] * args.b[p][t];
+#pragma unroll
+    for (int p = 0; p < NP; p++) {
         double v = block_sum(s[p], sh);
         if (threadIdx.x == 0) part[p * gridDim.x + blockIdx.x] = v;
     }
@@ -1924,6 +1930,7 @@ __global__ void k_maxabs(long n, int ncomp, const double* __restrict__ x,
     __shared__ double sh[EB_BLOCK];
     for (int m = 0; m < ncomp; m++) {
         double v = 0.0;
+#pragma unroll 4
         for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n;
              t += (long)gridDim.x * blockDim.x)
             v = nan_max(v, fabs(x[m * n + t]));
@@ -1965,6 +1972,7 @@ __global__ void k_bi_s_max(long n, double* __restrict__ sv, const double* __rest
     if (*st != 0) return;
     __shared__ double sh[EB_BLOCK];
     double al = ks[KS_AL], m = 0.0;
+#pragma unroll 4
     for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n;
          t += (long)gridDim.x * blockDim.x) {
         double s = r[t] - al * v[t];
@@ -1987,6 +1995,7 @@ __global__ void k_bi_xr_red(long n, double* __restrict__ x, double* __restrict__
     __shared__ double sh[EB_BLOCK];
     double al = ks[KS_AL], om = ks[KS_OM];
     double dot = 0.0, m = 0.0;
+#pragma unroll 4
     for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n;
          t += (long)gridDim.x * blockDim.x) {
         x[t] += al * (double)ph[t] + om * (double)sh_[t];
@@ -2009,6 +2018,7 @@ __global__ void k_cg_xr_max(long n, double* __restrict__ x, double* __restrict__
     if (*st != 0) return;
     __shared__ double sh[EB_BLOCK];
     double a = ks[KS_AL], m = 0.0;
+#pragma unroll 4
     for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n;
          t += (long)gridDim.x * blockDim.x) {
         x[t] += a * p[t];
@@ -2044,6 +2054,7 @@ __global__ void k_sum_open(GeomV g, const double* __restrict__ x, double* __rest
     if (gate && *gate) return;
     __shared__ double sh[EB_BLOCK];
     double s = 0.0, cnt = 0.0;
+#pragma unroll 4
     for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < g.N;
          t += (long)gridDim.x * blockDim.x)
         if (g.alpha[t] > 0.0) {
@@ -2689,6 +2700,16 @@ int red_blocks(long n) {
     return (int)(b < 1 ? 1 : b);
 }
 
+void dots_launch(long n, int np, const DotArgs& args, double* part, const int* gate, int nb,
+                 hipStream_t s) {
+    switch (np) {
+        case 1: k_dots<1><<<nb, EB_BLOCK, 0, s>>>(n, args, part, gate); break;
+        case 2: k_dots<2><<<nb, EB_BLOCK, 0, s>>>(n, args, part, gate); break;
+        case 3: k_dots<3><<<nb, EB_BLOCK, 0, s>>>(n, args, part, gate); break;
+        default: k_dots<4><<<nb, EB_BLOCK, 0, s>>>(n, args, part, gate); break;
+    }
+}
+
 void red_dots(long n, int np, const double* const a[4], const double* const b[4], double* part,
               double* out, hipStream_t s, const int* gate) {
     DotArgs args;
@@ -2697,7 +2718,7 @@ void red_dots(long n, int np, const double* const a[4], const double* const b[4]
         args.b[p] = p < np ? b[p] : nullptr;
     }
     int nb = red_blocks(n);
-    k_dots<<<nb, EB_BLOCK, 0, s>>>(n, np, args, part, gate);
+    dots_launch(n, np, args, part, gate, nb, s);
     k_final<<<1, EB_BLOCK, 0, s>>>(part, nb, np, 0, out, gate);
 }
 
@@ -2713,7 +2734,7 @@ void red_dots_op(long n, int np, const double* const a[4], const double* const b
     }
     o.maxmask = 0;
     int nb = red_blocks(n);
-    k_dots<<<nb, EB_BLOCK, 0, s>>>(n, np, args, part, st);
+    dots_launch(n, np, args, part, st, nb, s);
     k_final_op<<<1, EB_BLOCK, 0, s>>>(part, nb, np, o, op, ks, st, itc);
 }
 
