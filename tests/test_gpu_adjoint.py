@@ -338,6 +338,11 @@ def test_switch_record_replay():
 
 @pytest.mark.parametrize("n,nsteps", [(128, 5), (32, 20)])
 def test_adjoint_workload_fd(n, nsteps):
+    """(See _adjoint_fd.)"""
+    _adjoint_fd(n, nsteps)
+
+
+def _adjoint_fd(n, nsteps, ncells=2, cell_rel=1e-3):
     """The adjoint workload (sphere r = 0.125, Bi = 10, theta seeded, rho = 4e-3, dt = 5e-4)
     at n^3: the checkpointed autograd gradients of F_z in Bi and in the two most sensitive of
     16 seeded cells near the body against central differences of the forward run with its
@@ -408,8 +413,8 @@ def test_adjoint_workload_fd(n, nsteps):
     _, alpha, _, _, _ = api.eb_geometry_export(ctx)
     cand = np.flatnonzero((cpu(alpha) > 0).ravel() & (np.abs(dist).ravel() < 3 * w.h))
     picks = I.rng(2).choice(cand, size=16, replace=False)
-    for cidx in picks[np.argsort(-np.abs(g_th[picks]))[:2]]:
-        hc = 1e-3 * float(theta.view(-1)[cidx])
+    for cidx in picks[np.argsort(-np.abs(g_th[picks]))[:ncells]]:
+        hc = cell_rel * float(theta.view(-1)[cidx])
         tp, tm = theta.clone().view(-1), theta.clone().view(-1)
         tp[cidx] += hc
         tm[cidx] -= hc
@@ -438,3 +443,80 @@ def test_derived_adjoint_laws(s32, law):
                                          theta=P.dev(P.theta))
     assert rel_l2(cpu(gu), ru, P.open) < 1e-10
     assert rel_l2(cpu(gt), rt, P.open) < 1e-10
+
+
+def _oracle_fd_table():
+    """tests/golden/sphere128_fd_oracle.txt (make_sphere128_history.py fd, oracle only): per step
+    F_z at Bi, Bi + h, Bi - h (h = 1e-6 Bi) and max |u(Bi+h) - u(Bi)| over open cells."""
+    import os
+
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "sphere128_fd_oracle.txt")
+    if not os.path.exists(path):
+        pytest.skip("no stored oracle differences")
+    rows = [[float(x) for x in l.split()] for l in open(path)
+            if l.strip() and not l.startswith("#")]
+    return np.array(rows)
+
+
+def test_adjoint_workload_sensitivity_matches_oracle():
+    """The 20-step horizon of the adjoint workload (128^3 sphere, Bi = 10 with the seeded
+    yield-stress field, dt = 5e-4, solves to rtol 1e-12) run as the oracle's stored study ran
+    it: F_z at Bi, Bi + h and Bi - h (h = 1e-6 Bi) after every step.  The stored oracle run
+    itself shows where the drag stops being a smooth function of Bi on the scale of h: its
+    central differences change by less than 10% from step to step over steps 3 to 8 and by more
+    after that (they wander).  Over steps 1 to 8 the GPU's three drags equal the oracle's to
+    1e-10 and its central differences the oracle's to 1e-3 (what a 1e-10 agreement of F_z ~ 20
+    allows at h = 1e-5); later steps are printed.  This is why test_adjoint_workload_fd checks
+    5 steps at 128^3 and the 20-step check is skipped."""
+    import paper_1905_07392_amd as pkg
+    from paper_1905_07392_amd import api
+
+    _require_gpu()
+    tab = _oracle_fd_table()
+    nsteps = len(tab)
+    h = 1e-6 * 10.0
+    fd_or = (tab[:, 2] - tab[:, 3]) / (2 * h)
+    change = np.abs(np.diff(fd_or)) / np.abs(fd_or[:-1])  # change[s] = step s+1 -> s+2
+    print(f"[adjoint] oracle dF/dBi by step {np.array2string(fd_or, precision=4)}", flush=True)
+    horizon = 8
+    assert change[2:horizon - 1].max() < 0.1, change  # steps 3..8 smooth
+    assert change[horizon - 1:].max() > 0.1, change  # then it wanders
+    w = I.sphere128()
+    assert abs(h - 1e-6 * w.tau0) < 1e-18
+    box, body, rheo, opts = pkg.from_workload(w, max_iter=1000)
+    ctx = api.eb_geometry_build(box, body, "cuda:0")
+    theta = torch.from_numpy(I.yield_field(w, seed=1)).to("cuda:0")
+    fz = {}
+    for tag, bi in (("0", w.tau0), ("+", w.tau0 + h), ("-", w.tau0 - h)):
+        r = api.make_rheology(rheo.law, rheo.mu, bi, rheo.eps, rheo.rho)
+        u = torch.from_numpy(I.initial_velocity(w)).to("cuda:0")
+        p = ctx.scalar()
+        out = []
+        for _ in range(nsteps):
+            u, p, _ = api.eb_rk2_step(ctx, r, w.dt, opts, u, p, theta=theta)
+            out.append(api.eb_drag(ctx, r, u, p, theta=theta)[2])
+        fz[tag] = np.array(out)
+    fd_gpu = (fz["+"] - fz["-"]) / (2 * h)
+    ef = {k: np.abs(fz[k] - tab[:, c]) / np.abs(tab[:, c]) for k, c in (("0", 1), ("+", 2), ("-", 3))}
+    for s in range(nsteps):
+        print(f"[adjoint] sensitivity step {s + 1}: F_z rel {ef['0'][s]:.2e} {ef['+'][s]:.2e} "
+              f"{ef['-'][s]:.2e}; dF/dBi gpu {fd_gpu[s]:+.6e} oracle {fd_or[s]:+.6e}; oracle "
+              f"max|du| {tab[s, 4]:.2e}", flush=True)
+    for k in ef:
+        assert ef[k][:horizon].max() <= 1e-10, (k, ef[k])
+    rel = np.abs(fd_gpu[:horizon] - fd_or[:horizon]) / np.abs(fd_or[:horizon])
+    assert rel.max() <= 1e-3, rel
+
+
+@pytest.mark.skip(reason=(
+    "the 20-step drag of this configuration is not differentiable on the scale of any usable "
+    "step: the FP64 oracle's own central differences in Bi (tests/golden/sphere128_fd_oracle.txt) "
+    "are smooth through step 8 (about -0.5) and then wander from step to step (opposite signs, "
+    "magnitudes up to about 20), as the GPU's do (test_adjoint_workload_sensitivity_matches_oracle); "
+    "the configured dt is 2.7e5 times the step's stability rule.  The adjoint is checked against "
+    "differences over 5 steps at 128^3 and over 20 steps at 32^3 (test_adjoint_workload_fd)"))
+def test_adjoint_workload_fd_twenty_steps_16_cells():
+    """The configuration as specified: 20 steps at 128^3, central differences with step 1e-6 on
+    all 16 seeded cells and on Bi, 1e-5."""
+    _adjoint_fd(128, 20, ncells=16, cell_rel=1e-6)
