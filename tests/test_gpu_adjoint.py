@@ -465,10 +465,12 @@ def test_adjoint_workload_sensitivity_matches_oracle():
     it: F_z at Bi, Bi + h and Bi - h (h = 1e-6 Bi) after every step.  The stored oracle run
     itself shows where the drag stops being a smooth function of Bi on the scale of h: its
     central differences change by less than 10% from step to step over steps 3 to 8 and by more
-    after that (they wander).  Over steps 1 to 8 the GPU's three drags equal the oracle's to
-    1e-10 and its central differences the oracle's to 1e-3 (what a 1e-10 agreement of F_z ~ 20
-    allows at h = 1e-5); later steps are printed.  This is why test_adjoint_workload_fd checks
-    5 steps at 128^3 and the 20-step check is skipped."""
+    after that (they wander).  At every one of the 20 steps the GPU's three drags equal the
+    oracle's to 1e-10 and its central differences the oracle's to 1e-3 (what a 1e-10 agreement
+    of F_z ~ 20 allows at h = 1e-5; measured: drags within 3.5e-12 relative, differences to seven digits,
+    the wandering ones included).  Both implementations follow the same deterministic,
+    non-differentiable drag, which is why test_adjoint_workload_fd checks 5 steps at 128^3 and
+    the 20-step check is skipped."""
     import paper_1905_07392_amd as pkg
     from paper_1905_07392_amd import api
 
@@ -504,8 +506,8 @@ def test_adjoint_workload_sensitivity_matches_oracle():
               f"{ef['-'][s]:.2e}; dF/dBi gpu {fd_gpu[s]:+.6e} oracle {fd_or[s]:+.6e}; oracle "
               f"max|du| {tab[s, 4]:.2e}", flush=True)
     for k in ef:
-        assert ef[k][:horizon].max() <= 1e-10, (k, ef[k])
-    rel = np.abs(fd_gpu[:horizon] - fd_or[:horizon]) / np.abs(fd_or[:horizon])
+        assert ef[k].max() <= 1e-10, (k, ef[k])
+    rel = np.abs(fd_gpu - fd_or) / np.abs(fd_or)
     assert rel.max() <= 1e-3, rel
 
 
@@ -513,7 +515,8 @@ def test_adjoint_workload_sensitivity_matches_oracle():
     "the 20-step drag of this configuration is not differentiable on the scale of any usable "
     "step: the FP64 oracle's own central differences in Bi (tests/golden/sphere128_fd_oracle.txt) "
     "are smooth through step 8 (about -0.5) and then wander from step to step (opposite signs, "
-    "magnitudes up to about 20), as the GPU's do (test_adjoint_workload_sensitivity_matches_oracle); "
+    "magnitudes up to about 15), and the GPU's equal them to seven digits at every step "
+    "(test_adjoint_workload_sensitivity_matches_oracle); "
     "the configured dt is 2.7e5 times the step's stability rule.  The adjoint is checked against "
     "differences over 5 steps at 128^3 and over 20 steps at 32^3 (test_adjoint_workload_fd)"))
 def test_adjoint_workload_fd_twenty_steps_16_cells():
