@@ -90,10 +90,9 @@ namespace {
 constexpr int NSLOT = 8;
 }
 
-// one read-back of a solve's progress: its (state, count) slot and its residual max-norm
+// one read-back of a solve's progress: its (state, count) slot
 struct PollWord {
     int st[2];
-    double rn;
 };
 
 struct eb_ctx {
@@ -571,21 +570,16 @@ void vcyc(eb_ctx* c, int ncomp, const SolveCfg& k, const double* b, double* x, c
 
 // lagged convergence test: enqueue the read-back of the slot's state after iteration it and
 // wait for the one of iteration it-1 (already executed or about to be)
-// (the state word: 0 while running); with rn non-null, *rn receives the residual max-norm
-// after iteration it-1
-int poll_done(eb_ctx* c, int slot, int it, double* rn) {
+// (the state word: 0 while running)
+int poll_done(eb_ctx* c, int slot, int it) {
     int b = it & 1;
     HIPN(hipMemcpyAsync(c->pin[b].st, c->kst + 2 * slot, 2 * sizeof(int), hipMemcpyDeviceToHost,
                    c->s));
-    if (rn)
-        HIPN(hipMemcpyAsync(&c->pin[b].rn, c->ks + KS_RN, sizeof(double), hipMemcpyDeviceToHost,
-                       c->s));
     HIPN(hipEventRecord(c->ev[b], c->s));
     if (it < 2) return 0;
     int pb = (it - 1) & 1;
     HIPN(hipEventSynchronize(c->ev[pb]));
     if (hip_failed()) return 3;  // the runtime failed: stop; the entry point reports EB_EHIP
-    if (rn) *rn = c->pin[pb].rn;
     return c->pin[pb].st[0];
 }
 
@@ -610,11 +604,10 @@ int slot_count_now(eb_ctx* c, int slot) {
 // the conditioning of the level operators times the FP32 unit roundoff stays well below one
 // (high viscosity contrast, as in a nearly rigid plug next to a sheared layer, breaks this).
 // A mixed solve is given up when its residual max-norm has not fallen tenfold within
-// STALL_WINDOW iterations (a working V-cycle gains that in two or three), or when it has not
-// converged within mixed_budget iterations; the caller then solves again from the same
-// starting iterate with the FP64 V-cycle, so the result is the FP64 solve's.  The step's
+// KS_STALL_W iterations (the device's stall test, which ends the solve with state 4), or when
+// it has not converged within mixed_budget iterations; the caller then solves again from the
+// same starting iterate with the FP64 V-cycle, so the result is the FP64 solve's.  The step's
 // stats count such switches.
-constexpr int STALL_WINDOW = 6;
 
 int mixed_budget(const SolveCfg& k) {
     int b = k.max_iter / 10 > 20 ? k.max_iter / 10 : 20;
@@ -622,26 +615,12 @@ int mixed_budget(const SolveCfg& k) {
 }
 
 // up to max_iter iterations of a solve whose state lives in `slot`; returns the final state
-// (2 converged, 3 non-finite, 0 not converged: iterations exhausted, or stalled when `watch`)
+// (2 converged, 3 non-finite, 4 stalled (a watched solve), 0 iterations exhausted)
 template <class Body>
-int iterate(eb_ctx* c, const GraphKey& key, int slot, int max_iter, Body& body, bool watch) {
-    double best_old = INFINITY, recent[STALL_WINDOW];
+int iterate(eb_ctx* c, const GraphKey& key, int slot, int max_iter, Body& body) {
     for (int it = 1; it <= max_iter; it++) {
         run_iteration(c, key, body);
-        double rn = 0.0;
-        if (int s = poll_done(c, slot, it, watch ? &rn : nullptr)) return s == 1 ? 2 : s;
-        if (!watch || it < 2) continue;
-        int j = it - 1;  // the iteration rn belongs to
-        if (j > STALL_WINDOW) {
-            double gone = recent[j % STALL_WINDOW];  // iteration j - STALL_WINDOW
-            best_old = gone < best_old ? gone : best_old;
-        }
-        recent[j % STALL_WINDOW] = rn;
-        if (j > STALL_WINDOW) {
-            double best_new = INFINITY;
-            for (double r : recent) best_new = r < best_new ? r : best_new;
-            if (!(best_new <= 0.1 * best_old)) break;
-        }
+        if (int s = poll_done(c, slot, it)) return s == 1 ? 2 : s;
     }
     return slot_state(c, slot);
 }
@@ -671,7 +650,7 @@ int pcg(eb_ctx* c, const double* b, double* x, const SolveCfg& k, int slot) {
     vec_sub_scaled(N, b, 1.0, q, r, c->s);
     red_maxabs(N, 1, b, c->part, ks + KS_BN, c->s);
     red_maxabs(N, 1, r, c->part, ks + KS_RN, c->s);
-    ks_op(KS_INIT, ks, st, itc, c->s);
+    ks_op(k.mixed ? KS_INIT_WATCH : KS_INIT, ks, st, itc, c->s);
     vcyc(c, 1, k, r, z, st);
     cg_mean_free(c, z, st);
     vec_copy(N, z, pd, c->s);
@@ -701,7 +680,7 @@ int pcg(eb_ctx* c, const double* b, double* x, const SolveCfg& k, int slot) {
         red_dots_op(N, 1, A, B, c->part, KS_RZN, KS_CG_BETA, ks, st, itc, c->s);
         ks_cg_p(N, pd, z, ks, st, c->s);
     };
-    return iterate(c, key, slot, k.max_iter, body, k.mixed);
+    return iterate(c, key, slot, k.max_iter, body);
 }
 
 // Poisson solve for the projections: M p = -(D w - mean), then p normalised to zero mean
@@ -805,7 +784,7 @@ int nodal_pcg(eb_ctx* c, const double* b, double* x, const SolveCfg& k, int slot
         red_dots_op(M, 1, A, B, c->part, KS_RZN, KS_CG_BETA, ks, st, itc, c->s);
         ks_cg_p(M, pd, z, ks, st, c->s);
     };
-    return iterate(c, key, slot, nodal_max_iter(c, k), body, false);
+    return iterate(c, key, slot, nodal_max_iter(c, k), body);
 }
 
 // The nodal end-of-stage projection (Sec. III.A.4): u += beta G(pn_old); solve
@@ -905,7 +884,7 @@ int bicgstab(eb_ctx* c, double rho, double dt, const double* eta, const double* 
     apply(x, t, nullptr);
     vec_sub_scaled(N3, b, 1.0, t, r, c->s);
     red_maxabs(N3, 1, r, c->part, ks + KS_RN, c->s);
-    ks_op(KS_INIT, ks, st, itc, c->s);
+    ks_op(k.mixed ? KS_INIT_WATCH : KS_INIT, ks, st, itc, c->s);
     vec_copy(N3, r, rh, c->s);
     vec_fill(N3, 0.0, p, c->s);
     vec_fill(N3, 0.0, v, c->s);
@@ -959,7 +938,7 @@ int bicgstab(eb_ctx* c, double rho, double dt, const double* eta, const double* 
         if (f32) ks_bi_xr_op(N3, x, r, phf, shf, sv, t, rh, c->part, ks, st, itc, c->s);
         else ks_bi_xr_op(N3, x, r, ph, sh, sv, t, rh, c->part, ks, st, itc, c->s);
     };
-    return iterate(c, key, slot, k.max_iter, body, k.mixed);
+    return iterate(c, key, slot, k.max_iter, body);
 }
 
 // reads `n` solve slots (state, count) after the stream drains

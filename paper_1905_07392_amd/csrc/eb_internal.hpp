@@ -332,18 +332,39 @@ void op_shift_open(const GeomV& g, double* x, const double* sumcnt, hipStream_t 
                    const int* gate = nullptr);
 
 // device-resident Krylov scalars (slots of a double array) and scalar updates
+// the stall test's window (iterations) for a solve preconditioned by the FP32 V-cycle
+constexpr int KS_STALL_W = 6;
 enum {
     KS_RTOL, KS_BN, KS_SCALE, KS_TOL, KS_RN, KS_SN, KS_RHO_OLD, KS_AL, KS_OM, KS_BE, KS_RZ,
-    KS_RZN, KS_PQ, KS_RR, KS_RV, KS_TS, KS_TT, KS_SUM, KS_CNT, KS_RRN, KS_COUNT = 24
+    KS_RZN, KS_PQ, KS_RR, KS_RV, KS_TS, KS_TT, KS_SUM, KS_CNT, KS_RRN, KS_WATCH, KS_BEST_OLD,
+    KS_RING, KS_COUNT = 32
 };
+static_assert(KS_RING + KS_STALL_W <= KS_COUNT, "Krylov scalar slots");
 enum {
     KS_INIT, KS_CG_ALPHA, KS_CHECK_R, KS_CG_BETA, KS_BI_ALPHA, KS_BI_CHECK_S, KS_BI_OMEGA,
-    KS_BI_CHECK_R
+    KS_BI_CHECK_R, KS_INIT_WATCH
 };
+// The stall test of a watched solve (one preconditioned by the FP32 V-cycle), after the
+// residual max-norm rn of iteration it is known and has not met the tolerance: rn enters a ring
+// of the last KS_STALL_W values; from iteration KS_STALL_W + 1 on, the least of those must be
+// at most a tenth of the least before them (KS_BEST_OLD), else the state becomes 4 (stalled).
+// A working V-cycle gains a factor of ten in two or three iterations.
+__device__ inline void ks_stall_test(double* __restrict__ ks, int* __restrict__ st, int it) {
+    double* ring = ks + KS_RING;
+    int j = it % KS_STALL_W;
+    if (it > KS_STALL_W && ring[j] < ks[KS_BEST_OLD]) ks[KS_BEST_OLD] = ring[j];
+    ring[j] = ks[KS_RN];
+    if (it > KS_STALL_W) {
+        double best_new = INFINITY;
+        for (int q = 0; q < KS_STALL_W; q++) best_new = ring[q] < best_new ? ring[q] : best_new;
+        if (!(best_new <= 0.1 * ks[KS_BEST_OLD])) *st = 4;
+    }
+}
 // One Krylov scalar update, run by a single thread: op on the scalars ks of the solve whose
 // state word and count are st[0], st[1] and whose device iteration counter is *itc.  The state
 // is 0 while the solve runs, 1 when it converged at BiCGSTAB's half step (x update pending), 2
-// converged, 3 non-finite residual; once it leaves 0 the ops do nothing more.
+// converged, 3 non-finite residual, 4 stalled (a watched solve, KS_INIT_WATCH); once it leaves 0
+// the ops do nothing more.
 __device__ inline void ks_scalar_op(int op, double* __restrict__ ks, int* __restrict__ st,
                                     int* __restrict__ itc) {
     int s = *st;
@@ -351,7 +372,8 @@ __device__ inline void ks_scalar_op(int op, double* __restrict__ ks, int* __rest
     if (s == 0 && (op == KS_CG_ALPHA || op == KS_BI_ALPHA)) *itc += 1;
     int it = *itc;
     switch (op) {
-    case KS_INIT: {  // tol = rtol * max(bn, scale); converged already if rn <= tol
+    case KS_INIT:  // tol = rtol * max(bn, scale); converged already if rn <= tol
+    case KS_INIT_WATCH: {
         double bn = ks[KS_BN] > ks[KS_SCALE] ? ks[KS_BN] : ks[KS_SCALE];
         ks[KS_TOL] = ks[KS_RTOL] * bn;
         st[1] = 0;
@@ -362,6 +384,8 @@ __device__ inline void ks_scalar_op(int op, double* __restrict__ ks, int* __rest
         ks[KS_RHO_OLD] = 1.0;
         ks[KS_AL] = 1.0;
         ks[KS_OM] = 1.0;
+        ks[KS_WATCH] = op == KS_INIT_WATCH ? 1.0 : 0.0;
+        ks[KS_BEST_OLD] = INFINITY;
         break;
     }
     case KS_CG_ALPHA:
@@ -373,6 +397,8 @@ __device__ inline void ks_scalar_op(int op, double* __restrict__ ks, int* __rest
             else if (ks[KS_RN] <= ks[KS_TOL]) {
                 *st = 2;
                 st[1] = it;
+            } else if (ks[KS_WATCH] != 0.0) {
+                ks_stall_test(ks, st, it);
             }
         }
         break;
@@ -402,6 +428,8 @@ __device__ inline void ks_scalar_op(int op, double* __restrict__ ks, int* __rest
             else if (ks[KS_RN] <= ks[KS_TOL]) {
                 *st = 2;
                 st[1] = 2 * it;
+            } else if (ks[KS_WATCH] != 0.0) {
+                ks_stall_test(ks, st, it);
             }
         }
         break;

@@ -1758,14 +1758,18 @@ __global__ void __launch_bounds__(EB_BLOCK) k_visc_apply(GeomV g, double rho, do
             nb[2 * d + side] = cell_step(g.grid, c, i, j, k, d, side);
         }
     uint8_t fl = g.flag[c];
+    // a missing neighbour (across a wall) loads the cell itself, a value never used: the loads
+    // are unconditional, so none waits behind a branch (an FP32 input widened inside a branch
+    // would make each load wait before the next is issued)
     double uc[3], un[6][3], en[6];
 #pragma unroll
     for (int m = 0; m < 3; m++) uc[m] = (double)u[m * N + c];
 #pragma unroll
     for (int f = 0; f < 6; f++) {
-        en[f] = nb[f] >= 0 ? eta[nb[f]] : 0.0;
+        long q = nb[f] >= 0 ? nb[f] : c;
+        en[f] = eta[q];
 #pragma unroll
-        for (int m = 0; m < 3; m++) un[f][m] = nb[f] >= 0 ? (double)u[m * N + nb[f]] : 0.0;
+        for (int m = 0; m < 3; m++) un[f][m] = (double)u[m * N + q];
     }
     double ec = eta[c];
     if (fl == 0) {
@@ -1853,7 +1857,10 @@ __global__ void __launch_bounds__(EB_BLOCK) k_visc_apply_eb(GeomV g, double dt,
     for (int m = 0; m < 3; m++) {
         double ue = homog ? 0.0 : g.ueb[m];
 #pragma unroll
-        for (int t = 0; t < 18; t++) uv[m][t] = ci[t] >= 0 ? (double)u[m * N + ci[t]] : ue;
+        for (int t = 0; t < 18; t++) {
+            TU v = u[m * N + (ci[t] >= 0 ? (long)ci[t] : c)];  // unconditional, as above
+            uv[m][t] = ci[t] >= 0 ? (double)v : ue;
+        }
         o[m] = out[m * N + c];
     }
     double den = d1 * d2 * (d2 - d1) * g.grid.h;
