@@ -216,6 +216,12 @@ __device__ __forceinline__ unsigned xcd_block() {
     unsigned q = nb >> 3, r = nb & 7, x = b & 7, i = b >> 3;
     return x * q + (x < r ? x : r) + i;
 }
+// the same mapping over the first nb blocks of a larger grid (block b < nb)
+__device__ __forceinline__ unsigned xcd_block_in(unsigned nb) {
+    unsigned b = blockIdx.x;
+    unsigned q = nb >> 3, r = nb & 7, x = b & 7, i = b >> 3;
+    return x * q + (x < r ? x : r) + i;
+}
 
 inline unsigned grid_for(long n, int block = EB_BLOCK) {
     long b = (n + block - 1) / block;
@@ -247,6 +253,8 @@ struct Level {
     // finest level only: what its operator was built from, so the smoother can recompute the
     // coefficients of regular cells instead of reading them (flag: 0 covered, 1 cut, 2 regular)
     const uint8_t* flag = nullptr;
+    const int* cut = nullptr;  // the cut cells (flag 1) in ascending order, ncut of them
+    int ncut = 0;
     const double* eta = nullptr;
     float* etaf = nullptr;  // FP32 copy of eta for the mixed-precision smoother
     int sys = 0;  // EB_SYS_POISSON or EB_SYS_VISC

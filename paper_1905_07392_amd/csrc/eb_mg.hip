@@ -10,6 +10,7 @@
 // 1e7 viscosity contrast of a plug next to a sheared layer.  Smoothing is red-black Gauss-Seidel; within a colour every update depends only
 // on the other colour, so the result does not depend on thread order.
 #include "eb_internal.hpp"
+#include <type_traits>
 
 namespace {
 
@@ -542,6 +543,8 @@ struct Rb0V {
     FastDiv dnx, dny, dnxh;  // n_x, n_y, n_x / 2
     long N;
     const uint8_t* flag;
+    const int* cut;  // the cut cells (flag 1), ncut of them
+    int ncut;
     const double* eta;
     const float* etaf;
     const double* K[3];
@@ -803,6 +806,185 @@ __global__ void __launch_bounds__(EB_BLOCK)
     long t = xcd_block() * (long)blockDim.x + threadIdx.x;
     if (t >= (L.N >> 1)) return;
     smooth_rb_cell<T, NC, PRO_NONE, T>(L, b, x, col, t, nullptr);
+}
+
+// the row of a regular cell (flag 2: every aperture 1, no wall flux) from its loaded
+// viscosities, as rb0_row_ld forms it: K[f] per face and the diagonal, returned.  nb[f] >= 0
+// where the cell has a neighbour across face f; VISC: the viscous system (else Poisson).
+template <typename T, bool VISC>
+__device__ __forceinline__ T rb0_regular_row(const Rb0V& L, const long nb[6], T ec,
+                                             const T en[6], T K[6]) {
+    T kin = (T)L.kin, kwall = (T)L.kwall, kp = (T)L.kpois;
+    T sd = VISC ? (T)L.rho : (T)0;
+#pragma unroll
+    for (int f = 0; f < 6; f++) {
+        T kf;
+        if (VISC) kf = nb[f] >= 0 ? kin * (ec + en[f]) : kwall * ec;
+        else kf = nb[f] >= 0 ? kp : (T)0;
+        sd += kf;
+        K[f] = kf;
+    }
+    return sd;
+}
+// smooth_rb_cell's update of acc (b on entry) from that row and the loaded neighbours
+template <typename T, int NC>
+__device__ __forceinline__ void rb0_apply_row(const long nb[6], const T K[6], T dg,
+                                              const T xn[6][NC], T acc[NC]) {
+#pragma unroll
+    for (int f = 0; f < 6; f++) {
+        T kf = K[f];
+        if (kf == (T)0 || nb[f] < 0) continue;
+#pragma unroll
+        for (int m = 0; m < NC; m++) acc[m] += kf * xn[f][m];
+    }
+    T inv = (T)1 / dg;
+#pragma unroll
+    for (int m = 0; m < NC; m++) acc[m] = acc[m] * inv;
+}
+
+// k_smooth_rb with two cells per thread: half indices ih0 and ih0 + 1 (ih0 even) of one half
+// row, natural cells a = (i_a, j, k) and b = (i_a + 2, j, k), which needs n_x a multiple of 4.
+// The other colour's values come in 16-byte pairs: its pair (ih0, ih0 + 1) in the same row holds
+// three of the four x neighbours (the fourth is a lone load, wrapped in the row when periodic),
+// and the pair at ih0 in the neighbour row of each y and z face holds that face's neighbour of
+// both cells.  The viscosities of a, b and their x neighbours are the five natural cells from
+// i_a - 1 to i_a + 3: two aligned pairs and a lone load.  Every load is unconditional (a missing
+// neighbour loads the cell's own row or value, never used), so a thread waits once.  The first
+// ncb blocks (a multiple of 8) take one cut cell per thread (those of colour col) through the
+// one-cell path (smooth_rb_cell), which loads a cut cell's stored row; the blocks after them
+// update the regular cells of their pairs from the loaded values and leave covered and cut cells
+// alone.  Within a colour every update reads only the other colour, so the split changes
+// nothing: the rows and updates are the one-cell kernel's, bit for bit.  The cut-cell blocks are
+// dispatched first and spread over the XCDs by the hardware's round-robin, so their longer
+// dependent loads neither trail the launch nor load the few XCDs whose slabs hold the body.
+// Three components are the viscous system and one the Poisson system (the launch checks this
+// against L.sys).  Four waves per SIMD (at most 128 VGPRs) keep enough loads in flight.
+template <typename T, int NC>
+__global__ void __launch_bounds__(EB_BLOCK, 4)
+    k_smooth_rb_pair(Rb0V L, const T* __restrict__ b, T* __restrict__ x, int col, unsigned ncb) {
+    static_assert(sizeof(T) == 8, "pairs of FP64 values");
+    constexpr bool VISC = NC == 3;
+    if (L.gate && *L.gate) return;
+    long N = L.N, Nh = N >> 1;
+    if (blockIdx.x < ncb) {
+        long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+        if (q >= L.ncut) return;
+        long c = L.cut[q];
+        int i, j, k;
+        rb_coords(L, c, i, j, k);
+        if (((i + j + k) & 1) != col) return;
+        smooth_rb_cell<T, NC, PRO_NONE, T>(L, b, x, col, c >> 1, nullptr);
+        return;
+    }
+    // the pair blocks, mapped to tiles per XCD as xcd_block does (ncb is a multiple of 8, so
+    // block ncb + u runs on the XCD of u)
+    unsigned npb = gridDim.x - ncb, u = blockIdx.x - ncb;
+    unsigned tile = (u & 7) * (npb >> 3) + ((u & 7) < (npb & 7) ? (u & 7) : (npb & 7)) + (u >> 3);
+    long p = tile * (long)blockDim.x + threadIdx.x;
+    if (p >= (Nh >> 1)) return;
+    const GridV& g = L.grid;
+    unsigned t = 2u * (unsigned)p;
+    unsigned row = fdiv(t, L.dnxh);
+    int nxh = (int)L.dnxh.d;
+    int ih0 = (int)(t - row * (unsigned)nxh);
+    unsigned kq = fdiv(row, L.dny);
+    int j = (int)(row - kq * L.dny.d), k = (int)kq;
+    int s = (j + k + col) & 1;
+    int ia = 2 * ih0 + s;
+    long ca = cell_index(g, ia, j, k), cb = ca + 2;
+    long nba[6], nbb[6];
+#pragma unroll
+    for (int d = 0; d < 3; d++)
+#pragma unroll
+        for (int side = 0; side < 2; side++) {
+            nba[2 * d + side] = cell_step(g, ca, ia, j, k, d, side);
+            nbb[2 * d + side] = cell_step(g, cb, ia + 2, j, k, d, side);
+        }
+    const T* xo = x + (long)(1 - col) * Nh;
+    long own = (long)col * Nh + t;
+    // the first slots of the half rows holding the y and z neighbours (the natural row of a's
+    // neighbour: the same row index in the other colour)
+    long ry[2], rz[2];
+#pragma unroll
+    for (int side = 0; side < 2; side++) {
+        long q = nba[2 + side] >= 0 ? nba[2 + side] : ca;
+        ry[side] = (long)fdiv((unsigned)q, L.dnx) * nxh;
+        q = nba[4 + side] >= 0 ? nba[4 + side] : ca;
+        rz[side] = (long)fdiv((unsigned)q, L.dnx) * nxh;
+    }
+    long rx = (long)row * nxh;
+    // the lone x neighbour: a's lower one (s = 0) or b's upper one (s = 1)
+    long xe = s == 0 ? (ih0 > 0 ? ih0 - 1 : nxh - 1) : (ih0 + 2 < nxh ? ih0 + 2 : 0);
+    T acca[NC], accb[NC], xa[6][NC], xb[6][NC];
+#pragma unroll
+    for (int m = 0; m < NC; m++) {
+        double2 bv = *reinterpret_cast<const double2*>(b + m * N + own);
+        acca[m] = bv.x;
+        accb[m] = bv.y;
+        double2 xc = *reinterpret_cast<const double2*>(xo + m * N + rx + ih0);
+        T e = xo[m * N + rx + xe];
+        xa[0][m] = s == 0 ? e : xc.x;
+        xa[1][m] = s == 0 ? xc.x : xc.y;
+        xb[0][m] = s == 0 ? xc.x : xc.y;
+        xb[1][m] = s == 0 ? xc.y : e;
+#pragma unroll
+        for (int side = 0; side < 2; side++) {
+            double2 yv = *reinterpret_cast<const double2*>(xo + m * N + ry[side] + ih0);
+            double2 zv = *reinterpret_cast<const double2*>(xo + m * N + rz[side] + ih0);
+            xa[2 + side][m] = yv.x;
+            xb[2 + side][m] = yv.y;
+            xa[4 + side][m] = zv.x;
+            xb[4 + side][m] = zv.y;
+        }
+    }
+    T eca = (T)0, ecb = (T)0, ena[6], enb[6];
+    if (VISC) {
+        const T* eta = L.eta;
+        long e0 = ca - s;  // even: the pairs (e0, e0 + 1) and (e0 + 2, e0 + 3)
+        double2 e01 = *reinterpret_cast<const double2*>(eta + e0);
+        double2 e23 = *reinterpret_cast<const double2*>(eta + e0 + 2);
+        long qx = s == 0 ? (nba[0] >= 0 ? nba[0] : ca) : (nbb[1] >= 0 ? nbb[1] : cb);
+        T ex = eta[qx];
+        eca = s == 0 ? e01.x : e01.y;
+        ecb = s == 0 ? e23.x : e23.y;
+        ena[0] = s == 0 ? ex : e01.x;
+        ena[1] = s == 0 ? e01.y : e23.x;
+        enb[0] = s == 0 ? e01.y : e23.x;
+        enb[1] = s == 0 ? e23.y : ex;
+#pragma unroll
+        for (int f = 2; f < 6; f++) {
+            ena[f] = eta[nba[f] >= 0 ? nba[f] : ca];
+            enb[f] = eta[nbb[f] >= 0 ? nbb[f] : cb];
+        }
+    } else {
+#pragma unroll
+        for (int f = 0; f < 6; f++) ena[f] = enb[f] = (T)0;
+    }
+    uint8_t fla = L.flag[ca], flb = L.flag[cb];
+    // the rows of regular cells from the loaded viscosities (those of covered and cut cells are
+    // formed but never stored)
+    T Ka[6], Kb[6];
+    T da = rb0_regular_row<T, VISC>(L, nba, eca, ena, Ka);
+    T db = rb0_regular_row<T, VISC>(L, nbb, ecb, enb, Kb);
+    rb0_apply_row<T, NC>(nba, Ka, da, xa, acca);
+    rb0_apply_row<T, NC>(nbb, Kb, db, xb, accb);
+    bool ua = fla == 2 && da > (T)0, ub = flb == 2 && db > (T)0;
+    if (ua && ub) {
+#pragma unroll
+        for (int m = 0; m < NC; m++) {
+            double2 o;
+            o.x = acca[m];
+            o.y = accb[m];
+            *reinterpret_cast<double2*>(x + m * N + own) = o;
+        }
+    } else {
+        // a regular cell whose diagonal is not positive is not updated (as in smooth_rb_cell)
+#pragma unroll
+        for (int m = 0; m < NC; m++) {
+            if (ua) x[m * N + own] = acca[m];
+            if (ub) x[m * N + own + 1] = accb[m];
+        }
+    }
 }
 
 template <typename T, typename TC, int NC, int PRO>
@@ -2249,6 +2431,8 @@ Rb0V rb0_view(const Level& L) {
     v.dnxh = fast_div((unsigned)L.grid.n[0] / 2);
     v.N = L.N;
     v.flag = L.flag;
+    v.cut = L.cut;
+    v.ncut = L.ncut;
     v.eta = L.eta;
     v.etaf = L.etaf;
     for (int d = 0; d < 3; d++) v.K[d] = L.K[d];
@@ -2263,11 +2447,27 @@ Rb0V rb0_view(const Level& L) {
     return v;
 }
 
+// one colour's half sweep of level 0: in FP64 with n_x a multiple of 4 the two-cells-per-thread
+// kernel (FP32 pairs are 8 bytes, which the one-cell kernel's loads already match), else the
+// one-cell kernel; the same result either way
+template <typename T>
+void rb_half_sweep(const Rb0V& v, int nc, const T* b, T* x, int col, hipStream_t s) {
+    if constexpr (std::is_same<T, double>::value) {
+        if ((v.grid.n[0] & 3) == 0 && (nc == 3) == (v.sys == EB_SYS_VISC)) {
+            unsigned gp = grid_for(v.N / 4), gc = v.ncut > 0 ? (grid_for(v.ncut) + 7) & ~7u : 0;
+            if (nc == 3) k_smooth_rb_pair<T, 3><<<gc + gp, EB_BLOCK, 0, s>>>(v, b, x, col, gc);
+            else k_smooth_rb_pair<T, 1><<<gc + gp, EB_BLOCK, 0, s>>>(v, b, x, col, gc);
+            return;
+        }
+    }
+    unsigned gb = grid_for(v.N / 2);
+    if (nc == 3) k_smooth_rb<T, 3><<<gb, EB_BLOCK, 0, s>>>(v, b, x, col);
+    else k_smooth_rb<T, 1><<<gb, EB_BLOCK, 0, s>>>(v, b, x, col);
+}
+
 template <typename T>
 void smooth_rb_pass(const Level& L, int nc, const T* b, T* x, int col, hipStream_t s) {
-    unsigned gb = grid_for(L.N / 2);
-    if (nc == 3) k_smooth_rb<T, 3><<<gb, EB_BLOCK, 0, s>>>(rb0_view(L), b, x, col);
-    else k_smooth_rb<T, 1><<<gb, EB_BLOCK, 0, s>>>(rb0_view(L), b, x, col);
+    rb_half_sweep<T>(rb0_view(L), nc, b, x, col, s);
 }
 
 // first level handled by the one-work-group tail: the largest set of coarsest levels whose
@@ -2440,8 +2640,7 @@ void up_leg_rb(const VArgs& a, const Rb0V& v, const GridV& gc, const TC* ec, con
             if (nc == 3) k_smooth_rb_pro<T, TC, 3, PRO_NBR><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, 1, P);
             else k_smooth_rb_pro<T, TC, 1, PRO_NBR><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, 1, P);
         } else {
-            if (nc == 3) k_smooth_rb<T, 3><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, 1);
-            else k_smooth_rb<T, 1><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, 1);
+            rb_half_sweep<T>(v, nc, b, x, 1, a.s);
         }
         if (last && first) {
             if (nc == 3) k_smooth_last_rb_to<T, 3, PRO_OWN, TC, TD><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, x0, P);
@@ -2453,8 +2652,7 @@ void up_leg_rb(const VArgs& a, const Rb0V& v, const GridV& gc, const TC* ec, con
             if (nc == 3) k_smooth_rb_pro<T, TC, 3, PRO_OWN><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, 0, P);
             else k_smooth_rb_pro<T, TC, 1, PRO_OWN><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, 0, P);
         } else {
-            if (nc == 3) k_smooth_rb<T, 3><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, 0);
-            else k_smooth_rb<T, 1><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, 0);
+            rb_half_sweep<T>(v, nc, b, x, 0, a.s);
         }
     }
 }
@@ -2580,6 +2778,8 @@ void finish_operator(Level* lev, int nlev, bool mixed, hipStream_t s) {
 void mg_build_poisson(Level* lev, int nlev, const GeomV& g, double beta, bool mixed,
                       hipStream_t s) {
     lev[0].flag = g.flag;
+    lev[0].cut = g.cut;
+    lev[0].ncut = g.ncut;
     lev[0].eta = nullptr;
     lev[0].sys = EB_SYS_POISSON;
     lev[0].beta = beta;
@@ -2592,6 +2792,8 @@ void mg_build_poisson(Level* lev, int nlev, const GeomV& g, double beta, bool mi
 void mg_build_visc(Level* lev, int nlev, const GeomV& g, double rho, double dt,
                    const double* eta, const double* eta_eb, bool mixed, hipStream_t s) {
     lev[0].flag = g.flag;
+    lev[0].cut = g.cut;
+    lev[0].ncut = g.ncut;
     lev[0].eta = eta;
     lev[0].sys = EB_SYS_VISC;
     lev[0].rho = rho;
