@@ -65,13 +65,19 @@ def smoother_bytes_per_launch(N, ncomp, w):
     return (N // 2) * (3 * ncomp * w + w + 1)
 
 
+# the finest-level viscous smoother per precision: FP64 updates two cells per thread with paired
+# loads, FP32 one cell per thread
+SMOOTHER_KERNEL = {"fp64": "k_smooth_rb_pair", "mixed": "k_smooth_rb"}
+
+
 def counted_traffic(tag):
     """HBM bytes per launch of the finest-level smoother from the committed byte-counter summary
     (profiles/), or None when there is none for this precision or the kernel source has changed
     since the counters were taken."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", f"k_smooth_rb_sphere128_{tag}_counters.md")
+    kernel = SMOOTHER_KERNEL[tag]
+    path = os.path.join(ROOT, "profiles", f"{kernel}_sphere128_{tag}_counters.md")
     if not os.path.exists(path):
         return None
     fields = {}
@@ -442,7 +448,8 @@ def main():
         for _ in range(args.sweeps):
             dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"kernel": "k_smooth_rb<3> finest level", "avg_ms": ms,
+        tag = "mixed" if prec == api.EB_MIXED else "fp64"
+        print(json.dumps({"kernel": SMOOTHER_KERNEL[tag] + "<3> finest level", "avg_ms": ms,
                           "copy_bytes_each_way": src.numel() * 8}))
         return
 
@@ -464,7 +471,8 @@ def main():
     copy_gbs = copy_bandwidth(main_run["ctx"], torch)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_smooth_rb (finest level, 3 components, one colour)",
+                "kernel": SMOOTHER_KERNEL["fp64" if prec == api.EB_FP64 else "mixed"]
+                + " (finest level, 3 components, one colour)",
                 "kernel_ms": round(ms_k, 5), "bytes_per_launch": int(algo),
                 "device_copy_gbs": round(copy_gbs, 1),
                 "frac_of_device_copy": round(achieved / copy_gbs, 4),

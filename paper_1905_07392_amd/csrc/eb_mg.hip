@@ -858,9 +858,11 @@ __device__ __forceinline__ void rb0_apply_row(const long nb[6], const T K[6], T 
 // dispatched first and spread over the XCDs by the hardware's round-robin, so their longer
 // dependent loads neither trail the launch nor load the few XCDs whose slabs hold the body.
 // Three components are the viscous system and one the Poisson system (the launch checks this
-// against L.sys).  Four waves per SIMD (at most 128 VGPRs) keep enough loads in flight.
+// against L.sys).  Four waves per SIMD (at most 128 VGPRs) keep enough loads in flight; blocks
+// of one wave (PAIR_BLOCK) measured faster than 128-, 256- or 512-thread blocks.
+constexpr int PAIR_BLOCK = 64;
 template <typename T, int NC>
-__global__ void __launch_bounds__(EB_BLOCK, 4)
+__global__ void __launch_bounds__(PAIR_BLOCK, 4)
     k_smooth_rb_pair(Rb0V L, const T* __restrict__ b, T* __restrict__ x, int col, unsigned ncb) {
     static_assert(sizeof(T) == 8, "pairs of FP64 values");
     constexpr bool VISC = NC == 3;
@@ -2454,9 +2456,12 @@ template <typename T>
 void rb_half_sweep(const Rb0V& v, int nc, const T* b, T* x, int col, hipStream_t s) {
     if constexpr (std::is_same<T, double>::value) {
         if ((v.grid.n[0] & 3) == 0 && (nc == 3) == (v.sys == EB_SYS_VISC)) {
-            unsigned gp = grid_for(v.N / 4), gc = v.ncut > 0 ? (grid_for(v.ncut) + 7) & ~7u : 0;
-            if (nc == 3) k_smooth_rb_pair<T, 3><<<gc + gp, EB_BLOCK, 0, s>>>(v, b, x, col, gc);
-            else k_smooth_rb_pair<T, 1><<<gc + gp, EB_BLOCK, 0, s>>>(v, b, x, col, gc);
+            unsigned gp = grid_for(v.N / 4, PAIR_BLOCK);
+            unsigned gc = v.ncut > 0 ? (grid_for(v.ncut, PAIR_BLOCK) + 7) & ~7u : 0;
+            if (nc == 3)
+                k_smooth_rb_pair<T, 3><<<gc + gp, PAIR_BLOCK, 0, s>>>(v, b, x, col, gc);
+            else
+                k_smooth_rb_pair<T, 1><<<gc + gp, PAIR_BLOCK, 0, s>>>(v, b, x, col, gc);
             return;
         }
     }
