@@ -1000,34 +1000,36 @@ __global__ void __launch_bounds__(EB_BLOCK)
 
 // k_smooth_first_rb fused with the conversion of the right-hand side: reads b in natural
 // order (FP64), stores its colour-split copy (precision T) and the first iterate's colour 0;
-// colour 1 is left to the colour-1 half sweep that follows (PRO_ZERO: it writes every cell)
+// colour 1 is left to the colour-1 half sweep that follows (PRO_ZERO: it writes every cell).
+// Thread t takes slot t of both colours: the natural cells 2t and 2t + 1 (one of each colour,
+// n_x being even), read as one 16-byte pair, so a wave reads whole natural lines once.
 template <typename T, int NC>
 __global__ void k_smooth_first_rb_from(Rb0V L, const double* __restrict__ bnat,
                                        T* __restrict__ b, T* __restrict__ x) {
     if (L.gate && *L.gate) return;
     long N = L.N, Nh = N >> 1;
-    long u = xcd_block() * (long)blockDim.x + threadIdx.x;
-    if (u >= N) return;
-    int col = u >= Nh ? 1 : 0;
-    long t = u - col * Nh;
+    long t = xcd_block() * (long)blockDim.x + threadIdx.x;
+    if (t >= Nh) return;
     int i, j, k;
-    rb_cell(L, (unsigned)t, col, i, j, k);
-    long c = cell_index(L.grid, i, j, k);
-    T bv[NC];
+    rb_cell(L, (unsigned)t, 0, i, j, k);
+    long c = cell_index(L.grid, i, j, k);  // the colour-0 cell: 2t or 2t + 1
+    bool odd = (c & 1) != 0;
+    T b0[NC], b1[NC];
 #pragma unroll
-    for (int m = 0; m < NC; m++) bv[m] = (T)bnat[m * N + c];
-    bool upd = false;
-    T Dd = (T)1;
-    if (col == 0) {
-        T K[6], xn[6][NC];
-        long nb[6];
-        upd = rb0_row_ld<T, NC, false>(L, c, i, j, k, x, K, nb, Dd, xn);
+    for (int m = 0; m < NC; m++) {
+        double2 q = *reinterpret_cast<const double2*>(bnat + m * N + 2 * t);
+        b0[m] = (T)(odd ? q.y : q.x);
+        b1[m] = (T)(odd ? q.x : q.y);
     }
+    T K[6], xn[6][NC], Dd = (T)1;
+    long nb[6];
+    bool upd = rb0_row_ld<T, NC, false>(L, c, i, j, k, x, K, nb, Dd, xn);
     T inv = upd ? (T)1 / Dd : (T)0;
 #pragma unroll
     for (int m = 0; m < NC; m++) {
-        b[m * N + u] = bv[m];
-        if (col == 0) x[m * N + u] = upd ? bv[m] * inv : (T)0;
+        b[m * N + t] = b0[m];
+        b[m * N + Nh + t] = b1[m];
+        x[m * N + t] = upd ? b0[m] * inv : (T)0;
     }
 }
 
@@ -1246,11 +1248,12 @@ __global__ void k_prolong_rb(Rb0V L, GridV gc, const TC* __restrict__ ec, TF* __
     if (L.gate && *L.gate) return;
     long N = L.N, Nh = N >> 1;
     long Nc = (long)gc.n[0] * gc.n[1] * gc.n[2];
-    long u = xcd_block() * (long)blockDim.x + threadIdx.x;
-    if (u >= N) return;
-    int col = u >= Nh ? 1 : 0;
+    long v = xcd_block() * (long)blockDim.x + threadIdx.x;
+    if (v >= N) return;
+    int col = (int)(v & 1);  // threads 2t, 2t + 1: slot t of colours 0 and 1
+    long u = (long)col * Nh + (v >> 1);
     int i, j, k;
-    rb_cell(L, (unsigned)(u - col * Nh), col, i, j, k);
+    rb_cell(L, (unsigned)(v >> 1), col, i, j, k);
     long f = cell_index(L.grid, i, j, k);
     if (L.flag[f] == 0) return;
     long c = cell_index(gc, i >> 1, j >> 1, k >> 1);
@@ -1264,11 +1267,12 @@ __global__ void k_to_rb(GridV g, long N, const TS* __restrict__ a, TD* __restric
                         const int* gate) {
     if (gate && *gate) return;
     long Nh = N >> 1;
-    long u = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    if (u >= N) return;
-    int col = u >= Nh ? 1 : 0;
+    long v = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (v >= N) return;
+    int col = (int)(v & 1);  // threads 2t, 2t + 1: slot t of colours 0 and 1 (whole natural lines)
+    long u = (long)col * Nh + (v >> 1);
     int i, j, k;
-    rb_cell(g, (unsigned)(u - col * Nh), col, i, j, k);
+    rb_cell(g, (unsigned)(v >> 1), col, i, j, k);
     long c = cell_index(g, i, j, k);
 #pragma unroll
     for (int m = 0; m < NC; m++) r[m * N + u] = (TD)a[m * N + c];
@@ -2680,11 +2684,12 @@ void vcycle_level0_rb(const VArgs& a, const double* b0, TD* x0, T* b, T* x) {
     }
     for (int t = 0; t < a.nu1; t++) {
         if (t == 0) {
-            if (nc == 3) k_smooth_first_rb_from<T, 3><<<g, EB_BLOCK, 0, a.s>>>(v, b0, b, x);
-            else k_smooth_first_rb_from<T, 1><<<g, EB_BLOCK, 0, a.s>>>(v, b0, b, x);
+            // one thread per slot of both colours
+            unsigned gh = grid_for(L.N / 2);
+            if (nc == 3) k_smooth_first_rb_from<T, 3><<<gh, EB_BLOCK, 0, a.s>>>(v, b0, b, x);
+            else k_smooth_first_rb_from<T, 1><<<gh, EB_BLOCK, 0, a.s>>>(v, b0, b, x);
             // colour 1 of the first iterate is still unset: this sweep writes all of it
             ProV<T> Z{L.grid, nullptr};
-            unsigned gh = grid_for(L.N / 2);
             if (nc == 3) k_smooth_rb_pro<T, T, 3, PRO_ZERO><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, 1, Z);
             else k_smooth_rb_pro<T, T, 1, PRO_ZERO><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, 1, Z);
             continue;

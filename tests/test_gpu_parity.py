@@ -236,6 +236,27 @@ def test_vcycle_deeper_hierarchies(n, nu1, nu2):
     assert e1 <= 1e-12 and max(e3) <= 1e-12, (e1, e3)
 
 
+def test_vcycle_odd_half_rows():
+    """A box whose n_x is not a multiple of 4 (30 x 32 x 28, half rows of 15 cells): the FP64
+    finest level then takes the one-cell smoother instead of the two-cells-per-thread one, which
+    every other box here uses.  V-cycles of both systems against the oracle at 1e-12."""
+    P = Pair(I.sphere_n(32).replace(name="sphere30x32x28", n=(30, 32, 28)))
+    print("[parity] vcycle 30x32x28 (one-cell smoother)", flush=True)
+    r = I.random_field(P.og.shape, 43) * P.open
+    ref = P.og.vcycle(0, r, P.oopts, beta=0.37)
+    got = P.api.eb_mg_vcycle(P.ctx, P.api.EB_SYS_POISSON, P.dev(r), P.opts, beta=0.37)
+    e1 = rel_l2(cpu(got), ref, P.open)
+    u0, _ = P.O.prepare_state(P.w, P.og, P.oopts)
+    eta, eta_eb = P.og.viscosity(u0, P.orheo)
+    r3 = I.random_field((3,) + P.og.shape, 44) * P.open
+    ref3 = P.og.vcycle(1, r3, P.oopts, rho=P.w.rho, dt=P.w.dt, eta=eta, eta_eb=eta_eb)
+    got3 = P.api.eb_mg_vcycle(P.ctx, P.api.EB_SYS_VISC, P.dev(r3), P.opts, rho=P.w.rho,
+                              dt=P.w.dt, eta=P.dev(eta), eta_eb=P.dev(eta_eb))
+    e3 = [rel_l2(cpu(got3)[j], ref3[j], P.open) for j in range(3)]
+    print(f"[parity] vcycle 30x32x28: poisson {e1:.2e} visc {e3}", flush=True)
+    assert e1 <= 1e-12 and max(e3) <= 1e-12, (e1, e3)
+
+
 def test_fp32_sweep_needs_an_fp32_finest_level(s32):
     """A mixed hierarchy keeps levels below 64^3 cells in FP64, so on the 32^3 box the FP32
     sweep entry point has no FP32 operator to run and says so."""
