@@ -859,11 +859,16 @@ __device__ __forceinline__ void rb0_apply_row(const long nb[6], const T K[6], T 
 // dependent loads neither trail the launch nor load the few XCDs whose slabs hold the body.
 // Three components are the viscous system and one the Poisson system (the launch checks this
 // against L.sys).  Four waves per SIMD (at most 128 VGPRs) keep enough loads in flight; blocks
-// of one wave (PAIR_BLOCK) measured faster than 128-, 256- or 512-thread blocks.
+// of one wave (PAIR_BLOCK) measured faster than 128-, 256- or 512-thread blocks.  PRO as in
+// smooth_rb_cell: PRO_NONE, or PRO_ZERO (a cell that is not updated is set to 0; this half
+// sweep writes every cell of its colour).  (PRO_OWN stays with k_smooth_rb_pro: its rare
+// non-updated regular cell needs the cell's own value and the coarse correction, which push this
+// kernel past 128 VGPRs.)
 constexpr int PAIR_BLOCK = 64;
-template <typename T, int NC>
+template <typename T, int NC, int PRO = PRO_NONE>
 __global__ void __launch_bounds__(PAIR_BLOCK, 4)
     k_smooth_rb_pair(Rb0V L, const T* __restrict__ b, T* __restrict__ x, int col, unsigned ncb) {
+    static_assert(PRO == PRO_NONE || PRO == PRO_ZERO, "no prolongation in the pair kernel");
     static_assert(sizeof(T) == 8, "pairs of FP64 values");
     constexpr bool VISC = NC == 3;
     if (L.gate && *L.gate) return;
@@ -875,7 +880,7 @@ __global__ void __launch_bounds__(PAIR_BLOCK, 4)
         int i, j, k;
         rb_coords(L, c, i, j, k);
         if (((i + j + k) & 1) != col) return;
-        smooth_rb_cell<T, NC, PRO_NONE, T>(L, b, x, col, c >> 1, nullptr);
+        smooth_rb_cell<T, NC, PRO, T>(L, b, x, col, c >> 1, nullptr);
         return;
     }
     // the pair blocks, mapped to tiles per XCD as xcd_block does (ncb is a multiple of 8, so
@@ -971,6 +976,31 @@ __global__ void __launch_bounds__(PAIR_BLOCK, 4)
     rb0_apply_row<T, NC>(nba, Ka, da, xa, acca);
     rb0_apply_row<T, NC>(nbb, Kb, db, xb, accb);
     bool ua = fla == 2 && da > (T)0, ub = flb == 2 && db > (T)0;
+    if (PRO == PRO_ZERO) {
+        // every cell that is not cut is written: its update, or 0
+        bool wa = fla != 1, wb = flb != 1;
+#pragma unroll
+        for (int m = 0; m < NC; m++) {
+            acca[m] = ua ? acca[m] : (T)0;
+            accb[m] = ub ? accb[m] : (T)0;
+        }
+        if (wa && wb) {
+#pragma unroll
+            for (int m = 0; m < NC; m++) {
+                double2 o;
+                o.x = acca[m];
+                o.y = accb[m];
+                *reinterpret_cast<double2*>(x + m * N + own) = o;
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < NC; m++) {
+                if (wa) x[m * N + own] = acca[m];
+                if (wb) x[m * N + own + 1] = accb[m];
+            }
+        }
+        return;
+    }
     if (ua && ub) {
 #pragma unroll
         for (int m = 0; m < NC; m++) {
@@ -2474,6 +2504,27 @@ void rb_half_sweep(const Rb0V& v, int nc, const T* b, T* x, int col, hipStream_t
     else k_smooth_rb<T, 1><<<gb, EB_BLOCK, 0, s>>>(v, b, x, col);
 }
 
+// a half sweep of level 0 with a PRO variant: for PRO_ZERO the two-cells-per-thread kernel
+// where rb_half_sweep takes it, else k_smooth_rb_pro
+template <typename T, typename TC, int PRO>
+void rb_half_sweep_pro(const Rb0V& v, int nc, const T* b, T* x, int col, ProV<TC> P,
+                       hipStream_t s) {
+    if constexpr (std::is_same<T, double>::value && PRO == PRO_ZERO) {
+        if ((v.grid.n[0] & 3) == 0 && (nc == 3) == (v.sys == EB_SYS_VISC)) {
+            unsigned gp = grid_for(v.N / 4, PAIR_BLOCK);
+            unsigned gc = v.ncut > 0 ? (grid_for(v.ncut, PAIR_BLOCK) + 7) & ~7u : 0;
+            if (nc == 3)
+                k_smooth_rb_pair<T, 3, PRO><<<gc + gp, PAIR_BLOCK, 0, s>>>(v, b, x, col, gc);
+            else
+                k_smooth_rb_pair<T, 1, PRO><<<gc + gp, PAIR_BLOCK, 0, s>>>(v, b, x, col, gc);
+            return;
+        }
+    }
+    unsigned gh = grid_for(v.N / 2);
+    if (nc == 3) k_smooth_rb_pro<T, TC, 3, PRO><<<gh, EB_BLOCK, 0, s>>>(v, b, x, col, P);
+    else k_smooth_rb_pro<T, TC, 1, PRO><<<gh, EB_BLOCK, 0, s>>>(v, b, x, col, P);
+}
+
 template <typename T>
 void smooth_rb_pass(const Level& L, int nc, const T* b, T* x, int col, hipStream_t s) {
     rb_half_sweep<T>(rb0_view(L), nc, b, x, col, s);
@@ -2658,8 +2709,7 @@ void up_leg_rb(const VArgs& a, const Rb0V& v, const GridV& gc, const TC* ec, con
             if (nc == 3) k_smooth_last_rb_to<T, 3, PRO_NONE, TC, TD><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, x0, none);
             else k_smooth_last_rb_to<T, 1, PRO_NONE, TC, TD><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, x0, none);
         } else if (first) {
-            if (nc == 3) k_smooth_rb_pro<T, TC, 3, PRO_OWN><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, 0, P);
-            else k_smooth_rb_pro<T, TC, 1, PRO_OWN><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, 0, P);
+            rb_half_sweep_pro<T, TC, PRO_OWN>(v, nc, b, x, 0, P, a.s);
         } else {
             rb_half_sweep<T>(v, nc, b, x, 0, a.s);
         }
@@ -2690,8 +2740,7 @@ void vcycle_level0_rb(const VArgs& a, const double* b0, TD* x0, T* b, T* x) {
             else k_smooth_first_rb_from<T, 1><<<gh, EB_BLOCK, 0, a.s>>>(v, b0, b, x);
             // colour 1 of the first iterate is still unset: this sweep writes all of it
             ProV<T> Z{L.grid, nullptr};
-            if (nc == 3) k_smooth_rb_pro<T, T, 3, PRO_ZERO><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, 1, Z);
-            else k_smooth_rb_pro<T, T, 1, PRO_ZERO><<<gh, EB_BLOCK, 0, a.s>>>(v, b, x, 1, Z);
+            rb_half_sweep_pro<T, T, PRO_ZERO>(v, nc, b, x, 1, Z, a.s);
             continue;
         }
         smooth_rb_pass<T>(L, nc, b, x, 0, a.s);
