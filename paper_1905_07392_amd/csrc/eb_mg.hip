@@ -1942,32 +1942,45 @@ __global__ void k_tail_pack(PackArgs P) {
 // ------------------------------------------------------------------------------------------
 // exact EB viscous Helmholtz operator (Eq. implicit-viscous with the wall flux of Eq. dudn)
 // ------------------------------------------------------------------------------------------
-// Every load of a cell (flag, its velocity, the six neighbours' velocities and viscosities) is
-// issued before the first is needed; the arithmetic and its order are unchanged.
-// kin = dt/(2 h^2) and kwall = 2 dt/h^2 as the level-0 smoother forms them (regular cells take
-// K = kin (eta_c + eta_n) inside and kwall eta_c on a domain wall, with no division per face);
-// dnx, dny divide by the extents
-// (TU: the input's type; FP32 input is widened exactly)
+// the operator row of a regular cell (volume fraction and all six apertures 1, no wall flux)
+// from its loaded velocity, neighbours and viscosities; in[f]: a neighbour across face f
+__device__ __forceinline__ void visc_regular_row(const GeomV& g, double rho, double kin,
+                                                 double kwall, int homog, double ec,
+                                                 const double en[6], const double uc[3],
+                                                 const double un[6][3], const bool in[6],
+                                                 double acc[3]) {
+    for (int m = 0; m < 3; m++) acc[m] = 1.0 * rho * uc[m];
+#pragma unroll
+    for (int d = 0; d < 3; d++)
+#pragma unroll
+        for (int side = 0; side < 2; side++) {
+            int f = 2 * d + side;
+            if (in[f]) {
+                double K = kin * (ec + en[f]);
+                for (int m = 0; m < 3; m++) acc[m] -= K * (un[f][m] - uc[m]);
+            } else {
+                double K = kwall * ec;
+                for (int m = 0; m < 3; m++) {
+                    double uw = homog ? 0.0 : g.wall[2 * d + side][m];
+                    acc[m] -= K * (uw - uc[m]);
+                }
+            }
+        }
+}
+
+// One cell c = (i, j, k) of the operator, every load (flag, its velocity, the six neighbours'
+// velocities and viscosities) issued before the first is needed.  kin = dt/(2 h^2) and kwall =
+// 2 dt/h^2 as the level-0 smoother forms them (regular cells take K = kin (eta_c + eta_n) inside
+// and kwall eta_c on a domain wall, with no division per face).  TU: the input's type; FP32
+// input is widened exactly.
 template <typename TU>
-__global__ void __launch_bounds__(EB_BLOCK) k_visc_apply(GeomV g, double rho, double dt,
-                                                         double kin, double kwall, FastDiv dnx,
-                                                         FastDiv dny,
-                                                         const double* __restrict__ eta,
-                             const double* __restrict__ eta_eb, const TU* __restrict__ u,
-                             double* __restrict__ out, int homog, const int* gate) {
-    if (gate && *gate) return;
+__device__ __forceinline__ void visc_apply_cell(const GeomV& g, double rho, double dt,
+                                                double kin, double kwall,
+                                                const double* __restrict__ eta,
+                                                const TU* __restrict__ u,
+                                                double* __restrict__ out, int homog, long c,
+                                                int i, int j, int k) {
     long N = g.N;
-    long c = xcd_block() * (long)blockDim.x + threadIdx.x;
-    if (c >= N) return;
-    int i, j, k;
-    {
-        unsigned cu = (unsigned)c;
-        unsigned t = fdiv(cu, dnx);
-        i = (int)(cu - t * dnx.d);
-        unsigned k2 = fdiv(t, dny);
-        j = (int)(t - k2 * dny.d);
-        k = (int)k2;
-    }
     long nb[6];
 #pragma unroll
     for (int d = 0; d < 3; d++)
@@ -1997,24 +2010,10 @@ __global__ void __launch_bounds__(EB_BLOCK) k_visc_apply(GeomV g, double rho, do
     double h2 = g.grid.h * g.grid.h;
     double acc[3];
     if (fl == 2) {
-        // regular cell: volume fraction and all six apertures are 1, no wall flux
-        for (int m = 0; m < 3; m++) acc[m] = 1.0 * rho * uc[m];
+        bool in[6];
 #pragma unroll
-        for (int d = 0; d < 3; d++)
-#pragma unroll
-            for (int side = 0; side < 2; side++) {
-                int f = 2 * d + side;
-                if (nb[f] >= 0) {
-                    double K = kin * (ec + en[f]);
-                    for (int m = 0; m < 3; m++) acc[m] -= K * (un[f][m] - uc[m]);
-                } else {
-                    double K = kwall * ec;
-                    for (int m = 0; m < 3; m++) {
-                        double uw = homog ? 0.0 : g.wall[2 * d + side][m];
-                        acc[m] -= K * (uw - uc[m]);
-                    }
-                }
-            }
+        for (int f = 0; f < 6; f++) in[f] = nb[f] >= 0;
+        visc_regular_row(g, rho, kin, kwall, homog, ec, en, uc, un, in, acc);
         for (int m = 0; m < 3; m++) out[m * N + c] = acc[m];
         return;
     }
@@ -2041,6 +2040,141 @@ __global__ void __launch_bounds__(EB_BLOCK) k_visc_apply(GeomV g, double rho, do
             }
         }
     for (int m = 0; m < 3; m++) out[m * N + c] = acc[m];
+}
+
+// one cell per thread (any alignment of eta, u and out)
+template <typename TU>
+__global__ void __launch_bounds__(EB_BLOCK)
+    k_visc_apply_one(GeomV g, double rho, double dt, double kin, double kwall, FastDiv dnx,
+                     FastDiv dny, const double* __restrict__ eta, const TU* __restrict__ u,
+                     double* __restrict__ out, int homog, const int* gate) {
+    if (gate && *gate) return;
+    long c = xcd_block() * (long)blockDim.x + threadIdx.x;
+    if (c >= g.N) return;
+    unsigned cu = (unsigned)c;
+    unsigned t = fdiv(cu, dnx);
+    unsigned k2 = fdiv(t, dny);
+    visc_apply_cell<TU>(g, rho, dt, kin, kwall, eta, u, out, homog, c, (int)(cu - t * dnx.d),
+                        (int)(t - k2 * dny.d), (int)k2);
+}
+
+template <typename TU> struct Two;
+template <> struct Two<double> { using t = double2; };
+template <> struct Two<float> { using t = float2; };
+
+// The operator on two neighbouring cells a = (i0, j, k) and b = (i0 + 1, j, k), i0 even, per
+// thread: a's upper and b's lower x neighbour are each other, the two outer x neighbours are
+// lone loads, and each y and z face's neighbours of both cells are one aligned pair (16 bytes in
+// FP64), as are the two cells' own values and viscosities, so a regular cell needs about half
+// the load instructions of the one-cell form.  The first ncb blocks (a multiple of 8) take one
+// cut cell per thread through visc_apply_cell; the pair blocks write regular (and covered) cells
+// only.  Results are visc_apply_cell's, bit for bit.  dnx, dny divide by the extents.  Used for
+// FP32 input (124 VGPRs); with FP64 input the loaded values need more than 128 VGPRs (four waves
+// per SIMD) and spill, so FP64 input takes the one-cell kernel.
+template <typename TU>
+__global__ void __launch_bounds__(PAIR_BLOCK, 4)
+    k_visc_apply(GeomV g, double rho, double dt, double kin, double kwall, FastDiv dnx,
+                 FastDiv dny, const double* __restrict__ eta, const TU* __restrict__ u,
+                 double* __restrict__ out, int homog, const int* gate, unsigned ncb) {
+    using P2 = typename Two<TU>::t;
+    if (gate && *gate) return;
+    long N = g.N;
+    if (blockIdx.x < ncb) {
+        long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+        if (q >= g.ncut) return;
+        long c = g.cut[q];
+        unsigned cu = (unsigned)c;
+        unsigned t = fdiv(cu, dnx);
+        unsigned k2 = fdiv(t, dny);
+        visc_apply_cell<TU>(g, rho, dt, kin, kwall, eta, u, out, homog, c,
+                            (int)(cu - t * dnx.d), (int)(t - k2 * dny.d), (int)k2);
+        return;
+    }
+    unsigned npb = gridDim.x - ncb, v = blockIdx.x - ncb;
+    unsigned tile = (v & 7) * (npb >> 3) + ((v & 7) < (npb & 7) ? (v & 7) : (npb & 7)) + (v >> 3);
+    long p = tile * (long)blockDim.x + threadIdx.x;
+    if (p >= (N >> 1)) return;
+    long ca = 2 * p;
+    int i, j, k;
+    {
+        unsigned cu = (unsigned)ca;
+        unsigned t = fdiv(cu, dnx);
+        i = (int)(cu - t * dnx.d);
+        unsigned k2 = fdiv(t, dny);
+        j = (int)(t - k2 * dny.d);
+        k = (int)k2;
+    }
+    long nba[6], nbb[6];
+#pragma unroll
+    for (int d = 0; d < 3; d++)
+#pragma unroll
+        for (int side = 0; side < 2; side++) {
+            nba[2 * d + side] = cell_step(g.grid, ca, i, j, k, d, side);
+            nbb[2 * d + side] = cell_step(g.grid, ca + 1, i + 1, j, k, d, side);
+        }
+    uint8_t fla = g.flag[ca], flb = g.flag[ca + 1];
+    long qxa = nba[0] >= 0 ? nba[0] : ca, qxb = nbb[1] >= 0 ? nbb[1] : ca + 1;
+    long qy[2], qz[2];  // the even cell of each y and z neighbour pair (a's neighbour)
+#pragma unroll
+    for (int side = 0; side < 2; side++) {
+        qy[side] = nba[2 + side] >= 0 ? nba[2 + side] : ca;
+        qz[side] = nba[4 + side] >= 0 ? nba[4 + side] : ca;
+    }
+    double uca[3], ucb[3], una[6][3], unb[6][3];
+#pragma unroll
+    for (int m = 0; m < 3; m++) {
+        P2 o = *reinterpret_cast<const P2*>(u + m * N + ca);
+        uca[m] = (double)o.x;
+        ucb[m] = (double)o.y;
+        una[0][m] = (double)u[m * N + qxa];
+        unb[1][m] = (double)u[m * N + qxb];
+#pragma unroll
+        for (int side = 0; side < 2; side++) {
+            P2 y2 = *reinterpret_cast<const P2*>(u + m * N + qy[side]);
+            P2 z2 = *reinterpret_cast<const P2*>(u + m * N + qz[side]);
+            una[2 + side][m] = (double)y2.x;
+            unb[2 + side][m] = (double)y2.y;
+            una[4 + side][m] = (double)z2.x;
+            unb[4 + side][m] = (double)z2.y;
+        }
+        una[1][m] = ucb[m];
+        unb[0][m] = uca[m];
+    }
+    double ena[6], enb[6];
+    double2 e2 = *reinterpret_cast<const double2*>(eta + ca);
+    double eca = e2.x, ecb = e2.y;
+    ena[0] = eta[qxa];
+    enb[1] = eta[qxb];
+    ena[1] = ecb;
+    enb[0] = eca;
+#pragma unroll
+    for (int side = 0; side < 2; side++) {
+        double2 y2 = *reinterpret_cast<const double2*>(eta + qy[side]);
+        double2 z2 = *reinterpret_cast<const double2*>(eta + qz[side]);
+        ena[2 + side] = y2.x;
+        enb[2 + side] = y2.y;
+        ena[4 + side] = z2.x;
+        enb[4 + side] = z2.y;
+    }
+    bool ina[6], inb[6];
+#pragma unroll
+    for (int f = 0; f < 6; f++) {
+        ina[f] = nba[f] >= 0;
+        inb[f] = nbb[f] >= 0;
+    }
+    // one cell after the other (their values die sooner); covered cells are 0, cut cells the
+    // first blocks'
+    double acc[3];
+    visc_regular_row(g, rho, kin, kwall, homog, eca, ena, uca, una, ina, acc);
+    if (fla != 1) {
+#pragma unroll
+        for (int m = 0; m < 3; m++) out[m * N + ca] = fla == 0 ? 0.0 : acc[m];
+    }
+    visc_regular_row(g, rho, kin, kwall, homog, ecb, enb, ucb, unb, inb, acc);
+    if (flb != 1) {
+#pragma unroll
+        for (int m = 0; m < 3; m++) out[m * N + ca + 1] = flb == 0 ? 0.0 : acc[m];
+    }
 }
 
 // the wall-flux term of the cut-cell rows, added after k_visc_apply (one thread per cut cell,
@@ -2940,10 +3074,22 @@ void op_visc_apply_t(const GeomV& g, double rho, double dt, const double* eta,
                      hipStream_t s, const int* gate) {
     double h2 = g.grid.h * g.grid.h;
     double kin = dt * 0.5 / h2, kwall = 2.0 * dt / h2;
-    k_visc_apply<TU><<<grid_for(g.N), EB_BLOCK, 0, s>>>(g, rho, dt, kin, kwall,
-                                                        fast_div((unsigned)g.grid.n[0]),
-                                                        fast_div((unsigned)g.grid.n[1]), eta,
-                                                        eta_eb, u, out, homogeneous, gate);
+    FastDiv dnx = fast_div((unsigned)g.grid.n[0]), dny = fast_div((unsigned)g.grid.n[1]);
+    bool pair = false;
+    if constexpr (std::is_same<TU, float>::value) {
+        // the pair kernel (FP32 input) reads eta and u in aligned pairs
+        auto al = [](const void* q, size_t a) { return reinterpret_cast<uintptr_t>(q) % a == 0; };
+        if (al(eta, 16) && al(u, 8)) {
+            unsigned gp = grid_for(g.N / 2, PAIR_BLOCK);
+            unsigned gc = g.ncut > 0 ? (grid_for(g.ncut, PAIR_BLOCK) + 7) & ~7u : 0;
+            k_visc_apply<TU><<<gc + gp, PAIR_BLOCK, 0, s>>>(g, rho, dt, kin, kwall, dnx, dny,
+                                                            eta, u, out, homogeneous, gate, gc);
+            pair = true;
+        }
+    }
+    if (!pair)
+        k_visc_apply_one<TU><<<grid_for(g.N), EB_BLOCK, 0, s>>>(g, rho, dt, kin, kwall, dnx, dny,
+                                                               eta, u, out, homogeneous, gate);
     if (g.ncut > 0)
         k_visc_apply_eb<TU><<<grid_for(g.ncut), EB_BLOCK, 0, s>>>(g, dt, eta_eb, u, out,
                                                                 homogeneous, gate);
