@@ -235,7 +235,11 @@ size_t carve(eb_ctx* c, char* base, bool dry) {
         L.b = cv.take<double>(3 * L.N);
         L.xf = cv.take<float>(3 * L.N);
         L.bf = cv.take<float>(3 * L.N);
-        if (l == 0) L.etaf = cv.take<float>(L.N);
+        if (l == 0) {
+            L.etaf = cv.take<float>(L.N);
+            L.etacs = cv.take<double>(L.N);
+            L.flagcs = cv.take<uint8_t>(L.N);
+        }
         for (int d = 0; d < 3; d++) m[d] /= 2;
         h *= 2.0;
     }

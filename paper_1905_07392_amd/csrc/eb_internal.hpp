@@ -257,6 +257,10 @@ struct Level {
     int ncut = 0;
     const double* eta = nullptr;
     float* etaf = nullptr;  // FP32 copy of eta for the mixed-precision smoother
+    // colour-split copies of eta and the flags, made when an operator is built (the FP64
+    // two-cells-per-thread smoother reads them in pairs, like the iterate)
+    double* etacs = nullptr;
+    uint8_t* flagcs = nullptr;
     int sys = 0;  // EB_SYS_POISSON or EB_SYS_VISC
     double rho = 0.0, dt = 0.0, beta = 0.0;
     LevelV<double> v64() const {

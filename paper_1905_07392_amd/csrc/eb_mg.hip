@@ -545,6 +545,8 @@ struct Rb0V {
     const uint8_t* flag;
     const int* cut;  // the cut cells (flag 1), ncut of them
     int ncut;
+    const double* etacs;     // colour-split copies of eta and the flags (may be null)
+    const uint8_t* flagcs;
     const double* eta;
     const float* etaf;
     const double* K[3];
@@ -847,8 +849,8 @@ __device__ __forceinline__ void rb0_apply_row(const long nb[6], const T K[6], T 
 // The other colour's values come in 16-byte pairs: its pair (ih0, ih0 + 1) in the same row holds
 // three of the four x neighbours (the fourth is a lone load, wrapped in the row when periodic),
 // and the pair at ih0 in the neighbour row of each y and z face holds that face's neighbour of
-// both cells.  The viscosities of a, b and their x neighbours are the five natural cells from
-// i_a - 1 to i_a + 3: two aligned pairs and a lone load.  Every load is unconditional (a missing
+// both cells.  The viscosities and flags come from colour-split copies (Level::etacs, flagcs)
+// at the same slots, so they are pairs too.  Every load is unconditional (a missing
 // neighbour loads the cell's own row or value, never used), so a thread waits once.  The first
 // ncb blocks (a multiple of 8) take one cut cell per thread (those of colour col) through the
 // one-cell path (smooth_rb_cell), which loads a cut cell's stored row; the blocks after them
@@ -944,30 +946,35 @@ __global__ void __launch_bounds__(PAIR_BLOCK, 4)
             xb[4 + side][m] = zv.y;
         }
     }
+    // the viscosities from the colour-split copy, at the same slots as the values: the two
+    // cells' own pair, and the other colour's pairs and lone x neighbour
     T eca = (T)0, ecb = (T)0, ena[6], enb[6];
     if (VISC) {
-        const T* eta = L.eta;
-        long e0 = ca - s;  // even: the pairs (e0, e0 + 1) and (e0 + 2, e0 + 3)
-        double2 e01 = *reinterpret_cast<const double2*>(eta + e0);
-        double2 e23 = *reinterpret_cast<const double2*>(eta + e0 + 2);
-        long qx = s == 0 ? (nba[0] >= 0 ? nba[0] : ca) : (nbb[1] >= 0 ? nbb[1] : cb);
-        T ex = eta[qx];
-        eca = s == 0 ? e01.x : e01.y;
-        ecb = s == 0 ? e23.x : e23.y;
-        ena[0] = s == 0 ? ex : e01.x;
-        ena[1] = s == 0 ? e01.y : e23.x;
-        enb[0] = s == 0 ? e01.y : e23.x;
-        enb[1] = s == 0 ? e23.y : ex;
+        const T* eo = L.etacs + (long)(1 - col) * Nh;
+        double2 ec2 = *reinterpret_cast<const double2*>(L.etacs + own);
+        double2 ex2 = *reinterpret_cast<const double2*>(eo + rx + ih0);
+        T ex = eo[rx + xe];
+        eca = ec2.x;
+        ecb = ec2.y;
+        ena[0] = s == 0 ? ex : ex2.x;
+        ena[1] = s == 0 ? ex2.x : ex2.y;
+        enb[0] = s == 0 ? ex2.x : ex2.y;
+        enb[1] = s == 0 ? ex2.y : ex;
 #pragma unroll
-        for (int f = 2; f < 6; f++) {
-            ena[f] = eta[nba[f] >= 0 ? nba[f] : ca];
-            enb[f] = eta[nbb[f] >= 0 ? nbb[f] : cb];
+        for (int side = 0; side < 2; side++) {
+            double2 ey = *reinterpret_cast<const double2*>(eo + ry[side] + ih0);
+            double2 ez = *reinterpret_cast<const double2*>(eo + rz[side] + ih0);
+            ena[2 + side] = ey.x;
+            enb[2 + side] = ey.y;
+            ena[4 + side] = ez.x;
+            enb[4 + side] = ez.y;
         }
     } else {
 #pragma unroll
         for (int f = 0; f < 6; f++) ena[f] = enb[f] = (T)0;
     }
-    uint8_t fla = L.flag[ca], flb = L.flag[cb];
+    uchar2 fl2 = *reinterpret_cast<const uchar2*>(L.flagcs + own);
+    uint8_t fla = fl2.x, flb = fl2.y;
     // the rows of regular cells from the loaded viscosities (those of covered and cut cells are
     // formed but never stored)
     T Ka[6], Kb[6];
@@ -2603,6 +2610,8 @@ Rb0V rb0_view(const Level& L) {
     v.flag = L.flag;
     v.cut = L.cut;
     v.ncut = L.ncut;
+    v.etacs = L.etacs;
+    v.flagcs = L.flagcs;
     v.eta = L.eta;
     v.etaf = L.etaf;
     for (int d = 0; d < 3; d++) v.K[d] = L.K[d];
@@ -2617,13 +2626,20 @@ Rb0V rb0_view(const Level& L) {
     return v;
 }
 
+// whether the two-cells-per-thread kernel can take a level-0 half sweep: n_x a multiple of 4,
+// the component count matching the system, and the colour-split copies made
+bool pair_ok(const Rb0V& v, int nc) {
+    return (v.grid.n[0] & 3) == 0 && (nc == 3) == (v.sys == EB_SYS_VISC) && v.flagcs &&
+           (v.sys != EB_SYS_VISC || v.etacs);
+}
+
 // one colour's half sweep of level 0: in FP64 with n_x a multiple of 4 the two-cells-per-thread
 // kernel (FP32 pairs are 8 bytes, which the one-cell kernel's loads already match), else the
 // one-cell kernel; the same result either way
 template <typename T>
 void rb_half_sweep(const Rb0V& v, int nc, const T* b, T* x, int col, hipStream_t s) {
     if constexpr (std::is_same<T, double>::value) {
-        if ((v.grid.n[0] & 3) == 0 && (nc == 3) == (v.sys == EB_SYS_VISC)) {
+        if (pair_ok(v, nc)) {
             unsigned gp = grid_for(v.N / 4, PAIR_BLOCK);
             unsigned gc = v.ncut > 0 ? (grid_for(v.ncut, PAIR_BLOCK) + 7) & ~7u : 0;
             if (nc == 3)
@@ -2644,7 +2660,7 @@ template <typename T, typename TC, int PRO>
 void rb_half_sweep_pro(const Rb0V& v, int nc, const T* b, T* x, int col, ProV<TC> P,
                        hipStream_t s) {
     if constexpr (std::is_same<T, double>::value && PRO == PRO_ZERO) {
-        if ((v.grid.n[0] & 3) == 0 && (nc == 3) == (v.sys == EB_SYS_VISC)) {
+        if (pair_ok(v, nc)) {
             unsigned gp = grid_for(v.N / 4, PAIR_BLOCK);
             unsigned gc = v.ncut > 0 ? (grid_for(v.ncut, PAIR_BLOCK) + 7) & ~7u : 0;
             if (nc == 3)
@@ -2974,6 +2990,9 @@ void mg_build_poisson(Level* lev, int nlev, const GeomV& g, double beta, bool mi
     lev[0].cut = g.cut;
     lev[0].ncut = g.ncut;
     lev[0].eta = nullptr;
+    if (lev[0].flagcs && (g.grid.n[0] & 1) == 0)
+        k_to_rb<uint8_t, uint8_t, 1><<<grid_for(g.N), EB_BLOCK, 0, s>>>(g.grid, g.N, g.flag,
+                                                                        lev[0].flagcs, nullptr);
     lev[0].sys = EB_SYS_POISSON;
     lev[0].beta = beta;
     for (int d = 0; d < 3; d++)
@@ -2988,6 +3007,12 @@ void mg_build_visc(Level* lev, int nlev, const GeomV& g, double rho, double dt,
     lev[0].cut = g.cut;
     lev[0].ncut = g.ncut;
     lev[0].eta = eta;
+    if (lev[0].flagcs && lev[0].etacs && (g.grid.n[0] & 1) == 0) {
+        k_to_rb<uint8_t, uint8_t, 1><<<grid_for(g.N), EB_BLOCK, 0, s>>>(g.grid, g.N, g.flag,
+                                                                        lev[0].flagcs, nullptr);
+        k_to_rb<double, double, 1><<<grid_for(g.N), EB_BLOCK, 0, s>>>(g.grid, g.N, eta,
+                                                                      lev[0].etacs, nullptr);
+    }
     lev[0].sys = EB_SYS_VISC;
     lev[0].rho = rho;
     lev[0].dt = dt;
