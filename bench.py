@@ -41,7 +41,8 @@ def parse():
                     help="time only the --precision run (default: also the other precision)")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only the smoother timing loop (for the profiler)")
-    ap.add_argument("--sweeps", type=int, default=40)
+    ap.add_argument("--sweeps", type=int, default=100,
+                    help="back-to-back smoother launches timed for the roofline")
     ap.add_argument("--nu", type=int, default=2, help="smoothing pairs before and after")
     ap.add_argument("--nbottom", type=int, default=16)
     ap.add_argument("--adjoint-steps", type=int, default=20,
