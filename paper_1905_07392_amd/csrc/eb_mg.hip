@@ -861,12 +861,11 @@ __device__ __forceinline__ void rb0_apply_row(const long nb[6], const T K[6], T 
 // dependent loads neither trail the launch nor load the few XCDs whose slabs hold the body.
 // Three components are the viscous system and one the Poisson system (the launch checks this
 // against L.sys).  Four waves per SIMD (at most 128 VGPRs) keep enough loads in flight; blocks
-// of one wave (PAIR_BLOCK) measured fastest on the 128^3 sphere (17.5 us against 17.7 and 17.9
-// for 128 and 256 threads, alternated on one GPU).  PRO as in
-// smooth_rb_cell: PRO_NONE, or PRO_ZERO (a cell that is not updated is set to 0; this half
-// sweep writes every cell of its colour).  (PRO_OWN stays with k_smooth_rb_pro: its rare
-// non-updated regular cell needs the cell's own value and the coarse correction, which push this
-// kernel past 128 VGPRs.)
+// of one wave (PAIR_BLOCK) measured fastest on the 128^3 sphere (17.5 us against 17.7 and
+// 17.9 us for 128 and 256 threads, alternated on one GPU).  PRO as in smooth_rb_cell: PRO_NONE,
+// or PRO_ZERO (a cell that is not updated is set to 0; this half sweep writes every cell of its
+// colour).  PRO_OWN stays with k_smooth_rb_pro: its rare non-updated regular cell needs the
+// cell's own value and the coarse correction, which push this kernel past 128 VGPRs.
 constexpr int PAIR_BLOCK = 64;
 template <typename T, int NC, int PRO = PRO_NONE>
 __global__ void __launch_bounds__(PAIR_BLOCK, 4)
