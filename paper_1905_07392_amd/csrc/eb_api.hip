@@ -238,6 +238,7 @@ size_t carve(eb_ctx* c, char* base, bool dry) {
         if (l == 0) {
             L.etaf = cv.take<float>(L.N);
             L.etacs = cv.take<double>(L.N);
+            L.etafcs = cv.take<float>(L.N);
             L.flagcs = cv.take<uint8_t>(L.N);
         }
         for (int d = 0; d < 3; d++) m[d] /= 2;

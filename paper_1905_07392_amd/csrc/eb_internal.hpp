@@ -260,6 +260,7 @@ struct Level {
     // colour-split copies of eta and the flags, made when an operator is built (the FP64
     // two-cells-per-thread smoother reads them in pairs, like the iterate)
     double* etacs = nullptr;
+    float* etafcs = nullptr;  // (mixed builds)
     uint8_t* flagcs = nullptr;
     int sys = 0;  // EB_SYS_POISSON or EB_SYS_VISC
     double rho = 0.0, dt = 0.0, beta = 0.0;

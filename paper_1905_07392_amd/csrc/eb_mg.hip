@@ -545,7 +545,8 @@ struct Rb0V {
     const uint8_t* flag;
     const int* cut;  // the cut cells (flag 1), ncut of them
     int ncut;
-    const double* etacs;     // colour-split copies of eta and the flags (may be null)
+    const double* etacs;     // colour-split copies of eta, its FP32 copy, and the flags
+    const float* etafcs;     // (may be null)
     const uint8_t* flagcs;
     const double* eta;
     const float* etaf;
@@ -1023,6 +1024,206 @@ __global__ void __launch_bounds__(PAIR_BLOCK, 4)
             if (ua) x[m * N + own] = acca[m];
             if (ub) x[m * N + own + 1] = accb[m];
         }
+    }
+}
+
+// rb0_regular_row and rb0_apply_row with the neighbour test given as in[f] (bit for bit the
+// same arithmetic)
+template <typename T, bool VISC>
+__device__ __forceinline__ T rb0_regular_row_in(const Rb0V& L, const bool in[6], T ec,
+                                                const T en[6], T K[6]) {
+    T kin = (T)L.kin, kwall = (T)L.kwall, kp = (T)L.kpois;
+    T sd = VISC ? (T)L.rho : (T)0;
+#pragma unroll
+    for (int f = 0; f < 6; f++) {
+        T kf;
+        if (VISC) kf = in[f] ? kin * (ec + en[f]) : kwall * ec;
+        else kf = in[f] ? kp : (T)0;
+        sd += kf;
+        K[f] = kf;
+    }
+    return sd;
+}
+template <typename T, int NC>
+__device__ __forceinline__ void rb0_apply_row_in(const bool in[6], const T K[6], T dg,
+                                                 const T xn[6][NC], T acc[NC]) {
+#pragma unroll
+    for (int f = 0; f < 6; f++) {
+        T kf = K[f];
+        if (kf == (T)0 || !in[f]) continue;
+#pragma unroll
+        for (int m = 0; m < NC; m++) acc[m] += kf * xn[f][m];
+    }
+    T inv = (T)1 / dg;
+#pragma unroll
+    for (int m = 0; m < NC; m++) acc[m] = acc[m] * inv;
+}
+
+// The FP32 counterpart of k_smooth_rb_pair: four cells of colour col per thread, half indices
+// ih0 .. ih0 + 3 (ih0 a multiple of 4) of one half row, natural cells i_a + 2q (q = 0..3), which
+// needs n_x a multiple of 8.  The other colour's values come in 16-byte quads: its quad
+// (ih0 .. ih0 + 3) in the same row holds seven of the eight x neighbours (the eighth is a lone
+// load, wrapped in the row when periodic), and the quad at ih0 in the neighbour row of each y and
+// z face holds that face's neighbour of the four cells; the viscosities (FP32, the values of
+// Level::etaf) and flags come from the colour-split copies at the same slots.  The four cells
+// share their y and z neighbours' existence; only cell 0's lower and cell 3's upper x face can
+// meet a wall.  Cut cells, covered cells, PRO and the launch as in k_smooth_rb_pair; the rows and
+// updates are the one-cell FP32 kernel's, bit for bit.
+template <int NC, int PRO = PRO_NONE>
+__global__ void __launch_bounds__(PAIR_BLOCK, 4)
+    k_smooth_rb_quad(Rb0V L, const float* __restrict__ b, float* __restrict__ x, int col,
+                     unsigned ncb) {
+    static_assert(PRO == PRO_NONE || PRO == PRO_ZERO, "no prolongation in the quad kernel");
+    using T = float;
+    constexpr bool VISC = NC == 3;
+    if (L.gate && *L.gate) return;
+    long N = L.N, Nh = N >> 1;
+    if (blockIdx.x < ncb) {
+        long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+        if (q >= L.ncut) return;
+        long c = L.cut[q];
+        int i, j, k;
+        rb_coords(L, c, i, j, k);
+        if (((i + j + k) & 1) != col) return;
+        smooth_rb_cell<T, NC, PRO, T>(L, b, x, col, c >> 1, nullptr);
+        return;
+    }
+    unsigned npb = gridDim.x - ncb, u = blockIdx.x - ncb;
+    unsigned tile = (u & 7) * (npb >> 3) + ((u & 7) < (npb & 7) ? (u & 7) : (npb & 7)) + (u >> 3);
+    long p = tile * (long)blockDim.x + threadIdx.x;
+    if (p >= (Nh >> 2)) return;
+    const GridV& g = L.grid;
+    unsigned t = 4u * (unsigned)p;
+    unsigned row = fdiv(t, L.dnxh);
+    int nxh = (int)L.dnxh.d;
+    int ih0 = (int)(t - row * (unsigned)nxh);
+    unsigned kq = fdiv(row, L.dny);
+    int j = (int)(row - kq * L.dny.d), k = (int)kq;
+    int s = (j + k + col) & 1;
+    int ia = 2 * ih0 + s;
+    long c0 = cell_index(g, ia, j, k);
+    // which faces have a neighbour: y and z from cell 0 (the same for all four), x at the ends
+    long nyz[4];
+#pragma unroll
+    for (int side = 0; side < 2; side++) {
+        nyz[side] = cell_step(g, c0, ia, j, k, 1, side);
+        nyz[2 + side] = cell_step(g, c0, ia, j, k, 2, side);
+    }
+    bool in[4][6];
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        in[q][0] = (q > 0 || ia > 0) || g.per[0];
+        in[q][1] = (q < 3 || ia + 6 < g.n[0] - 1) || g.per[0];
+#pragma unroll
+        for (int f = 2; f < 6; f++) in[q][f] = nyz[f - 2] >= 0;
+    }
+    const T* xo = x + (long)(1 - col) * Nh;
+    long own = (long)col * Nh + t;
+    long ry[2], rz[2];
+#pragma unroll
+    for (int side = 0; side < 2; side++) {
+        long q = nyz[side] >= 0 ? nyz[side] : c0;
+        ry[side] = (long)fdiv((unsigned)q, L.dnx) * nxh;
+        q = nyz[2 + side] >= 0 ? nyz[2 + side] : c0;
+        rz[side] = (long)fdiv((unsigned)q, L.dnx) * nxh;
+    }
+    long rx = (long)row * nxh;
+    // the lone x neighbour: cell 0's lower one (s = 0) or cell 3's upper one (s = 1)
+    long xe = s == 0 ? (ih0 > 0 ? ih0 - 1 : nxh - 1) : (ih0 + 4 < nxh ? ih0 + 4 : 0);
+    T acc[4][NC], xn[4][6][NC];
+#pragma unroll
+    for (int m = 0; m < NC; m++) {
+        float4 bv = *reinterpret_cast<const float4*>(b + m * N + own);
+        acc[0][m] = bv.x;
+        acc[1][m] = bv.y;
+        acc[2][m] = bv.z;
+        acc[3][m] = bv.w;
+        float4 xc = *reinterpret_cast<const float4*>(xo + m * N + rx + ih0);
+        T e = xo[m * N + rx + xe];
+        T v[4] = {xc.x, xc.y, xc.z, xc.w};
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            xn[q][0][m] = s == 0 ? (q == 0 ? e : v[q > 0 ? q - 1 : 0]) : v[q];
+            xn[q][1][m] = s == 0 ? v[q] : (q == 3 ? e : v[q < 3 ? q + 1 : 3]);
+        }
+#pragma unroll
+        for (int side = 0; side < 2; side++) {
+            float4 yv = *reinterpret_cast<const float4*>(xo + m * N + ry[side] + ih0);
+            float4 zv = *reinterpret_cast<const float4*>(xo + m * N + rz[side] + ih0);
+            xn[0][2 + side][m] = yv.x;
+            xn[1][2 + side][m] = yv.y;
+            xn[2][2 + side][m] = yv.z;
+            xn[3][2 + side][m] = yv.w;
+            xn[0][4 + side][m] = zv.x;
+            xn[1][4 + side][m] = zv.y;
+            xn[2][4 + side][m] = zv.z;
+            xn[3][4 + side][m] = zv.w;
+        }
+    }
+    T ec[4], en[4][6];
+    if (VISC) {
+        const T* eo = L.etafcs + (long)(1 - col) * Nh;
+        float4 e4 = *reinterpret_cast<const float4*>(L.etafcs + own);
+        float4 ex4 = *reinterpret_cast<const float4*>(eo + rx + ih0);
+        T ex = eo[rx + xe];
+        ec[0] = e4.x;
+        ec[1] = e4.y;
+        ec[2] = e4.z;
+        ec[3] = e4.w;
+        T v[4] = {ex4.x, ex4.y, ex4.z, ex4.w};
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            en[q][0] = s == 0 ? (q == 0 ? ex : v[q > 0 ? q - 1 : 0]) : v[q];
+            en[q][1] = s == 0 ? v[q] : (q == 3 ? ex : v[q < 3 ? q + 1 : 3]);
+        }
+#pragma unroll
+        for (int side = 0; side < 2; side++) {
+            float4 ey = *reinterpret_cast<const float4*>(eo + ry[side] + ih0);
+            float4 ez = *reinterpret_cast<const float4*>(eo + rz[side] + ih0);
+            en[0][2 + side] = ey.x;
+            en[1][2 + side] = ey.y;
+            en[2][2 + side] = ey.z;
+            en[3][2 + side] = ey.w;
+            en[0][4 + side] = ez.x;
+            en[1][4 + side] = ez.y;
+            en[2][4 + side] = ez.z;
+            en[3][4 + side] = ez.w;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            ec[q] = (T)0;
+#pragma unroll
+            for (int f = 0; f < 6; f++) en[q][f] = (T)0;
+        }
+    }
+    unsigned fl4 = *reinterpret_cast<const unsigned*>(L.flagcs + own);
+    bool upd[4], wr[4];
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        unsigned fl = (fl4 >> (8 * q)) & 0xffu;
+        T K[6];
+        T dg = rb0_regular_row_in<T, VISC>(L, in[q], ec[q], en[q], K);
+        rb0_apply_row_in<T, NC>(in[q], K, dg, xn[q], acc[q]);
+        upd[q] = fl == 2 && dg > (T)0;
+        // PRO_ZERO: every cell that is not cut is written (its update, or 0)
+        wr[q] = PRO == PRO_ZERO ? fl != 1 : upd[q];
+        if (PRO == PRO_ZERO && !upd[q]) {
+#pragma unroll
+            for (int m = 0; m < NC; m++) acc[q][m] = (T)0;
+        }
+    }
+    if (wr[0] && wr[1] && wr[2] && wr[3]) {
+#pragma unroll
+        for (int m = 0; m < NC; m++)
+            *reinterpret_cast<float4*>(x + m * N + own) =
+                make_float4(acc[0][m], acc[1][m], acc[2][m], acc[3][m]);
+    } else {
+#pragma unroll
+        for (int q = 0; q < 4; q++)
+#pragma unroll
+            for (int m = 0; m < NC; m++)
+                if (wr[q]) x[m * N + own + q] = acc[q][m];
     }
 }
 
@@ -2611,6 +2812,7 @@ Rb0V rb0_view(const Level& L) {
     v.cut = L.cut;
     v.ncut = L.ncut;
     v.etacs = L.etacs;
+    v.etafcs = L.etafcs;
     v.flagcs = L.flagcs;
     v.eta = L.eta;
     v.etaf = L.etaf;
@@ -2632,10 +2834,22 @@ bool pair_ok(const Rb0V& v, int nc) {
     return (v.grid.n[0] & 3) == 0 && (nc == 3) == (v.sys == EB_SYS_VISC) && v.flagcs &&
            (v.sys != EB_SYS_VISC || v.etacs);
 }
+// the same for the four-cells-per-thread FP32 kernel: n_x a multiple of 8
+bool quad_ok(const Rb0V& v, int nc) {
+    return (v.grid.n[0] & 7) == 0 && (nc == 3) == (v.sys == EB_SYS_VISC) && v.flagcs &&
+           (v.sys != EB_SYS_VISC || v.etafcs);
+}
+template <int PRO>
+void launch_quad(const Rb0V& v, int nc, const float* b, float* x, int col, hipStream_t s) {
+    unsigned gp = grid_for(v.N / 8, PAIR_BLOCK);
+    unsigned gc = v.ncut > 0 ? (grid_for(v.ncut, PAIR_BLOCK) + 7) & ~7u : 0;
+    if (nc == 3) k_smooth_rb_quad<3, PRO><<<gc + gp, PAIR_BLOCK, 0, s>>>(v, b, x, col, gc);
+    else k_smooth_rb_quad<1, PRO><<<gc + gp, PAIR_BLOCK, 0, s>>>(v, b, x, col, gc);
+}
 
-// one colour's half sweep of level 0: in FP64 with n_x a multiple of 4 the two-cells-per-thread
-// kernel (FP32 pairs are 8 bytes, which the one-cell kernel's loads already match), else the
-// one-cell kernel; the same result either way
+// one colour's half sweep of level 0: the two-cells-per-thread kernel in FP64 (n_x a multiple
+// of 4), the four-cells-per-thread kernel in FP32 (n_x a multiple of 8), else the one-cell
+// kernel; the same result either way
 template <typename T>
 void rb_half_sweep(const Rb0V& v, int nc, const T* b, T* x, int col, hipStream_t s) {
     if constexpr (std::is_same<T, double>::value) {
@@ -2648,14 +2862,19 @@ void rb_half_sweep(const Rb0V& v, int nc, const T* b, T* x, int col, hipStream_t
                 k_smooth_rb_pair<T, 1><<<gc + gp, PAIR_BLOCK, 0, s>>>(v, b, x, col, gc);
             return;
         }
+    } else {
+        if (quad_ok(v, nc)) {
+            launch_quad<PRO_NONE>(v, nc, b, x, col, s);
+            return;
+        }
     }
     unsigned gb = grid_for(v.N / 2);
     if (nc == 3) k_smooth_rb<T, 3><<<gb, EB_BLOCK, 0, s>>>(v, b, x, col);
     else k_smooth_rb<T, 1><<<gb, EB_BLOCK, 0, s>>>(v, b, x, col);
 }
 
-// a half sweep of level 0 with a PRO variant: for PRO_ZERO the two-cells-per-thread kernel
-// where rb_half_sweep takes it, else k_smooth_rb_pro
+// a half sweep of level 0 with a PRO variant: for PRO_ZERO the two- or four-cells-per-thread
+// kernel where rb_half_sweep takes it, else k_smooth_rb_pro
 template <typename T, typename TC, int PRO>
 void rb_half_sweep_pro(const Rb0V& v, int nc, const T* b, T* x, int col, ProV<TC> P,
                        hipStream_t s) {
@@ -2667,6 +2886,12 @@ void rb_half_sweep_pro(const Rb0V& v, int nc, const T* b, T* x, int col, ProV<TC
                 k_smooth_rb_pair<T, 3, PRO><<<gc + gp, PAIR_BLOCK, 0, s>>>(v, b, x, col, gc);
             else
                 k_smooth_rb_pair<T, 1, PRO><<<gc + gp, PAIR_BLOCK, 0, s>>>(v, b, x, col, gc);
+            return;
+        }
+    }
+    if constexpr (std::is_same<T, float>::value && PRO == PRO_ZERO) {
+        if (quad_ok(v, nc)) {
+            launch_quad<PRO>(v, nc, b, x, col, s);
             return;
         }
     }
@@ -3018,6 +3243,9 @@ void mg_build_visc(Level* lev, int nlev, const GeomV& g, double rho, double dt,
     lev[0].dt = dt;
     if (mixed && lev[0].etaf)
         k_to_float<<<grid_for(g.N), EB_BLOCK, 0, s>>>(g.N, eta, lev[0].etaf);
+    if (mixed && lev[0].etafcs && (g.grid.n[0] & 1) == 0)
+        k_to_rb<double, float, 1><<<grid_for(g.N), EB_BLOCK, 0, s>>>(g.grid, g.N, eta,
+                                                                     lev[0].etafcs, nullptr);
     for (int d = 0; d < 3; d++)
         k_K_visc<<<grid_for(face_count(g.grid, d)), EB_BLOCK, 0, s>>>(g, d, dt, eta, lev[0].K[d]);
     k_S_visc<<<grid_for(g.N), EB_BLOCK, 0, s>>>(g, rho, dt, eta_eb, lev[0].S);
