@@ -66,9 +66,9 @@ def smoother_bytes_per_launch(N, ncomp, w):
     return (N // 2) * (3 * ncomp * w + w + 1)
 
 
-# the finest-level viscous smoother per precision: FP64 updates two cells per thread with paired
-# loads, FP32 one cell per thread
-SMOOTHER_KERNEL = {"fp64": "k_smooth_rb_pair", "mixed": "k_smooth_rb"}
+# the finest-level viscous smoother per precision: FP64 updates two cells per thread with 16-byte
+# pair loads, FP32 four cells per thread with 16-byte quad loads
+SMOOTHER_KERNEL = {"fp64": "k_smooth_rb_pair", "mixed": "k_smooth_rb_quad"}
 
 
 def counted_traffic(tag):
