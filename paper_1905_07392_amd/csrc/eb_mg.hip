@@ -2276,11 +2276,12 @@ template <> struct Two<float> { using t = float2; };
 // FP64), as are the two cells' own values and viscosities, so a regular cell needs about half
 // the load instructions of the one-cell form.  The first ncb blocks (a multiple of 8) take one
 // cut cell per thread through visc_apply_cell; the pair blocks write regular (and covered) cells
-// only.  Results are visc_apply_cell's, bit for bit.  dnx, dny divide by the extents.  Used for
-// FP32 input (124 VGPRs); with FP64 input the loaded values need more than 128 VGPRs (four waves
-// per SIMD) and spill, so FP64 input takes the one-cell kernel.
+// only.  Results are visc_apply_cell's, bit for bit.  dnx, dny divide by the extents.  FP32
+// input needs 124 VGPRs (four waves per SIMD); FP64 input 134 (three waves: at four it spills),
+// which still measured 0.35 ms per step faster at 128^3 than the one-cell kernel (35.1-35.2
+// against 35.5 ms, alternated on one GPU).
 template <typename TU>
-__global__ void __launch_bounds__(PAIR_BLOCK, 4)
+__global__ void __launch_bounds__(PAIR_BLOCK, 3)
     k_visc_apply(GeomV g, double rho, double dt, double kin, double kwall, FastDiv dnx,
                  FastDiv dny, const double* __restrict__ eta, const TU* __restrict__ u,
                  double* __restrict__ out, int homog, const int* gate, unsigned ncb) {
@@ -3329,10 +3330,10 @@ void op_visc_apply_t(const GeomV& g, double rho, double dt, const double* eta,
     double kin = dt * 0.5 / h2, kwall = 2.0 * dt / h2;
     FastDiv dnx = fast_div((unsigned)g.grid.n[0]), dny = fast_div((unsigned)g.grid.n[1]);
     bool pair = false;
-    if constexpr (std::is_same<TU, float>::value) {
-        // the pair kernel (FP32 input) reads eta and u in aligned pairs
+    {
+        // the pair kernel reads eta and u in aligned pairs (one-cell kernel otherwise)
         auto al = [](const void* q, size_t a) { return reinterpret_cast<uintptr_t>(q) % a == 0; };
-        if (al(eta, 16) && al(u, 8)) {
+        if (al(eta, 16) && al(u, 2 * sizeof(TU))) {
             unsigned gp = grid_for(g.N / 2, PAIR_BLOCK);
             unsigned gc = g.ncut > 0 ? (grid_for(g.ncut, PAIR_BLOCK) + 7) & ~7u : 0;
             k_visc_apply<TU><<<gc + gp, PAIR_BLOCK, 0, s>>>(g, rho, dt, kin, kwall, dnx, dny,
