@@ -1227,6 +1227,98 @@ __global__ void __launch_bounds__(PAIR_BLOCK, 4)
     }
 }
 
+// y = M x of the Poisson system (one component) on level 0, two neighbouring natural cells
+// a = (i, j, k), b = (i + 1, j, k), i even, per thread: a's upper and b's lower x neighbour are
+// each other, the outer x neighbours are lone loads, and each y and z face's neighbours of both
+// cells are one aligned pair, as are the two cells' own values and flags.  The first ncb blocks
+// (a multiple of 8) take one cut cell per thread through k_apply0's row (the stored one);
+// covered cells get 0.  Each y is k_apply0's bit for bit.
+__global__ void __launch_bounds__(PAIR_BLOCK)
+    k_apply0_pair(Rb0V L, const double* __restrict__ x, double* __restrict__ y, unsigned ncb) {
+    if (L.gate && *L.gate) return;
+    long N = L.N;
+    const GridV& g = L.grid;
+    if (blockIdx.x < ncb) {
+        long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+        if (q >= L.ncut) return;
+        long c = L.cut[q];
+        int i, j, k;
+        rb_coords(L, c, i, j, k);
+        long nb[6];
+#pragma unroll
+        for (int d = 0; d < 3; d++)
+#pragma unroll
+            for (int side = 0; side < 2; side++) nb[2 * d + side] = cell_step(g, c, i, j, k, d, side);
+        double xv = x[c], xn[6][1];
+#pragma unroll
+        for (int f = 0; f < 6; f++) xn[f][0] = nb[f] >= 0 ? x[nb[f]] : 0.0;
+        double K[6], dg, unused[6][1];
+        rb0_row_ld<double, 1, false>(L, c, i, j, k, x, K, nb, dg, unused);
+        double acc = 0.0;
+#pragma unroll
+        for (int f = 0; f < 6; f++) {
+            if (K[f] == 0.0 || nb[f] < 0) continue;
+            acc += K[f] * xn[f][0];
+        }
+        y[c] = dg * xv - acc;
+        return;
+    }
+    unsigned npb = gridDim.x - ncb, u = blockIdx.x - ncb;
+    unsigned tile = (u & 7) * (npb >> 3) + ((u & 7) < (npb & 7) ? (u & 7) : (npb & 7)) + (u >> 3);
+    long p = tile * (long)blockDim.x + threadIdx.x;
+    if (p >= (N >> 1)) return;
+    long ca = 2 * p;
+    int i, j, k;
+    rb_coords(L, ca, i, j, k);
+    long nba[6], nbb[6];
+#pragma unroll
+    for (int d = 0; d < 3; d++)
+#pragma unroll
+        for (int side = 0; side < 2; side++) {
+            nba[2 * d + side] = cell_step(g, ca, i, j, k, d, side);
+            nbb[2 * d + side] = cell_step(g, ca + 1, i + 1, j, k, d, side);
+        }
+    uchar2 fl2 = *reinterpret_cast<const uchar2*>(L.flag + ca);
+    double2 xo = *reinterpret_cast<const double2*>(x + ca);
+    double xla = x[nba[0] >= 0 ? nba[0] : ca], xlb = x[nbb[1] >= 0 ? nbb[1] : ca + 1];
+    double xa[6][1], xb[6][1];
+    xa[0][0] = xla;
+    xa[1][0] = xo.y;
+    xb[0][0] = xo.x;
+    xb[1][0] = xlb;
+#pragma unroll
+    for (int side = 0; side < 2; side++) {
+        long qy = nba[2 + side] >= 0 ? nba[2 + side] : ca;
+        long qz = nba[4 + side] >= 0 ? nba[4 + side] : ca;
+        double2 y2 = *reinterpret_cast<const double2*>(x + qy);
+        double2 z2 = *reinterpret_cast<const double2*>(x + qz);
+        xa[2 + side][0] = y2.x;
+        xb[2 + side][0] = y2.y;
+        xa[4 + side][0] = z2.x;
+        xb[4 + side][0] = z2.y;
+    }
+    double en[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, Ka[6], Kb[6];
+    double da = rb0_regular_row<double, false>(L, nba, 0.0, en, Ka);
+    double db = rb0_regular_row<double, false>(L, nbb, 0.0, en, Kb);
+    double acca = 0.0, accb = 0.0;
+#pragma unroll
+    for (int f = 0; f < 6; f++) {
+        if (!(Ka[f] == 0.0 || nba[f] < 0)) acca += Ka[f] * xa[f][0];
+        if (!(Kb[f] == 0.0 || nbb[f] < 0)) accb += Kb[f] * xb[f][0];
+    }
+    double ya = fl2.x == 0 ? 0.0 : da * xo.x - acca;
+    double yb = fl2.y == 0 ? 0.0 : db * xo.y - accb;
+    if (fl2.x != 1 && fl2.y != 1) {
+        double2 o;
+        o.x = ya;
+        o.y = yb;
+        *reinterpret_cast<double2*>(y + ca) = o;
+    } else {
+        if (fl2.x != 1) y[ca] = ya;
+        if (fl2.y != 1) y[ca + 1] = yb;
+    }
+}
+
 template <typename T, typename TC, int NC, int PRO>
 __global__ void __launch_bounds__(EB_BLOCK)
     k_smooth_rb_pro(Rb0V L, const T* __restrict__ b, T* __restrict__ x, int col, ProV<TC> P) {
@@ -3318,8 +3410,16 @@ void mg_apply_level0(const Level& L, int ncomp, const double* x, double* y, hipS
                      const int* gate) {
     Rb0V v = rb0_view(L);
     v.gate = gate;
-    if (ncomp == 3) k_apply0<3><<<grid_for(L.N), EB_BLOCK, 0, s>>>(v, x, y);
-    else k_apply0<1><<<grid_for(L.N), EB_BLOCK, 0, s>>>(v, x, y);
+    auto al = [](const void* q) { return reinterpret_cast<uintptr_t>(q) % 16 == 0; };
+    if (ncomp == 1 && v.sys == EB_SYS_POISSON && al(x) && al(y)) {
+        unsigned gp = grid_for(L.N / 2, PAIR_BLOCK);
+        unsigned gc = v.ncut > 0 ? (grid_for(v.ncut, PAIR_BLOCK) + 7) & ~7u : 0;
+        k_apply0_pair<<<gc + gp, PAIR_BLOCK, 0, s>>>(v, x, y, gc);
+    } else if (ncomp == 3) {
+        k_apply0<3><<<grid_for(L.N), EB_BLOCK, 0, s>>>(v, x, y);
+    } else {
+        k_apply0<1><<<grid_for(L.N), EB_BLOCK, 0, s>>>(v, x, y);
+    }
 }
 
 template <typename TU>
