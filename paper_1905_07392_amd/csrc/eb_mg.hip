@@ -7,8 +7,9 @@
 // average four child faces (and rescale by 1/4 for the doubled spacing) and eight child
 // cell shifts, the viscous faces with the viscosity along each child face's normal line taken
 // in series (coarsen_face_series), which keeps the coarse operators faithful across the
-// 1e7 viscosity contrast of a plug next to a sheared layer.  Smoothing is red-black Gauss-Seidel; within a colour every update depends only
-// on the other colour, so the result does not depend on thread order.
+// 1e7 viscosity contrast of a plug next to a sheared layer.  Smoothing is red-black
+// Gauss-Seidel; within a colour every update depends only on the other colour, so the result
+// does not depend on thread order (or on how many cells a thread updates).
 #include "eb_internal.hpp"
 #include <type_traits>
 
@@ -514,11 +515,13 @@ __global__ void k_prolong(GridV gf, GridV gc, const uint8_t* __restrict__ mf,
 // ------------------------------------------------------------------------------------------
 // finest level in colour-split storage.  Vectors of level 0 are kept as [component][colour]
 // [cell of that colour in natural order]: cell c = (i, j, k) of colour (i+j+k) mod 2 sits at
-// colour * N/2 + c/2 (nx is even).  A half sweep then reads one colour of the iterate and the
-// right-hand side contiguously and writes the other contiguously.  Coefficients of regular
-// cells (all six apertures 1) are recomputed from eta with the same expressions, in the same
-// order, as the stored operator, so results are bitwise those of the stored coefficients;
-// cut cells read the stored faces and diagonal.
+// colour * N/2 + c/2 (nx is even).  A half sweep then reads the other colour of the iterate and
+// its own colour of the right-hand side contiguously and writes its own colour contiguously;
+// the FP64 and FP32 half sweeps take two and four cells of one colour per thread, with 16-byte
+// loads (k_smooth_rb_pair, k_smooth_rb_quad).  Coefficients of regular cells (all six
+// apertures 1) are recomputed from eta with the same expressions, in the same order, as the
+// stored operator, so results are bitwise those of the stored coefficients; cut cells read the
+// stored faces and diagonal.
 // ------------------------------------------------------------------------------------------
 // unsigned division by a fixed divisor d, for dividends below 2^31, as a multiply-high, an add
 // and a shift (m and s from fast_div); the index arithmetic of the finest level's one-thread-
