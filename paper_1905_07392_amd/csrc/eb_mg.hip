@@ -1367,8 +1367,9 @@ __global__ void k_smooth_first_rb_from(Rb0V L, const double* __restrict__ bnat,
 }
 
 // the last half sweep (colour 0) fused with the conversion of the iterate back to natural
-// order (FP64, or FP32 from an FP32 level, which loses nothing): a thread updates its colour-0 cell and also copies the colour-1 cell next to it
-// in x, so every cell of the natural output is written once
+// order (FP64, or FP32 from an FP32 level, which loses nothing): a thread updates its colour-0
+// cell and also copies the colour-1 cell next to it in x, so every cell of the natural output is
+// written once
 template <typename T, int NC, int PRO = PRO_NONE, typename TC = T, typename TD = double>
 __global__ void k_smooth_last_rb_to(Rb0V L, const T* __restrict__ b, const T* __restrict__ x,
                                     TD* __restrict__ xnat, ProV<TC> P) {
