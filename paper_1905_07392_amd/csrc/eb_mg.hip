@@ -2563,6 +2563,27 @@ __device__ __forceinline__ double block_max(double v, double* sh) {
     return r;
 }
 
+// row p of nb per-block partials reduced in a fixed order (a sum, or a maximum if mx): thread i
+// takes partials i, i + B, i + 2B, ... in turn (B threads), then the block combines the
+// threads; the loads of four turns are issued before the first is used
+__device__ __forceinline__ double red_row(const double* __restrict__ part, int nb, int p, bool mx,
+                                          double* sh) {
+    double v = 0.0;
+    const int B = blockDim.x;
+    for (int t0 = 0; t0 < nb; t0 += 4 * B) {
+        double w[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            int t = t0 + k * B + threadIdx.x;
+            w[k] = t < nb ? part[p * nb + t] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+            if (t0 + k * B + (int)threadIdx.x < nb) v = mx ? nan_max(v, w[k]) : v + w[k];
+    }
+    return mx ? block_max(v, sh) : block_sum(v, sh);
+}
+
 struct DotArgs {
     const double* a[4];
     const double* b[4];
@@ -2618,11 +2639,7 @@ __global__ void k_final_op(const double* __restrict__ part, int nb, int nrow, Op
     __shared__ double sh[EB_BLOCK];
     if (*st == 0) {
         for (int p = 0; p < nrow; p++) {
-            bool mx = (o.maxmask >> p) & 1;
-            double v = 0.0;
-            for (int t = threadIdx.x; t < nb; t += blockDim.x)
-                v = mx ? nan_max(v, part[p * nb + t]) : v + part[p * nb + t];
-            v = mx ? block_max(v, sh) : block_sum(v, sh);
+            double v = red_row(part, nb, p, (o.maxmask >> p) & 1, sh);
             if (threadIdx.x == 0) ks[o.idx[p]] = v;
         }
     }
@@ -2769,10 +2786,7 @@ __global__ void k_final(const double* __restrict__ part, int nb, int nrow, int m
     if (gate && *gate) return;
     __shared__ double sh[EB_BLOCK];
     for (int p = 0; p < nrow; p++) {
-        double v = 0.0;
-        for (int t = threadIdx.x; t < nb; t += blockDim.x)
-            v = mode ? nan_max(v, part[p * nb + t]) : v + part[p * nb + t];
-        v = mode ? block_max(v, sh) : block_sum(v, sh);
+        double v = red_row(part, nb, p, mode != 0, sh);
         if (threadIdx.x == 0) out[p] = v;
     }
 }
