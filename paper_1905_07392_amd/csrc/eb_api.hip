@@ -995,16 +995,18 @@ int next_switches(eb_ctx* c, SwitchV* sw) {
     return EB_OK;
 }
 
-// DerivedQuantities; the MAC projection reports into `slot`
+// DerivedQuantities; the MAC projection reports into `slot` and starts from phi = 0, or, with
+// warm, from the phi its previous call left (the corrector starts from the predictor's: the
+// converged phi is the same to the solve's tolerance, in fewer iterations)
 int derived(eb_ctx* c, const eb_rheology& rh, const double* theta, const double* u,
             const eb_step_opts* o, double* C, double* eta, double* eta_eb, double* V,
-            int slot) {
+            int slot, bool warm = false) {
     SolveCfg k = cfg_of(o);
     double rtol = o && o->rtol_mac > 0 ? o->rtol_mac : 1e-12;
     SwitchV sw;
     if (int h = next_switches(c, &sw)) return h;
     op_face_extrap(c->g, u, c->f, sw, c->s);
-    vec_fill(c->N, 0.0, c->phi, c->s);
+    if (!warm) vec_fill(c->N, 0.0, c->phi, c->s);
     mac_project(c, 1.0, c->f, c->phi, rtol, k, slot, false);
     op_conv_dc(c->g, u, c->f, c->DC, sw, c->s);
     op_redistribute(c->g, c->DC, c->DH, c->rS, c->rdD, C, c->s);
@@ -1566,7 +1568,8 @@ int rk2_impl(eb_ctx* c, const eb_rheology* rheo, const double* theta, double dt,
     project(2);
     if (tp) vec_copy(N3, c->u1, tp->u1, c->s);
     // corrector: derived quantities at u*, averaged with the predictor's
-    if ((h = derived(c, *rheo, theta, c->u1, o, c->C1, c->eta1, c->eb1, c->V1, 3))) return h;
+    if ((h = derived(c, *rheo, theta, c->u1, o, c->C1, c->eta1, c->eb1, c->V1, 3, true)))
+        return h;
     if (tp)
         for (int d = 0; d < 3; d++) vec_copy(face_count(c->grid, d), c->f[d], tp->uf1[d], c->s);
     op_average(N3, c->C1, c->C0, c->s);
