@@ -656,3 +656,19 @@ def test_cylinder_newtonian_drag_approaches_faxen():
     print(f"[drag] Faxen {faxen:.4f}: C_D {cd16:.4f} (16/D, {e16:.2%}), {cd32:.4f} (32/D, "
           f"{e32:.2%})", flush=True)
     assert e32 < e16 and e32 < 0.05, (cd16, cd32, faxen)
+
+
+def test_step_depends_only_on_its_inputs(s32):
+    """The corrector's MAC solve starts from the predictor's phi of the same call (the oracle
+    starts both from zero), so a step's result depends on its inputs alone: the same step
+    repeated after a step from another state, which leaves another phi in the context, gives
+    bitwise the same u and p."""
+    P = s32
+    w = P.w
+    u0 = P.dev(I.initial_velocity(w))
+    p0 = P.ctx.scalar()
+    ua, pa, _ = P.api.eb_rk2_step(P.ctx, P.rheo, w.dt, P.opts, u0, p0)
+    P.api.eb_rk2_step(P.ctx, P.rheo, w.dt, P.opts, ua, pa)
+    ub, pb, _ = P.api.eb_rk2_step(P.ctx, P.rheo, w.dt, P.opts, u0, p0)
+    print(f"[parity] repeated step: max |du| {(ua - ub).abs().max().item():.3e}", flush=True)
+    assert torch.equal(ua, ub) and torch.equal(pa, pb)
